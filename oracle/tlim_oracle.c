@@ -1,0 +1,701 @@
+/*
+ * FP64 CPU oracle of the parabolic sub-step (arXiv 2106.00282, Sec. 3.2 and
+ * Sec. 3.4, Algorithm 1).  TEST INFRASTRUCTURE ONLY: the product path never
+ * links or calls it.  See tlim_oracle.h for the scope, the pins and what is
+ * left unpinned.
+ *
+ * Readings of the paper taken here (each one is also listed with its reason
+ * in the design notes of the repository):
+ *  - Chebyshev roots: beta_1 = cos(pi/2P) is the largest root, so that
+ *    a_1 = 0 < a_2 < ... < a_P (Sec. 3.2, parameters of eq. LIM).
+ *  - Stage order: the same multiset of parameters as the paper, in the
+ *    order (a_P, a_2, a_{P-1}, a_3, ...) twice with a_1 = 0 last.  Every
+ *    stage has the fixed point (I + tau A)^-1 g and the stage maps commute,
+ *    so in exact arithmetic every order gives the same result; in floating
+ *    point the printed order (a_P..a_2, a_P..a_1) and ascending pairs let
+ *    round-off grow by many orders of magnitude at tau*lambda = 400 on a
+ *    grid, the interleaved order does not.  Both others stay as options.
+ *  - v^(0) = v^n; the operator L_h of eq. LIM is -A with A = C^-1 D >= 0,
+ *    the final stage is v^n - tau A v_hat + tau f in flux form (eq. LIM_last).
+ *  - lambda_max is the Gershgorin bound of A, taken per Picard pass.
+ *  - Face conductivity: arithmetic mean of the cell values
+ *    Lambda = sum_k alpha_k lambda_k(T) (eq. qk_dis leaves it open).
+ *  - Heat step: with T_1 = T_2 = T and p_1 = p_2 held, the phase energy
+ *    equations reduce to C_eff dT/dt = sum_k (q_k + I_k), with
+ *    C_eff = C_1 + C_2 + B_1^2/(T^2 W), W = G1 C1/a1^2 + G2 C2/a2^2, and
+ *    d alpha_2/dT = -B_1/(T^2 W) (B_1 = p_inf,1 - p_inf,2).  For equal p_inf
+ *    this is the mixture heat equation with alpha_2 frozen.
+ *  - Temperature relaxation: the exact end state of the relaxation system
+ *    (phase energies summed, p_1 = p_2, T_1 = T_2); for equal p_inf it is
+ *    eq. Taverage.  The root with T' <= 0 is rejected.
+ *  - Picard: every pass restarts the LIM from T^n with coefficients lagged
+ *    at T^(it); err = max|T^(it+1) - T^(it)| / max|T^(it+1)|.
+ */
+#include "tlim_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PI 3.14159265358979323846
+
+static int64_t ncells(const orc_grid* g) { return g->n[0] * g->n[1] * g->n[2]; }
+
+static double cell_volume(const orc_grid* g) { return g->h[0] * g->h[1] * g->h[2]; }
+
+static double* dalloc(int64_t n) {
+    double* p = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    if (!p) abort();
+    return p;
+}
+
+/* The faces of one cell: neighbour index and weight s_axis / h_axis^2.
+ * A face exists towards the next cell along an axis, wrapping round on a
+ * periodic axis; an adiabatic end and an axis of a single cell have none.
+ * On a periodic axis of two cells both faces lead to the same neighbour. */
+typedef struct {
+    int count;
+    int64_t nb[6];
+    double w[6];
+} cell_faces;
+
+static void faces_of(const orc_grid* g, const double axis_scale[3], int64_t i, int64_t j, int64_t k,
+                     cell_faces* f) {
+    int64_t c[3] = {i, j, k};
+    int64_t stride[3] = {1, g->n[0], g->n[0] * g->n[1]};
+    int64_t a = i + g->n[0] * (j + g->n[1] * k);
+    f->count = 0;
+    for (int axis = 0; axis < 3; ++axis) {
+        int64_t n = g->n[axis];
+        if (n <= 1) continue;
+        double w = axis_scale[axis] / (g->h[axis] * g->h[axis]);
+        for (int dir = -1; dir <= 1; dir += 2) {
+            int64_t cn = c[axis] + dir;
+            if (cn < 0 || cn >= n) {
+                if (g->bc[axis] != ORC_PERIODIC) continue;
+                cn = (cn + n) % n;
+            }
+            f->nb[f->count] = a + (cn - c[axis]) * stride[axis];
+            f->w[f->count] = w;
+            f->count++;
+        }
+    }
+}
+
+static double face_value(double La, double Lb, int32_t face_mean) {
+    if (face_mean == ORC_FACE_HARMONIC) {
+        double s = La + Lb;
+        return s > 0.0 ? 2.0 * (La * Lb) / s : 0.0;
+    }
+    return 0.5 * (La + Lb);
+}
+
+/* d Lambda_f / d Lambda_a for the face mean (the other side by symmetry). */
+static double face_partial(double La, double Lb, int32_t face_mean) {
+    if (face_mean == ORC_FACE_HARMONIC) {
+        double s = La + Lb;
+        return s > 0.0 ? 2.0 * Lb * Lb / (s * s) : 0.0;
+    }
+    return 0.5;
+}
+
+static double conductivity(const orc_phase* p, double T) { return p->k0 * pow(T / p->T0, p->npow); }
+
+static double conductivity_dT(const orc_phase* p, double T) {
+    if (p->npow == 0.0) return 0.0;
+    return p->k0 * p->npow * pow(T / p->T0, p->npow - 1.0) / p->T0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Chebyshev parameters (Sec. 3.2, eq. LIM and the definition of a_m).       */
+
+int32_t orc_lim_P(double tau, double lambda_max) {
+    return (int32_t)ceil(PI / 4.0 * sqrt(tau * lambda_max + 1.0));
+}
+
+/* Large-small interleave of an increasing list x[0] < ... < x[n-1]:
+ * x[n-1], x[0], x[n-2], x[1], ... */
+static void interleave(const double* x, int32_t n, double* out) {
+    int32_t lo = 0, hi = n - 1, k = 0, take_hi = 1;
+    while (lo <= hi) {
+        out[k++] = take_hi ? x[hi--] : x[lo++];
+        take_hi = !take_hi;
+    }
+}
+
+void orc_lim_params(int32_t P, double lambda_max, int32_t order, double* b) {
+    /* beta_j = cos((2j-1) pi / (2P)), j = 1..P, beta_1 the largest root, and
+     * a_j = lambda_max (beta_1 - beta_j) / (1 + beta_1), so a_1 = 0 < a_2 < ... < a_P. */
+    double* a = dalloc(P + 1);
+    double beta1 = cos(PI / (2.0 * P));
+    for (int32_t j = 1; j <= P; ++j) {
+        double betaj = cos((2.0 * j - 1.0) * PI / (2.0 * P));
+        a[j] = lambda_max / (1.0 + beta1) * (beta1 - betaj);
+    }
+    a[1] = 0.0;
+    int32_t k = 0;
+    if (order == ORC_ORDER_PAPER) {
+        /* (a_P, a_{P-1}, ..., a_2, a_P, a_{P-1}, ..., a_1) as printed */
+        for (int32_t j = P; j >= 2; --j) b[k++] = a[j];
+        for (int32_t j = P; j >= 1; --j) b[k++] = a[j];
+    } else if (order == ORC_ORDER_ASCENDING) {
+        /* (a_2, a_2, a_3, a_3, ..., a_P, a_P, a_1) */
+        for (int32_t j = 2; j <= P; ++j) {
+            b[k++] = a[j];
+            b[k++] = a[j];
+        }
+        b[k++] = a[1];
+    } else {
+        /* (a_P, a_2, a_{P-1}, a_3, ...) twice, then a_1: the same multiset,
+         * ordered so that no partial product of stage factors grows large. */
+        if (P > 1) {
+            interleave(a + 2, P - 1, b);
+            interleave(a + 2, P - 1, b + (P - 1));
+        }
+        b[2 * P - 2] = a[1];
+    }
+    free(a);
+}
+
+void orc_cycle_params(int32_t s, double lambda_max, double* b) {
+    /* Richardson steps 1/(1 + tau b_j) with 1 + tau b_j at the Chebyshev
+     * nodes of [1, 1 + tau lambda_max]: b_j = lambda/2 (1 + cos((2j-1) pi/(2s))),
+     * applied in increasing order (j = s, ..., 1), so that each cycle ends with
+     * the stages that damp the high modes most and the residual reaches its
+     * rounding floor. */
+    for (int32_t k = 0; k < s; ++k) {
+        int32_t j = s - k;
+        b[k] = 0.5 * lambda_max * (1.0 + cos((2.0 * j - 1.0) * PI / (2.0 * s)));
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Coefficients (Sec. 3.4.2).                                                 */
+
+void orc_cell_conductivity(const orc_grid* g, const orc_phase ph[2], const double* alpha2,
+                           const double* T, double* Lam) {
+    int64_t N = ncells(g);
+    for (int64_t i = 0; i < N; ++i) {
+        double a2 = alpha2[i], a1 = 1.0 - a2;
+        Lam[i] = a1 * conductivity(&ph[0], T[i]) + a2 * conductivity(&ph[1], T[i]);
+    }
+}
+
+static int is_mixed(double a2, double eps) { return a2 > eps && a2 < 1.0 - eps; }
+
+/* W = Gamma_1 C_1 / alpha_1^2 + Gamma_2 C_2 / alpha_2^2 (mixed cells). */
+static double pressure_stiffness(const orc_phase ph[2], double a2, double C1, double C2) {
+    double a1 = 1.0 - a2;
+    return (ph[0].gamma - 1.0) * C1 / (a1 * a1) + (ph[1].gamma - 1.0) * C2 / (a2 * a2);
+}
+
+void orc_heat_capacity(const orc_grid* g, const orc_phase ph[2], double eps, const double* alpha2,
+                       const double* m1, const double* m2, const double* T, double* C) {
+    int64_t N = ncells(g);
+    double B1 = ph[0].pinf - ph[1].pinf;
+    for (int64_t i = 0; i < N; ++i) {
+        double C1 = m1[i] * ph[0].cv, C2 = m2[i] * ph[1].cv;
+        double c = C1 + C2;
+        if (B1 != 0.0 && is_mixed(alpha2[i], eps)) {
+            double W = pressure_stiffness(ph, alpha2[i], C1, C2);
+            c += B1 * B1 / (T[i] * T[i] * W);
+        }
+        C[i] = c;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Discrete operator D v = -div(Lambda grad v) (eq. qk_dis, all axes).       */
+/* Every loop below visits cells (i,j,k) independently; the (k,j) rows are  */
+/* shared out over OpenMP threads, which changes no arithmetic.              */
+
+double orc_gershgorin(const orc_grid* g, const double* Lam, const double* C,
+                      const double axis_scale[3], int32_t face_mean) {
+    double lam = 0.0;
+#pragma omp parallel for collapse(2) schedule(static) reduction(max : lam)
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                int64_t a = i + g->n[0] * (j + g->n[1] * k);
+                cell_faces f;
+                faces_of(g, axis_scale, i, j, k, &f);
+                /* d_a = sum_f w_f Lambda_f / C_a: the diagonal of A, equal to the
+                 * sum of the magnitudes of the off-diagonal entries of row a. */
+                double d = 0.0;
+                for (int q = 0; q < f.count; ++q) d += f.w[q] * face_value(Lam[a], Lam[f.nb[q]], face_mean);
+                double r = 2.0 * d / C[a];
+                if (r > lam) lam = r;
+            }
+    return lam;
+}
+
+/* div[a] = sum over faces of a of w Lambda_f (v_nb - v_a): the net flux into a.
+ * The flux through a face is the same number seen from either side, with
+ * opposite sign, so the sum over all cells cancels face by face. */
+static void face_flux_divergence(const orc_grid* g, const double* Lam, const double axis_scale[3],
+                                 int32_t face_mean, const double* v, double* div) {
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                int64_t a = i + g->n[0] * (j + g->n[1] * k);
+                cell_faces f;
+                faces_of(g, axis_scale, i, j, k, &f);
+                double s = 0.0;
+                for (int q = 0; q < f.count; ++q) {
+                    int64_t b = f.nb[q];
+                    s += f.w[q] * face_value(Lam[a], Lam[b], face_mean) * (v[b] - v[a]);
+                }
+                div[a] = s;
+            }
+}
+
+void orc_apply_A(const orc_grid* g, const double* Lam, const double* C, const double axis_scale[3],
+                 int32_t face_mean, const double* v, double* y) {
+    int64_t N = ncells(g);
+    face_flux_divergence(g, Lam, axis_scale, face_mean, v, y);
+    for (int64_t a = 0; a < N; ++a) y[a] = -y[a] / C[a];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Method of local iterations (Sec. 3.2, eqs. LIM and LIM_last).              */
+
+void orc_lim_pass(const orc_grid* g, const double* Lam, const double* C, const double axis_scale[3],
+                  int32_t face_mean, double tau, int32_t nst, const double* b, const double* rhs,
+                  const double* v0, double* out, double* stages) {
+    int64_t N = ncells(g);
+    double* cur = dalloc(N);
+    double* nxt = dalloc(N);
+    double* Av = dalloc(N);
+    memcpy(cur, v0, sizeof(double) * (size_t)N);
+    /* stages 1 .. nst-1: v^(m) = (g + tau b_m v^(m-1) - tau A v^(m-1)) / (1 + tau b_m) */
+    for (int32_t m = 1; m < nst; ++m) {
+        if (stages) memcpy(stages + (int64_t)(m - 1) * N, cur, sizeof(double) * (size_t)N);
+        orc_apply_A(g, Lam, C, axis_scale, face_mean, cur, Av);
+        double tb = tau * b[m - 1];
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i) nxt[i] = (rhs[i] + tb * cur[i] - tau * Av[i]) / (1.0 + tb);
+        double* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (stages) memcpy(stages + (int64_t)(nst - 1) * N, cur, sizeof(double) * (size_t)N);
+    /* last stage, b = 0: conservative flux difference of the predicted v_hat */
+    face_flux_divergence(g, Lam, axis_scale, face_mean, cur, Av);
+    for (int64_t i = 0; i < N; ++i) out[i] = rhs[i] + tau * Av[i] / C[i];
+    free(cur);
+    free(nxt);
+    free(Av);
+}
+
+double orc_be_residual(const orc_grid* g, const double* Lam, const double* C,
+                       const double axis_scale[3], int32_t face_mean, double tau, const double* rhs,
+                       const double* v) {
+    int64_t N = ncells(g);
+    double* div = dalloc(N);
+    face_flux_divergence(g, Lam, axis_scale, face_mean, v, div);
+    double rr = 0.0, gg = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        /* C (g - v) - tau D v, with D v = -div */
+        double r = C[i] * (rhs[i] - v[i]) + tau * div[i];
+        rr += r * r;
+        gg += (C[i] * rhs[i]) * (C[i] * rhs[i]);
+    }
+    free(div);
+    return gg > 0.0 ? sqrt(rr / gg) : sqrt(rr);
+}
+
+/* Chebyshev-Richardson cycles of s stages towards (I + tau A) v = g. */
+int32_t orc_cycle_solve(const orc_grid* g, const double* Lam, const double* C,
+                        const double axis_scale[3], int32_t face_mean, double tau,
+                        double lambda_max, int32_t s, const double* rhs, const double* v0,
+                        double tol, int32_t max_cycles, double* out, double* residual_hist) {
+    int64_t N = ncells(g);
+    double* b = dalloc(s);
+    double* Av = dalloc(N);
+    orc_cycle_params(s, lambda_max, b);
+    memcpy(out, v0, sizeof(double) * (size_t)N);
+    int32_t cyc = 0;
+    while (cyc < max_cycles) {
+        for (int32_t m = 0; m < s; ++m) {
+            orc_apply_A(g, Lam, C, axis_scale, face_mean, out, Av);
+            double tb = tau * b[m];
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < N; ++i) out[i] = (rhs[i] + tb * out[i] - tau * Av[i]) / (1.0 + tb);
+        }
+        ++cyc;
+        double r = orc_be_residual(g, Lam, C, axis_scale, face_mean, tau, rhs, out);
+        if (residual_hist) residual_hist[cyc - 1] = r;
+        if (r < tol) break;
+    }
+    free(b);
+    free(Av);
+    return cyc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Temperature relaxation (Sec. 3.4.1).                                      */
+
+/* Sign of p_1 - p_2 at alpha_2 = a, times a(1-a) > 0, with T(a) from the
+ * energy balance.  Returned as the quadratic T(a)(G1 C1 a - G2 C2 (1-a)) + B a (1-a). */
+static double relax_pressure_gap(const orc_phase ph[2], double C1, double C2, double Esens,
+                                 double a20, double a) {
+    double B = ph[1].pinf - ph[0].pinf;
+    double T = (Esens + (a20 - a) * B) / (C1 + C2);
+    return T * ((ph[0].gamma - 1.0) * C1 * a - (ph[1].gamma - 1.0) * C2 * (1.0 - a)) + B * a * (1.0 - a);
+}
+
+void orc_relax(const orc_grid* g, const orc_phase ph[2], double eps, double* alpha2,
+               const double* m1, const double* m2, double* T1, double* T2) {
+    int64_t N = ncells(g);
+    double B = ph[1].pinf - ph[0].pinf; /* p_inf,2 - p_inf,1 */
+    for (int64_t i = 0; i < N; ++i) {
+        double a20 = alpha2[i];
+        if (a20 <= eps) { /* only phase 1 present */
+            T2[i] = T1[i];
+            continue;
+        }
+        if (a20 >= 1.0 - eps) { /* only phase 2 present */
+            T1[i] = T2[i];
+            continue;
+        }
+        double C1 = m1[i] * ph[0].cv, C2 = m2[i] * ph[1].cv;
+        /* Energy: sum_k C_k T_k + alpha_k p_inf,k is conserved, so
+         * (C1 + C2) T'(a) = C1 T1 + C2 T2 + (alpha2^0 - a) B. */
+        double Esens = C1 * T1[i] + C2 * T2[i];
+        /* Admissible interval: 0 < a < 1 and T'(a) > 0. */
+        double lo = 0.0, hi = 1.0;
+        if (B > 0.0) {
+            double lim = a20 + Esens / B;
+            if (lim < hi) hi = lim;
+        } else if (B < 0.0) {
+            double lim = a20 + Esens / B;
+            if (lim > lo) lo = lim;
+        }
+        /* p_1 - p_2 goes from -inf (or -|B|) at lo to +inf (or +B) at hi and has
+         * a single root there: plain bisection. */
+        for (int it = 0; it < 200; ++it) {
+            double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            if (relax_pressure_gap(ph, C1, C2, Esens, a20, mid) < 0.0) lo = mid;
+            else hi = mid;
+        }
+        double a = 0.5 * (lo + hi);
+        double T = (Esens + (a20 - a) * B) / (C1 + C2);
+        alpha2[i] = a;
+        T1[i] = T;
+        T2[i] = T;
+    }
+}
+
+double orc_energy(const orc_grid* g, const orc_phase ph[2], const double* alpha2, const double* m1,
+                  const double* m2, const double* T1, const double* T2) {
+    int64_t N = ncells(g);
+    double e = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        double a2 = alpha2[i], a1 = 1.0 - a2;
+        e += m1[i] * ph[0].cv * T1[i] + m2[i] * ph[1].cv * T2[i] + a1 * ph[0].pinf + a2 * ph[1].pinf;
+    }
+    return e * cell_volume(g);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Picard loop of Algorithm 1 around LIM passes (no relaxation inside).       */
+
+static const double UNIT_SCALE[3] = {1.0, 1.0, 1.0};
+
+/* Heat conduction for one step from the relaxed state (alpha2, T).
+ * T holds T^n on entry and T^{n+1} on exit; alpha2 likewise. */
+static int32_t heat_picard(const orc_grid* g, const orc_phase ph[2], const orc_opts* o,
+                           double* alpha2, const double* m1, const double* m2, double* T,
+                           const double* src1, const double* src2, const double* frozen_lambda,
+                           orc_report* rep) {
+    int64_t N = ncells(g);
+    double tau = o->tau;
+    double B1 = ph[0].pinf - ph[1].pinf;
+    double* Tn = dalloc(N);
+    double* a2n = dalloc(N);
+    double* Lam = dalloc(N);
+    double* C = dalloc(N);
+    double* rhs = dalloc(N);
+    double* Tnew = dalloc(N);
+    memcpy(Tn, T, sizeof(double) * (size_t)N);
+    memcpy(a2n, alpha2, sizeof(double) * (size_t)N);
+    int32_t converged = 0, it;
+    for (it = 0; it < o->passes; ++it) {
+        /* Coefficients lagged at T^(it), alpha2^(it). */
+        orc_cell_conductivity(g, ph, alpha2, T, Lam);
+        orc_heat_capacity(g, ph, o->alpha_eps, alpha2, m1, m2, T, C);
+        for (int64_t i = 0; i < N; ++i) {
+            double f = 0.0;
+            if (src1) f += (1.0 - alpha2[i]) * src1[i];
+            if (src2) f += alpha2[i] * src2[i];
+            rhs[i] = Tn[i] + tau * f / C[i];
+        }
+        double lam = frozen_lambda ? frozen_lambda[it]
+                                   : orc_gershgorin(g, Lam, C, UNIT_SCALE, o->face_mean);
+        int32_t P = orc_lim_P(tau, lam);
+        int32_t nst = 2 * P - 1;
+        if (o->cycle_mode) {
+            double res = 0.0;
+            double* hist = dalloc(o->max_cycles > 0 ? o->max_cycles : 1);
+            int32_t nc = orc_cycle_solve(g, Lam, C, UNIT_SCALE, o->face_mean, tau, lam, nst, rhs, Tn,
+                                         o->cycle_tol, o->max_cycles, Tnew, hist);
+            res = nc > 0 ? hist[nc - 1] : 0.0;
+            free(hist);
+            if (rep && it < ORC_MAX_PASSES) {
+                rep->cycles[it] = nc;
+                rep->residual[it] = res;
+            }
+        } else {
+            double* b = dalloc(nst);
+            orc_lim_params(P, lam, o->order, b);
+            orc_lim_pass(g, Lam, C, UNIT_SCALE, o->face_mean, tau, nst, b, rhs, Tn, Tnew, NULL);
+            free(b);
+        }
+        /* Volume fraction (Algorithm 1, second solve): d alpha2 = -B1/(T^2 W) dT,
+         * integrated from the step start with the lagged coefficient. */
+        if (B1 != 0.0) {
+            for (int64_t i = 0; i < N; ++i) {
+                if (!is_mixed(a2n[i], o->alpha_eps)) continue;
+                double C1 = m1[i] * ph[0].cv, C2 = m2[i] * ph[1].cv;
+                double W = pressure_stiffness(ph, alpha2[i], C1, C2);
+                alpha2[i] = a2n[i] - B1 / (T[i] * T[i] * W) * (Tnew[i] - Tn[i]);
+            }
+        }
+        double dmax = 0.0, tmax = 0.0;
+        for (int64_t i = 0; i < N; ++i) {
+            double d = fabs(Tnew[i] - T[i]);
+            if (d > dmax) dmax = d;
+            if (fabs(Tnew[i]) > tmax) tmax = fabs(Tnew[i]);
+        }
+        double err = tmax > 0.0 ? dmax / tmax : dmax;
+        memcpy(T, Tnew, sizeof(double) * (size_t)N);
+        if (rep && it < ORC_MAX_PASSES) {
+            rep->P[it] = P;
+            rep->lambda_G[it] = lam;
+            rep->err[it] = err;
+        }
+        if (o->picard_tol > 0.0 && err < o->picard_tol) {
+            converged = 1;
+            ++it;
+            break;
+        }
+    }
+    if (rep) {
+        rep->passes_run = it;
+        rep->converged = converged || o->picard_tol <= 0.0;
+    }
+    free(Tn);
+    free(a2n);
+    free(Lam);
+    free(C);
+    free(rhs);
+    free(Tnew);
+    return (o->picard_tol > 0.0 && !converged) ? 3 : 0;
+}
+
+/* Viscous momentum diffusion, one LIM pass per velocity component. */
+static void viscous(const orc_grid* g, const orc_phase ph[2], const orc_opts* o,
+                    const double* alpha2, const double* m1, const double* m2, double* vel[3],
+                    const double* frozen_visc, orc_report* rep) {
+    int64_t N = ncells(g);
+    double* rho = dalloc(N);
+    double* mu = dalloc(N);
+    double* out = dalloc(N);
+    for (int64_t i = 0; i < N; ++i) {
+        rho[i] = m1[i] + m2[i];
+        mu[i] = (1.0 - alpha2[i]) * ph[0].mu + alpha2[i] * ph[1].mu;
+    }
+    for (int c = 0; c < 3; ++c) {
+        if (g->n[c] <= 1 || !vel[c]) continue;
+        /* rho du_c/dt = sum_d d_d(mu_cd d_d u_c), mu_cd = 4/3 mu on the own axis. */
+        double s[3] = {1.0, 1.0, 1.0};
+        s[c] = 4.0 / 3.0;
+        double lam = frozen_visc ? frozen_visc[c] : orc_gershgorin(g, mu, rho, s, o->face_mean);
+        int32_t P = orc_lim_P(o->tau, lam);
+        int32_t nst = 2 * P - 1;
+        double* b = dalloc(nst);
+        orc_lim_params(P, lam, o->order, b);
+        orc_lim_pass(g, mu, rho, s, o->face_mean, o->tau, nst, b, vel[c], vel[c], out, NULL);
+        memcpy(vel[c], out, sizeof(double) * (size_t)N);
+        free(b);
+        if (rep) {
+            rep->visc_P[c] = P;
+            rep->visc_lambda_G[c] = lam;
+        }
+    }
+    free(rho);
+    free(mu);
+    free(out);
+}
+
+int32_t orc_step(const orc_grid* g, const orc_phase ph[2], const orc_opts* o, double* alpha2,
+                 const double* m1, const double* m2, double* T1, double* T2, const double* src1,
+                 const double* src2, double* u, double* v, double* w, const double* frozen_lambda,
+                 const double* frozen_visc, orc_report* rep) {
+    if (rep) memset(rep, 0, sizeof(*rep));
+    if (rep) rep->energy_before = orc_energy(g, ph, alpha2, m1, m2, T1, T2);
+    /* Splitting order of the paper: viscous part, then temperature relaxation,
+     * then heat conduction. */
+    if (o->do_viscous) {
+        double* vel[3] = {u, v, w};
+        viscous(g, ph, o, alpha2, m1, m2, vel, frozen_visc, rep);
+    }
+    orc_relax(g, ph, o->alpha_eps, alpha2, m1, m2, T1, T2);
+    int32_t st = heat_picard(g, ph, o, alpha2, m1, m2, T1, src1, src2, frozen_lambda, rep);
+    memcpy(T2, T1, sizeof(double) * (size_t)ncells(g));
+    if (rep) rep->energy_after = orc_energy(g, ph, alpha2, m1, m2, T1, T2);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of the heat steps (discrete reverse of the LIM passes).           */
+
+/* Reverse of one LIM pass.  stages holds v^(0..nst-1); lam_io holds dL/dv^(nst)
+ * on entry and dL/dv^(0) on exit; dL/dg is added to dg and dL/dLambda_cell
+ * (through the face means) to gLam. */
+static void lim_pass_reverse(const orc_grid* g, const double* Lam, const double* C,
+                             const double axis_scale[3], int32_t face_mean, double tau, int32_t nst,
+                             const double* b, const double* stages, double* lam_io, double* dg,
+                             double* gLam) {
+    int64_t N = ncells(g);
+    double* wv = dalloc(N);
+    double* div = dalloc(N);
+    for (int32_t m = nst; m >= 1; --m) {
+        double tb = tau * b[m - 1];
+        double cm = 1.0 / (1.0 + tb);
+        const double* vp = stages + (int64_t)(m - 1) * N;
+        for (int64_t i = 0; i < N; ++i) dg[i] += cm * lam_io[i];
+        /* Stage m: v^(m)_a = cm (g_a + tb v_a - tau/C_a sum_f w Lambda_f (v_a - v_b)),
+         * v = v^(m-1).  Lambda_f enters rows a and b:
+         * dL/dLambda_f = cm tau w (v_b - v_a)(lambda_a/C_a - lambda_b/C_b),
+         * the same number from either side; each side adds its own share
+         * dLambda_f/dLambda_cell. */
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int64_t k = 0; k < g->n[2]; ++k)
+            for (int64_t j = 0; j < g->n[1]; ++j)
+                for (int64_t i = 0; i < g->n[0]; ++i) {
+                    int64_t a = i + g->n[0] * (j + g->n[1] * k);
+                    cell_faces f;
+                    faces_of(g, axis_scale, i, j, k, &f);
+                    double s = 0.0;
+                    for (int q = 0; q < f.count; ++q) {
+                        int64_t bb = f.nb[q];
+                        double G = cm * tau * f.w[q] * (vp[bb] - vp[a]) *
+                                   (lam_io[a] / C[a] - lam_io[bb] / C[bb]);
+                        s += G * face_partial(Lam[a], Lam[bb], face_mean);
+                    }
+                    gLam[a] += s;
+                }
+        /* lambda^(m-1) = cm (tb lambda^(m) - tau D C^-1 lambda^(m)), D w = -div(w):
+         * A = C^-1 D with D symmetric, so A^T = D C^-1. */
+        for (int64_t i = 0; i < N; ++i) wv[i] = lam_io[i] / C[i];
+        face_flux_divergence(g, Lam, axis_scale, face_mean, wv, div);
+        for (int64_t i = 0; i < N; ++i) lam_io[i] = cm * (tb * lam_io[i] + tau * div[i]);
+    }
+    free(wv);
+    free(div);
+}
+
+int32_t orc_heat_adjoint(const orc_grid* g, const orc_phase ph[2], const orc_opts* o, int32_t nsteps,
+                         const double* lamsched, const double* alpha2, const double* m1,
+                         const double* m2, const double* T0, const double* dL_dTN, double* dL_dT0,
+                         double* dL_dk0, double* TN) {
+    if (ph[0].pinf != ph[1].pinf || o->cycle_mode || o->do_viscous) return 1;
+    int64_t N = ncells(g);
+    int32_t np = o->passes;
+    double tau = o->tau;
+    double* C = dalloc(N);
+    double* Lam = dalloc(N);
+    double* Tsteps = dalloc(N * (nsteps + 1));
+    double* Tpass = dalloc(N * (np + 1));
+    double* mu = dalloc(N);
+    double* acc = dalloc(N);
+    double* dg = dalloc(N);
+    double* gLam = dalloc(N);
+    int32_t Pmax = 1;
+    for (int32_t k = 0; k < nsteps * np; ++k) {
+        int32_t P = orc_lim_P(tau, lamsched[k]);
+        if (P > Pmax) Pmax = P;
+    }
+    int64_t stride = (int64_t)(2 * Pmax - 1) * N;
+    double* stages = dalloc(stride * np);
+    double* b = dalloc(2 * Pmax - 1);
+    /* alpha2 is frozen and C constant when p_inf,1 = p_inf,2. */
+    orc_heat_capacity(g, ph, o->alpha_eps, alpha2, m1, m2, T0, C);
+
+    /* Forward sweep, keeping T^n of every step. */
+    memcpy(Tsteps, T0, sizeof(double) * (size_t)N);
+    for (int32_t n = 0; n < nsteps; ++n) {
+        const double* Tn = Tsteps + (int64_t)n * N;
+        memcpy(Tpass, Tn, sizeof(double) * (size_t)N);
+        for (int32_t it = 0; it < np; ++it) {
+            double lam = lamsched[n * np + it];
+            int32_t P = orc_lim_P(tau, lam), nst = 2 * P - 1;
+            orc_lim_params(P, lam, o->order, b);
+            orc_cell_conductivity(g, ph, alpha2, Tpass + (int64_t)it * N, Lam);
+            orc_lim_pass(g, Lam, C, UNIT_SCALE, o->face_mean, tau, nst, b, Tn, Tn,
+                         Tpass + (int64_t)(it + 1) * N, NULL);
+        }
+        memcpy(Tsteps + (int64_t)(n + 1) * N, Tpass + (int64_t)np * N, sizeof(double) * (size_t)N);
+    }
+    if (TN) memcpy(TN, Tsteps + (int64_t)nsteps * N, sizeof(double) * (size_t)N);
+
+    /* Reverse sweep. */
+    memcpy(mu, dL_dTN, sizeof(double) * (size_t)N);
+    dL_dk0[0] = dL_dk0[1] = 0.0;
+    for (int32_t n = nsteps - 1; n >= 0; --n) {
+        const double* Tn = Tsteps + (int64_t)n * N;
+        /* Recompute the passes of this step, keeping T^(it) and every stage. */
+        memcpy(Tpass, Tn, sizeof(double) * (size_t)N);
+        for (int32_t it = 0; it < np; ++it) {
+            double lam = lamsched[n * np + it];
+            int32_t P = orc_lim_P(tau, lam), nst = 2 * P - 1;
+            orc_lim_params(P, lam, o->order, b);
+            orc_cell_conductivity(g, ph, alpha2, Tpass + (int64_t)it * N, Lam);
+            orc_lim_pass(g, Lam, C, UNIT_SCALE, o->face_mean, tau, nst, b, Tn, Tn,
+                         Tpass + (int64_t)(it + 1) * N, stages + it * stride);
+        }
+        /* mu = dL/dT^{n+1}, the adjoint of the last pass's output; acc collects dL/dT^n. */
+        memset(acc, 0, sizeof(double) * (size_t)N);
+        for (int32_t it = np - 1; it >= 0; --it) {
+            double lam = lamsched[n * np + it];
+            int32_t P = orc_lim_P(tau, lam), nst = 2 * P - 1;
+            orc_lim_params(P, lam, o->order, b);
+            const double* Tit = Tpass + (int64_t)it * N;
+            orc_cell_conductivity(g, ph, alpha2, Tit, Lam);
+            memset(dg, 0, sizeof(double) * (size_t)N);
+            memset(gLam, 0, sizeof(double) * (size_t)N);
+            lim_pass_reverse(g, Lam, C, UNIT_SCALE, o->face_mean, tau, nst, b, stages + it * stride,
+                             mu, dg, gLam);
+            /* The pass reads T^n twice: as g and as v^(0). */
+            for (int64_t i = 0; i < N; ++i) acc[i] += dg[i] + mu[i];
+            /* Lambda_i = sum_k alpha_k k0_k (T_i/T0_k)^n_k, evaluated at T^(it). */
+            for (int64_t i = 0; i < N; ++i) {
+                double a2 = alpha2[i], a1 = 1.0 - a2;
+                dL_dk0[0] += gLam[i] * a1 * pow(Tit[i] / ph[0].T0, ph[0].npow);
+                dL_dk0[1] += gLam[i] * a2 * pow(Tit[i] / ph[1].T0, ph[1].npow);
+                mu[i] = gLam[i] * (a1 * conductivity_dT(&ph[0], Tit[i]) +
+                                   a2 * conductivity_dT(&ph[1], Tit[i]));
+            }
+            /* T^(1) = T^n, so the first pass's coefficient gradient is T^n's;
+             * otherwise mu is the adjoint of the previous pass's output. */
+            if (it == 0)
+                for (int64_t i = 0; i < N; ++i) acc[i] += mu[i];
+        }
+        memcpy(mu, acc, sizeof(double) * (size_t)N);
+    }
+    memcpy(dL_dT0, mu, sizeof(double) * (size_t)N);
+    free(C);
+    free(Lam);
+    free(Tsteps);
+    free(Tpass);
+    free(mu);
+    free(acc);
+    free(dg);
+    free(gLam);
+    free(stages);
+    free(b);
+    return 0;
+}

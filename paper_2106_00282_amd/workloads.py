@@ -1,0 +1,196 @@
+"""Seeded synthetic two-phase workloads.
+
+This module only builds inputs: grids, material constants and initial
+fields.  It holds none of the method's arithmetic (no coefficients, no
+spectral bound, no time step) and serves the GPU path, the oracle and the
+benchmark alike.  The time step of a workload is given as a multiple ``dt_factor``
+of the explicit stability limit 2/lambda_G of the initial post-relaxation
+state; whoever runs the workload evaluates lambda_G with its own code.
+
+Arrays are float64, C-contiguous, shaped (nz, ny, nx) with x fastest, on the
+unit box with cell centres at (i + 1/2) h.
+
+Materials (every workload): ideal gases (p_inf = q = 0), rho = (1, 10),
+C_v = (1, 0.5) so rho*C_v = (1, 5), gamma = (3.0, 1.4) so that
+(gamma_k - 1) rho_k C_v,k is the same for both phases and an initial state
+with T_1 = T_2 is in pressure equilibrium.  Conductivity
+lambda_k(T) = k0_k (T/T0)^n with T0 = 1.
+
+Workloads (sizes are parameters; the defaults are the full sizes):
+  heat1d     1024 cells, adiabatic; alpha_1 = (1 - tanh((x-1/2)/(3h)))/2,
+             k = (1, 0.1) constant, T = 2 left of 1/2 and 1 right; one
+             step at 100x the explicit limit.
+  levelset2d 1024^2 periodic; alpha_1 = (1 - tanh(phi/(2h)))/2 of a level set
+             of 8 random sinusoids with wavenumbers 1..6 scaled to unit
+             gradient; T lognormal (sigma 0.2) about 1; k0 = (1, 0.05),
+             n = 2; 10 steps at 200x, 3 Picard passes.
+  bubbles3d  256^3 periodic, 20 spheres of radius 10..30 cells (of a 256
+             grid) of phase 2 with a temperature jump of up to 2x and a
+             smooth velocity bump each; viscosity (1e-2, 1e-3); 5 steps.
+  levelset2d_adjoint  the level-set generator at 2048^2, 20 steps, loss
+             against a target made with k0 scaled by 1.1.
+  interface3d  512^3, x adiabatic, y and z periodic; planar interface at
+             x = 1/2 perturbed by 12 cosine modes of amplitude 5 cells;
+             k0 = (1, 0.01); T = 1 + alpha_1; 10 steps.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SEED_BASE = 210600282
+PERIODIC, ADIABATIC = 0, 1
+
+
+def base_phases(k0=(1.0, 0.05), npow=2.0, mu=(0.0, 0.0)):
+    rho = (1.0, 10.0)
+    cv = (1.0, 0.5)
+    gamma = (3.0, 1.4)
+    return [dict(gamma=gamma[k], pinf=0.0, cv=cv[k], q=0.0, k0=k0[k], T0=1.0, npow=npow,
+                 mu=mu[k], rho=rho[k]) for k in range(2)]
+
+
+def _streams(config_id: int, n: int):
+    ss = np.random.SeedSequence(SEED_BASE + config_id)
+    return [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(n)]
+
+
+def _centres(n: int):
+    return (np.arange(n, dtype=np.float64) + 0.5) / n
+
+
+def _finish(name, n, bc, phases, alpha1, T, dt_factor, steps, passes, vel=None, extra=None):
+    alpha1 = np.ascontiguousarray(alpha1, dtype=np.float64)
+    alpha2 = np.ascontiguousarray(1.0 - alpha1)
+    rho = [p["rho"] for p in phases]
+    fields = dict(alpha2=alpha2,
+                  m1=np.ascontiguousarray(alpha1 * rho[0]),
+                  m2=np.ascontiguousarray(alpha2 * rho[1]),
+                  T1=np.ascontiguousarray(T, dtype=np.float64),
+                  T2=np.ascontiguousarray(T, dtype=np.float64).copy())
+    if vel is not None:
+        for key, arr in zip(("u", "v", "w"), vel):
+            if arr is not None:
+                fields[key] = np.ascontiguousarray(arr, dtype=np.float64)
+    h = tuple(1.0 / x if x > 1 else 1.0 for x in n)
+    wl = dict(name=name, n=tuple(n), h=h, bc=tuple(bc), phases=phases, fields=fields,
+              dt_factor=float(dt_factor), steps=int(steps), passes=int(passes),
+              viscous=vel is not None)
+    if extra:
+        wl.update(extra)
+    return wl
+
+
+def heat1d(nx: int = 1024):
+    """Two-phase 1D conduction: one implicit step at 100x the explicit limit."""
+    phases = base_phases(k0=(1.0, 0.1), npow=0.0)
+    x = _centres(nx)
+    h = 1.0 / nx
+    alpha1 = 0.5 * (1.0 - np.tanh((x - 0.5) / (3.0 * h)))
+    T = np.where(x < 0.5, 2.0, 1.0)
+    return _finish("heat1d", (nx, 1, 1), (ADIABATIC, PERIODIC, PERIODIC), phases,
+                   alpha1.reshape(1, 1, nx), T.reshape(1, 1, nx), 100.0, 1, 1)
+
+
+def _levelset_fields(n: int, config_id: int):
+    rs_modes, rs_T = _streams(config_id, 2)
+    amp = rs_modes.uniform(0.5, 1.0, size=8)
+    kx = rs_modes.integers(1, 7, size=8) * rs_modes.choice([-1, 1], size=8)
+    ky = rs_modes.integers(1, 7, size=8) * rs_modes.choice([-1, 1], size=8)
+    theta = rs_modes.uniform(0.0, 2.0 * np.pi, size=8)
+    x = _centres(n)[None, :]
+    y = _centres(n)[:, None]
+    phi = np.zeros((n, n))
+    gx = np.zeros((n, n))
+    gy = np.zeros((n, n))
+    for j in range(8):
+        arg = 2.0 * np.pi * (kx[j] * x + ky[j] * y) + theta[j]
+        phi += amp[j] * np.sin(arg)
+        c = amp[j] * np.cos(arg) * 2.0 * np.pi
+        gx += c * kx[j]
+        gy += c * ky[j]
+    phi /= np.sqrt(gx * gx + gy * gy).max()
+    h = 1.0 / n
+    alpha1 = 0.5 * (1.0 - np.tanh(phi / (2.0 * h)))
+    T = np.exp(0.2 * rs_T.standard_normal((n, n)))
+    return alpha1.reshape(1, n, n), T.reshape(1, n, n)
+
+
+def levelset2d(n: int = 1024, steps: int = 10):
+    """2D periodic two-phase conduction with T^2 conductivities, 200x limit."""
+    phases = base_phases(k0=(1.0, 0.05), npow=2.0)
+    alpha1, T = _levelset_fields(n, 2)
+    return _finish("levelset2d", (n, n, 1), (PERIODIC,) * 3, phases, alpha1, T, 200.0, steps, 3)
+
+
+def levelset2d_adjoint(n: int = 2048, steps: int = 20):
+    """The level-set workload with a misfit loss for the adjoint: target made
+    with k0 scaled by 1.1 (both phases), same initial fields and time step."""
+    phases = base_phases(k0=(1.0, 0.05), npow=2.0)
+    alpha1, T = _levelset_fields(n, 2)
+    rs = _streams(4, 1)[0]
+    N = n * n
+    probe = rs.choice(N, size=16, replace=False)
+    return _finish("levelset2d_adjoint", (n, n, 1), (PERIODIC,) * 3, phases, alpha1, T, 200.0,
+                   steps, 3, extra=dict(target_k0_scale=1.1, fd_cells=np.sort(probe)))
+
+
+def bubbles3d(n: int = 256, steps: int = 5, nbubbles: int = 20):
+    """3D periodic bubbles with temperature jumps and velocity, plus viscosity."""
+    phases = base_phases(k0=(1.0, 0.05), npow=2.0, mu=(1e-2, 1e-3))
+    rs_c, rs_r, rs_J, rs_u = _streams(3, 4)
+    centres = rs_c.uniform(0.0, 1.0, size=(nbubbles, 3))
+    radii = rs_r.uniform(10.0, 30.0, size=nbubbles) / 256.0
+    jumps = rs_J.uniform(1.0, 2.0, size=nbubbles)
+    uvec = 0.1 * rs_u.uniform(-1.0, 1.0, size=(nbubbles, 3))
+    h = 1.0 / n
+    c = _centres(n)
+    alpha2 = np.zeros((n, n, n))
+    Tbump = np.zeros((n, n, n))
+    vel = [np.zeros((n, n, n)) for _ in range(3)]
+    for b in range(nbubbles):
+        # periodic distance along each axis (z, y, x order of the array)
+        dz = np.abs(c - centres[b, 2]); dz = np.minimum(dz, 1.0 - dz)
+        dy = np.abs(c - centres[b, 1]); dy = np.minimum(dy, 1.0 - dy)
+        dx = np.abs(c - centres[b, 0]); dx = np.minimum(dx, 1.0 - dx)
+        r = np.sqrt(dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2)
+        s = 0.5 * (1.0 - np.tanh((r - radii[b]) / (2.0 * h)))
+        np.maximum(alpha2, s, out=alpha2)
+        np.maximum(Tbump, (jumps[b] - 1.0) * s, out=Tbump)
+        for d in range(3):
+            vel[d] += uvec[b, d] * s
+    T = 1.0 + Tbump
+    return _finish("bubbles3d", (n, n, n), (PERIODIC,) * 3, phases, 1.0 - alpha2, T, 200.0,
+                   steps, 3, vel=vel)
+
+
+def interface3d(n: int = 512, steps: int = 10, nmodes: int = 12):
+    """3D perturbed planar interface, conductivity contrast 100."""
+    phases = base_phases(k0=(1.0, 0.01), npow=2.0)
+    rs = _streams(5, 1)[0]
+    modes = []
+    while len(modes) < nmodes:
+        m, q = (int(v) for v in rs.integers(0, 7, size=2))
+        if (m, q) != (0, 0) and (m, q) not in modes:
+            modes.append((m, q))
+    amp = rs.uniform(0.5, 1.0, size=nmodes)
+    theta = rs.uniform(0.0, 2.0 * np.pi, size=nmodes)
+    h = 1.0 / n
+    c = _centres(n)
+    y = c[:, None]
+    z = c[None, :]
+    pert = np.zeros((n, n))
+    for j, (m, q) in enumerate(modes):
+        pert += amp[j] * np.cos(2.0 * np.pi * (m * y + q * z) + theta[j])
+    pert *= 5.0 * h / np.abs(pert).max()
+    xint = 0.5 + pert  # indexed (y, z)
+    x = c
+    alpha1 = np.empty((n, n, n))
+    for k in range(n):  # z
+        alpha1[k] = 0.5 * (1.0 - np.tanh((x[None, :] - xint[:, k][:, None]) / (2.0 * h)))
+    T = 1.0 + alpha1
+    return _finish("interface3d", (n, n, n), (ADIABATIC, PERIODIC, PERIODIC), phases, alpha1, T,
+                   200.0, steps, 3)
+
+
+WORKLOADS = dict(heat1d=heat1d, levelset2d=levelset2d, bubbles3d=bubbles3d,
+                 levelset2d_adjoint=levelset2d_adjoint, interface3d=interface3d)
