@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the parabolic sub-step on one MI355X.
+
+Workload (a step = one parabolic step = temperature relaxation + 3 Picard
+passes, each a coefficient build, a Gershgorin bound and one LIM pass of
+2P-1 stencil sweeps): the 2D level-set case, 1024^2 periodic cells, two
+phases with conductivities k0 (T/T0)^2, k0 = (1, 0.05), rho*C_v = (1, 5),
+T lognormal (sigma 0.2), dt = 200x the explicit limit, 10 steps by
+default.  Inputs are seeded and synthetic, resident in HBM before the timed
+region.
+
+Reported (one JSON line):
+  value      FP64 cell-updates per second (N * sweeps / wall time of the steps)
+  fp32       the same for the FP32 form and its speedup over FP64
+  roofline   dominant kernel (the LIM sweep): algorithmic bytes per launch /
+             average launch time from HIP events on the library's stream
+  adjoint    adjoint / forward time on the 2048^2, 20-step adjoint workload
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per cell-update of one sweep launch: read v, rhs, Lambda,
+# 1/C and write v, one word each (stencil neighbours come from cache).
+BYTES_PER_UPDATE = {"fp64": 5 * 8, "fp32": 5 * 4}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_steps(solver, wl, opts, steps, reset=True):
+    import torch
+    if reset:
+        solver.set_workload(wl)
+    oc = opts.c()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = solver.advance_raw(oc)
+        if st != 0:
+            raise RuntimeError(f"tlim_advance returned {st}")
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def measure(precision, wl, tau, steps, warmup):
+    """Wall time of `steps` steps, then a second, identical run with sweep
+    events for the sweep count and the per-launch kernel time."""
+    from paper_2106_00282_amd.tlim import Solver, StepOpts
+    s = Solver(wl["n"], wl["h"], wl["bc"], precision=precision)
+    opts = StepOpts(dt=tau, passes=wl["passes"])
+    if warmup:
+        run_steps(s, wl, opts, warmup)
+    wall = run_steps(s, wl, opts, steps)
+    s.set_workload(wl)
+    sweeps = launches = 0
+    sweep_ms = 0.0
+    topts = StepOpts(dt=tau, passes=wl["passes"], time_sweeps=1)
+    for _ in range(steps):
+        st, rep = s.advance(topts)
+        sweeps += rep["sweeps"]
+        launches += rep["sweep_launches"]
+        sweep_ms += rep["sweep_ms"]
+    N = s.N
+    return dict(wall_s=wall, sweeps=sweeps, launches=launches, sweep_ms=sweep_ms, N=N,
+                gupd=N * sweeps / wall / 1e9)
+
+
+def adjoint_ratio():
+    """Adjoint / forward time on the 2048^2 level-set workload, 20 steps,
+    FP64, checkpoint every step (forward includes writing the checkpoints)."""
+    import torch
+    from paper_2106_00282_amd import workloads as W
+    from paper_2106_00282_amd.tlim import Solver, StepOpts
+    wl = W.levelset2d_adjoint(2048, 20)
+    s = Solver(wl["n"], wl["h"], wl["bc"])
+    s.set_workload(wl)
+    tau = wl["dt_factor"] * 2.0 / s.spectral_bound()
+    opts = StepOpts(dt=tau, passes=3)
+    steps = wl["steps"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ckpt, lam = s.forward_checkpointed(opts, steps, 1)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    TN = s.get_field("T1")
+    g = TN - torch.from_numpy(wl["fields"]["T1"]).to(TN.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.adjoint(opts, steps, 1, ckpt, lam, g)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    return dict(workload="levelset2d_adjoint 2048^2, 20 steps x 3 passes, FP64, checkpoint every step",
+                forward_s=round(t_fwd, 4), adjoint_s=round(t_adj, 4), ratio=round(t_adj / t_fwd, 3))
+
+
+def cpu_baseline(wl, tau, budget_s=12.0):
+    """The FP64 oracle, as it is, on whole steps of the same workload until
+    about budget_s of CPU time has passed."""
+    from oracle import oracle as orc
+    orc.build(force=False)
+    g = orc.make_grid(wl["n"], wl["h"], wl["bc"])
+    f = {k: v.copy() for k, v in wl["fields"].items()}
+    opts = orc.StepOpts(tau=tau, passes=wl["passes"])
+    updates, steps = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and steps < wl["steps"]:
+        st, rep = orc.step(g, wl["phases"], opts, f)
+        updates += wl["n"][0] * wl["n"][1] * wl["n"][2] * sum(2 * p - 1 for p in rep["P"])
+        steps += 1
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=round(updates / dt / 1e9, 5), unit="Gcell-updates/s", cores=cores, kind="oracle",
+                sample=f"first {steps} of the {wl['steps']} steps of the benchmark workload "
+                       f"({wl['n'][0]}x{wl['n'][1]}), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1024, help="cells per axis of the level-set workload")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--fp64-only", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding "
+              "notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2106_00282_amd import workloads as W
+    from paper_2106_00282_amd.tlim import Solver
+
+    wl = W.levelset2d(args.n, steps=args.steps)
+    probe = Solver(wl["n"], wl["h"], wl["bc"])
+    probe.set_workload(wl)
+    lam = probe.spectral_bound()
+    tau = wl["dt_factor"] * 2.0 / lam
+    del probe
+    log(f"workload levelset2d {args.n}^2, tau*lambda_G = {tau * lam:.1f}")
+
+    r64 = measure("fp64", wl, tau, args.steps, args.warmup)
+    log("fp64", r64)
+    r32 = None if args.fp64_only else measure("fp32", wl, tau, args.steps, args.warmup)
+    if r32:
+        log("fp32", r32)
+    adj = None if args.no_adjoint else adjoint_ratio()
+    if adj:
+        log("adjoint", adj)
+
+    avg_launch_ms = r64["sweep_ms"] / max(r64["launches"], 1)
+    bytes_per_launch = r64["N"] * BYTES_PER_UPDATE["fp64"] * (r64["sweeps"] / max(r64["launches"], 1))
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if avg_launch_ms > 0 else None
+    out = {
+        "metric": "Gcell-updates/s per Chebyshev sweep (FP64 vs FP32), HBM GB/s, adjoint/fwd",
+        "value": round(r64["gupd"], 4),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r64["wall_s"] / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"levelset2d {args.n}x{args.n} periodic, two phases, k=k0 (T/T0)^2, "
+                               f"dt=200x explicit limit, 3 Picard passes, {args.steps} steps",
+                   "cells": r64["N"], "sweeps_per_run": r64["sweeps"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
+                     "kernel": "LIM sweep (FP64)", "avg_launch_us": round(avg_launch_ms * 1e3, 3),
+                     "bytes_per_launch": int(bytes_per_launch)},
+    }
+    if r32:
+        l32 = r32["sweep_ms"] / max(r32["launches"], 1)
+        b32 = r32["N"] * BYTES_PER_UPDATE["fp32"] * (r32["sweeps"] / max(r32["launches"], 1))
+        out["fp32"] = {"value": round(r32["gupd"], 4), "unit": "Gcell-updates/s",
+                       "speedup_vs_fp64": round(r32["gupd"] / r64["gupd"], 3),
+                       "ms_per_step": round(r32["wall_s"] / args.steps * 1e3, 4),
+                       "sweep_GBs": round(b32 / (l32 * 1e-3) / 1e9, 1) if l32 > 0 else None}
+    if adj:
+        out["adjoint"] = adj
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, tau)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * tlim — parabolic sub-step (heat conduction + viscosity) of the
+ * two-temperature diffuse-interface model of Zhang, Menshov, Wang and Shen,
+ * "Diffuse interface relaxation model for two-phase compressible flows with
+ * diffusion processes" (arXiv 2106.00282), on one AMD Instinct MI355X
+ * (gfx950).
+ *
+ * One call of tlim_advance is one parabolic step of the paper's splitting
+ * (Sec. 3): the viscous part (Sec. 3.2, eq. viscous), instantaneous
+ * temperature relaxation in interface cells (Sec. 3.4.1) and heat conduction
+ * (Sec. 3.4.2, Algorithm 1).  Both diffusion problems are advanced with the
+ * method of local iterations with Chebyshev parameters (Sec. 3.2, eqs. LIM
+ * and LIM_last): 2P-1 explicit stencil sweeps,
+ * P = ceil(pi/4 sqrt(tau lambda_max + 1)), the last one in conservative
+ * flux form.  Heat conduction wraps the sweeps in a Picard loop with face
+ * conductivities lagged at the previous iterate (Algorithm 1).
+ *
+ * ---------------------------------------------------------------- conventions
+ * Memory.  Every pointer argument named *_dev is a device pointer on the
+ * device that was current at tlim_create; every other pointer is host
+ * memory.  The caller owns all memory, including the workspace it binds with
+ * tlim_bind_workspace; the library only borrows pointers during a call and
+ * never frees caller memory.  Fields are dense float64 arrays of
+ * nx*ny*nz values in C order with x fastest, index i + nx*(j + ny*k).
+ * Streams.  All device work of a context is enqueued on the HIP stream given
+ * to tlim_create (NULL = the null stream).  Calls that return values
+ * computed on the device (spectral bound, step report, adjoint k0
+ * gradient) synchronise that stream before returning; tlim_set_field and
+ * tlim_get_field do not.
+ * Errors.  Every entry point returns a tlim_status; nothing is thrown across
+ * the ABI.  TLIM_E_ARG leaves the context unchanged.  tlim_last_error gives
+ * a message for the last failing call on a context.
+ * Threading.  Contexts are independent; a context must not be used from two
+ * threads at once.
+ */
+#ifndef TLIM_H
+#define TLIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TLIM_OK = 0,
+    TLIM_E_ARG = 1,      /* invalid argument; nothing was changed */
+    TLIM_E_STATE = 2,    /* missing phase, field or workspace */
+    TLIM_E_HIP = 3,      /* a HIP runtime call failed */
+    TLIM_E_NOMEM = 4,    /* bound workspace smaller than required */
+    TLIM_E_NOCONV = 5,   /* Picard or cycle tolerance not met; fields hold the last iterate */
+    TLIM_E_NUMERIC = 6   /* non-finite or non-positive temperature found after a pass */
+} tlim_status;
+
+enum { TLIM_PERIODIC = 0, TLIM_ADIABATIC = 1 };         /* boundary per axis */
+enum { TLIM_FP64 = 0, TLIM_FP32 = 1 };                 /* arithmetic of the sweeps */
+enum { TLIM_ORDER_INTERLEAVED = 0, TLIM_ORDER_PAPER = 1, TLIM_ORDER_ASCENDING = 2 };
+enum { TLIM_FACE_ARITH = 0, TLIM_FACE_HARMONIC = 1 };
+
+/* Fields of the state (Sec. 3.4, data of Algorithm 1): volume fraction of
+ * phase 2, partial densities m_k = alpha_k rho_k (constant in this step),
+ * phase temperatures, velocity components, external heat sources I_k. */
+typedef enum {
+    TLIM_ALPHA2 = 0, TLIM_M1 = 1, TLIM_M2 = 2, TLIM_T1 = 3, TLIM_T2 = 4,
+    TLIM_U = 5, TLIM_V = 6, TLIM_W = 7, TLIM_SRC1 = 8, TLIM_SRC2 = 9,
+    TLIM_NFIELDS = 10
+} tlim_field;
+
+/* Cell-centred grid: n[0] cells along x, n[1] along y, n[2] along z (1 for
+ * unused axes), spacings h, boundary condition per axis. */
+typedef struct {
+    int64_t n[3];
+    double h[3];
+    int32_t bc[3];
+} tlim_grid;
+
+/* One phase: stiffened-gas EOS (eqs. eos_stiffened, eos_stiffened2:
+ * gamma, p_inf, C_v, q), conductivity lambda(T) = k0 (T/T0)^npow (Sec.
+ * 3.4.2 allows lambda = lambda(T)), dynamic viscosity mu (Sec. 3.2). */
+typedef struct {
+    double gamma, pinf, cv, q;
+    double k0, T0, npow;
+    double mu;
+} tlim_phase;
+
+/* Options of one parabolic step. */
+typedef struct {
+    double dt;                   /* time step tau > 0 */
+    int32_t passes;              /* Picard passes (maximum when picard_tol > 0), 1..64 */
+    double picard_tol;           /* stop when max|T^(it+1)-T^(it)|/max|T^(it+1)| < tol; 0 = run all */
+    int32_t order;               /* TLIM_ORDER_*: order of the 2P-2 inner Chebyshev parameters */
+    int32_t face_mean;           /* TLIM_FACE_*: face value of the cell conductivities */
+    int32_t cycle_mode;          /* 1: Chebyshev-Richardson cycles to the backward-Euler solution */
+    double cycle_tol;            /* cycle mode: relative residual target */
+    int32_t max_cycles;          /* cycle mode: cycle limit per pass */
+    double alpha_eps;            /* interface (mixed) cell: eps < alpha2 < 1 - eps */
+    int32_t do_viscous;          /* run the viscous sub-step first (needs U[,V[,W]]) */
+    const double* frozen_lambda; /* nullable, `passes` entries: lambda_max per pass instead of Gershgorin */
+    const double* frozen_visc;   /* nullable, 3 entries: lambda_max per velocity component */
+    int32_t time_sweeps;         /* 1: time the sweep launches with HIP events (report.sweep_ms) */
+} tlim_step_opts;
+
+#define TLIM_MAX_PASSES 64
+/* Per-step report, filled when a non-NULL pointer is passed. */
+typedef struct {
+    int32_t passes_run;
+    int32_t converged;
+    int32_t P[TLIM_MAX_PASSES];           /* Chebyshev parameter count per pass */
+    double lambda_G[TLIM_MAX_PASSES];     /* lambda_max used per pass */
+    double err[TLIM_MAX_PASSES];          /* Picard change per pass (Algorithm 1) */
+    int32_t cycles[TLIM_MAX_PASSES];      /* cycle mode: cycles per pass */
+    double residual[TLIM_MAX_PASSES];     /* cycle mode: final relative residual per pass */
+    int32_t visc_P[3];
+    double visc_lambda_G[3];
+    double energy_before, energy_after;   /* sum_i vol (sum_k C_k T_k + alpha_k p_inf,k) */
+    int64_t sweeps;                       /* stencil sweeps run (heat + viscous) */
+    int64_t sweep_launches;               /* sweep kernel launches (<= sweeps when fused) */
+    double sweep_ms;                      /* time_sweeps: summed event time of the sweep launches */
+    int64_t bad_cells;                    /* cells with non-finite or T <= 0 after the last pass */
+} tlim_step_report;
+
+typedef struct tlim_ctx tlim_ctx;
+
+/* Create a context for one grid.  precision = TLIM_FP64 or TLIM_FP32 (the
+ * FP32 form: stencil sweeps in float, state, energy, residual and Picard
+ * sums, relaxation and lambda_max in double).  hip_stream: hipStream_t or
+ * NULL.  Errors: TLIM_E_ARG for n < 1, h <= 0, an unknown bc or precision;
+ * TLIM_E_HIP if the device cannot be queried. */
+tlim_status tlim_create(const tlim_grid* grid, int32_t precision, void* hip_stream, tlim_ctx** out);
+
+/* Release a context (not the caller's memory).  NULL is accepted. */
+tlim_status tlim_destroy(tlim_ctx* ctx);
+
+/* Device workspace the context needs for state and stepping, in bytes. */
+tlim_status tlim_workspace_bytes(const tlim_ctx* ctx, size_t* bytes);
+
+/* Bind caller-allocated device memory (256-byte aligned, at least
+ * tlim_workspace_bytes) as the context's workspace.  Fields set before a
+ * new binding are lost.  Errors: TLIM_E_NOMEM if too small, TLIM_E_ARG if
+ * misaligned or NULL. */
+tlim_status tlim_bind_workspace(tlim_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Set phase k (0 or 1).  Errors: TLIM_E_ARG for k out of range, gamma <= 1,
+ * cv <= 0, k0 < 0, T0 <= 0 or mu < 0. */
+tlim_status tlim_set_phase(tlim_ctx* ctx, int32_t k, const tlim_phase* phase);
+
+/* Copy a field from caller device memory (dense float64, see conventions)
+ * into the context.  Sources are optional (absent = 0); velocity is needed
+ * only for the viscous sub-step. */
+tlim_status tlim_set_field(tlim_ctx* ctx, int32_t field, const double* src_dev);
+
+/* Copy a field out of the context into caller device memory. */
+tlim_status tlim_get_field(const tlim_ctx* ctx, int32_t field, double* dst_dev);
+
+/* Gershgorin bound lambda_G = max_i 2 d_i of the heat operator A = C^-1 D
+ * (Sec. 3.2 needs lambda_max of L_h; D from eq. qk_dis) for the current
+ * fields after temperature relaxation; the fields themselves are not
+ * changed.  The explicit stability limit is 2 / lambda_G.  Synchronises. */
+tlim_status tlim_spectral_bound(tlim_ctx* ctx, int32_t face_mean, double alpha_eps, double* lambda_out);
+
+/* Advance the fields by one parabolic step: viscous part (optional),
+ * temperature relaxation, Picard loop of LIM passes (Algorithm 1).
+ * report may be NULL.  Returns TLIM_E_NOCONV when picard_tol > 0 (or the
+ * cycle tolerance) was not met, TLIM_E_NUMERIC when a non-finite or
+ * non-positive temperature appears; in both cases the fields hold the last
+ * iterate.  Synchronises once per Picard pass (lambda_max readback). */
+tlim_status tlim_advance(tlim_ctx* ctx, const tlim_step_opts* opts, tlim_step_report* report);
+
+/* Forward run of nsteps heat steps with checkpoints for the adjoint: T^n is
+ * copied to ckpt_dev + (n / ckpt_every) * N before every step n with
+ * n % ckpt_every == 0 (so ckpt_dev holds ceil(nsteps/ckpt_every) fields),
+ * and lambda_max of every pass goes to lam_out[n * passes + it] (host).
+ * Requires equal p_inf of the two phases, no sources, no viscous part, no
+ * cycle mode, picard_tol = 0.  Relaxation is applied by tlim_advance as usual. */
+tlim_status tlim_forward_checkpointed(tlim_ctx* ctx, const tlim_step_opts* opts, int32_t nsteps,
+                                      int32_t ckpt_every, double* ckpt_dev, double* lam_out);
+
+/* Device scratch the adjoint needs for a schedule whose largest P is Pmax. */
+tlim_status tlim_adjoint_workspace_bytes(const tlim_ctx* ctx, const tlim_step_opts* opts,
+                                         int32_t Pmax, size_t* bytes);
+
+/* Discrete adjoint of nsteps heat steps with the frozen schedule lam
+ * (nsteps*passes host values, as written by tlim_forward_checkpointed):
+ * given dL/dT^N (dL_dTN_dev), returns dL/dT^0 (dL_dT0_dev, device) and
+ * dL/dk0 of both phases (dL_dk0, 2 host doubles).  Each step is recomputed
+ * from the nearest checkpoint, keeping every stage iterate in adj_ws_dev, and
+ * reversed stage by stage (lambda^(m-1) = c_m (tau b_m lambda^(m) -
+ * tau D C^-1 lambda^(m)), with the face-conductivity gradient chained
+ * through Lambda(T^(it)) of every Picard pass).  The forward model is the
+ * heat step without relaxation, which is the identity on the equilibrium
+ * states the forward run produces.  Same restrictions as
+ * tlim_forward_checkpointed; FP64 contexts only.  Synchronises. */
+tlim_status tlim_adjoint(tlim_ctx* ctx, const tlim_step_opts* opts, int32_t nsteps, int32_t ckpt_every,
+                         const double* ckpt_dev, const double* lam, const double* dL_dTN_dev,
+                         double* dL_dT0_dev, double* dL_dk0, void* adj_ws_dev, size_t adj_ws_bytes);
+
+/* Human-readable name of a status, and the last error message of a context. */
+const char* tlim_status_str(tlim_status s);
+const char* tlim_last_error(const tlim_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

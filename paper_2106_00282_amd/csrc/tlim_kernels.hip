@@ -1,0 +1,645 @@
+// gfx950 kernels of the parabolic sub-step (arXiv 2106.00282, Sec. 3.2 and
+// Sec. 3.4): temperature relaxation, coefficients, Gershgorin bound, LIM
+// stages in FP64 and in the FP32 correction form, the conservative final
+// stage, Picard reductions, cycle-mode residual and the adjoint stage.
+//
+// Layout: structure of arrays, one dense array per field, x fastest.
+// Stencil kernels run one work-item per cell on 64x4 tiles (a wave64 covers
+// 64 consecutive x cells, so every load is a coalesced 512 B / 256 B row);
+// the temporally blocked sweeps live in tlim_sweep.hip.
+// Reductions are two-level and deterministic: grid-stride blocks write
+// partials, one block folds them in a fixed order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "tlim_internal.h"
+
+namespace tlim {
+
+namespace {
+
+constexpr int TX = 64;
+constexpr int TY = 4;
+
+// ------------------------------------------------------------------ helpers
+
+// (T/T0)^n with the exponents the conductivity laws use written out, so the
+// common integer and half-integer cases are exact products.
+__device__ __forceinline__ double powlaw(double x, double n) {
+    if (n == 0.0) return 1.0;
+    if (n == 1.0) return x;
+    if (n == 2.0) return x * x;
+    if (n == 3.0) return x * x * x;
+    if (n == 2.5) return x * x * sqrt(x);
+    return pow(x, n);
+}
+
+template <typename R>
+__device__ __forceinline__ R face_mean(R a, R b, int face) {
+    if (face == 1) {
+        R s = a + b;
+        return s > R(0) ? R(2) * (a * b) / s : R(0);
+    }
+    return R(0.5) * (a + b);
+}
+
+template <typename R>
+__device__ __forceinline__ R face_partial(R a, R b, int face) {
+    if (face == 1) {
+        R s = a + b;
+        return s > R(0) ? R(2) * b * b / (s * s) : R(0);
+    }
+    return R(0.5);
+}
+
+// Neighbour offsets of cell (i,j,k): for each of the six faces, the linear
+// offset to the neighbour and whether the face exists (periodic wrap, no
+// face at an adiabatic end or on an axis of one cell).
+struct Faces {
+    int64_t off[6];
+    bool has[6];
+};
+
+__device__ __forceinline__ void faces_of(const DevGrid& g, int i, int j, int k, Faces& f) {
+    const int64_t sx = 1, sy = g.nx, sz = (int64_t)g.nx * g.ny;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int c[3] = {i, j, k};
+    const int64_t st[3] = {sx, sy, sz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        bool multi = n[d] > 1;
+        bool lo = c[d] > 0, hi = c[d] < n[d] - 1;
+        f.has[2 * d] = multi && (lo || g.per[d]);
+        f.off[2 * d] = lo ? -st[d] : (int64_t)(n[d] - 1) * st[d];
+        f.has[2 * d + 1] = multi && (hi || g.per[d]);
+        f.off[2 * d + 1] = hi ? st[d] : -(int64_t)(n[d] - 1) * st[d];
+    }
+}
+
+// S = sum_f w_f Lam_f (v_a - v_b), arithmetic in RA.
+template <typename RA, typename RV, typename RL>
+__device__ __forceinline__ RA stencil(const DevGrid& g, const Faces& f, int64_t a, const RV* __restrict__ v,
+                                      const RL* __restrict__ L, int face) {
+    RA va = (RA)v[a], La = (RA)L[a], S = RA(0);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        if (!f.has[q]) continue;
+        int64_t b = a + f.off[q];
+        S += (RA)g.w[q >> 1] * face_mean<RA>(La, (RA)L[b], face) * (va - (RA)v[b]);
+    }
+    return S;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block reductions for blockDim.x a multiple of 64 (<= 1024); the result is
+// valid in thread 0.
+__device__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    v = (int)threadIdx.x < nw ? sh[threadIdx.x] : 0.0;
+    if (wid == 0) v = wave_sum(v);
+    __syncthreads();
+    return v;
+}
+__device__ double block_max(double v, double* sh) {
+    v = wave_max(v);
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    v = (int)threadIdx.x < nw ? sh[threadIdx.x] : -INFINITY;
+    if (wid == 0) v = wave_max(v);
+    __syncthreads();
+    return v;
+}
+
+__device__ __forceinline__ void cell_ijk(const DevGrid& g, int64_t a, int& i, int& j, int& k) {
+    int64_t nxy = (int64_t)g.nx * g.ny;
+    k = (int)(a / nxy);
+    int64_t r = a - (int64_t)k * nxy;
+    j = (int)(r / g.nx);
+    i = (int)(r - (int64_t)j * g.nx);
+}
+
+__device__ __forceinline__ bool is_mixed(double a2, double eps) { return a2 > eps && a2 < 1.0 - eps; }
+
+// W = Gamma_1 C_1/alpha_1^2 + Gamma_2 C_2/alpha_2^2 (interface cells).
+__device__ __forceinline__ double pressure_stiffness(const DevPhases& ph, double a2, double C1, double C2) {
+    double a1 = 1.0 - a2;
+    return (ph.gamma[0] - 1.0) * C1 / (a1 * a1) + (ph.gamma[1] - 1.0) * C2 / (a2 * a2);
+}
+
+struct FinalizeSpec {
+    int op[kPartialStride];        // 0 none, 1 max, 2 sum
+    double* dst[kPartialStride];
+};
+
+__global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ partials, int nblocks,
+                                                  FinalizeSpec spec) {
+    __shared__ double sh[16];
+    for (int s = 0; s < kPartialStride; ++s) {
+        if (spec.op[s] == 0) continue;
+        bool isMax = spec.op[s] == 1;
+        double acc = isMax ? -INFINITY : 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+            double v = partials[(int64_t)b * kPartialStride + s];
+            acc = isMax ? fmax(acc, v) : acc + v;
+        }
+        acc = isMax ? block_max(acc, sh) : block_sum(acc, sh);
+        if (threadIdx.x == 0) *spec.dst[s] = acc;
+    }
+}
+
+int reduce_blocks(int64_t N) {
+    int64_t b = (N + kReduceThreads - 1) / kReduceThreads;
+    return (int)(b < kReduceBlocks ? (b > 0 ? b : 1) : kReduceBlocks);
+}
+
+dim3 tile_grid(const DevGrid& g) { return dim3((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, g.nz); }
+
+// -------------------------------------------------- temperature relaxation
+
+// End state of the relaxation system in an interface cell (Sec. 3.4.1):
+// phase energies summed conserve E = C1 T1 + C2 T2 + alpha_k p_inf,k, and
+// p_1 = p_2 at T_1 = T_2 = T'.  With B = p_inf,2 - p_inf,1,
+// T'(a) = (C1 T1 + C2 T2 + (alpha2^0 - a) B)/(C1 + C2) and
+// (p_1 - p_2) a (1-a) = A2 a^2 + A1 a + A0 is quadratic in a = alpha2'.
+// The root with 0 < a < 1 and T'(a) > 0 is taken (eq. Taverage when B = 0).
+__global__ void __launch_bounds__(256) k_relax(DevGrid g, DevPhases ph, double eps, double* alpha2,
+                                               const double* __restrict__ m1, const double* __restrict__ m2,
+                                               double* T1, double* T2) {
+    double B = ph.pinf[1] - ph.pinf[0];
+    double G1 = ph.gamma[0] - 1.0, G2 = ph.gamma[1] - 1.0;
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        double a20 = alpha2[a];
+        if (a20 <= eps) {
+            T2[a] = T1[a];
+            continue;
+        }
+        if (a20 >= 1.0 - eps) {
+            T1[a] = T2[a];
+            continue;
+        }
+        double C1 = m1[a] * ph.cv[0], C2 = m2[a] * ph.cv[1];
+        double S = C1 + C2;
+        double E = C1 * T1[a] + C2 * T2[a];
+        double t0 = (E + a20 * B) / S, t1 = -B / S;   // T'(a) = t0 + t1 a
+        double l0 = -G2 * C2, l1 = G1 * C1 + G2 * C2;  // L(a) = l0 + l1 a
+        double A2 = t1 * l1 - B, A1 = t0 * l1 + t1 * l0 + B, A0 = t0 * l0;
+        double root;
+        if (A2 == 0.0) {
+            root = -A0 / A1;
+        } else {
+            double disc = fmax(A1 * A1 - 4.0 * A2 * A0, 0.0);
+            double qq = -0.5 * (A1 + copysign(sqrt(disc), A1));
+            double r1 = qq / A2, r2 = A0 / qq;
+            bool ok1 = r1 > 0.0 && r1 < 1.0 && t0 + t1 * r1 > 0.0;
+            bool ok2 = r2 > 0.0 && r2 < 1.0 && t0 + t1 * r2 > 0.0;
+            root = ok1 ? r1 : r2;
+            if (ok1 && ok2) root = fabs(r1 - a20) < fabs(r2 - a20) ? r1 : r2;
+            if (!ok1 && !ok2) {
+                // rounding pushed the admissible root out: bisect the sign change
+                // of the quadratic on (lo, hi) = {0 < a < 1, T'(a) > 0}
+                double lo = 0.0, hi = 1.0;
+                if (t1 < 0.0) hi = fmin(hi, -t0 / t1);
+                if (t1 > 0.0) lo = fmax(lo, -t0 / t1);
+                for (int it = 0; it < 120; ++it) {
+                    double mid = 0.5 * (lo + hi);
+                    if ((A2 * mid + A1) * mid + A0 < 0.0) lo = mid;
+                    else hi = mid;
+                }
+                root = 0.5 * (lo + hi);
+            }
+            // two Newton steps on the quadratic polish the root
+            for (int it = 0; it < 2; ++it) {
+                double f = (A2 * root + A1) * root + A0, df = 2.0 * A2 * root + A1;
+                if (df != 0.0) root -= f / df;
+            }
+        }
+        double T = t0 + t1 * root;
+        alpha2[a] = root;
+        T1[a] = T;
+        T2[a] = T;
+    }
+}
+
+// ------------------------------------------------------------ coefficients
+
+__global__ void __launch_bounds__(256) k_heat_coeffs(DevGrid g, DevPhases ph, double eps, double tau,
+                                                     const double* __restrict__ T, const double* __restrict__ alpha2,
+                                                     const double* __restrict__ m1, const double* __restrict__ m2,
+                                                     const double* __restrict__ Tn, const double* __restrict__ src1,
+                                                     const double* __restrict__ src2, double* __restrict__ Lam,
+                                                     double* __restrict__ rC, double* __restrict__ rhs,
+                                                     float* __restrict__ Lam32, float* __restrict__ rC32) {
+    double B1 = ph.pinf[0] - ph.pinf[1];
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        double t = T[a], a2 = alpha2[a], a1 = 1.0 - a2;
+        double L = a1 * ph.k0[0] * powlaw(t / ph.T0[0], ph.npow[0]) + a2 * ph.k0[1] * powlaw(t / ph.T0[1], ph.npow[1]);
+        double C1 = m1[a] * ph.cv[0], C2 = m2[a] * ph.cv[1];
+        double C = C1 + C2;
+        if (B1 != 0.0 && is_mixed(a2, eps)) C += B1 * B1 / (t * t * pressure_stiffness(ph, a2, C1, C2));
+        double r = 1.0 / C;
+        double f = 0.0;
+        if (src1) f += a1 * src1[a];
+        if (src2) f += a2 * src2[a];
+        Lam[a] = L;
+        rC[a] = r;
+        rhs[a] = Tn[a] + tau * r * f;
+        if (Lam32) {
+            Lam32[a] = (float)L;
+            rC32[a] = (float)r;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_visc_coeffs(DevGrid g, DevPhases ph, const double* __restrict__ alpha2,
+                                                     const double* __restrict__ m1, const double* __restrict__ m2,
+                                                     double* __restrict__ Lam, double* __restrict__ rC,
+                                                     float* __restrict__ Lam32, float* __restrict__ rC32) {
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        double a2 = alpha2[a];
+        double mu = (1.0 - a2) * ph.mu[0] + a2 * ph.mu[1];
+        double r = 1.0 / (m1[a] + m2[a]);
+        Lam[a] = mu;
+        rC[a] = r;
+        if (Lam32) {
+            Lam32[a] = (float)mu;
+            rC32[a] = (float)r;
+        }
+    }
+}
+
+// --------------------------------------------------------------- reductions
+
+__global__ void __launch_bounds__(256) k_gershgorin(DevGrid g, int face, const double* __restrict__ Lam,
+                                                    const double* __restrict__ rC, double* partials) {
+    __shared__ double sh[16];
+    double mx = 0.0;
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        cell_ijk(g, a, i, j, k);
+        Faces f;
+        faces_of(g, i, j, k, f);
+        double d = 0.0, La = Lam[a];
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            if (f.has[q]) d += g.w[q >> 1] * face_mean<double>(La, Lam[a + f.off[q]], face);
+        mx = fmax(mx, 2.0 * d * rC[a]);
+    }
+    mx = block_max(mx, sh);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * kPartialStride + 4] = mx;
+}
+
+__global__ void __launch_bounds__(256) k_energy(DevGrid g, DevPhases ph, const double* __restrict__ alpha2,
+                                                const double* __restrict__ m1, const double* __restrict__ m2,
+                                                const double* __restrict__ T1, const double* __restrict__ T2,
+                                                double* partials) {
+    __shared__ double sh[16];
+    double e = 0.0;
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        double a2 = alpha2[a];
+        e += m1[a] * ph.cv[0] * T1[a] + m2[a] * ph.cv[1] * T2[a] + (1.0 - a2) * ph.pinf[0] + a2 * ph.pinf[1];
+    }
+    e = block_sum(e, sh);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * kPartialStride + 2] = e;
+}
+
+__global__ void __launch_bounds__(256) k_pass_update(DevGrid g, DevPhases ph, double eps,
+                                                     const double* __restrict__ Tit, const double* __restrict__ Tnew,
+                                                     const double* __restrict__ Tn, const double* __restrict__ alpha2n,
+                                                     const double* alpha2it, const double* __restrict__ m1,
+                                                     const double* __restrict__ m2, double* alpha2out,
+                                                     double* partials) {
+    __shared__ double sh[16];
+    double B1 = ph.pinf[0] - ph.pinf[1];
+    double dmax = 0.0, tmax = 0.0, bad = 0.0;
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        double tn = Tnew[a], ti = Tit[a];
+        dmax = fmax(dmax, fabs(tn - ti));
+        tmax = fmax(tmax, fabs(tn));
+        if (!(tn > 0.0) || isinf(tn)) bad += 1.0;
+        // d alpha2 = -B1/(T^2 W) dT from the step start, coefficient lagged at (T^(it), alpha2^(it))
+        if (B1 != 0.0 && is_mixed(alpha2n[a], eps)) {
+            double C1 = m1[a] * ph.cv[0], C2 = m2[a] * ph.cv[1];
+            double W = pressure_stiffness(ph, alpha2it[a], C1, C2);
+            alpha2out[a] = alpha2n[a] - B1 / (ti * ti * W) * (tn - Tn[a]);
+        }
+    }
+    double r0 = block_max(dmax, sh);
+    double r1 = block_max(tmax, sh);
+    double r3 = block_sum(bad, sh);
+    if (threadIdx.x == 0) {
+        double* p = partials + (int64_t)blockIdx.x * kPartialStride;
+        p[0] = r0;
+        p[1] = r1;
+        p[3] = r3;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_be_residual(DevGrid g, int face, const double* __restrict__ v,
+                                                     const double* __restrict__ rhs, const double* __restrict__ Lam,
+                                                     const double* __restrict__ rC, double tau, double* partials) {
+    __shared__ double sh[16];
+    double rr = 0.0, gg = 0.0;
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        cell_ijk(g, a, i, j, k);
+        Faces f;
+        faces_of(g, i, j, k, f);
+        double S = stencil<double, double, double>(g, f, a, v, Lam, face);
+        double C = 1.0 / rC[a];
+        double r = C * (rhs[a] - v[a]) - tau * S;
+        rr += r * r;
+        gg += (C * rhs[a]) * (C * rhs[a]);
+    }
+    double s0 = block_sum(rr, sh);
+    double s1 = block_sum(gg, sh);
+    if (threadIdx.x == 0) {
+        double* p = partials + (int64_t)blockIdx.x * kPartialStride;
+        p[5] = s0;
+        p[6] = s1;
+    }
+}
+
+// ------------------------------------------------------------ LIM stages
+
+__global__ void __launch_bounds__(256) k_stage64(DevGrid g, int face, const double* __restrict__ v,
+                                                 const double* __restrict__ rhs, const double* __restrict__ Lam,
+                                                 const double* __restrict__ rC, double* __restrict__ out,
+                                                 double cm, double tb, double tau) {
+    int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+    Faces f;
+    faces_of(g, i, j, k, f);
+    double S = stencil<double, double, double>(g, f, a, v, Lam, face);
+    out[a] = cm * (rhs[a] + tb * v[a] - tau * rC[a] * S);
+}
+
+__global__ void __launch_bounds__(256) k_final64(DevGrid g, int face, const double* __restrict__ v,
+                                                 const double* __restrict__ rhs, const double* __restrict__ Lam,
+                                                 const double* __restrict__ rC, double* __restrict__ out,
+                                                 double tau) {
+    int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+    Faces f;
+    faces_of(g, i, j, k, f);
+    // The flux w Lam_f (v_b - v_a) of a face is the same number with opposite
+    // sign when evaluated from its other cell, so sum_a C_a (out_a - rhs_a)
+    // cancels face by face (eq. LIM_last in conservative form).
+    double S = stencil<double, double, double>(g, f, a, v, Lam, face);
+    out[a] = rhs[a] - tau * rC[a] * S;
+}
+
+__global__ void __launch_bounds__(256) k_q32(DevGrid g, int face, const double* __restrict__ rhs,
+                                             const double* __restrict__ v0, const float* __restrict__ Lam32,
+                                             const float* __restrict__ rC32, double tau, float* __restrict__ q,
+                                             float* __restrict__ w0) {
+    int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+    Faces f;
+    faces_of(g, i, j, k, f);
+    double S = stencil<double, double, float>(g, f, a, rhs, Lam32, face);
+    q[a] = (float)(tau * (double)rC32[a] * S);
+    w0[a] = (float)(v0[a] - rhs[a]);
+}
+
+__global__ void __launch_bounds__(256) k_stage32(DevGrid g, int face, const float* __restrict__ w,
+                                                 const float* __restrict__ q, const float* __restrict__ Lam32,
+                                                 const float* __restrict__ rC32, float* __restrict__ out, float cm,
+                                                 float tb, float tau) {
+    int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+    Faces f;
+    faces_of(g, i, j, k, f);
+    float S = stencil<float, float, float>(g, f, a, w, Lam32, face);
+    out[a] = cm * (tb * w[a] - tau * rC32[a] * S - q[a]);
+}
+
+__global__ void __launch_bounds__(256) k_final32(DevGrid g, int face, const float* __restrict__ w,
+                                                 const double* __restrict__ rhs, const float* __restrict__ Lam32,
+                                                 const double* __restrict__ rC, double* __restrict__ out,
+                                                 double tau) {
+    int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+    Faces f;
+    faces_of(g, i, j, k, f);
+    double va = rhs[a] + (double)w[a], La = (double)Lam32[a], S = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        if (!f.has[q]) continue;
+        int64_t b = a + f.off[q];
+        S += g.w[q >> 1] * face_mean<double>(La, (double)Lam32[b], face) * (va - (rhs[b] + (double)w[b]));
+    }
+    out[a] = rhs[a] - tau * rC[a] * S;
+}
+
+// ----------------------------------------------------------------- adjoint
+
+__global__ void __launch_bounds__(256) k_adj_stage(DevGrid g, int face, const double* __restrict__ lam,
+                                                   const double* __restrict__ vprev, const double* __restrict__ Lam,
+                                                   const double* __restrict__ rC, double* __restrict__ lam_out,
+                                                   double* __restrict__ dg, double* __restrict__ gLam, double cm,
+                                                   double tb, double tau) {
+    int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+    Faces f;
+    faces_of(g, i, j, k, f);
+    double la = lam[a] * rC[a], La = Lam[a], va = vprev[a];
+    double Sadj = 0.0, G = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        if (!f.has[q]) continue;
+        int64_t b = a + f.off[q];
+        double Lb = Lam[b], lb = lam[b] * rC[b], w = g.w[q >> 1];
+        Sadj += w * face_mean<double>(La, Lb, face) * (lb - la);
+        G += cm * tau * w * (vprev[b] - va) * (la - lb) * face_partial<double>(La, Lb, face);
+    }
+    dg[a] += cm * lam[a];
+    gLam[a] += G;
+    lam_out[a] = cm * (tb * lam[a] + tau * Sadj);
+}
+
+__global__ void __launch_bounds__(256) k_adj_cell(DevGrid g, DevPhases ph, const double* __restrict__ Tit,
+                                                  const double* __restrict__ alpha2, const double* __restrict__ gLam,
+                                                  const double* __restrict__ dg, const double* __restrict__ lam0,
+                                                  double* __restrict__ acc, double* __restrict__ mu, int first_pass,
+                                                  double* partials) {
+    __shared__ double sh[16];
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        double t = Tit[a], a2 = alpha2[a], a1 = 1.0 - a2, gl = gLam[a];
+        double acc_a = acc[a] + dg[a] + lam0[a];
+        double x0 = t / ph.T0[0], x1 = t / ph.T0[1];
+        s0 += gl * a1 * powlaw(x0, ph.npow[0]);
+        s1 += gl * a2 * powlaw(x1, ph.npow[1]);
+        double dL = 0.0;
+        if (ph.npow[0] != 0.0) dL += a1 * ph.k0[0] * ph.npow[0] * powlaw(x0, ph.npow[0] - 1.0) / ph.T0[0];
+        if (ph.npow[1] != 0.0) dL += a2 * ph.k0[1] * ph.npow[1] * powlaw(x1, ph.npow[1] - 1.0) / ph.T0[1];
+        double m = gl * dL;
+        mu[a] = m;
+        acc[a] = first_pass ? acc_a + m : acc_a;
+    }
+    double r0 = block_sum(s0, sh);
+    double r1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) {
+        double* p = partials + (int64_t)blockIdx.x * kPartialStride;
+        p[0] = r0;
+        p[1] = r1;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fill(double* p, double v, int64_t n) {
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x)
+        p[a] = v;
+}
+
+__global__ void __launch_bounds__(256) k_copy(double* __restrict__ d, const double* __restrict__ s, int64_t n) {
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x)
+        d[a] = s[a];
+}
+
+void finalize(hipStream_t s, const double* partials, int nb, std::initializer_list<std::pair<int, double*>> slots,
+              int op) {
+    FinalizeSpec spec{};
+    for (auto& p : slots) {
+        spec.op[p.first] = op;
+        spec.dst[p.first] = p.second;
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, nb, spec);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launches
+
+void launch_relax(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double* alpha2,
+                  const double* m1, const double* m2, double* T1, double* T2) {
+    hipLaunchKernelGGL(k_relax, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, eps, alpha2, m1, m2,
+                       T1, T2);
+}
+
+void launch_heat_coeffs(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double tau,
+                        const double* T, const double* alpha2, const double* m1, const double* m2,
+                        const double* Tn, const double* src1, const double* src2, double* Lam, double* rC,
+                        double* rhs, float* Lam32, float* rC32) {
+    hipLaunchKernelGGL(k_heat_coeffs, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, eps, tau, T,
+                       alpha2, m1, m2, Tn, src1, src2, Lam, rC, rhs, Lam32, rC32);
+}
+
+void launch_visc_coeffs(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* alpha2,
+                        const double* m1, const double* m2, double* Lam, double* rC, float* Lam32, float* rC32) {
+    hipLaunchKernelGGL(k_visc_coeffs, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, alpha2, m1, m2,
+                       Lam, rC, Lam32, rC32);
+}
+
+void launch_gershgorin(hipStream_t s, const DevGrid& g, int face, const double* Lam, const double* rC,
+                       double* partials, PassResult* res) {
+    int nb = reduce_blocks(g.N);
+    hipLaunchKernelGGL(k_gershgorin, dim3(nb), dim3(kReduceThreads), 0, s, g, face, Lam, rC, partials);
+    finalize(s, partials, nb, {{4, &res->lambda}}, 1);
+}
+
+void launch_energy(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* alpha2, const double* m1,
+                   const double* m2, const double* T1, const double* T2, double* partials, PassResult* res) {
+    int nb = reduce_blocks(g.N);
+    hipLaunchKernelGGL(k_energy, dim3(nb), dim3(kReduceThreads), 0, s, g, ph, alpha2, m1, m2, T1, T2, partials);
+    finalize(s, partials, nb, {{2, &res->energy}}, 2);
+}
+
+void launch_stage64(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
+                    const double* Lam, const double* rC, double* out, double cm, double tb, double tau) {
+    hipLaunchKernelGGL(k_stage64, tile_grid(g), dim3(TX, TY), 0, s, g, face, v, rhs, Lam, rC, out, cm, tb, tau);
+}
+
+void launch_final64(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
+                    const double* Lam, const double* rC, double* out, double tau) {
+    hipLaunchKernelGGL(k_final64, tile_grid(g), dim3(TX, TY), 0, s, g, face, v, rhs, Lam, rC, out, tau);
+}
+
+void launch_q32(hipStream_t s, const DevGrid& g, int face, const double* rhs, const double* v0,
+                const float* Lam32, const float* rC32, double tau, float* q, float* w0) {
+    hipLaunchKernelGGL(k_q32, tile_grid(g), dim3(TX, TY), 0, s, g, face, rhs, v0, Lam32, rC32, tau, q, w0);
+}
+
+void launch_stage32(hipStream_t s, const DevGrid& g, int face, const float* w, const float* q,
+                    const float* Lam32, const float* rC32, float* out, float cm, float tb, float tau) {
+    hipLaunchKernelGGL(k_stage32, tile_grid(g), dim3(TX, TY), 0, s, g, face, w, q, Lam32, rC32, out, cm, tb, tau);
+}
+
+void launch_final32(hipStream_t s, const DevGrid& g, int face, const float* w, const double* rhs,
+                    const float* Lam32, const double* rC, double* out, double tau) {
+    hipLaunchKernelGGL(k_final32, tile_grid(g), dim3(TX, TY), 0, s, g, face, w, rhs, Lam32, rC, out, tau);
+}
+
+void launch_pass_update(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, const double* Tit,
+                        const double* Tnew, const double* Tn, const double* alpha2n, const double* alpha2it,
+                        const double* m1, const double* m2, double* alpha2out, double* partials,
+                        PassResult* res) {
+    int nb = reduce_blocks(g.N);
+    hipLaunchKernelGGL(k_pass_update, dim3(nb), dim3(kReduceThreads), 0, s, g, ph, eps, Tit, Tnew, Tn, alpha2n,
+                       alpha2it, m1, m2, alpha2out, partials);
+    finalize(s, partials, nb, {{0, &res->dmax}, {1, &res->tmax}}, 1);
+    finalize(s, partials, nb, {{3, &res->bad}}, 2);
+}
+
+void launch_be_residual(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
+                        const double* Lam, const double* rC, double tau, double* partials, PassResult* res) {
+    int nb = reduce_blocks(g.N);
+    hipLaunchKernelGGL(k_be_residual, dim3(nb), dim3(kReduceThreads), 0, s, g, face, v, rhs, Lam, rC, tau,
+                       partials);
+    finalize(s, partials, nb, {{5, &res->rr}, {6, &res->gg}}, 2);
+}
+
+void launch_adj_stage(hipStream_t s, const DevGrid& g, int face, const double* lam, const double* vprev,
+                      const double* Lam, const double* rC, double* lam_out, double* dg, double* gLam, double cm,
+                      double tb, double tau) {
+    hipLaunchKernelGGL(k_adj_stage, tile_grid(g), dim3(TX, TY), 0, s, g, face, lam, vprev, Lam, rC, lam_out, dg,
+                       gLam, cm, tb, tau);
+}
+
+void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* Tit, const double* alpha2,
+                     const double* gLam, const double* dg, const double* lam0, double* acc, double* mu,
+                     int first_pass, double* partials, PassResult* res) {
+    int nb = reduce_blocks(g.N);
+    hipLaunchKernelGGL(k_adj_cell, dim3(nb), dim3(kReduceThreads), 0, s, g, ph, Tit, alpha2, gLam, dg, lam0, acc,
+                       mu, first_pass, partials);
+    finalize(s, partials, nb, {{0, &res->k0g[0]}, {1, &res->k0g[1]}}, 2);
+}
+
+void launch_fill(hipStream_t s, double* p, double v, int64_t n) {
+    int64_t b = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096)), dim3(256), 0, s, p, v, n);
+}
+
+void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n) {
+    int64_t b = (n + 255) / 256;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096)), dim3(256), 0, s, dst, src, n);
+}
+
+}  // namespace tlim

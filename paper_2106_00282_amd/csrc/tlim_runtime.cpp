@@ -1,0 +1,852 @@
+// Host runtime and C ABI of the parabolic sub-step (see include/tlim.h).
+//
+// The runtime owns no device memory: the caller binds one workspace and the
+// context carves its fields and scratch out of it.  It computes the LIM
+// schedule on the host from the Gershgorin bound read back once per Picard
+// pass (the count of sweeps 2P-1 decides how many launches follow), and
+// enqueues everything else on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tlim.h"
+#include "tlim_internal.h"
+#include "tlim_sweep.h"
+
+using tlim::DevGrid;
+using tlim::DevPhases;
+using tlim::PassResult;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr size_t kAlign = 256;
+constexpr int kMaxEvents = 2 * (TLIM_MAX_PASSES + 4);
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+struct tlim_ctx {
+    int64_t n[3];
+    double h[3];
+    int32_t bc[3];
+    int64_t N;
+    int precision;
+    hipStream_t stream;
+    int device;
+    tlim_phase phase[2];
+    bool phase_set[2];
+    // workspace
+    char* ws;
+    size_t ws_bytes;
+    double* field[TLIM_NFIELDS];
+    bool fset[TLIM_NFIELDS];
+    double *Tn, *Tnew, *a2n, *Lam, *rC, *rhs, *vb[2], *partials;
+    float *Lam32, *rC32, *q32, *wb[2];
+    PassResult* res_dev;
+    PassResult* res_host;  // pinned
+    hipEvent_t ev[kMaxEvents];
+    std::string err;
+};
+
+namespace {
+
+tlim_status fail(tlim_ctx* c, tlim_status s, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define HIP_TRY(c, expr)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail((c), TLIM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// Layout of the workspace: byte offsets of every array (all 256-aligned).
+struct Layout {
+    size_t field[TLIM_NFIELDS];
+    size_t Tn, Tnew, a2n, Lam, rC, rhs, vb[2], partials, res;
+    size_t Lam32, rC32, q32, wb[2];
+    size_t total;
+};
+
+Layout layout_of(int64_t N, int precision) {
+    Layout L{};
+    size_t off = 0;
+    size_t d = align_up(sizeof(double) * (size_t)N), f = align_up(sizeof(float) * (size_t)N);
+    for (int i = 0; i < TLIM_NFIELDS; ++i) {
+        L.field[i] = off;
+        off += d;
+    }
+    size_t* dd[] = {&L.Tn, &L.Tnew, &L.a2n, &L.Lam, &L.rC, &L.rhs, &L.vb[0], &L.vb[1]};
+    for (size_t* p : dd) {
+        *p = off;
+        off += d;
+    }
+    L.partials = off;
+    off += align_up(sizeof(double) * tlim::kReduceBlocks * tlim::kPartialStride);
+    L.res = off;
+    off += align_up(sizeof(PassResult));
+    if (precision == TLIM_FP32) {
+        size_t* ff[] = {&L.Lam32, &L.rC32, &L.q32, &L.wb[0], &L.wb[1]};
+        for (size_t* p : ff) {
+            *p = off;
+            off += f;
+        }
+    }
+    L.total = off;
+    return L;
+}
+
+DevGrid dev_grid(const tlim_ctx* c, const double scale[3]) {
+    DevGrid g{};
+    g.nx = (int)c->n[0];
+    g.ny = (int)c->n[1];
+    g.nz = (int)c->n[2];
+    for (int d = 0; d < 3; ++d) {
+        g.per[d] = c->bc[d] == TLIM_PERIODIC;
+        g.w[d] = scale[d] / (c->h[d] * c->h[d]);
+    }
+    g.N = c->N;
+    return g;
+}
+
+const double kUnit[3] = {1.0, 1.0, 1.0};
+
+DevPhases dev_phases(const tlim_ctx* c) {
+    DevPhases p{};
+    for (int k = 0; k < 2; ++k) {
+        p.gamma[k] = c->phase[k].gamma;
+        p.pinf[k] = c->phase[k].pinf;
+        p.cv[k] = c->phase[k].cv;
+        p.k0[k] = c->phase[k].k0;
+        p.T0[k] = c->phase[k].T0;
+        p.npow[k] = c->phase[k].npow;
+        p.mu[k] = c->phase[k].mu;
+    }
+    return p;
+}
+
+// ---------------------------------------------------------------- schedule
+
+// Number of Chebyshev parameters of one LIM pass (Sec. 3.2).
+int lim_P(double tau, double lambda_max) { return (int)std::ceil(kPi / 4.0 * std::sqrt(tau * lambda_max + 1.0)); }
+
+// Parameters b_1..b_{2P-1} (Sec. 3.2): a_j = lambda (beta_1 - beta_j)/(1 + beta_1)
+// with beta_j = cos((2j-1) pi/(2P)) the roots of T_P, beta_1 the largest.  The
+// inner 2P-2 stages use every a_j (j >= 2) twice; order selects their sequence,
+// the last stage is always a_1 = 0.
+std::vector<double> lim_params(int P, double lambda_max, int order) {
+    std::vector<double> a(P + 1, 0.0);
+    const double beta1 = std::cos(kPi / (2.0 * P));
+    for (int j = 2; j <= P; ++j) a[j] = lambda_max / (1.0 + beta1) * (beta1 - std::cos((2.0 * j - 1.0) * kPi / (2.0 * P)));
+    std::vector<double> b;
+    b.reserve(2 * P - 1);
+    if (order == TLIM_ORDER_PAPER) {
+        for (int j = P; j >= 2; --j) b.push_back(a[j]);
+        for (int j = P; j >= 2; --j) b.push_back(a[j]);
+    } else if (order == TLIM_ORDER_ASCENDING) {
+        for (int j = 2; j <= P; ++j) {
+            b.push_back(a[j]);
+            b.push_back(a[j]);
+        }
+    } else {
+        // largest, smallest, second largest, second smallest, ... (twice): keeps
+        // every partial product of stage factors bounded, so round-off stays at
+        // the tau*lambda*eps floor of the final explicit stage
+        std::vector<double> once;
+        int lo = 2, hi = P;
+        bool take_hi = true;
+        while (lo <= hi) {
+            once.push_back(take_hi ? a[hi--] : a[lo++]);
+            take_hi = !take_hi;
+        }
+        b.insert(b.end(), once.begin(), once.end());
+        b.insert(b.end(), once.begin(), once.end());
+    }
+    b.push_back(0.0);
+    return b;
+}
+
+// Chebyshev-Richardson cycle of s stages: 1 + tau b_j at the Chebyshev nodes
+// of [1, 1 + tau lambda], increasing.
+std::vector<double> cycle_params(int s, double lambda_max) {
+    std::vector<double> b(s);
+    for (int k = 0; k < s; ++k) b[k] = 0.5 * lambda_max * (1.0 + std::cos((2.0 * (s - k) - 1.0) * kPi / (2.0 * s)));
+    return b;
+}
+
+// ------------------------------------------------------------------ checks
+
+tlim_status check_ready(tlim_ctx* c, bool need_T = true) {
+    if (!c->ws) return fail(c, TLIM_E_STATE, "no workspace bound");
+    if (!c->phase_set[0] || !c->phase_set[1]) return fail(c, TLIM_E_STATE, "both phases must be set");
+    const int need[] = {TLIM_ALPHA2, TLIM_M1, TLIM_M2, TLIM_T1, TLIM_T2};
+    for (int f : need)
+        if (need_T && !c->fset[f]) return fail(c, TLIM_E_STATE, "field %d not set", f);
+    return TLIM_OK;
+}
+
+tlim_status check_opts(tlim_ctx* c, const tlim_step_opts* o) {
+    if (!o) return fail(c, TLIM_E_ARG, "opts is NULL");
+    if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(c, TLIM_E_ARG, "dt must be finite and > 0");
+    if (o->passes < 1 || o->passes > TLIM_MAX_PASSES) return fail(c, TLIM_E_ARG, "passes out of range");
+    if (o->picard_tol < 0.0) return fail(c, TLIM_E_ARG, "picard_tol < 0");
+    if (o->order < 0 || o->order > 2) return fail(c, TLIM_E_ARG, "unknown order");
+    if (o->face_mean < 0 || o->face_mean > 1) return fail(c, TLIM_E_ARG, "unknown face_mean");
+    if (o->alpha_eps < 0.0 || o->alpha_eps >= 0.5) return fail(c, TLIM_E_ARG, "alpha_eps out of [0, 0.5)");
+    if (o->cycle_mode && (o->max_cycles < 1 || !(o->cycle_tol >= 0.0)))
+        return fail(c, TLIM_E_ARG, "cycle mode needs max_cycles >= 1 and cycle_tol >= 0");
+    if (o->cycle_mode && c->precision != TLIM_FP64) return fail(c, TLIM_E_ARG, "cycle mode runs in FP64 contexts");
+    if (o->do_viscous) {
+        for (int d = 0; d < 3; ++d)
+            if (c->n[d] > 1 && !c->fset[TLIM_U + d]) return fail(c, TLIM_E_STATE, "velocity component %d not set", d);
+    }
+    if (o->frozen_lambda)
+        for (int i = 0; i < o->passes; ++i)
+            if (!(o->frozen_lambda[i] >= 0.0) || !std::isfinite(o->frozen_lambda[i]))
+                return fail(c, TLIM_E_ARG, "frozen_lambda[%d] invalid", i);
+    return TLIM_OK;
+}
+
+// ---------------------------------------------------------- one LIM pass
+
+struct Timer {
+    tlim_ctx* c;
+    bool on;
+    int used = 0;
+    void start() {
+        if (on && used + 1 < kMaxEvents) (void)hipEventRecord(c->ev[used], c->stream);
+    }
+    void stop() {
+        if (on && used + 1 < kMaxEvents) {
+            (void)hipEventRecord(c->ev[used + 1], c->stream);
+            used += 2;
+        }
+    }
+    double elapsed_ms() {
+        double t = 0.0;
+        for (int i = 0; i + 1 < used; i += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess) t += ms;
+        }
+        return t;
+    }
+};
+
+struct SweepCount {
+    int64_t sweeps = 0, launches = 0;
+};
+
+// out = LIM pass (eqs. LIM, LIM_last) from v0 with right-hand side rhs and the
+// coefficients in c->Lam/c->rC (and their float copies in FP32 contexts).
+void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const std::vector<double>& b,
+                  const double* v0, const double* rhs, double* out, Timer& tm, SweepCount& sc) {
+    const int nst = (int)b.size();
+    hipStream_t s = c->stream;
+    tm.start();
+    if (c->precision == TLIM_FP32) {
+        tlim::launch_q32(s, g, face, rhs, v0, c->Lam32, c->rC32, tau, c->q32, c->wb[0]);
+        const float* cur = c->wb[0];
+        int m = 0;
+        while (m < nst - 1) {
+            int done = tlim::launch_sweeps32(s, g, face, cur, c->q32, c->Lam32, c->rC32,
+                                             cur == c->wb[0] ? c->wb[1] : c->wb[0], b.data() + m, nst - 1 - m,
+                                             tau);
+            cur = cur == c->wb[0] ? c->wb[1] : c->wb[0];
+            m += done;
+            sc.launches++;
+        }
+        tlim::launch_final32(s, g, face, cur, rhs, c->Lam32, c->rC, out, tau);
+    } else {
+        const double* cur = v0;
+        int m = 0;
+        int pp = 0;
+        while (m < nst - 1) {
+            double* nxt = c->vb[pp];
+            int done = tlim::launch_sweeps64(s, g, face, cur, rhs, c->Lam, c->rC, nxt, b.data() + m, nst - 1 - m, tau);
+            cur = nxt;
+            pp ^= 1;
+            m += done;
+            sc.launches++;
+        }
+        tlim::launch_final64(s, g, face, cur, rhs, c->Lam, c->rC, out, tau);
+    }
+    sc.launches++;
+    sc.sweeps += nst;
+    tm.stop();
+}
+
+tlim_status read_result(tlim_ctx* c) {
+    HIP_TRY(c, hipMemcpyAsync(c->res_host, c->res_dev, sizeof(PassResult), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TLIM_OK;
+}
+
+double cell_volume(const tlim_ctx* c) { return c->h[0] * c->h[1] * c->h[2]; }
+
+// Viscous sub-step: rho du_c/dt = sum_d d_d(mu_cd d_d u_c), mu_cd = 4/3 mu on
+// axis c (Sec. 3.2, eq. viscous1D extended per axis), one LIM pass per component.
+tlim_status viscous(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep, Timer& tm, SweepCount& sc) {
+    DevPhases ph = dev_phases(c);
+    DevGrid g0 = dev_grid(c, kUnit);
+    tlim::launch_visc_coeffs(c->stream, g0, ph, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], c->Lam,
+                             c->rC, c->Lam32, c->rC32);
+    for (int comp = 0; comp < 3; ++comp) {
+        if (c->n[comp] <= 1) continue;
+        double scale[3] = {1.0, 1.0, 1.0};
+        scale[comp] = 4.0 / 3.0;
+        DevGrid g = dev_grid(c, scale);
+        double lam;
+        if (o->frozen_visc) {
+            lam = o->frozen_visc[comp];
+        } else {
+            tlim::launch_gershgorin(c->stream, g, o->face_mean, c->Lam, c->rC, c->partials, c->res_dev);
+            tlim_status st = read_result(c);
+            if (st) return st;
+            lam = c->res_host->lambda;
+        }
+        int P = lim_P(o->dt, lam);
+        std::vector<double> b = lim_params(P, lam, o->order);
+        double* u = c->field[TLIM_U + comp];
+        run_lim_pass(c, g, o->face_mean, o->dt, b, u, u, c->Tnew, tm, sc);
+        std::swap(c->field[TLIM_U + comp], c->Tnew);
+        if (rep) {
+            rep->visc_P[comp] = P;
+            rep->visc_lambda_G[comp] = lam;
+        }
+    }
+    return TLIM_OK;
+}
+
+// Heat-conduction coefficients of the current iterate (T1, alpha2).
+void heat_coeffs(tlim_ctx* c, const DevGrid& g, const DevPhases& ph, const tlim_step_opts* o) {
+    tlim::launch_heat_coeffs(c->stream, g, ph, o->alpha_eps, o->dt, c->field[TLIM_T1], c->field[TLIM_ALPHA2],
+                             c->field[TLIM_M1], c->field[TLIM_M2], c->Tn,
+                             c->fset[TLIM_SRC1] ? c->field[TLIM_SRC1] : nullptr,
+                             c->fset[TLIM_SRC2] ? c->field[TLIM_SRC2] : nullptr, c->Lam, c->rC, c->rhs, c->Lam32,
+                             c->rC32);
+}
+
+// Chebyshev cycles to the backward-Euler solution of one pass (cycle mode).
+tlim_status cycle_pass(tlim_ctx* c, const DevGrid& g, const tlim_step_opts* o, int s_stages, double lam,
+                       int* cycles, double* residual, Timer& tm, SweepCount& sc) {
+    std::vector<double> b = cycle_params(s_stages, lam);
+    tlim::launch_copy(c->stream, c->vb[0], c->Tn, c->N);
+    int cur = 0;
+    int cyc = 0;
+    double r = 0.0;
+    while (cyc < o->max_cycles) {
+        tm.start();
+        for (int m = 0; m < s_stages; ++m) {
+            double tb = o->dt * b[m];
+            tlim::launch_stage64(c->stream, g, o->face_mean, c->vb[cur], c->rhs, c->Lam, c->rC, c->vb[cur ^ 1],
+                                 1.0 / (1.0 + tb), tb, o->dt);
+            cur ^= 1;
+            sc.launches++;
+        }
+        tm.stop();
+        sc.sweeps += s_stages;
+        ++cyc;
+        tlim::launch_be_residual(c->stream, g, o->face_mean, c->vb[cur], c->rhs, c->Lam, c->rC, o->dt, c->partials,
+                                 c->res_dev);
+        tlim_status st = read_result(c);
+        if (st) return st;
+        double rr = c->res_host->rr, gg = c->res_host->gg;
+        r = gg > 0.0 ? std::sqrt(rr / gg) : std::sqrt(rr);
+        if (r < o->cycle_tol) break;
+    }
+    tlim::launch_copy(c->stream, c->Tnew, c->vb[cur], c->N);
+    *cycles = cyc;
+    *residual = r;
+    return TLIM_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+const char* tlim_status_str(tlim_status s) {
+    switch (s) {
+        case TLIM_OK: return "TLIM_OK";
+        case TLIM_E_ARG: return "TLIM_E_ARG";
+        case TLIM_E_STATE: return "TLIM_E_STATE";
+        case TLIM_E_HIP: return "TLIM_E_HIP";
+        case TLIM_E_NOMEM: return "TLIM_E_NOMEM";
+        case TLIM_E_NOCONV: return "TLIM_E_NOCONV";
+        case TLIM_E_NUMERIC: return "TLIM_E_NUMERIC";
+    }
+    return "unknown";
+}
+
+const char* tlim_last_error(const tlim_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+tlim_status tlim_create(const tlim_grid* grid, int32_t precision, void* hip_stream, tlim_ctx** out) {
+    if (!grid || !out) return TLIM_E_ARG;
+    *out = nullptr;
+    // launch limits of the tiled kernels: ceil(ny/4) and nz blocks along y and z
+    const int64_t nmax[3] = {(int64_t)1 << 24, (int64_t)4 * 65535, 65535};
+    for (int d = 0; d < 3; ++d) {
+        if (grid->n[d] < 1 || grid->n[d] > nmax[d]) return TLIM_E_ARG;
+        if (!(grid->h[d] > 0.0) || !std::isfinite(grid->h[d])) return TLIM_E_ARG;
+        if (grid->bc[d] != TLIM_PERIODIC && grid->bc[d] != TLIM_ADIABATIC) return TLIM_E_ARG;
+    }
+    if (precision != TLIM_FP64 && precision != TLIM_FP32) return TLIM_E_ARG;
+    int64_t N = grid->n[0] * grid->n[1] * grid->n[2];
+    if (N > ((int64_t)1 << 34)) return TLIM_E_ARG;
+    tlim_ctx* c = new tlim_ctx();
+    for (int d = 0; d < 3; ++d) {
+        c->n[d] = grid->n[d];
+        c->h[d] = grid->h[d];
+        c->bc[d] = grid->bc[d];
+    }
+    c->N = N;
+    c->precision = precision;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return TLIM_E_HIP;
+    }
+    if (hipHostMalloc((void**)&c->res_host, sizeof(PassResult), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return TLIM_E_HIP;
+    }
+    for (int i = 0; i < kMaxEvents; ++i) {
+        if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->ev[j]);
+            (void)hipHostFree(c->res_host);
+            delete c;
+            return TLIM_E_HIP;
+        }
+    }
+    *out = c;
+    return TLIM_OK;
+}
+
+tlim_status tlim_destroy(tlim_ctx* c) {
+    if (!c) return TLIM_OK;
+    for (int i = 0; i < kMaxEvents; ++i) (void)hipEventDestroy(c->ev[i]);
+    (void)hipHostFree(c->res_host);
+    delete c;
+    return TLIM_OK;
+}
+
+tlim_status tlim_workspace_bytes(const tlim_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return TLIM_E_ARG;
+    *bytes = layout_of(c->N, c->precision).total;
+    return TLIM_OK;
+}
+
+tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
+    if (!c) return TLIM_E_ARG;
+    if (!dev_ptr || ((uintptr_t)dev_ptr % kAlign) != 0) return fail(c, TLIM_E_ARG, "workspace NULL or not 256-byte aligned");
+    Layout L = layout_of(c->N, c->precision);
+    if (bytes < L.total) return fail(c, TLIM_E_NOMEM, "workspace %zu bytes < %zu required", bytes, L.total);
+    char* base = (char*)dev_ptr;
+    c->ws = base;
+    c->ws_bytes = bytes;
+    for (int i = 0; i < TLIM_NFIELDS; ++i) {
+        c->field[i] = (double*)(base + L.field[i]);
+        c->fset[i] = false;
+    }
+    c->Tn = (double*)(base + L.Tn);
+    c->Tnew = (double*)(base + L.Tnew);
+    c->a2n = (double*)(base + L.a2n);
+    c->Lam = (double*)(base + L.Lam);
+    c->rC = (double*)(base + L.rC);
+    c->rhs = (double*)(base + L.rhs);
+    c->vb[0] = (double*)(base + L.vb[0]);
+    c->vb[1] = (double*)(base + L.vb[1]);
+    c->partials = (double*)(base + L.partials);
+    c->res_dev = (PassResult*)(base + L.res);
+    if (c->precision == TLIM_FP32) {
+        c->Lam32 = (float*)(base + L.Lam32);
+        c->rC32 = (float*)(base + L.rC32);
+        c->q32 = (float*)(base + L.q32);
+        c->wb[0] = (float*)(base + L.wb[0]);
+        c->wb[1] = (float*)(base + L.wb[1]);
+    } else {
+        c->Lam32 = c->rC32 = c->q32 = c->wb[0] = c->wb[1] = nullptr;
+    }
+    return TLIM_OK;
+}
+
+tlim_status tlim_set_phase(tlim_ctx* c, int32_t k, const tlim_phase* p) {
+    if (!c) return TLIM_E_ARG;
+    if (k < 0 || k > 1 || !p) return fail(c, TLIM_E_ARG, "phase index must be 0 or 1");
+    if (!(p->gamma > 1.0) || !(p->cv > 0.0) || !(p->k0 >= 0.0) || !(p->T0 > 0.0) || !(p->mu >= 0.0) ||
+        !std::isfinite(p->pinf) || !std::isfinite(p->npow))
+        return fail(c, TLIM_E_ARG, "invalid phase constants");
+    c->phase[k] = *p;
+    c->phase_set[k] = true;
+    return TLIM_OK;
+}
+
+tlim_status tlim_set_field(tlim_ctx* c, int32_t f, const double* src) {
+    if (!c) return TLIM_E_ARG;
+    if (f < 0 || f >= TLIM_NFIELDS || !src) return fail(c, TLIM_E_ARG, "bad field index or NULL source");
+    if (!c->ws) return fail(c, TLIM_E_STATE, "no workspace bound");
+    HIP_TRY(c, hipMemcpyAsync(c->field[f], src, sizeof(double) * (size_t)c->N, hipMemcpyDeviceToDevice, c->stream));
+    c->fset[f] = true;
+    return TLIM_OK;
+}
+
+tlim_status tlim_get_field(const tlim_ctx* cc, int32_t f, double* dst) {
+    tlim_ctx* c = const_cast<tlim_ctx*>(cc);
+    if (!c) return TLIM_E_ARG;
+    if (f < 0 || f >= TLIM_NFIELDS || !dst) return fail(c, TLIM_E_ARG, "bad field index or NULL destination");
+    if (!c->ws || !c->fset[f]) return fail(c, TLIM_E_STATE, "field %d not set", f);
+    HIP_TRY(c, hipMemcpyAsync(dst, c->field[f], sizeof(double) * (size_t)c->N, hipMemcpyDeviceToDevice, c->stream));
+    return TLIM_OK;
+}
+
+tlim_status tlim_spectral_bound(tlim_ctx* c, int32_t face_mean, double alpha_eps, double* lambda_out) {
+    if (!c) return TLIM_E_ARG;
+    if (!lambda_out || face_mean < 0 || face_mean > 1 || alpha_eps < 0.0 || alpha_eps >= 0.5)
+        return fail(c, TLIM_E_ARG, "bad arguments");
+    tlim_status st = check_ready(c);
+    if (st) return st;
+    // relax copies of (alpha2, T1, T2) into scratch, leaving the state untouched
+    DevGrid g = dev_grid(c, kUnit);
+    DevPhases ph = dev_phases(c);
+    tlim::launch_copy(c->stream, c->a2n, c->field[TLIM_ALPHA2], c->N);
+    tlim::launch_copy(c->stream, c->Tn, c->field[TLIM_T1], c->N);
+    tlim::launch_copy(c->stream, c->Tnew, c->field[TLIM_T2], c->N);
+    tlim::launch_relax(c->stream, g, ph, alpha_eps, c->a2n, c->field[TLIM_M1], c->field[TLIM_M2], c->Tn, c->Tnew);
+    tlim::launch_heat_coeffs(c->stream, g, ph, alpha_eps, 1.0, c->Tn, c->a2n, c->field[TLIM_M1], c->field[TLIM_M2],
+                             c->Tn, nullptr, nullptr, c->Lam, c->rC, c->rhs, nullptr, nullptr);
+    tlim::launch_gershgorin(c->stream, g, face_mean, c->Lam, c->rC, c->partials, c->res_dev);
+    st = read_result(c);
+    if (st) return st;
+    *lambda_out = c->res_host->lambda;
+    return TLIM_OK;
+}
+
+tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep) {
+    if (!c) return TLIM_E_ARG;
+    tlim_status st = check_opts(c, o);
+    if (st) return st;
+    st = check_ready(c);
+    if (st) return st;
+    if (rep) std::memset(rep, 0, sizeof(*rep));
+    hipStream_t s = c->stream;
+    DevGrid g = dev_grid(c, kUnit);
+    DevPhases ph = dev_phases(c);
+    const double vol = cell_volume(c);
+    const bool B1 = c->phase[0].pinf != c->phase[1].pinf;
+    Timer tm{c, o->time_sweeps != 0};
+    SweepCount sc;
+
+    if (rep) {
+        tlim::launch_energy(s, g, ph, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], c->field[TLIM_T1],
+                            c->field[TLIM_T2], c->partials, c->res_dev);
+        st = read_result(c);
+        if (st) return st;
+        rep->energy_before = c->res_host->energy * vol;
+    }
+    // splitting order of the paper: viscous part, temperature relaxation, heat conduction
+    if (o->do_viscous) {
+        st = viscous(c, o, rep, tm, sc);
+        if (st) return st;
+    }
+    tlim::launch_relax(s, g, ph, o->alpha_eps, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2],
+                       c->field[TLIM_T1], c->field[TLIM_T2]);
+    tlim::launch_copy(s, c->Tn, c->field[TLIM_T1], c->N);
+    if (B1) tlim::launch_copy(s, c->a2n, c->field[TLIM_ALPHA2], c->N);
+
+    // Algorithm 1: Picard passes with coefficients lagged at T^(it).
+    const bool need_bound = o->frozen_lambda == nullptr;
+    heat_coeffs(c, g, ph, o);
+    if (need_bound) tlim::launch_gershgorin(s, g, o->face_mean, c->Lam, c->rC, c->partials, c->res_dev);
+    int it = 0;
+    bool converged = false, cycle_fail = false;
+    double last_err = 0.0;
+    for (it = 0; it < o->passes; ++it) {
+        // one readback brings lambda_G of this pass and the change of the previous one
+        const bool sync_now = need_bound || (o->picard_tol > 0.0 && it > 0);
+        if (sync_now) {
+            st = read_result(c);
+            if (st) return st;
+        }
+        if (it > 0 && sync_now) {
+            double tmax = c->res_host->tmax;
+            last_err = tmax > 0.0 ? c->res_host->dmax / tmax : c->res_host->dmax;
+            if (rep) rep->err[it - 1] = last_err;
+            if (o->picard_tol > 0.0 && last_err < o->picard_tol) {
+                converged = true;
+                break;
+            }
+        }
+        double lam = need_bound ? c->res_host->lambda : o->frozen_lambda[it];
+        int P = lim_P(o->dt, lam);
+        if (rep) {
+            rep->P[it] = P;
+            rep->lambda_G[it] = lam;
+        }
+        if (o->cycle_mode) {
+            int ncyc = 0;
+            double res = 0.0;
+            st = cycle_pass(c, g, o, 2 * P - 1, lam, &ncyc, &res, tm, sc);
+            if (st) return st;
+            if (rep) {
+                rep->cycles[it] = ncyc;
+                rep->residual[it] = res;
+            }
+            if (!(res < o->cycle_tol)) cycle_fail = true;  // keep the last iterate
+        } else {
+            std::vector<double> b = lim_params(P, lam, o->order);
+            run_lim_pass(c, g, o->face_mean, o->dt, b, c->Tn, c->rhs, c->Tnew, tm, sc);
+        }
+        tlim::launch_pass_update(s, g, ph, o->alpha_eps, c->field[TLIM_T1], c->Tnew, c->Tn, c->a2n,
+                                 c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], c->field[TLIM_ALPHA2],
+                                 c->partials, c->res_dev);
+        std::swap(c->field[TLIM_T1], c->Tnew);
+        if (it + 1 < o->passes) {
+            heat_coeffs(c, g, ph, o);
+            if (need_bound) tlim::launch_gershgorin(s, g, o->face_mean, c->Lam, c->rC, c->partials, c->res_dev);
+        }
+    }
+    int passes_run = it;
+    if (!converged) {
+        st = read_result(c);
+        if (st) return st;
+        double tmax = c->res_host->tmax;
+        last_err = tmax > 0.0 ? c->res_host->dmax / tmax : c->res_host->dmax;
+        if (rep && passes_run > 0) rep->err[passes_run - 1] = last_err;
+        if (o->picard_tol > 0.0 && last_err < o->picard_tol) converged = true;
+    }
+    double bad = c->res_host->bad;
+    tlim::launch_copy(s, c->field[TLIM_T2], c->field[TLIM_T1], c->N);
+    if (rep) {
+        tlim::launch_energy(s, g, ph, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], c->field[TLIM_T1],
+                            c->field[TLIM_T2], c->partials, c->res_dev);
+        st = read_result(c);
+        if (st) return st;
+        rep->energy_after = c->res_host->energy * vol;
+        rep->passes_run = passes_run;
+        rep->converged = (o->picard_tol <= 0.0 || converged) && !cycle_fail;
+        rep->sweeps = sc.sweeps;
+        rep->sweep_launches = sc.launches;
+        rep->bad_cells = (int64_t)bad;
+        if (tm.on) {
+            HIP_TRY(c, hipStreamSynchronize(s));
+            rep->sweep_ms = tm.elapsed_ms();
+        }
+    }
+    HIP_TRY(c, hipGetLastError());
+    if (bad > 0.0) return fail(c, TLIM_E_NUMERIC, "%.0f cells with non-finite or non-positive T", bad);
+    if ((o->picard_tol > 0.0 && !converged) || cycle_fail)
+        return fail(c, TLIM_E_NOCONV, "tolerance not reached (last Picard change %.3e)", last_err);
+    return TLIM_OK;
+}
+
+// ------------------------------------------------------------------ adjoint
+
+namespace {
+
+tlim_status check_adjoint(tlim_ctx* c, const tlim_step_opts* o) {
+    tlim_status st = check_opts(c, o);
+    if (st) return st;
+    st = check_ready(c);
+    if (st) return st;
+    if (c->phase[0].pinf != c->phase[1].pinf) return fail(c, TLIM_E_ARG, "adjoint needs equal p_inf of both phases");
+    if (o->cycle_mode || o->do_viscous || o->picard_tol > 0.0)
+        return fail(c, TLIM_E_ARG, "adjoint runs plain LIM heat steps (no cycle mode, viscous part or Picard tol)");
+    if (c->fset[TLIM_SRC1] || c->fset[TLIM_SRC2]) return fail(c, TLIM_E_ARG, "adjoint runs without heat sources");
+    return TLIM_OK;
+}
+
+struct AdjLayout {
+    size_t stages, Tpass, mu, acc, dg, gLam, lamA, lamB, total;
+    int nst;
+};
+
+AdjLayout adj_layout(int64_t N, int passes, int Pmax) {
+    AdjLayout L{};
+    size_t d = align_up(sizeof(double) * (size_t)N);
+    L.nst = 2 * Pmax - 1;
+    size_t off = 0;
+    L.stages = off;
+    off += d * (size_t)passes * (size_t)L.nst;
+    L.Tpass = off;
+    off += d * (size_t)(passes + 1);
+    size_t* rest[] = {&L.mu, &L.acc, &L.dg, &L.gLam, &L.lamA, &L.lamB};
+    for (size_t* p : rest) {
+        *p = off;
+        off += d;
+    }
+    L.total = off;
+    return L;
+}
+
+// Heat passes of one step without relaxation, from Tpass[0], storing every
+// stage iterate of every pass (when stages != NULL) and T^(it) in Tpass[it].
+void adj_forward_step(tlim_ctx* c, const tlim_step_opts* o, const double* lamv, double* Tpass, double* stages,
+                      size_t stride_field, size_t stride_pass) {
+    DevGrid g = dev_grid(c, kUnit);
+    DevPhases ph = dev_phases(c);
+    hipStream_t s = c->stream;
+    const int64_t N = c->N;
+    const double* Tn = Tpass;
+    for (int it = 0; it < o->passes; ++it) {
+        double* Tit = Tpass + (size_t)it * stride_field;
+        double* Tout = Tpass + (size_t)(it + 1) * stride_field;
+        tlim::launch_heat_coeffs(s, g, ph, o->alpha_eps, o->dt, Tit, c->field[TLIM_ALPHA2], c->field[TLIM_M1],
+                                 c->field[TLIM_M2], Tn, nullptr, nullptr, c->Lam, c->rC, c->rhs, nullptr, nullptr);
+        int P = lim_P(o->dt, lamv[it]);
+        std::vector<double> b = lim_params(P, lamv[it], o->order);
+        int nst = (int)b.size();
+        if (stages) {
+            double* st0 = stages + (size_t)it * stride_pass;
+            tlim::launch_copy(s, st0, Tn, N);
+            for (int m = 1; m < nst; ++m) {
+                double tb = o->dt * b[m - 1];
+                tlim::launch_stage64(s, g, o->face_mean, st0 + (size_t)(m - 1) * stride_field, c->rhs, c->Lam, c->rC,
+                                     st0 + (size_t)m * stride_field, 1.0 / (1.0 + tb), tb, o->dt);
+            }
+            tlim::launch_final64(s, g, o->face_mean, st0 + (size_t)(nst - 1) * stride_field, c->rhs, c->Lam, c->rC,
+                                 Tout, o->dt);
+        } else {
+            const double* cur = Tn;
+            int pp = 0;
+            for (int m = 1; m < nst; ++m) {
+                double tb = o->dt * b[m - 1];
+                tlim::launch_stage64(s, g, o->face_mean, cur, c->rhs, c->Lam, c->rC, c->vb[pp], 1.0 / (1.0 + tb), tb,
+                                     o->dt);
+                cur = c->vb[pp];
+                pp ^= 1;
+            }
+            tlim::launch_final64(s, g, o->face_mean, cur, c->rhs, c->Lam, c->rC, Tout, o->dt);
+        }
+    }
+}
+
+}  // namespace
+
+tlim_status tlim_forward_checkpointed(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, int32_t ckpt_every,
+                                      double* ckpt_dev, double* lam_out) {
+    if (!c) return TLIM_E_ARG;
+    tlim_status st = check_adjoint(c, o);
+    if (st) return st;
+    if (nsteps < 1 || ckpt_every < 1 || !ckpt_dev || !lam_out) return fail(c, TLIM_E_ARG, "bad checkpoint arguments");
+    if (o->frozen_lambda) return fail(c, TLIM_E_ARG, "the forward run records its own schedule");
+    for (int n = 0; n < nsteps; ++n) {
+        if (n % ckpt_every == 0)
+            tlim::launch_copy(c->stream, ckpt_dev + (size_t)(n / ckpt_every) * (size_t)c->N, c->field[TLIM_T1], c->N);
+        tlim_step_report rep;
+        st = tlim_advance(c, o, &rep);
+        if (st) return st;
+        for (int it = 0; it < o->passes; ++it) lam_out[(size_t)n * o->passes + it] = rep.lambda_G[it];
+    }
+    return TLIM_OK;
+}
+
+tlim_status tlim_adjoint_workspace_bytes(const tlim_ctx* c, const tlim_step_opts* o, int32_t Pmax, size_t* bytes) {
+    if (!c || !o || !bytes || Pmax < 1 || o->passes < 1 || o->passes > TLIM_MAX_PASSES) return TLIM_E_ARG;
+    *bytes = adj_layout(c->N, o->passes, Pmax).total;
+    return TLIM_OK;
+}
+
+tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, int32_t ckpt_every,
+                         const double* ckpt_dev, const double* lam, const double* dL_dTN_dev, double* dL_dT0_dev,
+                         double* dL_dk0, void* adj_ws_dev, size_t adj_ws_bytes) {
+    if (!c) return TLIM_E_ARG;
+    tlim_status st = check_adjoint(c, o);
+    if (st) return st;
+    if (c->precision != TLIM_FP64) return fail(c, TLIM_E_ARG, "the adjoint runs in FP64 contexts");
+    if (nsteps < 1 || ckpt_every < 1 || !ckpt_dev || !lam || !dL_dTN_dev || !dL_dT0_dev || !dL_dk0 || !adj_ws_dev)
+        return fail(c, TLIM_E_ARG, "bad adjoint arguments");
+    if (((uintptr_t)adj_ws_dev % kAlign) != 0) return fail(c, TLIM_E_ARG, "adjoint workspace not 256-byte aligned");
+    const int np = o->passes;
+    int Pmax = 1;
+    for (int k = 0; k < nsteps * np; ++k) {
+        if (!(lam[k] >= 0.0) || !std::isfinite(lam[k])) return fail(c, TLIM_E_ARG, "schedule entry %d invalid", k);
+        Pmax = std::max(Pmax, lim_P(o->dt, lam[k]));
+    }
+    AdjLayout L = adj_layout(c->N, np, Pmax);
+    if (adj_ws_bytes < L.total) return fail(c, TLIM_E_NOMEM, "adjoint workspace %zu < %zu bytes", adj_ws_bytes, L.total);
+    char* base = (char*)adj_ws_dev;
+    const size_t sf = align_up(sizeof(double) * (size_t)c->N) / sizeof(double);  // doubles per field slot
+    double* stages = (double*)(base + L.stages);
+    double* Tpass = (double*)(base + L.Tpass);
+    double* mu = (double*)(base + L.mu);
+    double* acc = (double*)(base + L.acc);
+    double* dg = (double*)(base + L.dg);
+    double* gLam = (double*)(base + L.gLam);
+    double* lamA = (double*)(base + L.lamA);
+    double* lamB = (double*)(base + L.lamB);
+    const size_t stride_pass = sf * (size_t)L.nst;
+    hipStream_t s = c->stream;
+    DevGrid g = dev_grid(c, kUnit);
+    DevPhases ph = dev_phases(c);
+    const int64_t N = c->N;
+    double k0g[2] = {0.0, 0.0};
+
+    tlim::launch_copy(s, mu, dL_dTN_dev, N);
+    for (int n = nsteps - 1; n >= 0; --n) {
+        // T^n from the nearest checkpoint at or before n
+        int base_step = (n / ckpt_every) * ckpt_every;
+        tlim::launch_copy(s, Tpass, ckpt_dev + (size_t)(n / ckpt_every) * (size_t)N, N);
+        for (int m = base_step; m < n; ++m) {
+            adj_forward_step(c, o, lam + (size_t)m * np, Tpass, nullptr, sf, stride_pass);
+            tlim::launch_copy(s, Tpass, Tpass + (size_t)np * sf, N);
+        }
+        // recompute step n keeping every stage
+        adj_forward_step(c, o, lam + (size_t)n * np, Tpass, stages, sf, stride_pass);
+        tlim::launch_fill(s, acc, 0.0, N);
+        for (int it = np - 1; it >= 0; --it) {
+            const double* Tit = Tpass + (size_t)it * sf;
+            tlim::launch_heat_coeffs(s, g, ph, o->alpha_eps, o->dt, Tit, c->field[TLIM_ALPHA2], c->field[TLIM_M1],
+                                     c->field[TLIM_M2], Tpass, nullptr, nullptr, c->Lam, c->rC, c->rhs, nullptr,
+                                     nullptr);
+            int P = lim_P(o->dt, lam[(size_t)n * np + it]);
+            std::vector<double> b = lim_params(P, lam[(size_t)n * np + it], o->order);
+            int nst = (int)b.size();
+            tlim::launch_fill(s, dg, 0.0, N);
+            tlim::launch_fill(s, gLam, 0.0, N);
+            const double* cur = mu;
+            double* bufs[2] = {lamA, lamB};
+            int pp = 0;
+            const double* st0 = stages + (size_t)it * stride_pass;
+            for (int m = nst; m >= 1; --m) {
+                double tb = o->dt * b[m - 1];
+                tlim::launch_adj_stage(s, g, o->face_mean, cur, st0 + (size_t)(m - 1) * sf, c->Lam, c->rC, bufs[pp],
+                                       dg, gLam, 1.0 / (1.0 + tb), tb, o->dt);
+                cur = bufs[pp];
+                pp ^= 1;
+            }
+            // cur = dL/dv^(0); mu <- dL/dT^(it) through Lambda(T^(it))
+            tlim::launch_adj_cell(s, g, ph, Tit, c->field[TLIM_ALPHA2], gLam, dg, cur, acc, mu, it == 0 ? 1 : 0,
+                                  c->partials, c->res_dev);
+            st = read_result(c);
+            if (st) return st;
+            k0g[0] += c->res_host->k0g[0];
+            k0g[1] += c->res_host->k0g[1];
+        }
+        tlim::launch_copy(s, mu, acc, N);
+    }
+    tlim::launch_copy(s, dL_dT0_dev, mu, N);
+    HIP_TRY(c, hipStreamSynchronize(s));
+    HIP_TRY(c, hipGetLastError());
+    dL_dk0[0] = k0g[0];
+    dL_dk0[1] = k0g[1];
+    return TLIM_OK;
+}
+
+}  // extern "C"

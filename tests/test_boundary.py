@@ -1,0 +1,75 @@
+"""CPU checks of the C ABI boundary: the library builds, loads and exports
+every entry point include/tlim.h declares.  No device call is made."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tlim.h")
+LIB = os.path.join(ROOT, "paper_2106_00282_amd", "libtlim.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tlim_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    syms = declared_symbols()
+    for name in ("tlim_create", "tlim_advance", "tlim_set_field", "tlim_get_field", "tlim_adjoint"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        from paper_2106_00282_amd import build
+        build.build()
+    lib = ctypes.CDLL(LIB)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_binding_declares_every_symbol():
+    from paper_2106_00282_amd import tlim
+    assert sorted(tlim.EXPORTED) == declared_symbols()
+    lib = tlim.load_library()
+    # host-only calls: status names
+    assert lib.tlim_status_str(0) == b"TLIM_OK"
+    assert lib.tlim_status_str(5) == b"TLIM_E_NOCONV"
+
+
+def test_create_rejects_bad_grid_without_device():
+    """Argument validation happens before any device query."""
+    from paper_2106_00282_amd import tlim
+    lib = tlim.load_library()
+    g = tlim.Grid()
+    for d in range(3):
+        g.n[d], g.h[d], g.bc[d] = 4, 0.25, 0
+    g.n[1] = 0
+    out = ctypes.c_void_p()
+    assert lib.tlim_create(ctypes.byref(g), 0, None, ctypes.byref(out)) == tlim.E_ARG
+    g.n[1] = 4
+    g.bc[2] = 7
+    assert lib.tlim_create(ctypes.byref(g), 0, None, ctypes.byref(out)) == tlim.E_ARG
+    g.bc[2] = 0
+    assert lib.tlim_create(ctypes.byref(g), 3, None, ctypes.byref(out)) == tlim.E_ARG
+
+
+def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2106_00282_amd import tlim
+    monkeypatch.setattr(tlim, "_lib", None)
+    with pytest.raises(ImportError):
+        tlim.load_library(str(tmp_path / "missing.so"))
+
+
+def test_product_does_not_import_oracle():
+    """The package never refers to the oracle."""
+    pkg = os.path.join(ROOT, "paper_2106_00282_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "oracle" not in text.lower() or fn == "workloads.py", fn

@@ -1,0 +1,349 @@
+"""GPU parity: the HIP path against the FP64 oracle on the same seeded
+inputs, through the C ABI.
+
+Tolerances: FP64 path <= 1e-12 relative (max-norm per field); FP32 form
+<= 1e-5 relative per field; adjoint vs oracle adjoint <= 1e-12, vs central
+finite differences <= 1e-6.  The schedule (lambda_max per pass) is the
+oracle's, frozen into both sides, wherever a test compares several passes,
+so that P (an integer decided in floating point) is decided once.
+"""
+import numpy as np
+import pytest
+
+from paper_2106_00282_amd import workloads as W
+from _cases import oracle_dt, rel_err, run_gpu, run_oracle, make_solver
+
+pytestmark = pytest.mark.gpu
+
+FIELDS_T = ("T1", "T2", "alpha2")
+
+
+def _frozen(reps):
+    return [r["lambda_G"] for r in reps]
+
+
+def _compare(fo, fg, names, tol):
+    errs = {k: rel_err(fg[k], fo[k]) for k in names}
+    for k, e in errs.items():
+        assert e <= tol, (k, e, errs)
+    return errs
+
+
+# ----------------------------------------------------------------- FP64 path
+
+def test_heat1d_fp64_single_step():
+    """1024 cells, one step at 100x the explicit limit: P = 12, 23 sweeps."""
+    from oracle import oracle as orc
+    wl = W.heat1d()
+    tau, lam = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 1)
+    fg, rg, s = run_gpu(wl, tau, 1)
+    assert rg[0]["P"] == ro[0]["P"] == [12]
+    assert rg[0]["lambda_G"][0] == pytest.approx(ro[0]["lambda_G"][0], rel=1e-14)
+    _compare(fo, fg, FIELDS_T, 1e-12)
+    assert abs(rg[0]["energy_after"] / rg[0]["energy_before"] - 1) < 1e-14
+
+
+@pytest.mark.parametrize("shape", [(100, 76), (64, 4), (67, 1), (3, 130)])
+def test_levelset2d_fp64_ragged(shape):
+    """Reduced level-set workload on grids that span several 64x4 tiles and
+    leave ragged tails; 2 steps x 3 Picard passes."""
+    from oracle import oracle as orc
+    wl = W.levelset2d(128)
+    nx, ny = shape
+    for k in wl["fields"]:
+        wl["fields"][k] = np.ascontiguousarray(wl["fields"][k][:, :ny, :nx])
+    wl["n"] = (nx, ny, 1)
+    wl["h"] = (1.0 / 128, 1.0 / 128, 1.0)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 2)
+    fg, rg, _ = run_gpu(wl, tau, 2, frozen=_frozen(ro))
+    _compare(fo, fg, FIELDS_T, 1e-12)
+
+
+def test_levelset2d_fp64_full_size():
+    """1024^2 periodic, T^2 conductivities, 10 steps x 3 passes at 200x the
+    explicit limit (the benchmark workload) against the full oracle run."""
+    from oracle import oracle as orc
+    wl = W.levelset2d(1024)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 10)
+    fg, rg, _ = run_gpu(wl, tau, 10)
+    assert [r["P"] for r in rg] == [r["P"] for r in ro]
+    _compare(fo, fg, FIELDS_T, 1e-12)
+    for r in rg:
+        assert abs(r["energy_after"] / r["energy_before"] - 1) < 1e-13
+
+
+def test_bubbles3d_fp64_with_viscous():
+    """3D periodic bubbles, heat + viscous sub-step, on a 40x36x33 grid."""
+    from oracle import oracle as orc
+    wl = W.bubbles3d(40)
+    for k in wl["fields"]:
+        wl["fields"][k] = np.ascontiguousarray(wl["fields"][k][:33, :36, :])
+    wl["n"] = (40, 36, 33)
+    wl["h"] = (1 / 40, 1 / 40, 1 / 40)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 2)
+    fg, rg, _ = run_gpu(wl, tau, 2, frozen=_frozen(ro))
+    assert [r["visc_P"] for r in rg] == [r["visc_P"] for r in ro]
+    _compare(fo, fg, FIELDS_T + ("u", "v", "w"), 1e-12)
+
+
+def test_interface3d_fp64_adiabatic_x():
+    from oracle import oracle as orc
+    wl = W.interface3d(32, nmodes=12)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 2)
+    fg, rg, _ = run_gpu(wl, tau, 2, frozen=_frozen(ro))
+    _compare(fo, fg, FIELDS_T, 1e-12)
+
+
+def test_paper_order_and_harmonic_faces():
+    from oracle import oracle as orc
+    wl = W.levelset2d(48)
+    tau, _ = oracle_dt(orc, wl)
+    tau *= 0.05  # tau*lambda = 20: the printed order is still accurate here
+    for order, face in ((1, 0), (2, 1), (0, 1)):
+        fo, ro = run_oracle(orc, wl, tau, 1, order=order, face_mean=face)
+        fg, rg, _ = run_gpu(wl, tau, 1, frozen=_frozen(ro), order=order, face_mean=face)
+        _compare(fo, fg, ("T1",), 1e-12)
+
+
+def test_cycle_mode_reaches_backward_euler():
+    """Cycle mode on heat1d agrees with the oracle's cycle mode and both with
+    the direct tridiagonal BE solve."""
+    from oracle import oracle as orc
+    from scipy.linalg import solve_banded
+    wl = W.heat1d()
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 1, passes=1, cycle_mode=1, cycle_tol=1e-14)
+    fg, rg, _ = run_gpu(wl, tau, 1, passes=1, frozen=_frozen(ro), cycle_mode=1, cycle_tol=1e-14)
+    assert rg[0]["residual"][0] < 1e-14
+    g = orc.make_grid(wl["n"], wl["h"], wl["bc"])
+    f = {k: v.copy() for k, v in wl["fields"].items()}
+    orc.relax(g, wl["phases"], f["alpha2"], f["m1"], f["m2"], f["T1"], f["T2"])
+    Lam = orc.cell_conductivity(g, wl["phases"], f["alpha2"], f["T1"]).ravel()
+    Cap = orc.heat_capacity(g, wl["phases"], f["alpha2"], f["m1"], f["m2"], f["T1"]).ravel()
+    Lf = 0.5 * (Lam[1:] + Lam[:-1]) / wl["h"][0] ** 2
+    diag = Cap.copy()
+    diag[:-1] += tau * Lf
+    diag[1:] += tau * Lf
+    ab = np.vstack([np.concatenate([[0.0], -tau * Lf]), diag, np.concatenate([-tau * Lf, [0.0]])])
+    Tbe = solve_banded((1, 1), ab, Cap * f["T1"].ravel())
+    assert rel_err(fg["T1"].ravel(), Tbe) < 1e-13
+    assert rel_err(fg["T1"], fo["T1"]) < 1e-13
+
+
+def test_relaxation_unequal_pinf_and_sources():
+    """Stiffened-gas phases (p_inf 6e8/0, Sec. 5 constants) out of thermal
+    equilibrium, with heat sources: relaxation, C_eff, the alpha2 update and
+    the source term against the oracle."""
+    from oracle import oracle as orc
+    n = 48
+    rng = np.random.default_rng(11)
+    ph = [dict(gamma=4.4, pinf=6e8, cv=1606.0, q=0.0, k0=0.6, T0=300.0, npow=1.0, mu=0.0),
+          dict(gamma=1.4, pinf=0.0, cv=714.0, q=0.0, k0=0.03, T0=300.0, npow=1.0, mu=0.0)]
+    x = (np.arange(n) + 0.5) / n
+    a1 = 0.5 * (1 - np.tanh((x[None, :] - 0.5 - 0.1 * np.sin(2 * np.pi * x[:, None])) / (2.0 / n)))
+    a2 = 1 - a1
+    rho1 = (1e9 + 6e8) / (3.4 * 1606.0 * 293.0)
+    rho2 = 1e5 / (0.4 * 714.0 * 293.0)
+    T1 = 293.0 + 20 * rng.random((n, n))
+    T2 = 293.0 + 20 * rng.random((n, n))
+    fields = dict(alpha2=a2.reshape(1, n, n), m1=(a1 * rho1).reshape(1, n, n), m2=(a2 * rho2).reshape(1, n, n),
+                  T1=T1.reshape(1, n, n), T2=T2.reshape(1, n, n),
+                  src1=(1e3 * rng.random((1, n, n))), src2=(1e2 * rng.random((1, n, n))))
+    fields = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in fields.items()}
+    wl = dict(n=(n, n, 1), h=(1e-3, 1e-3, 1.0), bc=(0, 1, 0), phases=ph, fields=fields, dt_factor=50.0,
+              passes=3, viscous=False)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 2)
+    fg, rg, _ = run_gpu(wl, tau, 2, frozen=_frozen(ro))
+    _compare(fo, fg, FIELDS_T, 1e-12)
+
+
+def test_picard_tolerance_and_noconv():
+    from oracle import oracle as orc
+    from paper_2106_00282_amd.tlim import StepOpts, E_NOCONV
+    wl = W.levelset2d(32)
+    tau, _ = oracle_dt(orc, wl)
+    tau *= 0.1
+    fo, ro = run_oracle(orc, wl, tau, 1, passes=40, picard_tol=1e-10)
+    s = make_solver(wl)
+    st, rep = s.advance(StepOpts(dt=tau, passes=40, picard_tol=1e-10))
+    assert st == 0 and rep["converged"]
+    assert rep["passes_run"] == ro[0]["passes_run"]
+    assert rel_err(s.get_field("T1").cpu().numpy(), fo["T1"]) < 1e-12
+    s2 = make_solver(wl)
+    st, rep = s2.advance(StepOpts(dt=tau, passes=2, picard_tol=1e-15))
+    assert st == E_NOCONV and not rep["converged"] and rep["passes_run"] == 2
+
+
+def test_numeric_and_argument_errors():
+    import torch
+    from paper_2106_00282_amd.tlim import StepOpts, E_NUMERIC, E_ARG, TlimError
+    wl = W.levelset2d(24)
+    s = make_solver(wl)
+    T = torch.from_numpy(wl["fields"]["T1"].copy())
+    T[0, 3, 5] = float("nan")
+    s.set_field("T1", T)
+    s.set_field("T2", T)
+    st, rep = s.advance(StepOpts(dt=1e-6))
+    assert st == E_NUMERIC and rep["bad_cells"] >= 1
+    with pytest.raises(TlimError) as ei:
+        s.advance(StepOpts(dt=-1.0))
+    assert ei.value.status == E_ARG
+    with pytest.raises(TlimError):
+        s.advance(StepOpts(dt=1e-6, passes=0))
+
+
+def test_get_set_roundtrip_and_spectral_bound():
+    import torch
+    from oracle import oracle as orc
+    wl = W.levelset2d(40)
+    s = make_solver(wl)
+    for k, v in wl["fields"].items():
+        assert np.array_equal(s.get_field(k).cpu().numpy(), v)
+    _, lam = oracle_dt(orc, wl)
+    assert s.spectral_bound() == pytest.approx(lam, rel=1e-14)
+    # the bound did not change the state
+    assert np.array_equal(s.get_field("T1").cpu().numpy(), wl["fields"]["T1"])
+
+
+def test_single_cell_and_two_cell_periodic():
+    from oracle import oracle as orc
+    for n in ((1, 1, 1), (2, 1, 1), (2, 2, 2)):
+        wl = W.levelset2d(8)
+        N = n[0] * n[1] * n[2]
+        rng = np.random.default_rng(N)
+        for k in wl["fields"]:
+            wl["fields"][k] = np.ascontiguousarray(wl["fields"][k].ravel()[:N].reshape(n[2], n[1], n[0]))
+        wl["fields"]["T1"] = np.ascontiguousarray(1 + rng.random((n[2], n[1], n[0])))
+        wl["fields"]["T2"] = wl["fields"]["T1"].copy()
+        wl["n"] = n
+        wl["h"] = tuple(1.0 / x if x > 1 else 1.0 for x in n)
+        tau = 1e-3
+        fo, ro = run_oracle(orc, wl, tau, 1)
+        fg, rg, _ = run_gpu(wl, tau, 1, frozen=_frozen(ro))
+        _compare(fo, fg, ("T1",), 1e-12)
+
+
+# ------------------------------------------------------------------ FP32 form
+
+def test_levelset2d_fp32_full_size():
+    """FP32 sweeps, FP64 state and sums: per-field error against the FP64
+    oracle at the benchmark workload (10 steps)."""
+    from oracle import oracle as orc
+    wl = W.levelset2d(1024)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 10)
+    fg, rg, _ = run_gpu(wl, tau, 10, precision="fp32", frozen=_frozen(ro))
+    errs = {k: rel_err(fg[k], fo[k]) for k in FIELDS_T}
+    print("fp32 per-field relative error vs FP64 oracle:", errs)
+    assert errs["T1"] <= 1e-5 and errs["alpha2"] <= 1e-12
+    for r in rg:
+        assert abs(r["energy_after"] / r["energy_before"] - 1) < 1e-12
+
+
+def test_bubbles3d_fp32_with_viscous():
+    from oracle import oracle as orc
+    wl = W.bubbles3d(48)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 2)
+    fg, rg, _ = run_gpu(wl, tau, 2, precision="fp32", frozen=_frozen(ro))
+    errs = {k: rel_err(fg[k], fo[k]) for k in ("T1", "u", "v", "w")}
+    print("fp32 bubbles per-field error:", errs)
+    for k, e in errs.items():
+        assert e <= 1e-5, (k, e)
+
+
+# ------------------------------------------------------------------- adjoint
+
+def _adjoint_setup(n=48, steps=3):
+    from oracle import oracle as orc
+    wl = W.levelset2d(n)
+    tau, _ = oracle_dt(orc, wl)
+    return orc, wl, tau, steps
+
+
+def test_adjoint_vs_oracle_adjoint():
+    import torch
+    from paper_2106_00282_amd.tlim import StepOpts
+    orc, wl, tau, steps = _adjoint_setup()
+    s = make_solver(wl)
+    opts = StepOpts(dt=tau, passes=3)
+    ckpt, lam = s.forward_checkpointed(opts, steps, 1)
+    TN = s.get_field("T1").cpu().numpy()
+    rng = np.random.default_rng(12)
+    Tstar = wl["fields"]["T1"] * (1 + 0.05 * rng.standard_normal(TN.shape))
+    dT0, dk0 = s.adjoint(opts, steps, 1, ckpt, lam, torch.from_numpy(TN - Tstar))
+    f = wl["fields"]
+    oopts = orc.StepOpts(tau=tau, passes=3)
+    odT0, odk0, oTN = orc.heat_adjoint(orc.make_grid(wl["n"], wl["h"], wl["bc"]), wl["phases"], oopts, steps,
+                                       np.array(lam), f["alpha2"], f["m1"], f["m2"], f["T1"], TN - Tstar)
+    assert rel_err(TN, oTN) < 1e-12
+    assert rel_err(dT0.cpu().numpy(), odT0) < 1e-12
+    for k in range(2):
+        assert dk0[k] == pytest.approx(odk0[k], rel=1e-12)
+    # checkpoints every 2 steps give the same gradient
+    s2 = make_solver(wl)
+    ck2, lam2 = s2.forward_checkpointed(opts, steps, 2)
+    d2, k2 = s2.adjoint(opts, steps, 2, ck2, lam2, torch.from_numpy(TN - Tstar))
+    assert rel_err(d2.cpu().numpy(), dT0.cpu().numpy()) < 1e-13
+
+
+def test_autograd_function_vs_central_fd():
+    """torch.autograd through ParabolicRun against central differences of the
+    GPU forward (frozen schedule) on 16 cells and both k0."""
+    import torch
+    from paper_2106_00282_amd.tlim import ParabolicRun, StepOpts
+    orc, wl, tau, steps = _adjoint_setup(40, 3)
+    s = make_solver(wl)
+    opts = StepOpts(dt=tau, passes=3)
+    dev = s.device
+    T0 = torch.from_numpy(wl["fields"]["T1"].copy()).to(dev).requires_grad_(True)
+    k0 = torch.tensor([wl["phases"][0]["k0"], wl["phases"][1]["k0"]], dtype=torch.float64, device=dev,
+                      requires_grad=True)
+    rng = np.random.default_rng(13)
+    Tstar = torch.from_numpy(wl["fields"]["T1"] * (1 + 0.05 * rng.standard_normal(wl["fields"]["T1"].shape))).to(dev)
+    TN = ParabolicRun.apply(T0, k0, s, opts, steps, 1, wl["phases"])
+    loss = 0.5 * ((TN - Tstar) ** 2).sum()
+    loss.backward()
+    lam = None
+
+    def fwd_loss(T0v, k0v):
+        nonlocal lam
+        ph = [dict(p) for p in wl["phases"]]
+        for k in range(2):
+            ph[k]["k0"] = float(k0v[k])
+            s.set_phase(k, ph[k])
+        s.set_field("T1", T0v)
+        s.set_field("T2", T0v)
+        for n in range(steps):
+            o = StepOpts(dt=tau, passes=3, frozen_lambda=lam[3 * n:3 * n + 3])
+            st, _ = s.advance(o)
+            assert st == 0
+        r = s.get_field("T1") - Tstar
+        return 0.5 * float((r * r).sum())
+
+    # the schedule of the recorded forward run
+    s2 = make_solver(wl)
+    _, lam = s2.forward_checkpointed(opts, steps, 1)
+    cells = rng.choice(T0.numel(), size=16, replace=False)
+    base = T0.detach().clone()
+    for c in cells:
+        hstep = 1e-5 * float(base.view(-1)[c])
+        Tp, Tm = base.clone(), base.clone()
+        Tp.view(-1)[c] += hstep
+        Tm.view(-1)[c] -= hstep
+        fd = (fwd_loss(Tp, k0.detach()) - fwd_loss(Tm, k0.detach())) / (2 * hstep)
+        g = float(T0.grad.view(-1)[c])
+        assert g == pytest.approx(fd, rel=1e-6, abs=1e-9 * float(T0.grad.abs().max()))
+    for k in range(2):
+        hstep = 1e-4 * float(k0[k])
+        kp, km = k0.detach().clone(), k0.detach().clone()
+        kp[k] += hstep
+        km[k] -= hstep
+        fd = (fwd_loss(base, kp) - fwd_loss(base, km)) / (2 * hstep)
+        assert float(k0.grad[k]) == pytest.approx(fd, rel=1e-6)
