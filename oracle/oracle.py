@@ -102,11 +102,19 @@ def lib():
     return _lib
 
 
-def _p(a):
+def _p(a, n=None):
+    """Pointer to a C-contiguous float64 array, checked to hold n values."""
     if a is None:
         return None
-    assert a.dtype == np.float64 and a.flags.c_contiguous, "oracle arrays are C-contiguous float64"
+    if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous):
+        raise TypeError("oracle arrays are C-contiguous float64 numpy arrays")
+    if n is not None and a.size != n:
+        raise ValueError(f"array has {a.size} values, the grid has {n}")
     return a.ctypes.data_as(_dp)
+
+
+def _ncell(g) -> int:
+    return int(g.n[0] * g.n[1] * g.n[2])
 
 
 def make_grid(n, h=None, bc=None) -> Grid:
@@ -175,63 +183,72 @@ def cycle_params(s, lam):
 
 def cell_conductivity(g, ph, alpha2, T):
     """Lambda = sum_k alpha_k lambda_k(T) (Sec. 3.4.2, eq. qk_dis)."""
+    N = _ncell(g)
     out = np.empty_like(T)
-    lib().orc_cell_conductivity(C.byref(g), make_phases(ph), _p(alpha2), _p(T), _p(out))
+    lib().orc_cell_conductivity(C.byref(g), make_phases(ph), _p(alpha2, N), _p(T, N), _p(out, N))
     return out
 
 
 def heat_capacity(g, ph, alpha2, m1, m2, T, eps=1e-10):
+    N = _ncell(g)
     out = np.empty_like(T)
-    lib().orc_heat_capacity(C.byref(g), make_phases(ph), eps, _p(alpha2), _p(m1), _p(m2), _p(T), _p(out))
+    lib().orc_heat_capacity(C.byref(g), make_phases(ph), eps, _p(alpha2, N), _p(m1, N), _p(m2, N), _p(T, N), _p(out, N))
     return out
 
 
 def gershgorin(g, Lam, Cap, scale=(1.0, 1.0, 1.0), face_mean=FACE_ARITH):
+    N = _ncell(g)
     s = np.asarray(scale, dtype=np.float64)
-    return float(lib().orc_gershgorin(C.byref(g), _p(Lam), _p(Cap), _p(s), face_mean))
+    return float(lib().orc_gershgorin(C.byref(g), _p(Lam, N), _p(Cap, N), _p(s), face_mean))
 
 
 def apply_A(g, Lam, Cap, v, scale=(1.0, 1.0, 1.0), face_mean=FACE_ARITH):
+    N = _ncell(g)
     s = np.asarray(scale, dtype=np.float64)
     y = np.empty_like(v)
-    lib().orc_apply_A(C.byref(g), _p(Lam), _p(Cap), _p(s), face_mean, _p(v), _p(y))
+    lib().orc_apply_A(C.byref(g), _p(Lam, N), _p(Cap, N), _p(s), face_mean, _p(v, N), _p(y, N))
     return y
 
 
 def lim_pass(g, Lam, Cap, tau, b, rhs, v0, scale=(1.0, 1.0, 1.0), face_mean=FACE_ARITH,
              keep_stages=False):
     """One LIM pass, eqs. LIM and LIM_last (Sec. 3.2)."""
+    N = _ncell(g)
     s = np.asarray(scale, dtype=np.float64)
     out = np.empty_like(rhs)
     b = np.ascontiguousarray(b, dtype=np.float64)
     st = np.empty((len(b),) + rhs.shape) if keep_stages else None
-    lib().orc_lim_pass(C.byref(g), _p(Lam), _p(Cap), _p(s), face_mean, tau, len(b), _p(b),
-                       _p(rhs), _p(v0), _p(out), _p(st) if st is not None else None)
+    lib().orc_lim_pass(C.byref(g), _p(Lam, N), _p(Cap, N), _p(s), face_mean, tau, len(b), _p(b),
+                       _p(rhs, N), _p(v0, N), _p(out, N), _p(st) if st is not None else None)
     return (out, st) if keep_stages else out
 
 
 def cycle_solve(g, Lam, Cap, tau, lam, s, rhs, v0, tol=1e-14, max_cycles=200,
                 scale=(1.0, 1.0, 1.0), face_mean=FACE_ARITH):
+    N = _ncell(g)
     sc = np.asarray(scale, dtype=np.float64)
     out = np.empty_like(rhs)
     hist = np.zeros(max(max_cycles, 1))
-    nc = lib().orc_cycle_solve(C.byref(g), _p(Lam), _p(Cap), _p(sc), face_mean, tau, lam, s,
-                               _p(rhs), _p(v0), tol, max_cycles, _p(out), _p(hist))
+    nc = lib().orc_cycle_solve(C.byref(g), _p(Lam, N), _p(Cap, N), _p(sc), face_mean, tau, lam, s,
+                               _p(rhs, N), _p(v0, N), tol, max_cycles, _p(out, N), _p(hist))
     return out, hist[:nc]
 
 
 def be_residual(g, Lam, Cap, tau, rhs, v, scale=(1.0, 1.0, 1.0), face_mean=FACE_ARITH):
+    N = _ncell(g)
     sc = np.asarray(scale, dtype=np.float64)
-    return float(lib().orc_be_residual(C.byref(g), _p(Lam), _p(Cap), _p(sc), face_mean, tau, _p(rhs), _p(v)))
+    return float(lib().orc_be_residual(C.byref(g), _p(Lam, N), _p(Cap, N), _p(sc), face_mean, tau, _p(rhs, N), _p(v, N)))
 
 
 def relax(g, ph, alpha2, m1, m2, T1, T2, eps=1e-10):
     """Temperature relaxation in mixed cells, in place (Sec. 3.4.1)."""
-    lib().orc_relax(C.byref(g), make_phases(ph), eps, _p(alpha2), _p(m1), _p(m2), _p(T1), _p(T2))
+    N = _ncell(g)
+    lib().orc_relax(C.byref(g), make_phases(ph), eps, _p(alpha2, N), _p(m1, N), _p(m2, N), _p(T1, N), _p(T2, N))
 
 
 def energy(g, ph, alpha2, m1, m2, T1, T2):
-    return float(lib().orc_energy(C.byref(g), make_phases(ph), _p(alpha2), _p(m1), _p(m2), _p(T1), _p(T2)))
+    N = _ncell(g)
+    return float(lib().orc_energy(C.byref(g), make_phases(ph), _p(alpha2, N), _p(m1, N), _p(m2, N), _p(T1, N), _p(T2, N)))
 
 
 def _report(r: Report, passes: int):
@@ -245,12 +262,17 @@ def _report(r: Report, passes: int):
 def step(g, ph, opts: StepOpts, f: dict, frozen_lambda=None, frozen_visc=None):
     """One parabolic step (viscous, relaxation, Algorithm 1) on the fields of
     ``f`` in place.  Returns (status, report dict)."""
+    N = _ncell(g)
     rep = Report()
     fl = None if frozen_lambda is None else np.ascontiguousarray(frozen_lambda, dtype=np.float64)
     fv = None if frozen_visc is None else np.ascontiguousarray(frozen_visc, dtype=np.float64)
-    st = lib().orc_step(C.byref(g), make_phases(ph), C.byref(opts.c()), _p(f["alpha2"]), _p(f["m1"]),
-                        _p(f["m2"]), _p(f["T1"]), _p(f["T2"]), _p(f.get("src1")), _p(f.get("src2")),
-                        _p(f.get("u")), _p(f.get("v")), _p(f.get("w")),
+    if fl is not None and fl.size < opts.passes:
+        raise ValueError("frozen_lambda needs one value per pass")
+    if fv is not None and fv.size < 3:
+        raise ValueError("frozen_visc needs 3 values")
+    st = lib().orc_step(C.byref(g), make_phases(ph), C.byref(opts.c()), _p(f["alpha2"], N), _p(f["m1"], N),
+                        _p(f["m2"], N), _p(f["T1"], N), _p(f["T2"], N), _p(f.get("src1"), N), _p(f.get("src2"), N),
+                        _p(f.get("u"), N), _p(f.get("v"), N), _p(f.get("w"), N),
                         _p(fl) if fl is not None else None, _p(fv) if fv is not None else None,
                         C.byref(rep))
     return int(st), _report(rep, opts.passes)
@@ -259,12 +281,15 @@ def step(g, ph, opts: StepOpts, f: dict, frozen_lambda=None, frozen_visc=None):
 def heat_adjoint(g, ph, opts: StepOpts, nsteps, lamsched, alpha2, m1, m2, T0, dL_dTN):
     """Discrete adjoint of ``nsteps`` heat steps with a frozen schedule.
     Returns (dL/dT0, dL/dk0[2], T^N)."""
+    N = _ncell(g)
     lamsched = np.ascontiguousarray(lamsched, dtype=np.float64).ravel()
+    if lamsched.size < nsteps * opts.passes:
+        raise ValueError("the schedule needs nsteps * passes values")
     dT0 = np.empty_like(T0)
     dk0 = np.zeros(2)
     TN = np.empty_like(T0)
     st = lib().orc_heat_adjoint(C.byref(g), make_phases(ph), C.byref(opts.c()), nsteps, _p(lamsched),
-                                _p(alpha2), _p(m1), _p(m2), _p(T0), _p(dL_dTN), _p(dT0), _p(dk0), _p(TN))
+                                _p(alpha2, N), _p(m1, N), _p(m2, N), _p(T0, N), _p(dL_dTN, N), _p(dT0, N), _p(dk0), _p(TN, N))
     if st != 0:
         raise ValueError("oracle adjoint: unsupported configuration")
     return dT0, dk0, TN

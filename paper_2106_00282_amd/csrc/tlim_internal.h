@@ -72,8 +72,8 @@ void launch_final64(hipStream_t s, const DevGrid& g, int face, const double* v, 
                     const double* Lam, const double* rC, double* out, double tau);
 
 // FP32 correction form, w = v - rhs:
-//   q = tau rC' D' rhs (computed in double, stored float), w0 = float(v0 - rhs)
-//   w^(m) = cm (tb w - tau rC D w - q)                               (float)
+//   q = -tau rC' D' rhs (computed in double, stored float), w0 = float(v0 - rhs)
+//   w^(m) = cm (q + tb w - tau rC D w)                               (float)
 //   out = rhs + tau rC64 sum_f w Lam'_f ((rhs+w)_b - (rhs+w)_a)        (double)
 void launch_q32(hipStream_t s, const DevGrid& g, int face, const double* rhs, const double* v0,
                 const float* Lam32, const float* rC32, double tau, float* q, float* w0);

@@ -421,7 +421,7 @@ __global__ void __launch_bounds__(256) k_q32(DevGrid g, int face, const double* 
     Faces f;
     faces_of(g, i, j, k, f);
     double S = stencil<double, double, float>(g, f, a, rhs, Lam32, face);
-    q[a] = (float)(tau * (double)rC32[a] * S);
+    q[a] = (float)(-tau * (double)rC32[a] * S);
     w0[a] = (float)(v0[a] - rhs[a]);
 }
 
@@ -435,7 +435,7 @@ __global__ void __launch_bounds__(256) k_stage32(DevGrid g, int face, const floa
     Faces f;
     faces_of(g, i, j, k, f);
     float S = stencil<float, float, float>(g, f, a, w, Lam32, face);
-    out[a] = cm * (tb * w[a] - tau * rC32[a] * S - q[a]);
+    out[a] = cm * (q[a] + tb * w[a] - tau * rC32[a] * S);
 }
 
 __global__ void __launch_bounds__(256) k_final32(DevGrid g, int face, const float* __restrict__ w,

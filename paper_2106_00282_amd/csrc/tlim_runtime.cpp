@@ -264,29 +264,31 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const std
         const float* cur = c->wb[0];
         int m = 0;
         while (m < nst - 1) {
-            int done = tlim::launch_sweeps32(s, g, face, cur, c->q32, c->Lam32, c->rC32,
-                                             cur == c->wb[0] ? c->wb[1] : c->wb[0], b.data() + m, nst - 1 - m,
-                                             tau);
-            cur = cur == c->wb[0] ? c->wb[1] : c->wb[0];
+            int k = tlim::sweeps_per_launch(g, nst - 1 - m);
+            float* nxt = cur == c->wb[0] ? c->wb[1] : c->wb[0];
+            int done = tlim::launch_sweeps32(s, g, face, cur, c->q32, c->Lam32, c->rC32, nxt, b.data() + m, k, tau);
+            cur = nxt;
             m += done;
             sc.launches++;
         }
         tlim::launch_final32(s, g, face, cur, rhs, c->Lam32, c->rC, out, tau);
+        sc.launches++;
     } else {
+        // all 2P-1 stages, the last (b = 0) in flux form; the launch that
+        // reaches it writes `out`
         const double* cur = v0;
         int m = 0;
         int pp = 0;
-        while (m < nst - 1) {
-            double* nxt = c->vb[pp];
-            int done = tlim::launch_sweeps64(s, g, face, cur, rhs, c->Lam, c->rC, nxt, b.data() + m, nst - 1 - m, tau);
+        while (m < nst) {
+            int k = tlim::sweeps_per_launch(g, nst - m);
+            double* nxt = m + k == nst ? out : c->vb[pp];
+            int done = tlim::launch_sweeps64(s, g, face, cur, rhs, c->Lam, c->rC, nxt, b.data() + m, k, tau);
             cur = nxt;
             pp ^= 1;
             m += done;
             sc.launches++;
         }
-        tlim::launch_final64(s, g, face, cur, rhs, c->Lam, c->rC, out, tau);
     }
-    sc.launches++;
     sc.sweeps += nst;
     tm.stop();
 }

@@ -49,12 +49,14 @@ def test_levelset2d_fp64_ragged(shape):
     """Reduced level-set workload on grids that span several 64x4 tiles and
     leave ragged tails; 2 steps x 3 Picard passes."""
     from oracle import oracle as orc
-    wl = W.levelset2d(128)
     nx, ny = shape
+    ng = max(128, nx, ny)
+    wl = W.levelset2d(ng)
     for k in wl["fields"]:
         wl["fields"][k] = np.ascontiguousarray(wl["fields"][k][:, :ny, :nx])
+        assert wl["fields"][k].shape == (1, ny, nx)
     wl["n"] = (nx, ny, 1)
-    wl["h"] = (1.0 / 128, 1.0 / 128, 1.0)
+    wl["h"] = (1.0 / ng, 1.0 / ng, 1.0)
     tau, _ = oracle_dt(orc, wl)
     fo, ro = run_oracle(orc, wl, tau, 2)
     fg, rg, _ = run_gpu(wl, tau, 2, frozen=_frozen(ro))
@@ -333,13 +335,16 @@ def test_autograd_function_vs_central_fd():
     cells = rng.choice(T0.numel(), size=16, replace=False)
     base = T0.detach().clone()
     for c in cells:
-        hstep = 1e-5 * float(base.view(-1)[c])
+        # step 1e-3: truncation ~2e-7 relative.  The forward carries a
+        # rounding floor of ~tau*lambda*eps per pass, which a smaller step
+        # turns into FD noise of 1e-6 (1e-4) to 4e-5 (1e-5)
+        hstep = 1e-3 * float(base.view(-1)[c])
         Tp, Tm = base.clone(), base.clone()
         Tp.view(-1)[c] += hstep
         Tm.view(-1)[c] -= hstep
         fd = (fwd_loss(Tp, k0.detach()) - fwd_loss(Tm, k0.detach())) / (2 * hstep)
         g = float(T0.grad.view(-1)[c])
-        assert g == pytest.approx(fd, rel=1e-6, abs=1e-9 * float(T0.grad.abs().max()))
+        assert g == pytest.approx(fd, rel=1e-6, abs=1e-8 * float(T0.grad.abs().max()))
     for k in range(2):
         hstep = 1e-4 * float(k0[k])
         kp, km = k0.detach().clone(), k0.detach().clone()
