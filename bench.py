@@ -54,26 +54,35 @@ def run_steps(solver, wl, opts, steps, reset=True):
 
 
 def measure(precision, wl, tau, steps, warmup):
-    """Wall time of `steps` steps, then a second, identical run with sweep
-    events for the sweep count and the per-launch kernel time."""
+    """Wall time of `steps` steps from the initial state on a fresh context
+    (no schedule history), after `warmup` steps on another context; then an
+    identical untimed run with sweep events for the sweep count and the
+    per-launch kernel time."""
     from paper_2106_00282_amd.tlim import Solver, StepOpts
-    s = Solver(wl["n"], wl["h"], wl["bc"], precision=precision)
     opts = StepOpts(dt=tau, passes=wl["passes"])
     if warmup:
-        run_steps(s, wl, opts, warmup)
-    wall = run_steps(s, wl, opts, steps)
+        w = Solver(wl["n"], wl["h"], wl["bc"], precision=precision)
+        run_steps(w, wl, opts, warmup)
+        del w
+    s = Solver(wl["n"], wl["h"], wl["bc"], precision=precision)
     s.set_workload(wl)
+    wall = run_steps(s, wl, opts, steps, reset=False)
+    s2 = Solver(wl["n"], wl["h"], wl["bc"], precision=precision)
+    s2.set_workload(wl)
     sweeps = launches = 0
     sweep_ms = 0.0
+    predicted = mispredicted = 0
     topts = StepOpts(dt=tau, passes=wl["passes"], time_sweeps=1)
     for _ in range(steps):
-        st, rep = s.advance(topts)
+        st, rep = s2.advance(topts)
         sweeps += rep["sweeps"]
         launches += rep["sweep_launches"]
         sweep_ms += rep["sweep_ms"]
+        predicted += rep["predicted"]
+        mispredicted += rep["mispredicted"]
     N = s.N
     return dict(wall_s=wall, sweeps=sweeps, launches=launches, sweep_ms=sweep_ms, N=N,
-                gupd=N * sweeps / wall / 1e9)
+                gupd=N * sweeps / wall / 1e9, predicted_steps=predicted, mispredicted_steps=mispredicted)
 
 
 def adjoint_ratio():
@@ -179,7 +188,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"levelset2d {args.n}x{args.n} periodic, two phases, k=k0 (T/T0)^2, "
                                f"dt=200x explicit limit, 3 Picard passes, {args.steps} steps",
-                   "cells": r64["N"], "sweeps_per_run": r64["sweeps"]},
+                   "cells": r64["N"], "sweeps_per_run": r64["sweeps"],
+                   "predicted_steps": r64["predicted_steps"], "mispredicted_steps": r64["mispredicted_steps"]},
+        "sweep_kernel_gupd": round(r64["N"] * r64["sweeps"] / (r64["sweep_ms"] * 1e-3) / 1e9, 2)
+        if r64["sweep_ms"] > 0 else None,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,

@@ -118,6 +118,10 @@ typedef struct {
     int64_t sweep_launches;               /* sweep kernel launches (<= sweeps when fused) */
     double sweep_ms;                      /* time_sweeps: summed event time of the sweep launches */
     int64_t bad_cells;                    /* cells with non-finite or T <= 0 after the last pass */
+    int32_t predicted;                    /* 1: P of every pass was predicted from the previous step
+                                             and confirmed (no per-pass readback) */
+    int32_t mispredicted;                 /* 1: a predicted P was wrong; the heat passes were rerun
+                                             with one readback per pass (sweeps counts the rerun only) */
 } tlim_step_report;
 
 typedef struct tlim_ctx tlim_ctx;
@@ -164,7 +168,13 @@ tlim_status tlim_spectral_bound(tlim_ctx* ctx, int32_t face_mean, double alpha_e
  * report may be NULL.  Returns TLIM_E_NOCONV when picard_tol > 0 (or the
  * cycle tolerance) was not met, TLIM_E_NUMERIC when a non-finite or
  * non-positive temperature appears; in both cases the fields hold the last
- * iterate.  Synchronises once per Picard pass (lambda_max readback). */
+ * iterate.  The number of sweeps of a pass, 2P-1, follows from lambda_max of
+ * that pass.  With frozen_lambda the host knows it; otherwise, when the
+ * previous step ran the same number of passes (and picard_tol = 0, no cycle
+ * mode), P of every pass is predicted from that step, the stages read
+ * lambda_max from device memory, and one readback at the end confirms the
+ * predictions (a wrong one rolls the heat part back and reruns it with one
+ * readback per pass).  Otherwise it synchronises once per Picard pass. */
 tlim_status tlim_advance(tlim_ctx* ctx, const tlim_step_opts* opts, tlim_step_report* report);
 
 /* Forward run of nsteps heat steps with checkpoints for the adjoint: T^n is

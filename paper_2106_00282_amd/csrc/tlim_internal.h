@@ -20,28 +20,64 @@ struct DevGrid {
 // Material constants the kernels need (both phases).
 struct DevPhases {
     double gamma[2], pinf[2], cv[2];
-    double k0[2], T0[2], npow[2];
+    double k0[2], T0[2], invT0[2], npow[2];
     double mu[2];
 };
 
-// Results of the per-pass reduction, read back to the host.
-struct PassResult {
-    double dmax;      // max |T^(it+1) - T^(it)|
-    double tmax;      // max |T^(it+1)|
-    double energy;    // sum (C1 T1 + C2 T2 + alpha_k p_inf,k), without the cell volume
-    double bad;       // count of non-finite or T <= 0
-    double lambda;    // Gershgorin bound of the next pass (when requested)
-    double rr, gg;    // cycle mode: squared residual norm and squared |C g|
-    double k0g[2];    // adjoint: dL/dk0 partial sums
+constexpr int kMaxPasses = 64;
+
+// Reductions.  Every reduction result ("target") owns a row of kSlots
+// doubles in the accumulator array; a block folds its cells and adds one
+// atomic to slot (block % kSlots) of the row -- atomicMax on the bit pattern
+// for non-negative maxima (exact, order-independent), atomicAdd for sums --
+// so no address sees more than blocks/kSlots atomics.  Kernels that need a
+// result on the device fold the row themselves (row_max); launch_collect
+// folds rows into one double each for the host readback.
+constexpr int kSlots = 256;
+enum {
+    kTgtPass = 0,  // 4 targets per Picard pass: lambda_G, dmax, tmax, bad
+    kTgtLambda = 4 * kMaxPasses,
+    kTgtEnergy,
+    kTgtRR,
+    kTgtGG,
+    kTgtK0a,
+    kTgtK0b,
+    kTargets
 };
+__host__ __device__ constexpr int tgt_lam(int it) { return 4 * it; }
+__host__ __device__ constexpr int tgt_dmax(int it) { return 4 * it + 1; }
+__host__ __device__ constexpr int tgt_tmax(int it) { return 4 * it + 2; }
+__host__ __device__ constexpr int tgt_bad(int it) { return 4 * it + 3; }
+// reduction of a target: sums for counts and sums, max otherwise
+__host__ __device__ constexpr bool tgt_is_sum(int t) {
+    return (t < kTgtLambda && (t & 3) == 3) || t == kTgtEnergy || t == kTgtRR || t == kTgtGG || t == kTgtK0a ||
+           t == kTgtK0b;
+}
+
+// Results folded for the host (one double per target).
+struct PassResult {
+    double v[kTargets];
+};
+
+// Fold rows [t0, t1) of the accumulator into res->v[t0..t1).
+void launch_collect(hipStream_t s, const double* acc, PassResult* res, int t0, int t1);
+// Zero rows [t0, t1) of the accumulator.
+void launch_zero_rows(hipStream_t s, double* acc, int t0, int t1);
 
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
-constexpr int kPartialStride = 8;  // doubles per block in the partials array
+
+// Rows of the pass reductions of one Picard pass.
+struct PassSlots {
+    double* dmax;
+    double* tmax;
+    double* bad;
+};
 
 // ---- launches (all enqueue on `s`, none synchronises) ----
+// Relaxation in place; also writes the relaxed T to Tn and alpha2 to a2n (each nullable).
 void launch_relax(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double* alpha2,
-                  const double* m1, const double* m2, double* T1, double* T2);
+                  const double* m1, const double* m2, double* T1, double* T2, double* Tn, double* a2n);
 
 // Heat coefficients at (T, alpha2): Lam = sum alpha_k lambda_k(T), rC = 1/C_eff,
 // rhs = Tn + tau rC (alpha1 I1 + alpha2 I2).  Optional float copies.
@@ -55,21 +91,36 @@ void launch_visc_coeffs(hipStream_t s, const DevGrid& g, const DevPhases& ph, co
                         const double* m1, const double* m2, double* Lam, double* rC, float* Lam32,
                         float* rC32);
 
-// Gershgorin bound max_i 2 rC_i sum_f w Lam_f -> partials, then res->lambda.
-void launch_gershgorin(hipStream_t s, const DevGrid& g, int face, const double* Lam, const double* rC,
-                       double* partials, PassResult* res);
+// Heat coefficients plus the Gershgorin bound (max into the accumulator row
+// lam) in one stencil pass over (T, alpha2).
+void launch_heat_coeffs_bound(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double tau, int face,
+                              const double* T, const double* alpha2, const double* m1, const double* m2,
+                              const double* Tn, const double* src1, const double* src2, double* Lam, double* rC,
+                              double* rhs, float* Lam32, float* rC32, double* lam);
 
-// Energy sum of the state -> res->energy.
+// Gershgorin bound max_i 2 rC_i sum_f w Lam_f -> max into the row lam.
+void launch_gershgorin(hipStream_t s, const DevGrid& g, int face, const double* Lam, const double* rC, double* lam);
+
+// Energy sum of the state -> added to the row energy.
 void launch_energy(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* alpha2,
-                   const double* m1, const double* m2, const double* T1, const double* T2,
-                   double* partials, PassResult* res);
+                   const double* m1, const double* m2, const double* T1, const double* T2, double* energy);
 
-// One FP64 LIM stage: out = cm (rhs + tb v - tau rC sum_f w Lam_f (v_a - v_b)).
+// Stage parameter of a LIM stage: tau*b either given (lam == NULL: tb) or
+// taken from the device-resident bound, tau * row_max(lam) * chat, lam being
+// the accumulator row of the pass's lambda_G.
+struct StageParam {
+    const double* lam;
+    double tb;
+    double chat;
+};
+
+// One FP64 LIM stage: out = cm (rhs + tb v - tau rC sum_f w Lam_f (v_a - v_b)), cm = 1/(1+tb).
 void launch_stage64(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
-                    const double* Lam, const double* rC, double* out, double cm, double tb, double tau);
+                    const double* Lam, const double* rC, double* out, StageParam sp, double tau);
 // Final FP64 stage (b = 0) in flux form: out = rhs + tau rC sum_f w Lam_f (v_b - v_a).
+// With Tit != NULL it also accumulates the pass reductions into ps.
 void launch_final64(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
-                    const double* Lam, const double* rC, double* out, double tau);
+                    const double* Lam, const double* rC, double* out, double tau, const double* Tit, PassSlots ps);
 
 // FP32 correction form, w = v - rhs:
 //   q = -tau rC' D' rhs (computed in double, stored float), w0 = float(v0 - rhs)
@@ -78,19 +129,19 @@ void launch_final64(hipStream_t s, const DevGrid& g, int face, const double* v, 
 void launch_q32(hipStream_t s, const DevGrid& g, int face, const double* rhs, const double* v0,
                 const float* Lam32, const float* rC32, double tau, float* q, float* w0);
 void launch_stage32(hipStream_t s, const DevGrid& g, int face, const float* w, const float* q,
-                    const float* Lam32, const float* rC32, float* out, float cm, float tb, float tau);
+                    const float* Lam32, const float* rC32, float* out, StageParam sp, double tau);
 void launch_final32(hipStream_t s, const DevGrid& g, int face, const float* w, const double* rhs,
-                    const float* Lam32, const double* rC, double* out, double tau);
+                    const float* Lam32, const double* rC, double* out, double tau, const double* Tit, PassSlots ps);
 
-// After a pass: alpha2 update (B1 != 0) and reductions (dmax, tmax, bad).
+// After a pass: alpha2 update (B1 != 0) and the pass reductions into ps.
 void launch_pass_update(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps,
                         const double* Tit, const double* Tnew, const double* Tn, const double* alpha2n,
                         const double* alpha2it, const double* m1, const double* m2, double* alpha2out,
-                        double* partials, PassResult* res);
+                        PassSlots ps);
 
-// Cycle mode: relative BE residual || C(rhs - v) - tau D v ||^2, || C rhs ||^2 -> res->rr, gg.
+// Cycle mode: || C(rhs - v) - tau D v ||^2 and || C rhs ||^2 added to the rows rr, gg.
 void launch_be_residual(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
-                        const double* Lam, const double* rC, double tau, double* partials, PassResult* res);
+                        const double* Lam, const double* rC, double tau, double* rr, double* gg);
 
 // Adjoint of one stage (FP64):
 //   dg += cm lam;  gLam_a += sum_f cm tau w (v_b - v_a)(lam_a rC_a - lam_b rC_b) dLam_f/dLam_a;
@@ -98,11 +149,11 @@ void launch_be_residual(hipStream_t s, const DevGrid& g, int face, const double*
 void launch_adj_stage(hipStream_t s, const DevGrid& g, int face, const double* lam, const double* vprev,
                       const double* Lam, const double* rC, double* lam_out, double* dg, double* gLam,
                       double cm, double tb, double tau);
-// After a reversed pass: acc += dg + lam0; mu = gLam dLam/dT(Tit); k0 partial sums;
-// if first_pass: acc += mu.
+// After a reversed pass: acc += dg + lam0; mu = gLam dLam/dT(Tit); the two dL/dk0
+// sums are added to the rows k0a, k0b; if first_pass: acc += mu.
 void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* Tit,
                      const double* alpha2, const double* gLam, const double* dg, const double* lam0,
-                     double* acc, double* mu, int first_pass, double* partials, PassResult* res);
+                     double* acc, double* mu, int first_pass, double* k0a, double* k0b);
 
 void launch_fill(hipStream_t s, double* p, double v, int64_t n);
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n);

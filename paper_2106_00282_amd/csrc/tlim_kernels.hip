@@ -7,8 +7,8 @@
 // Stencil kernels run one work-item per cell on 64x4 tiles (a wave64 covers
 // 64 consecutive x cells, so every load is a coalesced 512 B / 256 B row);
 // the temporally blocked sweeps live in tlim_sweep.hip.
-// Reductions are two-level and deterministic: grid-stride blocks write
-// partials, one block folds them in a fixed order.
+// Reductions fold each block's cells and add one atomic per block (max on
+// the bit pattern of non-negative doubles, add for sums).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -101,28 +101,78 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Block reductions for blockDim.x a multiple of 64 (<= 1024); the result is
-// valid in thread 0.
+// Block reductions for blocks of a multiple of 64 threads (<= 1024) of any
+// shape; the result is valid in the block's first thread.
+__device__ __forceinline__ int flat_tid() { return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z); }
+__device__ __forceinline__ int block_threads() { return blockDim.x * blockDim.y * blockDim.z; }
+
 __device__ double block_sum(double v, double* sh) {
     v = wave_sum(v);
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int t = flat_tid(), lane = t & 63, wid = t >> 6, nw = block_threads() >> 6;
     if (lane == 0) sh[wid] = v;
     __syncthreads();
-    v = (int)threadIdx.x < nw ? sh[threadIdx.x] : 0.0;
+    v = t < nw ? sh[t] : 0.0;
     if (wid == 0) v = wave_sum(v);
     __syncthreads();
     return v;
 }
 __device__ double block_max(double v, double* sh) {
     v = wave_max(v);
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int t = flat_tid(), lane = t & 63, wid = t >> 6, nw = block_threads() >> 6;
     if (lane == 0) sh[wid] = v;
     __syncthreads();
-    v = (int)threadIdx.x < nw ? sh[threadIdx.x] : -INFINITY;
+    v = t < nw ? sh[t] : -INFINITY;
     if (wid == 0) v = wave_max(v);
     __syncthreads();
     return v;
 }
+
+__device__ __forceinline__ int block_slot() {
+    return (int)((blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z)) % kSlots);
+}
+// slot of a wave: blocks and their waves spread over the row
+__device__ __forceinline__ int wave_slot() {
+    int64_t b = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+    return (int)((b * (block_threads() >> 6) + (flat_tid() >> 6)) % kSlots);
+}
+
+// atomicMax on the bit pattern orders non-negative doubles (and lets a NaN
+// win); -0 is folded to +0 first.
+__device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
+    v = v + 0.0;
+    atomicMax((unsigned long long*)p, (unsigned long long)__double_as_longlong(v));
+}
+
+// Max of an accumulator row, computed by every wave on its own (all lanes
+// of the wave must call it).
+__device__ __forceinline__ double row_max(const double* row) {
+    const int lane = flat_tid() & 63;
+    double m = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSlots / 64; ++k) m = fmax(m, row[lane + 64 * k]);
+    return wave_max(m);
+}
+
+// Per-cell contribution to the pass reductions of a new iterate tn given the
+// previous iterate ti: max |tn - ti|, max |tn|, count of tn not finite or <= 0.
+struct PassAcc {
+    double dmax = 0.0, tmax = 0.0, bad = 0.0;
+    __device__ void add(double tn, double ti) {
+        dmax = fmax(dmax, fabs(tn - ti));
+        tmax = fmax(tmax, fabs(tn));
+        if (!(tn > 0.0) || isinf(tn)) bad += 1.0;
+    }
+    // wave-level fold, then lane 0 of every wave adds to a slot (no barrier)
+    __device__ void store(const PassSlots& ps) {
+        double r0 = wave_max(dmax), r1 = wave_max(tmax), r3 = wave_sum(bad);
+        if ((flat_tid() & 63) == 0) {
+            const int sl = wave_slot();
+            atomic_max_nonneg(ps.dmax + sl, r0);
+            atomic_max_nonneg(ps.tmax + sl, r1);
+            if (r3 != 0.0) atomicAdd(ps.bad + sl, r3);
+        }
+    }
+};
 
 __device__ __forceinline__ void cell_ijk(const DevGrid& g, int64_t a, int& i, int& j, int& k) {
     int64_t nxy = (int64_t)g.nx * g.ny;
@@ -138,27 +188,6 @@ __device__ __forceinline__ bool is_mixed(double a2, double eps) { return a2 > ep
 __device__ __forceinline__ double pressure_stiffness(const DevPhases& ph, double a2, double C1, double C2) {
     double a1 = 1.0 - a2;
     return (ph.gamma[0] - 1.0) * C1 / (a1 * a1) + (ph.gamma[1] - 1.0) * C2 / (a2 * a2);
-}
-
-struct FinalizeSpec {
-    int op[kPartialStride];        // 0 none, 1 max, 2 sum
-    double* dst[kPartialStride];
-};
-
-__global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ partials, int nblocks,
-                                                  FinalizeSpec spec) {
-    __shared__ double sh[16];
-    for (int s = 0; s < kPartialStride; ++s) {
-        if (spec.op[s] == 0) continue;
-        bool isMax = spec.op[s] == 1;
-        double acc = isMax ? -INFINITY : 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-            double v = partials[(int64_t)b * kPartialStride + s];
-            acc = isMax ? fmax(acc, v) : acc + v;
-        }
-        acc = isMax ? block_max(acc, sh) : block_sum(acc, sh);
-        if (threadIdx.x == 0) *spec.dst[s] = acc;
-    }
 }
 
 int reduce_blocks(int64_t N) {
@@ -178,18 +207,19 @@ dim3 tile_grid(const DevGrid& g) { return dim3((g.nx + TX - 1) / TX, (g.ny + TY 
 // The root with 0 < a < 1 and T'(a) > 0 is taken (eq. Taverage when B = 0).
 __global__ void __launch_bounds__(256) k_relax(DevGrid g, DevPhases ph, double eps, double* alpha2,
                                                const double* __restrict__ m1, const double* __restrict__ m2,
-                                               double* T1, double* T2) {
+                                               double* T1, double* T2, double* Tn, double* a2n) {
     double B = ph.pinf[1] - ph.pinf[0];
     double G1 = ph.gamma[0] - 1.0, G2 = ph.gamma[1] - 1.0;
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
          a += (int64_t)gridDim.x * blockDim.x) {
         double a20 = alpha2[a];
-        if (a20 <= eps) {
-            T2[a] = T1[a];
-            continue;
-        }
-        if (a20 >= 1.0 - eps) {
-            T1[a] = T2[a];
+        if (a20 <= eps || a20 >= 1.0 - eps) {
+            // pure cell: the absent phase takes the present phase's temperature
+            double t = a20 <= eps ? T1[a] : T2[a];
+            T1[a] = t;
+            T2[a] = t;
+            if (Tn) Tn[a] = t;
+            if (a2n) a2n[a] = a20;
             continue;
         }
         double C1 = m1[a] * ph.cv[0], C2 = m2[a] * ph.cv[1];
@@ -232,10 +262,68 @@ __global__ void __launch_bounds__(256) k_relax(DevGrid g, DevPhases ph, double e
         alpha2[a] = root;
         T1[a] = T;
         T2[a] = T;
+        if (Tn) Tn[a] = T;
+        if (a2n) a2n[a] = root;
     }
 }
 
 // ------------------------------------------------------------ coefficients
+
+__device__ __forceinline__ double cell_conductivity(const DevPhases& ph, double t, double a2) {
+    return (1.0 - a2) * ph.k0[0] * powlaw(t * ph.invT0[0], ph.npow[0]) + a2 * ph.k0[1] * powlaw(t * ph.invT0[1], ph.npow[1]);
+}
+
+// 1 / C_eff (Sec. 3.4.2 under T_1 = T_2 and p_1 = p_2).
+__device__ __forceinline__ double inv_heat_capacity(const DevPhases& ph, double eps, double t, double a2, double m1,
+                                                    double m2) {
+    double B1 = ph.pinf[0] - ph.pinf[1];
+    double C1 = m1 * ph.cv[0], C2 = m2 * ph.cv[1];
+    double C = C1 + C2;
+    if (B1 != 0.0 && is_mixed(a2, eps)) C += B1 * B1 / (t * t * pressure_stiffness(ph, a2, C1, C2));
+    return 1.0 / C;
+}
+
+// Coefficients of a Picard pass and the partial Gershgorin maxima in one
+// pass over (T, alpha2): the neighbours' conductivities are recomputed from
+// their (T, alpha2) rather than read back from a first pass.
+__global__ void __launch_bounds__(256) k_heat_coeffs_bound(
+    DevGrid g, DevPhases ph, double eps, double tau, int face, const double* __restrict__ T,
+    const double* __restrict__ alpha2, const double* __restrict__ m1, const double* __restrict__ m2,
+    const double* __restrict__ Tn, const double* __restrict__ src1, const double* __restrict__ src2,
+    double* __restrict__ Lam, double* __restrict__ rC, double* __restrict__ rhs, float* __restrict__ Lam32,
+    float* __restrict__ rC32, double* __restrict__ lam) {
+    __shared__ double sh[16];
+    int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
+    double bound = 0.0;
+    if (i < g.nx && j < g.ny) {
+        int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+        double t = T[a], a2 = alpha2[a];
+        double L = cell_conductivity(ph, t, a2);
+        double r = inv_heat_capacity(ph, eps, t, a2, m1[a], m2[a]);
+        double f = 0.0;
+        if (src1) f += (1.0 - a2) * src1[a];
+        if (src2) f += a2 * src2[a];
+        Lam[a] = L;
+        rC[a] = r;
+        rhs[a] = Tn[a] + tau * r * f;
+        if (Lam32) {
+            Lam32[a] = (float)L;
+            rC32[a] = (float)r;
+        }
+        Faces fc;
+        faces_of(g, i, j, k, fc);
+        double d = 0.0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            if (!fc.has[q]) continue;
+            int64_t b = a + fc.off[q];
+            d += g.w[q >> 1] * face_mean<double>(L, cell_conductivity(ph, T[b], alpha2[b]), face);
+        }
+        bound = 2.0 * d * r;
+    }
+    bound = wave_max(bound);
+    if ((flat_tid() & 63) == 0) atomic_max_nonneg(lam + wave_slot(), bound);
+}
 
 __global__ void __launch_bounds__(256) k_heat_coeffs(DevGrid g, DevPhases ph, double eps, double tau,
                                                      const double* __restrict__ T, const double* __restrict__ alpha2,
@@ -248,7 +336,7 @@ __global__ void __launch_bounds__(256) k_heat_coeffs(DevGrid g, DevPhases ph, do
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
          a += (int64_t)gridDim.x * blockDim.x) {
         double t = T[a], a2 = alpha2[a], a1 = 1.0 - a2;
-        double L = a1 * ph.k0[0] * powlaw(t / ph.T0[0], ph.npow[0]) + a2 * ph.k0[1] * powlaw(t / ph.T0[1], ph.npow[1]);
+        double L = a1 * ph.k0[0] * powlaw(t * ph.invT0[0], ph.npow[0]) + a2 * ph.k0[1] * powlaw(t * ph.invT0[1], ph.npow[1]);
         double C1 = m1[a] * ph.cv[0], C2 = m2[a] * ph.cv[1];
         double C = C1 + C2;
         if (B1 != 0.0 && is_mixed(a2, eps)) C += B1 * B1 / (t * t * pressure_stiffness(ph, a2, C1, C2));
@@ -287,29 +375,28 @@ __global__ void __launch_bounds__(256) k_visc_coeffs(DevGrid g, DevPhases ph, co
 // --------------------------------------------------------------- reductions
 
 __global__ void __launch_bounds__(256) k_gershgorin(DevGrid g, int face, const double* __restrict__ Lam,
-                                                    const double* __restrict__ rC, double* partials) {
+                                                    const double* __restrict__ rC, double* lam) {
     __shared__ double sh[16];
+    int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
     double mx = 0.0;
-    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
-         a += (int64_t)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_ijk(g, a, i, j, k);
+    if (i < g.nx && j < g.ny) {
+        int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
         Faces f;
         faces_of(g, i, j, k, f);
         double d = 0.0, La = Lam[a];
 #pragma unroll
         for (int q = 0; q < 6; ++q)
             if (f.has[q]) d += g.w[q >> 1] * face_mean<double>(La, Lam[a + f.off[q]], face);
-        mx = fmax(mx, 2.0 * d * rC[a]);
+        mx = 2.0 * d * rC[a];
     }
     mx = block_max(mx, sh);
-    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * kPartialStride + 4] = mx;
+    if (flat_tid() == 0) atomic_max_nonneg(lam + block_slot(), mx);
 }
 
 __global__ void __launch_bounds__(256) k_energy(DevGrid g, DevPhases ph, const double* __restrict__ alpha2,
                                                 const double* __restrict__ m1, const double* __restrict__ m2,
                                                 const double* __restrict__ T1, const double* __restrict__ T2,
-                                                double* partials) {
+                                                double* energy) {
     __shared__ double sh[16];
     double e = 0.0;
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
@@ -318,7 +405,7 @@ __global__ void __launch_bounds__(256) k_energy(DevGrid g, DevPhases ph, const d
         e += m1[a] * ph.cv[0] * T1[a] + m2[a] * ph.cv[1] * T2[a] + (1.0 - a2) * ph.pinf[0] + a2 * ph.pinf[1];
     }
     e = block_sum(e, sh);
-    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * kPartialStride + 2] = e;
+    if (threadIdx.x == 0) atomicAdd(energy + block_slot(), e);
 }
 
 __global__ void __launch_bounds__(256) k_pass_update(DevGrid g, DevPhases ph, double eps,
@@ -326,16 +413,14 @@ __global__ void __launch_bounds__(256) k_pass_update(DevGrid g, DevPhases ph, do
                                                      const double* __restrict__ Tn, const double* __restrict__ alpha2n,
                                                      const double* alpha2it, const double* __restrict__ m1,
                                                      const double* __restrict__ m2, double* alpha2out,
-                                                     double* partials) {
+                                                     PassSlots ps) {
     __shared__ double sh[16];
     double B1 = ph.pinf[0] - ph.pinf[1];
-    double dmax = 0.0, tmax = 0.0, bad = 0.0;
+    PassAcc acc;
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
          a += (int64_t)gridDim.x * blockDim.x) {
         double tn = Tnew[a], ti = Tit[a];
-        dmax = fmax(dmax, fabs(tn - ti));
-        tmax = fmax(tmax, fabs(tn));
-        if (!(tn > 0.0) || isinf(tn)) bad += 1.0;
+        acc.add(tn, ti);
         // d alpha2 = -B1/(T^2 W) dT from the step start, coefficient lagged at (T^(it), alpha2^(it))
         if (B1 != 0.0 && is_mixed(alpha2n[a], eps)) {
             double C1 = m1[a] * ph.cv[0], C2 = m2[a] * ph.cv[1];
@@ -343,20 +428,13 @@ __global__ void __launch_bounds__(256) k_pass_update(DevGrid g, DevPhases ph, do
             alpha2out[a] = alpha2n[a] - B1 / (ti * ti * W) * (tn - Tn[a]);
         }
     }
-    double r0 = block_max(dmax, sh);
-    double r1 = block_max(tmax, sh);
-    double r3 = block_sum(bad, sh);
-    if (threadIdx.x == 0) {
-        double* p = partials + (int64_t)blockIdx.x * kPartialStride;
-        p[0] = r0;
-        p[1] = r1;
-        p[3] = r3;
-    }
+    acc.store(ps);
 }
 
 __global__ void __launch_bounds__(256) k_be_residual(DevGrid g, int face, const double* __restrict__ v,
                                                      const double* __restrict__ rhs, const double* __restrict__ Lam,
-                                                     const double* __restrict__ rC, double tau, double* partials) {
+                                                     const double* __restrict__ rC, double tau, double* rrp,
+                                                     double* ggp) {
     __shared__ double sh[16];
     double rr = 0.0, gg = 0.0;
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
@@ -374,18 +452,24 @@ __global__ void __launch_bounds__(256) k_be_residual(DevGrid g, int face, const 
     double s0 = block_sum(rr, sh);
     double s1 = block_sum(gg, sh);
     if (threadIdx.x == 0) {
-        double* p = partials + (int64_t)blockIdx.x * kPartialStride;
-        p[5] = s0;
-        p[6] = s1;
+        atomicAdd(rrp + block_slot(), s0);
+        atomicAdd(ggp + block_slot(), s1);
     }
 }
 
 // ------------------------------------------------------------ LIM stages
 
+// tau*b of a stage; with the bound on the device every wave folds its row
+// (call before any lane leaves).
+__device__ __forceinline__ double stage_tb(const StageParam& sp, double tau) {
+    return sp.lam ? tau * row_max(sp.lam) * sp.chat : sp.tb;
+}
+
 __global__ void __launch_bounds__(256) k_stage64(DevGrid g, int face, const double* __restrict__ v,
                                                  const double* __restrict__ rhs, const double* __restrict__ Lam,
                                                  const double* __restrict__ rC, double* __restrict__ out,
-                                                 double cm, double tb, double tau) {
+                                                 StageParam sp, double tau) {
+    const double tb = stage_tb(sp, tau), cm = 1.0 / (1.0 + tb);
     int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
     if (i >= g.nx || j >= g.ny) return;
     int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
@@ -398,17 +482,23 @@ __global__ void __launch_bounds__(256) k_stage64(DevGrid g, int face, const doub
 __global__ void __launch_bounds__(256) k_final64(DevGrid g, int face, const double* __restrict__ v,
                                                  const double* __restrict__ rhs, const double* __restrict__ Lam,
                                                  const double* __restrict__ rC, double* __restrict__ out,
-                                                 double tau) {
+                                                 double tau, const double* __restrict__ Tit, PassSlots ps) {
+    __shared__ double sh[16];
     int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
-    if (i >= g.nx || j >= g.ny) return;
-    int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
-    Faces f;
-    faces_of(g, i, j, k, f);
-    // The flux w Lam_f (v_b - v_a) of a face is the same number with opposite
-    // sign when evaluated from its other cell, so sum_a C_a (out_a - rhs_a)
-    // cancels face by face (eq. LIM_last in conservative form).
-    double S = stencil<double, double, double>(g, f, a, v, Lam, face);
-    out[a] = rhs[a] - tau * rC[a] * S;
+    PassAcc acc;
+    if (i < g.nx && j < g.ny) {
+        int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+        Faces f;
+        faces_of(g, i, j, k, f);
+        // The flux w Lam_f (v_b - v_a) of a face is the same number with opposite
+        // sign when evaluated from its other cell, so sum_a C_a (out_a - rhs_a)
+        // cancels face by face (eq. LIM_last in conservative form).
+        double S = stencil<double, double, double>(g, f, a, v, Lam, face);
+        double t = rhs[a] - tau * rC[a] * S;
+        out[a] = t;
+        if (Tit) acc.add(t, Tit[a]);
+    }
+    if (Tit) acc.store(ps);
 }
 
 __global__ void __launch_bounds__(256) k_q32(DevGrid g, int face, const double* __restrict__ rhs,
@@ -427,34 +517,42 @@ __global__ void __launch_bounds__(256) k_q32(DevGrid g, int face, const double* 
 
 __global__ void __launch_bounds__(256) k_stage32(DevGrid g, int face, const float* __restrict__ w,
                                                  const float* __restrict__ q, const float* __restrict__ Lam32,
-                                                 const float* __restrict__ rC32, float* __restrict__ out, float cm,
-                                                 float tb, float tau) {
+                                                 const float* __restrict__ rC32, float* __restrict__ out,
+                                                 StageParam sp, double tau) {
+    const double tbd = stage_tb(sp, tau);
     int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
     if (i >= g.nx || j >= g.ny) return;
     int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+    const float tb = (float)tbd, cm = (float)(1.0 / (1.0 + tbd)), tf = (float)tau;
     Faces f;
     faces_of(g, i, j, k, f);
     float S = stencil<float, float, float>(g, f, a, w, Lam32, face);
-    out[a] = cm * (q[a] + tb * w[a] - tau * rC32[a] * S);
+    out[a] = cm * (q[a] + tb * w[a] - tf * rC32[a] * S);
 }
 
 __global__ void __launch_bounds__(256) k_final32(DevGrid g, int face, const float* __restrict__ w,
                                                  const double* __restrict__ rhs, const float* __restrict__ Lam32,
                                                  const double* __restrict__ rC, double* __restrict__ out,
-                                                 double tau) {
+                                                 double tau, const double* __restrict__ Tit, PassSlots ps) {
+    __shared__ double sh[16];
     int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
-    if (i >= g.nx || j >= g.ny) return;
-    int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
-    Faces f;
-    faces_of(g, i, j, k, f);
-    double va = rhs[a] + (double)w[a], La = (double)Lam32[a], S = 0.0;
+    PassAcc acc;
+    if (i < g.nx && j < g.ny) {
+        int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+        Faces f;
+        faces_of(g, i, j, k, f);
+        double va = rhs[a] + (double)w[a], La = (double)Lam32[a], S = 0.0;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        if (!f.has[q]) continue;
-        int64_t b = a + f.off[q];
-        S += g.w[q >> 1] * face_mean<double>(La, (double)Lam32[b], face) * (va - (rhs[b] + (double)w[b]));
+        for (int q = 0; q < 6; ++q) {
+            if (!f.has[q]) continue;
+            int64_t b = a + f.off[q];
+            S += g.w[q >> 1] * face_mean<double>(La, (double)Lam32[b], face) * (va - (rhs[b] + (double)w[b]));
+        }
+        double t = rhs[a] - tau * rC[a] * S;
+        out[a] = t;
+        if (Tit) acc.add(t, Tit[a]);
     }
-    out[a] = rhs[a] - tau * rC[a] * S;
+    if (Tit) acc.store(ps);
 }
 
 // ----------------------------------------------------------------- adjoint
@@ -488,19 +586,19 @@ __global__ void __launch_bounds__(256) k_adj_cell(DevGrid g, DevPhases ph, const
                                                   const double* __restrict__ alpha2, const double* __restrict__ gLam,
                                                   const double* __restrict__ dg, const double* __restrict__ lam0,
                                                   double* __restrict__ acc, double* __restrict__ mu, int first_pass,
-                                                  double* partials) {
+                                                  double* k0a, double* k0b) {
     __shared__ double sh[16];
     double s0 = 0.0, s1 = 0.0;
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
          a += (int64_t)gridDim.x * blockDim.x) {
         double t = Tit[a], a2 = alpha2[a], a1 = 1.0 - a2, gl = gLam[a];
         double acc_a = acc[a] + dg[a] + lam0[a];
-        double x0 = t / ph.T0[0], x1 = t / ph.T0[1];
+        double x0 = t * ph.invT0[0], x1 = t * ph.invT0[1];
         s0 += gl * a1 * powlaw(x0, ph.npow[0]);
         s1 += gl * a2 * powlaw(x1, ph.npow[1]);
         double dL = 0.0;
-        if (ph.npow[0] != 0.0) dL += a1 * ph.k0[0] * ph.npow[0] * powlaw(x0, ph.npow[0] - 1.0) / ph.T0[0];
-        if (ph.npow[1] != 0.0) dL += a2 * ph.k0[1] * ph.npow[1] * powlaw(x1, ph.npow[1] - 1.0) / ph.T0[1];
+        if (ph.npow[0] != 0.0) dL += a1 * ph.k0[0] * ph.npow[0] * powlaw(x0, ph.npow[0] - 1.0) * ph.invT0[0];
+        if (ph.npow[1] != 0.0) dL += a2 * ph.k0[1] * ph.npow[1] * powlaw(x1, ph.npow[1] - 1.0) * ph.invT0[1];
         double m = gl * dL;
         mu[a] = m;
         acc[a] = first_pass ? acc_a + m : acc_a;
@@ -508,10 +606,21 @@ __global__ void __launch_bounds__(256) k_adj_cell(DevGrid g, DevPhases ph, const
     double r0 = block_sum(s0, sh);
     double r1 = block_sum(s1, sh);
     if (threadIdx.x == 0) {
-        double* p = partials + (int64_t)blockIdx.x * kPartialStride;
-        p[0] = r0;
-        p[1] = r1;
+        atomicAdd(k0a + block_slot(), r0);
+        atomicAdd(k0b + block_slot(), r1);
     }
+}
+
+// One wave per target: fold its kSlots slots with the target's operation.
+__global__ void __launch_bounds__(64) k_collect(const double* __restrict__ acc, PassResult* res, int t0) {
+    const int t = t0 + blockIdx.x, lane = threadIdx.x;
+    const double* row = acc + (int64_t)t * kSlots;
+    const bool sum = tgt_is_sum(t);
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSlots / 64; ++k) v = sum ? v + row[lane + 64 * k] : fmax(v, row[lane + 64 * k]);
+    v = sum ? wave_sum(v) : wave_max(v);
+    if (lane == 0) res->v[t] = v;
 }
 
 __global__ void __launch_bounds__(256) k_fill(double* p, double v, int64_t n) {
@@ -524,62 +633,73 @@ __global__ void __launch_bounds__(256) k_copy(double* __restrict__ d, const doub
         d[a] = s[a];
 }
 
-void finalize(hipStream_t s, const double* partials, int nb, std::initializer_list<std::pair<int, double*>> slots,
-              int op) {
-    FinalizeSpec spec{};
-    for (auto& p : slots) {
-        spec.op[p.first] = op;
-        spec.dst[p.first] = p.second;
-    }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, nb, spec);
-}
-
 }  // namespace
 
 // ------------------------------------------------------------------ launches
 
+namespace {
+// Grid-stride launches use enough blocks to keep every CU busy.
+int pointwise_blocks(int64_t N) {
+    int64_t b = (N + kReduceThreads - 1) / kReduceThreads;
+    return (int)(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+}  // namespace
+
+void launch_zero_rows(hipStream_t s, double* acc, int t0, int t1) {
+    int64_t n = (int64_t)(t1 - t0) * kSlots;
+    hipLaunchKernelGGL(k_fill, dim3(pointwise_blocks(n)), dim3(256), 0, s, acc + (int64_t)t0 * kSlots, 0.0, n);
+}
+
+void launch_collect(hipStream_t s, const double* acc, PassResult* res, int t0, int t1) {
+    hipLaunchKernelGGL(k_collect, dim3(t1 - t0), dim3(64), 0, s, acc, res, t0);
+}
+
 void launch_relax(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double* alpha2,
-                  const double* m1, const double* m2, double* T1, double* T2) {
-    hipLaunchKernelGGL(k_relax, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, eps, alpha2, m1, m2,
-                       T1, T2);
+                  const double* m1, const double* m2, double* T1, double* T2, double* Tn, double* a2n) {
+    hipLaunchKernelGGL(k_relax, dim3(pointwise_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, eps, alpha2, m1, m2,
+                       T1, T2, Tn, a2n);
 }
 
 void launch_heat_coeffs(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double tau,
                         const double* T, const double* alpha2, const double* m1, const double* m2,
                         const double* Tn, const double* src1, const double* src2, double* Lam, double* rC,
                         double* rhs, float* Lam32, float* rC32) {
-    hipLaunchKernelGGL(k_heat_coeffs, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, eps, tau, T,
+    hipLaunchKernelGGL(k_heat_coeffs, dim3(pointwise_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, eps, tau, T,
                        alpha2, m1, m2, Tn, src1, src2, Lam, rC, rhs, Lam32, rC32);
+}
+
+void launch_heat_coeffs_bound(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double tau, int face,
+                              const double* T, const double* alpha2, const double* m1, const double* m2,
+                              const double* Tn, const double* src1, const double* src2, double* Lam, double* rC,
+                              double* rhs, float* Lam32, float* rC32, double* lam) {
+    hipLaunchKernelGGL(k_heat_coeffs_bound, tile_grid(g), dim3(TX, TY), 0, s, g, ph, eps, tau, face, T, alpha2, m1,
+                       m2, Tn, src1, src2, Lam, rC, rhs, Lam32, rC32, lam);
 }
 
 void launch_visc_coeffs(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* alpha2,
                         const double* m1, const double* m2, double* Lam, double* rC, float* Lam32, float* rC32) {
-    hipLaunchKernelGGL(k_visc_coeffs, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, alpha2, m1, m2,
+    hipLaunchKernelGGL(k_visc_coeffs, dim3(pointwise_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, alpha2, m1, m2,
                        Lam, rC, Lam32, rC32);
 }
 
-void launch_gershgorin(hipStream_t s, const DevGrid& g, int face, const double* Lam, const double* rC,
-                       double* partials, PassResult* res) {
-    int nb = reduce_blocks(g.N);
-    hipLaunchKernelGGL(k_gershgorin, dim3(nb), dim3(kReduceThreads), 0, s, g, face, Lam, rC, partials);
-    finalize(s, partials, nb, {{4, &res->lambda}}, 1);
+void launch_gershgorin(hipStream_t s, const DevGrid& g, int face, const double* Lam, const double* rC, double* lam) {
+    hipLaunchKernelGGL(k_gershgorin, tile_grid(g), dim3(TX, TY), 0, s, g, face, Lam, rC, lam);
 }
 
 void launch_energy(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* alpha2, const double* m1,
-                   const double* m2, const double* T1, const double* T2, double* partials, PassResult* res) {
-    int nb = reduce_blocks(g.N);
-    hipLaunchKernelGGL(k_energy, dim3(nb), dim3(kReduceThreads), 0, s, g, ph, alpha2, m1, m2, T1, T2, partials);
-    finalize(s, partials, nb, {{2, &res->energy}}, 2);
+                   const double* m2, const double* T1, const double* T2, double* energy) {
+    hipLaunchKernelGGL(k_energy, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, alpha2, m1, m2, T1, T2,
+                       energy);
 }
 
 void launch_stage64(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
-                    const double* Lam, const double* rC, double* out, double cm, double tb, double tau) {
-    hipLaunchKernelGGL(k_stage64, tile_grid(g), dim3(TX, TY), 0, s, g, face, v, rhs, Lam, rC, out, cm, tb, tau);
+                    const double* Lam, const double* rC, double* out, StageParam sp, double tau) {
+    hipLaunchKernelGGL(k_stage64, tile_grid(g), dim3(TX, TY), 0, s, g, face, v, rhs, Lam, rC, out, sp, tau);
 }
 
 void launch_final64(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
-                    const double* Lam, const double* rC, double* out, double tau) {
-    hipLaunchKernelGGL(k_final64, tile_grid(g), dim3(TX, TY), 0, s, g, face, v, rhs, Lam, rC, out, tau);
+                    const double* Lam, const double* rC, double* out, double tau, const double* Tit, PassSlots ps) {
+    hipLaunchKernelGGL(k_final64, tile_grid(g), dim3(TX, TY), 0, s, g, face, v, rhs, Lam, rC, out, tau, Tit, ps);
 }
 
 void launch_q32(hipStream_t s, const DevGrid& g, int face, const double* rhs, const double* v0,
@@ -588,32 +708,26 @@ void launch_q32(hipStream_t s, const DevGrid& g, int face, const double* rhs, co
 }
 
 void launch_stage32(hipStream_t s, const DevGrid& g, int face, const float* w, const float* q,
-                    const float* Lam32, const float* rC32, float* out, float cm, float tb, float tau) {
-    hipLaunchKernelGGL(k_stage32, tile_grid(g), dim3(TX, TY), 0, s, g, face, w, q, Lam32, rC32, out, cm, tb, tau);
+                    const float* Lam32, const float* rC32, float* out, StageParam sp, double tau) {
+    hipLaunchKernelGGL(k_stage32, tile_grid(g), dim3(TX, TY), 0, s, g, face, w, q, Lam32, rC32, out, sp, tau);
 }
 
 void launch_final32(hipStream_t s, const DevGrid& g, int face, const float* w, const double* rhs,
-                    const float* Lam32, const double* rC, double* out, double tau) {
-    hipLaunchKernelGGL(k_final32, tile_grid(g), dim3(TX, TY), 0, s, g, face, w, rhs, Lam32, rC, out, tau);
+                    const float* Lam32, const double* rC, double* out, double tau, const double* Tit, PassSlots ps) {
+    hipLaunchKernelGGL(k_final32, tile_grid(g), dim3(TX, TY), 0, s, g, face, w, rhs, Lam32, rC, out, tau, Tit, ps);
 }
 
 void launch_pass_update(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, const double* Tit,
                         const double* Tnew, const double* Tn, const double* alpha2n, const double* alpha2it,
-                        const double* m1, const double* m2, double* alpha2out, double* partials,
-                        PassResult* res) {
-    int nb = reduce_blocks(g.N);
-    hipLaunchKernelGGL(k_pass_update, dim3(nb), dim3(kReduceThreads), 0, s, g, ph, eps, Tit, Tnew, Tn, alpha2n,
-                       alpha2it, m1, m2, alpha2out, partials);
-    finalize(s, partials, nb, {{0, &res->dmax}, {1, &res->tmax}}, 1);
-    finalize(s, partials, nb, {{3, &res->bad}}, 2);
+                        const double* m1, const double* m2, double* alpha2out, PassSlots ps) {
+    hipLaunchKernelGGL(k_pass_update, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, eps, Tit, Tnew,
+                       Tn, alpha2n, alpha2it, m1, m2, alpha2out, ps);
 }
 
 void launch_be_residual(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
-                        const double* Lam, const double* rC, double tau, double* partials, PassResult* res) {
-    int nb = reduce_blocks(g.N);
-    hipLaunchKernelGGL(k_be_residual, dim3(nb), dim3(kReduceThreads), 0, s, g, face, v, rhs, Lam, rC, tau,
-                       partials);
-    finalize(s, partials, nb, {{5, &res->rr}, {6, &res->gg}}, 2);
+                        const double* Lam, const double* rC, double tau, double* rr, double* gg) {
+    hipLaunchKernelGGL(k_be_residual, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, face, v, rhs, Lam,
+                       rC, tau, rr, gg);
 }
 
 void launch_adj_stage(hipStream_t s, const DevGrid& g, int face, const double* lam, const double* vprev,
@@ -625,21 +739,17 @@ void launch_adj_stage(hipStream_t s, const DevGrid& g, int face, const double* l
 
 void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* Tit, const double* alpha2,
                      const double* gLam, const double* dg, const double* lam0, double* acc, double* mu,
-                     int first_pass, double* partials, PassResult* res) {
-    int nb = reduce_blocks(g.N);
-    hipLaunchKernelGGL(k_adj_cell, dim3(nb), dim3(kReduceThreads), 0, s, g, ph, Tit, alpha2, gLam, dg, lam0, acc,
-                       mu, first_pass, partials);
-    finalize(s, partials, nb, {{0, &res->k0g[0]}, {1, &res->k0g[1]}}, 2);
+                     int first_pass, double* k0a, double* k0b) {
+    hipLaunchKernelGGL(k_adj_cell, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, Tit, alpha2, gLam, dg,
+                       lam0, acc, mu, first_pass, k0a, k0b);
 }
 
 void launch_fill(hipStream_t s, double* p, double v, int64_t n) {
-    int64_t b = (n + 255) / 256;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096)), dim3(256), 0, s, p, v, n);
+    hipLaunchKernelGGL(k_fill, dim3(pointwise_blocks(n)), dim3(256), 0, s, p, v, n);
 }
 
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n) {
-    int64_t b = (n + 255) / 256;
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096)), dim3(256), 0, s, dst, src, n);
+    hipLaunchKernelGGL(k_copy, dim3(pointwise_blocks(n)), dim3(256), 0, s, dst, src, n);
 }
 
 }  // namespace tlim

@@ -48,11 +48,19 @@ struct tlim_ctx {
     size_t ws_bytes;
     double* field[TLIM_NFIELDS];
     bool fset[TLIM_NFIELDS];
-    double *Tn, *Tnew, *a2n, *Lam, *rC, *rhs, *vb[2], *partials;
+    double *Tn, *Tnew, *a2n, *Lam, *rC, *rhs, *vb[2];
     float *Lam32, *rC32, *q32, *wb[2];
-    PassResult* res_dev;
-    PassResult* res_host;  // pinned
+    double* acc;           // reduction rows: kTargets x kSlots
+    PassResult* res_dev;   // folded results (one double per target)
+    PassResult* res_host;  // pinned copy
     hipEvent_t ev[kMaxEvents];
+    // Schedule history for P prediction: P of each Picard pass of the last
+    // completed step (hist_passes = 0: none).
+    int hist_passes;
+    int hist_P[TLIM_MAX_PASSES];
+    // After a step T_2 = T_1 everywhere: the T2 field then reads through T1.
+    bool t2_alias;
+    int64_t predict_misses;
     std::string err;
 };
 
@@ -79,12 +87,13 @@ tlim_status fail(tlim_ctx* c, tlim_status s, const char* fmt, ...) {
 // Layout of the workspace: byte offsets of every array (all 256-aligned).
 struct Layout {
     size_t field[TLIM_NFIELDS];
-    size_t Tn, Tnew, a2n, Lam, rC, rhs, vb[2], partials, res;
+    size_t Tn, Tnew, a2n, Lam, rC, rhs, vb[2], acc, res;
     size_t Lam32, rC32, q32, wb[2];
     size_t total;
 };
 
-Layout layout_of(int64_t N, int precision) {
+Layout layout_of(const int64_t n[3], int precision) {
+    const int64_t N = n[0] * n[1] * n[2];
     Layout L{};
     size_t off = 0;
     size_t d = align_up(sizeof(double) * (size_t)N), f = align_up(sizeof(float) * (size_t)N);
@@ -97,8 +106,8 @@ Layout layout_of(int64_t N, int precision) {
         *p = off;
         off += d;
     }
-    L.partials = off;
-    off += align_up(sizeof(double) * tlim::kReduceBlocks * tlim::kPartialStride);
+    L.acc = off;
+    off += align_up(sizeof(double) * (size_t)tlim::kTargets * tlim::kSlots);
     L.res = off;
     off += align_up(sizeof(PassResult));
     if (precision == TLIM_FP32) {
@@ -135,6 +144,7 @@ DevPhases dev_phases(const tlim_ctx* c) {
         p.cv[k] = c->phase[k].cv;
         p.k0[k] = c->phase[k].k0;
         p.T0[k] = c->phase[k].T0;
+        p.invT0[k] = 1.0 / c->phase[k].T0;
         p.npow[k] = c->phase[k].npow;
         p.mu[k] = c->phase[k].mu;
     }
@@ -252,11 +262,60 @@ struct SweepCount {
     int64_t sweeps = 0, launches = 0;
 };
 
+// Reduction rows are zeroed before the kernels that accumulate into them
+// (stream order); collect folds them for the host.
+double* row(tlim_ctx* c, int t) { return c->acc + (size_t)t * tlim::kSlots; }
+void zero_rows(tlim_ctx* c, int t0, int t1) { tlim::launch_zero_rows(c->stream, c->acc, t0, t1); }
+double result(const tlim_ctx* c, int t) { return c->res_host->v[t]; }
+
+tlim::PassSlots pass_slots(tlim_ctx* c, int it) {
+    return tlim::PassSlots{row(c, tlim::tgt_dmax(it)), row(c, tlim::tgt_tmax(it)), row(c, tlim::tgt_bad(it))};
+}
+
+double* T2_ptr(tlim_ctx* c) { return c->t2_alias ? c->field[TLIM_T1] : c->field[TLIM_T2]; }
+
+// Stage parameters of one pass: given b (lam_dev == NULL) or, with the
+// bound on the device, the normalised parameters b/lambda of the same P.
+struct PassSchedule {
+    const double* lam_dev = nullptr;
+    std::vector<double> tb;    // tau * b_m (host bound)
+    std::vector<double> chat;  // b_m / lambda (device bound)
+    int nst = 0;
+    tlim::Stages at(int m) const {
+        tlim::Stages st;
+        st.lam = lam_dev;
+        st.tb = lam_dev ? nullptr : tb.data() + m;
+        st.chat = lam_dev ? chat.data() + m : nullptr;
+        return st;
+    }
+};
+
+PassSchedule host_schedule(double tau, double lam, int order) {
+    PassSchedule ps;
+    int P = lim_P(tau, lam);
+    std::vector<double> b = lim_params(P, lam, order);
+    ps.nst = (int)b.size();
+    ps.tb.resize(b.size());
+    for (size_t m = 0; m < b.size(); ++m) ps.tb[m] = tau * b[m];
+    return ps;
+}
+
+PassSchedule device_schedule(int P, int order, const double* lam_dev) {
+    PassSchedule ps;
+    ps.chat = lim_params(P, 1.0, order);
+    ps.nst = (int)ps.chat.size();
+    ps.lam_dev = lam_dev;
+    return ps;
+}
+
 // out = LIM pass (eqs. LIM, LIM_last) from v0 with right-hand side rhs and the
 // coefficients in c->Lam/c->rC (and their float copies in FP32 contexts).
-void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const std::vector<double>& b,
-                  const double* v0, const double* rhs, double* out, Timer& tm, SweepCount& sc) {
-    const int nst = (int)b.size();
+// With Tit != NULL the kernel that writes `out` also accumulates the pass
+// reductions into ps.
+void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const PassSchedule& ps, const double* v0,
+                  const double* rhs, double* out, const double* Tit, tlim::PassSlots slots, Timer& tm,
+                  SweepCount& sc) {
+    const int nst = ps.nst;
     hipStream_t s = c->stream;
     tm.start();
     if (c->precision == TLIM_FP32) {
@@ -266,12 +325,12 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const std
         while (m < nst - 1) {
             int k = tlim::sweeps_per_launch(g, nst - 1 - m);
             float* nxt = cur == c->wb[0] ? c->wb[1] : c->wb[0];
-            int done = tlim::launch_sweeps32(s, g, face, cur, c->q32, c->Lam32, c->rC32, nxt, b.data() + m, k, tau);
+            int done = tlim::launch_sweeps32(s, g, face, cur, c->q32, c->Lam32, c->rC32, nxt, ps.at(m), k, tau);
             cur = nxt;
             m += done;
             sc.launches++;
         }
-        tlim::launch_final32(s, g, face, cur, rhs, c->Lam32, c->rC, out, tau);
+        tlim::launch_final32(s, g, face, cur, rhs, c->Lam32, c->rC, out, tau, Tit, slots);
         sc.launches++;
     } else {
         // all 2P-1 stages, the last (b = 0) in flux form; the launch that
@@ -281,8 +340,10 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const std
         int pp = 0;
         while (m < nst) {
             int k = tlim::sweeps_per_launch(g, nst - m);
-            double* nxt = m + k == nst ? out : c->vb[pp];
-            int done = tlim::launch_sweeps64(s, g, face, cur, rhs, c->Lam, c->rC, nxt, b.data() + m, k, tau);
+            bool last = m + k == nst;
+            double* nxt = last ? out : c->vb[pp];
+            int done = tlim::launch_sweeps64(s, g, face, cur, rhs, c->Lam, c->rC, nxt, ps.at(m), k, last, tau, Tit,
+                                             slots);
             cur = nxt;
             pp ^= 1;
             m += done;
@@ -293,7 +354,9 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const std
     tm.stop();
 }
 
-tlim_status read_result(tlim_ctx* c) {
+// Fold the rows [t0, t1) and bring the results to the host (synchronises).
+tlim_status read_result(tlim_ctx* c, int t0, int t1) {
+    tlim::launch_collect(c->stream, c->acc, c->res_dev, t0, t1);
     HIP_TRY(c, hipMemcpyAsync(c->res_host, c->res_dev, sizeof(PassResult), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return TLIM_OK;
@@ -317,31 +380,32 @@ tlim_status viscous(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep,
         if (o->frozen_visc) {
             lam = o->frozen_visc[comp];
         } else {
-            tlim::launch_gershgorin(c->stream, g, o->face_mean, c->Lam, c->rC, c->partials, c->res_dev);
-            tlim_status st = read_result(c);
+            zero_rows(c, tlim::kTgtLambda, tlim::kTgtLambda + 1);
+            tlim::launch_gershgorin(c->stream, g, o->face_mean, c->Lam, c->rC, row(c, tlim::kTgtLambda));
+            tlim_status st = read_result(c, tlim::kTgtLambda, tlim::kTgtLambda + 1);
             if (st) return st;
-            lam = c->res_host->lambda;
+            lam = result(c, tlim::kTgtLambda);
         }
-        int P = lim_P(o->dt, lam);
-        std::vector<double> b = lim_params(P, lam, o->order);
+        PassSchedule ps = host_schedule(o->dt, lam, o->order);
         double* u = c->field[TLIM_U + comp];
-        run_lim_pass(c, g, o->face_mean, o->dt, b, u, u, c->Tnew, tm, sc);
+        run_lim_pass(c, g, o->face_mean, o->dt, ps, u, u, c->Tnew, nullptr, tlim::PassSlots{}, tm, sc);
         std::swap(c->field[TLIM_U + comp], c->Tnew);
         if (rep) {
-            rep->visc_P[comp] = P;
+            rep->visc_P[comp] = lim_P(o->dt, lam);
             rep->visc_lambda_G[comp] = lam;
         }
     }
     return TLIM_OK;
 }
 
-// Heat-conduction coefficients of the current iterate (T1, alpha2).
-void heat_coeffs(tlim_ctx* c, const DevGrid& g, const DevPhases& ph, const tlim_step_opts* o) {
-    tlim::launch_heat_coeffs(c->stream, g, ph, o->alpha_eps, o->dt, c->field[TLIM_T1], c->field[TLIM_ALPHA2],
-                             c->field[TLIM_M1], c->field[TLIM_M2], c->Tn,
-                             c->fset[TLIM_SRC1] ? c->field[TLIM_SRC1] : nullptr,
-                             c->fset[TLIM_SRC2] ? c->field[TLIM_SRC2] : nullptr, c->Lam, c->rC, c->rhs, c->Lam32,
-                             c->rC32);
+// Heat-conduction coefficients of the current iterate (T1, alpha2) and the
+// Gershgorin bound (max into *lam).
+void heat_coeffs(tlim_ctx* c, const DevGrid& g, const DevPhases& ph, const tlim_step_opts* o, double* lam) {
+    tlim::launch_heat_coeffs_bound(c->stream, g, ph, o->alpha_eps, o->dt, o->face_mean, c->field[TLIM_T1],
+                                   c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], c->Tn,
+                                   c->fset[TLIM_SRC1] ? c->field[TLIM_SRC1] : nullptr,
+                                   c->fset[TLIM_SRC2] ? c->field[TLIM_SRC2] : nullptr, c->Lam, c->rC, c->rhs,
+                                   c->Lam32, c->rC32, lam);
 }
 
 // Chebyshev cycles to the backward-Euler solution of one pass (cycle mode).
@@ -355,26 +419,143 @@ tlim_status cycle_pass(tlim_ctx* c, const DevGrid& g, const tlim_step_opts* o, i
     while (cyc < o->max_cycles) {
         tm.start();
         for (int m = 0; m < s_stages; ++m) {
-            double tb = o->dt * b[m];
-            tlim::launch_stage64(c->stream, g, o->face_mean, c->vb[cur], c->rhs, c->Lam, c->rC, c->vb[cur ^ 1],
-                                 1.0 / (1.0 + tb), tb, o->dt);
+            tlim::StageParam sp{nullptr, o->dt * b[m], 0.0};
+            tlim::launch_stage64(c->stream, g, o->face_mean, c->vb[cur], c->rhs, c->Lam, c->rC, c->vb[cur ^ 1], sp,
+                                 o->dt);
             cur ^= 1;
             sc.launches++;
         }
         tm.stop();
         sc.sweeps += s_stages;
         ++cyc;
-        tlim::launch_be_residual(c->stream, g, o->face_mean, c->vb[cur], c->rhs, c->Lam, c->rC, o->dt, c->partials,
-                                 c->res_dev);
-        tlim_status st = read_result(c);
+        zero_rows(c, tlim::kTgtRR, tlim::kTgtGG + 1);
+        tlim::launch_be_residual(c->stream, g, o->face_mean, c->vb[cur], c->rhs, c->Lam, c->rC, o->dt,
+                                 row(c, tlim::kTgtRR), row(c, tlim::kTgtGG));
+        tlim_status st = read_result(c, tlim::kTgtRR, tlim::kTgtGG + 1);
         if (st) return st;
-        double rr = c->res_host->rr, gg = c->res_host->gg;
+        double rr = result(c, tlim::kTgtRR), gg = result(c, tlim::kTgtGG);
         r = gg > 0.0 ? std::sqrt(rr / gg) : std::sqrt(rr);
         if (r < o->cycle_tol) break;
     }
     tlim::launch_copy(c->stream, c->Tnew, c->vb[cur], c->N);
     *cycles = cyc;
     *residual = r;
+    return TLIM_OK;
+}
+
+enum class Mode { Sync, Frozen, Predict };
+
+struct HeatOutcome {
+    int passes_run = 0;
+    bool converged = false;
+    bool cycle_fail = false;
+    bool mispredicted = false;
+    double last_err = 0.0;
+    double bad = 0.0;
+};
+
+// Picard loop of Algorithm 1 from the relaxed state (T1 = T^n, copied in Tn).
+// Sync: one readback per pass brings lambda_G of the pass (and the change of
+// the previous one).  Frozen: lambda per pass from the caller.  Predict: the
+// P of each pass is taken from the previous step and the stages read lambda_G
+// from device memory; the predictions are checked after one readback at the
+// end (mispredicted = true means the caller must roll back and rerun).
+tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_step_report* rep, Timer& tm,
+                        SweepCount& sc, HeatOutcome& out) {
+    hipStream_t s = c->stream;
+    DevGrid g = dev_grid(c, kUnit);
+    DevPhases ph = dev_phases(c);
+    const bool B1 = c->phase[0].pinf != c->phase[1].pinf;
+    int it;
+    int P_used[TLIM_MAX_PASSES] = {0};
+    zero_rows(c, tlim::tgt_lam(0), tlim::tgt_lam(o->passes));
+    auto change = [&](int i) {
+        double tmax = result(c, tlim::tgt_tmax(i)), dmax = result(c, tlim::tgt_dmax(i));
+        return tmax > 0.0 ? dmax / tmax : dmax;
+    };
+    for (it = 0; it < o->passes; ++it) {
+        heat_coeffs(c, g, ph, o, row(c, tlim::tgt_lam(it)));
+        double lam = 0.0;
+        if (mode == Mode::Sync) {
+            // one readback: lambda_G of this pass and the change of the previous one
+            tlim_status st = read_result(c, tlim::tgt_lam(0), tlim::tgt_lam(it + 1));
+            if (st) return st;
+            lam = result(c, tlim::tgt_lam(it));
+            if (it > 0) {
+                out.last_err = change(it - 1);
+                if (rep) rep->err[it - 1] = out.last_err;
+                if (o->picard_tol > 0.0 && out.last_err < o->picard_tol) {
+                    out.converged = true;
+                    out.bad = result(c, tlim::tgt_bad(it - 1));
+                    break;
+                }
+            }
+        } else if (mode == Mode::Frozen) {
+            lam = o->frozen_lambda[it];
+        }
+        PassSchedule ps;
+        int P;
+        if (mode == Mode::Predict) {
+            P = c->hist_P[it];
+            ps = device_schedule(P, o->order, row(c, tlim::tgt_lam(it)));
+        } else {
+            P = lim_P(o->dt, lam);
+            ps = host_schedule(o->dt, lam, o->order);
+            if (rep) rep->lambda_G[it] = lam;
+        }
+        P_used[it] = P;
+        if (rep) rep->P[it] = P;
+        const bool need_update = B1 || o->cycle_mode;
+        if (o->cycle_mode) {
+            int ncyc = 0;
+            double res = 0.0;
+            tlim_status st = cycle_pass(c, g, o, 2 * P - 1, lam, &ncyc, &res, tm, sc);
+            if (st) return st;
+            if (rep) {
+                rep->cycles[it] = ncyc;
+                rep->residual[it] = res;
+            }
+            if (!(res < o->cycle_tol)) out.cycle_fail = true;  // keep the last iterate
+        } else {
+            run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->rhs, c->Tnew,
+                         need_update ? nullptr : c->field[TLIM_T1], pass_slots(c, it), tm, sc);
+        }
+        if (need_update) {
+            tlim::launch_pass_update(s, g, ph, o->alpha_eps, c->field[TLIM_T1], c->Tnew, c->Tn, c->a2n,
+                                     c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2],
+                                     c->field[TLIM_ALPHA2], pass_slots(c, it));
+        }
+        std::swap(c->field[TLIM_T1], c->Tnew);
+    }
+    out.passes_run = it;
+    if (!out.converged) {
+        tlim_status st = read_result(c, tlim::tgt_lam(0), tlim::tgt_lam(it));
+        if (st) return st;
+        int last = it - 1;
+        out.last_err = change(last);
+        out.bad = result(c, tlim::tgt_bad(last));
+        if (rep) rep->err[last] = out.last_err;
+        if (o->picard_tol > 0.0 && out.last_err < o->picard_tol) out.converged = true;
+    }
+    if (mode == Mode::Predict) {
+        // check every predicted P against the bound the step actually met
+        for (int i = 0; i < out.passes_run; ++i) {
+            double lam = result(c, tlim::tgt_lam(i));
+            if (rep) rep->lambda_G[i] = lam;
+            if (lim_P(o->dt, lam) != P_used[i]) out.mispredicted = true;
+        }
+        if (rep)
+            for (int i = 0; i + 1 < out.passes_run; ++i) rep->err[i] = change(i);
+    }
+    if (mode != Mode::Frozen && !out.mispredicted && !o->cycle_mode && out.passes_run > 0) {
+        // The next step's passes start from T^{n+1}, the output of this step's
+        // last pass, whose conductivities are closest to this step's last
+        // lagged iterate: predict every pass of the next step with the P of
+        // this step's last pass.
+        c->hist_passes = out.passes_run;
+        const int Plast = lim_P(o->dt, result(c, tlim::tgt_lam(out.passes_run - 1)));
+        for (int i = 0; i < out.passes_run; ++i) c->hist_P[i] = Plast;
+    }
     return TLIM_OK;
 }
 
@@ -451,14 +632,14 @@ tlim_status tlim_destroy(tlim_ctx* c) {
 
 tlim_status tlim_workspace_bytes(const tlim_ctx* c, size_t* bytes) {
     if (!c || !bytes) return TLIM_E_ARG;
-    *bytes = layout_of(c->N, c->precision).total;
+    *bytes = layout_of(c->n, c->precision).total;
     return TLIM_OK;
 }
 
 tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
     if (!c) return TLIM_E_ARG;
     if (!dev_ptr || ((uintptr_t)dev_ptr % kAlign) != 0) return fail(c, TLIM_E_ARG, "workspace NULL or not 256-byte aligned");
-    Layout L = layout_of(c->N, c->precision);
+    Layout L = layout_of(c->n, c->precision);
     if (bytes < L.total) return fail(c, TLIM_E_NOMEM, "workspace %zu bytes < %zu required", bytes, L.total);
     char* base = (char*)dev_ptr;
     c->ws = base;
@@ -475,8 +656,10 @@ tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
     c->rhs = (double*)(base + L.rhs);
     c->vb[0] = (double*)(base + L.vb[0]);
     c->vb[1] = (double*)(base + L.vb[1]);
-    c->partials = (double*)(base + L.partials);
+    c->acc = (double*)(base + L.acc);
     c->res_dev = (PassResult*)(base + L.res);
+    c->t2_alias = false;
+    c->hist_passes = 0;
     if (c->precision == TLIM_FP32) {
         c->Lam32 = (float*)(base + L.Lam32);
         c->rC32 = (float*)(base + L.rC32);
@@ -504,6 +687,11 @@ tlim_status tlim_set_field(tlim_ctx* c, int32_t f, const double* src) {
     if (!c) return TLIM_E_ARG;
     if (f < 0 || f >= TLIM_NFIELDS || !src) return fail(c, TLIM_E_ARG, "bad field index or NULL source");
     if (!c->ws) return fail(c, TLIM_E_STATE, "no workspace bound");
+    if (c->t2_alias && (f == TLIM_T1 || f == TLIM_T2)) {
+        // give T2 its own values again before either temperature changes
+        tlim::launch_copy(c->stream, c->field[TLIM_T2], c->field[TLIM_T1], c->N);
+        c->t2_alias = false;
+    }
     HIP_TRY(c, hipMemcpyAsync(c->field[f], src, sizeof(double) * (size_t)c->N, hipMemcpyDeviceToDevice, c->stream));
     c->fset[f] = true;
     return TLIM_OK;
@@ -514,7 +702,8 @@ tlim_status tlim_get_field(const tlim_ctx* cc, int32_t f, double* dst) {
     if (!c) return TLIM_E_ARG;
     if (f < 0 || f >= TLIM_NFIELDS || !dst) return fail(c, TLIM_E_ARG, "bad field index or NULL destination");
     if (!c->ws || !c->fset[f]) return fail(c, TLIM_E_STATE, "field %d not set", f);
-    HIP_TRY(c, hipMemcpyAsync(dst, c->field[f], sizeof(double) * (size_t)c->N, hipMemcpyDeviceToDevice, c->stream));
+    const double* src = f == TLIM_T2 ? T2_ptr(c) : c->field[f];
+    HIP_TRY(c, hipMemcpyAsync(dst, src, sizeof(double) * (size_t)c->N, hipMemcpyDeviceToDevice, c->stream));
     return TLIM_OK;
 }
 
@@ -529,14 +718,16 @@ tlim_status tlim_spectral_bound(tlim_ctx* c, int32_t face_mean, double alpha_eps
     DevPhases ph = dev_phases(c);
     tlim::launch_copy(c->stream, c->a2n, c->field[TLIM_ALPHA2], c->N);
     tlim::launch_copy(c->stream, c->Tn, c->field[TLIM_T1], c->N);
-    tlim::launch_copy(c->stream, c->Tnew, c->field[TLIM_T2], c->N);
-    tlim::launch_relax(c->stream, g, ph, alpha_eps, c->a2n, c->field[TLIM_M1], c->field[TLIM_M2], c->Tn, c->Tnew);
-    tlim::launch_heat_coeffs(c->stream, g, ph, alpha_eps, 1.0, c->Tn, c->a2n, c->field[TLIM_M1], c->field[TLIM_M2],
-                             c->Tn, nullptr, nullptr, c->Lam, c->rC, c->rhs, nullptr, nullptr);
-    tlim::launch_gershgorin(c->stream, g, face_mean, c->Lam, c->rC, c->partials, c->res_dev);
-    st = read_result(c);
+    tlim::launch_copy(c->stream, c->Tnew, T2_ptr(c), c->N);
+    tlim::launch_relax(c->stream, g, ph, alpha_eps, c->a2n, c->field[TLIM_M1], c->field[TLIM_M2], c->Tn, c->Tnew,
+                       nullptr, nullptr);
+    zero_rows(c, tlim::kTgtLambda, tlim::kTgtLambda + 1);
+    tlim::launch_heat_coeffs_bound(c->stream, g, ph, alpha_eps, 1.0, face_mean, c->Tn, c->a2n, c->field[TLIM_M1],
+                                   c->field[TLIM_M2], c->Tn, nullptr, nullptr, c->Lam, c->rC, c->rhs, nullptr,
+                                   nullptr, row(c, tlim::kTgtLambda));
+    st = read_result(c, tlim::kTgtLambda, tlim::kTgtLambda + 1);
     if (st) return st;
-    *lambda_out = c->res_host->lambda;
+    *lambda_out = result(c, tlim::kTgtLambda);
     return TLIM_OK;
 }
 
@@ -556,11 +747,12 @@ tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
     SweepCount sc;
 
     if (rep) {
+        zero_rows(c, tlim::kTgtEnergy, tlim::kTgtEnergy + 1);
         tlim::launch_energy(s, g, ph, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], c->field[TLIM_T1],
-                            c->field[TLIM_T2], c->partials, c->res_dev);
-        st = read_result(c);
+                            T2_ptr(c), row(c, tlim::kTgtEnergy));
+        st = read_result(c, tlim::kTgtEnergy, tlim::kTgtEnergy + 1);
         if (st) return st;
-        rep->energy_before = c->res_host->energy * vol;
+        rep->energy_before = result(c, tlim::kTgtEnergy) * vol;
     }
     // splitting order of the paper: viscous part, temperature relaxation, heat conduction
     if (o->do_viscous) {
@@ -568,93 +760,52 @@ tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
         if (st) return st;
     }
     tlim::launch_relax(s, g, ph, o->alpha_eps, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2],
-                       c->field[TLIM_T1], c->field[TLIM_T2]);
-    tlim::launch_copy(s, c->Tn, c->field[TLIM_T1], c->N);
-    if (B1) tlim::launch_copy(s, c->a2n, c->field[TLIM_ALPHA2], c->N);
+                       c->field[TLIM_T1], T2_ptr(c), c->Tn, B1 ? c->a2n : nullptr);
+    c->t2_alias = true;  // T_1 = T_2 from here on
 
-    // Algorithm 1: Picard passes with coefficients lagged at T^(it).
-    const bool need_bound = o->frozen_lambda == nullptr;
-    heat_coeffs(c, g, ph, o);
-    if (need_bound) tlim::launch_gershgorin(s, g, o->face_mean, c->Lam, c->rC, c->partials, c->res_dev);
-    int it = 0;
-    bool converged = false, cycle_fail = false;
-    double last_err = 0.0;
-    for (it = 0; it < o->passes; ++it) {
-        // one readback brings lambda_G of this pass and the change of the previous one
-        const bool sync_now = need_bound || (o->picard_tol > 0.0 && it > 0);
-        if (sync_now) {
-            st = read_result(c);
-            if (st) return st;
-        }
-        if (it > 0 && sync_now) {
-            double tmax = c->res_host->tmax;
-            last_err = tmax > 0.0 ? c->res_host->dmax / tmax : c->res_host->dmax;
-            if (rep) rep->err[it - 1] = last_err;
-            if (o->picard_tol > 0.0 && last_err < o->picard_tol) {
-                converged = true;
-                break;
-            }
-        }
-        double lam = need_bound ? c->res_host->lambda : o->frozen_lambda[it];
-        int P = lim_P(o->dt, lam);
-        if (rep) {
-            rep->P[it] = P;
-            rep->lambda_G[it] = lam;
-        }
-        if (o->cycle_mode) {
-            int ncyc = 0;
-            double res = 0.0;
-            st = cycle_pass(c, g, o, 2 * P - 1, lam, &ncyc, &res, tm, sc);
-            if (st) return st;
-            if (rep) {
-                rep->cycles[it] = ncyc;
-                rep->residual[it] = res;
-            }
-            if (!(res < o->cycle_tol)) cycle_fail = true;  // keep the last iterate
-        } else {
-            std::vector<double> b = lim_params(P, lam, o->order);
-            run_lim_pass(c, g, o->face_mean, o->dt, b, c->Tn, c->rhs, c->Tnew, tm, sc);
-        }
-        tlim::launch_pass_update(s, g, ph, o->alpha_eps, c->field[TLIM_T1], c->Tnew, c->Tn, c->a2n,
-                                 c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], c->field[TLIM_ALPHA2],
-                                 c->partials, c->res_dev);
-        std::swap(c->field[TLIM_T1], c->Tnew);
-        if (it + 1 < o->passes) {
-            heat_coeffs(c, g, ph, o);
-            if (need_bound) tlim::launch_gershgorin(s, g, o->face_mean, c->Lam, c->rC, c->partials, c->res_dev);
-        }
-    }
-    int passes_run = it;
-    if (!converged) {
-        st = read_result(c);
+    Mode mode = Mode::Sync;
+    if (o->frozen_lambda) mode = Mode::Frozen;
+    else if (!o->cycle_mode && o->picard_tol <= 0.0 && c->hist_passes == o->passes) mode = Mode::Predict;
+    HeatOutcome out;
+    st = heat_passes(c, o, mode, rep, tm, sc, out);
+    if (st) return st;
+    const bool predicted = mode == Mode::Predict && !out.mispredicted;
+    const bool mispredicted = out.mispredicted;
+    if (out.mispredicted) {
+        // roll back to the relaxed state and rerun with one readback per pass;
+        // only the rerun's sweeps count
+        c->predict_misses++;
+        tlim::launch_copy(s, c->field[TLIM_T1], c->Tn, c->N);
+        if (B1) tlim::launch_copy(s, c->field[TLIM_ALPHA2], c->a2n, c->N);
+        out = HeatOutcome{};
+        sc = SweepCount{};
+        tm.used = 0;
+        st = heat_passes(c, o, Mode::Sync, rep, tm, sc, out);
         if (st) return st;
-        double tmax = c->res_host->tmax;
-        last_err = tmax > 0.0 ? c->res_host->dmax / tmax : c->res_host->dmax;
-        if (rep && passes_run > 0) rep->err[passes_run - 1] = last_err;
-        if (o->picard_tol > 0.0 && last_err < o->picard_tol) converged = true;
     }
-    double bad = c->res_host->bad;
-    tlim::launch_copy(s, c->field[TLIM_T2], c->field[TLIM_T1], c->N);
     if (rep) {
+        zero_rows(c, tlim::kTgtEnergy, tlim::kTgtEnergy + 1);
         tlim::launch_energy(s, g, ph, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], c->field[TLIM_T1],
-                            c->field[TLIM_T2], c->partials, c->res_dev);
-        st = read_result(c);
+                            c->field[TLIM_T1], row(c, tlim::kTgtEnergy));
+        st = read_result(c, tlim::kTgtEnergy, tlim::kTgtEnergy + 1);
         if (st) return st;
-        rep->energy_after = c->res_host->energy * vol;
-        rep->passes_run = passes_run;
-        rep->converged = (o->picard_tol <= 0.0 || converged) && !cycle_fail;
+        rep->energy_after = result(c, tlim::kTgtEnergy) * vol;
+        rep->passes_run = out.passes_run;
+        rep->converged = (o->picard_tol <= 0.0 || out.converged) && !out.cycle_fail;
         rep->sweeps = sc.sweeps;
         rep->sweep_launches = sc.launches;
-        rep->bad_cells = (int64_t)bad;
+        rep->bad_cells = (int64_t)out.bad;
+        rep->predicted = predicted ? 1 : 0;
+        rep->mispredicted = mispredicted ? 1 : 0;
         if (tm.on) {
             HIP_TRY(c, hipStreamSynchronize(s));
             rep->sweep_ms = tm.elapsed_ms();
         }
     }
     HIP_TRY(c, hipGetLastError());
-    if (bad > 0.0) return fail(c, TLIM_E_NUMERIC, "%.0f cells with non-finite or non-positive T", bad);
-    if ((o->picard_tol > 0.0 && !converged) || cycle_fail)
-        return fail(c, TLIM_E_NOCONV, "tolerance not reached (last Picard change %.3e)", last_err);
+    if (out.bad > 0.0) return fail(c, TLIM_E_NUMERIC, "%.0f cells with non-finite or non-positive T", out.bad);
+    if ((o->picard_tol > 0.0 && !out.converged) || out.cycle_fail)
+        return fail(c, TLIM_E_NOCONV, "tolerance not reached (last Picard change %.3e)", out.last_err);
     return TLIM_OK;
 }
 
@@ -718,23 +869,22 @@ void adj_forward_step(tlim_ctx* c, const tlim_step_opts* o, const double* lamv, 
             double* st0 = stages + (size_t)it * stride_pass;
             tlim::launch_copy(s, st0, Tn, N);
             for (int m = 1; m < nst; ++m) {
-                double tb = o->dt * b[m - 1];
+                tlim::StageParam sp{nullptr, o->dt * b[m - 1], 0.0};
                 tlim::launch_stage64(s, g, o->face_mean, st0 + (size_t)(m - 1) * stride_field, c->rhs, c->Lam, c->rC,
-                                     st0 + (size_t)m * stride_field, 1.0 / (1.0 + tb), tb, o->dt);
+                                     st0 + (size_t)m * stride_field, sp, o->dt);
             }
             tlim::launch_final64(s, g, o->face_mean, st0 + (size_t)(nst - 1) * stride_field, c->rhs, c->Lam, c->rC,
-                                 Tout, o->dt);
+                                 Tout, o->dt, nullptr, tlim::PassSlots{});
         } else {
             const double* cur = Tn;
             int pp = 0;
             for (int m = 1; m < nst; ++m) {
-                double tb = o->dt * b[m - 1];
-                tlim::launch_stage64(s, g, o->face_mean, cur, c->rhs, c->Lam, c->rC, c->vb[pp], 1.0 / (1.0 + tb), tb,
-                                     o->dt);
+                tlim::StageParam sp{nullptr, o->dt * b[m - 1], 0.0};
+                tlim::launch_stage64(s, g, o->face_mean, cur, c->rhs, c->Lam, c->rC, c->vb[pp], sp, o->dt);
                 cur = c->vb[pp];
                 pp ^= 1;
             }
-            tlim::launch_final64(s, g, o->face_mean, cur, c->rhs, c->Lam, c->rC, Tout, o->dt);
+            tlim::launch_final64(s, g, o->face_mean, cur, c->rhs, c->Lam, c->rC, Tout, o->dt, nullptr, tlim::PassSlots{});
         }
     }
 }
@@ -834,12 +984,13 @@ tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, i
                 pp ^= 1;
             }
             // cur = dL/dv^(0); mu <- dL/dT^(it) through Lambda(T^(it))
+            zero_rows(c, tlim::kTgtK0a, tlim::kTgtK0b + 1);
             tlim::launch_adj_cell(s, g, ph, Tit, c->field[TLIM_ALPHA2], gLam, dg, cur, acc, mu, it == 0 ? 1 : 0,
-                                  c->partials, c->res_dev);
-            st = read_result(c);
+                                  row(c, tlim::kTgtK0a), row(c, tlim::kTgtK0b));
+            st = read_result(c, tlim::kTgtK0a, tlim::kTgtK0b + 1);
             if (st) return st;
-            k0g[0] += c->res_host->k0g[0];
-            k0g[1] += c->res_host->k0g[1];
+            k0g[0] += result(c, tlim::kTgtK0a);
+            k0g[1] += result(c, tlim::kTgtK0b);
         }
         tlim::launch_copy(s, mu, acc, N);
     }

@@ -39,16 +39,20 @@ struct TBArgs {
     const R* Lam;
     const R* rC;
     R* out;
+    const double* lam;       // accumulator row of lambda_max (NULL: use tb)
+    const double* Tit;       // previous iterate: accumulate the pass reductions (last launch, FP64)
+    PassSlots ps;
     int nx, ny, perx, pery;
     R wx, wy, tau;
     int K, face, tiles_x, ox, oy;
-    R cm[KMAX], tb[KMAX];
+    double taud;
+    double tb[KMAX], chat[KMAX];
 };
 
-// Lane i receives lane i-1 (wave_shr:1) or lane i+1 (wave_shl:1); the lanes
-// at the ends receive 0 and are halo lanes.
-__device__ __forceinline__ int dpp_from_left(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, false); }
-__device__ __forceinline__ int dpp_from_right(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, false); }
+// Lane i receives lane i-1 (wave_shr:1) or lane i+1 (wave_shl:1); with
+// bound_ctrl the lanes at the ends receive 0 (they are halo lanes).
+__device__ __forceinline__ int dpp_from_left(int x) { return __builtin_amdgcn_mov_dpp(x, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_from_right(int x) { return __builtin_amdgcn_mov_dpp(x, 0x130, 0xF, 0xF, true); }
 
 __device__ __forceinline__ double from_left(double x) {
     return __hiloint2double(dpp_from_left(__double2hiint(x)), dpp_from_left(__double2loint(x)));
@@ -80,7 +84,7 @@ __device__ __forceinline__ int fold(int c, int n, int per) {
 }
 
 template <typename R>
-__global__ void __launch_bounds__(64 * WAVES) k_tb2d(TBArgs<R> a) {
+__global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
     __shared__ R sh_lo[2][WAVES][64];  // row 0 of each wave (the "up" row of the wave below)
     __shared__ R sh_hi[2][WAVES][64];  // row ROWS-1 of each wave (the "down" row of the wave above)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -125,6 +129,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_tb2d(TBArgs<R> a) {
             kU[r] = fU ? t[r] * a.wy * fmean<R>(L[r], Lu, a.face) : R(0);
         }
     }
+    // lambda_G of the pass from its accumulator row (every wave folds it)
+    double lamv = 0.0;
+    if (a.lam) {
+#pragma unroll
+        for (int k = 0; k < kSlots / 64; ++k) lamv = fmax(lamv, a.lam[lane + 64 * k]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) lamv = fmax(lamv, __shfl_xor(lamv, o, 64));
+    }
     // Stage s exchanges the seam rows through LDS buffer (s+1)&1; buffer 0
     // held the Lambda seams, whose reads all precede the first barrier below.
     for (int s = 0; s < K; ++s) {
@@ -134,7 +146,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_tb2d(TBArgs<R> a) {
         __syncthreads();
         const R vdn = wv > 0 ? sh_hi[buf][wv - 1][lane] : v[0];
         const R vup = wv < WAVES - 1 ? sh_lo[buf][wv + 1][lane] : v[ROWS - 1];
-        const R cm = a.cm[s], tb = a.tb[s];
+        const double tbd = a.lam ? a.taud * lamv * a.chat[s] : a.tb[s];
+        const R cm = (R)(1.0 / (1.0 + tbd)), tb = (R)tbd;
         R prev = vdn;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
@@ -146,19 +159,44 @@ __global__ void __launch_bounds__(64 * WAVES) k_tb2d(TBArgs<R> a) {
             prev = c;
         }
     }
+    double dmax = 0.0, tmax = 0.0, bad = 0.0;
     if (lane >= K && lane < 64 - K && xg < a.nx) {
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int row = wv * ROWS + r;
             const int y = yg0 + r;
-            if (row >= K && row < EXT_Y - K && y < a.ny) a.out[(int64_t)y * a.nx + xg] = v[r];
+            if (row >= K && row < EXT_Y - K && y < a.ny) {
+                const int64_t o = (int64_t)y * a.nx + xg;
+                a.out[o] = v[r];
+                if (a.Tit) {
+                    const double tn = (double)v[r];
+                    dmax = fmax(dmax, fabs(tn - a.Tit[o]));
+                    tmax = fmax(tmax, fabs(tn));
+                    if (!(tn > 0.0) || isinf(tn)) bad += 1.0;
+                }
+            }
+        }
+    }
+    if (a.Tit) {
+        // wave-level fold, then lane 0 of every wave adds to a slot of the rows
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+            tmax = fmax(tmax, __shfl_xor(tmax, o, 64));
+            bad += __shfl_xor(bad, o, 64);
+        }
+        if (lane == 0) {
+            const int sl = (int)(((int64_t)blockIdx.x * WAVES + wv) % kSlots);
+            atomicMax((unsigned long long*)(a.ps.dmax + sl), (unsigned long long)__double_as_longlong(dmax + 0.0));
+            atomicMax((unsigned long long*)(a.ps.tmax + sl), (unsigned long long)__double_as_longlong(tmax + 0.0));
+            if (bad != 0.0) atomicAdd(a.ps.bad + sl, bad);
         }
     }
 }
 
 template <typename R>
 int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* G, const R* Lam, const R* rC,
-                R* out, const double* b, int count, double tau) {
+                R* out, Stages st, int count, double tau, const double* Tit, PassSlots ps) {
     TBArgs<R> a{};
     int K = count < KMAX ? count : KMAX;
     a.v = v;
@@ -166,6 +204,9 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
     a.Lam = Lam;
     a.rC = rC;
     a.out = out;
+    a.lam = st.lam;
+    a.Tit = Tit;
+    a.ps = ps;
     a.nx = g.nx;
     a.ny = g.ny;
     a.perx = g.per[0];
@@ -173,6 +214,7 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
     a.wx = (R)g.w[0];
     a.wy = (R)g.w[1];
     a.tau = (R)tau;
+    a.taud = tau;
     a.K = K;
     a.face = face;
     a.ox = 64 - 2 * K;
@@ -180,9 +222,8 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
     a.tiles_x = (g.nx + a.ox - 1) / a.ox;
     int tiles_y = (g.ny + a.oy - 1) / a.oy;
     for (int k = 0; k < K; ++k) {
-        double tb = tau * b[k];
-        a.cm[k] = (R)(1.0 / (1.0 + tb));
-        a.tb[k] = (R)tb;
+        if (st.lam) a.chat[k] = st.chat[k];
+        else a.tb[k] = st.tb[k];
     }
     hipLaunchKernelGGL(k_tb2d<R>, dim3((unsigned)(a.tiles_x * tiles_y)), dim3(64 * WAVES), 0, s, a);
     return K;
@@ -190,6 +231,14 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
 
 bool use_tb2d(const DevGrid& g, int count) {
     return g.nz == 1 && g.ny >= EXT_Y / 2 && count >= 2;
+}
+
+StageParam one_stage(const Stages& st) {
+    StageParam sp;
+    sp.lam = st.lam;
+    sp.tb = st.lam ? 0.0 : st.tb[0];
+    sp.chat = st.lam ? st.chat[0] : 0.0;
+    return sp;
 }
 
 }  // namespace
@@ -200,22 +249,24 @@ int sweeps_per_launch(const DevGrid& g, int count) {
 }
 
 int launch_sweeps64(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
-                    const double* Lam, const double* rC, double* out, const double* b, int count, double tau) {
-    if (use_tb2d(g, count)) return launch_tb2d<double>(s, g, face, v, rhs, Lam, rC, out, b, count, tau);
-    double tb = tau * b[0];
-    if (b[0] == 0.0 && count == 1) {
-        launch_final64(s, g, face, v, rhs, Lam, rC, out, tau);
+                    const double* Lam, const double* rC, double* out, Stages st, int count, bool last, double tau,
+                    const double* Tit, PassSlots ps) {
+    if (use_tb2d(g, count))
+        return launch_tb2d<double>(s, g, face, v, rhs, Lam, rC, out, st, count, tau, last ? Tit : nullptr, ps);
+    if (last) {
+        // the final stage, b = 0, in flux form
+        launch_final64(s, g, face, v, rhs, Lam, rC, out, tau, Tit, ps);
     } else {
-        launch_stage64(s, g, face, v, rhs, Lam, rC, out, 1.0 / (1.0 + tb), tb, tau);
+        launch_stage64(s, g, face, v, rhs, Lam, rC, out, one_stage(st), tau);
     }
     return 1;
 }
 
 int launch_sweeps32(hipStream_t s, const DevGrid& g, int face, const float* w, const float* qn,
-                    const float* Lam32, const float* rC32, float* out, const double* b, int count, double tau) {
-    if (use_tb2d(g, count)) return launch_tb2d<float>(s, g, face, w, qn, Lam32, rC32, out, b, count, tau);
-    double tb = tau * b[0];
-    launch_stage32(s, g, face, w, qn, Lam32, rC32, out, (float)(1.0 / (1.0 + tb)), (float)tb, (float)tau);
+                    const float* Lam32, const float* rC32, float* out, Stages st, int count, double tau) {
+    if (use_tb2d(g, count))
+        return launch_tb2d<float>(s, g, face, w, qn, Lam32, rC32, out, st, count, tau, nullptr, PassSlots{});
+    launch_stage32(s, g, face, w, qn, Lam32, rC32, out, one_stage(st), tau);
     return 1;
 }
 

@@ -60,7 +60,8 @@ class ReportC(C.Structure):
                 ("residual", C.c_double * MAX_PASSES), ("visc_P", C.c_int32 * 3),
                 ("visc_lambda_G", C.c_double * 3), ("energy_before", C.c_double),
                 ("energy_after", C.c_double), ("sweeps", C.c_int64), ("sweep_launches", C.c_int64),
-                ("sweep_ms", C.c_double), ("bad_cells", C.c_int64)]
+                ("sweep_ms", C.c_double), ("bad_cells", C.c_int64), ("predicted", C.c_int32),
+                ("mispredicted", C.c_int32)]
 
 
 _lib = None
@@ -139,7 +140,8 @@ def _report(r: ReportC) -> dict:
                 residual=list(r.residual[:n]), visc_P=list(r.visc_P),
                 visc_lambda_G=list(r.visc_lambda_G), energy_before=r.energy_before,
                 energy_after=r.energy_after, sweeps=r.sweeps, sweep_launches=r.sweep_launches,
-                sweep_ms=r.sweep_ms, bad_cells=r.bad_cells)
+                sweep_ms=r.sweep_ms, bad_cells=r.bad_cells, predicted=bool(r.predicted),
+                mispredicted=bool(r.mispredicted))
 
 
 class Solver:

@@ -75,6 +75,9 @@ def test_levelset2d_fp64_full_size():
     _compare(fo, fg, FIELDS_T, 1e-12)
     for r in rg:
         assert abs(r["energy_after"] / r["energy_before"] - 1) < 1e-13
+    # after the first step the schedule is predicted and confirmed without a
+    # readback per pass
+    assert not rg[0]["predicted"] and sum(r["predicted"] for r in rg[1:]) >= 5
 
 
 def test_bubbles3d_fp64_with_viscous():
@@ -99,6 +102,33 @@ def test_interface3d_fp64_adiabatic_x():
     fo, ro = run_oracle(orc, wl, tau, 2)
     fg, rg, _ = run_gpu(wl, tau, 2, frozen=_frozen(ro))
     _compare(fo, fg, FIELDS_T, 1e-12)
+
+
+def test_mispredicted_schedule_rolls_back():
+    """Change k0 between steps so that the predicted P is wrong: the step is
+    rolled back, rerun with one readback per pass, and still matches the
+    oracle run with the same change."""
+    from oracle import oracle as orc
+    wl = W.levelset2d(96)
+    tau, _ = oracle_dt(orc, wl)
+    g = orc.make_grid(wl["n"], wl["h"], wl["bc"])
+    fo = {k: v.copy() for k, v in wl["fields"].items()}
+    s = make_solver(wl)
+    from paper_2106_00282_amd.tlim import StepOpts
+    ph = [dict(p) for p in wl["phases"]]
+    reps = []
+    for step, scale in enumerate((1.0, 1.0, 4.0, 4.0)):
+        for k in range(2):
+            ph[k]["k0"] = wl["phases"][k]["k0"] * scale
+            s.set_phase(k, ph[k])
+        orc.step(g, ph, orc.StepOpts(tau=tau, passes=3), fo)
+        st, rep = s.advance(StepOpts(dt=tau, passes=3))
+        assert st == 0
+        reps.append(rep)
+    assert reps[2]["mispredicted"] and not reps[2]["predicted"]
+    assert reps[3]["predicted"]
+    assert reps[2]["sweeps"] == sum(2 * p - 1 for p in reps[2]["P"])
+    assert rel_err(s.get_field("T1").cpu().numpy(), fo["T1"]) < 1e-12
 
 
 def test_paper_order_and_harmonic_faces():
