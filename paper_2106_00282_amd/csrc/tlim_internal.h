@@ -92,11 +92,13 @@ void launch_visc_coeffs(hipStream_t s, const DevGrid& g, const DevPhases& ph, co
                         float* rC32);
 
 // Heat coefficients plus the Gershgorin bound (max into the accumulator row
-// lam) in one stencil pass over (T, alpha2).
+// lam) in one stencil pass over (T, alpha2).  With q32 != NULL (FP32
+// contexts) also the correction-form source and start: q32 = -tau rC' D' g,
+// w0 = float(Tn - g).
 void launch_heat_coeffs_bound(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double tau, int face,
                               const double* T, const double* alpha2, const double* m1, const double* m2,
                               const double* Tn, const double* src1, const double* src2, double* Lam, double* rC,
-                              double* rhs, float* Lam32, float* rC32, double* lam);
+                              double* rhs, float* Lam32, float* rC32, float* q32, float* w0, double* lam);
 
 // Gershgorin bound max_i 2 rC_i sum_f w Lam_f -> max into the row lam.
 void launch_gershgorin(hipStream_t s, const DevGrid& g, int face, const double* Lam, const double* rC, double* lam);
@@ -149,11 +151,13 @@ void launch_be_residual(hipStream_t s, const DevGrid& g, int face, const double*
 void launch_adj_stage(hipStream_t s, const DevGrid& g, int face, const double* lam, const double* vprev,
                       const double* Lam, const double* rC, double* lam_out, double* dg, double* gLam,
                       double cm, double tb, double tau);
-// After a reversed pass: acc += dg + lam0; mu = gLam dLam/dT(Tit); the two dL/dk0
-// sums are added to the rows k0a, k0b; if first_pass: acc += mu.
+// After a reversed pass: acc += dg + lam0 (with rCpsi != NULL the two are in
+// psi = C^-1 lambda form and divided by rCpsi = 1/C first); mu = gLam
+// dLam/dT(Tit); the two dL/dk0 sums are added to the rows k0a, k0b; if
+// first_pass: acc += mu.
 void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* Tit,
                      const double* alpha2, const double* gLam, const double* dg, const double* lam0,
-                     double* acc, double* mu, int first_pass, double* k0a, double* k0b);
+                     double* acc, double* mu, int first_pass, const double* rCpsi, double* k0a, double* k0b);
 
 void launch_fill(hipStream_t s, double* p, double v, int64_t n);
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n);

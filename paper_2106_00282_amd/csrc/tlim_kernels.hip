@@ -162,11 +162,25 @@ struct PassAcc {
         tmax = fmax(tmax, fabs(tn));
         if (!(tn > 0.0) || isinf(tn)) bad += 1.0;
     }
-    // wave-level fold, then lane 0 of every wave adds to a slot (no barrier)
+    // fold the three values over the block with one barrier, then one
+    // atomic per value from the block's first thread
     __device__ void store(const PassSlots& ps) {
+        __shared__ double red[3][16];
         double r0 = wave_max(dmax), r1 = wave_max(tmax), r3 = wave_sum(bad);
-        if ((flat_tid() & 63) == 0) {
-            const int sl = wave_slot();
+        const int t = flat_tid(), nw = block_threads() >> 6;
+        if ((t & 63) == 0) {
+            red[0][t >> 6] = r0;
+            red[1][t >> 6] = r1;
+            red[2][t >> 6] = r3;
+        }
+        __syncthreads();
+        if (t == 0) {
+            for (int w = 1; w < nw; ++w) {
+                r0 = fmax(r0, red[0][w]);
+                r1 = fmax(r1, red[1][w]);
+                r3 += red[2][w];
+            }
+            const int sl = block_slot();
             atomic_max_nonneg(ps.dmax + sl, r0);
             atomic_max_nonneg(ps.tmax + sl, r1);
             if (r3 != 0.0) atomicAdd(ps.bad + sl, r3);
@@ -283,46 +297,128 @@ __device__ __forceinline__ double inv_heat_capacity(const DevPhases& ph, double 
     return 1.0 / C;
 }
 
-// Coefficients of a Picard pass and the partial Gershgorin maxima in one
-// pass over (T, alpha2): the neighbours' conductivities are recomputed from
-// their (T, alpha2) rather than read back from a first pass.
-__global__ void __launch_bounds__(256) k_heat_coeffs_bound(
-    DevGrid g, DevPhases ph, double eps, double tau, int face, const double* __restrict__ T,
-    const double* __restrict__ alpha2, const double* __restrict__ m1, const double* __restrict__ m2,
-    const double* __restrict__ Tn, const double* __restrict__ src1, const double* __restrict__ src2,
-    double* __restrict__ Lam, double* __restrict__ rC, double* __restrict__ rhs, float* __restrict__ Lam32,
-    float* __restrict__ rC32, double* __restrict__ lam) {
-    __shared__ double sh[16];
-    int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
+// Coefficients of a Picard pass and the Gershgorin bound in one pass over
+// (T, alpha2).  Every cell of the block's 64x4 tile, and of its one-cell
+// halo, evaluates its conductivity (and g) once into LDS; the stencil reads
+// the neighbours from there.  Tile and halo positions hold the values of the
+// folded (periodic-wrapped, adiabatic-clamped) coordinates, so lookups by
+// position are right on periodic axes and unused across walls.
+// In FP32 contexts (q32 != NULL) it also writes the correction source
+// q = -tau rC' D' g (doubles from the float-rounded Lambda' and rC') and
+// w0 = float(Tn - g) of the correction form.
+struct CoefIn {
+    const double *T, *alpha2, *m1, *m2, *Tn, *src1, *src2;
+};
+
+// Coordinate of a tile or halo position: one periodic wrap (exact for every
+// position a stencil of the tile reads, which is at most one cell outside
+// the grid), then a clamp that keeps the unused positions of partial tiles
+// in bounds.
+__device__ __forceinline__ int fold_coord(int c, int n, int per) {
+    if (per) c = c < 0 ? c + n : (c >= n ? c - n : c);
+    return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
+
+// conductivity, 1/C and g = Tn + tau f/C of cell a
+__device__ __forceinline__ void cell_coef(const DevPhases& ph, double eps, double tau, const CoefIn& in, int64_t a,
+                                          double& L, double& r, double& gv) {
+    double t = in.T[a], a2 = in.alpha2[a];
+    L = cell_conductivity(ph, t, a2);
+    r = inv_heat_capacity(ph, eps, t, a2, in.m1[a], in.m2[a]);
+    double f = 0.0;
+    if (in.src1) f += (1.0 - a2) * in.src1[a];
+    if (in.src2) f += a2 * in.src2[a];
+    gv = in.Tn[a] + tau * r * f;
+}
+
+__global__ void __launch_bounds__(256) k_heat_coeffs_bound(DevGrid g, DevPhases ph, double eps, double tau, int face,
+                                                           CoefIn in, double* __restrict__ Lam,
+                                                           double* __restrict__ rC, double* __restrict__ rhs,
+                                                           float* __restrict__ Lam32, float* __restrict__ rC32,
+                                                           float* __restrict__ q32, float* __restrict__ w0,
+                                                           double* __restrict__ lam) {
+    // in-plane tile with halo: rows j0-1 .. j0+TY, columns i0-1 .. i0+TX
+    __shared__ double sL[TY + 2][TX + 2], sG[TY + 2][TX + 2];
+    __shared__ double zL[2][TY][TX], zG[2][TY][TX];  // layers k-1 and k+1
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
+    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY, k = blockIdx.z;
+    const bool q = q32 != nullptr;
+    const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+    const int kf = k;
+    auto at = [&](int i, int j, int kk) {
+        return (int64_t)fold_coord(i, g.nx, g.per[0]) + sy * fold_coord(j, g.ny, g.per[1]) +
+               sz * fold_coord(kk, g.nz, g.per[2]);
+    };
+    // own cell (folded position)
+    double L, r, gv;
+    const int64_t a_self = at(i0 + tx, j0 + ty, kf);
+    cell_coef(ph, eps, tau, in, a_self, L, r, gv);
+    sL[ty + 1][tx + 1] = L;
+    sG[ty + 1][tx + 1] = gv;
+    // halo: x sides (2 x TY cells), y sides (2 x TX cells), z layers (2 x TX x TY)
+    if (tid < 2 * TY) {
+        int side = tid / TY, jj = tid % TY;
+        int ii = side ? i0 + TX : i0 - 1;
+        double hl, hr, hg;
+        cell_coef(ph, eps, tau, in, at(ii, j0 + jj, kf), hl, hr, hg);
+        sL[jj + 1][side ? TX + 1 : 0] = hl;
+        sG[jj + 1][side ? TX + 1 : 0] = hg;
+    }
+    if (tid < 2 * TX) {
+        int side = tid / TX, ii = tid % TX;
+        int jj = side ? j0 + TY : j0 - 1;
+        double hl, hr, hg;
+        cell_coef(ph, eps, tau, in, at(i0 + ii, jj, kf), hl, hr, hg);
+        sL[side ? TY + 1 : 0][ii + 1] = hl;
+        sG[side ? TY + 1 : 0][ii + 1] = hg;
+    }
+    if (g.nz > 1) {
+        for (int side = 0; side < 2; ++side) {
+            double hl, hr, hg;
+            cell_coef(ph, eps, tau, in, at(i0 + tx, j0 + ty, side ? k + 1 : k - 1), hl, hr, hg);
+            zL[side][ty][tx] = hl;
+            zG[side][ty][tx] = hg;
+        }
+    }
+    __syncthreads();
+
+    const int i = i0 + tx, j = j0 + ty;
     double bound = 0.0;
     if (i < g.nx && j < g.ny) {
-        int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
-        double t = T[a], a2 = alpha2[a];
-        double L = cell_conductivity(ph, t, a2);
-        double r = inv_heat_capacity(ph, eps, t, a2, m1[a], m2[a]);
-        double f = 0.0;
-        if (src1) f += (1.0 - a2) * src1[a];
-        if (src2) f += a2 * src2[a];
+        const int64_t a = a_self;
         Lam[a] = L;
         rC[a] = r;
-        rhs[a] = Tn[a] + tau * r * f;
+        rhs[a] = gv;
         if (Lam32) {
             Lam32[a] = (float)L;
             rC32[a] = (float)r;
         }
         Faces fc;
         faces_of(g, i, j, k, fc);
+        const double nbL[6] = {sL[ty + 1][tx], sL[ty + 1][tx + 2], sL[ty][tx + 1], sL[ty + 2][tx + 1],
+                               g.nz > 1 ? zL[0][ty][tx] : 0.0, g.nz > 1 ? zL[1][ty][tx] : 0.0};
         double d = 0.0;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            if (!fc.has[q]) continue;
-            int64_t b = a + fc.off[q];
-            d += g.w[q >> 1] * face_mean<double>(L, cell_conductivity(ph, T[b], alpha2[b]), face);
-        }
+        for (int qf = 0; qf < 6; ++qf)
+            if (fc.has[qf]) d += g.w[qf >> 1] * face_mean<double>(L, nbL[qf], face);
         bound = 2.0 * d * r;
+        if (q) {
+            const double nbG[6] = {sG[ty + 1][tx], sG[ty + 1][tx + 2], sG[ty][tx + 1], sG[ty + 2][tx + 1],
+                                   g.nz > 1 ? zG[0][ty][tx] : 0.0, g.nz > 1 ? zG[1][ty][tx] : 0.0};
+            const double Lf = (double)(float)L, rf = (double)(float)r;
+            double S = 0.0;
+#pragma unroll
+            for (int qf = 0; qf < 6; ++qf)
+                if (fc.has[qf]) S += g.w[qf >> 1] * face_mean<double>(Lf, (double)(float)nbL[qf], face) * (gv - nbG[qf]);
+            q32[a] = (float)(-tau * rf * S);
+            w0[a] = (float)(in.Tn[a] - gv);
+        }
     }
+    __shared__ double red[4];
     bound = wave_max(bound);
-    if ((flat_tid() & 63) == 0) atomic_max_nonneg(lam + wave_slot(), bound);
+    if ((tid & 63) == 0) red[tid >> 6] = bound;
+    __syncthreads();
+    if (tid == 0) atomic_max_nonneg(lam + block_slot(), fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
 }
 
 __global__ void __launch_bounds__(256) k_heat_coeffs(DevGrid g, DevPhases ph, double eps, double tau,
@@ -414,7 +510,6 @@ __global__ void __launch_bounds__(256) k_pass_update(DevGrid g, DevPhases ph, do
                                                      const double* alpha2it, const double* __restrict__ m1,
                                                      const double* __restrict__ m2, double* alpha2out,
                                                      PassSlots ps) {
-    __shared__ double sh[16];
     double B1 = ph.pinf[0] - ph.pinf[1];
     PassAcc acc;
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
@@ -483,7 +578,6 @@ __global__ void __launch_bounds__(256) k_final64(DevGrid g, int face, const doub
                                                  const double* __restrict__ rhs, const double* __restrict__ Lam,
                                                  const double* __restrict__ rC, double* __restrict__ out,
                                                  double tau, const double* __restrict__ Tit, PassSlots ps) {
-    __shared__ double sh[16];
     int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
     PassAcc acc;
     if (i < g.nx && j < g.ny) {
@@ -534,7 +628,6 @@ __global__ void __launch_bounds__(256) k_final32(DevGrid g, int face, const floa
                                                  const double* __restrict__ rhs, const float* __restrict__ Lam32,
                                                  const double* __restrict__ rC, double* __restrict__ out,
                                                  double tau, const double* __restrict__ Tit, PassSlots ps) {
-    __shared__ double sh[16];
     int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
     PassAcc acc;
     if (i < g.nx && j < g.ny) {
@@ -586,13 +679,14 @@ __global__ void __launch_bounds__(256) k_adj_cell(DevGrid g, DevPhases ph, const
                                                   const double* __restrict__ alpha2, const double* __restrict__ gLam,
                                                   const double* __restrict__ dg, const double* __restrict__ lam0,
                                                   double* __restrict__ acc, double* __restrict__ mu, int first_pass,
-                                                  double* k0a, double* k0b) {
+                                                  const double* __restrict__ rCpsi, double* k0a, double* k0b) {
     __shared__ double sh[16];
     double s0 = 0.0, s1 = 0.0;
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
          a += (int64_t)gridDim.x * blockDim.x) {
         double t = Tit[a], a2 = alpha2[a], a1 = 1.0 - a2, gl = gLam[a];
-        double acc_a = acc[a] + dg[a] + lam0[a];
+        // lambda form, or psi = C^-1 lambda form (rCpsi = 1/C): lambda = psi / rC
+        double acc_a = rCpsi ? acc[a] + (dg[a] + lam0[a]) / rCpsi[a] : acc[a] + dg[a] + lam0[a];
         double x0 = t * ph.invT0[0], x1 = t * ph.invT0[1];
         s0 += gl * a1 * powlaw(x0, ph.npow[0]);
         s1 += gl * a2 * powlaw(x1, ph.npow[1]);
@@ -671,9 +765,10 @@ void launch_heat_coeffs(hipStream_t s, const DevGrid& g, const DevPhases& ph, do
 void launch_heat_coeffs_bound(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double tau, int face,
                               const double* T, const double* alpha2, const double* m1, const double* m2,
                               const double* Tn, const double* src1, const double* src2, double* Lam, double* rC,
-                              double* rhs, float* Lam32, float* rC32, double* lam) {
-    hipLaunchKernelGGL(k_heat_coeffs_bound, tile_grid(g), dim3(TX, TY), 0, s, g, ph, eps, tau, face, T, alpha2, m1,
-                       m2, Tn, src1, src2, Lam, rC, rhs, Lam32, rC32, lam);
+                              double* rhs, float* Lam32, float* rC32, float* q32, float* w0, double* lam) {
+    CoefIn in{T, alpha2, m1, m2, Tn, src1, src2};
+    hipLaunchKernelGGL(k_heat_coeffs_bound, tile_grid(g), dim3(TX, TY), 0, s, g, ph, eps, tau, face, in, Lam, rC, rhs,
+                       Lam32, rC32, q32, w0, lam);
 }
 
 void launch_visc_coeffs(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* alpha2,
@@ -739,9 +834,9 @@ void launch_adj_stage(hipStream_t s, const DevGrid& g, int face, const double* l
 
 void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* Tit, const double* alpha2,
                      const double* gLam, const double* dg, const double* lam0, double* acc, double* mu,
-                     int first_pass, double* k0a, double* k0b) {
+                     int first_pass, const double* rCpsi, double* k0a, double* k0b) {
     hipLaunchKernelGGL(k_adj_cell, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, Tit, alpha2, gLam, dg,
-                       lam0, acc, mu, first_pass, k0a, k0b);
+                       lam0, acc, mu, first_pass, rCpsi, k0a, k0b);
 }
 
 void launch_fill(hipStream_t s, double* p, double v, int64_t n) {

@@ -312,26 +312,30 @@ PassSchedule device_schedule(int P, int order, const double* lam_dev) {
 // coefficients in c->Lam/c->rC (and their float copies in FP32 contexts).
 // With Tit != NULL the kernel that writes `out` also accumulates the pass
 // reductions into ps.
+// In FP32 contexts q and w0 come from the heat coefficient kernel
+// (have_q = true) or are built here.
 void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const PassSchedule& ps, const double* v0,
                   const double* rhs, double* out, const double* Tit, tlim::PassSlots slots, Timer& tm,
-                  SweepCount& sc) {
+                  SweepCount& sc, bool have_q = false) {
     const int nst = ps.nst;
     hipStream_t s = c->stream;
     tm.start();
     if (c->precision == TLIM_FP32) {
-        tlim::launch_q32(s, g, face, rhs, v0, c->Lam32, c->rC32, tau, c->q32, c->wb[0]);
+        if (!have_q) tlim::launch_q32(s, g, face, rhs, v0, c->Lam32, c->rC32, tau, c->q32, c->wb[0]);
+        // 2P-2 float stages on the correction, the final one in double; the
+        // launch that reaches it writes `out`
         const float* cur = c->wb[0];
         int m = 0;
-        while (m < nst - 1) {
-            int k = tlim::sweeps_per_launch(g, nst - 1 - m);
+        while (m < nst) {
+            int k = tlim::sweeps_per_launch(g, nst - m);
+            bool last = m + k == nst;
             float* nxt = cur == c->wb[0] ? c->wb[1] : c->wb[0];
-            int done = tlim::launch_sweeps32(s, g, face, cur, c->q32, c->Lam32, c->rC32, nxt, ps.at(m), k, tau);
+            int done = tlim::launch_sweeps32(s, g, face, cur, c->q32, c->Lam32, c->rC32, nxt, ps.at(m), k, last, tau,
+                                             rhs, c->rC, out, Tit, slots);
             cur = nxt;
             m += done;
             sc.launches++;
         }
-        tlim::launch_final32(s, g, face, cur, rhs, c->Lam32, c->rC, out, tau, Tit, slots);
-        sc.launches++;
     } else {
         // all 2P-1 stages, the last (b = 0) in flux form; the launch that
         // reaches it writes `out`
@@ -405,7 +409,7 @@ void heat_coeffs(tlim_ctx* c, const DevGrid& g, const DevPhases& ph, const tlim_
                                    c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], c->Tn,
                                    c->fset[TLIM_SRC1] ? c->field[TLIM_SRC1] : nullptr,
                                    c->fset[TLIM_SRC2] ? c->field[TLIM_SRC2] : nullptr, c->Lam, c->rC, c->rhs,
-                                   c->Lam32, c->rC32, lam);
+                                   c->Lam32, c->rC32, c->q32, c->wb[0], lam);
 }
 
 // Chebyshev cycles to the backward-Euler solution of one pass (cycle mode).
@@ -518,7 +522,7 @@ tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_st
             if (!(res < o->cycle_tol)) out.cycle_fail = true;  // keep the last iterate
         } else {
             run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->rhs, c->Tnew,
-                         need_update ? nullptr : c->field[TLIM_T1], pass_slots(c, it), tm, sc);
+                         need_update ? nullptr : c->field[TLIM_T1], pass_slots(c, it), tm, sc, true);
         }
         if (need_update) {
             tlim::launch_pass_update(s, g, ph, o->alpha_eps, c->field[TLIM_T1], c->Tnew, c->Tn, c->a2n,
@@ -724,7 +728,7 @@ tlim_status tlim_spectral_bound(tlim_ctx* c, int32_t face_mean, double alpha_eps
     zero_rows(c, tlim::kTgtLambda, tlim::kTgtLambda + 1);
     tlim::launch_heat_coeffs_bound(c->stream, g, ph, alpha_eps, 1.0, face_mean, c->Tn, c->a2n, c->field[TLIM_M1],
                                    c->field[TLIM_M2], c->Tn, nullptr, nullptr, c->Lam, c->rC, c->rhs, nullptr,
-                                   nullptr, row(c, tlim::kTgtLambda));
+                                   nullptr, nullptr, nullptr, row(c, tlim::kTgtLambda));
     st = read_result(c, tlim::kTgtLambda, tlim::kTgtLambda + 1);
     if (st) return st;
     *lambda_out = result(c, tlim::kTgtLambda);
@@ -866,15 +870,35 @@ void adj_forward_step(tlim_ctx* c, const tlim_step_opts* o, const double* lamv, 
         std::vector<double> b = lim_params(P, lamv[it], o->order);
         int nst = (int)b.size();
         if (stages) {
+            // every iterate v^(m), m < nst, goes to slot m of the pass
             double* st0 = stages + (size_t)it * stride_pass;
             tlim::launch_copy(s, st0, Tn, N);
-            for (int m = 1; m < nst; ++m) {
-                tlim::StageParam sp{nullptr, o->dt * b[m - 1], 0.0};
-                tlim::launch_stage64(s, g, o->face_mean, st0 + (size_t)(m - 1) * stride_field, c->rhs, c->Lam, c->rC,
-                                     st0 + (size_t)m * stride_field, sp, o->dt);
+            std::vector<double> tbv(nst);
+            for (int m = 0; m < nst; ++m) tbv[m] = o->dt * b[m];
+            int m = 0;
+            while (m < nst) {
+                int k = tlim::sweeps_per_launch(g, nst - m);
+                double* out = m + k == nst ? Tout : st0 + (size_t)(m + k) * stride_field;
+                tlim::Stages stg{nullptr, tbv.data() + m, nullptr};
+                int done = -1;
+                if (k > 1)
+                    done = tlim::launch_sweeps64_keep(s, g, o->face_mean, st0 + (size_t)m * stride_field, c->rhs,
+                                                      c->Lam, c->rC, out, stg, k, o->dt,
+                                                      st0 + (size_t)m * stride_field, (int64_t)stride_field);
+                if (done < 0) {
+                    double* one = m + 1 == nst ? Tout : st0 + (size_t)(m + 1) * stride_field;
+                    if (m + 1 == nst) {
+                        tlim::launch_final64(s, g, o->face_mean, st0 + (size_t)m * stride_field, c->rhs, c->Lam,
+                                             c->rC, one, o->dt, nullptr, tlim::PassSlots{});
+                    } else {
+                        tlim::StageParam sp{nullptr, tbv[m], 0.0};
+                        tlim::launch_stage64(s, g, o->face_mean, st0 + (size_t)m * stride_field, c->rhs, c->Lam,
+                                             c->rC, one, sp, o->dt);
+                    }
+                    done = 1;
+                }
+                m += done;
             }
-            tlim::launch_final64(s, g, o->face_mean, st0 + (size_t)(nst - 1) * stride_field, c->rhs, c->Lam, c->rC,
-                                 Tout, o->dt, nullptr, tlim::PassSlots{});
         } else {
             const double* cur = Tn;
             int pp = 0;
@@ -970,23 +994,48 @@ tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, i
             int P = lim_P(o->dt, lam[(size_t)n * np + it]);
             std::vector<double> b = lim_params(P, lam[(size_t)n * np + it], o->order);
             int nst = (int)b.size();
-            tlim::launch_fill(s, dg, 0.0, N);
-            tlim::launch_fill(s, gLam, 0.0, N);
             const double* cur = mu;
             double* bufs[2] = {lamA, lamB};
             int pp = 0;
             const double* st0 = stages + (size_t)it * stride_pass;
-            for (int m = nst; m >= 1; --m) {
-                double tb = o->dt * b[m - 1];
-                tlim::launch_adj_stage(s, g, o->face_mean, cur, st0 + (size_t)(m - 1) * sf, c->Lam, c->rC, bufs[pp],
-                                       dg, gLam, 1.0 / (1.0 + tb), tb, o->dt);
-                cur = bufs[pp];
-                pp ^= 1;
+            // blocked reverse stages in psi = C^-1 lambda form where the grid allows
+            bool psi_form = false;
+            {
+                std::vector<double> cmv, tbv;
+                int m = nst;
+                while (m >= 1) {
+                    int k = std::min(m, tlim::sweeps_per_launch(g, m));
+                    cmv.assign(k, 0.0);
+                    tbv.assign(k, 0.0);
+                    for (int q = 0; q < k; ++q) {
+                        tbv[q] = o->dt * b[m - 1 - q];
+                        cmv[q] = 1.0 / (1.0 + tbv[q]);
+                    }
+                    int done = tlim::launch_adjoint_sweeps(s, g, o->face_mean, cur, m == nst ? 1 : 0, c->Lam, c->rC,
+                                                           st0, (int64_t)sf, m, bufs[pp], dg, gLam,
+                                                           m == nst ? 0 : 1, cmv.data(), tbv.data(), k, o->dt);
+                    if (done < 0) break;
+                    psi_form = true;
+                    cur = bufs[pp];
+                    pp ^= 1;
+                    m -= done;
+                }
             }
-            // cur = dL/dv^(0); mu <- dL/dT^(it) through Lambda(T^(it))
+            if (!psi_form) {
+                tlim::launch_fill(s, dg, 0.0, N);
+                tlim::launch_fill(s, gLam, 0.0, N);
+                for (int m = nst; m >= 1; --m) {
+                    double tb = o->dt * b[m - 1];
+                    tlim::launch_adj_stage(s, g, o->face_mean, cur, st0 + (size_t)(m - 1) * sf, c->Lam, c->rC,
+                                           bufs[pp], dg, gLam, 1.0 / (1.0 + tb), tb, o->dt);
+                    cur = bufs[pp];
+                    pp ^= 1;
+                }
+            }
+            // cur = dL/dv^(0) (or its psi); mu <- dL/dT^(it) through Lambda(T^(it))
             zero_rows(c, tlim::kTgtK0a, tlim::kTgtK0b + 1);
             tlim::launch_adj_cell(s, g, ph, Tit, c->field[TLIM_ALPHA2], gLam, dg, cur, acc, mu, it == 0 ? 1 : 0,
-                                  row(c, tlim::kTgtK0a), row(c, tlim::kTgtK0b));
+                                  psi_form ? c->rC : nullptr, row(c, tlim::kTgtK0a), row(c, tlim::kTgtK0b));
             st = read_result(c, tlim::kTgtK0a, tlim::kTgtK0b + 1);
             if (st) return st;
             k0g[0] += result(c, tlim::kTgtK0a);

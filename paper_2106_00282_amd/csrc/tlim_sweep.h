@@ -5,8 +5,10 @@
 // stage is launched.  In FP64 the final stage (b = 0, flux form) may be among
 // them: a launch with last = true ends the pass and, when Tit != NULL, also
 // accumulates the pass reductions (dmax, tmax, bad) into ps.  The FP32
-// correction form advances inner stages only (source qn = -tau A' g) and
-// finishes with launch_final32.
+// correction form advances the float correction w = v - g (source
+// qn = -tau A' g); its final stage is evaluated in double on g + w and the
+// launch that reaches it writes out64 (rhs = g and rC in double) instead of
+// out.
 #pragma once
 
 #include "tlim_internal.h"
@@ -22,7 +24,8 @@ struct Stages {
     const double* chat;
 };
 
-// Number of stages the next launch will advance when `count` remain.
+// Number of stages the next launch will advance when `count` remain (the
+// launches of a pass get equal shares of at most KMAX stages).
 int sweeps_per_launch(const DevGrid& g, int count);
 
 int launch_sweeps64(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
@@ -30,6 +33,32 @@ int launch_sweeps64(hipStream_t s, const DevGrid& g, int face, const double* v, 
                     const double* Tit, PassSlots ps);
 
 int launch_sweeps32(hipStream_t s, const DevGrid& g, int face, const float* w, const float* qn,
-                    const float* Lam32, const float* rC32, float* out, Stages st, int count, double tau);
+                    const float* Lam32, const float* rC32, float* out, Stages st, int count, bool last, double tau,
+                    const double* rhs, const double* rC, double* out64, const double* Tit, PassSlots ps);
+
+// Blocked FP64 stages that also keep their intermediate results: the result
+// of the launch's stage k (k = 1 .. K-1) goes to stages + k*sstride and the
+// last one to out.  Returns K, or -1 where blocking does not apply (then
+// nothing is launched).
+int launch_sweeps64_keep(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
+                         const double* Lam, const double* rC, double* out, Stages st, int count, double tau,
+                         double* stages, int64_t sstride);
+
+// Blocked reverse stages of the adjoint in the scaled form psi = C^-1 lambda
+// (psi^(m-1) = c_m (tau b_m - tau A) psi^(m), the forward stage operator
+// without source), for stages mt, mt-1, ..., mt-count+1 of one LIM pass:
+//   psi_in   psi^(mt) (first = 1: lambda^(mt), scaled by 1/C on load)
+//   stages   forward iterates, v^(j) at stages + j*sstride
+//   psi_out  psi^(mt-K)
+//   dgpsi   += sum_m c_m psi^(m)           (dL/dg = C dgpsi)
+//   gLam    += sum_m sum_f c_m tau w/2 (v_b - v_a)^(m-1) (psi_a - psi_b)^(m)
+//             (dL/dLambda_cell through arithmetic face means)
+// accumulate = 0 starts the sums at zero.  cm, tb: c_m and tau*b_m of the K
+// stages in the order they are reversed.  Returns K, or -1 where blocking
+// does not apply (3D grid, harmonic faces): nothing is launched.
+int launch_adjoint_sweeps(hipStream_t s, const DevGrid& g, int face, const double* psi_in, int first,
+                          const double* Lam, const double* rC, const double* stages, int64_t sstride, int mt,
+                          double* psi_out, double* dgpsi, double* gLam, int accumulate, const double* cm,
+                          const double* tb, int count, double tau);
 
 }  // namespace tlim

@@ -21,16 +21,21 @@
 // output cell, for K stages.
 #include <hip/hip_runtime.h>
 
+#include "tlim_device.h"
 #include "tlim_sweep.h"
 
 namespace tlim {
 
 namespace {
 
-constexpr int KMAX = 8;
-constexpr int WAVES = 8;
-constexpr int ROWS = 8;
-constexpr int EXT_Y = WAVES * ROWS;
+using tb::KMAX;
+using tb::WAVES;
+using tb::ROWS;
+using tb::EXT_Y;
+using tb::from_left;
+using tb::from_right;
+using tb::fmean;
+using tb::fold;
 
 template <typename R>
 struct TBArgs {
@@ -42,46 +47,20 @@ struct TBArgs {
     const double* lam;       // accumulator row of lambda_max (NULL: use tb)
     const double* Tit;       // previous iterate: accumulate the pass reductions (last launch, FP64)
     PassSlots ps;
+    R* stages;               // non-NULL: the result of stage s < K-1 also goes to stages + (s+1)*sstride
+    int64_t sstride;
+    // FP32 correction form: with g64 != NULL the launch's last stage is the
+    // final one, evaluated in double from g64 + w with rC64, into out64
+    const double* g64;
+    const double* rC64;
+    double* out64;
+    double g64w[2];          // face weights in double for that stage
     int nx, ny, perx, pery;
     R wx, wy, tau;
     int K, face, tiles_x, ox, oy;
     double taud;
     double tb[KMAX], chat[KMAX];
 };
-
-// Lane i receives lane i-1 (wave_shr:1) or lane i+1 (wave_shl:1); with
-// bound_ctrl the lanes at the ends receive 0 (they are halo lanes).
-__device__ __forceinline__ int dpp_from_left(int x) { return __builtin_amdgcn_mov_dpp(x, 0x138, 0xF, 0xF, true); }
-__device__ __forceinline__ int dpp_from_right(int x) { return __builtin_amdgcn_mov_dpp(x, 0x130, 0xF, 0xF, true); }
-
-__device__ __forceinline__ double from_left(double x) {
-    return __hiloint2double(dpp_from_left(__double2hiint(x)), dpp_from_left(__double2loint(x)));
-}
-__device__ __forceinline__ double from_right(double x) {
-    return __hiloint2double(dpp_from_right(__double2hiint(x)), dpp_from_right(__double2loint(x)));
-}
-__device__ __forceinline__ float from_left(float x) { return __int_as_float(dpp_from_left(__float_as_int(x))); }
-__device__ __forceinline__ float from_right(float x) { return __int_as_float(dpp_from_right(__float_as_int(x))); }
-
-template <typename R>
-__device__ __forceinline__ R fmean(R a, R b, int face) {
-    if (face == 1) {
-        R s = a + b;
-        return s > R(0) ? R(2) * (a * b) / s : R(0);
-    }
-    return R(0.5) * (a + b);
-}
-
-// Index of an unwrapped coordinate: wrap on a periodic axis, clamp on an
-// adiabatic one (clamped copies only feed halo cells, whose wall faces
-// carry kappa = 0).
-__device__ __forceinline__ int fold(int c, int n, int per) {
-    if (per) {
-        int m = c % n;
-        return m < 0 ? m + n : m;
-    }
-    return c < 0 ? 0 : (c >= n ? n - 1 : c);
-}
 
 template <typename R>
 __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
@@ -97,7 +76,16 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
     const bool fL = a.perx ? a.nx > 1 : (inx && xg > 0);
     const bool fR = a.perx ? a.nx > 1 : (inx && xg < a.nx - 1);
 
+    constexpr bool kFloat = sizeof(R) == 4;
+    const bool fin = kFloat && a.g64 != nullptr;
+    // In double the source G lives in LDS (read once per cell and stage):
+    // the four kappa and v already take 80 of the 128 VGPRs that four
+    // workgroups per CU leave, and G in registers spills.
+    constexpr bool kGinLds = !kFloat;
+    __shared__ R sG[kGinLds ? EXT_Y : 1][64];
     R v[ROWS], G[ROWS], kL[ROWS], kR[ROWS], kD[ROWS], kU[ROWS];
+    R Lk[ROWS];     // cell conductivities, kept for a fused FP64 final stage
+    R Ldk = 0, Luk = 0;
     {
         R L[ROWS], t[ROWS];
 #pragma unroll
@@ -105,7 +93,8 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
             const int yi = fold(yg0 + r, a.ny, a.pery);
             const int64_t idx = (int64_t)yi * a.nx + xi;
             v[r] = a.v[idx];
-            G[r] = a.G[idx];
+            if constexpr (kGinLds) sG[wv * ROWS + r][lane] = a.G[idx];
+            else G[r] = a.G[idx];
             L[r] = a.Lam[idx];
             t[r] = a.tau * a.rC[idx];
         }
@@ -128,6 +117,12 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
             kD[r] = fD ? t[r] * a.wy * fmean<R>(L[r], Ld, a.face) : R(0);
             kU[r] = fU ? t[r] * a.wy * fmean<R>(L[r], Lu, a.face) : R(0);
         }
+        if constexpr (kFloat) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) Lk[r] = L[r];
+            Ldk = Ldn;
+            Luk = Lup;
+        }
     }
     // lambda_G of the pass from its accumulator row (every wave folds it)
     double lamv = 0.0;
@@ -139,7 +134,8 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
     }
     // Stage s exchanges the seam rows through LDS buffer (s+1)&1; buffer 0
     // held the Lambda seams, whose reads all precede the first barrier below.
-    for (int s = 0; s < K; ++s) {
+    const int Kin = fin ? K - 1 : K;
+    for (int s = 0; s < Kin; ++s) {
         const int buf = (s + 1) & 1;
         sh_lo[buf][wv][lane] = v[0];
         sh_hi[buf][wv][lane] = v[ROWS - 1];
@@ -155,8 +151,66 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
             const R up = r < ROWS - 1 ? v[r + 1] : vup;
             const R lf = from_left(c), rt = from_right(c);
             const R S = kL[r] * (c - lf) + kR[r] * (c - rt) + kD[r] * (c - prev) + kU[r] * (c - up);
-            v[r] = cm * (G[r] + tb * c - S);
+            R Gr;
+            if constexpr (kGinLds) Gr = sG[wv * ROWS + r][lane];
+            else Gr = G[r];
+            v[r] = cm * (Gr + tb * c - S);
             prev = c;
+        }
+        // the output cells are exact after every stage: keep the intermediate
+        // stages when asked (the adjoint's recomputation)
+        if (a.stages && s + 1 < K && lane >= K && lane < 64 - K && xg < a.nx) {
+            R* dst = a.stages + (int64_t)(s + 1) * a.sstride;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int row = wv * ROWS + r;
+                const int y = yg0 + r;
+                if (row >= K && row < EXT_Y - K && y < a.ny) dst[(int64_t)y * a.nx + xg] = v[r];
+            }
+        }
+    }
+    // Final stage (b = 0) of the FP32 correction form, in double on v = g + w:
+    // T = g - tau rC64 sum_f w_f mean(Lambda'_a, Lambda'_b) (v_a - v_b), with
+    // Lambda' the float conductivities.  Sfin holds the flux sum, gfin g.
+    double Sfin[ROWS], gfin[ROWS];
+    if constexpr (kFloat) {
+        if (fin) {
+            __shared__ double dsh_lo[WAVES][64], dsh_hi[WAVES][64];
+            double vf[ROWS];
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int64_t idx = (int64_t)fold(yg0 + r, a.ny, a.pery) * a.nx + xi;
+                gfin[r] = a.g64[idx];
+                vf[r] = gfin[r] + (double)v[r];
+            }
+            dsh_lo[wv][lane] = vf[0];
+            dsh_hi[wv][lane] = vf[ROWS - 1];
+            __syncthreads();
+            const double vdn = wv > 0 ? dsh_hi[wv - 1][lane] : vf[0];
+            const double vup = wv < WAVES - 1 ? dsh_lo[wv + 1][lane] : vf[ROWS - 1];
+            const double wxd = a.g64w[0], wyd = a.g64w[1];
+            double prev = vdn;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int y = yg0 + r;
+                const bool iny = y >= 0 && y < a.ny;
+                const bool fD = a.pery ? a.ny > 1 : (iny && y > 0);
+                const bool fU = a.pery ? a.ny > 1 : (iny && y < a.ny - 1);
+                const double c = vf[r];
+                const double up = r < ROWS - 1 ? vf[r + 1] : vup;
+                const double La = (double)Lk[r];
+                const double Ll = (double)from_left(Lk[r]), Lr = (double)from_right(Lk[r]);
+                const double Ld = (double)(r > 0 ? Lk[r - 1] : Ldk);
+                const double Lu = (double)(r < ROWS - 1 ? Lk[r + 1] : Luk);
+                const double lf = from_left(c), rt = from_right(c);
+                double S = 0.0;
+                if (fL) S += wxd * fmean<double>(La, Ll, a.face) * (c - lf);
+                if (fR) S += wxd * fmean<double>(La, Lr, a.face) * (c - rt);
+                if (fD) S += wyd * fmean<double>(La, Ld, a.face) * (c - prev);
+                if (fU) S += wyd * fmean<double>(La, Lu, a.face) * (c - up);
+                prev = c;
+                Sfin[r] = S;
+            }
         }
     }
     double dmax = 0.0, tmax = 0.0, bad = 0.0;
@@ -167,9 +221,16 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
             const int y = yg0 + r;
             if (row >= K && row < EXT_Y - K && y < a.ny) {
                 const int64_t o = (int64_t)y * a.nx + xg;
-                a.out[o] = v[r];
+                double tnew;
+                if (fin) {
+                    tnew = gfin[r] - a.taud * a.rC64[o] * Sfin[r];
+                    a.out64[o] = tnew;
+                } else {
+                    a.out[o] = v[r];
+                    tnew = (double)v[r];
+                }
                 if (a.Tit) {
-                    const double tn = (double)v[r];
+                    const double tn = tnew;
                     dmax = fmax(dmax, fabs(tn - a.Tit[o]));
                     tmax = fmax(tmax, fabs(tn));
                     if (!(tn > 0.0) || isinf(tn)) bad += 1.0;
@@ -196,8 +257,17 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
 
 template <typename R>
 int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* G, const R* Lam, const R* rC,
-                R* out, Stages st, int count, double tau, const double* Tit, PassSlots ps) {
+                R* out, Stages st, int count, double tau, const double* Tit, PassSlots ps, R* stages = nullptr,
+                int64_t sstride = 0, const double* g64 = nullptr, const double* rC64 = nullptr,
+                double* out64 = nullptr) {
     TBArgs<R> a{};
+    a.g64 = g64;
+    a.rC64 = rC64;
+    a.out64 = out64;
+    a.g64w[0] = g.w[0];
+    a.g64w[1] = g.w[1];
+    a.stages = stages;
+    a.sstride = sstride;
     int K = count < KMAX ? count : KMAX;
     a.v = v;
     a.G = G;
@@ -243,9 +313,21 @@ StageParam one_stage(const Stages& st) {
 
 }  // namespace
 
+int launch_sweeps64_keep(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
+                         const double* Lam, const double* rC, double* out, Stages st, int count, double tau,
+                         double* stages, int64_t sstride) {
+    if (use_tb2d(g, count))
+        return launch_tb2d<double>(s, g, face, v, rhs, Lam, rC, out, st, count, tau, nullptr, PassSlots{}, stages,
+                                   sstride);
+    return -1;
+}
+
 int sweeps_per_launch(const DevGrid& g, int count) {
-    if (use_tb2d(g, count)) return count < KMAX ? count : KMAX;
-    return 1;
+    if (!use_tb2d(g, count)) return 1;
+    // as few launches as KMAX allows, with equal stage counts: a launch of K
+    // stages recomputes a ring of width K, so even launches waste least
+    const int launches = (count + KMAX - 1) / KMAX;
+    return (count + launches - 1) / launches;
 }
 
 int launch_sweeps64(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
@@ -263,10 +345,19 @@ int launch_sweeps64(hipStream_t s, const DevGrid& g, int face, const double* v, 
 }
 
 int launch_sweeps32(hipStream_t s, const DevGrid& g, int face, const float* w, const float* qn,
-                    const float* Lam32, const float* rC32, float* out, Stages st, int count, double tau) {
-    if (use_tb2d(g, count))
+                    const float* Lam32, const float* rC32, float* out, Stages st, int count, bool last, double tau,
+                    const double* rhs, const double* rC, double* out64, const double* Tit, PassSlots ps) {
+    if (use_tb2d(g, count)) {
+        if (last)
+            return launch_tb2d<float>(s, g, face, w, qn, Lam32, rC32, nullptr, st, count, tau, Tit, ps, nullptr, 0,
+                                      rhs, rC, out64);
         return launch_tb2d<float>(s, g, face, w, qn, Lam32, rC32, out, st, count, tau, nullptr, PassSlots{});
-    launch_stage32(s, g, face, w, qn, Lam32, rC32, out, one_stage(st), tau);
+    }
+    if (last) {
+        launch_final32(s, g, face, w, rhs, Lam32, rC, out64, tau, Tit, ps);
+    } else {
+        launch_stage32(s, g, face, w, qn, Lam32, rC32, out, one_stage(st), tau);
+    }
     return 1;
 }
 
