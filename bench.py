@@ -20,6 +20,7 @@ Reported (one JSON line):
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -32,6 +33,38 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per cell-update of one sweep launch: read v, rhs, Lambda,
 # 1/C and write v, one word each (stencil neighbours come from cache).
 BYTES_PER_UPDATE = {"fp64": 5 * 8, "fp32": 5 * 4}
+
+
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_tb2d_f64_levelset2d_1024.md")
+SWEEP_SOURCES = ("tlim_sweep.hip", "tlim_device.h", "tlim_sweep.h", "tlim_internal.h")
+
+
+def sweep_source_digest():
+    """Digest of the sources that define the blocked sweep kernel."""
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2106_00282_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic():
+    """HBM bytes per launch of the FP64 blocked sweep from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (each scaled by what the same
+    counter reads for a plain copy of known size).  None when the summary is
+    missing or the kernel's sources changed since the counters were taken."""
+    try:
+        with open(PMC_SUMMARY) as fh:
+            kv = dict(line.split(": ", 1) for line in fh.read().splitlines() if ": " in line and " " not in
+                      line.split(": ", 1)[0])
+    except OSError:
+        return None
+    if kv.get("source_digest", "").strip() != sweep_source_digest():
+        return None
+    try:
+        return float(kv["sweep_fp64_traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -173,6 +206,8 @@ def main():
     avg_launch_ms = r64["sweep_ms"] / max(r64["launches"], 1)
     bytes_per_launch = r64["N"] * BYTES_PER_UPDATE["fp64"] * (r64["sweeps"] / max(r64["launches"], 1))
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if avg_launch_ms > 0 else None
+    traffic = pmc_traffic() if args.n == 1024 else None
+    dram_gbs = traffic / (avg_launch_ms * 1e-3) / 1e9 if traffic and avg_launch_ms > 0 else None
     out = {
         "metric": "Gcell-updates/s per Chebyshev sweep (FP64 vs FP32), HBM GB/s, adjoint/fwd",
         "value": round(r64["gupd"], 4),
@@ -194,9 +229,12 @@ def main():
         if r64["sweep_ms"] > 0 else None,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
-                     "kernel": "LIM sweep (FP64)", "avg_launch_us": round(avg_launch_ms * 1e3, 3),
-                     "bytes_per_launch": int(bytes_per_launch)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                     "traffic": int(traffic) if traffic else None,
+                     "kernel": "LIM sweep (FP64, blocked)", "avg_launch_us": round(avg_launch_ms * 1e3, 3),
+                     "bytes_per_launch": int(bytes_per_launch),
+                     "dram_GBs": round(dram_gbs, 1) if dram_gbs else None,
+                     "dram_frac": round(dram_gbs / HBM_PEAK_GBS, 4) if dram_gbs else None},
     }
     if r32:
         l32 = r32["sweep_ms"] / max(r32["launches"], 1)

@@ -36,6 +36,7 @@ struct AdjArgs {
     const double* Lam;
     const double* rC;
     const double* stages;
+    const double* v0;
     double* psi_out;
     double* dgpsi;
     double* gLam;
@@ -102,7 +103,8 @@ __global__ void __launch_bounds__(64 * WAVES, 2) k_tb2d_adj(AdjArgs a) {
     for (int s = 0; s < K; ++s) {
         const int buf = (s + 1) & 1;
         // forward iterate v^(m-1) of stage m = mt - s
-        const double* vsrc = a.stages + (int64_t)(a.mt - 1 - s) * a.sstride;
+        const int j = a.mt - 1 - s;
+        const double* vsrc = j == 0 ? a.v0 : a.stages + (int64_t)j * a.sstride;
         double v[ROWS];
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) v[r] = vsrc[idx[r]];
@@ -153,7 +155,8 @@ __global__ void __launch_bounds__(64 * WAVES, 2) k_tb2d_adj(AdjArgs a) {
 }  // namespace
 
 int launch_adjoint_sweeps(hipStream_t s, const DevGrid& g, int face, const double* psi_in, int first,
-                          const double* Lam, const double* rC, const double* stages, int64_t sstride, int mt,
+                          const double* Lam, const double* rC, const double* stages, const double* v0,
+                          int64_t sstride, int mt,
                           double* psi_out, double* dgpsi, double* gLam, int accumulate, const double* cm,
                           const double* tb, int count, double tau) {
     if (!(g.nz == 1 && g.ny >= EXT_Y / 2 && face == 0)) return -1;
@@ -163,6 +166,7 @@ int launch_adjoint_sweeps(hipStream_t s, const DevGrid& g, int face, const doubl
     a.Lam = Lam;
     a.rC = rC;
     a.stages = stages;
+    a.v0 = v0;
     a.psi_out = psi_out;
     a.dgpsi = dgpsi;
     a.gLam = gLam;

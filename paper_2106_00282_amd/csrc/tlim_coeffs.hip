@@ -1,0 +1,203 @@
+// Coefficients of a Picard pass and the Gershgorin bound on 2D grids whose
+// heat step has no source term (Sec. 3.4.2, eq. qk_dis; bound of eq. LIM).
+//
+// Per cell: Lambda = sum_k alpha_k lambda_k(T^(it)) and, where it changes,
+// 1/C_eff; per cell the bound 2 rC sum_f w_f mean(Lambda_a, Lambda_b), folded
+// into a max.  Without sources g = T^n, so no right-hand side is written (the
+// stages read T^n), and with p_inf,1 = p_inf,2 the capacity depends on the
+// partial densities only, which the parabolic step does not change: 1/C is
+// then built by the first pass of a step and read by the others.
+//
+// The first pass of a step can also take the temperature relaxation
+// (Sec. 3.4.1) that precedes it: every strip then relaxes its cells (halo
+// rows included) from (alpha2, T1, T2, m1, m2) before building the
+// coefficients at the relaxed state, and writes T^n and the relaxed alpha2
+// of its own cells to separate arrays (alpha2 is not updated in place, as
+// neighbouring strips still read the unrelaxed values of their halo).
+//
+// One wave owns a strip of 64 columns (62 output columns plus one halo
+// column on each side) by kRows rows and marches down it, keeping the
+// conductivities of three consecutive rows in registers; the x-neighbours
+// come from the adjacent lanes (DPP).  Loads of T and alpha2 are coalesced
+// 512 B rows; halo overhead is (kRows+2)/kRows x 64/62.  No LDS, no barrier:
+// waves are independent.
+#include <hip/hip_runtime.h>
+
+#include "tlim_device.h"
+#include "tlim_internal.h"
+
+namespace tlim {
+
+namespace {
+
+using phys::cell_conductivity;
+using phys::inv_heat_capacity;
+using tb::fmean;
+using tb::fold;
+using tb::from_left;
+using tb::from_right;
+
+constexpr int kRows = 8;
+constexpr int kOut = 62;
+constexpr int kWaves = 4;
+
+struct Coef2DArgs {
+    DevPhases ph;
+    const double* T;      // T^(it); with relaxation: T1
+    const double* T2;     // with relaxation
+    double* Tn_out;       // with relaxation: the relaxed T
+    double* a2_out;       // with relaxation: the relaxed alpha2
+    const double* alpha2;
+    const double* m1;
+    const double* m2;
+    const double* g;      // T^n (read for the FP32 correction source only)
+    const double* rC_in;  // 1/C of the step when it is not rebuilt
+    double* Lam;          // nullable
+    double* rC;           // written when rebuilt
+    float* Lam32;         // FP32 contexts
+    float* rC32;
+    float* q32;
+    float* w0;
+    double* lam;          // accumulator row of the bound
+    int nx, ny, perx, pery;
+    double wx, wy, tau, eps;
+    int face, rebuild, tiles_x, strips;
+};
+
+template <bool kRelax>
+__global__ void __launch_bounds__(64 * kWaves) k_coeffs2d(Coef2DArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int strip = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (strip >= a.strips) return;  // wave-uniform
+    const int tx = strip % a.tiles_x, ty = strip / a.tiles_x;
+    const int xg = tx * kOut - 1 + lane;
+    const int xi = fold(xg, a.nx, a.perx);
+    const bool out_lane = lane >= 1 && lane <= kOut && xg < a.nx;
+    const bool fL = a.perx ? a.nx > 1 : xg > 0;
+    const bool fR = a.perx ? a.nx > 1 : xg < a.nx - 1;
+    const int y0 = ty * kRows;
+    const bool q = a.q32 != nullptr;
+
+    auto at = [&](int y) { return (int64_t)fold(y, a.ny, a.pery) * a.nx + xi; };
+    // rows y0-1 .. y0+kRows: T, alpha2 -> Lambda (and g in FP32 contexts)
+    double Lw[kRows + 2], tw[kRows + 2], aw[kRows + 2], gw[kRows + 2];
+#pragma unroll
+    for (int r = 0; r < kRows + 2; ++r) {
+        const int64_t idx = at(y0 - 1 + r);
+        if constexpr (kRelax) {
+            const double t1 = a.T[idx];
+            const double t2 = a.T2 == a.T ? t1 : a.T2[idx];
+            phys::relax_cell(a.ph, a.eps, a.alpha2[idx], t1, t2, a.m1[idx], a.m2[idx], tw[r], aw[r]);
+            gw[r] = tw[r];  // g = T^n, the relaxed T
+        } else {
+            tw[r] = a.T[idx];
+            aw[r] = a.alpha2[idx];
+            gw[r] = q ? a.g[idx] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kRows + 2; ++r) Lw[r] = cell_conductivity(a.ph, tw[r], aw[r]);
+
+    double bound = 0.0;
+#pragma unroll
+    for (int r = 1; r <= kRows; ++r) {
+        const int y = y0 + r - 1;
+        const double L = Lw[r], Lm = Lw[r - 1], Lp = Lw[r + 1];
+        const double Ll = from_left(L), Lr = from_right(L);
+        const float Lf = (float)L;
+        const float Llf = from_left(Lf), Lrf = from_right(Lf);
+        const double gl = from_left(gw[r]), gr = from_right(gw[r]);
+        if (out_lane && y < a.ny) {
+            const int64_t o = (int64_t)y * a.nx + xg;
+            const bool fD = a.pery ? a.ny > 1 : y > 0;
+            const bool fU = a.pery ? a.ny > 1 : y < a.ny - 1;
+            if constexpr (kRelax) {
+                a.Tn_out[o] = tw[r];
+                a.a2_out[o] = aw[r];
+            }
+            double rc;
+            if (a.rebuild) {
+                rc = inv_heat_capacity(a.ph, a.eps, tw[r], aw[r], a.m1[o], a.m2[o]);
+                a.rC[o] = rc;
+                if (a.rC32) a.rC32[o] = (float)rc;
+            } else {
+                rc = a.rC_in[o];
+            }
+            if (a.Lam) a.Lam[o] = L;
+            if (a.Lam32) a.Lam32[o] = Lf;
+            // faces in the order -x, +x, -y, +y
+            double d = 0.0;
+            if (fL) d += a.wx * fmean<double>(L, Ll, a.face);
+            if (fR) d += a.wx * fmean<double>(L, Lr, a.face);
+            if (fD) d += a.wy * fmean<double>(L, Lm, a.face);
+            if (fU) d += a.wy * fmean<double>(L, Lp, a.face);
+            bound = fmax(bound, 2.0 * d * rc);
+            if (q) {
+                // q = -tau rC' D' g from the float-rounded Lambda' and rC'
+                const double La = (double)Lf, rf = (double)(float)rc, ga = gw[r];
+                double S = 0.0;
+                if (fL) S += a.wx * fmean<double>(La, (double)Llf, a.face) * (ga - gl);
+                if (fR) S += a.wx * fmean<double>(La, (double)Lrf, a.face) * (ga - gr);
+                if (fD) S += a.wy * fmean<double>(La, (double)(float)Lm, a.face) * (ga - gw[r - 1]);
+                if (fU) S += a.wy * fmean<double>(La, (double)(float)Lp, a.face) * (ga - gw[r + 1]);
+                a.q32[o] = (float)(-a.tau * rf * S);
+                a.w0[o] = 0.0f;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bound = fmax(bound, __shfl_xor(bound, o, 64));
+    if (lane == 0) {
+        const int sl = strip % kSlots;
+        atomicMax((unsigned long long*)(a.lam + sl), (unsigned long long)__double_as_longlong(bound + 0.0));
+    }
+}
+
+}  // namespace
+
+bool coeffs2d_applies(const DevGrid& g) { return g.nz == 1; }
+
+void launch_coeffs2d(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double tau, int face,
+                     const double* T, const double* alpha2, const double* m1, const double* m2, const double* Tn,
+                     int rebuild, double* Lam, double* rC, float* Lam32, float* rC32, float* q32, float* w0,
+                     double* lam, const double* T2_relax, double* Tn_out, double* a2_out) {
+    Coef2DArgs a{};
+    a.ph = ph;
+    a.T = T;
+    a.T2 = T2_relax;
+    a.Tn_out = Tn_out;
+    a.a2_out = a2_out;
+    a.alpha2 = alpha2;
+    a.m1 = m1;
+    a.m2 = m2;
+    a.g = Tn;
+    a.rC_in = rC;
+    a.Lam = Lam;
+    a.rC = rC;
+    a.Lam32 = Lam32;
+    a.rC32 = rC32;
+    a.q32 = q32;
+    a.w0 = w0;
+    a.lam = lam;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.perx = g.per[0];
+    a.pery = g.per[1];
+    a.wx = g.w[0];
+    a.wy = g.w[1];
+    a.tau = tau;
+    a.eps = eps;
+    a.face = face;
+    a.rebuild = rebuild;
+    a.tiles_x = (g.nx + kOut - 1) / kOut;
+    a.strips = a.tiles_x * ((g.ny + kRows - 1) / kRows);
+    const int blocks = (a.strips + kWaves - 1) / kWaves;
+    if (T2_relax) {
+        a.rebuild = 1;
+        hipLaunchKernelGGL(k_coeffs2d<true>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_coeffs2d<false>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+    }
+}
+
+}  // namespace tlim

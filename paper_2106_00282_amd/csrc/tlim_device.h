@@ -1,10 +1,110 @@
-// Device helpers shared by the temporally blocked 2D kernels (forward
-// stages in tlim_sweep.hip, reverse stages in tlim_adjoint.hip).
+// Device helpers shared by the kernel files: the material laws (all
+// kernels) and the wave-level tools of the 2D kernels that keep one column
+// per lane (blocked stages in tlim_sweep.hip, reverse stages in
+// tlim_adjoint.hip, 2D coefficients in tlim_coeffs.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "tlim_internal.h"
 
 namespace tlim {
+namespace phys {
+
+// (T/T0)^n with the exponents the conductivity laws use written out, so the
+// common integer and half-integer cases are exact products.
+static __device__ __forceinline__ double powlaw(double x, double n) {
+    if (n == 0.0) return 1.0;
+    if (n == 1.0) return x;
+    if (n == 2.0) return x * x;
+    if (n == 3.0) return x * x * x;
+    if (n == 2.5) return x * x * sqrt(x);
+    return pow(x, n);
+}
+
+static __device__ __forceinline__ bool is_mixed(double a2, double eps) { return a2 > eps && a2 < 1.0 - eps; }
+
+// W = Gamma_1 C_1/alpha_1^2 + Gamma_2 C_2/alpha_2^2 (interface cells).
+static __device__ __forceinline__ double pressure_stiffness(const DevPhases& ph, double a2, double C1, double C2) {
+    double a1 = 1.0 - a2;
+    return (ph.gamma[0] - 1.0) * C1 / (a1 * a1) + (ph.gamma[1] - 1.0) * C2 / (a2 * a2);
+}
+
+// Cell conductivity Lambda = sum_k alpha_k k0_k (T/T0_k)^n_k (eq. qk_dis).
+static __device__ __forceinline__ double cell_conductivity(const DevPhases& ph, double t, double a2) {
+    return (1.0 - a2) * ph.k0[0] * powlaw(t * ph.invT0[0], ph.npow[0]) +
+           a2 * ph.k0[1] * powlaw(t * ph.invT0[1], ph.npow[1]);
+}
+
+// 1 / C_eff (Sec. 3.4.2 under T_1 = T_2 and p_1 = p_2).
+static __device__ __forceinline__ double inv_heat_capacity(const DevPhases& ph, double eps, double t, double a2,
+                                                           double m1, double m2) {
+    double B1 = ph.pinf[0] - ph.pinf[1];
+    double C1 = m1 * ph.cv[0], C2 = m2 * ph.cv[1];
+    double C = C1 + C2;
+    if (B1 != 0.0 && is_mixed(a2, eps)) C += B1 * B1 / (t * t * pressure_stiffness(ph, a2, C1, C2));
+    return 1.0 / C;
+}
+
+// End state of the relaxation system in an interface cell (Sec. 3.4.1):
+// phase energies summed conserve E = C1 T1 + C2 T2 + alpha_k p_inf,k, and
+// p_1 = p_2 at T_1 = T_2 = T'.  With B = p_inf,2 - p_inf,1,
+// T'(a) = (C1 T1 + C2 T2 + (alpha2^0 - a) B)/(C1 + C2) and
+// (p_1 - p_2) a (1-a) = A2 a^2 + A1 a + A0 is quadratic in a = alpha2'.
+// The root with 0 < a < 1 and T'(a) > 0 is taken (eq. Taverage when B = 0).
+static __device__ __forceinline__ void relax_cell(const DevPhases& ph, double eps, double a20, double T1,
+                                                  double T2, double m1, double m2, double& T, double& a2) {
+    if (a20 <= eps || a20 >= 1.0 - eps) {
+        // pure cell: the absent phase takes the present phase's temperature
+        T = a20 <= eps ? T1 : T2;
+        a2 = a20;
+        return;
+    }
+    const double B = ph.pinf[1] - ph.pinf[0];
+    const double G1 = ph.gamma[0] - 1.0, G2 = ph.gamma[1] - 1.0;
+    double C1 = m1 * ph.cv[0], C2 = m2 * ph.cv[1];
+    double S = C1 + C2;
+    double E = C1 * T1 + C2 * T2;
+    double t0 = (E + a20 * B) / S, t1 = -B / S;   // T'(a) = t0 + t1 a
+    double l0 = -G2 * C2, l1 = G1 * C1 + G2 * C2;  // L(a) = l0 + l1 a
+    double A2 = t1 * l1 - B, A1 = t0 * l1 + t1 * l0 + B, A0 = t0 * l0;
+    double root;
+    if (A2 == 0.0) {
+        root = -A0 / A1;
+    } else {
+        double disc = fmax(A1 * A1 - 4.0 * A2 * A0, 0.0);
+        double qq = -0.5 * (A1 + copysign(sqrt(disc), A1));
+        double r1 = qq / A2, r2 = A0 / qq;
+        bool ok1 = r1 > 0.0 && r1 < 1.0 && t0 + t1 * r1 > 0.0;
+        bool ok2 = r2 > 0.0 && r2 < 1.0 && t0 + t1 * r2 > 0.0;
+        root = ok1 ? r1 : r2;
+        if (ok1 && ok2) root = fabs(r1 - a20) < fabs(r2 - a20) ? r1 : r2;
+        if (!ok1 && !ok2) {
+            // rounding pushed the admissible root out: bisect the sign change
+            // of the quadratic on (lo, hi) = {0 < a < 1, T'(a) > 0}
+            double lo = 0.0, hi = 1.0;
+            if (t1 < 0.0) hi = fmin(hi, -t0 / t1);
+            if (t1 > 0.0) lo = fmax(lo, -t0 / t1);
+            for (int it = 0; it < 120; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if ((A2 * mid + A1) * mid + A0 < 0.0) lo = mid;
+                else hi = mid;
+            }
+            root = 0.5 * (lo + hi);
+        }
+        // two Newton steps on the quadratic polish the root
+        for (int it = 0; it < 2; ++it) {
+            double f = (A2 * root + A1) * root + A0, df = 2.0 * A2 * root + A1;
+            if (df != 0.0) root -= f / df;
+        }
+    }
+    T = t0 + t1 * root;
+    a2 = root;
+}
+
+}  // namespace phys
+
 namespace tb {
 
 // Extended tile: 64 lanes (x) by WAVES waves of ROWS rows (y) per workgroup;

@@ -59,8 +59,9 @@ struct PassResult {
     double v[kTargets];
 };
 
-// Fold rows [t0, t1) of the accumulator into res->v[t0..t1).
-void launch_collect(hipStream_t s, const double* acc, PassResult* res, int t0, int t1);
+// Fold rows [t0, t1) of the accumulator into res->v[t0..t1) (res may be
+// pinned host memory); consume = 1 also zeroes the rows.
+void launch_collect(hipStream_t s, double* acc, PassResult* res, int t0, int t1, int consume);
 // Zero rows [t0, t1) of the accumulator.
 void launch_zero_rows(hipStream_t s, double* acc, int t0, int t1);
 
@@ -80,7 +81,8 @@ void launch_relax(hipStream_t s, const DevGrid& g, const DevPhases& ph, double e
                   const double* m1, const double* m2, double* T1, double* T2, double* Tn, double* a2n);
 
 // Heat coefficients at (T, alpha2): Lam = sum alpha_k lambda_k(T), rC = 1/C_eff,
-// rhs = Tn + tau rC (alpha1 I1 + alpha2 I2).  Optional float copies.
+// rhs = Tn + tau rC (alpha1 I1 + alpha2 I2).  rC and rhs may be NULL (not
+// written).  Optional float copies.
 void launch_heat_coeffs(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double tau,
                         const double* T, const double* alpha2, const double* m1, const double* m2,
                         const double* Tn, const double* src1, const double* src2, double* Lam,
@@ -99,6 +101,23 @@ void launch_heat_coeffs_bound(hipStream_t s, const DevGrid& g, const DevPhases& 
                               const double* T, const double* alpha2, const double* m1, const double* m2,
                               const double* Tn, const double* src1, const double* src2, double* Lam, double* rC,
                               double* rhs, float* Lam32, float* rC32, float* q32, float* w0, double* lam);
+
+// 2D grids (nz == 1) without sources: the same coefficients and bound from
+// one pass over (T, alpha2) in column strips.  g = Tn is not copied (the
+// stages read Tn).  rebuild = 0 keeps rC (and rC32) from an earlier pass of
+// the step -- valid when 1/C does not depend on T (equal p_inf).  Lam may be
+// NULL (FP32 contexts need Lam32 only); q32/w0 as above (w0 = 0).
+// With T2_relax != NULL the kernel first relaxes every cell from (alpha2,
+// T = T1, T2_relax, m1, m2) -- as launch_relax -- and builds the coefficients
+// at the relaxed state (rebuild implied); the relaxed T goes to Tn_out (also
+// g, so Tn is not read), the relaxed alpha2 to a2_out (alpha2 itself is not
+// written).
+bool coeffs2d_applies(const DevGrid& g);
+void launch_coeffs2d(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double tau, int face,
+                     const double* T, const double* alpha2, const double* m1, const double* m2, const double* Tn,
+                     int rebuild, double* Lam, double* rC, float* Lam32, float* rC32, float* q32, float* w0,
+                     double* lam, const double* T2_relax = nullptr, double* Tn_out = nullptr,
+                     double* a2_out = nullptr);
 
 // Gershgorin bound max_i 2 rC_i sum_f w Lam_f -> max into the row lam.
 void launch_gershgorin(hipStream_t s, const DevGrid& g, int face, const double* Lam, const double* rC, double* lam);
@@ -152,12 +171,13 @@ void launch_adj_stage(hipStream_t s, const DevGrid& g, int face, const double* l
                       const double* Lam, const double* rC, double* lam_out, double* dg, double* gLam,
                       double cm, double tb, double tau);
 // After a reversed pass: acc += dg + lam0 (with rCpsi != NULL the two are in
-// psi = C^-1 lambda form and divided by rCpsi = 1/C first); mu = gLam
-// dLam/dT(Tit); the two dL/dk0 sums are added to the rows k0a, k0b; if
-// first_pass: acc += mu.
+// psi = C^-1 lambda form and divided by rCpsi = 1/C first; init = 1 starts
+// acc at zero instead of reading it); mu = gLam dLam/dT(Tit); the two dL/dk0
+// sums are added to the rows k0a, k0b; if first_pass: acc += mu.
 void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* Tit,
                      const double* alpha2, const double* gLam, const double* dg, const double* lam0,
-                     double* acc, double* mu, int first_pass, const double* rCpsi, double* k0a, double* k0b);
+                     double* acc, double* mu, int first_pass, const double* rCpsi, double* k0a, double* k0b,
+                     int init);
 
 void launch_fill(hipStream_t s, double* p, double v, int64_t n);
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n);

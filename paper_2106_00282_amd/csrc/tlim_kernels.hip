@@ -12,27 +12,23 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "tlim_device.h"
 #include "tlim_internal.h"
 
 namespace tlim {
 
 namespace {
 
+using phys::cell_conductivity;
+using phys::inv_heat_capacity;
+using phys::is_mixed;
+using phys::powlaw;
+using phys::pressure_stiffness;
+
 constexpr int TX = 64;
 constexpr int TY = 4;
 
 // ------------------------------------------------------------------ helpers
-
-// (T/T0)^n with the exponents the conductivity laws use written out, so the
-// common integer and half-integer cases are exact products.
-__device__ __forceinline__ double powlaw(double x, double n) {
-    if (n == 0.0) return 1.0;
-    if (n == 1.0) return x;
-    if (n == 2.0) return x * x;
-    if (n == 3.0) return x * x * x;
-    if (n == 2.5) return x * x * sqrt(x);
-    return pow(x, n);
-}
 
 template <typename R>
 __device__ __forceinline__ R face_mean(R a, R b, int face) {
@@ -196,14 +192,6 @@ __device__ __forceinline__ void cell_ijk(const DevGrid& g, int64_t a, int& i, in
     i = (int)(r - (int64_t)j * g.nx);
 }
 
-__device__ __forceinline__ bool is_mixed(double a2, double eps) { return a2 > eps && a2 < 1.0 - eps; }
-
-// W = Gamma_1 C_1/alpha_1^2 + Gamma_2 C_2/alpha_2^2 (interface cells).
-__device__ __forceinline__ double pressure_stiffness(const DevPhases& ph, double a2, double C1, double C2) {
-    double a1 = 1.0 - a2;
-    return (ph.gamma[0] - 1.0) * C1 / (a1 * a1) + (ph.gamma[1] - 1.0) * C2 / (a2 * a2);
-}
-
 int reduce_blocks(int64_t N) {
     int64_t b = (N + kReduceThreads - 1) / kReduceThreads;
     return (int)(b < kReduceBlocks ? (b > 0 ? b : 1) : kReduceBlocks);
@@ -213,89 +201,24 @@ dim3 tile_grid(const DevGrid& g) { return dim3((g.nx + TX - 1) / TX, (g.ny + TY 
 
 // -------------------------------------------------- temperature relaxation
 
-// End state of the relaxation system in an interface cell (Sec. 3.4.1):
-// phase energies summed conserve E = C1 T1 + C2 T2 + alpha_k p_inf,k, and
-// p_1 = p_2 at T_1 = T_2 = T'.  With B = p_inf,2 - p_inf,1,
-// T'(a) = (C1 T1 + C2 T2 + (alpha2^0 - a) B)/(C1 + C2) and
-// (p_1 - p_2) a (1-a) = A2 a^2 + A1 a + A0 is quadratic in a = alpha2'.
-// The root with 0 < a < 1 and T'(a) > 0 is taken (eq. Taverage when B = 0).
+// Relaxation of every cell (phys::relax_cell) in place; Tn and a2n (each
+// nullable) also receive the relaxed T and alpha2.
 __global__ void __launch_bounds__(256) k_relax(DevGrid g, DevPhases ph, double eps, double* alpha2,
                                                const double* __restrict__ m1, const double* __restrict__ m2,
                                                double* T1, double* T2, double* Tn, double* a2n) {
-    double B = ph.pinf[1] - ph.pinf[0];
-    double G1 = ph.gamma[0] - 1.0, G2 = ph.gamma[1] - 1.0;
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
          a += (int64_t)gridDim.x * blockDim.x) {
-        double a20 = alpha2[a];
-        if (a20 <= eps || a20 >= 1.0 - eps) {
-            // pure cell: the absent phase takes the present phase's temperature
-            double t = a20 <= eps ? T1[a] : T2[a];
-            T1[a] = t;
-            T2[a] = t;
-            if (Tn) Tn[a] = t;
-            if (a2n) a2n[a] = a20;
-            continue;
-        }
-        double C1 = m1[a] * ph.cv[0], C2 = m2[a] * ph.cv[1];
-        double S = C1 + C2;
-        double E = C1 * T1[a] + C2 * T2[a];
-        double t0 = (E + a20 * B) / S, t1 = -B / S;   // T'(a) = t0 + t1 a
-        double l0 = -G2 * C2, l1 = G1 * C1 + G2 * C2;  // L(a) = l0 + l1 a
-        double A2 = t1 * l1 - B, A1 = t0 * l1 + t1 * l0 + B, A0 = t0 * l0;
-        double root;
-        if (A2 == 0.0) {
-            root = -A0 / A1;
-        } else {
-            double disc = fmax(A1 * A1 - 4.0 * A2 * A0, 0.0);
-            double qq = -0.5 * (A1 + copysign(sqrt(disc), A1));
-            double r1 = qq / A2, r2 = A0 / qq;
-            bool ok1 = r1 > 0.0 && r1 < 1.0 && t0 + t1 * r1 > 0.0;
-            bool ok2 = r2 > 0.0 && r2 < 1.0 && t0 + t1 * r2 > 0.0;
-            root = ok1 ? r1 : r2;
-            if (ok1 && ok2) root = fabs(r1 - a20) < fabs(r2 - a20) ? r1 : r2;
-            if (!ok1 && !ok2) {
-                // rounding pushed the admissible root out: bisect the sign change
-                // of the quadratic on (lo, hi) = {0 < a < 1, T'(a) > 0}
-                double lo = 0.0, hi = 1.0;
-                if (t1 < 0.0) hi = fmin(hi, -t0 / t1);
-                if (t1 > 0.0) lo = fmax(lo, -t0 / t1);
-                for (int it = 0; it < 120; ++it) {
-                    double mid = 0.5 * (lo + hi);
-                    if ((A2 * mid + A1) * mid + A0 < 0.0) lo = mid;
-                    else hi = mid;
-                }
-                root = 0.5 * (lo + hi);
-            }
-            // two Newton steps on the quadratic polish the root
-            for (int it = 0; it < 2; ++it) {
-                double f = (A2 * root + A1) * root + A0, df = 2.0 * A2 * root + A1;
-                if (df != 0.0) root -= f / df;
-            }
-        }
-        double T = t0 + t1 * root;
-        alpha2[a] = root;
+        double T, a2;
+        phys::relax_cell(ph, eps, alpha2[a], T1[a], T2[a], m1[a], m2[a], T, a2);
+        alpha2[a] = a2;
         T1[a] = T;
         T2[a] = T;
         if (Tn) Tn[a] = T;
-        if (a2n) a2n[a] = root;
+        if (a2n) a2n[a] = a2;
     }
 }
 
 // ------------------------------------------------------------ coefficients
-
-__device__ __forceinline__ double cell_conductivity(const DevPhases& ph, double t, double a2) {
-    return (1.0 - a2) * ph.k0[0] * powlaw(t * ph.invT0[0], ph.npow[0]) + a2 * ph.k0[1] * powlaw(t * ph.invT0[1], ph.npow[1]);
-}
-
-// 1 / C_eff (Sec. 3.4.2 under T_1 = T_2 and p_1 = p_2).
-__device__ __forceinline__ double inv_heat_capacity(const DevPhases& ph, double eps, double t, double a2, double m1,
-                                                    double m2) {
-    double B1 = ph.pinf[0] - ph.pinf[1];
-    double C1 = m1 * ph.cv[0], C2 = m2 * ph.cv[1];
-    double C = C1 + C2;
-    if (B1 != 0.0 && is_mixed(a2, eps)) C += B1 * B1 / (t * t * pressure_stiffness(ph, a2, C1, C2));
-    return 1.0 / C;
-}
 
 // Coefficients of a Picard pass and the Gershgorin bound in one pass over
 // (T, alpha2).  Every cell of the block's 64x4 tile, and of its one-cell
@@ -441,8 +364,8 @@ __global__ void __launch_bounds__(256) k_heat_coeffs(DevGrid g, DevPhases ph, do
         if (src1) f += a1 * src1[a];
         if (src2) f += a2 * src2[a];
         Lam[a] = L;
-        rC[a] = r;
-        rhs[a] = Tn[a] + tau * r * f;
+        if (rC) rC[a] = r;
+        if (rhs) rhs[a] = Tn[a] + tau * r * f;
         if (Lam32) {
             Lam32[a] = (float)L;
             rC32[a] = (float)r;
@@ -679,14 +602,16 @@ __global__ void __launch_bounds__(256) k_adj_cell(DevGrid g, DevPhases ph, const
                                                   const double* __restrict__ alpha2, const double* __restrict__ gLam,
                                                   const double* __restrict__ dg, const double* __restrict__ lam0,
                                                   double* __restrict__ acc, double* __restrict__ mu, int first_pass,
-                                                  const double* __restrict__ rCpsi, double* k0a, double* k0b) {
+                                                  const double* __restrict__ rCpsi, double* k0a, double* k0b,
+                                                  int init) {
     __shared__ double sh[16];
     double s0 = 0.0, s1 = 0.0;
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
          a += (int64_t)gridDim.x * blockDim.x) {
         double t = Tit[a], a2 = alpha2[a], a1 = 1.0 - a2, gl = gLam[a];
         // lambda form, or psi = C^-1 lambda form (rCpsi = 1/C): lambda = psi / rC
-        double acc_a = rCpsi ? acc[a] + (dg[a] + lam0[a]) / rCpsi[a] : acc[a] + dg[a] + lam0[a];
+        const double acc0 = init ? 0.0 : acc[a];
+        double acc_a = rCpsi ? acc0 + (dg[a] + lam0[a]) / rCpsi[a] : acc0 + dg[a] + lam0[a];
         double x0 = t * ph.invT0[0], x1 = t * ph.invT0[1];
         s0 += gl * a1 * powlaw(x0, ph.npow[0]);
         s1 += gl * a2 * powlaw(x1, ph.npow[1]);
@@ -705,14 +630,19 @@ __global__ void __launch_bounds__(256) k_adj_cell(DevGrid g, DevPhases ph, const
     }
 }
 
-// One wave per target: fold its kSlots slots with the target's operation.
-__global__ void __launch_bounds__(64) k_collect(const double* __restrict__ acc, PassResult* res, int t0) {
+// One wave per target row folds its kSlots slots with the target's
+// operation; consume = 1 also clears the row for its next use.
+__global__ void __launch_bounds__(64) k_collect(double* __restrict__ acc, PassResult* res, int t0, int consume) {
     const int t = t0 + blockIdx.x, lane = threadIdx.x;
-    const double* row = acc + (int64_t)t * kSlots;
+    double* row = acc + (int64_t)t * kSlots;
     const bool sum = tgt_is_sum(t);
     double v = 0.0;
 #pragma unroll
     for (int k = 0; k < kSlots / 64; ++k) v = sum ? v + row[lane + 64 * k] : fmax(v, row[lane + 64 * k]);
+    if (consume) {
+#pragma unroll
+        for (int k = 0; k < kSlots / 64; ++k) row[lane + 64 * k] = 0.0;
+    }
     v = sum ? wave_sum(v) : wave_max(v);
     if (lane == 0) res->v[t] = v;
 }
@@ -744,8 +674,8 @@ void launch_zero_rows(hipStream_t s, double* acc, int t0, int t1) {
     hipLaunchKernelGGL(k_fill, dim3(pointwise_blocks(n)), dim3(256), 0, s, acc + (int64_t)t0 * kSlots, 0.0, n);
 }
 
-void launch_collect(hipStream_t s, const double* acc, PassResult* res, int t0, int t1) {
-    hipLaunchKernelGGL(k_collect, dim3(t1 - t0), dim3(64), 0, s, acc, res, t0);
+void launch_collect(hipStream_t s, double* acc, PassResult* res, int t0, int t1, int consume) {
+    hipLaunchKernelGGL(k_collect, dim3(t1 - t0), dim3(64), 0, s, acc, res, t0, consume);
 }
 
 void launch_relax(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double* alpha2,
@@ -834,9 +764,9 @@ void launch_adj_stage(hipStream_t s, const DevGrid& g, int face, const double* l
 
 void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* Tit, const double* alpha2,
                      const double* gLam, const double* dg, const double* lam0, double* acc, double* mu,
-                     int first_pass, const double* rCpsi, double* k0a, double* k0b) {
+                     int first_pass, const double* rCpsi, double* k0a, double* k0b, int init) {
     hipLaunchKernelGGL(k_adj_cell, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, Tit, alpha2, gLam, dg,
-                       lam0, acc, mu, first_pass, rCpsi, k0a, k0b);
+                       lam0, acc, mu, first_pass, rCpsi, k0a, k0b, init);
 }
 
 void launch_fill(hipStream_t s, double* p, double v, int64_t n) {

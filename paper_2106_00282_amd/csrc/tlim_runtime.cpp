@@ -49,10 +49,15 @@ struct tlim_ctx {
     double* field[TLIM_NFIELDS];
     bool fset[TLIM_NFIELDS];
     double *Tn, *Tnew, *a2n, *Lam, *rC, *rhs, *vb[2];
+    const double* g_heat;  // right-hand side g of the heat passes: rhs, or Tn when there is no source
     float *Lam32, *rC32, *q32, *wb[2];
     double* acc;           // reduction rows: kTargets x kSlots
     PassResult* res_dev;   // folded results (one double per target)
     PassResult* res_host;  // pinned copy
+    PassResult* res_host_dev;  // device address of res_host (NULL: copy from res_dev)
+    // Leading rows of the Picard-pass targets known to be zero, and the count
+    // to restore when the step's final readback consumes its rows.
+    int clean_rows, clean_keep;
     hipEvent_t ev[kMaxEvents];
     // Schedule history for P prediction: P of each Picard pass of the last
     // completed step (hist_passes = 0: none).
@@ -359,11 +364,26 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
 }
 
 // Fold the rows [t0, t1) and bring the results to the host (synchronises).
-tlim_status read_result(tlim_ctx* c, int t0, int t1) {
-    tlim::launch_collect(c->stream, c->acc, c->res_dev, t0, t1);
-    HIP_TRY(c, hipMemcpyAsync(c->res_host, c->res_dev, sizeof(PassResult), hipMemcpyDeviceToHost, c->stream));
+// With consume the rows are also cleared on the device.
+tlim_status read_result(tlim_ctx* c, int t0, int t1, bool consume = false) {
+    if (c->res_host_dev) {
+        // the fold writes straight into the pinned result block
+        tlim::launch_collect(c->stream, c->acc, c->res_host_dev, t0, t1, consume ? 1 : 0);
+    } else {
+        tlim::launch_collect(c->stream, c->acc, c->res_dev, t0, t1, consume ? 1 : 0);
+        HIP_TRY(c, hipMemcpyAsync(c->res_host, c->res_dev, sizeof(PassResult), hipMemcpyDeviceToHost, c->stream));
+    }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return TLIM_OK;
+}
+
+// Zero the rows of the Picard-pass targets a step uses, unless the previous
+// step's final readback left them zero.
+void begin_pass_rows(tlim_ctx* c, int passes) {
+    const int need = tlim::tgt_lam(passes);
+    if (c->clean_rows < need) zero_rows(c, tlim::tgt_lam(0), need);
+    c->clean_keep = std::max(c->clean_rows, need);
+    c->clean_rows = 0;  // until the step's rows are consumed
 }
 
 double cell_volume(const tlim_ctx* c) { return c->h[0] * c->h[1] * c->h[2]; }
@@ -402,14 +422,31 @@ tlim_status viscous(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep,
     return TLIM_OK;
 }
 
-// Heat-conduction coefficients of the current iterate (T1, alpha2) and the
-// Gershgorin bound (max into *lam).
-void heat_coeffs(tlim_ctx* c, const DevGrid& g, const DevPhases& ph, const tlim_step_opts* o, double* lam) {
-    tlim::launch_heat_coeffs_bound(c->stream, g, ph, o->alpha_eps, o->dt, o->face_mean, c->field[TLIM_T1],
-                                   c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], c->Tn,
+// Heat-conduction coefficients of pass `it` at the current iterate (T1,
+// alpha2) and the Gershgorin bound (max into *lam); sets c->g_heat.
+bool fast_coeffs(const tlim_ctx* c, const DevGrid& g) {
+    return !(c->fset[TLIM_SRC1] || c->fset[TLIM_SRC2]) && tlim::coeffs2d_applies(g);
+}
+
+void heat_coeffs(tlim_ctx* c, const DevGrid& g, const DevPhases& ph, const tlim_step_opts* o, double* lam, int it) {
+    // T^(0) is the relaxed state T^n
+    const double* T = it == 0 ? c->Tn : c->field[TLIM_T1];
+    if (fast_coeffs(c, g)) {
+        // 1/C depends on T only through B1 = p_inf,1 - p_inf,2
+        const bool rebuild = it == 0 || c->phase[0].pinf != c->phase[1].pinf;
+        const bool need_lam64 = c->precision == TLIM_FP64 || o->cycle_mode;
+        tlim::launch_coeffs2d(c->stream, g, ph, o->alpha_eps, o->dt, o->face_mean, T, c->field[TLIM_ALPHA2],
+                              c->field[TLIM_M1], c->field[TLIM_M2], c->Tn, rebuild ? 1 : 0,
+                              need_lam64 ? c->Lam : nullptr, c->rC, c->Lam32, c->rC32, c->q32, c->wb[0], lam);
+        c->g_heat = c->Tn;
+        return;
+    }
+    tlim::launch_heat_coeffs_bound(c->stream, g, ph, o->alpha_eps, o->dt, o->face_mean, T, c->field[TLIM_ALPHA2],
+                                   c->field[TLIM_M1], c->field[TLIM_M2], c->Tn,
                                    c->fset[TLIM_SRC1] ? c->field[TLIM_SRC1] : nullptr,
                                    c->fset[TLIM_SRC2] ? c->field[TLIM_SRC2] : nullptr, c->Lam, c->rC, c->rhs,
                                    c->Lam32, c->rC32, c->q32, c->wb[0], lam);
+    c->g_heat = c->rhs;
 }
 
 // Chebyshev cycles to the backward-Euler solution of one pass (cycle mode).
@@ -424,8 +461,8 @@ tlim_status cycle_pass(tlim_ctx* c, const DevGrid& g, const tlim_step_opts* o, i
         tm.start();
         for (int m = 0; m < s_stages; ++m) {
             tlim::StageParam sp{nullptr, o->dt * b[m], 0.0};
-            tlim::launch_stage64(c->stream, g, o->face_mean, c->vb[cur], c->rhs, c->Lam, c->rC, c->vb[cur ^ 1], sp,
-                                 o->dt);
+            tlim::launch_stage64(c->stream, g, o->face_mean, c->vb[cur], c->g_heat, c->Lam, c->rC, c->vb[cur ^ 1],
+                                 sp, o->dt);
             cur ^= 1;
             sc.launches++;
         }
@@ -433,7 +470,7 @@ tlim_status cycle_pass(tlim_ctx* c, const DevGrid& g, const tlim_step_opts* o, i
         sc.sweeps += s_stages;
         ++cyc;
         zero_rows(c, tlim::kTgtRR, tlim::kTgtGG + 1);
-        tlim::launch_be_residual(c->stream, g, o->face_mean, c->vb[cur], c->rhs, c->Lam, c->rC, o->dt,
+        tlim::launch_be_residual(c->stream, g, o->face_mean, c->vb[cur], c->g_heat, c->Lam, c->rC, o->dt,
                                  row(c, tlim::kTgtRR), row(c, tlim::kTgtGG));
         tlim_status st = read_result(c, tlim::kTgtRR, tlim::kTgtGG + 1);
         if (st) return st;
@@ -464,21 +501,25 @@ struct HeatOutcome {
 // P of each pass is taken from the previous step and the stages read lambda_G
 // from device memory; the predictions are checked after one readback at the
 // end (mispredicted = true means the caller must roll back and rerun).
+// pass0_done: the coefficients and bound of the first pass were built with
+// the relaxation (and the accumulator rows zeroed before it).
 tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_step_report* rep, Timer& tm,
-                        SweepCount& sc, HeatOutcome& out) {
+                        SweepCount& sc, HeatOutcome& out, bool pass0_done) {
     hipStream_t s = c->stream;
     DevGrid g = dev_grid(c, kUnit);
     DevPhases ph = dev_phases(c);
     const bool B1 = c->phase[0].pinf != c->phase[1].pinf;
     int it;
     int P_used[TLIM_MAX_PASSES] = {0};
-    zero_rows(c, tlim::tgt_lam(0), tlim::tgt_lam(o->passes));
+    if (!pass0_done) begin_pass_rows(c, o->passes);
     auto change = [&](int i) {
         double tmax = result(c, tlim::tgt_tmax(i)), dmax = result(c, tlim::tgt_dmax(i));
         return tmax > 0.0 ? dmax / tmax : dmax;
     };
     for (it = 0; it < o->passes; ++it) {
-        heat_coeffs(c, g, ph, o, row(c, tlim::tgt_lam(it)));
+        if (!(it == 0 && pass0_done)) heat_coeffs(c, g, ph, o, row(c, tlim::tgt_lam(it)), it);
+        // previous iterate T^(it) (T^(0) = T^n)
+        const double* Tit = it == 0 ? c->Tn : c->field[TLIM_T1];
         double lam = 0.0;
         if (mode == Mode::Sync) {
             // one readback: lambda_G of this pass and the change of the previous one
@@ -521,11 +562,11 @@ tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_st
             }
             if (!(res < o->cycle_tol)) out.cycle_fail = true;  // keep the last iterate
         } else {
-            run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->rhs, c->Tnew,
-                         need_update ? nullptr : c->field[TLIM_T1], pass_slots(c, it), tm, sc, true);
+            run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->g_heat, c->Tnew, need_update ? nullptr : Tit,
+                         pass_slots(c, it), tm, sc, true);
         }
         if (need_update) {
-            tlim::launch_pass_update(s, g, ph, o->alpha_eps, c->field[TLIM_T1], c->Tnew, c->Tn, c->a2n,
+            tlim::launch_pass_update(s, g, ph, o->alpha_eps, Tit, c->Tnew, c->Tn, c->a2n,
                                      c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2],
                                      c->field[TLIM_ALPHA2], pass_slots(c, it));
         }
@@ -533,8 +574,10 @@ tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_st
     }
     out.passes_run = it;
     if (!out.converged) {
-        tlim_status st = read_result(c, tlim::tgt_lam(0), tlim::tgt_lam(it));
+        // it = o->passes here: the readback consumes every row the step used
+        tlim_status st = read_result(c, tlim::tgt_lam(0), tlim::tgt_lam(it), true);
         if (st) return st;
+        c->clean_rows = c->clean_keep;
         int last = it - 1;
         out.last_err = change(last);
         out.bad = result(c, tlim::tgt_bad(last));
@@ -614,6 +657,11 @@ tlim_status tlim_create(const tlim_grid* grid, int32_t precision, void* hip_stre
         delete c;
         return TLIM_E_HIP;
     }
+    if (hipHostGetDevicePointer((void**)&c->res_host_dev, c->res_host, 0) != hipSuccess) {
+        c->res_host_dev = nullptr;
+        (void)hipGetLastError();
+    }
+    c->clean_rows = c->clean_keep = 0;
     for (int i = 0; i < kMaxEvents; ++i) {
         if (hipEventCreate(&c->ev[i]) != hipSuccess) {
             for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->ev[j]);
@@ -664,6 +712,7 @@ tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
     c->res_dev = (PassResult*)(base + L.res);
     c->t2_alias = false;
     c->hist_passes = 0;
+    c->clean_rows = c->clean_keep = 0;  // the new accumulator is not known to be zero
     if (c->precision == TLIM_FP32) {
         c->Lam32 = (float*)(base + L.Lam32);
         c->rC32 = (float*)(base + L.rC32);
@@ -763,15 +812,33 @@ tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
         st = viscous(c, o, rep, tm, sc);
         if (st) return st;
     }
-    tlim::launch_relax(s, g, ph, o->alpha_eps, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2],
-                       c->field[TLIM_T1], T2_ptr(c), c->Tn, B1 ? c->a2n : nullptr);
+    // Relaxation.  On 2D grids without sources it is fused with the first
+    // pass's coefficients and bound; the relaxed state goes to Tn and a2n,
+    // and a2n becomes the alpha2 field.  T1 is not written: every pass
+    // starts from Tn and the last one writes T1.
+    bool pass0_done = false;
+    if (fast_coeffs(c, g)) {
+        begin_pass_rows(c, o->passes);
+        const bool need_lam64 = c->precision == TLIM_FP64 || o->cycle_mode;
+        tlim::launch_coeffs2d(s, g, ph, o->alpha_eps, o->dt, o->face_mean, c->field[TLIM_T1], c->field[TLIM_ALPHA2],
+                              c->field[TLIM_M1], c->field[TLIM_M2], nullptr, 1, need_lam64 ? c->Lam : nullptr, c->rC,
+                              c->Lam32, c->rC32, c->q32, c->wb[0], row(c, tlim::tgt_lam(0)), T2_ptr(c), c->Tn,
+                              c->a2n);
+        std::swap(c->field[TLIM_ALPHA2], c->a2n);
+        if (B1) tlim::launch_copy(s, c->a2n, c->field[TLIM_ALPHA2], c->N);  // kept for a rollback
+        c->g_heat = c->Tn;
+        pass0_done = true;
+    } else {
+        tlim::launch_relax(s, g, ph, o->alpha_eps, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2],
+                           c->field[TLIM_T1], T2_ptr(c), c->Tn, B1 ? c->a2n : nullptr);
+    }
     c->t2_alias = true;  // T_1 = T_2 from here on
 
     Mode mode = Mode::Sync;
     if (o->frozen_lambda) mode = Mode::Frozen;
     else if (!o->cycle_mode && o->picard_tol <= 0.0 && c->hist_passes == o->passes) mode = Mode::Predict;
     HeatOutcome out;
-    st = heat_passes(c, o, mode, rep, tm, sc, out);
+    st = heat_passes(c, o, mode, rep, tm, sc, out, pass0_done);
     if (st) return st;
     const bool predicted = mode == Mode::Predict && !out.mispredicted;
     const bool mispredicted = out.mispredicted;
@@ -779,12 +846,11 @@ tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
         // roll back to the relaxed state and rerun with one readback per pass;
         // only the rerun's sweeps count
         c->predict_misses++;
-        tlim::launch_copy(s, c->field[TLIM_T1], c->Tn, c->N);
         if (B1) tlim::launch_copy(s, c->field[TLIM_ALPHA2], c->a2n, c->N);
         out = HeatOutcome{};
         sc = SweepCount{};
         tm.used = 0;
-        st = heat_passes(c, o, Mode::Sync, rep, tm, sc, out);
+        st = heat_passes(c, o, Mode::Sync, rep, tm, sc, out, false);
         if (st) return st;
     }
     if (rep) {
@@ -830,7 +896,7 @@ tlim_status check_adjoint(tlim_ctx* c, const tlim_step_opts* o) {
 }
 
 struct AdjLayout {
-    size_t stages, Tpass, mu, acc, dg, gLam, lamA, lamB, total;
+    size_t stages, Tpass, Lp, mu, acc, dg, gLam, lamA, lamB, total;
     int nst;
 };
 
@@ -843,6 +909,8 @@ AdjLayout adj_layout(int64_t N, int passes, int Pmax) {
     off += d * (size_t)passes * (size_t)L.nst;
     L.Tpass = off;
     off += d * (size_t)(passes + 1);
+    L.Lp = off;
+    off += d * (size_t)passes;
     size_t* rest[] = {&L.mu, &L.acc, &L.dg, &L.gLam, &L.lamA, &L.lamB};
     for (size_t* p : rest) {
         *p = off;
@@ -852,63 +920,69 @@ AdjLayout adj_layout(int64_t N, int passes, int Pmax) {
     return L;
 }
 
-// Heat passes of one step without relaxation, from Tpass[0], storing every
-// stage iterate of every pass (when stages != NULL) and T^(it) in Tpass[it].
-void adj_forward_step(tlim_ctx* c, const tlim_step_opts* o, const double* lamv, double* Tpass, double* stages,
-                      size_t stride_field, size_t stride_pass) {
+// Heat passes of one step without relaxation, from T0: pass it reads
+// T^(it) (T0 for it = 0, else Tpass + it*sf) and writes T^(it+1) to
+// Tpass + (it+1)*sf.  With stages != NULL every stage iterate v^(m),
+// 1 <= m < nst, of pass it goes to slot m of stages + it*stride_pass
+// (v^(0) = T0 is not copied), and the conductivities of pass it to
+// Lp + it*sf.  1/C is built by the first pass that finds rC_ready false.
+void adj_forward_step(tlim_ctx* c, const tlim_step_opts* o, const double* lamv, const double* T0, double* Tpass,
+                      double* stages, double* Lp, size_t sf, size_t stride_pass, bool& rC_ready) {
     DevGrid g = dev_grid(c, kUnit);
     DevPhases ph = dev_phases(c);
     hipStream_t s = c->stream;
-    const int64_t N = c->N;
-    const double* Tn = Tpass;
     for (int it = 0; it < o->passes; ++it) {
-        double* Tit = Tpass + (size_t)it * stride_field;
-        double* Tout = Tpass + (size_t)(it + 1) * stride_field;
+        const double* Tit = it == 0 ? T0 : Tpass + (size_t)it * sf;
+        double* Tout = Tpass + (size_t)(it + 1) * sf;
+        double* Lam = Lp ? Lp + (size_t)it * sf : c->Lam;
+        // no sources: g = T0, and no right-hand side is written
         tlim::launch_heat_coeffs(s, g, ph, o->alpha_eps, o->dt, Tit, c->field[TLIM_ALPHA2], c->field[TLIM_M1],
-                                 c->field[TLIM_M2], Tn, nullptr, nullptr, c->Lam, c->rC, c->rhs, nullptr, nullptr);
+                                 c->field[TLIM_M2], T0, nullptr, nullptr, Lam, rC_ready ? nullptr : c->rC, nullptr,
+                                 nullptr, nullptr);
+        rC_ready = true;
         int P = lim_P(o->dt, lamv[it]);
         std::vector<double> b = lim_params(P, lamv[it], o->order);
         int nst = (int)b.size();
+        std::vector<double> tbv(nst);
+        for (int m = 0; m < nst; ++m) tbv[m] = o->dt * b[m];
         if (stages) {
-            // every iterate v^(m), m < nst, goes to slot m of the pass
             double* st0 = stages + (size_t)it * stride_pass;
-            tlim::launch_copy(s, st0, Tn, N);
-            std::vector<double> tbv(nst);
-            for (int m = 0; m < nst; ++m) tbv[m] = o->dt * b[m];
+            auto vin = [&](int m) -> const double* { return m == 0 ? T0 : st0 + (size_t)m * sf; };
             int m = 0;
             while (m < nst) {
                 int k = tlim::sweeps_per_launch(g, nst - m);
-                double* out = m + k == nst ? Tout : st0 + (size_t)(m + k) * stride_field;
+                double* out = m + k == nst ? Tout : st0 + (size_t)(m + k) * sf;
                 tlim::Stages stg{nullptr, tbv.data() + m, nullptr};
                 int done = -1;
                 if (k > 1)
-                    done = tlim::launch_sweeps64_keep(s, g, o->face_mean, st0 + (size_t)m * stride_field, c->rhs,
-                                                      c->Lam, c->rC, out, stg, k, o->dt,
-                                                      st0 + (size_t)m * stride_field, (int64_t)stride_field);
+                    done = tlim::launch_sweeps64_keep(s, g, o->face_mean, vin(m), T0, Lam, c->rC, out, stg, k, o->dt,
+                                                      st0 + (size_t)m * sf, (int64_t)sf);
                 if (done < 0) {
-                    double* one = m + 1 == nst ? Tout : st0 + (size_t)(m + 1) * stride_field;
+                    double* one = m + 1 == nst ? Tout : st0 + (size_t)(m + 1) * sf;
                     if (m + 1 == nst) {
-                        tlim::launch_final64(s, g, o->face_mean, st0 + (size_t)m * stride_field, c->rhs, c->Lam,
-                                             c->rC, one, o->dt, nullptr, tlim::PassSlots{});
+                        tlim::launch_final64(s, g, o->face_mean, vin(m), T0, Lam, c->rC, one, o->dt, nullptr,
+                                             tlim::PassSlots{});
                     } else {
                         tlim::StageParam sp{nullptr, tbv[m], 0.0};
-                        tlim::launch_stage64(s, g, o->face_mean, st0 + (size_t)m * stride_field, c->rhs, c->Lam,
-                                             c->rC, one, sp, o->dt);
+                        tlim::launch_stage64(s, g, o->face_mean, vin(m), T0, Lam, c->rC, one, sp, o->dt);
                     }
                     done = 1;
                 }
                 m += done;
             }
         } else {
-            const double* cur = Tn;
-            int pp = 0;
-            for (int m = 1; m < nst; ++m) {
-                tlim::StageParam sp{nullptr, o->dt * b[m - 1], 0.0};
-                tlim::launch_stage64(s, g, o->face_mean, cur, c->rhs, c->Lam, c->rC, c->vb[pp], sp, o->dt);
-                cur = c->vb[pp];
+            const double* cur = T0;
+            int pp = 0, m = 0;
+            while (m < nst) {
+                int k = tlim::sweeps_per_launch(g, nst - m);
+                bool last = m + k == nst;
+                double* nxt = last ? Tout : c->vb[pp];
+                tlim::Stages stg{nullptr, tbv.data() + m, nullptr};
+                m += tlim::launch_sweeps64(s, g, o->face_mean, cur, T0, Lam, c->rC, nxt, stg, k, last, o->dt, nullptr,
+                                           tlim::PassSlots{});
+                cur = nxt;
                 pp ^= 1;
             }
-            tlim::launch_final64(s, g, o->face_mean, cur, c->rhs, c->Lam, c->rC, Tout, o->dt, nullptr, tlim::PassSlots{});
         }
     }
 }
@@ -974,23 +1048,25 @@ tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, i
     const int64_t N = c->N;
     double k0g[2] = {0.0, 0.0};
 
+    double* Lp = (double*)(base + L.Lp);
+    bool rC_ready = false;
     tlim::launch_copy(s, mu, dL_dTN_dev, N);
+    // dL/dk0 sums accumulate on the device over all passes and steps
+    zero_rows(c, tlim::kTgtK0a, tlim::kTgtK0b + 1);
     for (int n = nsteps - 1; n >= 0; --n) {
         // T^n from the nearest checkpoint at or before n
-        int base_step = (n / ckpt_every) * ckpt_every;
-        tlim::launch_copy(s, Tpass, ckpt_dev + (size_t)(n / ckpt_every) * (size_t)N, N);
+        const int base_step = (n / ckpt_every) * ckpt_every;
+        const double* T0 = ckpt_dev + (size_t)(n / ckpt_every) * (size_t)N;
         for (int m = base_step; m < n; ++m) {
-            adj_forward_step(c, o, lam + (size_t)m * np, Tpass, nullptr, sf, stride_pass);
+            adj_forward_step(c, o, lam + (size_t)m * np, T0, Tpass, nullptr, nullptr, sf, stride_pass, rC_ready);
             tlim::launch_copy(s, Tpass, Tpass + (size_t)np * sf, N);
+            T0 = Tpass;
         }
-        // recompute step n keeping every stage
-        adj_forward_step(c, o, lam + (size_t)n * np, Tpass, stages, sf, stride_pass);
-        tlim::launch_fill(s, acc, 0.0, N);
+        // recompute step n keeping every stage and every pass's conductivities
+        adj_forward_step(c, o, lam + (size_t)n * np, T0, Tpass, stages, Lp, sf, stride_pass, rC_ready);
         for (int it = np - 1; it >= 0; --it) {
-            const double* Tit = Tpass + (size_t)it * sf;
-            tlim::launch_heat_coeffs(s, g, ph, o->alpha_eps, o->dt, Tit, c->field[TLIM_ALPHA2], c->field[TLIM_M1],
-                                     c->field[TLIM_M2], Tpass, nullptr, nullptr, c->Lam, c->rC, c->rhs, nullptr,
-                                     nullptr);
+            const double* Tit = it == 0 ? T0 : Tpass + (size_t)it * sf;
+            const double* Lam = Lp + (size_t)it * sf;
             int P = lim_P(o->dt, lam[(size_t)n * np + it]);
             std::vector<double> b = lim_params(P, lam[(size_t)n * np + it], o->order);
             int nst = (int)b.size();
@@ -1011,9 +1087,9 @@ tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, i
                         tbv[q] = o->dt * b[m - 1 - q];
                         cmv[q] = 1.0 / (1.0 + tbv[q]);
                     }
-                    int done = tlim::launch_adjoint_sweeps(s, g, o->face_mean, cur, m == nst ? 1 : 0, c->Lam, c->rC,
-                                                           st0, (int64_t)sf, m, bufs[pp], dg, gLam,
-                                                           m == nst ? 0 : 1, cmv.data(), tbv.data(), k, o->dt);
+                    int done = tlim::launch_adjoint_sweeps(s, g, o->face_mean, cur, m == nst ? 1 : 0, Lam, c->rC, st0,
+                                                           T0, (int64_t)sf, m, bufs[pp], dg, gLam, m == nst ? 0 : 1,
+                                                           cmv.data(), tbv.data(), k, o->dt);
                     if (done < 0) break;
                     psi_form = true;
                     cur = bufs[pp];
@@ -1026,23 +1102,25 @@ tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, i
                 tlim::launch_fill(s, gLam, 0.0, N);
                 for (int m = nst; m >= 1; --m) {
                     double tb = o->dt * b[m - 1];
-                    tlim::launch_adj_stage(s, g, o->face_mean, cur, st0 + (size_t)(m - 1) * sf, c->Lam, c->rC,
-                                           bufs[pp], dg, gLam, 1.0 / (1.0 + tb), tb, o->dt);
+                    const double* vprev = m == 1 ? T0 : st0 + (size_t)(m - 1) * sf;
+                    tlim::launch_adj_stage(s, g, o->face_mean, cur, vprev, Lam, c->rC, bufs[pp], dg, gLam,
+                                           1.0 / (1.0 + tb), tb, o->dt);
                     cur = bufs[pp];
                     pp ^= 1;
                 }
             }
-            // cur = dL/dv^(0) (or its psi); mu <- dL/dT^(it) through Lambda(T^(it))
-            zero_rows(c, tlim::kTgtK0a, tlim::kTgtK0b + 1);
+            // cur = dL/dv^(0) (or its psi); mu <- dL/dT^(it) through Lambda(T^(it));
+            // the last pass (reversed first) starts the step's sum acc
             tlim::launch_adj_cell(s, g, ph, Tit, c->field[TLIM_ALPHA2], gLam, dg, cur, acc, mu, it == 0 ? 1 : 0,
-                                  psi_form ? c->rC : nullptr, row(c, tlim::kTgtK0a), row(c, tlim::kTgtK0b));
-            st = read_result(c, tlim::kTgtK0a, tlim::kTgtK0b + 1);
-            if (st) return st;
-            k0g[0] += result(c, tlim::kTgtK0a);
-            k0g[1] += result(c, tlim::kTgtK0b);
+                                  psi_form ? c->rC : nullptr, row(c, tlim::kTgtK0a), row(c, tlim::kTgtK0b),
+                                  it == np - 1 ? 1 : 0);
         }
-        tlim::launch_copy(s, mu, acc, N);
+        std::swap(mu, acc);  // dL/dT^n seeds step n-1
     }
+    st = read_result(c, tlim::kTgtK0a, tlim::kTgtK0b + 1);
+    if (st) return st;
+    k0g[0] = result(c, tlim::kTgtK0a);
+    k0g[1] = result(c, tlim::kTgtK0b);
     tlim::launch_copy(s, dL_dT0_dev, mu, N);
     HIP_TRY(c, hipStreamSynchronize(s));
     HIP_TRY(c, hipGetLastError());

@@ -48,7 +48,7 @@ int launch_sweeps64_keep(hipStream_t s, const DevGrid& g, int face, const double
 // (psi^(m-1) = c_m (tau b_m - tau A) psi^(m), the forward stage operator
 // without source), for stages mt, mt-1, ..., mt-count+1 of one LIM pass:
 //   psi_in   psi^(mt) (first = 1: lambda^(mt), scaled by 1/C on load)
-//   stages   forward iterates, v^(j) at stages + j*sstride
+//   stages   forward iterates, v^(j) at stages + j*sstride (j >= 1), v^(0) at v0
 //   psi_out  psi^(mt-K)
 //   dgpsi   += sum_m c_m psi^(m)           (dL/dg = C dgpsi)
 //   gLam    += sum_m sum_f c_m tau w/2 (v_b - v_a)^(m-1) (psi_a - psi_b)^(m)
@@ -57,7 +57,8 @@ int launch_sweeps64_keep(hipStream_t s, const DevGrid& g, int face, const double
 // stages in the order they are reversed.  Returns K, or -1 where blocking
 // does not apply (3D grid, harmonic faces): nothing is launched.
 int launch_adjoint_sweeps(hipStream_t s, const DevGrid& g, int face, const double* psi_in, int first,
-                          const double* Lam, const double* rC, const double* stages, int64_t sstride, int mt,
+                          const double* Lam, const double* rC, const double* stages, const double* v0,
+                          int64_t sstride, int mt,
                           double* psi_out, double* dgpsi, double* gLam, int accumulate, const double* cm,
                           const double* tb, int count, double tau);
 

@@ -84,6 +84,7 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
     constexpr bool kGinLds = !kFloat;
     __shared__ R sG[kGinLds ? EXT_Y : 1][64];
     R v[ROWS], G[ROWS], kL[ROWS], kR[ROWS], kD[ROWS], kU[ROWS];
+    const bool same = a.v == a.G;
     R Lk[ROWS];     // cell conductivities, kept for a fused FP64 final stage
     R Ldk = 0, Luk = 0;
     {
@@ -93,8 +94,10 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
             const int yi = fold(yg0 + r, a.ny, a.pery);
             const int64_t idx = (int64_t)yi * a.nx + xi;
             v[r] = a.v[idx];
-            if constexpr (kGinLds) sG[wv * ROWS + r][lane] = a.G[idx];
-            else G[r] = a.G[idx];
+            // the first launch of a pass starts from v^(0) = T^n = g
+            const R gv = same ? v[r] : a.G[idx];
+            if constexpr (kGinLds) sG[wv * ROWS + r][lane] = gv;
+            else G[r] = gv;
             L[r] = a.Lam[idx];
             t[r] = a.tau * a.rC[idx];
         }

@@ -167,27 +167,34 @@ def test_cycle_mode_reaches_backward_euler():
     assert rel_err(fg["T1"], fo["T1"]) < 1e-13
 
 
-def test_relaxation_unequal_pinf_and_sources():
+@pytest.mark.parametrize("sources,shape", [(True, (48, 48)), (False, (48, 48)), (False, (70, 33))])
+def test_relaxation_unequal_pinf_and_sources(sources, shape):
     """Stiffened-gas phases (p_inf 6e8/0, Sec. 5 constants) out of thermal
-    equilibrium, with heat sources: relaxation, C_eff, the alpha2 update and
-    the source term against the oracle."""
+    equilibrium, with and without heat sources: relaxation, C_eff, the alpha2
+    update and the source term against the oracle.  Without sources the 2D
+    relaxation runs fused with the first pass's coefficients."""
     from oracle import oracle as orc
-    n = 48
+    nx, ny = shape
+    n = nx
     rng = np.random.default_rng(11)
     ph = [dict(gamma=4.4, pinf=6e8, cv=1606.0, q=0.0, k0=0.6, T0=300.0, npow=1.0, mu=0.0),
           dict(gamma=1.4, pinf=0.0, cv=714.0, q=0.0, k0=0.03, T0=300.0, npow=1.0, mu=0.0)]
-    x = (np.arange(n) + 0.5) / n
-    a1 = 0.5 * (1 - np.tanh((x[None, :] - 0.5 - 0.1 * np.sin(2 * np.pi * x[:, None])) / (2.0 / n)))
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    a1 = 0.5 * (1 - np.tanh((x[None, :] - 0.5 - 0.1 * np.sin(2 * np.pi * y[:, None])) / (2.0 / nx)))
     a2 = 1 - a1
     rho1 = (1e9 + 6e8) / (3.4 * 1606.0 * 293.0)
     rho2 = 1e5 / (0.4 * 714.0 * 293.0)
-    T1 = 293.0 + 20 * rng.random((n, n))
-    T2 = 293.0 + 20 * rng.random((n, n))
-    fields = dict(alpha2=a2.reshape(1, n, n), m1=(a1 * rho1).reshape(1, n, n), m2=(a2 * rho2).reshape(1, n, n),
-                  T1=T1.reshape(1, n, n), T2=T2.reshape(1, n, n),
-                  src1=(1e3 * rng.random((1, n, n))), src2=(1e2 * rng.random((1, n, n))))
+    T1 = 293.0 + 20 * rng.random((ny, nx))
+    T2 = 293.0 + 20 * rng.random((ny, nx))
+    s1 = 1e3 * rng.random((1, ny, nx))
+    s2 = 1e2 * rng.random((1, ny, nx))
+    fields = dict(alpha2=a2.reshape(1, ny, nx), m1=(a1 * rho1).reshape(1, ny, nx),
+                  m2=(a2 * rho2).reshape(1, ny, nx), T1=T1.reshape(1, ny, nx), T2=T2.reshape(1, ny, nx))
+    if sources:
+        fields.update(src1=s1, src2=s2)
     fields = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in fields.items()}
-    wl = dict(n=(n, n, 1), h=(1e-3, 1e-3, 1.0), bc=(0, 1, 0), phases=ph, fields=fields, dt_factor=50.0,
+    wl = dict(n=(nx, ny, 1), h=(1e-3, 1e-3, 1.0), bc=(0, 1, 0), phases=ph, fields=fields, dt_factor=50.0,
               passes=3, viscous=False)
     tau, _ = oracle_dt(orc, wl)
     fo, ro = run_oracle(orc, wl, tau, 2)
