@@ -12,7 +12,14 @@
 //   gLam  += c_m tau w/2 sum_f (v_b - v_a)^(m-1) (psi_a - psi_b)^(m)
 // where dL/dLambda_f = c_m tau w (v_b - v_a)(psi_a - psi_b) and the arithmetic
 // face mean gives dLambda_f/dLambda_a = 1/2.  The forward iterate v^(m-1) of
-// every stage is read from the stored stages (one field per stage).
+// every stage is read from the stored stages (one field per stage), one
+// stage ahead of its use.
+//
+// The launch that reaches v^(0) can also finish the pass at its output
+// cells (AdjCell): dL/dT^n += C (dgpsi + psi^(0)), the chain through the
+// conductivity of the lagged iterate mu = gLam dLambda/dT(T^(it)) (added to
+// dL/dT^n too for the first pass, whose iterate is T^n), and the two dL/dk0
+// sums of the pass.
 #include <hip/hip_runtime.h>
 
 #include "tlim_device.h"
@@ -22,6 +29,7 @@ namespace tlim {
 
 namespace {
 
+using phys::powlaw;
 using tb::EXT_Y;
 using tb::fmean;
 using tb::fold;
@@ -46,6 +54,7 @@ struct AdjArgs {
     double wx, wy, tau;
     int K, tiles_x, ox, oy;
     double cm[KMAX], tb[KMAX];
+    AdjCell cell;  // cell.acc != NULL: finish the pass (this launch reaches v^(0))
 };
 
 __global__ void __launch_bounds__(64 * WAVES, 2) k_tb2d_adj(AdjArgs a) {
@@ -100,14 +109,24 @@ __global__ void __launch_bounds__(64 * WAVES, 2) k_tb2d_adj(AdjArgs a) {
         }
     }
     const double gxl = fL ? hx : 0.0, gxr = fR ? hx : 0.0;
+    // forward iterate v^(m-1) of stage m = mt - s, loaded one stage ahead
+    auto vsrc = [&](int s) { const int j = a.mt - 1 - s; return j == 0 ? a.v0 : a.stages + (int64_t)j * a.sstride; };
+    double vnext[ROWS];
+    {
+        const double* p = vsrc(0);
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) vnext[r] = p[idx[r]];
+    }
     for (int s = 0; s < K; ++s) {
         const int buf = (s + 1) & 1;
-        // forward iterate v^(m-1) of stage m = mt - s
-        const int j = a.mt - 1 - s;
-        const double* vsrc = j == 0 ? a.v0 : a.stages + (int64_t)j * a.sstride;
         double v[ROWS];
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) v[r] = vsrc[idx[r]];
+        for (int r = 0; r < ROWS; ++r) v[r] = vnext[r];
+        if (s + 1 < K) {
+            const double* p = vsrc(s + 1);
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) vnext[r] = p[idx[r]];
+        }
         sh_lo[buf][wv][lane] = psi[0];
         sh_hi[buf][wv][lane] = psi[ROWS - 1];
         sv_lo[buf][wv][lane] = v[0];
@@ -137,6 +156,8 @@ __global__ void __launch_bounds__(64 * WAVES, 2) k_tb2d_adj(AdjArgs a) {
             prev = c;
         }
     }
+    const AdjCell& cl = a.cell;
+    double s0 = 0.0, s1 = 0.0;
     if (lane >= K && lane < 64 - K && xg < a.nx) {
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
@@ -144,10 +165,41 @@ __global__ void __launch_bounds__(64 * WAVES, 2) k_tb2d_adj(AdjArgs a) {
             const int y = yg0 + r;
             if (row >= K && row < EXT_Y - K && y < a.ny) {
                 const int64_t o = (int64_t)y * a.nx + xg;
-                a.psi_out[o] = psi[r];
-                a.dgpsi[o] = dga[r];
-                a.gLam[o] = gla[r];
+                if (cl.acc) {
+                    const DevPhases& ph = cl.ph;
+                    const double t = cl.Tit[o], a2 = cl.alpha2[o], a1 = 1.0 - a2, gl = gla[r];
+                    const double acc0 = cl.init ? 0.0 : cl.acc[o];
+                    double acc_a = acc0 + (dga[r] + psi[r]) / a.rC[o];
+                    const double x0 = t * ph.invT0[0], x1 = t * ph.invT0[1];
+                    s0 += gl * a1 * powlaw(x0, ph.npow[0]);
+                    s1 += gl * a2 * powlaw(x1, ph.npow[1]);
+                    double dL = 0.0;
+                    if (ph.npow[0] != 0.0)
+                        dL += a1 * ph.k0[0] * ph.npow[0] * powlaw(x0, ph.npow[0] - 1.0) * ph.invT0[0];
+                    if (ph.npow[1] != 0.0)
+                        dL += a2 * ph.k0[1] * ph.npow[1] * powlaw(x1, ph.npow[1] - 1.0) * ph.invT0[1];
+                    const double mu = gl * dL;
+                    cl.mu[o] = mu;
+                    cl.acc[o] = cl.first_pass ? acc_a + mu : acc_a;
+                } else {
+                    a.psi_out[o] = psi[r];
+                    a.dgpsi[o] = dga[r];
+                    a.gLam[o] = gla[r];
+                }
             }
+        }
+    }
+    if (cl.acc) {
+        // wave sums, then one atomic per wave into a slot of each row
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            s0 += __shfl_xor(s0, o, 64);
+            s1 += __shfl_xor(s1, o, 64);
+        }
+        if (lane == 0) {
+            const int sl = (int)(((int64_t)blockIdx.x * WAVES + wv) % kSlots);
+            atomicAdd(cl.k0a + sl, s0);
+            atomicAdd(cl.k0b + sl, s1);
         }
     }
 }
@@ -158,10 +210,11 @@ int launch_adjoint_sweeps(hipStream_t s, const DevGrid& g, int face, const doubl
                           const double* Lam, const double* rC, const double* stages, const double* v0,
                           int64_t sstride, int mt,
                           double* psi_out, double* dgpsi, double* gLam, int accumulate, const double* cm,
-                          const double* tb, int count, double tau) {
+                          const double* tb, int count, double tau, const AdjCell* cell) {
     if (!(g.nz == 1 && g.ny >= EXT_Y / 2 && face == 0)) return -1;
     AdjArgs a{};
     const int K = count < KMAX ? count : KMAX;
+    if (cell && mt - K == 0) a.cell = *cell;
     a.psi_in = psi_in;
     a.Lam = Lam;
     a.rC = rC;

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -59,6 +60,7 @@ struct tlim_ctx {
     // to restore when the step's final readback consumes its rows.
     int clean_rows, clean_keep;
     hipEvent_t ev[kMaxEvents];
+    hipEvent_t ev_sync;  // readback completion (polled)
     // Schedule history for P prediction: P of each Picard pass of the last
     // completed step (hist_passes = 0: none).
     int hist_passes;
@@ -373,7 +375,18 @@ tlim_status read_result(tlim_ctx* c, int t0, int t1, bool consume = false) {
         tlim::launch_collect(c->stream, c->acc, c->res_dev, t0, t1, consume ? 1 : 0);
         HIP_TRY(c, hipMemcpyAsync(c->res_host, c->res_dev, sizeof(PassResult), hipMemcpyDeviceToHost, c->stream));
     }
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    // The readbacks sit on the critical path between steps: poll the
+    // completion for up to ~2 ms before falling back to a blocking wait.
+    HIP_TRY(c, hipEventRecord(c->ev_sync, c->stream));
+    hipError_t e = hipErrorNotReady;
+    const auto t0c = std::chrono::steady_clock::now();
+    while ((e = hipEventQuery(c->ev_sync)) == hipErrorNotReady) {
+        if (std::chrono::steady_clock::now() - t0c > std::chrono::microseconds(2000)) {
+            e = hipEventSynchronize(c->ev_sync);
+            break;
+        }
+    }
+    if (e != hipSuccess) return fail(c, TLIM_E_HIP, "readback: %s", hipGetErrorString(e));
     return TLIM_OK;
 }
 
@@ -670,6 +683,12 @@ tlim_status tlim_create(const tlim_grid* grid, int32_t precision, void* hip_stre
             return TLIM_E_HIP;
         }
     }
+    if (hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming) != hipSuccess) {
+        for (int j = 0; j < kMaxEvents; ++j) (void)hipEventDestroy(c->ev[j]);
+        (void)hipHostFree(c->res_host);
+        delete c;
+        return TLIM_E_HIP;
+    }
     *out = c;
     return TLIM_OK;
 }
@@ -677,6 +696,7 @@ tlim_status tlim_create(const tlim_grid* grid, int32_t precision, void* hip_stre
 tlim_status tlim_destroy(tlim_ctx* c) {
     if (!c) return TLIM_OK;
     for (int i = 0; i < kMaxEvents; ++i) (void)hipEventDestroy(c->ev[i]);
+    (void)hipEventDestroy(c->ev_sync);
     (void)hipHostFree(c->res_host);
     delete c;
     return TLIM_OK;
@@ -1074,8 +1094,11 @@ tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, i
             double* bufs[2] = {lamA, lamB};
             int pp = 0;
             const double* st0 = stages + (size_t)it * stride_pass;
-            // blocked reverse stages in psi = C^-1 lambda form where the grid allows
-            bool psi_form = false;
+            // blocked reverse stages in psi = C^-1 lambda form where the grid
+            // allows; the launch that reaches v^(0) also finishes the pass
+            bool psi_form = false, cell_done = false;
+            tlim::AdjCell cell{ph, Tit, c->field[TLIM_ALPHA2], acc, mu, it == np - 1 ? 1 : 0, it == 0 ? 1 : 0,
+                               row(c, tlim::kTgtK0a), row(c, tlim::kTgtK0b)};
             {
                 std::vector<double> cmv, tbv;
                 int m = nst;
@@ -1089,9 +1112,10 @@ tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, i
                     }
                     int done = tlim::launch_adjoint_sweeps(s, g, o->face_mean, cur, m == nst ? 1 : 0, Lam, c->rC, st0,
                                                            T0, (int64_t)sf, m, bufs[pp], dg, gLam, m == nst ? 0 : 1,
-                                                           cmv.data(), tbv.data(), k, o->dt);
+                                                           cmv.data(), tbv.data(), k, o->dt, &cell);
                     if (done < 0) break;
                     psi_form = true;
+                    if (m - done == 0) cell_done = true;
                     cur = bufs[pp];
                     pp ^= 1;
                     m -= done;
@@ -1111,9 +1135,10 @@ tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, i
             }
             // cur = dL/dv^(0) (or its psi); mu <- dL/dT^(it) through Lambda(T^(it));
             // the last pass (reversed first) starts the step's sum acc
-            tlim::launch_adj_cell(s, g, ph, Tit, c->field[TLIM_ALPHA2], gLam, dg, cur, acc, mu, it == 0 ? 1 : 0,
-                                  psi_form ? c->rC : nullptr, row(c, tlim::kTgtK0a), row(c, tlim::kTgtK0b),
-                                  it == np - 1 ? 1 : 0);
+            if (!cell_done)
+                tlim::launch_adj_cell(s, g, ph, Tit, c->field[TLIM_ALPHA2], gLam, dg, cur, acc, mu, it == 0 ? 1 : 0,
+                                      psi_form ? c->rC : nullptr, row(c, tlim::kTgtK0a), row(c, tlim::kTgtK0b),
+                                      it == np - 1 ? 1 : 0);
         }
         std::swap(mu, acc);  // dL/dT^n seeds step n-1
     }

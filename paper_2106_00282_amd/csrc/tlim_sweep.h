@@ -54,12 +54,25 @@ int launch_sweeps64_keep(hipStream_t s, const DevGrid& g, int face, const double
 //   gLam    += sum_m sum_f c_m tau w/2 (v_b - v_a)^(m-1) (psi_a - psi_b)^(m)
 //             (dL/dLambda_cell through arithmetic face means)
 // accumulate = 0 starts the sums at zero.  cm, tb: c_m and tau*b_m of the K
-// stages in the order they are reversed.  Returns K, or -1 where blocking
-// does not apply (3D grid, harmonic faces): nothing is launched.
+// stages in the order they are reversed.  When the launch reaches v^(0)
+// (mt == K) and cell != NULL it finishes the pass as launch_adj_cell does
+// (psi form) instead of writing psi_out, dgpsi and gLam.  Returns K, or -1
+// where blocking does not apply (3D grid, harmonic faces): nothing is
+// launched.
+struct AdjCell {
+    DevPhases ph;
+    const double* Tit;     // T^(it), the lagged iterate of the pass
+    const double* alpha2;
+    double* acc;           // dL/dT^n accumulator
+    double* mu;            // out: dL/dT^(it) through Lambda(T^(it))
+    int init, first_pass;  // as launch_adj_cell
+    double* k0a;           // accumulator rows of the dL/dk0 sums
+    double* k0b;
+};
 int launch_adjoint_sweeps(hipStream_t s, const DevGrid& g, int face, const double* psi_in, int first,
                           const double* Lam, const double* rC, const double* stages, const double* v0,
                           int64_t sstride, int mt,
                           double* psi_out, double* dgpsi, double* gLam, int accumulate, const double* cm,
-                          const double* tb, int count, double tau);
+                          const double* tb, int count, double tau, const AdjCell* cell = nullptr);
 
 }  // namespace tlim
