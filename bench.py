@@ -82,6 +82,9 @@ def run_steps(solver, wl, opts, steps, reset=True):
         st = solver.advance_raw(oc)
         if st != 0:
             raise RuntimeError(f"tlim_advance returned {st}")
+    st = solver.finish()  # the last step's readback is checked inside the timed region
+    if st != 0:
+        raise RuntimeError(f"tlim_finish returned {st}")
     torch.cuda.synchronize()
     return time.perf_counter() - t0
 

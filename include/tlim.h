@@ -122,6 +122,8 @@ typedef struct {
                                              and confirmed (no per-pass readback) */
     int32_t mispredicted;                 /* 1: a predicted P was wrong; the heat passes were rerun
                                              with one readback per pass (sweeps counts the rerun only) */
+    int64_t pipelined_steps;              /* context totals so far: steps run pipelined (see */
+    int64_t pipeline_redos;               /* tlim_advance) and pipelined steps redone */
 } tlim_step_report;
 
 typedef struct tlim_ctx tlim_ctx;
@@ -154,8 +156,9 @@ tlim_status tlim_set_phase(tlim_ctx* ctx, int32_t k, const tlim_phase* phase);
  * only for the viscous sub-step. */
 tlim_status tlim_set_field(tlim_ctx* ctx, int32_t field, const double* src_dev);
 
-/* Copy a field out of the context into caller device memory. */
-tlim_status tlim_get_field(const tlim_ctx* ctx, int32_t field, double* dst_dev);
+/* Copy a field out of the context into caller device memory (a pending
+ * pipelined step is completed first, see tlim_advance). */
+tlim_status tlim_get_field(tlim_ctx* ctx, int32_t field, double* dst_dev);
 
 /* Gershgorin bound lambda_G = max_i 2 d_i of the heat operator A = C^-1 D
  * (Sec. 3.2 needs lambda_max of L_h; D from eq. qk_dis) for the current
@@ -174,8 +177,23 @@ tlim_status tlim_spectral_bound(tlim_ctx* ctx, int32_t face_mean, double alpha_e
  * mode), P of every pass is predicted from that step, the stages read
  * lambda_max from device memory, and one readback at the end confirms the
  * predictions (a wrong one rolls the heat part back and reruns it with one
- * readback per pass).  Otherwise it synchronises once per Picard pass. */
+ * readback per pass).  Otherwise it synchronises once per Picard pass.
+ *
+ * Pipelining.  A predicted step with report == NULL, no viscous part, no
+ * timing, equal p_inf, on a 2D grid without sources, returns as soon as it
+ * is enqueued; its readback is checked by the next call on the context,
+ * after that call has enqueued its own step, so consecutive steps run back
+ * to back on the device.  A wrong prediction found then redoes the checked
+ * step (and reruns the newer one with its own readback); a non-finite or
+ * non-positive temperature of the checked step is returned by that call as
+ * TLIM_E_NUMERIC.  Every other entry point, and tlim_finish, completes the
+ * pending step first. */
 tlim_status tlim_advance(tlim_ctx* ctx, const tlim_step_opts* opts, tlim_step_report* report);
+
+/* Complete a pending pipelined step (see tlim_advance): wait for its
+ * readback, redo it if its schedule was mispredicted, and return its status
+ * (TLIM_OK when nothing is pending).  Synchronises. */
+tlim_status tlim_finish(tlim_ctx* ctx);
 
 /* Forward run of nsteps heat steps with checkpoints for the adjoint: T^n is
  * copied to ckpt_dev + (n / ckpt_every) * N before every step n with

@@ -54,8 +54,24 @@ struct tlim_ctx {
     float *Lam32, *rC32, *q32, *wb[2];
     double* acc;           // reduction rows: kTargets x kSlots
     PassResult* res_dev;   // folded results (one double per target)
-    PassResult* res_host;  // pinned copy
+    PassResult* res_host;  // pinned copy (the current block of res_blk)
     PassResult* res_host_dev;  // device address of res_host (NULL: copy from res_dev)
+    PassResult* res_blk[2];    // two pinned result blocks: a pipelined step keeps its own
+    PassResult* res_blk_dev[2];
+    int res_cur;
+    double* Tn_buf[2];         // T^n of consecutive steps alternate between two arrays
+    // A predicted step enqueued without waiting for its readback (pipelined
+    // mode); it is verified by the next call.
+    bool pending;
+    struct Pending {
+        tlim_step_opts o;
+        int P_used[TLIM_MAX_PASSES];
+        int blk;                // its result block
+        double* Tn;             // its relaxed T
+        double* alpha2;         // its relaxed alpha2 (the alpha2 field during its passes)
+        double* alpha2_other;   // the other alpha2 array
+    } pend;
+    hipEvent_t ev_pend[2];
     // Leading rows of the Picard-pass targets known to be zero, and the count
     // to restore when the step's final readback consumes its rows.
     int clean_rows, clean_keep;
@@ -65,9 +81,16 @@ struct tlim_ctx {
     // completed step (hist_passes = 0: none).
     int hist_passes;
     int hist_P[TLIM_MAX_PASSES];
+    // lambda_G per pass of the last verified step (hist_nlam = 1: present)
+    double hist_lam[TLIM_MAX_PASSES];
+    int hist_nlam;
+    // Consecutive verified steps whose passes all ran the P of the step
+    // before's last pass (a schedule settled enough to pipeline).
+    int hist_steady;
     // After a step T_2 = T_1 everywhere: the T2 field then reads through T1.
     bool t2_alias;
     int64_t predict_misses;
+    int64_t pipelined_steps, pipeline_redos;
     std::string err;
 };
 
@@ -94,7 +117,7 @@ tlim_status fail(tlim_ctx* c, tlim_status s, const char* fmt, ...) {
 // Layout of the workspace: byte offsets of every array (all 256-aligned).
 struct Layout {
     size_t field[TLIM_NFIELDS];
-    size_t Tn, Tnew, a2n, Lam, rC, rhs, vb[2], acc, res;
+    size_t Tn, Tn2, Tnew, a2n, Lam, rC, rhs, vb[2], acc, res;
     size_t Lam32, rC32, q32, wb[2];
     size_t total;
 };
@@ -108,7 +131,7 @@ Layout layout_of(const int64_t n[3], int precision) {
         L.field[i] = off;
         off += d;
     }
-    size_t* dd[] = {&L.Tn, &L.Tnew, &L.a2n, &L.Lam, &L.rC, &L.rhs, &L.vb[0], &L.vb[1]};
+    size_t* dd[] = {&L.Tn, &L.Tn2, &L.Tnew, &L.a2n, &L.Lam, &L.rC, &L.rhs, &L.vb[0], &L.vb[1]};
     for (size_t* p : dd) {
         *p = off;
         off += d;
@@ -242,26 +265,39 @@ tlim_status check_opts(tlim_ctx* c, const tlim_step_opts* o) {
 
 // ---------------------------------------------------------- one LIM pass
 
+// Kernel time of the sweep launches (time_sweeps): a pair of events around
+// every launch; when the pairs run out the elapsed times so far are folded
+// (which waits for them) and the events are reused.
 struct Timer {
     tlim_ctx* c;
     bool on;
     int used = 0;
+    double folded_ms = 0.0;
     void start() {
-        if (on && used + 1 < kMaxEvents) (void)hipEventRecord(c->ev[used], c->stream);
+        if (!on) return;
+        if (used + 1 >= kMaxEvents) fold();
+        (void)hipEventRecord(c->ev[used], c->stream);
     }
     void stop() {
-        if (on && used + 1 < kMaxEvents) {
-            (void)hipEventRecord(c->ev[used + 1], c->stream);
-            used += 2;
-        }
+        if (!on) return;
+        (void)hipEventRecord(c->ev[used + 1], c->stream);
+        used += 2;
     }
-    double elapsed_ms() {
-        double t = 0.0;
+    void fold() {
+        if (used > 0) (void)hipEventSynchronize(c->ev[used - 1]);
         for (int i = 0; i + 1 < used; i += 2) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess) t += ms;
+            if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess) folded_ms += ms;
         }
-        return t;
+        used = 0;
+    }
+    void reset() {
+        used = 0;
+        folded_ms = 0.0;
+    }
+    double elapsed_ms() {
+        fold();
+        return folded_ms;
     }
 };
 
@@ -326,7 +362,6 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
                   SweepCount& sc, bool have_q = false) {
     const int nst = ps.nst;
     hipStream_t s = c->stream;
-    tm.start();
     if (c->precision == TLIM_FP32) {
         if (!have_q) tlim::launch_q32(s, g, face, rhs, v0, c->Lam32, c->rC32, tau, c->q32, c->wb[0]);
         // 2P-2 float stages on the correction, the final one in double; the
@@ -337,8 +372,10 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
             int k = tlim::sweeps_per_launch(g, nst - m);
             bool last = m + k == nst;
             float* nxt = cur == c->wb[0] ? c->wb[1] : c->wb[0];
+            tm.start();
             int done = tlim::launch_sweeps32(s, g, face, cur, c->q32, c->Lam32, c->rC32, nxt, ps.at(m), k, last, tau,
                                              rhs, c->rC, out, Tit, slots);
+            tm.stop();
             cur = nxt;
             m += done;
             sc.launches++;
@@ -353,8 +390,10 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
             int k = tlim::sweeps_per_launch(g, nst - m);
             bool last = m + k == nst;
             double* nxt = last ? out : c->vb[pp];
+            tm.start();
             int done = tlim::launch_sweeps64(s, g, face, cur, rhs, c->Lam, c->rC, nxt, ps.at(m), k, last, tau, Tit,
                                              slots);
+            tm.stop();
             cur = nxt;
             pp ^= 1;
             m += done;
@@ -362,7 +401,6 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
         }
     }
     sc.sweeps += nst;
-    tm.stop();
 }
 
 // Fold the rows [t0, t1) and bring the results to the host (synchronises).
@@ -471,15 +509,15 @@ tlim_status cycle_pass(tlim_ctx* c, const DevGrid& g, const tlim_step_opts* o, i
     int cyc = 0;
     double r = 0.0;
     while (cyc < o->max_cycles) {
-        tm.start();
         for (int m = 0; m < s_stages; ++m) {
             tlim::StageParam sp{nullptr, o->dt * b[m], 0.0};
+            tm.start();
             tlim::launch_stage64(c->stream, g, o->face_mean, c->vb[cur], c->g_heat, c->Lam, c->rC, c->vb[cur ^ 1],
                                  sp, o->dt);
+            tm.stop();
             cur ^= 1;
             sc.launches++;
         }
-        tm.stop();
         sc.sweeps += s_stages;
         ++cyc;
         zero_rows(c, tlim::kTgtRR, tlim::kTgtGG + 1);
@@ -514,6 +552,31 @@ struct HeatOutcome {
 // P of each pass is taken from the previous step and the stages read lambda_G
 // from device memory; the predictions are checked after one readback at the
 // end (mispredicted = true means the caller must roll back and rerun).
+// After a verified step with lambda_G per pass lam[0..passes), predict P of
+// every pass of the next step.  Its first pass starts from T^{n+1}, the
+// output of this step's last pass, whose conductivities are closest to this
+// step's last lagged iterate: it gets the bound of this step's last pass.
+// Its later passes follow the same pass of this step, extrapolated with the
+// change since the step before when that change is small (the bound drifts
+// as T smooths; a jump, e.g. from new material constants, is not a trend).
+void record_schedule(tlim_ctx* c, int passes, const double* lam, double dt) {
+    bool steady = c->hist_passes == passes;
+    for (int i = 0; i < passes && steady; ++i) steady = lim_P(dt, lam[i]) == c->hist_P[i];
+    c->hist_steady = steady ? c->hist_steady + 1 : 0;
+    const bool have_prev = c->hist_nlam >= 1 && c->hist_passes == passes;
+    for (int i = 0; i < passes; ++i) {
+        double l = i == 0 ? lam[passes - 1] : lam[i];
+        if (i > 0 && have_prev) {
+            const double d = lam[i] - c->hist_lam[i];
+            if (std::fabs(d) <= 0.1 * lam[i]) l += d;
+        }
+        c->hist_P[i] = lim_P(dt, l > 0.0 ? l : 0.0);
+    }
+    for (int i = 0; i < passes; ++i) c->hist_lam[i] = lam[i];
+    c->hist_nlam = 1;
+    c->hist_passes = passes;
+}
+
 // pass0_done: the coefficients and bound of the first pass were built with
 // the relaxation (and the accumulator rows zeroed before it).
 tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_step_report* rep, Timer& tm,
@@ -612,9 +675,11 @@ tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_st
         // last pass, whose conductivities are closest to this step's last
         // lagged iterate: predict every pass of the next step with the P of
         // this step's last pass.
-        c->hist_passes = out.passes_run;
-        const int Plast = lim_P(o->dt, result(c, tlim::tgt_lam(out.passes_run - 1)));
-        for (int i = 0; i < out.passes_run; ++i) c->hist_P[i] = Plast;
+        double lv[TLIM_MAX_PASSES];
+        for (int i = 0; i < out.passes_run; ++i) lv[i] = result(c, tlim::tgt_lam(i));
+        record_schedule(c, out.passes_run, lv, o->dt);
+    } else {
+        c->hist_steady = 0;
     }
     return TLIM_OK;
 }
@@ -624,6 +689,10 @@ tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_st
 // =================================================================== C ABI
 
 extern "C" {
+
+namespace {
+tlim_status resolve(tlim_ctx* c);
+}  // namespace
 
 const char* tlim_status_str(tlim_status s) {
     switch (s) {
@@ -666,26 +735,34 @@ tlim_status tlim_create(const tlim_grid* grid, int32_t precision, void* hip_stre
         delete c;
         return TLIM_E_HIP;
     }
-    if (hipHostMalloc((void**)&c->res_host, sizeof(PassResult), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->res_blk[0], 2 * sizeof(PassResult), hipHostMallocDefault) != hipSuccess) {
         delete c;
         return TLIM_E_HIP;
     }
-    if (hipHostGetDevicePointer((void**)&c->res_host_dev, c->res_host, 0) != hipSuccess) {
-        c->res_host_dev = nullptr;
+    c->res_blk[1] = c->res_blk[0] + 1;
+    if (hipHostGetDevicePointer((void**)&c->res_blk_dev[0], c->res_blk[0], 0) != hipSuccess) {
+        c->res_blk_dev[0] = nullptr;
         (void)hipGetLastError();
     }
+    c->res_blk_dev[1] = c->res_blk_dev[0] ? c->res_blk_dev[0] + 1 : nullptr;
+    c->res_cur = 0;
+    c->res_host = c->res_blk[0];
+    c->res_host_dev = c->res_blk_dev[0];
     c->clean_rows = c->clean_keep = 0;
+    c->pending = false;
     for (int i = 0; i < kMaxEvents; ++i) {
         if (hipEventCreate(&c->ev[i]) != hipSuccess) {
             for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->ev[j]);
-            (void)hipHostFree(c->res_host);
+            (void)hipHostFree(c->res_blk[0]);
             delete c;
             return TLIM_E_HIP;
         }
     }
-    if (hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming) != hipSuccess) {
+    if (hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_pend[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_pend[1], hipEventDisableTiming) != hipSuccess) {
         for (int j = 0; j < kMaxEvents; ++j) (void)hipEventDestroy(c->ev[j]);
-        (void)hipHostFree(c->res_host);
+        (void)hipHostFree(c->res_blk[0]);
         delete c;
         return TLIM_E_HIP;
     }
@@ -695,9 +772,12 @@ tlim_status tlim_create(const tlim_grid* grid, int32_t precision, void* hip_stre
 
 tlim_status tlim_destroy(tlim_ctx* c) {
     if (!c) return TLIM_OK;
+    (void)resolve(c);
     for (int i = 0; i < kMaxEvents; ++i) (void)hipEventDestroy(c->ev[i]);
     (void)hipEventDestroy(c->ev_sync);
-    (void)hipHostFree(c->res_host);
+    (void)hipEventDestroy(c->ev_pend[0]);
+    (void)hipEventDestroy(c->ev_pend[1]);
+    (void)hipHostFree(c->res_blk[0]);
     delete c;
     return TLIM_OK;
 }
@@ -710,6 +790,8 @@ tlim_status tlim_workspace_bytes(const tlim_ctx* c, size_t* bytes) {
 
 tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
     if (!c) return TLIM_E_ARG;
+    tlim_status pst = resolve(c);
+    if (pst) return pst;
     if (!dev_ptr || ((uintptr_t)dev_ptr % kAlign) != 0) return fail(c, TLIM_E_ARG, "workspace NULL or not 256-byte aligned");
     Layout L = layout_of(c->n, c->precision);
     if (bytes < L.total) return fail(c, TLIM_E_NOMEM, "workspace %zu bytes < %zu required", bytes, L.total);
@@ -721,6 +803,8 @@ tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
         c->fset[i] = false;
     }
     c->Tn = (double*)(base + L.Tn);
+    c->Tn_buf[0] = c->Tn;
+    c->Tn_buf[1] = (double*)(base + L.Tn2);
     c->Tnew = (double*)(base + L.Tnew);
     c->a2n = (double*)(base + L.a2n);
     c->Lam = (double*)(base + L.Lam);
@@ -732,6 +816,8 @@ tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
     c->res_dev = (PassResult*)(base + L.res);
     c->t2_alias = false;
     c->hist_passes = 0;
+    c->hist_steady = 0;
+    c->hist_nlam = 0;
     c->clean_rows = c->clean_keep = 0;  // the new accumulator is not known to be zero
     if (c->precision == TLIM_FP32) {
         c->Lam32 = (float*)(base + L.Lam32);
@@ -747,6 +833,8 @@ tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
 
 tlim_status tlim_set_phase(tlim_ctx* c, int32_t k, const tlim_phase* p) {
     if (!c) return TLIM_E_ARG;
+    tlim_status pst = resolve(c);
+    if (pst) return pst;
     if (k < 0 || k > 1 || !p) return fail(c, TLIM_E_ARG, "phase index must be 0 or 1");
     if (!(p->gamma > 1.0) || !(p->cv > 0.0) || !(p->k0 >= 0.0) || !(p->T0 > 0.0) || !(p->mu >= 0.0) ||
         !std::isfinite(p->pinf) || !std::isfinite(p->npow))
@@ -758,6 +846,8 @@ tlim_status tlim_set_phase(tlim_ctx* c, int32_t k, const tlim_phase* p) {
 
 tlim_status tlim_set_field(tlim_ctx* c, int32_t f, const double* src) {
     if (!c) return TLIM_E_ARG;
+    tlim_status pst = resolve(c);
+    if (pst) return pst;
     if (f < 0 || f >= TLIM_NFIELDS || !src) return fail(c, TLIM_E_ARG, "bad field index or NULL source");
     if (!c->ws) return fail(c, TLIM_E_STATE, "no workspace bound");
     if (c->t2_alias && (f == TLIM_T1 || f == TLIM_T2)) {
@@ -770,9 +860,10 @@ tlim_status tlim_set_field(tlim_ctx* c, int32_t f, const double* src) {
     return TLIM_OK;
 }
 
-tlim_status tlim_get_field(const tlim_ctx* cc, int32_t f, double* dst) {
-    tlim_ctx* c = const_cast<tlim_ctx*>(cc);
+tlim_status tlim_get_field(tlim_ctx* c, int32_t f, double* dst) {
     if (!c) return TLIM_E_ARG;
+    tlim_status pst = resolve(c);
+    if (pst) return pst;
     if (f < 0 || f >= TLIM_NFIELDS || !dst) return fail(c, TLIM_E_ARG, "bad field index or NULL destination");
     if (!c->ws || !c->fset[f]) return fail(c, TLIM_E_STATE, "field %d not set", f);
     const double* src = f == TLIM_T2 ? T2_ptr(c) : c->field[f];
@@ -782,6 +873,8 @@ tlim_status tlim_get_field(const tlim_ctx* cc, int32_t f, double* dst) {
 
 tlim_status tlim_spectral_bound(tlim_ctx* c, int32_t face_mean, double alpha_eps, double* lambda_out) {
     if (!c) return TLIM_E_ARG;
+    tlim_status pst = resolve(c);
+    if (pst) return pst;
     if (!lambda_out || face_mean < 0 || face_mean > 1 || alpha_eps < 0.0 || alpha_eps >= 0.5)
         return fail(c, TLIM_E_ARG, "bad arguments");
     tlim_status st = check_ready(c);
@@ -804,12 +897,43 @@ tlim_status tlim_spectral_bound(tlim_ctx* c, int32_t face_mean, double alpha_eps
     return TLIM_OK;
 }
 
-tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep) {
-    if (!c) return TLIM_E_ARG;
-    tlim_status st = check_opts(c, o);
-    if (st) return st;
-    st = check_ready(c);
-    if (st) return st;
+namespace {
+
+// Temperature relaxation at the start of a step (Sec. 3.4.1).  On 2D grids
+// without sources it is fused with the first pass's coefficients and bound
+// (returns true); the relaxed state goes to Tn and a2n, and a2n becomes the
+// alpha2 field.  T1 is not written: every pass starts from Tn and the last
+// one writes T1.  T^n alternates between two arrays from step to step, so a
+// step's T^n outlives the next step's enqueue.
+bool relax_step(tlim_ctx* c, const tlim_step_opts* o) {
+    hipStream_t s = c->stream;
+    DevGrid g = dev_grid(c, kUnit);
+    DevPhases ph = dev_phases(c);
+    const bool B1 = c->phase[0].pinf != c->phase[1].pinf;
+    c->Tn = c->Tn == c->Tn_buf[0] ? c->Tn_buf[1] : c->Tn_buf[0];
+    bool pass0_done = false;
+    if (fast_coeffs(c, g)) {
+        begin_pass_rows(c, o->passes);
+        const bool need_lam64 = c->precision == TLIM_FP64 || o->cycle_mode;
+        tlim::launch_coeffs2d(s, g, ph, o->alpha_eps, o->dt, o->face_mean, c->field[TLIM_T1], c->field[TLIM_ALPHA2],
+                              c->field[TLIM_M1], c->field[TLIM_M2], nullptr, 1, need_lam64 ? c->Lam : nullptr, c->rC,
+                              c->Lam32, c->rC32, c->q32, c->wb[0], row(c, tlim::tgt_lam(0)), T2_ptr(c), c->Tn,
+                              c->a2n);
+        std::swap(c->field[TLIM_ALPHA2], c->a2n);
+        if (B1) tlim::launch_copy(s, c->a2n, c->field[TLIM_ALPHA2], c->N);  // kept for a rollback
+        c->g_heat = c->Tn;
+        pass0_done = true;
+    } else {
+        tlim::launch_relax(s, g, ph, o->alpha_eps, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2],
+                           c->field[TLIM_T1], T2_ptr(c), c->Tn, B1 ? c->a2n : nullptr);
+    }
+    c->t2_alias = true;  // T_1 = T_2 from here on
+    return pass0_done;
+}
+
+// One step with a readback of its own (all modes).
+tlim_status advance_sync(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep) {
+    tlim_status st = TLIM_OK;
     if (rep) std::memset(rep, 0, sizeof(*rep));
     hipStream_t s = c->stream;
     DevGrid g = dev_grid(c, kUnit);
@@ -832,27 +956,7 @@ tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
         st = viscous(c, o, rep, tm, sc);
         if (st) return st;
     }
-    // Relaxation.  On 2D grids without sources it is fused with the first
-    // pass's coefficients and bound; the relaxed state goes to Tn and a2n,
-    // and a2n becomes the alpha2 field.  T1 is not written: every pass
-    // starts from Tn and the last one writes T1.
-    bool pass0_done = false;
-    if (fast_coeffs(c, g)) {
-        begin_pass_rows(c, o->passes);
-        const bool need_lam64 = c->precision == TLIM_FP64 || o->cycle_mode;
-        tlim::launch_coeffs2d(s, g, ph, o->alpha_eps, o->dt, o->face_mean, c->field[TLIM_T1], c->field[TLIM_ALPHA2],
-                              c->field[TLIM_M1], c->field[TLIM_M2], nullptr, 1, need_lam64 ? c->Lam : nullptr, c->rC,
-                              c->Lam32, c->rC32, c->q32, c->wb[0], row(c, tlim::tgt_lam(0)), T2_ptr(c), c->Tn,
-                              c->a2n);
-        std::swap(c->field[TLIM_ALPHA2], c->a2n);
-        if (B1) tlim::launch_copy(s, c->a2n, c->field[TLIM_ALPHA2], c->N);  // kept for a rollback
-        c->g_heat = c->Tn;
-        pass0_done = true;
-    } else {
-        tlim::launch_relax(s, g, ph, o->alpha_eps, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2],
-                           c->field[TLIM_T1], T2_ptr(c), c->Tn, B1 ? c->a2n : nullptr);
-    }
-    c->t2_alias = true;  // T_1 = T_2 from here on
+    const bool pass0_done = relax_step(c, o);
 
     Mode mode = Mode::Sync;
     if (o->frozen_lambda) mode = Mode::Frozen;
@@ -869,7 +973,7 @@ tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
         if (B1) tlim::launch_copy(s, c->field[TLIM_ALPHA2], c->a2n, c->N);
         out = HeatOutcome{};
         sc = SweepCount{};
-        tm.used = 0;
+        tm.reset();
         st = heat_passes(c, o, Mode::Sync, rep, tm, sc, out, false);
         if (st) return st;
     }
@@ -887,6 +991,8 @@ tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
         rep->bad_cells = (int64_t)out.bad;
         rep->predicted = predicted ? 1 : 0;
         rep->mispredicted = mispredicted ? 1 : 0;
+        rep->pipelined_steps = c->pipelined_steps;
+        rep->pipeline_redos = c->pipeline_redos;
         if (tm.on) {
             HIP_TRY(c, hipStreamSynchronize(s));
             rep->sweep_ms = tm.elapsed_ms();
@@ -897,6 +1003,170 @@ tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
     if ((o->picard_tol > 0.0 && !out.converged) || out.cycle_fail)
         return fail(c, TLIM_E_NOCONV, "tolerance not reached (last Picard change %.3e)", out.last_err);
     return TLIM_OK;
+}
+
+void next_result_block(tlim_ctx* c) {
+    c->res_cur ^= 1;
+    c->res_host = c->res_blk[c->res_cur];
+    c->res_host_dev = c->res_blk_dev[c->res_cur];
+}
+
+// Steps that may run pipelined: predicted schedule, no report, no viscous
+// part, no timing, equal p_inf, 2D without sources (fused relaxation, whose
+// relaxed alpha2 and T^n go to fresh arrays).
+// A pipelined step is predicted from the step two back, and a miss costs the
+// newer step too, so pipelining waits until two consecutive steps kept the
+// same schedule.
+bool pipeline_ok(const tlim_ctx* c, const tlim_step_opts* o, const tlim_step_report* rep) {
+    return !rep && !o->do_viscous && !o->time_sweeps && !o->cycle_mode && !o->frozen_lambda && o->picard_tol <= 0.0 &&
+           c->phase[0].pinf == c->phase[1].pinf && fast_coeffs(c, dev_grid(c, kUnit)) &&
+           c->hist_passes == o->passes && c->hist_steady >= 2 && c->res_host_dev != nullptr;
+}
+
+// Enqueue a predicted step without waiting for anything: relaxation with the
+// first coefficients, the passes with the predicted P, and the fold of the
+// step's reductions into its own pinned result block, followed by an event.
+void enqueue_predicted(tlim_ctx* c, const tlim_step_opts* o, tlim_ctx::Pending& p) {
+    hipStream_t s = c->stream;
+    DevGrid g = dev_grid(c, kUnit);
+    DevPhases ph = dev_phases(c);
+    next_result_block(c);
+    relax_step(c, o);
+    Timer tm{c, false};
+    SweepCount sc;
+    for (int it = 0; it < o->passes; ++it) {
+        if (it > 0) heat_coeffs(c, g, ph, o, row(c, tlim::tgt_lam(it)), it);
+        const double* Tit = it == 0 ? c->Tn : c->field[TLIM_T1];
+        const int P = c->hist_P[it];
+        p.P_used[it] = P;
+        PassSchedule ps = device_schedule(P, o->order, row(c, tlim::tgt_lam(it)));
+        run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->g_heat, c->Tnew, Tit, pass_slots(c, it), tm, sc, true);
+        std::swap(c->field[TLIM_T1], c->Tnew);
+    }
+    tlim::launch_collect(s, c->acc, c->res_host_dev, tlim::tgt_lam(0), tlim::tgt_lam(o->passes), 1);
+    c->clean_rows = c->clean_keep;
+    (void)hipEventRecord(c->ev_pend[c->res_cur], s);
+    p.o = *o;
+    p.o.frozen_lambda = nullptr;
+    p.o.frozen_visc = nullptr;
+    p.blk = c->res_cur;
+    p.Tn = c->Tn;
+    p.alpha2 = c->field[TLIM_ALPHA2];
+    p.alpha2_other = c->a2n;
+}
+
+struct Verdict {
+    tlim_status st;
+    bool mispredicted;
+    double bad;
+    double lam[TLIM_MAX_PASSES];  // the step's lambda_G per pass
+};
+
+// Wait for a pending step's readback (polled, like read_result) and check
+// the P it used in every pass against its lambda_G.
+Verdict verify(tlim_ctx* c, const tlim_ctx::Pending& p) {
+    Verdict v{TLIM_OK, false, 0.0, {0}};
+    hipEvent_t e = c->ev_pend[p.blk];
+    hipError_t r = hipErrorNotReady;
+    const auto t0c = std::chrono::steady_clock::now();
+    while ((r = hipEventQuery(e)) == hipErrorNotReady) {
+        if (std::chrono::steady_clock::now() - t0c > std::chrono::microseconds(2000)) {
+            r = hipEventSynchronize(e);
+            break;
+        }
+    }
+    if (r != hipSuccess) {
+        v.st = fail(c, TLIM_E_HIP, "pipelined step: %s", hipGetErrorString(r));
+        return v;
+    }
+    const PassResult* res = c->res_blk[p.blk];
+    const int np = p.o.passes;
+    for (int i = 0; i < np; ++i) {
+        v.lam[i] = res->v[tlim::tgt_lam(i)];
+        if (lim_P(p.o.dt, v.lam[i]) != p.P_used[i]) v.mispredicted = true;
+    }
+    v.bad = res->v[tlim::tgt_bad(np - 1)];
+    return v;
+}
+
+// Redo the passes of a mispredicted step from its relaxed state, with one
+// readback per pass.
+tlim_status redo_pending(tlim_ctx* c, const tlim_ctx::Pending& p) {
+    c->Tn = p.Tn;
+    c->g_heat = p.Tn;
+    c->field[TLIM_ALPHA2] = p.alpha2;
+    c->a2n = p.alpha2_other;
+    c->predict_misses++;
+    c->pipeline_redos++;
+    Timer tm{c, false};
+    SweepCount sc;
+    HeatOutcome out;
+    tlim_status st = heat_passes(c, &p.o, Mode::Sync, nullptr, tm, sc, out, false);
+    if (st) return st;
+    if (out.bad > 0.0) return fail(c, TLIM_E_NUMERIC, "%.0f cells with non-finite or non-positive T", out.bad);
+    return TLIM_OK;
+}
+
+// Verify the pending step, if any (redoing it when mispredicted); every entry
+// point that reads or changes the state calls this first.
+tlim_status resolve(tlim_ctx* c) {
+    if (!c || !c->pending) return TLIM_OK;
+    c->pending = false;
+    const tlim_ctx::Pending p = c->pend;
+    Verdict v = verify(c, p);
+    if (v.st) return v.st;
+    if (v.mispredicted) return redo_pending(c, p);
+    record_schedule(c, p.o.passes, v.lam, p.o.dt);
+    if (v.bad > 0.0) return fail(c, TLIM_E_NUMERIC, "%.0f cells with non-finite or non-positive T", v.bad);
+    return TLIM_OK;
+}
+
+}  // namespace
+
+tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep) {
+    if (!c) return TLIM_E_ARG;
+    tlim_status st = check_opts(c, o);
+    if (st) return st;
+    st = check_ready(c);
+    if (st) return st;
+    if (!pipeline_ok(c, o, rep)) {
+        st = resolve(c);
+        if (st) return st;
+        return advance_sync(c, o, rep);
+    }
+    // Pipelined: enqueue this step first, then verify the previous one while
+    // this one runs.
+    tlim_ctx::Pending np{};
+    enqueue_predicted(c, o, np);
+    c->pipelined_steps++;
+    if (!c->pending) {
+        c->pending = true;
+        c->pend = np;
+        return TLIM_OK;
+    }
+    const tlim_ctx::Pending prev = c->pend;
+    c->pending = false;
+    Verdict v = verify(c, prev);
+    if (v.st) return v.st;
+    if (v.mispredicted) {
+        // this step started from a state that is redone: let it finish,
+        // redo the previous step, then run this one with its own readback
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        st = redo_pending(c, prev);
+        if (st) return st;
+        return advance_sync(c, o, nullptr);
+    }
+    record_schedule(c, prev.o.passes, v.lam, prev.o.dt);
+    c->pending = true;
+    c->pend = np;
+    if (v.bad > 0.0)
+        return fail(c, TLIM_E_NUMERIC, "%.0f cells with non-finite or non-positive T (previous step)", v.bad);
+    return TLIM_OK;
+}
+
+tlim_status tlim_finish(tlim_ctx* c) {
+    if (!c) return TLIM_E_ARG;
+    return resolve(c);
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -1012,6 +1282,8 @@ void adj_forward_step(tlim_ctx* c, const tlim_step_opts* o, const double* lamv, 
 tlim_status tlim_forward_checkpointed(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, int32_t ckpt_every,
                                       double* ckpt_dev, double* lam_out) {
     if (!c) return TLIM_E_ARG;
+    tlim_status pst = resolve(c);
+    if (pst) return pst;
     tlim_status st = check_adjoint(c, o);
     if (st) return st;
     if (nsteps < 1 || ckpt_every < 1 || !ckpt_dev || !lam_out) return fail(c, TLIM_E_ARG, "bad checkpoint arguments");
@@ -1037,6 +1309,8 @@ tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, i
                          const double* ckpt_dev, const double* lam, const double* dL_dTN_dev, double* dL_dT0_dev,
                          double* dL_dk0, void* adj_ws_dev, size_t adj_ws_bytes) {
     if (!c) return TLIM_E_ARG;
+    tlim_status pst = resolve(c);
+    if (pst) return pst;
     tlim_status st = check_adjoint(c, o);
     if (st) return st;
     if (c->precision != TLIM_FP64) return fail(c, TLIM_E_ARG, "the adjoint runs in FP64 contexts");

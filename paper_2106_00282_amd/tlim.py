@@ -27,7 +27,7 @@ MAX_PASSES = 64
 
 EXPORTED = ("tlim_create", "tlim_destroy", "tlim_workspace_bytes", "tlim_bind_workspace",
             "tlim_set_phase", "tlim_set_field", "tlim_get_field", "tlim_spectral_bound",
-            "tlim_advance", "tlim_forward_checkpointed", "tlim_adjoint_workspace_bytes",
+            "tlim_advance", "tlim_finish", "tlim_forward_checkpointed", "tlim_adjoint_workspace_bytes",
             "tlim_adjoint", "tlim_status_str", "tlim_last_error")
 
 
@@ -61,7 +61,7 @@ class ReportC(C.Structure):
                 ("visc_lambda_G", C.c_double * 3), ("energy_before", C.c_double),
                 ("energy_after", C.c_double), ("sweeps", C.c_int64), ("sweep_launches", C.c_int64),
                 ("sweep_ms", C.c_double), ("bad_cells", C.c_int64), ("predicted", C.c_int32),
-                ("mispredicted", C.c_int32)]
+                ("mispredicted", C.c_int32), ("pipelined_steps", C.c_int64), ("pipeline_redos", C.c_int64)]
 
 
 _lib = None
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     L.tlim_get_field.argtypes = [vp, C.c_int32, vp]
     L.tlim_spectral_bound.argtypes = [vp, C.c_int32, C.c_double, dp]
     L.tlim_advance.argtypes = [vp, C.POINTER(StepOptsC), C.POINTER(ReportC)]
+    L.tlim_finish.argtypes = [vp]
     L.tlim_forward_checkpointed.argtypes = [vp, C.POINTER(StepOptsC), C.c_int32, C.c_int32, vp, dp]
     L.tlim_adjoint_workspace_bytes.argtypes = [vp, C.POINTER(StepOptsC), C.c_int32, C.POINTER(C.c_size_t)]
     L.tlim_adjoint.argtypes = [vp, C.POINTER(StepOptsC), C.c_int32, C.c_int32, vp, dp, vp, vp, dp, vp,
@@ -141,7 +142,8 @@ def _report(r: ReportC) -> dict:
                 visc_lambda_G=list(r.visc_lambda_G), energy_before=r.energy_before,
                 energy_after=r.energy_after, sweeps=r.sweeps, sweep_launches=r.sweep_launches,
                 sweep_ms=r.sweep_ms, bad_cells=r.bad_cells, predicted=bool(r.predicted),
-                mispredicted=bool(r.mispredicted))
+                mispredicted=bool(r.mispredicted), pipelined_steps=r.pipelined_steps,
+                pipeline_redos=r.pipeline_redos)
 
 
 class Solver:
@@ -242,8 +244,14 @@ class Solver:
         return st, (_report(rep) if report else None)
 
     def advance_raw(self, oc: StepOptsC) -> int:
-        """Advance with a prepared options struct and no report (timing loops)."""
+        """Advance with a prepared options struct and no report (timing
+        loops).  Predicted steps may stay pending (pipelined): finish()
+        completes them."""
         return load_library().tlim_advance(self._ctx, C.byref(oc), None)
+
+    def finish(self) -> int:
+        """Complete a pending pipelined step; returns its status."""
+        return load_library().tlim_finish(self._ctx)
 
     # ------------------------------------------------------------- adjoint
     def forward_checkpointed(self, opts: StepOpts, nsteps: int, ckpt_every: int = 1):

@@ -131,6 +131,94 @@ def test_mispredicted_schedule_rolls_back():
     assert rel_err(s.get_field("T1").cpu().numpy(), fo["T1"]) < 1e-12
 
 
+@pytest.mark.parametrize("precision,n,hot,miss", [("fp64", 256, 1.0, False), ("fp64", 192, 3.0, True),
+                                                  ("fp32", 192, 3.0, True), ("fp32", 256, 3.0, False)])
+def test_pipelined_steps_match_oracle(precision, n, hot, miss):
+    """Steps without a report run pipelined (each verified by the next call).
+    With a hot spot (T up to 1 + hot) lambda_G falls from step to step, so
+    the P predicted from two steps back is wrong now and then and the step
+    must be redone; the result must still match the oracle's unfrozen run."""
+    from oracle import oracle as orc
+    from paper_2106_00282_amd.tlim import StepOpts
+    wl = W.levelset2d(n)
+    if hot != 1.0:
+        x = (np.arange(n) + 0.5) / n
+        r2 = (x[None, :] - 0.3) ** 2 + (x[:, None] - 0.6) ** 2
+        bump = 1.0 + hot * np.exp(-r2 / (2 * 0.03 ** 2))
+        for k in ("T1", "T2"):
+            wl["fields"][k] = np.ascontiguousarray(wl["fields"][k] * bump[None])
+    tau, _ = oracle_dt(orc, wl)
+    steps = 8
+    fo, ro = run_oracle(orc, wl, tau, steps)
+    Ps = [r["P"] for r in ro]
+    s = make_solver(wl, precision)
+    o = StepOpts(dt=tau, passes=3)
+    st, rep = s.advance(o)  # first step: synchronous, sets the schedule history
+    assert st == 0 and rep["P"] == Ps[0]
+    for _ in range(steps - 1):
+        assert s.advance(o, report=False)[0] == 0
+    assert s.finish() == 0
+    fg = {k: s.get_field(k).cpu().numpy() for k in FIELDS_T}
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    _compare(fo, fg, FIELDS_T, tol)
+    if miss:
+        # a pipelined step k >= 2 is predicted with the last P of step k-2
+        # for every pass: here the schedule changes enough for some to miss
+        assert any(Ps[k] != [Ps[k - 2][-1]] * 3 for k in range(2, steps)), Ps
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pipelined_dt_change_redoes_steps(precision):
+    """Once the schedule is steady, steps without a report run pipelined.  A
+    larger dt then makes the pending step's predicted P wrong: the next call
+    finds it after enqueuing its own step, redoes the pending one and reruns
+    its own; a final finish() completes the last one.  Matches the oracle run
+    with the same dt sequence."""
+    from oracle import oracle as orc
+    from paper_2106_00282_amd.tlim import StepOpts
+    wl = W.levelset2d(160)
+    tau, _ = oracle_dt(orc, wl)
+    dts = [tau] * 5 + [2.5 * tau] * 3 + [tau] * 2
+    g = orc.make_grid(wl["n"], wl["h"], wl["bc"])
+    fo = {k: v.copy() for k, v in wl["fields"].items()}
+    s = make_solver(wl, precision)
+    for dt in dts:
+        orc.step(g, wl["phases"], orc.StepOpts(tau=dt, passes=3), fo)
+        assert s.advance(StepOpts(dt=dt, passes=3), report=False)[0] == 0
+    assert s.finish() == 0
+    # one reported step reads the context's pipelining totals
+    orc.step(g, wl["phases"], orc.StepOpts(tau=tau, passes=3), fo)
+    st, rep = s.advance(StepOpts(dt=tau, passes=3))
+    assert st == 0
+    assert rep["pipelined_steps"] >= 3 and rep["pipeline_redos"] >= 1, rep
+    fg = {k: s.get_field(k).cpu().numpy() for k in FIELDS_T}
+    _compare(fo, fg, FIELDS_T, 1e-12 if precision == "fp64" else 1e-5)
+
+
+def test_pipelined_step_then_report_and_phase_change():
+    """A pending pipelined step is completed by set_phase (which may make
+    the next prediction wrong) and by a reported step; the sequence matches
+    the oracle."""
+    from oracle import oracle as orc
+    from paper_2106_00282_amd.tlim import StepOpts
+    wl = W.levelset2d(128)
+    tau, _ = oracle_dt(orc, wl)
+    g = orc.make_grid(wl["n"], wl["h"], wl["bc"])
+    fo = {k: v.copy() for k, v in wl["fields"].items()}
+    s = make_solver(wl)
+    ph = [dict(p) for p in wl["phases"]]
+    o = StepOpts(dt=tau, passes=3)
+    for step, (scale, report) in enumerate(((1.0, True), (1.0, False), (1.0, False), (3.0, False), (3.0, False),
+                                             (3.0, True), (3.0, False))):
+        for k in range(2):
+            ph[k]["k0"] = wl["phases"][k]["k0"] * scale
+            s.set_phase(k, ph[k])
+        orc.step(g, ph, orc.StepOpts(tau=tau, passes=3), fo)
+        st, _ = s.advance(o, report=report)
+        assert st == 0
+    assert rel_err(s.get_field("T1").cpu().numpy(), fo["T1"]) < 1e-12
+
+
 def test_paper_order_and_harmonic_faces():
     from oracle import oracle as orc
     wl = W.levelset2d(48)
