@@ -266,8 +266,9 @@ tlim_status check_opts(tlim_ctx* c, const tlim_step_opts* o) {
 // ---------------------------------------------------------- one LIM pass
 
 // Kernel time of the sweep launches (time_sweeps): a pair of events around
-// every launch; when the pairs run out the elapsed times so far are folded
-// (which waits for them) and the events are reused.
+// each run of back-to-back sweep launches; when the pairs run out the
+// elapsed times so far are folded (which waits for them) and the events are
+// reused.
 struct Timer {
     tlim_ctx* c;
     bool on;
@@ -362,8 +363,11 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
                   SweepCount& sc, bool have_q = false) {
     const int nst = ps.nst;
     hipStream_t s = c->stream;
+    if (c->precision == TLIM_FP32 && !have_q)
+        tlim::launch_q32(s, g, face, rhs, v0, c->Lam32, c->rC32, tau, c->q32, c->wb[0]);
+    // one event pair around the pass's back-to-back sweep launches
+    tm.start();
     if (c->precision == TLIM_FP32) {
-        if (!have_q) tlim::launch_q32(s, g, face, rhs, v0, c->Lam32, c->rC32, tau, c->q32, c->wb[0]);
         // 2P-2 float stages on the correction, the final one in double; the
         // launch that reaches it writes `out`
         const float* cur = c->wb[0];
@@ -372,10 +376,8 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
             int k = tlim::sweeps_per_launch(g, nst - m);
             bool last = m + k == nst;
             float* nxt = cur == c->wb[0] ? c->wb[1] : c->wb[0];
-            tm.start();
             int done = tlim::launch_sweeps32(s, g, face, cur, c->q32, c->Lam32, c->rC32, nxt, ps.at(m), k, last, tau,
                                              rhs, c->rC, out, Tit, slots);
-            tm.stop();
             cur = nxt;
             m += done;
             sc.launches++;
@@ -390,16 +392,15 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
             int k = tlim::sweeps_per_launch(g, nst - m);
             bool last = m + k == nst;
             double* nxt = last ? out : c->vb[pp];
-            tm.start();
             int done = tlim::launch_sweeps64(s, g, face, cur, rhs, c->Lam, c->rC, nxt, ps.at(m), k, last, tau, Tit,
                                              slots);
-            tm.stop();
             cur = nxt;
             pp ^= 1;
             m += done;
             sc.launches++;
         }
     }
+    tm.stop();
     sc.sweeps += nst;
 }
 
@@ -509,15 +510,15 @@ tlim_status cycle_pass(tlim_ctx* c, const DevGrid& g, const tlim_step_opts* o, i
     int cyc = 0;
     double r = 0.0;
     while (cyc < o->max_cycles) {
+        tm.start();
         for (int m = 0; m < s_stages; ++m) {
             tlim::StageParam sp{nullptr, o->dt * b[m], 0.0};
-            tm.start();
             tlim::launch_stage64(c->stream, g, o->face_mean, c->vb[cur], c->g_heat, c->Lam, c->rC, c->vb[cur ^ 1],
                                  sp, o->dt);
-            tm.stop();
             cur ^= 1;
             sc.launches++;
         }
+        tm.stop();
         sc.sweeps += s_stages;
         ++cyc;
         zero_rows(c, tlim::kTgtRR, tlim::kTgtGG + 1);

@@ -36,6 +36,14 @@ int launch_sweeps32(hipStream_t s, const DevGrid& g, int face, const float* w, c
                     const float* Lam32, const float* rC32, float* out, Stages st, int count, bool last, double tau,
                     const double* rhs, const double* rC, double* out64, const double* Tit, PassSlots ps);
 
+// One stage on a 3D grid by z-marching waves (tlim_sweep3d.hip): as
+// launch_stage64 / launch_stage32, and with Tit != NULL also the pass
+// reductions of launch_final64 (for the final stage pass sp.tb = 0).
+bool use_z3d(const DevGrid& g);
+template <typename R>
+void launch_z3d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* G, const R* Lam, const R* rC, R* out,
+                StageParam sp, double tau, const double* Tit, PassSlots ps);
+
 // Blocked FP64 stages that also keep their intermediate results: the result
 // of the launch's stage k (k = 1 .. K-1) goes to stages + k*sstride and the
 // last one to out.  Returns K, or -1 where blocking does not apply (then

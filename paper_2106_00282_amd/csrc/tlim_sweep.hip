@@ -338,6 +338,11 @@ int launch_sweeps64(hipStream_t s, const DevGrid& g, int face, const double* v, 
                     const double* Tit, PassSlots ps) {
     if (use_tb2d(g, count))
         return launch_tb2d<double>(s, g, face, v, rhs, Lam, rC, out, st, count, tau, last ? Tit : nullptr, ps);
+    if (use_z3d(g)) {
+        if (last) launch_z3d<double>(s, g, face, v, rhs, Lam, rC, out, StageParam{nullptr, 0.0, 0.0}, tau, Tit, ps);
+        else launch_z3d<double>(s, g, face, v, rhs, Lam, rC, out, one_stage(st), tau, nullptr, PassSlots{});
+        return 1;
+    }
     if (last) {
         // the final stage, b = 0, in flux form
         launch_final64(s, g, face, v, rhs, Lam, rC, out, tau, Tit, ps);
@@ -358,6 +363,8 @@ int launch_sweeps32(hipStream_t s, const DevGrid& g, int face, const float* w, c
     }
     if (last) {
         launch_final32(s, g, face, w, rhs, Lam32, rC, out64, tau, Tit, ps);
+    } else if (use_z3d(g)) {
+        launch_z3d<float>(s, g, face, w, qn, Lam32, rC32, out, one_stage(st), tau, nullptr, PassSlots{});
     } else {
         launch_stage32(s, g, face, w, qn, Lam32, rC32, out, one_stage(st), tau);
     }

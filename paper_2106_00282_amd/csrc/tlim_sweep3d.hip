@@ -1,0 +1,257 @@
+// One LIM stage (eq. LIM; with b = 0 the final stage, eq. LIM_last) on 3D
+// grids, marching along z.
+//
+// A wave owns 64 consecutive x cells (one per lane) by ROWS consecutive y
+// rows and a chunk of z planes.  It walks the chunk plane by plane, keeping
+// v and Lambda of the previous, current and next plane for its rows and the
+// two rows around them in registers: the z- and y-neighbours of a cell are
+// the lane's own registers, the x-neighbours come from the adjacent lanes
+// (DPP), and the two lanes at the ends of the wave load the x-halo cell of
+// their row.  Every value is read from memory once per plane and chunk (the
+// extra y rows and z planes of the window are the only re-reads), and waves
+// never wait on each other: no LDS, no barrier.
+//
+// Arithmetic as the one-stage kernels: S = sum_f w_f mean(Lambda_a,
+// Lambda_b) (v_a - v_b) over the faces -x, +x, -y, +y, -z, +z, then
+// out = c_m (G + tau b_m v - tau rC S); in FP32 contexts v is the correction
+// w and G the correction source q, in float.
+#include <hip/hip_runtime.h>
+
+#include "tlim_device.h"
+#include "tlim_sweep.h"
+
+namespace tlim {
+
+namespace {
+
+using tb::fmean;
+using tb::fold;
+using tb::from_left;
+using tb::from_right;
+
+constexpr int kZWaves = 4;
+
+template <typename R>
+struct Z3Args {
+    const R* v;
+    const R* G;
+    const R* Lam;
+    const R* rC;
+    R* out;
+    StageParam sp;
+    double tau;
+    const double* Tit;  // FP64 final stage: accumulate the pass reductions into ps
+    PassSlots ps;
+    int nx, ny, nz, perx, pery, perz;
+    double wx, wy, wz;
+    int face, tiles_x, tiles_y, zc, nwaves;
+};
+
+template <typename R, int ROWS>
+__global__ void __launch_bounds__(64 * kZWaves) k_z3d(Z3Args<R> a) {
+    constexpr int RW = ROWS + 2;
+    const int lane = threadIdx.x & 63;
+    const int wid = blockIdx.x * kZWaves + (threadIdx.x >> 6);
+    // tau*b of the stage (every lane of every wave takes part in the fold)
+    double tbd = a.sp.tb;
+    if (a.sp.lam) {
+        double m = 0.0;
+#pragma unroll
+        for (int k = 0; k < kSlots / 64; ++k) m = fmax(m, a.sp.lam[lane + 64 * k]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        tbd = a.tau * m * a.sp.chat;
+    }
+    if (wid >= a.nwaves) return;  // wave-uniform
+    const int tx = wid % a.tiles_x, rest = wid / a.tiles_x;
+    const int ty = rest % a.tiles_y, tz = rest / a.tiles_y;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int xg = tx * 64 + lane;
+    const int xi = fold(xg, nx, a.perx);
+    const int xl = fold(tx * 64 - 1, nx, a.perx), xr = fold(tx * 64 + 64, nx, a.perx);
+    const bool inx = xg < nx;
+    const bool fL = a.perx ? nx > 1 : (inx && xg > 0);
+    const bool fR = a.perx ? nx > 1 : (inx && xg < nx - 1);
+    const int y0 = ty * ROWS, z0 = tz * a.zc;
+    const int z1 = z0 + a.zc < nz ? z0 + a.zc : nz;
+    const R cm = (R)(1.0 / (1.0 + tbd)), tb = (R)tbd, tf = (R)a.tau;
+    const R wx = (R)a.wx, wy = (R)a.wy, wz = (R)a.wz;
+    const int face = a.face;
+
+    // 32-bit element offsets (the launcher requires N < 2^32): global loads
+    // then take a scalar base and one VGPR offset
+    unsigned rowoff[RW];  // y offsets of the window rows within a plane
+#pragma unroll
+    for (int r = 0; r < RW; ++r) rowoff[r] = (unsigned)fold(y0 - 1 + r, ny, a.pery) * (unsigned)nx;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const unsigned uxi = (unsigned)xi;
+
+    // Software pipeline: while plane z is computed, plane z+2 (and the own
+    // cells' G, 1/C and the x-halo of plane z+1) are already being loaded.
+    R vm[RW], vc[RW], vp[RW], vq[RW], Lm[RW], Lc[RW], Lp[RW], Lq[RW];
+    R Gc[ROWS], rc_c[ROWS], Gn[ROWS], rc_n[ROWS], hvc[ROWS], hLc[ROWS], hvn[ROWS], hLn[ROWS];
+    const unsigned hx = (unsigned)(lane == 0 ? xl : xr);
+    const bool halo_lane = lane == 0 || lane == 63;
+    auto load_plane = [&](int z, R* vv, R* LL) {
+        const unsigned pz = (unsigned)fold(z, nz, a.perz) * plane;
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            vv[r] = a.v[pz + rowoff[r] + uxi];
+            LL[r] = a.Lam[pz + rowoff[r] + uxi];
+        }
+    };
+    // own cells of plane z (clamped into the grid: only used for z < z1):
+    // G and 1/C, and the x-halo cells of the ends of the wave
+    auto load_own = [&](int z, R* GG, R* rr, R* hv, R* hL) {
+        const unsigned pz = (unsigned)(z < nz ? z : nz - 1) * plane;
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            GG[r] = a.G[pz + rowoff[r + 1] + uxi];
+            rr[r] = a.rC[pz + rowoff[r + 1] + uxi];
+            hv[r] = R(0);
+            hL[r] = R(0);
+            if (halo_lane) {
+                hv[r] = a.v[pz + rowoff[r + 1] + hx];
+                hL[r] = a.Lam[pz + rowoff[r + 1] + hx];
+            }
+        }
+    };
+    load_plane(z0 - 1, vm, Lm);
+    load_plane(z0, vc, Lc);
+    load_plane(z0 + 1, vp, Lp);
+    load_own(z0, Gc, rc_c, hvc, hLc);
+    double dmax = 0.0, tmax = 0.0, bad = 0.0;
+    for (int z = z0; z < z1; ++z) {
+        const unsigned pc = (unsigned)z * plane;
+        load_plane(z + 2, vq, Lq);
+        load_own(z + 1, Gn, rc_n, hvn, hLn);
+        // x-neighbours of the current plane, with every lane active
+        R vl[ROWS], vr[ROWS], Ll[ROWS], Lr[ROWS];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            vl[r] = from_left(vc[r + 1]);
+            vr[r] = from_right(vc[r + 1]);
+            Ll[r] = from_left(Lc[r + 1]);
+            Lr[r] = from_right(Lc[r + 1]);
+            if (lane == 0) {
+                vl[r] = hvc[r];
+                Ll[r] = hLc[r];
+            }
+            if (lane == 63) {
+                vr[r] = hvc[r];
+                Lr[r] = hLc[r];
+            }
+        }
+        const bool fB = a.perz ? nz > 1 : z > 0;
+        const bool fF = a.perz ? nz > 1 : z < nz - 1;
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int y = y0 + r;
+            if (inx && y < ny) {
+                const bool fD = a.pery ? ny > 1 : y > 0;
+                const bool fU = a.pery ? ny > 1 : y < ny - 1;
+                const R c = vc[r + 1], La = Lc[r + 1];
+                R S = R(0);
+                if (fL) S += wx * fmean<R>(La, Ll[r], face) * (c - vl[r]);
+                if (fR) S += wx * fmean<R>(La, Lr[r], face) * (c - vr[r]);
+                if (fD) S += wy * fmean<R>(La, Lc[r], face) * (c - vc[r]);
+                if (fU) S += wy * fmean<R>(La, Lc[r + 2], face) * (c - vc[r + 2]);
+                if (fB) S += wz * fmean<R>(La, Lm[r + 1], face) * (c - vm[r + 1]);
+                if (fF) S += wz * fmean<R>(La, Lp[r + 1], face) * (c - vp[r + 1]);
+                const unsigned o = pc + (unsigned)y * (unsigned)nx + (unsigned)xg;
+                const R t = cm * (Gc[r] + tb * c - tf * rc_c[r] * S);
+                a.out[o] = t;
+                if (a.Tit) {
+                    const double tn = (double)t;
+                    dmax = fmax(dmax, fabs(tn - a.Tit[o]));
+                    tmax = fmax(tmax, fabs(tn));
+                    if (!(tn > 0.0) || isinf(tn)) bad += 1.0;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            vm[r] = vc[r];
+            Lm[r] = Lc[r];
+            vc[r] = vp[r];
+            Lc[r] = Lp[r];
+            vp[r] = vq[r];
+            Lp[r] = Lq[r];
+        }
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            Gc[r] = Gn[r];
+            rc_c[r] = rc_n[r];
+            hvc[r] = hvn[r];
+            hLc[r] = hLn[r];
+        }
+    }
+    if (a.Tit) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+            tmax = fmax(tmax, __shfl_xor(tmax, o, 64));
+            bad += __shfl_xor(bad, o, 64);
+        }
+        if (lane == 0) {
+            const int sl = wid % kSlots;
+            atomicMax((unsigned long long*)(a.ps.dmax + sl), (unsigned long long)__double_as_longlong(dmax + 0.0));
+            atomicMax((unsigned long long*)(a.ps.tmax + sl), (unsigned long long)__double_as_longlong(tmax + 0.0));
+            if (bad != 0.0) atomicAdd(a.ps.bad + sl, bad);
+        }
+    }
+}
+
+// y rows per wave: fewer in double, to keep two waves per SIMD
+template <typename R>
+constexpr int z_rows() {
+    return sizeof(R) == 8 ? 4 : 8;
+}
+
+}  // namespace
+
+bool use_z3d(const DevGrid& g) { return g.nz > 1 && g.N < ((int64_t)1 << 32); }
+
+template <typename R>
+void launch_z3d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* G, const R* Lam, const R* rC, R* out,
+                StageParam sp, double tau, const double* Tit, PassSlots ps) {
+    Z3Args<R> a{};
+    a.v = v;
+    a.G = G;
+    a.Lam = Lam;
+    a.rC = rC;
+    a.out = out;
+    a.sp = sp;
+    a.tau = tau;
+    a.Tit = Tit;
+    a.ps = ps;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nz = g.nz;
+    a.perx = g.per[0];
+    a.pery = g.per[1];
+    a.perz = g.per[2];
+    a.wx = g.w[0];
+    a.wy = g.w[1];
+    a.wz = g.w[2];
+    a.face = face;
+    a.tiles_x = (g.nx + 63) / 64;
+    constexpr int rows = z_rows<R>();
+    a.tiles_y = (g.ny + rows - 1) / rows;
+    // z chunks sized for about 4096 waves, 4..64 planes each
+    const int64_t cols = (int64_t)a.tiles_x * a.tiles_y;
+    int64_t zc = (int64_t)g.nz * cols / 4096;
+    zc = zc < 4 ? 4 : (zc > 64 ? 64 : zc);
+    a.zc = (int)zc;
+    const int64_t nw = cols * ((g.nz + a.zc - 1) / a.zc);
+    a.nwaves = (int)nw;
+    const unsigned blocks = (unsigned)((nw + kZWaves - 1) / kZWaves);
+    hipLaunchKernelGGL((k_z3d<R, rows>), dim3(blocks), dim3(64 * kZWaves), 0, s, a);
+}
+
+template void launch_z3d<double>(hipStream_t, const DevGrid&, int, const double*, const double*, const double*,
+                                 const double*, double*, StageParam, double, const double*, PassSlots);
+template void launch_z3d<float>(hipStream_t, const DevGrid&, int, const float*, const float*, const float*,
+                                const float*, float*, StageParam, double, const double*, PassSlots);
+
+}  // namespace tlim
