@@ -12,9 +12,13 @@ region.
 Reported (one JSON line):
   value      FP64 cell-updates per second (N * sweeps / wall time of the steps)
   fp32       the same for the FP32 form and its speedup over FP64
-  roofline   dominant kernel (the LIM sweep): algorithmic bytes per launch /
-             average launch time from HIP events on the library's stream
+  roofline   dominant kernel (the blocked LIM sweep): algorithmic bytes per
+             launch (N x 40 B x stages, an unfused sweep's compulsory bytes) /
+             average launch time from HIP events on the library's stream;
+             traffic = HBM bytes per launch from the committed rocprofv3
+             FETCH_SIZE/WRITE_SIZE summary (null once the kernel changed)
   adjoint    adjoint / forward time on the 2048^2, 20-step adjoint workload
+  bubbles3d  the 256^3 FP32 workload with the viscous part
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload
 """
 from __future__ import annotations
@@ -36,7 +40,7 @@ BYTES_PER_UPDATE = {"fp64": 5 * 8, "fp32": 5 * 4}
 
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_tb2d_f64_levelset2d_1024.md")
-SWEEP_SOURCES = ("tlim_sweep.hip", "tlim_device.h", "tlim_sweep.h", "tlim_internal.h")
+SWEEP_SOURCES = ("tlim_sweep.hip", "tlim_device.h")
 
 
 def sweep_source_digest():
@@ -149,6 +153,35 @@ def adjoint_ratio():
                 forward_s=round(t_fwd, 4), adjoint_s=round(t_adj, 4), ratio=round(t_adj / t_fwd, 3))
 
 
+def bubbles3d_rate(n=256, steps=5):
+    """The 3D bubbles workload (256^3 periodic, FP32 sweeps, viscous part on,
+    5 steps): whole-step throughput and sweep-kernel rate."""
+    import torch
+    from paper_2106_00282_amd import workloads as W
+    from paper_2106_00282_amd.tlim import Solver, StepOpts
+    wl = W.bubbles3d(n, steps=steps)
+    s = Solver(wl["n"], wl["h"], wl["bc"], precision="fp32")
+    s.set_workload(wl)
+    tau = wl["dt_factor"] * 2.0 / s.spectral_bound()
+    opts = StepOpts(dt=tau, passes=wl["passes"], do_viscous=1)
+    run_steps(s, wl, opts, 1)  # warm-up step on the same fields, then start over
+    s.set_workload(wl)
+    # timed: the steps with reports (the viscous part reads its bounds back anyway)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sweeps = 0
+    for _ in range(steps):
+        st, rep = s.advance(opts)
+        if st != 0:
+            raise RuntimeError(f"tlim_advance returned {st}")
+        sweeps += rep["sweeps"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return dict(workload=f"bubbles3d {n}^3 periodic, FP32 sweeps, viscous part, {steps} steps",
+                value=round(s.N * sweeps / wall / 1e9, 3), unit="Gcell-updates/s",
+                ms_per_step=round(wall / steps * 1e3, 3), sweeps=sweeps)
+
+
 def cpu_baseline(wl, tau, budget_s=12.0):
     """The FP64 oracle, as it is, on whole steps of the same workload until
     about budget_s of CPU time has passed."""
@@ -179,6 +212,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding "
@@ -205,6 +239,9 @@ def main():
     adj = None if args.no_adjoint else adjoint_ratio()
     if adj:
         log("adjoint", adj)
+    b3 = None if args.no_3d or args.fp64_only else bubbles3d_rate()
+    if b3:
+        log("bubbles3d", b3)
 
     avg_launch_ms = r64["sweep_ms"] / max(r64["launches"], 1)
     bytes_per_launch = r64["N"] * BYTES_PER_UPDATE["fp64"] * (r64["sweeps"] / max(r64["launches"], 1))
@@ -248,6 +285,8 @@ def main():
                        "sweep_GBs": round(b32 / (l32 * 1e-3) / 1e9, 1) if l32 > 0 else None}
     if adj:
         out["adjoint"] = adj
+    if b3:
+        out["bubbles3d"] = b3
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, tau)
     print(json.dumps(out), flush=True)

@@ -218,7 +218,9 @@ tlim_status tlim_adjoint_workspace_bytes(const tlim_ctx* ctx, const tlim_step_op
  * through Lambda(T^(it)) of every Picard pass).  The forward model is the
  * heat step without relaxation, which is the identity on the equilibrium
  * states the forward run produces.  Same restrictions as
- * tlim_forward_checkpointed; FP64 contexts only.  Synchronises. */
+ * tlim_forward_checkpointed.  The recomputation and the reverse stages run
+ * in FP64 also in FP32 contexts: the result is the gradient of the FP64
+ * discretisation at the checkpointed states.  Synchronises. */
 tlim_status tlim_adjoint(tlim_ctx* ctx, const tlim_step_opts* opts, int32_t nsteps, int32_t ckpt_every,
                          const double* ckpt_dev, const double* lam, const double* dL_dTN_dev,
                          double* dL_dT0_dev, double* dL_dk0, void* adj_ws_dev, size_t adj_ws_bytes);

@@ -1,5 +1,5 @@
-// Coefficients of a Picard pass and the Gershgorin bound on 2D grids whose
-// heat step has no source term (Sec. 3.4.2, eq. qk_dis; bound of eq. LIM).
+// Coefficients of a Picard pass and the Gershgorin bound on grids whose heat
+// step has no source term (Sec. 3.4.2, eq. qk_dis; bound of eq. LIM).
 //
 // Per cell: Lambda = sum_k alpha_k lambda_k(T^(it)) and, where it changes,
 // 1/C_eff; per cell the bound 2 rC sum_f w_f mean(Lambda_a, Lambda_b), folded
@@ -62,6 +62,9 @@ struct Coef2DArgs {
     int nx, ny, perx, pery;
     double wx, wy, tau, eps;
     int face, rebuild, tiles_x, strips;
+    // 3D grids
+    int nz, perz, tiles_y, zc;
+    double wz;
 };
 
 template <bool kRelax>
@@ -153,9 +156,132 @@ __global__ void __launch_bounds__(64 * kWaves) k_coeffs2d(Coef2DArgs a) {
     }
 }
 
+// 3D grids: the same per-cell work, with each wave marching through a chunk
+// of z planes (kRows3 rows per wave) and keeping the conductivities (and g)
+// of the previous, current and next plane in registers.
+constexpr int kRows3 = 4;
+
+template <bool kRelax>
+__global__ void __launch_bounds__(64 * kWaves) k_coeffs3d(Coef2DArgs a) {
+    constexpr int RW = kRows3 + 2;
+    const int lane = threadIdx.x & 63;
+    const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (wid >= a.strips) return;  // wave-uniform
+    const int tx = wid % a.tiles_x, rest = wid / a.tiles_x;
+    const int ty = rest % a.tiles_y, tz = rest / a.tiles_y;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int xg = tx * kOut - 1 + lane;
+    const int xi = fold(xg, nx, a.perx);
+    const bool out_lane = lane >= 1 && lane <= kOut && xg < nx;
+    const bool fL = a.perx ? nx > 1 : xg > 0;
+    const bool fR = a.perx ? nx > 1 : xg < nx - 1;
+    const int y0 = ty * kRows3, z0 = tz * a.zc;
+    const int z1 = z0 + a.zc < nz ? z0 + a.zc : nz;
+    const bool q = a.q32 != nullptr;
+
+    // 32-bit element offsets (the launcher requires N < 2^32)
+    unsigned rowoff[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) rowoff[r] = (unsigned)fold(y0 - 1 + r, ny, a.pery) * (unsigned)nx + (unsigned)xi;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    // T, alpha2 (relaxed when kRelax), Lambda and g of the window rows of plane z
+    auto load_plane = [&](int z, double* tw, double* aw, double* Lw, double* gw) {
+        const unsigned pz = (unsigned)fold(z, nz, a.perz) * plane;
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const unsigned idx = pz + rowoff[r];
+            if constexpr (kRelax) {
+                const double t1 = a.T[idx];
+                const double t2 = a.T2 == a.T ? t1 : a.T2[idx];
+                phys::relax_cell(a.ph, a.eps, a.alpha2[idx], t1, t2, a.m1[idx], a.m2[idx], tw[r], aw[r]);
+                gw[r] = tw[r];
+            } else {
+                tw[r] = a.T[idx];
+                aw[r] = a.alpha2[idx];
+                gw[r] = q ? a.g[idx] : 0.0;
+            }
+            Lw[r] = cell_conductivity(a.ph, tw[r], aw[r]);
+        }
+    };
+    // window: Lambda and g of planes z-1, z, z+1; T and alpha2 of z and z+1
+    double Lm[RW], gm[RW], tc[RW], ac[RW], Lc[RW], gc[RW], tp[RW], ap[RW], Lp[RW], gp[RW];
+    load_plane(z0 - 1, tp, ap, Lm, gm);
+    load_plane(z0, tc, ac, Lc, gc);
+    double bound = 0.0;
+    for (int z = z0; z < z1; ++z) {
+        load_plane(z + 1, tp, ap, Lp, gp);
+        const bool fB = a.perz ? nz > 1 : z > 0;
+        const bool fF = a.perz ? nz > 1 : z < nz - 1;
+#pragma unroll
+        for (int r = 1; r <= kRows3; ++r) {
+            const int y = y0 + r - 1;
+            const double L = Lc[r];
+            const double Ll = from_left(L), Lr = from_right(L);
+            const float Lf = (float)L;
+            const float Llf = from_left(Lf), Lrf = from_right(Lf);
+            const double gl = from_left(gc[r]), gr = from_right(gc[r]);
+            if (out_lane && y < ny) {
+                const unsigned o = (unsigned)z * plane + (unsigned)y * (unsigned)nx + (unsigned)xg;
+                const bool fD = a.pery ? ny > 1 : y > 0;
+                const bool fU = a.pery ? ny > 1 : y < ny - 1;
+                if constexpr (kRelax) {
+                    a.Tn_out[o] = tc[r];
+                    a.a2_out[o] = ac[r];
+                }
+                double rc;
+                if (a.rebuild) {
+                    rc = inv_heat_capacity(a.ph, a.eps, tc[r], ac[r], a.m1[o], a.m2[o]);
+                    a.rC[o] = rc;
+                    if (a.rC32) a.rC32[o] = (float)rc;
+                } else {
+                    rc = a.rC_in[o];
+                }
+                if (a.Lam) a.Lam[o] = L;
+                if (a.Lam32) a.Lam32[o] = Lf;
+                // faces in the order -x, +x, -y, +y, -z, +z
+                double d = 0.0;
+                if (fL) d += a.wx * fmean<double>(L, Ll, a.face);
+                if (fR) d += a.wx * fmean<double>(L, Lr, a.face);
+                if (fD) d += a.wy * fmean<double>(L, Lc[r - 1], a.face);
+                if (fU) d += a.wy * fmean<double>(L, Lc[r + 1], a.face);
+                if (fB) d += a.wz * fmean<double>(L, Lm[r], a.face);
+                if (fF) d += a.wz * fmean<double>(L, Lp[r], a.face);
+                bound = fmax(bound, 2.0 * d * rc);
+                if (q) {
+                    const double La = (double)Lf, rf = (double)(float)rc, ga = gc[r];
+                    double S = 0.0;
+                    if (fL) S += a.wx * fmean<double>(La, (double)Llf, a.face) * (ga - gl);
+                    if (fR) S += a.wx * fmean<double>(La, (double)Lrf, a.face) * (ga - gr);
+                    if (fD) S += a.wy * fmean<double>(La, (double)(float)Lc[r - 1], a.face) * (ga - gc[r - 1]);
+                    if (fU) S += a.wy * fmean<double>(La, (double)(float)Lc[r + 1], a.face) * (ga - gc[r + 1]);
+                    if (fB) S += a.wz * fmean<double>(La, (double)(float)Lm[r], a.face) * (ga - gm[r]);
+                    if (fF) S += a.wz * fmean<double>(La, (double)(float)Lp[r], a.face) * (ga - gp[r]);
+                    a.q32[o] = (float)(-a.tau * rf * S);
+                    a.w0[o] = 0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            Lm[r] = Lc[r];
+            gm[r] = gc[r];
+            tc[r] = tp[r];
+            ac[r] = ap[r];
+            Lc[r] = Lp[r];
+            gc[r] = gp[r];
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bound = fmax(bound, __shfl_xor(bound, o, 64));
+    if (lane == 0) {
+        const int sl = wid % kSlots;
+        atomicMax((unsigned long long*)(a.lam + sl), (unsigned long long)__double_as_longlong(bound + 0.0));
+    }
+}
+
 }  // namespace
 
-bool coeffs2d_applies(const DevGrid& g) { return g.nz == 1; }
+bool coeffs2d_applies(const DevGrid& g) { return g.nz == 1 || g.N < ((int64_t)1 << 32); }
 
 void launch_coeffs2d(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double tau, int face,
                      const double* T, const double* alpha2, const double* m1, const double* m2, const double* Tn,
@@ -190,14 +316,27 @@ void launch_coeffs2d(hipStream_t s, const DevGrid& g, const DevPhases& ph, doubl
     a.face = face;
     a.rebuild = rebuild;
     a.tiles_x = (g.nx + kOut - 1) / kOut;
-    a.strips = a.tiles_x * ((g.ny + kRows - 1) / kRows);
-    const int blocks = (a.strips + kWaves - 1) / kWaves;
-    if (T2_relax) {
-        a.rebuild = 1;
-        hipLaunchKernelGGL(k_coeffs2d<true>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
-    } else {
-        hipLaunchKernelGGL(k_coeffs2d<false>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+    if (T2_relax) a.rebuild = 1;
+    if (g.nz == 1) {
+        a.strips = a.tiles_x * ((g.ny + kRows - 1) / kRows);
+        const int blocks = (a.strips + kWaves - 1) / kWaves;
+        if (T2_relax) hipLaunchKernelGGL(k_coeffs2d<true>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+        else hipLaunchKernelGGL(k_coeffs2d<false>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+        return;
     }
+    a.nz = g.nz;
+    a.perz = g.per[2];
+    a.wz = g.w[2];
+    a.tiles_y = (g.ny + kRows3 - 1) / kRows3;
+    // z chunks sized for about 4096 waves, 4..64 planes each
+    const int64_t cols = (int64_t)a.tiles_x * a.tiles_y;
+    int64_t zc = (int64_t)g.nz * cols / 4096;
+    zc = zc < 4 ? 4 : (zc > 64 ? 64 : zc);
+    a.zc = (int)zc;
+    a.strips = (int)(cols * ((g.nz + a.zc - 1) / a.zc));
+    const int blocks = (a.strips + kWaves - 1) / kWaves;
+    if (T2_relax) hipLaunchKernelGGL(k_coeffs3d<true>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+    else hipLaunchKernelGGL(k_coeffs3d<false>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
 }
 
 }  // namespace tlim

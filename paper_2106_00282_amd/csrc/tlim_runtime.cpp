@@ -1314,7 +1314,6 @@ tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, i
     if (pst) return pst;
     tlim_status st = check_adjoint(c, o);
     if (st) return st;
-    if (c->precision != TLIM_FP64) return fail(c, TLIM_E_ARG, "the adjoint runs in FP64 contexts");
     if (nsteps < 1 || ckpt_every < 1 || !ckpt_dev || !lam || !dL_dTN_dev || !dL_dT0_dev || !dL_dk0 || !adj_ws_dev)
         return fail(c, TLIM_E_ARG, "bad adjoint arguments");
     if (((uintptr_t)adj_ws_dev % kAlign) != 0) return fail(c, TLIM_E_ARG, "adjoint workspace not 256-byte aligned");

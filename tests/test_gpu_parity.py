@@ -446,6 +446,30 @@ def test_adjoint_vs_oracle_adjoint():
     assert rel_err(d2.cpu().numpy(), dT0.cpu().numpy()) < 1e-13
 
 
+def test_adjoint_in_fp32_context():
+    """FP32 forward run (checkpoint at T^0 only): the adjoint recomputes and
+    reverses in FP64, so with the run's schedule it equals the FP64 oracle
+    adjoint from the same T^0."""
+    import torch
+    from paper_2106_00282_amd.tlim import StepOpts
+    orc, wl, tau, steps = _adjoint_setup(n=64, steps=3)
+    s = make_solver(wl, "fp32")
+    opts = StepOpts(dt=tau, passes=3)
+    ckpt, lam = s.forward_checkpointed(opts, steps, steps)
+    TN32 = s.get_field("T1").cpu().numpy()
+    rng = np.random.default_rng(13)
+    g = 0.05 * rng.standard_normal(TN32.shape)
+    dT0, dk0 = s.adjoint(opts, steps, steps, ckpt, lam, torch.from_numpy(g))
+    f = wl["fields"]
+    odT0, odk0, oTN = orc.heat_adjoint(orc.make_grid(wl["n"], wl["h"], wl["bc"]), wl["phases"],
+                                       orc.StepOpts(tau=tau, passes=3), steps, np.array(lam), f["alpha2"], f["m1"],
+                                       f["m2"], f["T1"], g)
+    assert rel_err(TN32, oTN) < 1e-5
+    assert rel_err(dT0.cpu().numpy(), odT0) < 1e-11
+    for k in range(2):
+        assert dk0[k] == pytest.approx(odk0[k], rel=1e-10)
+
+
 @pytest.mark.parametrize("case", ["harmonic2d", "grid3d", "adiabatic2d"])
 def test_adjoint_other_paths_vs_oracle(case):
     """The adjoint on grids and face means outside the blocked 2D path
