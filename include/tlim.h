@@ -99,6 +99,8 @@ typedef struct {
     const double* frozen_lambda; /* nullable, `passes` entries: lambda_max per pass instead of Gershgorin */
     const double* frozen_visc;   /* nullable, 3 entries: lambda_max per velocity component */
     int32_t time_sweeps;         /* 1: time the sweep launches with HIP events (report.sweep_ms) */
+    int32_t visc_heating;        /* with do_viscous: the viscous part also heats the phases (Sec. 3.2,
+                                    phase internal-energy update with the predicted velocity) */
 } tlim_step_opts;
 
 #define TLIM_MAX_PASSES 64

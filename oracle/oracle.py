@@ -48,7 +48,7 @@ class Opts(C.Structure):
     _fields_ = [("tau", C.c_double), ("passes", C.c_int32), ("picard_tol", C.c_double),
                 ("order", C.c_int32), ("face_mean", C.c_int32), ("cycle_mode", C.c_int32),
                 ("cycle_tol", C.c_double), ("max_cycles", C.c_int32), ("alpha_eps", C.c_double),
-                ("do_viscous", C.c_int32)]
+                ("do_viscous", C.c_int32), ("visc_heating", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -95,6 +95,9 @@ def lib():
                                       _dp, _dp]
         L.orc_be_residual.restype = C.c_double
         L.orc_be_residual.argtypes = [C.POINTER(Grid), _dp, _dp, _dp, C.c_int32, C.c_double, _dp, _dp]
+        L.orc_visc_heat.restype = None
+        L.orc_visc_heat.argtypes = [C.POINTER(Grid), C.POINTER(Phase), C.c_double, C.c_int32, _dp, _dp, _dp, _dp,
+                                    _dp, C.c_double, _dp, _dp, _dp]
         L.orc_heat_adjoint.restype = C.c_int32
         L.orc_heat_adjoint.argtypes = [C.POINTER(Grid), C.POINTER(Phase), C.POINTER(Opts), C.c_int32,
                                        _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -152,11 +155,12 @@ class StepOpts:
     max_cycles: int = 200
     alpha_eps: float = 1e-10
     do_viscous: int = 0
+    visc_heating: int = 0
 
     def c(self) -> Opts:
         o = Opts()
         for k in ("tau", "passes", "picard_tol", "order", "face_mean", "cycle_mode",
-                  "cycle_tol", "max_cycles", "alpha_eps", "do_viscous"):
+                  "cycle_tol", "max_cycles", "alpha_eps", "do_viscous", "visc_heating"):
             setattr(o, k, getattr(self, k))
         return o
 
@@ -244,6 +248,15 @@ def relax(g, ph, alpha2, m1, m2, T1, T2, eps=1e-10):
     """Temperature relaxation in mixed cells, in place (Sec. 3.4.1)."""
     N = _ncell(g)
     lib().orc_relax(C.byref(g), make_phases(ph), eps, _p(alpha2, N), _p(m1, N), _p(m2, N), _p(T1, N), _p(T2, N))
+
+
+def visc_heat(g, ph, alpha2, m1, m2, mu, scale, tau, uh, T1, T2, eps=1e-10, face_mean=FACE_ARITH):
+    """Viscous heating of the phases by one velocity component, in place on
+    T1, T2 (Sec. 3.2, phase internal energies); uh the predicted velocity."""
+    N = _ncell(g)
+    sc = np.asarray(scale, dtype=np.float64)
+    lib().orc_visc_heat(C.byref(g), make_phases(ph), eps, face_mean, _p(alpha2, N), _p(m1, N), _p(m2, N), _p(mu, N),
+                        _p(sc), tau, _p(uh, N), _p(T1, N), _p(T2, N))
 
 
 def energy(g, ph, alpha2, m1, m2, T1, T2):

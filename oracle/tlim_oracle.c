@@ -495,10 +495,75 @@ static int32_t heat_picard(const orc_grid* g, const orc_phase ph[2], const orc_o
     return (o->picard_tol > 0.0 && !converged) ? 3 : 0;
 }
 
-/* Viscous momentum diffusion, one LIM pass per velocity component. */
+/* Viscous heating (Sec. 3.2, phase internal energies).  Along axis d the
+ * viscous flux through the face between cell a and b = a + e_d is
+ * F = s_d mu_f (uh_b - uh_a) / h_d, with face values uh_f = (uh_a + uh_b)/2
+ * and alpha_k,f = (alpha_k,a + alpha_k,b)/2.  The energy of phase k in cell a
+ * changes by
+ *   tau/h_d [alpha_k,f+ uh_f+ F_f+ - alpha_k,f- uh_f- F_f-]
+ *     - tau/h_d uh_a [alpha_k,f+ F_f+ - alpha_k,f- F_f-]
+ * summed over the axes (f+ / f- the faces towards a + e_d / a - e_d; a face
+ * that does not exist carries no flux).  With rho_k and alpha_k fixed in
+ * this part, T_k changes by that energy over C_k = m_k C_v,k; in a cell
+ * without phase k (alpha_k outside (eps, 1-eps)) the phase present takes
+ * both shares. */
+void orc_visc_heat(const orc_grid* g, const orc_phase ph[2], double eps, int32_t face_mean,
+                   const double* alpha2, const double* m1, const double* m2, const double* mu,
+                   const double axis_scale[3], double tau, const double* uh, double* T1, double* T2) {
+    const int64_t stride[3] = {1, g->n[0], g->n[0] * g->n[1]};
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                const int64_t c[3] = {i, j, k};
+                const int64_t a = i + g->n[0] * (j + g->n[1] * k);
+                double dE[2] = {0.0, 0.0};
+                for (int axis = 0; axis < 3; ++axis) {
+                    const int64_t n = g->n[axis];
+                    if (n <= 1) continue;
+                    const double h = g->h[axis];
+                    /* F, uh_f and alpha_k,f of the faces a+e_d (side +1) and a-e_d (side -1) */
+                    double F[2] = {0.0, 0.0}, uf[2] = {0.0, 0.0}, af[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+                    for (int side = 0; side < 2; ++side) {
+                        const int dir = side == 0 ? 1 : -1;
+                        int64_t cn = c[axis] + dir;
+                        if (cn < 0 || cn >= n) {
+                            if (g->bc[axis] != ORC_PERIODIC) continue;
+                            cn = (cn + n) % n;
+                        }
+                        const int64_t b = a + (cn - c[axis]) * stride[axis];
+                        const double muf = face_value(mu[a], mu[b], face_mean);
+                        /* flux in the +d direction through this face */
+                        const double grad = dir > 0 ? (uh[b] - uh[a]) / h : (uh[a] - uh[b]) / h;
+                        F[side] = axis_scale[axis] * muf * grad;
+                        uf[side] = 0.5 * (uh[a] + uh[b]);
+                        af[side][0] = 0.5 * ((1.0 - alpha2[a]) + (1.0 - alpha2[b]));
+                        af[side][1] = 0.5 * (alpha2[a] + alpha2[b]);
+                    }
+                    for (int ph_k = 0; ph_k < 2; ++ph_k) {
+                        const double work = af[0][ph_k] * uf[0] * F[0] - af[1][ph_k] * uf[1] * F[1];
+                        const double force = af[0][ph_k] * F[0] - af[1][ph_k] * F[1];
+                        dE[ph_k] += tau / h * work - tau / h * uh[a] * force;
+                    }
+                }
+                const double a2 = alpha2[a];
+                const double C1 = m1[a] * ph[0].cv, C2 = m2[a] * ph[1].cv;
+                if (a2 <= eps) {
+                    T1[a] += (dE[0] + dE[1]) / C1;
+                } else if (a2 >= 1.0 - eps) {
+                    T2[a] += (dE[0] + dE[1]) / C2;
+                } else {
+                    T1[a] += dE[0] / C1;
+                    T2[a] += dE[1] / C2;
+                }
+            }
+}
+
+/* Viscous momentum diffusion, one LIM pass per velocity component, with the
+ * viscous heating of the phases when asked. */
 static void viscous(const orc_grid* g, const orc_phase ph[2], const orc_opts* o,
                     const double* alpha2, const double* m1, const double* m2, double* vel[3],
-                    const double* frozen_visc, orc_report* rep) {
+                    const double* frozen_visc, double* T1, double* T2, orc_report* rep) {
     int64_t N = ncells(g);
     double* rho = dalloc(N);
     double* mu = dalloc(N);
@@ -517,7 +582,16 @@ static void viscous(const orc_grid* g, const orc_phase ph[2], const orc_opts* o,
         int32_t nst = 2 * P - 1;
         double* b = dalloc(nst);
         orc_lim_params(P, lam, o->order, b);
-        orc_lim_pass(g, mu, rho, s, o->face_mean, o->tau, nst, b, vel[c], vel[c], out, NULL);
+        if (o->visc_heating) {
+            /* keep the stage iterates: the last one, v^(2P-2), is the predicted velocity */
+            double* st = dalloc((int64_t)nst * N);
+            orc_lim_pass(g, mu, rho, s, o->face_mean, o->tau, nst, b, vel[c], vel[c], out, st);
+            orc_visc_heat(g, ph, o->alpha_eps, o->face_mean, alpha2, m1, m2, mu, s, o->tau,
+                          st + (int64_t)(nst - 1) * N, T1, T2);
+            free(st);
+        } else {
+            orc_lim_pass(g, mu, rho, s, o->face_mean, o->tau, nst, b, vel[c], vel[c], out, NULL);
+        }
         memcpy(vel[c], out, sizeof(double) * (size_t)N);
         free(b);
         if (rep) {
@@ -540,7 +614,7 @@ int32_t orc_step(const orc_grid* g, const orc_phase ph[2], const orc_opts* o, do
      * then heat conduction. */
     if (o->do_viscous) {
         double* vel[3] = {u, v, w};
-        viscous(g, ph, o, alpha2, m1, m2, vel, frozen_visc, rep);
+        viscous(g, ph, o, alpha2, m1, m2, vel, frozen_visc, T1, T2, rep);
     }
     orc_relax(g, ph, o->alpha_eps, alpha2, m1, m2, T1, T2);
     int32_t st = heat_picard(g, ph, o, alpha2, m1, m2, T1, src1, src2, frozen_lambda, rep);

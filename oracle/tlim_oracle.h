@@ -75,6 +75,7 @@ typedef struct {
     int32_t max_cycles;
     double alpha_eps;    /* mixed cell: eps < alpha2 < 1 - eps */
     int32_t do_viscous;  /* run the viscous sub-step first */
+    int32_t visc_heating; /* viscous part also heats the phases (orc_visc_heat) */
 } orc_opts;
 
 /* Per-step report (filled by the step driver). */
@@ -122,6 +123,15 @@ void orc_lim_pass(const orc_grid* g, const double* Lam, const double* C,
                   const double axis_scale[3], int32_t face_mean, double tau,
                   int32_t nst, const double* b, const double* rhs, const double* v0,
                   double* out, double* stages);
+
+/* Viscous heating of the phases by one velocity component (Sec. 3.2, the
+ * phase internal-energy update after the momentum pass).  uh is the
+ * predicted velocity (after the first 2P-2 stages), mu the cell viscosity,
+ * axis_scale the factors s_d of mu_cd (4/3 on the component's own axis).
+ * T1, T2 are updated in place. */
+void orc_visc_heat(const orc_grid* g, const orc_phase ph[2], double eps, int32_t face_mean,
+                   const double* alpha2, const double* m1, const double* m2, const double* mu,
+                   const double axis_scale[3], double tau, const double* uh, double* T1, double* T2);
 
 /* Temperature relaxation in mixed cells (in place on alpha2, T1, T2). */
 void orc_relax(const orc_grid* g, const orc_phase ph[2], double eps,

@@ -179,6 +179,18 @@ void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const
                      double* acc, double* mu, int first_pass, const double* rCpsi, double* k0a, double* k0b,
                      int init);
 
+// Viscous heating by one velocity component (Sec. 3.2, phase internal
+// energies): with the predicted velocity uh (uh64, or g64 + w32 in the FP32
+// correction form) and the cell viscosity mu, phase k of cell a gains
+//   tau sum_f 1/2 w_f alpha_k,f mu_f (uh_b - uh_a)^2
+// (g.w carries the 4/3 factor of the component's own axis), which is the
+// paper's flux form with face values uh_f = (uh_a+uh_b)/2 and alpha_k,f the
+// arithmetic face mean; T_k += that / C_k, and in a cell without phase k the
+// phase present takes both shares.  T1, T2 in place.
+void launch_visc_heat(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, int face, double tau,
+                      const double* alpha2, const double* m1, const double* m2, const double* mu,
+                      const double* uh64, const double* g64, const float* w32, double* T1, double* T2);
+
 void launch_fill(hipStream_t s, double* p, double v, int64_t n);
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n);
 

@@ -630,6 +630,42 @@ __global__ void __launch_bounds__(256) k_adj_cell(DevGrid g, DevPhases ph, const
     }
 }
 
+__global__ void __launch_bounds__(256) k_visc_heat(DevGrid g, DevPhases ph, double eps, int face, double tau,
+                                                   const double* __restrict__ alpha2, const double* __restrict__ m1,
+                                                   const double* __restrict__ m2, const double* __restrict__ mu,
+                                                   const double* __restrict__ uh64, const double* __restrict__ g64,
+                                                   const float* __restrict__ w32, double* T1, double* T2) {
+    int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    const int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+    auto uh = [&](int64_t c) { return uh64 ? uh64[c] : g64[c] + (double)w32[c]; };
+    Faces f;
+    faces_of(g, i, j, k, f);
+    const double ua = uh(a), a2a = alpha2[a], mua = mu[a];
+    double e1 = 0.0, e2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        if (!f.has[q]) continue;
+        const int64_t b = a + f.off[q];
+        const double du = uh(b) - ua;
+        const double d = 0.5 * g.w[q >> 1] * face_mean<double>(mua, mu[b], face) * du * du;
+        const double a2f = 0.5 * (a2a + alpha2[b]);
+        e1 += (1.0 - a2f) * d;
+        e2 += a2f * d;
+    }
+    e1 *= tau;
+    e2 *= tau;
+    const double C1 = m1[a] * ph.cv[0], C2 = m2[a] * ph.cv[1];
+    if (a2a <= eps) {
+        T1[a] += (e1 + e2) / C1;
+    } else if (a2a >= 1.0 - eps) {
+        T2[a] += (e1 + e2) / C2;
+    } else {
+        T1[a] += e1 / C1;
+        T2[a] += e2 / C2;
+    }
+}
+
 // One wave per target row folds its kSlots slots with the target's
 // operation; consume = 1 also clears the row for its next use.
 __global__ void __launch_bounds__(64) k_collect(double* __restrict__ acc, PassResult* res, int t0, int consume) {
@@ -767,6 +803,13 @@ void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const
                      int first_pass, const double* rCpsi, double* k0a, double* k0b, int init) {
     hipLaunchKernelGGL(k_adj_cell, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, Tit, alpha2, gLam, dg,
                        lam0, acc, mu, first_pass, rCpsi, k0a, k0b, init);
+}
+
+void launch_visc_heat(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, int face, double tau,
+                      const double* alpha2, const double* m1, const double* m2, const double* mu,
+                      const double* uh64, const double* g64, const float* w32, double* T1, double* T2) {
+    hipLaunchKernelGGL(k_visc_heat, tile_grid(g), dim3(TX, TY), 0, s, g, ph, eps, face, tau, alpha2, m1, m2, mu, uh64,
+                       g64, w32, T1, T2);
 }
 
 void launch_fill(hipStream_t s, double* p, double v, int64_t n) {

@@ -358,9 +358,17 @@ PassSchedule device_schedule(int P, int order, const double* lam_dev) {
 // reductions into ps.
 // In FP32 contexts q and w0 come from the heat coefficient kernel
 // (have_q = true) or are built here.
+// The predicted iterate v^(2P-2) of a pass run with its final stage on its
+// own (uh64, or g64 + w32 in FP32 contexts).
+struct Vhat {
+    const double* v64 = nullptr;
+    const double* g64 = nullptr;
+    const float* w32 = nullptr;
+};
+
 void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const PassSchedule& ps, const double* v0,
                   const double* rhs, double* out, const double* Tit, tlim::PassSlots slots, Timer& tm,
-                  SweepCount& sc, bool have_q = false) {
+                  SweepCount& sc, bool have_q = false, Vhat* vh = nullptr) {
     const int nst = ps.nst;
     hipStream_t s = c->stream;
     if (c->precision == TLIM_FP32 && !have_q)
@@ -372,9 +380,10 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
         // launch that reaches it writes `out`
         const float* cur = c->wb[0];
         int m = 0;
-        while (m < nst) {
-            int k = tlim::sweeps_per_launch(g, nst - m);
-            bool last = m + k == nst;
+        const int upto = vh ? nst - 1 : nst;  // with vh the final stage runs on its own
+        while (m < upto) {
+            int k = tlim::sweeps_per_launch(g, upto - m);
+            bool last = !vh && m + k == nst;
             float* nxt = cur == c->wb[0] ? c->wb[1] : c->wb[0];
             int done = tlim::launch_sweeps32(s, g, face, cur, c->q32, c->Lam32, c->rC32, nxt, ps.at(m), k, last, tau,
                                              rhs, c->rC, out, Tit, slots);
@@ -382,15 +391,22 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
             m += done;
             sc.launches++;
         }
+        if (vh) {
+            tlim::launch_final32(s, g, face, cur, rhs, c->Lam32, c->rC, out, tau, Tit, slots);
+            sc.launches++;
+            vh->g64 = rhs;
+            vh->w32 = cur;
+        }
     } else {
         // all 2P-1 stages, the last (b = 0) in flux form; the launch that
         // reaches it writes `out`
         const double* cur = v0;
         int m = 0;
         int pp = 0;
-        while (m < nst) {
-            int k = tlim::sweeps_per_launch(g, nst - m);
-            bool last = m + k == nst;
+        const int upto = vh ? nst - 1 : nst;
+        while (m < upto) {
+            int k = tlim::sweeps_per_launch(g, upto - m);
+            bool last = !vh && m + k == nst;
             double* nxt = last ? out : c->vb[pp];
             int done = tlim::launch_sweeps64(s, g, face, cur, rhs, c->Lam, c->rC, nxt, ps.at(m), k, last, tau, Tit,
                                              slots);
@@ -398,6 +414,11 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
             pp ^= 1;
             m += done;
             sc.launches++;
+        }
+        if (vh) {
+            tlim::launch_final64(s, g, face, cur, rhs, c->Lam, c->rC, out, tau, Tit, slots);
+            sc.launches++;
+            vh->v64 = cur;
         }
     }
     tm.stop();
@@ -447,6 +468,12 @@ tlim_status viscous(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep,
     DevGrid g0 = dev_grid(c, kUnit);
     tlim::launch_visc_coeffs(c->stream, g0, ph, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], c->Lam,
                              c->rC, c->Lam32, c->rC32);
+    const bool heat = o->visc_heating != 0;
+    if (heat && c->t2_alias) {
+        // the phases are heated differently: T2 gets its own array again
+        tlim::launch_copy(c->stream, c->field[TLIM_T2], c->field[TLIM_T1], c->N);
+        c->t2_alias = false;
+    }
     for (int comp = 0; comp < 3; ++comp) {
         if (c->n[comp] <= 1) continue;
         double scale[3] = {1.0, 1.0, 1.0};
@@ -464,7 +491,13 @@ tlim_status viscous(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep,
         }
         PassSchedule ps = host_schedule(o->dt, lam, o->order);
         double* u = c->field[TLIM_U + comp];
-        run_lim_pass(c, g, o->face_mean, o->dt, ps, u, u, c->Tnew, nullptr, tlim::PassSlots{}, tm, sc);
+        Vhat vh;
+        run_lim_pass(c, g, o->face_mean, o->dt, ps, u, u, c->Tnew, nullptr, tlim::PassSlots{}, tm, sc, false,
+                     heat ? &vh : nullptr);
+        if (heat)
+            tlim::launch_visc_heat(c->stream, g, ph, o->alpha_eps, o->face_mean, o->dt, c->field[TLIM_ALPHA2],
+                                   c->field[TLIM_M1], c->field[TLIM_M2], c->Lam, vh.v64, vh.g64, vh.w32,
+                                   c->field[TLIM_T1], c->field[TLIM_T2]);
         std::swap(c->field[TLIM_U + comp], c->Tnew);
         if (rep) {
             rep->visc_P[comp] = lim_P(o->dt, lam);

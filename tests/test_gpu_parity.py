@@ -95,6 +95,31 @@ def test_bubbles3d_fp64_with_viscous():
     _compare(fo, fg, FIELDS_T + ("u", "v", "w"), 1e-12)
 
 
+@pytest.mark.parametrize("precision,walls", [("fp64", False), ("fp64", True), ("fp32", False)])
+def test_viscous_heating_vs_oracle(precision, walls):
+    """Viscous part with the phase heating (Sec. 3.2, phase internal
+    energies) on 3D bubbles with a 30x stronger velocity, periodic or with
+    adiabatic walls in x and z: temperatures, volume fraction and velocity
+    after 2 steps against the oracle; the heating itself must be visible."""
+    from oracle import oracle as orc
+    wl = W.bubbles3d(40)
+    for k in wl["fields"]:
+        wl["fields"][k] = np.ascontiguousarray(wl["fields"][k][:33, :36, :])
+    for c in "uvw":
+        wl["fields"][c] = np.ascontiguousarray(30.0 * wl["fields"][c])
+    wl["n"] = (40, 36, 33)
+    wl["h"] = (1 / 40, 1 / 40, 1 / 40)
+    if walls:
+        wl["bc"] = (W.ADIABATIC, W.PERIODIC, W.ADIABATIC)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 2, visc_heating=1)
+    fn, _ = run_oracle(orc, wl, tau, 2)
+    assert rel_err(fo["T1"], fn["T1"]) > 1e-4  # the heating changes T
+    fg, rg, _ = run_gpu(wl, tau, 2, precision=precision, frozen=_frozen(ro), visc_heating=1)
+    assert [r["visc_P"] for r in rg] == [r["visc_P"] for r in ro]
+    _compare(fo, fg, FIELDS_T + ("u", "v", "w"), 1e-12 if precision == "fp64" else 1e-5)
+
+
 def test_interface3d_fp64_adiabatic_x():
     from oracle import oracle as orc
     wl = W.interface3d(32, nmodes=12)
@@ -568,3 +593,114 @@ def test_autograd_function_vs_central_fd():
         km[k] -= hstep
         fd = (fwd_loss(base, kp) - fwd_loss(base, km)) / (2 * hstep)
         assert float(k0.grad[k]) == pytest.approx(fd, rel=1e-6)
+
+
+# ------------------------------------------------ adjoint at the full sizes
+
+def _frozen_loss(s, wl, tau, lam, steps, T0, k0, Tstar):
+    """L = 1/2 sum (T^N - T*)^2 of the GPU forward from (T0, k0) with the
+    recorded schedule frozen."""
+    from paper_2106_00282_amd.tlim import StepOpts
+    ph = [dict(p) for p in wl["phases"]]
+    for k in range(2):
+        ph[k]["k0"] = float(k0[k])
+        s.set_phase(k, ph[k])
+    s.set_field("T1", T0)
+    s.set_field("T2", T0)
+    for n in range(steps):
+        st, _ = s.advance(StepOpts(dt=tau, passes=3, frozen_lambda=lam[3 * n:3 * n + 3]), report=False)
+        assert st == 0
+    r = s.get_field("T1") - Tstar
+    return 0.5 * float((r * r).sum())
+
+
+def _target(wl, tau, steps, precision="fp64"):
+    """T^N of the run with both k0 scaled by the workload's target factor."""
+    from paper_2106_00282_amd.tlim import StepOpts
+    wt = dict(wl)
+    wt["phases"] = [dict(p, k0=p["k0"] * wl.get("target_k0_scale", 1.1)) for p in wl["phases"]]
+    st = make_solver(wt, precision)
+    for _ in range(steps):
+        assert st.advance(StepOpts(dt=tau, passes=3), report=False)[0] == 0
+    assert st.finish() == 0
+    out = st.get_field("T1")
+    st.close()
+    return out
+
+
+def test_adjoint_full_size_2048_fd():
+    """The 2048^2, 20-step adjoint workload (checkpoint every step): the
+    gradient w.r.t. the 16 probe cells of T^0 and both k0 against central
+    differences of the frozen-schedule GPU forward."""
+    import torch
+    from paper_2106_00282_amd.tlim import StepOpts
+    wl = W.levelset2d_adjoint(2048, 20)
+    steps = wl["steps"]
+    s = make_solver(wl)
+    tau = wl["dt_factor"] * 2.0 / s.spectral_bound()
+    Tstar = _target(wl, tau, steps)
+    opts = StepOpts(dt=tau, passes=3)
+    ckpt, lam = s.forward_checkpointed(opts, steps, 1)
+    TN = s.get_field("T1")
+    dT0, dk0 = s.adjoint(opts, steps, 1, ckpt, lam, TN - Tstar)
+    base = torch.from_numpy(wl["fields"]["T1"].copy()).to(s.device)
+    k0 = [p["k0"] for p in wl["phases"]]
+    gmax = float(dT0.abs().max())
+
+    def fd_cell(c, h):
+        Tp, Tm = base.clone(), base.clone()
+        Tp.view(-1)[c] += h
+        Tm.view(-1)[c] -= h
+        return (_frozen_loss(s, wl, tau, lam, steps, Tp, k0, Tstar) -
+                _frozen_loss(s, wl, tau, lam, steps, Tm, k0, Tstar)) / (2 * h)
+
+    def fd_k0(k, h):
+        kp, km = list(k0), list(k0)
+        kp[k] += h
+        km[k] -= h
+        return (_frozen_loss(s, wl, tau, lam, steps, base, kp, Tstar) -
+                _frozen_loss(s, wl, tau, lam, steps, base, km, Tstar)) / (2 * h)
+
+    # central differences at h and h/2, extrapolated (Richardson): the O(h^2)
+    # truncation of the 20-step nonlinear forward is ~1e-6 at h = 1e-3
+    for c in wl["fd_cells"]:
+        h = 1e-3 * float(base.view(-1)[int(c)])
+        fd = (4 * fd_cell(int(c), h / 2) - fd_cell(int(c), h)) / 3
+        assert float(dT0.view(-1)[int(c)]) == pytest.approx(fd, rel=1e-6, abs=1e-8 * gmax), c
+    for k in range(2):
+        h = 1e-3 * k0[k]
+        fd = (4 * fd_k0(k, h / 2) - fd_k0(k, h)) / 3
+        assert dk0[k] == pytest.approx(fd, rel=1e-6), k
+
+
+def test_adjoint_full_size_512cube_directional():
+    """The 512^3 interface workload, 10 steps with checkpoints every 2 steps
+    (about 140 GB of device memory with the stage storage): the adjoint's
+    directional derivative along a random (T^0, k0) direction against a
+    central difference of the frozen-schedule forward."""
+    import torch
+    from paper_2106_00282_amd.tlim import StepOpts
+    wl = W.interface3d(512, steps=10)
+    steps = wl["steps"]
+    s = make_solver(wl)
+    tau = wl["dt_factor"] * 2.0 / s.spectral_bound()
+    Tstar = _target(wl, tau, steps)
+    opts = StepOpts(dt=tau, passes=3)
+    ckpt, lam = s.forward_checkpointed(opts, steps, 2)
+    TN = s.get_field("T1")
+    dT0, dk0 = s.adjoint(opts, steps, 2, ckpt, lam, TN - Tstar)
+    del ckpt
+    gen = torch.Generator(device=s.device).manual_seed(5)
+    base = torch.from_numpy(wl["fields"]["T1"]).to(s.device)
+    dT = 1e-3 * base * torch.rand(base.shape, generator=gen, device=s.device, dtype=torch.float64)
+    k0 = [p["k0"] for p in wl["phases"]]
+    dk = [0.3 * k0[0], -0.2 * k0[1]]
+    dadj = float((dT0 * dT).sum()) + dk0[0] * dk[0] + dk0[1] * dk[1]
+
+    def fd(eps):
+        Lp = _frozen_loss(s, wl, tau, lam, steps, base + eps * dT, [k0[i] + eps * dk[i] for i in range(2)], Tstar)
+        Lm = _frozen_loss(s, wl, tau, lam, steps, base - eps * dT, [k0[i] - eps * dk[i] for i in range(2)], Tstar)
+        return (Lp - Lm) / (2 * eps)
+
+    dfd = (4 * fd(5e-4) - fd(1e-3)) / 3  # Richardson-extrapolated central difference
+    assert dadj == pytest.approx(dfd, rel=1e-6)

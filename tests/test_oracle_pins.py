@@ -11,6 +11,131 @@ from numpy.polynomial import chebyshev as npcheb
 from paper_2106_00282_amd import workloads as W
 
 
+# -------------------------------------------------------- viscous heating
+
+def _dissipation(uh, mu, alpha2, h, scale, bc):
+    """Per cell and phase: tau-free dissipation sum over faces of
+    1/2 s_d/h_d^2 alpha_k,f mu_f (uh_b - uh_a)^2 (arithmetic face means),
+    written with numpy rolls, independent of the oracle's flux form."""
+    e = [np.zeros_like(uh), np.zeros_like(uh)]
+    for d, ax in ((0, 2), (1, 1), (2, 0)):  # grid axis d is array axis ax
+        n = uh.shape[ax]
+        if n <= 1:
+            continue
+        for sh in (1, -1):
+            ub = np.roll(uh, -sh, axis=ax)
+            mub = np.roll(mu, -sh, axis=ax)
+            a2b = np.roll(alpha2, -sh, axis=ax)
+            term = 0.5 * scale[d] / h[d] ** 2 * 0.5 * (mu + mub) * (ub - uh) ** 2
+            if bc[d] != 0:  # adiabatic: no face at the ends
+                idx = [slice(None)] * 3
+                idx[ax] = n - 1 if sh == 1 else 0
+                term[tuple(idx)] = 0.0
+            a2f = 0.5 * (alpha2 + a2b)
+            e[0] += (1.0 - a2f) * term
+            e[1] += a2f * term
+    return e
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 0, 1)])
+def test_visc_heat_is_the_face_dissipation(orc, bc):
+    """The paper's phase energy update (flux form with face velocities and
+    face volume fractions) equals, cell by cell and phase by phase, the
+    dissipation sum of 1/2 s/h^2 alpha_k,f mu_f (du)^2 over the faces; pure
+    cells give both shares to the phase present."""
+    rng = np.random.default_rng(3)
+    n = (10, 8, 6)
+    shape = (n[2], n[1], n[0])
+    h = (0.1, 0.125, 0.2)
+    g = orc.make_grid(n, h, bc)
+    ph = W.base_phases(mu=(0.7, 0.2))
+    a2 = rng.uniform(0.05, 0.95, shape)
+    a2[0, 0, :3] = 0.0   # pure phase 1
+    a2[1, 2, 4:6] = 1.0  # pure phase 2
+    m1 = (1.0 - a2) * 1.0
+    m2 = a2 * 10.0
+    mu = rng.uniform(0.1, 1.0, shape)
+    uh = rng.standard_normal(shape)
+    scale = (4.0 / 3.0, 1.0, 1.0)
+    tau = 0.013
+    T1 = np.full(shape, 2.0)
+    T2 = np.full(shape, 3.0)
+    orc.visc_heat(g, ph, a2, m1, m2, mu, scale, tau, uh, T1, T2)
+    e = _dissipation(uh, mu, a2, h, scale, bc)
+    C1, C2 = m1 * ph[0]["cv"], m2 * ph[1]["cv"]
+    mixed = (a2 > 1e-10) & (a2 < 1 - 1e-10)
+    tot = tau * (e[0] + e[1])
+    np.testing.assert_allclose(((T1 - 2.0) * C1)[mixed], tau * e[0][mixed], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(((T2 - 3.0) * C2)[mixed], tau * e[1][mixed], rtol=1e-12, atol=1e-15)
+    p1, p2 = a2 <= 1e-10, a2 >= 1 - 1e-10
+    np.testing.assert_allclose(((T1 - 2.0) * C1)[p1], tot[p1], rtol=1e-12)
+    np.testing.assert_allclose(((T2 - 3.0) * C2)[p2], tot[p2], rtol=1e-12)
+    assert np.all(T2[p1] == 3.0) and np.all(T1[p2] == 2.0)
+    assert np.all(T1 >= 2.0) and np.all(T2 >= 3.0)
+
+
+def test_visc_heat_sine_mode_closed_form(orc):
+    """1D periodic, constant mu and alpha: u = A sin(2 pi x) heats the cells
+    by tau (4/3) mu/h^2 times sum (u_{i+1} - u_i)^2 in total, and the sum of
+    squared differences of N samples of a full sine period is 2 N A^2 sin^2(pi/N);
+    phase k takes the fraction alpha_k.  A uniform velocity heats nothing."""
+    N = 40
+    g = orc.make_grid((N, 1, 1))
+    ph = W.base_phases(mu=(0.4, 0.4))
+    shape = (1, 1, N)
+    a2 = np.full(shape, 0.3)
+    m1, m2 = (1 - a2) * 1.0, a2 * 10.0
+    mu = np.full(shape, 0.4)
+    A, tau, h = 0.7, 0.01, 1.0 / N
+    x = (np.arange(N) + 0.5) / N
+    uh = (A * np.sin(2 * np.pi * x)).reshape(shape)
+    T1, T2 = np.ones(shape), np.ones(shape)
+    orc.visc_heat(g, ph, a2, m1, m2, mu, (4.0 / 3.0, 1, 1), tau, uh, T1, T2)
+    heat1 = np.sum((T1 - 1.0) * m1 * ph[0]["cv"])
+    heat2 = np.sum((T2 - 1.0) * m2 * ph[1]["cv"])
+    total = tau * (4.0 / 3.0) * 0.4 / h ** 2 * 2 * N * A ** 2 * np.sin(np.pi / N) ** 2
+    assert heat1 + heat2 == pytest.approx(total, rel=1e-12)
+    assert heat2 / (heat1 + heat2) == pytest.approx(0.3, rel=1e-12)
+    T1u, T2u = np.ones(shape), np.ones(shape)
+    orc.visc_heat(g, ph, a2, m1, m2, mu, (4.0 / 3.0, 1, 1), tau, np.full(shape, 0.37), T1u, T2u)
+    assert np.all(T1u == 1.0) and np.all(T2u == 1.0)
+
+
+def test_visc_heat_in_the_step_uses_the_predicted_velocity(orc):
+    """In a step with viscous heating the phases gain, per velocity component,
+    the dissipation of the velocity after the first 2P-2 stages of its pass
+    (reproduced here from the pass's stored stages), before relaxation."""
+    wl = W.bubbles3d(12)
+    g = orc.make_grid(wl["n"], wl["h"], wl["bc"])
+    f = {k: v.copy() for k, v in wl["fields"].items()}
+    ph = wl["phases"]
+    tau = 2e-3
+    # by hand: the three passes with stored stages, heating from the last stored stage
+    T1, T2 = f["T1"].copy(), f["T2"].copy()
+    rho = f["m1"] + f["m2"]
+    mu = (1 - f["alpha2"]) * ph[0]["mu"] + f["alpha2"] * ph[1]["mu"]
+    vel = {c: f[c].copy() for c in "uvw"}
+    for comp, cname in enumerate("uvw"):
+        s = [1.0, 1.0, 1.0]
+        s[comp] = 4.0 / 3.0
+        lam = orc.gershgorin(g, mu, rho, s)
+        P = orc.lim_P(tau, lam)
+        b = orc.lim_params(P, lam)
+        out, st = orc.lim_pass(g, mu, rho, tau, b, vel[cname], vel[cname], scale=s, keep_stages=True)
+        orc.visc_heat(g, ph, f["alpha2"], f["m1"], f["m2"], mu, s, tau, np.ascontiguousarray(st[-1]), T1, T2)
+        vel[cname] = out
+    orc.relax(g, ph, f["alpha2"], f["m1"], f["m2"], T1, T2)
+    # the step's viscous part, then stop before heat conduction: compare after
+    # one step with zero conductivity (heat conduction is then the identity)
+    ph0 = [dict(p, k0=0.0) for p in ph]
+    orc.step(g, ph0, orc.StepOpts(tau=tau, passes=1, do_viscous=1, visc_heating=1), f)
+    for cname in "uvw":
+        np.testing.assert_allclose(f[cname], vel[cname], rtol=0, atol=1e-15 * np.abs(vel[cname]).max())
+    np.testing.assert_allclose(f["T1"], T1, rtol=1e-14, atol=0)
+    assert np.max(T1 - np.maximum(wl["fields"]["T1"], 0)) > 1e-9  # the heating is visible
+    assert np.all(f["T1"] >= np.minimum(wl["fields"]["T1"], wl["fields"]["T2"]) - 1e-15)
+
+
 # ----------------------------------------------------------------- helpers
 
 def const_problem(orc, n=(16, 12, 1), Lam0=0.7, C0=1.3, h=None, bc=None):
