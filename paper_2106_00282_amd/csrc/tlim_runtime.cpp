@@ -50,6 +50,7 @@ struct tlim_ctx {
     double* field[TLIM_NFIELDS];
     bool fset[TLIM_NFIELDS];
     double *Tn, *Tnew, *a2n, *Lam, *rC, *rhs, *vb[2];
+    double* Lam_alt;  // the next pass's conductivities, built by the pass before
     const double* g_heat;  // right-hand side g of the heat passes: rhs, or Tn when there is no source
     float *Lam32, *rC32, *q32, *wb[2];
     double* acc;           // reduction rows: kTargets x kSlots
@@ -117,7 +118,7 @@ tlim_status fail(tlim_ctx* c, tlim_status s, const char* fmt, ...) {
 // Layout of the workspace: byte offsets of every array (all 256-aligned).
 struct Layout {
     size_t field[TLIM_NFIELDS];
-    size_t Tn, Tn2, Tnew, a2n, Lam, rC, rhs, vb[2], acc, res;
+    size_t Tn, Tn2, Tnew, a2n, Lam, Lam2, rC, rhs, vb[2], acc, res;
     size_t Lam32, rC32, q32, wb[2];
     size_t total;
 };
@@ -131,7 +132,7 @@ Layout layout_of(const int64_t n[3], int precision) {
         L.field[i] = off;
         off += d;
     }
-    size_t* dd[] = {&L.Tn, &L.Tn2, &L.Tnew, &L.a2n, &L.Lam, &L.rC, &L.rhs, &L.vb[0], &L.vb[1]};
+    size_t* dd[] = {&L.Tn, &L.Tn2, &L.Tnew, &L.a2n, &L.Lam, &L.Lam2, &L.rC, &L.rhs, &L.vb[0], &L.vb[1]};
     for (size_t* p : dd) {
         *p = off;
         off += d;
@@ -366,9 +367,13 @@ struct Vhat {
     const float* w32 = nullptr;
 };
 
+// nc (FP64, nullable): the launch that reaches the final stage also builds
+// the next pass's coefficients when it can; *nc_done tells whether it did.
 void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const PassSchedule& ps, const double* v0,
                   const double* rhs, double* out, const double* Tit, tlim::PassSlots slots, Timer& tm,
-                  SweepCount& sc, bool have_q = false, Vhat* vh = nullptr) {
+                  SweepCount& sc, bool have_q = false, Vhat* vh = nullptr, const tlim::NextCoef* nc = nullptr,
+                  bool* nc_done = nullptr) {
+    if (nc_done) *nc_done = false;
     const int nst = ps.nst;
     hipStream_t s = c->stream;
     if (c->precision == TLIM_FP32 && !have_q)
@@ -409,7 +414,7 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
             bool last = !vh && m + k == nst;
             double* nxt = last ? out : c->vb[pp];
             int done = tlim::launch_sweeps64(s, g, face, cur, rhs, c->Lam, c->rC, nxt, ps.at(m), k, last, tau, Tit,
-                                             slots);
+                                             slots, last ? nc : nullptr, last ? nc_done : nullptr);
             cur = nxt;
             pp ^= 1;
             m += done;
@@ -611,6 +616,14 @@ void record_schedule(tlim_ctx* c, int passes, const double* lam, double dt) {
     c->hist_passes = passes;
 }
 
+// The blocked FP64 sweep can build the next pass's coefficients in its last
+// launch: 2D grids without sources (conductivities from T and alpha2 only)
+// and equal p_inf (1/C and alpha2 fixed within the step).
+bool next_coef_ok(const tlim_ctx* c, const DevGrid& g) {
+    return c->precision == TLIM_FP64 && fast_coeffs(c, g) && g.nz == 1 &&
+           c->phase[0].pinf == c->phase[1].pinf;
+}
+
 // pass0_done: the coefficients and bound of the first pass were built with
 // the relaxation (and the accumulator rows zeroed before it).
 tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_step_report* rep, Timer& tm,
@@ -626,8 +639,10 @@ tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_st
         double tmax = result(c, tlim::tgt_tmax(i)), dmax = result(c, tlim::tgt_dmax(i));
         return tmax > 0.0 ? dmax / tmax : dmax;
     };
+    bool coef_ready = pass0_done;  // this pass's coefficients were built by the step before it
     for (it = 0; it < o->passes; ++it) {
-        if (!(it == 0 && pass0_done)) heat_coeffs(c, g, ph, o, row(c, tlim::tgt_lam(it)), it);
+        if (!coef_ready) heat_coeffs(c, g, ph, o, row(c, tlim::tgt_lam(it)), it);
+        coef_ready = false;
         // previous iterate T^(it) (T^(0) = T^n)
         const double* Tit = it == 0 ? c->Tn : c->field[TLIM_T1];
         double lam = 0.0;
@@ -672,8 +687,11 @@ tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_st
             }
             if (!(res < o->cycle_tol)) out.cycle_fail = true;  // keep the last iterate
         } else {
+            tlim::NextCoef nc{row(c, tlim::tgt_lam(it + 1)), c->field[TLIM_ALPHA2], c->Lam_alt, ph};
+            const bool want = !need_update && it + 1 < o->passes && next_coef_ok(c, g);
             run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->g_heat, c->Tnew, need_update ? nullptr : Tit,
-                         pass_slots(c, it), tm, sc, true);
+                         pass_slots(c, it), tm, sc, true, nullptr, want ? &nc : nullptr, &coef_ready);
+            if (coef_ready) std::swap(c->Lam, c->Lam_alt);
         }
         if (need_update) {
             tlim::launch_pass_update(s, g, ph, o->alpha_eps, Tit, c->Tnew, c->Tn, c->a2n,
@@ -842,6 +860,7 @@ tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
     c->Tnew = (double*)(base + L.Tnew);
     c->a2n = (double*)(base + L.a2n);
     c->Lam = (double*)(base + L.Lam);
+    c->Lam_alt = (double*)(base + L.Lam2);
     c->rC = (double*)(base + L.rC);
     c->rhs = (double*)(base + L.rhs);
     c->vb[0] = (double*)(base + L.vb[0]);
@@ -1068,13 +1087,18 @@ void enqueue_predicted(tlim_ctx* c, const tlim_step_opts* o, tlim_ctx::Pending& 
     relax_step(c, o);
     Timer tm{c, false};
     SweepCount sc;
+    bool coef_ready = true;  // the first pass's coefficients come with the relaxation
     for (int it = 0; it < o->passes; ++it) {
-        if (it > 0) heat_coeffs(c, g, ph, o, row(c, tlim::tgt_lam(it)), it);
+        if (!coef_ready) heat_coeffs(c, g, ph, o, row(c, tlim::tgt_lam(it)), it);
         const double* Tit = it == 0 ? c->Tn : c->field[TLIM_T1];
         const int P = c->hist_P[it];
         p.P_used[it] = P;
         PassSchedule ps = device_schedule(P, o->order, row(c, tlim::tgt_lam(it)));
-        run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->g_heat, c->Tnew, Tit, pass_slots(c, it), tm, sc, true);
+        tlim::NextCoef nc{row(c, tlim::tgt_lam(it + 1)), c->field[TLIM_ALPHA2], c->Lam_alt, ph};
+        const bool want = it + 1 < o->passes && next_coef_ok(c, g);
+        run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->g_heat, c->Tnew, Tit, pass_slots(c, it), tm, sc, true,
+                     nullptr, want ? &nc : nullptr, &coef_ready);
+        if (coef_ready) std::swap(c->Lam, c->Lam_alt);
         std::swap(c->field[TLIM_T1], c->Tnew);
     }
     tlim::launch_collect(s, c->acc, c->res_host_dev, tlim::tgt_lam(0), tlim::tgt_lam(o->passes), 1);

@@ -28,9 +28,20 @@ struct Stages {
 // launches of a pass get equal shares of at most KMAX stages).
 int sweeps_per_launch(const DevGrid& g, int count);
 
+// The next Picard pass's coefficients, built by the launch that reaches the
+// final stage when it can (FP64 blocked 2D launches): Lam = sum_k alpha_k
+// lambda_k(T^(it+1)) and the Gershgorin bound (max into the row lam), with
+// 1/C unchanged (equal p_inf).  nc_done tells whether that happened.
+struct NextCoef {
+    double* lam;
+    const double* alpha2;
+    double* Lam;  // must not be the Lam the pass reads
+    DevPhases ph;
+};
+
 int launch_sweeps64(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
                     const double* Lam, const double* rC, double* out, Stages st, int count, bool last, double tau,
-                    const double* Tit, PassSlots ps);
+                    const double* Tit, PassSlots ps, const NextCoef* nc = nullptr, bool* nc_done = nullptr);
 
 int launch_sweeps32(hipStream_t s, const DevGrid& g, int face, const float* w, const float* qn,
                     const float* Lam32, const float* rC32, float* out, Stages st, int count, bool last, double tau,

@@ -55,9 +55,18 @@ struct TBArgs {
     const double* rC64;
     double* out64;
     double g64w[2];          // face weights in double for that stage
+    // FP64, launch with the final stage: with lam_next != NULL also the next
+    // Picard pass's conductivities (Lam_next) and Gershgorin bound (max into
+    // the row lam_next) from the new iterate; the output ring is then one
+    // cell narrower (halo H = K + 1) so that the new iterate is known on the
+    // neighbours of every output cell.
+    double* lam_next;
+    const double* alpha2;
+    double* Lam_next;
+    DevPhases ph;
     int nx, ny, perx, pery;
     R wx, wy, tau;
-    int K, face, tiles_x, ox, oy;
+    int K, H, face, tiles_x, ox, oy;
     double taud;
     double tb[KMAX], chat[KMAX];
 };
@@ -67,10 +76,10 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
     __shared__ R sh_lo[2][WAVES][64];  // row 0 of each wave (the "up" row of the wave below)
     __shared__ R sh_hi[2][WAVES][64];  // row ROWS-1 of each wave (the "down" row of the wave above)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int K = a.K;
+    const int K = a.K, H = a.H;
     const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
-    const int xg = tx * a.ox - K + lane;
-    const int yg0 = ty * a.oy - K + wv * ROWS;
+    const int xg = tx * a.ox - H + lane;
+    const int yg0 = ty * a.oy - H + wv * ROWS;
     const int xi = fold(xg, a.nx, a.perx);
     const bool inx = xg >= 0 && xg < a.nx;
     const bool fL = a.perx ? a.nx > 1 : (inx && xg > 0);
@@ -162,13 +171,13 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
         }
         // the output cells are exact after every stage: keep the intermediate
         // stages when asked (the adjoint's recomputation)
-        if (a.stages && s + 1 < K && lane >= K && lane < 64 - K && xg < a.nx) {
+        if (a.stages && s + 1 < K && lane >= H && lane < 64 - H && xg < a.nx) {
             R* dst = a.stages + (int64_t)(s + 1) * a.sstride;
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
                 const int row = wv * ROWS + r;
                 const int y = yg0 + r;
-                if (row >= K && row < EXT_Y - K && y < a.ny) dst[(int64_t)y * a.nx + xg] = v[r];
+                if (row >= H && row < EXT_Y - H && y < a.ny) dst[(int64_t)y * a.nx + xg] = v[r];
             }
         }
     }
@@ -217,12 +226,12 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
         }
     }
     double dmax = 0.0, tmax = 0.0, bad = 0.0;
-    if (lane >= K && lane < 64 - K && xg < a.nx) {
+    if (lane >= H && lane < 64 - H && xg < a.nx) {
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int row = wv * ROWS + r;
             const int y = yg0 + r;
-            if (row >= K && row < EXT_Y - K && y < a.ny) {
+            if (row >= H && row < EXT_Y - H && y < a.ny) {
                 const int64_t o = (int64_t)y * a.nx + xg;
                 double tnew;
                 if (fin) {
@@ -256,14 +265,69 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
             if (bad != 0.0) atomicAdd(a.ps.bad + sl, bad);
         }
     }
+    if constexpr (!kFloat) {
+        if (a.lam_next) {
+            // Coefficients of the next Picard pass at the new iterate v (valid
+            // K cells in from the edge): Lambda = sum_k alpha_k lambda_k(v),
+            // and at the output cells (K+1 in) the bound 2 rC sum_f w_f
+            // mean(Lambda_a, Lambda_b), faces in the order -x, +x, -y, +y.
+            double Ln[ROWS];
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int64_t idx = (int64_t)fold(yg0 + r, a.ny, a.pery) * a.nx + xi;
+                Ln[r] = phys::cell_conductivity(a.ph, v[r], a.alpha2[idx]);
+            }
+            // the seam buffer not used by the last stage: its reads all
+            // precede that stage's barrier
+            const int b2 = (K + 1) & 1;
+            sh_lo[b2][wv][lane] = Ln[0];
+            sh_hi[b2][wv][lane] = Ln[ROWS - 1];
+            __syncthreads();
+            const double Ldn = wv > 0 ? sh_hi[b2][wv - 1][lane] : Ln[0];
+            const double Lup = wv < WAVES - 1 ? sh_lo[b2][wv + 1][lane] : Ln[ROWS - 1];
+            double bound = 0.0;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const double Ll = from_left(Ln[r]), Lr = from_right(Ln[r]);
+                const double Ld = r > 0 ? Ln[r - 1] : Ldn;
+                const double Lu = r < ROWS - 1 ? Ln[r + 1] : Lup;
+                const int row = wv * ROWS + r;
+                const int y = yg0 + r;
+                if (lane >= H && lane < 64 - H && xg < a.nx && row >= H && row < EXT_Y - H && y < a.ny) {
+                    const bool fD = a.pery ? a.ny > 1 : y > 0;
+                    const bool fU = a.pery ? a.ny > 1 : y < a.ny - 1;
+                    const int64_t o = (int64_t)y * a.nx + xg;
+                    double d = 0.0;
+                    if (fL) d += a.wx * fmean<double>(Ln[r], Ll, a.face);
+                    if (fR) d += a.wx * fmean<double>(Ln[r], Lr, a.face);
+                    if (fD) d += a.wy * fmean<double>(Ln[r], Ld, a.face);
+                    if (fU) d += a.wy * fmean<double>(Ln[r], Lu, a.face);
+                    bound = fmax(bound, 2.0 * d * a.rC[o]);
+                    a.Lam_next[o] = Ln[r];
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) bound = fmax(bound, __shfl_xor(bound, o, 64));
+            if (lane == 0) {
+                const int sl = (int)(((int64_t)blockIdx.x * WAVES + wv) % kSlots);
+                atomicMax((unsigned long long*)(a.lam_next + sl), (unsigned long long)__double_as_longlong(bound + 0.0));
+            }
+        }
+    }
 }
 
 template <typename R>
 int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* G, const R* Lam, const R* rC,
                 R* out, Stages st, int count, double tau, const double* Tit, PassSlots ps, R* stages = nullptr,
                 int64_t sstride = 0, const double* g64 = nullptr, const double* rC64 = nullptr,
-                double* out64 = nullptr) {
+                double* out64 = nullptr, const NextCoef* nc = nullptr) {
     TBArgs<R> a{};
+    if (nc) {
+        a.lam_next = nc->lam;
+        a.alpha2 = nc->alpha2;
+        a.Lam_next = nc->Lam;
+        a.ph = nc->ph;
+    }
     a.g64 = g64;
     a.rC64 = rC64;
     a.out64 = out64;
@@ -289,9 +353,10 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
     a.tau = (R)tau;
     a.taud = tau;
     a.K = K;
+    a.H = nc ? K + 1 : K;
     a.face = face;
-    a.ox = 64 - 2 * K;
-    a.oy = EXT_Y - 2 * K;
+    a.ox = 64 - 2 * a.H;
+    a.oy = EXT_Y - 2 * a.H;
     a.tiles_x = (g.nx + a.ox - 1) / a.ox;
     int tiles_y = (g.ny + a.oy - 1) / a.oy;
     for (int k = 0; k < K; ++k) {
@@ -335,9 +400,14 @@ int sweeps_per_launch(const DevGrid& g, int count) {
 
 int launch_sweeps64(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,
                     const double* Lam, const double* rC, double* out, Stages st, int count, bool last, double tau,
-                    const double* Tit, PassSlots ps) {
-    if (use_tb2d(g, count))
-        return launch_tb2d<double>(s, g, face, v, rhs, Lam, rC, out, st, count, tau, last ? Tit : nullptr, ps);
+                    const double* Tit, PassSlots ps, const NextCoef* nc, bool* nc_done) {
+    if (nc_done) *nc_done = false;
+    if (use_tb2d(g, count)) {
+        const bool with_nc = last && nc != nullptr;
+        if (nc_done) *nc_done = with_nc;
+        return launch_tb2d<double>(s, g, face, v, rhs, Lam, rC, out, st, count, tau, last ? Tit : nullptr, ps,
+                                   nullptr, 0, nullptr, nullptr, nullptr, with_nc ? nc : nullptr);
+    }
     if (use_z3d(g)) {
         if (last) launch_z3d<double>(s, g, face, v, rhs, Lam, rC, out, StageParam{nullptr, 0.0, 0.0}, tau, Tit, ps);
         else launch_z3d<double>(s, g, face, v, rhs, Lam, rC, out, one_stage(st), tau, nullptr, PassSlots{});
