@@ -54,6 +54,10 @@ bool use_z3d(const DevGrid& g);
 template <typename R>
 void launch_z3d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* G, const R* Lam, const R* rC, R* out,
                 StageParam sp, double tau, const double* Tit, PassSlots ps);
+// The FP32 correction form's final stage on a 3D grid (as launch_final32).
+void launch_z3d_final32(hipStream_t s, const DevGrid& g, int face, const float* w, const double* rhs,
+                        const float* Lam32, const double* rC, double* out, double tau, const double* Tit,
+                        PassSlots ps);
 
 // Blocked FP64 stages that also keep their intermediate results: the result
 // of the launch's stage k (k = 1 .. K-1) goes to stages + k*sstride and the

@@ -432,7 +432,8 @@ int launch_sweeps32(hipStream_t s, const DevGrid& g, int face, const float* w, c
         return launch_tb2d<float>(s, g, face, w, qn, Lam32, rC32, out, st, count, tau, nullptr, PassSlots{});
     }
     if (last) {
-        launch_final32(s, g, face, w, rhs, Lam32, rC, out64, tau, Tit, ps);
+        if (use_z3d(g)) launch_z3d_final32(s, g, face, w, rhs, Lam32, rC, out64, tau, Tit, ps);
+        else launch_final32(s, g, face, w, rhs, Lam32, rC, out64, tau, Tit, ps);
     } else if (use_z3d(g)) {
         launch_z3d<float>(s, g, face, w, qn, Lam32, rC32, out, one_stage(st), tau, nullptr, PassSlots{});
     } else {

@@ -45,9 +45,14 @@ struct Z3Args {
     int nx, ny, nz, perx, pery, perz;
     double wx, wy, wz;
     int face, tiles_x, tiles_y, zc, nwaves;
+    // kCorr (R = double): the final stage of the FP32 correction form, on
+    // v = G + w32 with the float conductivities Lam32 (G = g, rC = 1/C in
+    // double); v and Lam are then unused
+    const float* w32;
+    const float* Lam32;
 };
 
-template <typename R, int ROWS>
+template <typename R, int ROWS, bool kCorr>
 __global__ void __launch_bounds__(64 * kZWaves) k_z3d(Z3Args<R> a) {
     constexpr int RW = ROWS + 2;
     const int lane = threadIdx.x & 63;
@@ -92,12 +97,20 @@ __global__ void __launch_bounds__(64 * kZWaves) k_z3d(Z3Args<R> a) {
     R Gc[ROWS], rc_c[ROWS], Gn[ROWS], rc_n[ROWS], hvc[ROWS], hLc[ROWS], hvn[ROWS], hLn[ROWS];
     const unsigned hx = (unsigned)(lane == 0 ? xl : xr);
     const bool halo_lane = lane == 0 || lane == 63;
+    auto ld_v = [&](unsigned i) -> R {
+        if constexpr (kCorr) return a.G[i] + (R)a.w32[i];
+        else return a.v[i];
+    };
+    auto ld_L = [&](unsigned i) -> R {
+        if constexpr (kCorr) return (R)a.Lam32[i];
+        else return a.Lam[i];
+    };
     auto load_plane = [&](int z, R* vv, R* LL) {
         const unsigned pz = (unsigned)fold(z, nz, a.perz) * plane;
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
-            vv[r] = a.v[pz + rowoff[r] + uxi];
-            LL[r] = a.Lam[pz + rowoff[r] + uxi];
+            vv[r] = ld_v(pz + rowoff[r] + uxi);
+            LL[r] = ld_L(pz + rowoff[r] + uxi);
         }
     };
     // own cells of plane z (clamped into the grid: only used for z < z1):
@@ -111,8 +124,8 @@ __global__ void __launch_bounds__(64 * kZWaves) k_z3d(Z3Args<R> a) {
             hv[r] = R(0);
             hL[r] = R(0);
             if (halo_lane) {
-                hv[r] = a.v[pz + rowoff[r + 1] + hx];
-                hL[r] = a.Lam[pz + rowoff[r + 1] + hx];
+                hv[r] = ld_v(pz + rowoff[r + 1] + hx);
+                hL[r] = ld_L(pz + rowoff[r + 1] + hx);
             }
         }
     };
@@ -208,14 +221,14 @@ constexpr int z_rows() {
     return sizeof(R) == 8 ? 4 : 8;
 }
 
-}  // namespace
 
-bool use_z3d(const DevGrid& g) { return g.nz > 1 && g.N < ((int64_t)1 << 32); }
-
-template <typename R>
-void launch_z3d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* G, const R* Lam, const R* rC, R* out,
-                StageParam sp, double tau, const double* Tit, PassSlots ps) {
+template <typename R, bool kCorr>
+void launch_z3d_impl(hipStream_t s, const DevGrid& g, int face, const R* v, const R* G, const R* Lam, const R* rC,
+                     R* out, StageParam sp, double tau, const double* Tit, PassSlots ps, const float* w32,
+                     const float* Lam32) {
     Z3Args<R> a{};
+    a.w32 = w32;
+    a.Lam32 = Lam32;
     a.v = v;
     a.G = G;
     a.Lam = Lam;
@@ -246,8 +259,25 @@ void launch_z3d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
     const int64_t nw = cols * ((g.nz + a.zc - 1) / a.zc);
     a.nwaves = (int)nw;
     const unsigned blocks = (unsigned)((nw + kZWaves - 1) / kZWaves);
-    hipLaunchKernelGGL((k_z3d<R, rows>), dim3(blocks), dim3(64 * kZWaves), 0, s, a);
+    hipLaunchKernelGGL((k_z3d<R, rows, kCorr>), dim3(blocks), dim3(64 * kZWaves), 0, s, a);
 }
+
+}  // namespace
+
+template <typename R>
+void launch_z3d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* G, const R* Lam, const R* rC, R* out,
+                StageParam sp, double tau, const double* Tit, PassSlots ps) {
+    launch_z3d_impl<R, false>(s, g, face, v, G, Lam, rC, out, sp, tau, Tit, ps, nullptr, nullptr);
+}
+
+void launch_z3d_final32(hipStream_t s, const DevGrid& g, int face, const float* w, const double* rhs,
+                        const float* Lam32, const double* rC, double* out, double tau, const double* Tit,
+                        PassSlots ps) {
+    launch_z3d_impl<double, true>(s, g, face, nullptr, rhs, nullptr, rC, out, StageParam{nullptr, 0.0, 0.0}, tau, Tit,
+                                  ps, w, Lam32);
+}
+
+bool use_z3d(const DevGrid& g) { return g.nz > 1 && g.N < ((int64_t)1 << 32); }
 
 template void launch_z3d<double>(hipStream_t, const DevGrid&, int, const double*, const double*, const double*,
                                  const double*, double*, StageParam, double, const double*, PassSlots);
