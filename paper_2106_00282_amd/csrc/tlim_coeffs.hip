@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_coeffs2d(Coef2DArgs a) {
                 if (fD) S += a.wy * fmean<double>(La, (double)(float)Lm, a.face) * (ga - gw[r - 1]);
                 if (fU) S += a.wy * fmean<double>(La, (double)(float)Lp, a.face) * (ga - gw[r + 1]);
                 a.q32[o] = (float)(-a.tau * rf * S);
-                a.w0[o] = 0.0f;
+                if (a.w0) a.w0[o] = 0.0f;
             }
         }
     }
@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_coeffs3d(Coef2DArgs a) {
                     if (fB) S += a.wz * fmean<double>(La, (double)(float)Lm[r], a.face) * (ga - gm[r]);
                     if (fF) S += a.wz * fmean<double>(La, (double)(float)Lp[r], a.face) * (ga - gp[r]);
                     a.q32[o] = (float)(-a.tau * rf * S);
-                    a.w0[o] = 0.0f;
+                    if (a.w0) a.w0[o] = 0.0f;
                 }
             }
         }

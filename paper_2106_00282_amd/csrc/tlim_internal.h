@@ -106,7 +106,8 @@ void launch_heat_coeffs_bound(hipStream_t s, const DevGrid& g, const DevPhases& 
 // one pass over (T, alpha2) in column strips.  g = Tn is not copied (the
 // stages read Tn).  rebuild = 0 keeps rC (and rC32) from an earlier pass of
 // the step -- valid when 1/C does not depend on T (equal p_inf).  Lam may be
-// NULL (FP32 contexts need Lam32 only); q32/w0 as above (w0 = 0).
+// NULL (FP32 contexts need Lam32 only); q32 as above; w0 = 0 is written
+// only when w0 != NULL.
 // With T2_relax != NULL the kernel first relaxes every cell from (alpha2,
 // T = T1, T2_relax, m1, m2) -- as launch_relax -- and builds the coefficients
 // at the relaxed state (rebuild implied); the relaxed T goes to Tn_out (also

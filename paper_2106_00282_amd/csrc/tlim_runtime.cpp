@@ -53,6 +53,9 @@ struct tlim_ctx {
     double* Lam_alt;  // the next pass's conductivities, built by the pass before
     const double* g_heat;  // right-hand side g of the heat passes: rhs, or Tn when there is no source
     float *Lam32, *rC32, *q32, *wb[2];
+    float *Lam32_alt, *q32_alt;  // the next pass's float coefficients, built by the pass before
+    float* wzero;                // all zero: the correction form's start w0 = T^n - g without sources
+    bool w0_zero;                // the coefficients of the current pass came without sources
     double* acc;           // reduction rows: kTargets x kSlots
     PassResult* res_dev;   // folded results (one double per target)
     PassResult* res_host;  // pinned copy (the current block of res_blk)
@@ -119,7 +122,7 @@ tlim_status fail(tlim_ctx* c, tlim_status s, const char* fmt, ...) {
 struct Layout {
     size_t field[TLIM_NFIELDS];
     size_t Tn, Tn2, Tnew, a2n, Lam, Lam2, rC, rhs, vb[2], acc, res;
-    size_t Lam32, rC32, q32, wb[2];
+    size_t Lam32, rC32, q32, wb[2], Lam32b, q32b, wzero;
     size_t total;
 };
 
@@ -142,7 +145,7 @@ Layout layout_of(const int64_t n[3], int precision) {
     L.res = off;
     off += align_up(sizeof(PassResult));
     if (precision == TLIM_FP32) {
-        size_t* ff[] = {&L.Lam32, &L.rC32, &L.q32, &L.wb[0], &L.wb[1]};
+        size_t* ff[] = {&L.Lam32, &L.rC32, &L.q32, &L.wb[0], &L.wb[1], &L.Lam32b, &L.q32b, &L.wzero};
         for (size_t* p : ff) {
             *p = off;
             off += f;
@@ -383,7 +386,8 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
     if (c->precision == TLIM_FP32) {
         // 2P-2 float stages on the correction, the final one in double; the
         // launch that reaches it writes `out`
-        const float* cur = c->wb[0];
+        // w0 = 0 without sources: start from the zero array (no write needed)
+        const float* cur = have_q && c->w0_zero ? c->wzero : c->wb[0];
         int m = 0;
         const int upto = vh ? nst - 1 : nst;  // with vh the final stage runs on its own
         while (m < upto) {
@@ -391,7 +395,8 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
             bool last = !vh && m + k == nst;
             float* nxt = cur == c->wb[0] ? c->wb[1] : c->wb[0];
             int done = tlim::launch_sweeps32(s, g, face, cur, c->q32, c->Lam32, c->rC32, nxt, ps.at(m), k, last, tau,
-                                             rhs, c->rC, out, Tit, slots);
+                                             rhs, c->rC, out, Tit, slots, last ? nc : nullptr,
+                                             last ? nc_done : nullptr);
             cur = nxt;
             m += done;
             sc.launches++;
@@ -527,8 +532,9 @@ void heat_coeffs(tlim_ctx* c, const DevGrid& g, const DevPhases& ph, const tlim_
         const bool need_lam64 = c->precision == TLIM_FP64 || o->cycle_mode;
         tlim::launch_coeffs2d(c->stream, g, ph, o->alpha_eps, o->dt, o->face_mean, T, c->field[TLIM_ALPHA2],
                               c->field[TLIM_M1], c->field[TLIM_M2], c->Tn, rebuild ? 1 : 0,
-                              need_lam64 ? c->Lam : nullptr, c->rC, c->Lam32, c->rC32, c->q32, c->wb[0], lam);
+                              need_lam64 ? c->Lam : nullptr, c->rC, c->Lam32, c->rC32, c->q32, nullptr, lam);
         c->g_heat = c->Tn;
+        c->w0_zero = true;
         return;
     }
     tlim::launch_heat_coeffs_bound(c->stream, g, ph, o->alpha_eps, o->dt, o->face_mean, T, c->field[TLIM_ALPHA2],
@@ -537,6 +543,7 @@ void heat_coeffs(tlim_ctx* c, const DevGrid& g, const DevPhases& ph, const tlim_
                                    c->fset[TLIM_SRC2] ? c->field[TLIM_SRC2] : nullptr, c->Lam, c->rC, c->rhs,
                                    c->Lam32, c->rC32, c->q32, c->wb[0], lam);
     c->g_heat = c->rhs;
+    c->w0_zero = false;
 }
 
 // Chebyshev cycles to the backward-Euler solution of one pass (cycle mode).
@@ -620,8 +627,23 @@ void record_schedule(tlim_ctx* c, int passes, const double* lam, double dt) {
 // launch: 2D grids without sources (conductivities from T and alpha2 only)
 // and equal p_inf (1/C and alpha2 fixed within the step).
 bool next_coef_ok(const tlim_ctx* c, const DevGrid& g) {
-    return c->precision == TLIM_FP64 && fast_coeffs(c, g) && g.nz == 1 &&
-           c->phase[0].pinf == c->phase[1].pinf;
+    return fast_coeffs(c, g) && g.nz == 1 && c->phase[0].pinf == c->phase[1].pinf;
+}
+
+// After a pass whose last launch built the next pass's coefficients.
+void adopt_next_coef(tlim_ctx* c) {
+    if (c->precision == TLIM_FP32) {
+        std::swap(c->Lam32, c->Lam32_alt);
+        std::swap(c->q32, c->q32_alt);
+        c->w0_zero = true;
+    } else {
+        std::swap(c->Lam, c->Lam_alt);
+    }
+}
+
+tlim::NextCoef next_coef(tlim_ctx* c, int it, const DevPhases& ph) {
+    return tlim::NextCoef{row(c, tlim::tgt_lam(it + 1)), c->field[TLIM_ALPHA2], c->Lam_alt, c->Lam32_alt, c->q32_alt,
+                          ph};
 }
 
 // pass0_done: the coefficients and bound of the first pass were built with
@@ -687,11 +709,11 @@ tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_st
             }
             if (!(res < o->cycle_tol)) out.cycle_fail = true;  // keep the last iterate
         } else {
-            tlim::NextCoef nc{row(c, tlim::tgt_lam(it + 1)), c->field[TLIM_ALPHA2], c->Lam_alt, ph};
+            tlim::NextCoef nc = next_coef(c, it, ph);
             const bool want = !need_update && it + 1 < o->passes && next_coef_ok(c, g);
             run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->g_heat, c->Tnew, need_update ? nullptr : Tit,
                          pass_slots(c, it), tm, sc, true, nullptr, want ? &nc : nullptr, &coef_ready);
-            if (coef_ready) std::swap(c->Lam, c->Lam_alt);
+            if (coef_ready) adopt_next_coef(c);
         }
         if (need_update) {
             tlim::launch_pass_update(s, g, ph, o->alpha_eps, Tit, c->Tnew, c->Tn, c->a2n,
@@ -878,9 +900,15 @@ tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
         c->q32 = (float*)(base + L.q32);
         c->wb[0] = (float*)(base + L.wb[0]);
         c->wb[1] = (float*)(base + L.wb[1]);
+        c->Lam32_alt = (float*)(base + L.Lam32b);
+        c->q32_alt = (float*)(base + L.q32b);
+        c->wzero = (float*)(base + L.wzero);
+        HIP_TRY(c, hipMemsetAsync(c->wzero, 0, sizeof(float) * (size_t)c->N, c->stream));
     } else {
         c->Lam32 = c->rC32 = c->q32 = c->wb[0] = c->wb[1] = nullptr;
+        c->Lam32_alt = c->q32_alt = c->wzero = nullptr;
     }
+    c->w0_zero = false;
     return TLIM_OK;
 }
 
@@ -970,8 +998,9 @@ bool relax_step(tlim_ctx* c, const tlim_step_opts* o) {
         const bool need_lam64 = c->precision == TLIM_FP64 || o->cycle_mode;
         tlim::launch_coeffs2d(s, g, ph, o->alpha_eps, o->dt, o->face_mean, c->field[TLIM_T1], c->field[TLIM_ALPHA2],
                               c->field[TLIM_M1], c->field[TLIM_M2], nullptr, 1, need_lam64 ? c->Lam : nullptr, c->rC,
-                              c->Lam32, c->rC32, c->q32, c->wb[0], row(c, tlim::tgt_lam(0)), T2_ptr(c), c->Tn,
+                              c->Lam32, c->rC32, c->q32, nullptr, row(c, tlim::tgt_lam(0)), T2_ptr(c), c->Tn,
                               c->a2n);
+        c->w0_zero = true;
         std::swap(c->field[TLIM_ALPHA2], c->a2n);
         if (B1) tlim::launch_copy(s, c->a2n, c->field[TLIM_ALPHA2], c->N);  // kept for a rollback
         c->g_heat = c->Tn;
@@ -1094,11 +1123,11 @@ void enqueue_predicted(tlim_ctx* c, const tlim_step_opts* o, tlim_ctx::Pending& 
         const int P = c->hist_P[it];
         p.P_used[it] = P;
         PassSchedule ps = device_schedule(P, o->order, row(c, tlim::tgt_lam(it)));
-        tlim::NextCoef nc{row(c, tlim::tgt_lam(it + 1)), c->field[TLIM_ALPHA2], c->Lam_alt, ph};
+        tlim::NextCoef nc = next_coef(c, it, ph);
         const bool want = it + 1 < o->passes && next_coef_ok(c, g);
         run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->g_heat, c->Tnew, Tit, pass_slots(c, it), tm, sc, true,
                      nullptr, want ? &nc : nullptr, &coef_ready);
-        if (coef_ready) std::swap(c->Lam, c->Lam_alt);
+        if (coef_ready) adopt_next_coef(c);
         std::swap(c->field[TLIM_T1], c->Tnew);
     }
     tlim::launch_collect(s, c->acc, c->res_host_dev, tlim::tgt_lam(0), tlim::tgt_lam(o->passes), 1);

@@ -29,13 +29,17 @@ struct Stages {
 int sweeps_per_launch(const DevGrid& g, int count);
 
 // The next Picard pass's coefficients, built by the launch that reaches the
-// final stage when it can (FP64 blocked 2D launches): Lam = sum_k alpha_k
+// final stage when it can (blocked 2D launches): Lam = sum_k alpha_k
 // lambda_k(T^(it+1)) and the Gershgorin bound (max into the row lam), with
-// 1/C unchanged (equal p_inf).  nc_done tells whether that happened.
+// 1/C unchanged (equal p_inf); in the FP32 form the float conductivities and
+// the correction source instead of Lam.  nc_done tells whether that
+// happened.
 struct NextCoef {
     double* lam;
     const double* alpha2;
-    double* Lam;  // must not be the Lam the pass reads
+    double* Lam;    // FP64 (must not be the Lam the pass reads)
+    float* Lam32;   // FP32 correction form: float conductivities and the
+    float* q32;     // correction source of the next pass (not the ones read)
     DevPhases ph;
 };
 
@@ -45,7 +49,8 @@ int launch_sweeps64(hipStream_t s, const DevGrid& g, int face, const double* v, 
 
 int launch_sweeps32(hipStream_t s, const DevGrid& g, int face, const float* w, const float* qn,
                     const float* Lam32, const float* rC32, float* out, Stages st, int count, bool last, double tau,
-                    const double* rhs, const double* rC, double* out64, const double* Tit, PassSlots ps);
+                    const double* rhs, const double* rC, double* out64, const double* Tit, PassSlots ps,
+                    const NextCoef* nc = nullptr, bool* nc_done = nullptr);
 
 // One stage on a 3D grid by z-marching waves (tlim_sweep3d.hip): as
 // launch_stage64 / launch_stage32, and with Tit != NULL also the pass

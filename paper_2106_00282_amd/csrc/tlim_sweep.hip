@@ -55,14 +55,16 @@ struct TBArgs {
     const double* rC64;
     double* out64;
     double g64w[2];          // face weights in double for that stage
-    // FP64, launch with the final stage: with lam_next != NULL also the next
+    // Launch with the final stage: with lam_next != NULL also the next
     // Picard pass's conductivities (Lam_next) and Gershgorin bound (max into
     // the row lam_next) from the new iterate; the output ring is then one
     // cell narrower (halo H = K + 1) so that the new iterate is known on the
     // neighbours of every output cell.
     double* lam_next;
     const double* alpha2;
-    double* Lam_next;
+    double* Lam_next;        // FP64
+    float* Lam32_next;       // FP32 correction form: float conductivities and
+    float* q32_next;         // the correction source -tau rC' D' g of the next pass
     DevPhases ph;
     int nx, ny, perx, pery;
     R wx, wy, tau;
@@ -223,6 +225,71 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
                 prev = c;
                 Sfin[r] = S;
             }
+            if (a.lam_next) {
+                // Coefficients of the next Picard pass at the new iterate T
+                // (valid K cells in from the edge; g = T^n): the conductivity
+                // in double for the bound, its float rounding and the source
+                // q = -tau rC' D' g from the float-rounded Lambda' and rC', at
+                // the output cells (K+1 in), faces in the order -x, +x, -y, +y.
+                double Ln[ROWS], rc[ROWS];
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) {
+                    const int64_t idx = (int64_t)fold(yg0 + r, a.ny, a.pery) * a.nx + xi;
+                    rc[r] = a.rC64[idx];
+                    const double tn = gfin[r] - a.taud * rc[r] * Sfin[r];
+                    Ln[r] = phys::cell_conductivity(a.ph, tn, a.alpha2[idx]);
+                }
+                __shared__ double esh[4][WAVES][64];  // seams of Lambda and g
+                esh[0][wv][lane] = Ln[0];
+                esh[1][wv][lane] = Ln[ROWS - 1];
+                esh[2][wv][lane] = gfin[0];
+                esh[3][wv][lane] = gfin[ROWS - 1];
+                __syncthreads();
+                const double Ldn = wv > 0 ? esh[1][wv - 1][lane] : Ln[0];
+                const double Lup = wv < WAVES - 1 ? esh[0][wv + 1][lane] : Ln[ROWS - 1];
+                const double gdn = wv > 0 ? esh[3][wv - 1][lane] : gfin[0];
+                const double gup = wv < WAVES - 1 ? esh[2][wv + 1][lane] : gfin[ROWS - 1];
+                const double wxd = a.g64w[0], wyd = a.g64w[1];
+                double bound = 0.0;
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) {
+                    const double L = Ln[r];
+                    const double Ll = from_left(L), Lr = from_right(L);
+                    const float Lf = (float)L;
+                    const float Llf = from_left(Lf), Lrf = from_right(Lf);
+                    const double gl = from_left(gfin[r]), gr = from_right(gfin[r]);
+                    const double Ld = r > 0 ? Ln[r - 1] : Ldn, Lu = r < ROWS - 1 ? Ln[r + 1] : Lup;
+                    const double gd = r > 0 ? gfin[r - 1] : gdn, gu = r < ROWS - 1 ? gfin[r + 1] : gup;
+                    const int row = wv * ROWS + r;
+                    const int y = yg0 + r;
+                    if (lane >= H && lane < 64 - H && xg < a.nx && row >= H && row < EXT_Y - H && y < a.ny) {
+                        const bool fD = a.pery ? a.ny > 1 : y > 0;
+                        const bool fU = a.pery ? a.ny > 1 : y < a.ny - 1;
+                        const int64_t o = (int64_t)y * a.nx + xg;
+                        double d = 0.0;
+                        if (fL) d += wxd * fmean<double>(L, Ll, a.face);
+                        if (fR) d += wxd * fmean<double>(L, Lr, a.face);
+                        if (fD) d += wyd * fmean<double>(L, Ld, a.face);
+                        if (fU) d += wyd * fmean<double>(L, Lu, a.face);
+                        bound = fmax(bound, 2.0 * d * rc[r]);
+                        const double La = (double)Lf, rf = (double)(float)rc[r], ga = gfin[r];
+                        double Sq = 0.0;
+                        if (fL) Sq += wxd * fmean<double>(La, (double)Llf, a.face) * (ga - gl);
+                        if (fR) Sq += wxd * fmean<double>(La, (double)Lrf, a.face) * (ga - gr);
+                        if (fD) Sq += wyd * fmean<double>(La, (double)(float)Ld, a.face) * (ga - gd);
+                        if (fU) Sq += wyd * fmean<double>(La, (double)(float)Lu, a.face) * (ga - gu);
+                        a.Lam32_next[o] = Lf;
+                        a.q32_next[o] = (float)(-a.taud * rf * Sq);
+                    }
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) bound = fmax(bound, __shfl_xor(bound, o, 64));
+                if (lane == 0) {
+                    const int sl = (int)(((int64_t)blockIdx.x * WAVES + wv) % kSlots);
+                    atomicMax((unsigned long long*)(a.lam_next + sl),
+                              (unsigned long long)__double_as_longlong(bound + 0.0));
+                }
+            }
         }
     }
     double dmax = 0.0, tmax = 0.0, bad = 0.0;
@@ -326,6 +393,8 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
         a.lam_next = nc->lam;
         a.alpha2 = nc->alpha2;
         a.Lam_next = nc->Lam;
+        a.Lam32_next = nc->Lam32;
+        a.q32_next = nc->q32;
         a.ph = nc->ph;
     }
     a.g64 = g64;
@@ -424,11 +493,15 @@ int launch_sweeps64(hipStream_t s, const DevGrid& g, int face, const double* v, 
 
 int launch_sweeps32(hipStream_t s, const DevGrid& g, int face, const float* w, const float* qn,
                     const float* Lam32, const float* rC32, float* out, Stages st, int count, bool last, double tau,
-                    const double* rhs, const double* rC, double* out64, const double* Tit, PassSlots ps) {
+                    const double* rhs, const double* rC, double* out64, const double* Tit, PassSlots ps,
+                    const NextCoef* nc, bool* nc_done) {
+    if (nc_done) *nc_done = false;
     if (use_tb2d(g, count)) {
-        if (last)
+        if (last) {
+            if (nc_done) *nc_done = nc != nullptr;
             return launch_tb2d<float>(s, g, face, w, qn, Lam32, rC32, nullptr, st, count, tau, Tit, ps, nullptr, 0,
-                                      rhs, rC, out64);
+                                      rhs, rC, out64, nc);
+        }
         return launch_tb2d<float>(s, g, face, w, qn, Lam32, rC32, out, st, count, tau, nullptr, PassSlots{});
     }
     if (last) {
