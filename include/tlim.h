@@ -60,11 +60,21 @@ enum { TLIM_FACE_ARITH = 0, TLIM_FACE_HARMONIC = 1 };
 
 /* Fields of the state (Sec. 3.4, data of Algorithm 1): volume fraction of
  * phase 2, partial densities m_k = alpha_k rho_k (constant in this step),
- * phase temperatures, velocity components, external heat sources I_k. */
+ * phase temperatures, velocity components, external heat sources I_k, and
+ * the mixture total energy density rho E (optional).  Once E has been set,
+ * every step updates it as the six-equation model's mixture energy equation
+ * does in this sub-step: the viscous part adds, per velocity component, the
+ * divergence of the work of the viscous flux, tau sum_f w_f mu_f uh_f
+ * (uh_b - uh_a) with the predicted velocity uh (Sec. 3.2, total-energy
+ * update); the heat part adds C_eff (T^{n+1} - T^n) with the last Picard
+ * pass's C_eff and the relaxed T^n, which is that pass's conductive flux
+ * divergence plus tau sum_k alpha_k I_k (Sec. 3.4.2, heat-conduction
+ * system).  Steps with E set are not pipelined. */
 typedef enum {
     TLIM_ALPHA2 = 0, TLIM_M1 = 1, TLIM_M2 = 2, TLIM_T1 = 3, TLIM_T2 = 4,
     TLIM_U = 5, TLIM_V = 6, TLIM_W = 7, TLIM_SRC1 = 8, TLIM_SRC2 = 9,
-    TLIM_NFIELDS = 10
+    TLIM_E = 10,
+    TLIM_NFIELDS = 11
 } tlim_field;
 
 /* Cell-centred grid: n[0] cells along x, n[1] along y, n[2] along z (1 for
@@ -161,6 +171,11 @@ tlim_status tlim_set_field(tlim_ctx* ctx, int32_t field, const double* src_dev);
 /* Copy a field out of the context into caller device memory (a pending
  * pipelined step is completed first, see tlim_advance). */
 tlim_status tlim_get_field(tlim_ctx* ctx, int32_t field, double* dst_dev);
+
+/* Mark an optional field (TLIM_U, TLIM_V, TLIM_W, TLIM_SRC1, TLIM_SRC2,
+ * TLIM_E) as not set: absent sources are zero again and the total energy is
+ * no longer updated.  Errors: TLIM_E_ARG for any other field. */
+tlim_status tlim_clear_field(tlim_ctx* ctx, int32_t field);
 
 /* Gershgorin bound lambda_G = max_i 2 d_i of the heat operator A = C^-1 D
  * (Sec. 3.2 needs lambda_max of L_h; D from eq. qk_dis) for the current

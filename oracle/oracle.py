@@ -87,7 +87,7 @@ def lib():
         L.orc_energy.argtypes = [C.POINTER(Grid), C.POINTER(Phase), _dp, _dp, _dp, _dp, _dp]
         L.orc_step.restype = C.c_int32
         L.orc_step.argtypes = [C.POINTER(Grid), C.POINTER(Phase), C.POINTER(Opts),
-                               _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                               _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
                                C.POINTER(Report)]
         L.orc_cycle_solve.restype = C.c_int32
         L.orc_cycle_solve.argtypes = [C.POINTER(Grid), _dp, _dp, _dp, C.c_int32, C.c_double,
@@ -98,6 +98,8 @@ def lib():
         L.orc_visc_heat.restype = None
         L.orc_visc_heat.argtypes = [C.POINTER(Grid), C.POINTER(Phase), C.c_double, C.c_int32, _dp, _dp, _dp, _dp,
                                     _dp, C.c_double, _dp, _dp, _dp]
+        L.orc_visc_energy.restype = None
+        L.orc_visc_energy.argtypes = [C.POINTER(Grid), C.c_int32, _dp, _dp, C.c_double, _dp, _dp]
         L.orc_heat_adjoint.restype = C.c_int32
         L.orc_heat_adjoint.argtypes = [C.POINTER(Grid), C.POINTER(Phase), C.POINTER(Opts), C.c_int32,
                                        _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -259,6 +261,14 @@ def visc_heat(g, ph, alpha2, m1, m2, mu, scale, tau, uh, T1, T2, eps=1e-10, face
                         _p(sc), tau, _p(uh, N), _p(T1, N), _p(T2, N))
 
 
+def visc_energy(g, mu, scale, tau, uh, E, face_mean=FACE_ARITH):
+    """Total-energy update of the viscous part by one velocity component, in
+    place on E (Sec. 3.2); uh the predicted velocity."""
+    N = _ncell(g)
+    sc = np.asarray(scale, dtype=np.float64)
+    lib().orc_visc_energy(C.byref(g), face_mean, _p(mu, N), _p(sc), tau, _p(uh, N), _p(E, N))
+
+
 def energy(g, ph, alpha2, m1, m2, T1, T2):
     N = _ncell(g)
     return float(lib().orc_energy(C.byref(g), make_phases(ph), _p(alpha2, N), _p(m1, N), _p(m2, N), _p(T1, N), _p(T2, N)))
@@ -274,7 +284,8 @@ def _report(r: Report, passes: int):
 
 def step(g, ph, opts: StepOpts, f: dict, frozen_lambda=None, frozen_visc=None):
     """One parabolic step (viscous, relaxation, Algorithm 1) on the fields of
-    ``f`` in place.  Returns (status, report dict)."""
+    ``f`` in place; the total energy f["E"] is updated when present.
+    Returns (status, report dict)."""
     N = _ncell(g)
     rep = Report()
     fl = None if frozen_lambda is None else np.ascontiguousarray(frozen_lambda, dtype=np.float64)
@@ -285,7 +296,7 @@ def step(g, ph, opts: StepOpts, f: dict, frozen_lambda=None, frozen_visc=None):
         raise ValueError("frozen_visc needs 3 values")
     st = lib().orc_step(C.byref(g), make_phases(ph), C.byref(opts.c()), _p(f["alpha2"], N), _p(f["m1"], N),
                         _p(f["m2"], N), _p(f["T1"], N), _p(f["T2"], N), _p(f.get("src1"), N), _p(f.get("src2"), N),
-                        _p(f.get("u"), N), _p(f.get("v"), N), _p(f.get("w"), N),
+                        _p(f.get("u"), N), _p(f.get("v"), N), _p(f.get("w"), N), _p(f.get("E"), N),
                         _p(fl) if fl is not None else None, _p(fv) if fv is not None else None,
                         C.byref(rep))
     return int(st), _report(rep, opts.passes)

@@ -409,7 +409,7 @@ static const double UNIT_SCALE[3] = {1.0, 1.0, 1.0};
 static int32_t heat_picard(const orc_grid* g, const orc_phase ph[2], const orc_opts* o,
                            double* alpha2, const double* m1, const double* m2, double* T,
                            const double* src1, const double* src2, const double* frozen_lambda,
-                           orc_report* rep) {
+                           double* E, orc_report* rep) {
     int64_t N = ncells(g);
     double tau = o->tau;
     double B1 = ph[0].pinf - ph[1].pinf;
@@ -486,6 +486,10 @@ static int32_t heat_picard(const orc_grid* g, const orc_phase ph[2], const orc_o
         rep->passes_run = it;
         rep->converged = converged || o->picard_tol <= 0.0;
     }
+    /* Total energy: the last pass's final stage moved C_eff (T^{n+1} - T^n)
+     * into each cell, its flux divergence plus sources. */
+    if (E)
+        for (int64_t i = 0; i < N; ++i) E[i] += C[i] * (T[i] - Tn[i]);
     free(Tn);
     free(a2n);
     free(Lam);
@@ -559,11 +563,46 @@ void orc_visc_heat(const orc_grid* g, const orc_phase ph[2], double eps, int32_t
             }
 }
 
+/* Total-energy update of the viscous part (Sec. 3.2): the divergence of the
+ * work uh_f F_f of the viscous flux, face by face as in orc_visc_heat. */
+void orc_visc_energy(const orc_grid* g, int32_t face_mean, const double* mu, const double axis_scale[3],
+                     double tau, const double* uh, double* E) {
+    const int64_t stride[3] = {1, g->n[0], g->n[0] * g->n[1]};
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                const int64_t c[3] = {i, j, k};
+                const int64_t a = i + g->n[0] * (j + g->n[1] * k);
+                double dE = 0.0;
+                for (int axis = 0; axis < 3; ++axis) {
+                    const int64_t n = g->n[axis];
+                    if (n <= 1) continue;
+                    const double h = g->h[axis];
+                    double work[2] = {0.0, 0.0}; /* uh_f F_f at the faces a+e_d, a-e_d */
+                    for (int side = 0; side < 2; ++side) {
+                        const int dir = side == 0 ? 1 : -1;
+                        int64_t cn = c[axis] + dir;
+                        if (cn < 0 || cn >= n) {
+                            if (g->bc[axis] != ORC_PERIODIC) continue;
+                            cn = (cn + n) % n;
+                        }
+                        const int64_t b = a + (cn - c[axis]) * stride[axis];
+                        const double muf = face_value(mu[a], mu[b], face_mean);
+                        const double grad = dir > 0 ? (uh[b] - uh[a]) / h : (uh[a] - uh[b]) / h;
+                        work[side] = 0.5 * (uh[a] + uh[b]) * axis_scale[axis] * muf * grad;
+                    }
+                    dE += tau / h * (work[0] - work[1]);
+                }
+                E[a] += dE;
+            }
+}
+
 /* Viscous momentum diffusion, one LIM pass per velocity component, with the
- * viscous heating of the phases when asked. */
+ * viscous heating of the phases and the total-energy update when asked. */
 static void viscous(const orc_grid* g, const orc_phase ph[2], const orc_opts* o,
                     const double* alpha2, const double* m1, const double* m2, double* vel[3],
-                    const double* frozen_visc, double* T1, double* T2, orc_report* rep) {
+                    const double* frozen_visc, double* T1, double* T2, double* E, orc_report* rep) {
     int64_t N = ncells(g);
     double* rho = dalloc(N);
     double* mu = dalloc(N);
@@ -582,12 +621,14 @@ static void viscous(const orc_grid* g, const orc_phase ph[2], const orc_opts* o,
         int32_t nst = 2 * P - 1;
         double* b = dalloc(nst);
         orc_lim_params(P, lam, o->order, b);
-        if (o->visc_heating) {
+        if (o->visc_heating || E) {
             /* keep the stage iterates: the last one, v^(2P-2), is the predicted velocity */
             double* st = dalloc((int64_t)nst * N);
             orc_lim_pass(g, mu, rho, s, o->face_mean, o->tau, nst, b, vel[c], vel[c], out, st);
-            orc_visc_heat(g, ph, o->alpha_eps, o->face_mean, alpha2, m1, m2, mu, s, o->tau,
-                          st + (int64_t)(nst - 1) * N, T1, T2);
+            const double* uh = st + (int64_t)(nst - 1) * N;
+            if (o->visc_heating)
+                orc_visc_heat(g, ph, o->alpha_eps, o->face_mean, alpha2, m1, m2, mu, s, o->tau, uh, T1, T2);
+            if (E) orc_visc_energy(g, o->face_mean, mu, s, o->tau, uh, E);
             free(st);
         } else {
             orc_lim_pass(g, mu, rho, s, o->face_mean, o->tau, nst, b, vel[c], vel[c], out, NULL);
@@ -606,7 +647,7 @@ static void viscous(const orc_grid* g, const orc_phase ph[2], const orc_opts* o,
 
 int32_t orc_step(const orc_grid* g, const orc_phase ph[2], const orc_opts* o, double* alpha2,
                  const double* m1, const double* m2, double* T1, double* T2, const double* src1,
-                 const double* src2, double* u, double* v, double* w, const double* frozen_lambda,
+                 const double* src2, double* u, double* v, double* w, double* E, const double* frozen_lambda,
                  const double* frozen_visc, orc_report* rep) {
     if (rep) memset(rep, 0, sizeof(*rep));
     if (rep) rep->energy_before = orc_energy(g, ph, alpha2, m1, m2, T1, T2);
@@ -614,10 +655,10 @@ int32_t orc_step(const orc_grid* g, const orc_phase ph[2], const orc_opts* o, do
      * then heat conduction. */
     if (o->do_viscous) {
         double* vel[3] = {u, v, w};
-        viscous(g, ph, o, alpha2, m1, m2, vel, frozen_visc, T1, T2, rep);
+        viscous(g, ph, o, alpha2, m1, m2, vel, frozen_visc, T1, T2, E, rep);
     }
     orc_relax(g, ph, o->alpha_eps, alpha2, m1, m2, T1, T2);
-    int32_t st = heat_picard(g, ph, o, alpha2, m1, m2, T1, src1, src2, frozen_lambda, rep);
+    int32_t st = heat_picard(g, ph, o, alpha2, m1, m2, T1, src1, src2, frozen_lambda, E, rep);
     memcpy(T2, T1, sizeof(double) * (size_t)ncells(g));
     if (rep) rep->energy_after = orc_energy(g, ph, alpha2, m1, m2, T1, T2);
     return st;

@@ -133,6 +133,12 @@ void orc_visc_heat(const orc_grid* g, const orc_phase ph[2], double eps, int32_t
                    const double* alpha2, const double* m1, const double* m2, const double* mu,
                    const double axis_scale[3], double tau, const double* uh, double* T1, double* T2);
 
+/* Total-energy update of the viscous part by one velocity component (Sec.
+ * 3.2): (rho E)_a changes by tau/h_d [uh_f+ F_f+ - uh_f- F_f-] summed over
+ * the axes, with F and the face values as in orc_visc_heat.  E in place. */
+void orc_visc_energy(const orc_grid* g, int32_t face_mean, const double* mu, const double axis_scale[3],
+                     double tau, const double* uh, double* E);
+
 /* Temperature relaxation in mixed cells (in place on alpha2, T1, T2). */
 void orc_relax(const orc_grid* g, const orc_phase ph[2], double eps,
                double* alpha2, const double* m1, const double* m2,
@@ -146,13 +152,17 @@ double orc_energy(const orc_grid* g, const orc_phase ph[2], const double* alpha2
 
 /* One parabolic step: [viscous], relaxation, Picard loop of LIM passes.
  * u, v, w may be NULL when do_viscous = 0.  src1/src2 may be NULL.
+ * E (nullable) is the mixture total energy density rho E: the viscous part
+ * adds orc_visc_energy per component, the heat part C_eff (T^{n+1} - T^n)
+ * with the last pass's C_eff and the relaxed T^n -- the conductive flux
+ * divergence plus the sources of that pass's final stage.
  * frozen_lambda (nullable, `passes` entries) replaces the Gershgorin bound of
  * each pass; frozen_visc (nullable, 3 entries) that of each velocity component.
  * Returns 0, or 3 when picard_tol > 0 was not reached. */
 int32_t orc_step(const orc_grid* g, const orc_phase ph[2], const orc_opts* o,
                  double* alpha2, const double* m1, const double* m2,
                  double* T1, double* T2, const double* src1, const double* src2,
-                 double* u, double* v, double* w,
+                 double* u, double* v, double* w, double* E,
                  const double* frozen_lambda, const double* frozen_visc,
                  orc_report* rep);
 

@@ -187,10 +187,17 @@ void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const
 // (g.w carries the 4/3 factor of the component's own axis), which is the
 // paper's flux form with face values uh_f = (uh_a+uh_b)/2 and alpha_k,f the
 // arithmetic face mean; T_k += that / C_k, and in a cell without phase k the
-// phase present takes both shares.  T1, T2 in place.
+// phase present takes both shares.  T1, T2 in place (T1 == NULL: no
+// heating).  With E != NULL also the total-energy update of the viscous
+// part, E += tau sum_f w_f mu_f uh_f (uh_b - uh_a).
 void launch_visc_heat(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, int face, double tau,
                       const double* alpha2, const double* m1, const double* m2, const double* mu,
-                      const double* uh64, const double* g64, const float* w32, double* T1, double* T2);
+                      const double* uh64, const double* g64, const float* w32, double* T1, double* T2,
+                      double* E);
+// Total energy of the heat part: E += (T - Tn) / rC, rC = 1/C_eff of the
+// pass whose final stage wrote T.
+void launch_total_energy_heat(hipStream_t s, int64_t N, const double* T, const double* Tn, const double* rC,
+                              double* E);
 
 void launch_fill(hipStream_t s, double* p, double v, int64_t n);
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n);

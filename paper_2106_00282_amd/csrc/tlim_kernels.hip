@@ -634,7 +634,8 @@ __global__ void __launch_bounds__(256) k_visc_heat(DevGrid g, DevPhases ph, doub
                                                    const double* __restrict__ alpha2, const double* __restrict__ m1,
                                                    const double* __restrict__ m2, const double* __restrict__ mu,
                                                    const double* __restrict__ uh64, const double* __restrict__ g64,
-                                                   const float* __restrict__ w32, double* T1, double* T2) {
+                                                   const float* __restrict__ w32, double* T1, double* T2,
+                                                   double* E) {
     int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
     if (i >= g.nx || j >= g.ny) return;
     const int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
@@ -642,17 +643,23 @@ __global__ void __launch_bounds__(256) k_visc_heat(DevGrid g, DevPhases ph, doub
     Faces f;
     faces_of(g, i, j, k, f);
     const double ua = uh(a), a2a = alpha2[a], mua = mu[a];
-    double e1 = 0.0, e2 = 0.0;
+    double e1 = 0.0, e2 = 0.0, work = 0.0;
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         if (!f.has[q]) continue;
         const int64_t b = a + f.off[q];
-        const double du = uh(b) - ua;
-        const double d = 0.5 * g.w[q >> 1] * face_mean<double>(mua, mu[b], face) * du * du;
+        const double ub = uh(b);
+        const double du = ub - ua;
+        const double wmu = g.w[q >> 1] * face_mean<double>(mua, mu[b], face);
+        // total energy: uh_f times the flux w mu_f (uh_b - uh_a) through the face
+        work += 0.5 * (ua + ub) * wmu * du;
+        const double d = 0.5 * wmu * du * du;
         const double a2f = 0.5 * (a2a + alpha2[b]);
         e1 += (1.0 - a2f) * d;
         e2 += a2f * d;
     }
+    if (E) E[a] += tau * work;
+    if (!T1) return;
     e1 *= tau;
     e2 *= tau;
     const double C1 = m1[a] * ph.cv[0], C2 = m2[a] * ph.cv[1];
@@ -664,6 +671,15 @@ __global__ void __launch_bounds__(256) k_visc_heat(DevGrid g, DevPhases ph, doub
         T1[a] += e1 / C1;
         T2[a] += e2 / C2;
     }
+}
+
+// Total energy of the heat part: the last pass's final stage moved
+// C_eff (T^{n+1} - T^n) into each cell.
+__global__ void __launch_bounds__(256) k_total_energy_heat(int64_t n, const double* __restrict__ T,
+                                                           const double* __restrict__ Tn,
+                                                           const double* __restrict__ rC, double* __restrict__ E) {
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x)
+        E[a] += (T[a] - Tn[a]) / rC[a];
 }
 
 // One wave per target row folds its kSlots slots with the target's
@@ -807,9 +823,15 @@ void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const
 
 void launch_visc_heat(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, int face, double tau,
                       const double* alpha2, const double* m1, const double* m2, const double* mu,
-                      const double* uh64, const double* g64, const float* w32, double* T1, double* T2) {
+                      const double* uh64, const double* g64, const float* w32, double* T1, double* T2,
+                      double* E) {
     hipLaunchKernelGGL(k_visc_heat, tile_grid(g), dim3(TX, TY), 0, s, g, ph, eps, face, tau, alpha2, m1, m2, mu, uh64,
-                       g64, w32, T1, T2);
+                       g64, w32, T1, T2, E);
+}
+
+void launch_total_energy_heat(hipStream_t s, int64_t N, const double* T, const double* Tn, const double* rC,
+                              double* E) {
+    hipLaunchKernelGGL(k_total_energy_heat, dim3(pointwise_blocks(N)), dim3(256), 0, s, N, T, Tn, rC, E);
 }
 
 void launch_fill(hipStream_t s, double* p, double v, int64_t n) {

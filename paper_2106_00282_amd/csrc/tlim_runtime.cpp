@@ -479,6 +479,7 @@ tlim_status viscous(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep,
     tlim::launch_visc_coeffs(c->stream, g0, ph, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], c->Lam,
                              c->rC, c->Lam32, c->rC32);
     const bool heat = o->visc_heating != 0;
+    double* E = c->fset[TLIM_E] ? c->field[TLIM_E] : nullptr;
     if (heat && c->t2_alias) {
         // the phases are heated differently: T2 gets its own array again
         tlim::launch_copy(c->stream, c->field[TLIM_T2], c->field[TLIM_T1], c->N);
@@ -503,11 +504,11 @@ tlim_status viscous(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep,
         double* u = c->field[TLIM_U + comp];
         Vhat vh;
         run_lim_pass(c, g, o->face_mean, o->dt, ps, u, u, c->Tnew, nullptr, tlim::PassSlots{}, tm, sc, false,
-                     heat ? &vh : nullptr);
-        if (heat)
+                     heat || E ? &vh : nullptr);
+        if (heat || E)
             tlim::launch_visc_heat(c->stream, g, ph, o->alpha_eps, o->face_mean, o->dt, c->field[TLIM_ALPHA2],
                                    c->field[TLIM_M1], c->field[TLIM_M2], c->Lam, vh.v64, vh.g64, vh.w32,
-                                   c->field[TLIM_T1], c->field[TLIM_T2]);
+                                   heat ? c->field[TLIM_T1] : nullptr, heat ? c->field[TLIM_T2] : nullptr, E);
         std::swap(c->field[TLIM_U + comp], c->Tnew);
         if (rep) {
             rep->visc_P[comp] = lim_P(o->dt, lam);
@@ -952,6 +953,15 @@ tlim_status tlim_get_field(tlim_ctx* c, int32_t f, double* dst) {
     return TLIM_OK;
 }
 
+tlim_status tlim_clear_field(tlim_ctx* c, int32_t f) {
+    if (!c) return TLIM_E_ARG;
+    tlim_status pst = resolve(c);
+    if (pst) return pst;
+    if (f < TLIM_U || f >= TLIM_NFIELDS) return fail(c, TLIM_E_ARG, "field %d is not optional", f);
+    c->fset[f] = false;
+    return TLIM_OK;
+}
+
 tlim_status tlim_spectral_bound(tlim_ctx* c, int32_t face_mean, double alpha_eps, double* lambda_out) {
     if (!c) return TLIM_E_ARG;
     tlim_status pst = resolve(c);
@@ -1059,6 +1069,7 @@ tlim_status advance_sync(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
         st = heat_passes(c, o, Mode::Sync, rep, tm, sc, out, false);
         if (st) return st;
     }
+    if (c->fset[TLIM_E]) tlim::launch_total_energy_heat(s, c->N, c->field[TLIM_T1], c->Tn, c->rC, c->field[TLIM_E]);
     if (rep) {
         zero_rows(c, tlim::kTgtEnergy, tlim::kTgtEnergy + 1);
         tlim::launch_energy(s, g, ph, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], c->field[TLIM_T1],
@@ -1094,13 +1105,14 @@ void next_result_block(tlim_ctx* c) {
 }
 
 // Steps that may run pipelined: predicted schedule, no report, no viscous
-// part, no timing, equal p_inf, 2D without sources (fused relaxation, whose
+// part, no total energy, no timing, equal p_inf, 2D without sources (fused relaxation, whose
 // relaxed alpha2 and T^n go to fresh arrays).
 // A pipelined step is predicted from the step two back, and a miss costs the
 // newer step too, so pipelining waits until two consecutive steps kept the
 // same schedule.
 bool pipeline_ok(const tlim_ctx* c, const tlim_step_opts* o, const tlim_step_report* rep) {
     return !rep && !o->do_viscous && !o->time_sweeps && !o->cycle_mode && !o->frozen_lambda && o->picard_tol <= 0.0 &&
+           !c->fset[TLIM_E] &&
            c->phase[0].pinf == c->phase[1].pinf && fast_coeffs(c, dev_grid(c, kUnit)) &&
            c->hist_passes == o->passes && c->hist_steady >= 2 && c->res_host_dev != nullptr;
 }
@@ -1269,6 +1281,7 @@ tlim_status check_adjoint(tlim_ctx* c, const tlim_step_opts* o) {
     if (o->cycle_mode || o->do_viscous || o->picard_tol > 0.0)
         return fail(c, TLIM_E_ARG, "adjoint runs plain LIM heat steps (no cycle mode, viscous part or Picard tol)");
     if (c->fset[TLIM_SRC1] || c->fset[TLIM_SRC2]) return fail(c, TLIM_E_ARG, "adjoint runs without heat sources");
+    if (c->fset[TLIM_E]) return fail(c, TLIM_E_ARG, "adjoint runs without the total energy field");
     return TLIM_OK;
 }
 

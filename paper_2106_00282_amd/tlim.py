@@ -22,11 +22,11 @@ PERIODIC, ADIABATIC = 0, 1
 FP64, FP32 = 0, 1
 ORDER_INTERLEAVED, ORDER_PAPER, ORDER_ASCENDING = 0, 1, 2
 FACE_ARITH, FACE_HARMONIC = 0, 1
-FIELDS = dict(alpha2=0, m1=1, m2=2, T1=3, T2=4, u=5, v=6, w=7, src1=8, src2=9)
+FIELDS = dict(alpha2=0, m1=1, m2=2, T1=3, T2=4, u=5, v=6, w=7, src1=8, src2=9, E=10)
 MAX_PASSES = 64
 
 EXPORTED = ("tlim_create", "tlim_destroy", "tlim_workspace_bytes", "tlim_bind_workspace",
-            "tlim_set_phase", "tlim_set_field", "tlim_get_field", "tlim_spectral_bound",
+            "tlim_set_phase", "tlim_set_field", "tlim_get_field", "tlim_clear_field", "tlim_spectral_bound",
             "tlim_advance", "tlim_finish", "tlim_forward_checkpointed", "tlim_adjoint_workspace_bytes",
             "tlim_adjoint", "tlim_status_str", "tlim_last_error")
 
@@ -85,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     L.tlim_set_phase.argtypes = [vp, C.c_int32, C.POINTER(Phase)]
     L.tlim_set_field.argtypes = [vp, C.c_int32, vp]
     L.tlim_get_field.argtypes = [vp, C.c_int32, vp]
+    L.tlim_clear_field.argtypes = [vp, C.c_int32]
     L.tlim_spectral_bound.argtypes = [vp, C.c_int32, C.c_double, dp]
     L.tlim_advance.argtypes = [vp, C.POINTER(StepOptsC), C.POINTER(ReportC)]
     L.tlim_finish.argtypes = [vp]
@@ -217,6 +218,10 @@ class Solver:
         t = self._dev(values)
         self._check(load_library().tlim_set_field(self._ctx, FIELDS[name], C.c_void_p(t.data_ptr())))
         self.stream.synchronize()
+
+    def clear_field(self, name: str) -> None:
+        """Mark an optional field (u, v, w, src1, src2, E) as not set."""
+        self._check(load_library().tlim_clear_field(self._ctx, FIELDS[name]))
 
     def get_field(self, name: str) -> torch.Tensor:
         out = torch.empty(self.shape, dtype=torch.float64, device=self.device)

@@ -120,6 +120,94 @@ def test_viscous_heating_vs_oracle(precision, walls):
     _compare(fo, fg, FIELDS_T + ("u", "v", "w"), 1e-12 if precision == "fp64" else 1e-5)
 
 
+def _with_total_energy(wl):
+    """Add rho E = sum_k (m_k C_v,k T_k + alpha_k p_inf,k) + rho |u|^2 / 2."""
+    f = wl["fields"]
+    ph = wl["phases"]
+    a2 = f["alpha2"]
+    E = (f["m1"] * ph[0]["cv"] * f["T1"] + (1 - a2) * ph[0]["pinf"] + f["m2"] * ph[1]["cv"] * f["T2"]
+         + a2 * ph[1]["pinf"])
+    E = E + 0.5 * (f["m1"] + f["m2"]) * sum(f[c] ** 2 for c in "uvw" if c in f)
+    f["E"] = np.ascontiguousarray(E)
+    return f["E"].copy()
+
+
+@pytest.mark.parametrize("precision,walls", [("fp64", False), ("fp64", True), ("fp32", True)])
+def test_total_energy_viscous_and_heat_vs_oracle(precision, walls):
+    """Total energy through 2 steps of 3D bubbles with the viscous part
+    (work of the viscous flux with the predicted velocity) and heat
+    conduction (flux divergence of the last pass), 30x stronger velocity:
+    E and its change against the oracle."""
+    from oracle import oracle as orc
+    wl = W.bubbles3d(40)
+    for k in wl["fields"]:
+        wl["fields"][k] = np.ascontiguousarray(wl["fields"][k][:33, :36, :])
+    for c in "uvw":
+        wl["fields"][c] = np.ascontiguousarray(30.0 * wl["fields"][c])
+    wl["n"] = (40, 36, 33)
+    wl["h"] = (1 / 40, 1 / 40, 1 / 40)
+    if walls:
+        wl["bc"] = (W.ADIABATIC, W.PERIODIC, W.ADIABATIC)
+    E0 = _with_total_energy(wl)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 2, visc_heating=1)
+    fg, rg, _ = run_gpu(wl, tau, 2, precision=precision, frozen=_frozen(ro), visc_heating=1)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    _compare(fo, fg, FIELDS_T + ("u", "v", "w", "E"), tol)
+    dEo, dEg = fo["E"] - E0, fg["E"] - E0
+    assert np.abs(dEo).max() > 1e-6 * np.abs(E0).max()
+    assert rel_err(dEg, dEo) < (1e-9 if precision == "fp64" else 1e-2)
+    if not walls:
+        # periodic, no sources: the total energy is conserved
+        assert abs(dEg.sum()) < 1e-9 * np.abs(dEg).sum()
+
+
+@pytest.mark.parametrize("case", ["levelset_fp64", "levelset_fp32", "sg_sources"])
+def test_total_energy_heat_only_vs_oracle(case):
+    """Heat steps with the total energy: the fused 2D path (relaxation with
+    the first coefficients, next-pass coefficients in the last launch) in
+    both precisions, and the general stiffened-gas step with heat sources;
+    clearing E stops its update."""
+    from oracle import oracle as orc
+    if case == "sg_sources":
+        rng = np.random.default_rng(11)
+        nx, ny = 48, 40
+        ph = [dict(gamma=4.4, pinf=6e8, cv=1606.0, q=0.0, k0=0.6, T0=300.0, npow=1.0, mu=0.0),
+              dict(gamma=1.4, pinf=0.0, cv=714.0, q=0.0, k0=0.03, T0=300.0, npow=1.0, mu=0.0)]
+        x = (np.arange(nx) + 0.5) / nx
+        y = (np.arange(ny) + 0.5) / ny
+        a1 = 0.5 * (1 - np.tanh((x[None, :] - 0.5 - 0.1 * np.sin(2 * np.pi * y[:, None])) / (2.0 / nx)))
+        rho1 = (1e9 + 6e8) / (3.4 * 1606.0 * 293.0)
+        rho2 = 1e5 / (0.4 * 714.0 * 293.0)
+        fields = dict(alpha2=1 - a1, m1=a1 * rho1, m2=(1 - a1) * rho2, T1=293.0 + 20 * rng.random((ny, nx)),
+                      T2=293.0 + 20 * rng.random((ny, nx)), src1=1e9 * rng.random((ny, nx)),
+                      src2=1e8 * rng.random((ny, nx)))
+        fields = {k: np.ascontiguousarray(v.reshape(1, ny, nx), dtype=np.float64) for k, v in fields.items()}
+        wl = dict(n=(nx, ny, 1), h=(1e-3, 1e-3, 1.0), bc=(0, 1, 0), phases=ph, fields=fields, dt_factor=50.0,
+                  passes=3, viscous=False)
+        precision = "fp64"
+    else:
+        wl = W.levelset2d(96)
+        precision = case.split("_")[1]
+    E0 = _with_total_energy(wl)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 3)
+    fg, rg, s = run_gpu(wl, tau, 3, precision=precision, frozen=_frozen(ro))
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    _compare(fo, fg, FIELDS_T + ("E",), tol)
+    dEo, dEg = fo["E"] - E0, fg["E"] - E0
+    assert np.abs(dEo).max() > 1e-6 * np.abs(E0).max()
+    assert rel_err(dEg, dEo) < (1e-9 if precision == "fp64" else 1e-2)
+    from paper_2106_00282_amd.tlim import StepOpts, TlimError
+    s.clear_field("E")
+    st, _ = s.advance(StepOpts(dt=tau, passes=wl["passes"]))
+    assert st == 0
+    with pytest.raises(TlimError):
+        s.get_field("E")
+    with pytest.raises(TlimError):
+        s.clear_field("T1")
+
+
 def test_interface3d_fp64_adiabatic_x():
     from oracle import oracle as orc
     wl = W.interface3d(32, nmodes=12)

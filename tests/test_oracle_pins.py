@@ -136,6 +136,122 @@ def test_visc_heat_in_the_step_uses_the_predicted_velocity(orc):
     assert np.all(f["T1"] >= np.minimum(wl["fields"]["T1"], wl["fields"]["T2"]) - 1e-15)
 
 
+# ------------------------------------------------------------ total energy
+
+def test_visc_energy_sine_mode_closed_form(orc):
+    """1D periodic, constant mu: with uh = A sin(k x) the work divergence
+    tau/h (uh_f+ F_f+ - uh_f- F_f-) is tau s mu/(2 h^2) times the second
+    difference of uh^2, i.e. tau s mu A^2 sin^2(k h) cos(2 k x_a) / h^2 in
+    every cell; a uniform velocity does no work."""
+    N = 36
+    g = orc.make_grid((N, 1, 1))
+    shape = (1, 1, N)
+    mu = np.full(shape, 0.3)
+    A, tau, h, s = 0.8, 0.02, 1.0 / N, 4.0 / 3.0
+    x = (np.arange(N) + 0.5) / N
+    k = 2 * np.pi
+    uh = (A * np.sin(k * x)).reshape(shape)
+    E = np.full(shape, 5.0)
+    orc.visc_energy(g, mu, (s, 1, 1), tau, uh, E)
+    expect = tau * s * 0.3 * A ** 2 * np.sin(k * h) ** 2 * np.cos(2 * k * x) / h ** 2
+    np.testing.assert_allclose((E - 5.0).ravel(), expect, rtol=0, atol=1e-12 * np.abs(expect).max())
+    E2 = np.full(shape, 5.0)
+    orc.visc_energy(g, mu, (s, 1, 1), tau, np.full(shape, 0.37), E2)
+    assert np.all(E2 == 5.0)
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 0, 1)])
+def test_visc_energy_splits_into_heating_and_kinetic_work(orc, bc):
+    """Per cell and per velocity component, the total-energy change of the
+    viscous part is the heating of both phases plus uh_a times the momentum
+    change rho_a (u^{n+1}_a - u^n_a) of the pass's final stage (the paper's
+    identity between the stress work and the dissipation, with u_a = uh_a);
+    summed over the domain the total energy is unchanged (periodic or walls)."""
+    rng = np.random.default_rng(8)
+    n = (9, 8, 7)
+    shape = (n[2], n[1], n[0])
+    h = (0.1, 0.08, 0.125)
+    g = orc.make_grid(n, h, bc)
+    ph = W.base_phases(mu=(0.5, 0.1))
+    a2 = rng.uniform(0.0, 1.0, shape)
+    a2[a2 < 0.1] = 0.0
+    a2[a2 > 0.9] = 1.0
+    m1 = (1.0 - a2) * 1.0 + 1e-3
+    m2 = a2 * 8.0 + 1e-3
+    rho = m1 + m2
+    mu = (1 - a2) * 0.5 + a2 * 0.1
+    tau = 0.01
+    for comp in range(3):
+        s = [1.0, 1.0, 1.0]
+        s[comp] = 4.0 / 3.0
+        u0 = rng.standard_normal(shape)
+        lam = orc.gershgorin(g, mu, rho, s)
+        P = orc.lim_P(tau, lam)
+        b = orc.lim_params(P, lam)
+        u1, st = orc.lim_pass(g, mu, rho, tau, b, u0, u0, scale=s, keep_stages=True)
+        uh = np.ascontiguousarray(st[-1])
+        T1, T2 = np.full(shape, 2.0), np.full(shape, 3.0)
+        orc.visc_heat(g, ph, a2, m1, m2, mu, s, tau, uh, T1, T2)
+        heat = (T1 - 2.0) * m1 * ph[0]["cv"] + (T2 - 3.0) * m2 * ph[1]["cv"]
+        E = np.zeros(shape)
+        orc.visc_energy(g, mu, s, tau, uh, E)
+        np.testing.assert_allclose(E, heat + uh * rho * (u1 - u0), rtol=0, atol=1e-12 * np.abs(E).max())
+        assert abs(E.sum()) < 1e-12 * np.abs(E).sum()
+        assert np.abs(E).max() > 1e-3
+
+
+def _sg_general_case(n=(20, 14, 1), sources=True, seed=5):
+    """Stiffened gas p_inf 6e8/0 out of thermal equilibrium (Sec. 5
+    constants), optional heat sources."""
+    rng = np.random.default_rng(seed)
+    nx, ny = n[0], n[1]
+    ph = [dict(gamma=4.4, pinf=6e8, cv=1606.0, q=0.0, k0=0.6, T0=300.0, npow=1.0, mu=0.0),
+          dict(gamma=1.4, pinf=0.0, cv=714.0, q=0.0, k0=0.03, T0=300.0, npow=1.0, mu=0.0)]
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    a1 = 0.5 * (1 - np.tanh((x[None, :] - 0.5 - 0.1 * np.sin(2 * np.pi * y[:, None])) / (2.0 / nx)))
+    a2 = 1 - a1
+    rho1 = (1e9 + 6e8) / (3.4 * 1606.0 * 293.0)
+    rho2 = 1e5 / (0.4 * 714.0 * 293.0)
+    f = dict(alpha2=a2, m1=a1 * rho1, m2=a2 * rho2, T1=293.0 + 20 * rng.random((ny, nx)),
+             T2=293.0 + 20 * rng.random((ny, nx)))
+    if sources:
+        f.update(src1=1e9 * rng.random((ny, nx)), src2=1e8 * rng.random((ny, nx)))
+    f = {k: np.ascontiguousarray(v.reshape(1, ny, nx), dtype=np.float64) for k, v in f.items()}
+    return ph, f
+
+
+@pytest.mark.parametrize("equal_pinf", [True, False])
+def test_total_energy_heat_part(orc, equal_pinf):
+    """Heat part: the total energy gains the conductive flux divergence plus
+    the sources.  Summed over the domain that is tau sum_k alpha_k I_k; with
+    equal p_inf (alpha fixed, C_eff = sum_k C_k) it is, cell by cell, the
+    internal-energy change sum_k C_k (T_k^{n+1} - T') from the relaxed state
+    T'; with p_inf,1 != p_inf,2 and no sources the sum is still unchanged."""
+    ph, f = _sg_general_case(sources=equal_pinf)
+    if equal_pinf:
+        ph = [dict(p, pinf=0.0) for p in ph]
+    g = orc.make_grid((20, 14, 1), (1e-3, 1e-3, 1.0), (0, 1, 0))
+    E0 = np.full(f["T1"].shape, 1e5)
+    f["E"] = E0.copy()
+    relaxed = {k: v.copy() for k, v in f.items()}
+    orc.relax(g, ph, relaxed["alpha2"], relaxed["m1"], relaxed["m2"], relaxed["T1"], relaxed["T2"])
+    tau = 2e-4
+    st, rep = orc.step(g, ph, orc.StepOpts(tau=tau, passes=3), f)
+    assert st == 0
+    dE = f["E"] - E0
+    assert np.abs(dE).max() > 1e2
+    if equal_pinf:
+        C = f["m1"] * ph[0]["cv"] + f["m2"] * ph[1]["cv"]
+        np.testing.assert_allclose(dE, C * (f["T1"] - relaxed["T1"]), rtol=1e-12, atol=0)
+        src = tau * ((1 - f["alpha2"]) * f["src1"] + f["alpha2"] * f["src2"])
+        assert dE.sum() == pytest.approx(src.sum(), rel=1e-12)
+        assert np.array_equal(f["alpha2"], relaxed["alpha2"])
+    else:
+        assert abs(dE.sum()) < 1e-13 * np.abs(dE).sum()
+        assert not np.array_equal(f["alpha2"], relaxed["alpha2"])
+
+
 # ----------------------------------------------------------------- helpers
 
 def const_problem(orc, n=(16, 12, 1), Lam0=0.7, C0=1.3, h=None, bc=None):
