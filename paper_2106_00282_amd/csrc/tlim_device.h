@@ -148,5 +148,22 @@ static __device__ __forceinline__ int fold(int c, int n, int per) {
     return c < 0 ? 0 : (c >= n ? n - 1 : c);
 }
 
+// Folded index of row yg0 + r, given yi0 = fold(yg0): the grids blocked
+// by rows have at least ROWS rows, so a periodic row wraps at most once.
+static __device__ __forceinline__ int row_index(int yi0, int yg0, int r, int ny, int per) {
+    if (per) {
+        const int y = yi0 + r;
+        return y >= ny ? y - ny : y;
+    }
+    const int y = yg0 + r;
+    return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+}
+
+// Lane l's value of a double (l wave-uniform), without memory access.
+static __device__ __forceinline__ double lane_value(double x, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                            __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
 }  // namespace tb
 }  // namespace tlim

@@ -25,7 +25,7 @@ struct Stages {
 };
 
 // Number of stages the next launch will advance when `count` remain (the
-// launches of a pass get equal shares of at most KMAX stages).
+// launches of a pass get equal shares of at most 8 or 10 stages, by tile height).
 int sweeps_per_launch(const DevGrid& g, int count);
 
 // The next Picard pass's coefficients, built by the launch that reaches the

@@ -7,8 +7,8 @@
 // where v is the correction w = v - g).  The final stage (b = 0) of the FP64
 // form is the same update with c = 1.
 //
-// k_tb2d advances K <= KMAX stages per launch.  A workgroup of WAVES wave64s
-// loads a 64 x (WAVES*ROWS) extended tile once (v, G, Lambda, 1/C; one
+// k_tb2d advances K stages per launch.  A workgroup of NW wave64s
+// loads a 64 x (NW*ROWS) extended tile once (v, G, Lambda, 1/C; one
 // coalesced 64-wide row per wave per field), builds the four kappa of every
 // cell in registers, and then runs the K stages out of registers:
 //   - x-neighbours come from the adjacent lanes through DPP wave shifts;
@@ -16,7 +16,13 @@
 //     consecutive cells of one column), except at the seams between waves,
 //     which go through a double-buffered LDS row (one barrier per stage).
 // Cells within K of the extended tile's edge go stale one ring per stage;
-// the inner (64-2K) x (WAVES*ROWS-2K) cells are exact and written out.
+// the inner (64-2K) x (NW*ROWS-2K) cells are exact and written out.
+// Grids of at least 128 rows use 16 waves (128-row tiles, one workgroup per
+// CU, up to 10 stages per launch), smaller ones 8 waves (64-row tiles, up to
+// 8 stages).  Every workgroup of a launch is resident at once on the 1024^2
+// grids, so a launch costs one load phase plus its stages: the taller tile
+// halves the halo per stage and lets a Picard pass of 15-20 stages run in
+// two launches instead of three.
 // Bytes per launch: 4 words read per extended cell + 1 word written per
 // output cell, for K stages.
 #include <hip/hip_runtime.h>
@@ -28,10 +34,13 @@ namespace tlim {
 
 namespace {
 
-using tb::KMAX;
-using tb::WAVES;
 using tb::ROWS;
-using tb::EXT_Y;
+using tb::row_index;
+using tb::lane_value;
+
+constexpr int KMAX_TB = 10;     // stages per launch, 16-wave tiles
+constexpr int KMAX_SHORT = 8;   // stages per launch, 8-wave tiles
+constexpr int TALL_ROWS = 128;  // grids with at least this many rows use 16-wave tiles
 using tb::from_left;
 using tb::from_right;
 using tb::fmean;
@@ -70,11 +79,13 @@ struct TBArgs {
     R wx, wy, tau;
     int K, H, face, tiles_x, ox, oy;
     double taud;
-    double tb[KMAX], chat[KMAX];
+    double tb[KMAX_TB], chat[KMAX_TB];
 };
 
-template <typename R>
-__global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
+template <typename R, int NW, bool kKeep>
+__global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
+    constexpr int WAVES = NW;
+    constexpr int EXT_Y = NW * ROWS;
     __shared__ R sh_lo[2][WAVES][64];  // row 0 of each wave (the "up" row of the wave below)
     __shared__ R sh_hi[2][WAVES][64];  // row ROWS-1 of each wave (the "down" row of the wave above)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -83,6 +94,7 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
     const int xg = tx * a.ox - H + lane;
     const int yg0 = ty * a.oy - H + wv * ROWS;
     const int xi = fold(xg, a.nx, a.perx);
+    const int yi0 = fold(yg0, a.ny, a.pery);
     const bool inx = xg >= 0 && xg < a.nx;
     const bool fL = a.perx ? a.nx > 1 : (inx && xg > 0);
     const bool fR = a.perx ? a.nx > 1 : (inx && xg < a.nx - 1);
@@ -102,7 +114,7 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
         R L[ROWS], t[ROWS];
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
-            const int yi = fold(yg0 + r, a.ny, a.pery);
+            const int yi = row_index(yi0, yg0, r, a.ny, a.pery);
             const int64_t idx = (int64_t)yi * a.nx + xi;
             v[r] = a.v[idx];
             // the first launch of a pass starts from v^(0) = T^n = g
@@ -146,18 +158,28 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) lamv = fmax(lamv, __shfl_xor(lamv, o, 64));
     }
+    // Stage parameters: lane s holds tau*b_s and c_s = 1/(1 + tau*b_s) of
+    // stage s; the stage loop reads them with readlane.
+    double ptb = 0.0, pcm = 1.0;
+    if (lane < K) {
+        ptb = a.lam ? a.taud * lamv * a.chat[lane] : a.tb[lane];
+        pcm = 1.0 / (1.0 + ptb);
+    }
     // Stage s exchanges the seam rows through LDS buffer (s+1)&1; buffer 0
     // held the Lambda seams, whose reads all precede the first barrier below.
+    // The end waves read a valid row and discard it (no branch).
     const int Kin = fin ? K - 1 : K;
+    const int wdn = wv > 0 ? wv - 1 : 0, wup = wv < WAVES - 1 ? wv + 1 : wv;
     for (int s = 0; s < Kin; ++s) {
         const int buf = (s + 1) & 1;
         sh_lo[buf][wv][lane] = v[0];
         sh_hi[buf][wv][lane] = v[ROWS - 1];
         __syncthreads();
-        const R vdn = wv > 0 ? sh_hi[buf][wv - 1][lane] : v[0];
-        const R vup = wv < WAVES - 1 ? sh_lo[buf][wv + 1][lane] : v[ROWS - 1];
-        const double tbd = a.lam ? a.taud * lamv * a.chat[s] : a.tb[s];
-        const R cm = (R)(1.0 / (1.0 + tbd)), tb = (R)tbd;
+        const R sdn = sh_hi[buf][wdn][lane], sup = sh_lo[buf][wup][lane];
+        const R vdn = wv > 0 ? sdn : v[0];
+        const R vup = wv < WAVES - 1 ? sup : v[ROWS - 1];
+        const double tbd = lane_value(ptb, s);
+        const R cm = (R)lane_value(pcm, s), tb = (R)tbd;
         R prev = vdn;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
@@ -173,7 +195,7 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
         }
         // the output cells are exact after every stage: keep the intermediate
         // stages when asked (the adjoint's recomputation)
-        if (a.stages && s + 1 < K && lane >= H && lane < 64 - H && xg < a.nx) {
+        if (kKeep && s + 1 < K && lane >= H && lane < 64 - H && xg < a.nx) {
             R* dst = a.stages + (int64_t)(s + 1) * a.sstride;
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
@@ -193,7 +215,7 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
             double vf[ROWS];
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
-                const int64_t idx = (int64_t)fold(yg0 + r, a.ny, a.pery) * a.nx + xi;
+                const int64_t idx = (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + xi;
                 gfin[r] = a.g64[idx];
                 vf[r] = gfin[r] + (double)v[r];
             }
@@ -234,7 +256,7 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
                 double Ln[ROWS], rc[ROWS];
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r) {
-                    const int64_t idx = (int64_t)fold(yg0 + r, a.ny, a.pery) * a.nx + xi;
+                    const int64_t idx = (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + xi;
                     rc[r] = a.rC64[idx];
                     const double tn = gfin[r] - a.taud * rc[r] * Sfin[r];
                     Ln[r] = phys::cell_conductivity(a.ph, tn, a.alpha2[idx]);
@@ -341,7 +363,7 @@ __global__ void __launch_bounds__(64 * WAVES, 4) k_tb2d(TBArgs<R> a) {
             double Ln[ROWS];
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
-                const int64_t idx = (int64_t)fold(yg0 + r, a.ny, a.pery) * a.nx + xi;
+                const int64_t idx = (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + xi;
                 Ln[r] = phys::cell_conductivity(a.ph, v[r], a.alpha2[idx]);
             }
             // the seam buffer not used by the last stage: its reads all
@@ -404,7 +426,10 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
     a.g64w[1] = g.w[1];
     a.stages = stages;
     a.sstride = sstride;
-    int K = count < KMAX ? count : KMAX;
+    const bool tall = g.ny >= TALL_ROWS;
+    const int kmax = tall ? KMAX_TB : KMAX_SHORT;
+    const int EXT_Y = (tall ? 16 : 8) * ROWS;
+    int K = count < kmax ? count : kmax;
     a.v = v;
     a.G = G;
     a.Lam = Lam;
@@ -432,12 +457,19 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
         if (st.lam) a.chat[k] = st.chat[k];
         else a.tb[k] = st.tb[k];
     }
-    hipLaunchKernelGGL(k_tb2d<R>, dim3((unsigned)(a.tiles_x * tiles_y)), dim3(64 * WAVES), 0, s, a);
+    const dim3 grid((unsigned)(a.tiles_x * tiles_y));
+    if (stages) {
+        if (tall) hipLaunchKernelGGL((k_tb2d<R, 16, true>), grid, dim3(64 * 16), 0, s, a);
+        else hipLaunchKernelGGL((k_tb2d<R, 8, true>), grid, dim3(64 * 8), 0, s, a);
+    } else {
+        if (tall) hipLaunchKernelGGL((k_tb2d<R, 16, false>), grid, dim3(64 * 16), 0, s, a);
+        else hipLaunchKernelGGL((k_tb2d<R, 8, false>), grid, dim3(64 * 8), 0, s, a);
+    }
     return K;
 }
 
 bool use_tb2d(const DevGrid& g, int count) {
-    return g.nz == 1 && g.ny >= EXT_Y / 2 && count >= 2;
+    return g.nz == 1 && g.ny >= 8 * ROWS / 2 && count >= 2;
 }
 
 StageParam one_stage(const Stages& st) {
@@ -461,9 +493,10 @@ int launch_sweeps64_keep(hipStream_t s, const DevGrid& g, int face, const double
 
 int sweeps_per_launch(const DevGrid& g, int count) {
     if (!use_tb2d(g, count)) return 1;
-    // as few launches as KMAX allows, with equal stage counts: a launch of K
-    // stages recomputes a ring of width K, so even launches waste least
-    const int launches = (count + KMAX - 1) / KMAX;
+    // as few launches as the tile allows, with equal stage counts: a launch
+    // of K stages recomputes a ring of width K, so even launches waste least
+    const int kmax = g.ny >= TALL_ROWS ? KMAX_TB : KMAX_SHORT;
+    const int launches = (count + kmax - 1) / kmax;
     return (count + launches - 1) / launches;
 }
 

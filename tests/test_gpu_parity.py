@@ -44,10 +44,10 @@ def test_heat1d_fp64_single_step():
     assert abs(rg[0]["energy_after"] / rg[0]["energy_before"] - 1) < 1e-14
 
 
-@pytest.mark.parametrize("shape", [(100, 76), (64, 4), (67, 1), (3, 130)])
+@pytest.mark.parametrize("shape", [(100, 76), (64, 4), (67, 1), (3, 130), (260, 150), (90, 331)])
 def test_levelset2d_fp64_ragged(shape):
-    """Reduced level-set workload on grids that span several 64x4 tiles and
-    leave ragged tails; 2 steps x 3 Picard passes."""
+    """Reduced level-set workload on grids that span several tiles and leave
+    ragged tails (64- and 128-row blocked tiles); 2 steps x 3 Picard passes."""
     from oracle import oracle as orc
     nx, ny = shape
     ng = max(128, nx, ny)
@@ -487,7 +487,8 @@ def test_levelset2d_fp32_full_size():
 
 
 @pytest.mark.parametrize("shape,bc", [((100, 76), "periodic"), ((3, 130), "periodic"),
-                                      ((130, 47), "adiabatic"), ((64, 64), "adiabatic")])
+                                      ((130, 47), "adiabatic"), ((64, 64), "adiabatic"),
+                                      ((200, 131), "adiabatic"), ((150, 260), "periodic")])
 def test_levelset2d_fp32_ragged(shape, bc):
     """FP32 form on grids with ragged tiles and on adiabatic walls: the
     blocked float stages and the double final stage fused into the last
