@@ -12,6 +12,8 @@ region.
 Reported (one JSON line):
   value      FP64 cell-updates per second (N * sweeps / wall time of the steps)
   fp32       the same for the FP32 form and its speedup over FP64
+  fp64_whole_step  FP64 with every step as one cooperative launch (P decided
+             on the device) instead of one launch per block of stages
   roofline   dominant kernel (the blocked LIM sweep): algorithmic bytes per
              launch (N x 40 B x stages, an unfused sweep's compulsory bytes) /
              average launch time from HIP events on the library's stream;
@@ -93,13 +95,13 @@ def run_steps(solver, wl, opts, steps, reset=True):
     return time.perf_counter() - t0
 
 
-def measure(precision, wl, tau, steps, warmup):
+def measure(precision, wl, tau, steps, warmup, whole=0):
     """Wall time of `steps` steps from the initial state on a fresh context
     (no schedule history), after `warmup` steps on another context; then an
     identical untimed run with sweep events for the sweep count and the
     per-launch kernel time."""
     from paper_2106_00282_amd.tlim import Solver, StepOpts
-    opts = StepOpts(dt=tau, passes=wl["passes"])
+    opts = StepOpts(dt=tau, passes=wl["passes"], whole_step=whole)
     if warmup:
         w = Solver(wl["n"], wl["h"], wl["bc"], precision=precision)
         run_steps(w, wl, opts, warmup)
@@ -112,7 +114,7 @@ def measure(precision, wl, tau, steps, warmup):
     sweeps = launches = 0
     sweep_ms = 0.0
     predicted = mispredicted = 0
-    topts = StepOpts(dt=tau, passes=wl["passes"], time_sweeps=1)
+    topts = StepOpts(dt=tau, passes=wl["passes"], time_sweeps=1, whole_step=whole)
     for _ in range(steps):
         st, rep = s2.advance(topts)
         sweeps += rep["sweeps"]
@@ -213,6 +215,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-whole", action="store_true", help="skip the one-launch-per-step FP64 variant")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding "
@@ -236,6 +239,9 @@ def main():
     r32 = None if args.fp64_only else measure("fp32", wl, tau, args.steps, args.warmup)
     if r32:
         log("fp32", r32)
+    rw = None if args.fp64_only or args.no_whole else measure("fp64", wl, tau, args.steps, args.warmup, whole=1)
+    if rw:
+        log("fp64 whole-step", rw)
     adj = None if args.no_adjoint else adjoint_ratio()
     if adj:
         log("adjoint", adj)
@@ -283,6 +289,10 @@ def main():
                        "speedup_vs_fp64": round(r32["gupd"] / r64["gupd"], 3),
                        "ms_per_step": round(r32["wall_s"] / args.steps * 1e3, 4),
                        "sweep_GBs": round(b32 / (l32 * 1e-3) / 1e9, 1) if l32 > 0 else None}
+    if rw:
+        out["fp64_whole_step"] = {"value": round(rw["gupd"], 4), "unit": "Gcell-updates/s",
+                                  "ms_per_step": round(rw["wall_s"] / args.steps * 1e3, 4),
+                                  "launches_per_step": rw["launches"] / args.steps}
     if adj:
         out["adjoint"] = adj
     if b3:

@@ -111,6 +111,11 @@ typedef struct {
     int32_t time_sweeps;         /* 1: time the sweep launches with HIP events (report.sweep_ms) */
     int32_t visc_heating;        /* with do_viscous: the viscous part also heats the phases (Sec. 3.2,
                                     phase internal-energy update with the predicted velocity) */
+    int32_t whole_step;          /* 1: FP64 2D steps without sources and with equal p_inf whose tiles
+                                    all fit on the device at once run as one cooperative launch
+                                    (relaxation and every pass, P decided on the device from the
+                                    reduced lambda_G, no host prediction); 0: one launch per block
+                                    of stages.  Same results up to rounding order */
 } tlim_step_opts;
 
 #define TLIM_MAX_PASSES 64

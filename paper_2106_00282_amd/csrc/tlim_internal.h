@@ -42,7 +42,9 @@ enum {
     kTgtGG,
     kTgtK0a,
     kTgtK0b,
-    kTargets
+    kTgtFlag,      // whole-step kernel: failure count (schedule out of range, barrier time-out)
+    kTgtP0,        // whole-step kernel: P of pass it in slot 0 of row kTgtP0 + it
+    kTargets = kTgtP0 + kMaxPasses
 };
 __host__ __device__ constexpr int tgt_lam(int it) { return 4 * it; }
 __host__ __device__ constexpr int tgt_dmax(int it) { return 4 * it + 1; }
@@ -51,7 +53,7 @@ __host__ __device__ constexpr int tgt_bad(int it) { return 4 * it + 3; }
 // reduction of a target: sums for counts and sums, max otherwise
 __host__ __device__ constexpr bool tgt_is_sum(int t) {
     return (t < kTgtLambda && (t & 3) == 3) || t == kTgtEnergy || t == kTgtRR || t == kTgtGG || t == kTgtK0a ||
-           t == kTgtK0b;
+           t == kTgtK0b || t == kTgtFlag;
 }
 
 // Results folded for the host (one double per target).
@@ -198,6 +200,34 @@ void launch_visc_heat(hipStream_t s, const DevGrid& g, const DevPhases& ph, doub
 // pass whose final stage wrote T.
 void launch_total_energy_heat(hipStream_t s, int64_t N, const double* T, const double* Tn, const double* rC,
                               double* E);
+
+// One heat step of a 2D grid without sources and with equal p_inf in a
+// single cooperative launch (tlim_step2d.hip): relaxation, then `passes`
+// Picard passes, each with its P computed on the device from lambda_G.
+constexpr int kStepMaxTiles = 4096;
+struct Step2D {
+    const double* alpha2;
+    const double* T1;
+    const double* T2;
+    const double* m1;
+    const double* m2;
+    double* Tn;        // relaxed T (= g), all cells
+    double* a2n;       // relaxed alpha2
+    double* rC;        // 1/C_eff
+    double* Tout[2];   // pass it writes T^(it+1) to Tout[it & 1]
+    double* vx[2];     // exchange buffers between blocks of stages
+    double* acc;       // accumulator rows (pass rows, kTgtFlag, kTgtP0..)
+    unsigned* bar;     // kStepMaxTiles arrival words, zero before the launch
+    const double* chat;  // b/lambda of P at chat + (P-1)^2, P = 1..pmax
+    int pmax;
+    int passes;
+};
+// Tiles the whole-step kernel uses on grid g (0 if it does not apply: fewer
+// than 128 rows, or more tiles than can be resident at once).
+int step2d_tiles(const DevGrid& g);
+// Enqueue the step; false if the cooperative launch was refused (nothing ran).
+bool launch_step2d(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double tau, int face,
+                   const Step2D& st);
 
 void launch_fill(hipStream_t s, double* p, double v, int64_t n);
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n);

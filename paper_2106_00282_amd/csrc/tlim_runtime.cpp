@@ -29,6 +29,7 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kAlign = 256;
 constexpr int kMaxEvents = 2 * (TLIM_MAX_PASSES + 4);
+constexpr int kStepPmax = 256;  // largest P of the whole-step kernel's parameter table
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -55,6 +56,9 @@ struct tlim_ctx {
     float *Lam32, *rC32, *q32, *wb[2];
     float *Lam32_alt, *q32_alt;  // the next pass's float coefficients, built by the pass before
     float* wzero;                // all zero: the correction form's start w0 = T^n - g without sources
+    double* chat_tab;            // whole-step kernel: b/lambda per P (order chat_order, -1: not built)
+    int chat_order;
+    unsigned* bar;               // whole-step kernel: barrier counter
     bool w0_zero;                // the coefficients of the current pass came without sources
     double* acc;           // reduction rows: kTargets x kSlots
     PassResult* res_dev;   // folded results (one double per target)
@@ -74,6 +78,7 @@ struct tlim_ctx {
         double* Tn;             // its relaxed T
         double* alpha2;         // its relaxed alpha2 (the alpha2 field during its passes)
         double* alpha2_other;   // the other alpha2 array
+        bool whole;             // run by the whole-step kernel (P decided on the device)
     } pend;
     hipEvent_t ev_pend[2];
     // Leading rows of the Picard-pass targets known to be zero, and the count
@@ -123,6 +128,7 @@ struct Layout {
     size_t field[TLIM_NFIELDS];
     size_t Tn, Tn2, Tnew, a2n, Lam, Lam2, rC, rhs, vb[2], acc, res;
     size_t Lam32, rC32, q32, wb[2], Lam32b, q32b, wzero;
+    size_t chat, bar;
     size_t total;
 };
 
@@ -144,6 +150,10 @@ Layout layout_of(const int64_t n[3], int precision) {
     off += align_up(sizeof(double) * (size_t)tlim::kTargets * tlim::kSlots);
     L.res = off;
     off += align_up(sizeof(PassResult));
+    L.chat = off;
+    off += align_up(sizeof(double) * (size_t)kStepPmax * kStepPmax);
+    L.bar = off;
+    off += align_up(sizeof(unsigned) * tlim::kStepMaxTiles);
     if (precision == TLIM_FP32) {
         size_t* ff[] = {&L.Lam32, &L.rC32, &L.q32, &L.wb[0], &L.wb[1], &L.Lam32b, &L.q32b, &L.wzero};
         for (size_t* p : ff) {
@@ -890,11 +900,15 @@ tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
     c->vb[1] = (double*)(base + L.vb[1]);
     c->acc = (double*)(base + L.acc);
     c->res_dev = (PassResult*)(base + L.res);
+    c->chat_tab = (double*)(base + L.chat);
+    c->chat_order = -1;
+    c->bar = (unsigned*)(base + L.bar);
     c->t2_alias = false;
     c->hist_passes = 0;
     c->hist_steady = 0;
     c->hist_nlam = 0;
     c->clean_rows = c->clean_keep = 0;  // the new accumulator is not known to be zero
+    zero_rows(c, tlim::kTgtFlag, tlim::kTgtFlag + 1);
     if (c->precision == TLIM_FP32) {
         c->Lam32 = (float*)(base + L.Lam32);
         c->rC32 = (float*)(base + L.rC32);
@@ -990,6 +1004,137 @@ tlim_status tlim_spectral_bound(tlim_ctx* c, int32_t face_mean, double alpha_eps
 
 namespace {
 
+// ---- whole-step kernel (2D, FP64, no sources, equal p_inf)
+
+// The step runs as one cooperative launch (relaxation and every Picard pass,
+// P decided on the device) when asked, the grid's tiles can all be resident
+// and the schedule is not given by the caller.
+bool step2d_ok(const tlim_ctx* c, const tlim_step_opts* o) {
+    if (!o->whole_step || c->precision != TLIM_FP64 || o->cycle_mode || o->frozen_lambda || o->picard_tol > 0.0)
+        return false;
+    if (c->phase[0].pinf != c->phase[1].pinf) return false;
+    const DevGrid g = dev_grid(c, kUnit);
+    return fast_coeffs(c, g) && tlim::step2d_tiles(g) > 0;
+}
+
+// b/lambda of every P <= kStepPmax for the stage order, at offset (P-1)^2.
+tlim_status step2d_table(tlim_ctx* c, int order) {
+    if (c->chat_order == order) return TLIM_OK;
+    std::vector<double> t((size_t)kStepPmax * kStepPmax, 0.0);
+    for (int P = 1; P <= kStepPmax; ++P) {
+        const std::vector<double> ch = lim_params(P, 1.0, order);
+        std::copy(ch.begin(), ch.end(), t.begin() + (size_t)(P - 1) * (P - 1));
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->chat_tab, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->chat_order = order;
+    return TLIM_OK;
+}
+
+// Enqueue a step by the whole-step kernel followed by the fold of its rows
+// (lambda_G, change, bad cells, P per pass and the failure count) into `res`
+// (device address of a pinned block; NULL: the device result block).  On
+// success the relaxed state becomes the step's T^n and alpha2.  False: the
+// launch was refused and nothing but the row clearing ran.
+bool step2d_enqueue(tlim_ctx* c, const tlim_step_opts* o, PassResult* res) {
+    hipStream_t s = c->stream;
+    const DevGrid g = dev_grid(c, kUnit);
+    begin_pass_rows(c, o->passes);
+    tlim::launch_fill(s, (double*)c->bar, 0.0, tlim::kStepMaxTiles / 2);
+    double* Tn = c->Tn == c->Tn_buf[0] ? c->Tn_buf[1] : c->Tn_buf[0];
+    tlim::Step2D st{};
+    st.alpha2 = c->field[TLIM_ALPHA2];
+    st.T1 = c->field[TLIM_T1];
+    st.T2 = T2_ptr(c);
+    st.m1 = c->field[TLIM_M1];
+    st.m2 = c->field[TLIM_M2];
+    st.Tn = Tn;
+    st.a2n = c->a2n;
+    st.rC = c->rC;
+    // the last pass writes the T1 field (the relaxation has read it by then)
+    const int f = (o->passes - 1) & 1;
+    st.Tout[f] = c->field[TLIM_T1];
+    st.Tout[1 - f] = c->Tnew;
+    st.vx[0] = c->vb[0];
+    st.vx[1] = c->vb[1];
+    st.acc = c->acc;
+    st.bar = c->bar;
+    st.chat = c->chat_tab;
+    st.pmax = kStepPmax;
+    st.passes = o->passes;
+    if (!tlim::launch_step2d(s, g, dev_phases(c), o->alpha_eps, o->dt, o->face_mean, st)) return false;
+    c->Tn = Tn;
+    c->g_heat = Tn;
+    std::swap(c->field[TLIM_ALPHA2], c->a2n);
+    c->t2_alias = true;
+    tlim::launch_collect(s, c->acc, res ? res : c->res_dev, tlim::tgt_lam(0), tlim::kTgtP0 + o->passes, 1);
+    c->clean_rows = c->clean_keep;
+    return true;
+}
+
+// Outcome of a whole-step run from its folded rows.  A failure count means
+// a P beyond the table (rerun the passes from the relaxed state) or a
+// barrier time-out.
+struct Step2DResult {
+    bool out_of_range = false, timeout = false;
+    int P[TLIM_MAX_PASSES];
+    double lam[TLIM_MAX_PASSES];
+};
+void step2d_result(const PassResult* r, int passes, Step2DResult& o) {
+    o = Step2DResult{};
+    for (int i = 0; i < passes; ++i) {
+        o.lam[i] = r->v[tlim::tgt_lam(i)];
+        const double P = r->v[tlim::kTgtP0 + i];
+        o.P[i] = (int)P;
+        if (r->v[tlim::kTgtFlag] > 0.0 && !(P >= 1.0 && P <= kStepPmax)) o.out_of_range = true;
+    }
+    if (r->v[tlim::kTgtFlag] > 0.0 && !o.out_of_range) o.timeout = true;
+}
+
+// One step's heat part by the whole-step kernel with a readback; on return
+// `done` tells whether it ran (else the caller takes the launch-per-stage
+// path from the unrelaxed state).
+tlim_status step2d_sync(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep, Timer& tm, SweepCount& sc,
+                        HeatOutcome& out, bool& done) {
+    done = false;
+    tlim_status st = step2d_table(c, o->order);
+    if (st) return st;
+    tm.start();
+    const bool ok = step2d_enqueue(c, o, c->res_host_dev);
+    tm.stop();
+    if (!ok) return TLIM_OK;
+    done = true;
+    if (!c->res_host_dev) HIP_TRY(c, hipMemcpyAsync(c->res_host, c->res_dev, sizeof(PassResult), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    Step2DResult r;
+    step2d_result(c->res_host, o->passes, r);
+    if (r.timeout) return fail(c, TLIM_E_HIP, "whole-step kernel: barrier time-out");
+    if (r.out_of_range) {
+        // schedule beyond the table: the passes again, one launch per block of stages
+        out = HeatOutcome{};
+        return heat_passes(c, o, Mode::Sync, rep, tm, sc, out, false);
+    }
+    out.passes_run = o->passes;
+    out.converged = true;
+    auto change = [&](int i) {
+        const double tmax = result(c, tlim::tgt_tmax(i)), dmax = result(c, tlim::tgt_dmax(i));
+        return tmax > 0.0 ? dmax / tmax : dmax;
+    };
+    out.last_err = change(o->passes - 1);
+    out.bad = result(c, tlim::tgt_bad(o->passes - 1));
+    for (int i = 0; i < o->passes; ++i) {
+        sc.sweeps += 2 * r.P[i] - 1;
+        if (rep) {
+            rep->P[i] = r.P[i];
+            rep->lambda_G[i] = r.lam[i];
+            rep->err[i] = change(i);
+        }
+    }
+    sc.launches += 1;
+    record_schedule(c, o->passes, r.lam, o->dt);
+    return TLIM_OK;
+}
+
 // Temperature relaxation at the start of a step (Sec. 3.4.1).  On 2D grids
 // without sources it is fused with the first pass's coefficients and bound
 // (returns true); the relaxed state goes to Tn and a2n, and a2n becomes the
@@ -1048,26 +1193,33 @@ tlim_status advance_sync(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
         st = viscous(c, o, rep, tm, sc);
         if (st) return st;
     }
-    const bool pass0_done = relax_step(c, o);
-
-    Mode mode = Mode::Sync;
-    if (o->frozen_lambda) mode = Mode::Frozen;
-    else if (!o->cycle_mode && o->picard_tol <= 0.0 && c->hist_passes == o->passes) mode = Mode::Predict;
     HeatOutcome out;
-    st = heat_passes(c, o, mode, rep, tm, sc, out, pass0_done);
-    if (st) return st;
-    const bool predicted = mode == Mode::Predict && !out.mispredicted;
-    const bool mispredicted = out.mispredicted;
-    if (out.mispredicted) {
-        // roll back to the relaxed state and rerun with one readback per pass;
-        // only the rerun's sweeps count
-        c->predict_misses++;
-        if (B1) tlim::launch_copy(s, c->field[TLIM_ALPHA2], c->a2n, c->N);
-        out = HeatOutcome{};
-        sc = SweepCount{};
-        tm.reset();
-        st = heat_passes(c, o, Mode::Sync, rep, tm, sc, out, false);
+    bool whole = false;  // relaxation and passes by the whole-step kernel
+    if (step2d_ok(c, o)) {
+        st = step2d_sync(c, o, rep, tm, sc, out, whole);
         if (st) return st;
+    }
+    bool predicted = false, mispredicted = false;
+    if (!whole) {
+        const bool pass0_done = relax_step(c, o);
+        Mode mode = Mode::Sync;
+        if (o->frozen_lambda) mode = Mode::Frozen;
+        else if (!o->cycle_mode && o->picard_tol <= 0.0 && c->hist_passes == o->passes) mode = Mode::Predict;
+        st = heat_passes(c, o, mode, rep, tm, sc, out, pass0_done);
+        if (st) return st;
+        predicted = mode == Mode::Predict && !out.mispredicted;
+        mispredicted = out.mispredicted;
+        if (out.mispredicted) {
+            // roll back to the relaxed state and rerun with one readback per
+            // pass; only the rerun's sweeps count
+            c->predict_misses++;
+            if (B1) tlim::launch_copy(s, c->field[TLIM_ALPHA2], c->a2n, c->N);
+            out = HeatOutcome{};
+            sc = SweepCount{};
+            tm.reset();
+            st = heat_passes(c, o, Mode::Sync, rep, tm, sc, out, false);
+            if (st) return st;
+        }
     }
     if (c->fset[TLIM_E]) tlim::launch_total_energy_heat(s, c->N, c->field[TLIM_T1], c->Tn, c->rC, c->field[TLIM_E]);
     if (rep) {
@@ -1152,6 +1304,31 @@ void enqueue_predicted(tlim_ctx* c, const tlim_step_opts* o, tlim_ctx::Pending& 
     p.Tn = c->Tn;
     p.alpha2 = c->field[TLIM_ALPHA2];
     p.alpha2_other = c->a2n;
+    p.whole = false;
+}
+
+// Steps the whole-step kernel may run pipelined (its P needs no prediction):
+// no report, no viscous part, no total energy, no timing.
+bool pipeline_whole_ok(const tlim_ctx* c, const tlim_step_opts* o, const tlim_step_report* rep) {
+    return !rep && !o->do_viscous && !o->time_sweeps && !c->fset[TLIM_E] && c->res_host_dev != nullptr &&
+           step2d_ok(c, o);
+}
+
+// Enqueue a whole-step kernel step and the fold of its rows into its own
+// pinned block, followed by an event.  False: the launch was refused.
+bool enqueue_whole(tlim_ctx* c, const tlim_step_opts* o, tlim_ctx::Pending& p) {
+    next_result_block(c);
+    if (!step2d_enqueue(c, o, c->res_host_dev)) return false;
+    (void)hipEventRecord(c->ev_pend[c->res_cur], c->stream);
+    p.o = *o;
+    p.o.frozen_lambda = nullptr;
+    p.o.frozen_visc = nullptr;
+    p.blk = c->res_cur;
+    p.Tn = c->Tn;
+    p.alpha2 = c->field[TLIM_ALPHA2];
+    p.alpha2_other = c->a2n;
+    p.whole = true;
+    return true;
 }
 
 struct Verdict {
@@ -1180,9 +1357,20 @@ Verdict verify(tlim_ctx* c, const tlim_ctx::Pending& p) {
     }
     const PassResult* res = c->res_blk[p.blk];
     const int np = p.o.passes;
-    for (int i = 0; i < np; ++i) {
-        v.lam[i] = res->v[tlim::tgt_lam(i)];
-        if (lim_P(p.o.dt, v.lam[i]) != p.P_used[i]) v.mispredicted = true;
+    if (p.whole) {
+        Step2DResult r;
+        step2d_result(res, np, r);
+        if (r.timeout) {
+            v.st = fail(c, TLIM_E_HIP, "whole-step kernel: barrier time-out");
+            return v;
+        }
+        v.mispredicted = r.out_of_range;  // redone with one launch per block of stages
+        for (int i = 0; i < np; ++i) v.lam[i] = r.lam[i];
+    } else {
+        for (int i = 0; i < np; ++i) {
+            v.lam[i] = res->v[tlim::tgt_lam(i)];
+            if (lim_P(p.o.dt, v.lam[i]) != p.P_used[i]) v.mispredicted = true;
+        }
     }
     v.bad = res->v[tlim::tgt_bad(np - 1)];
     return v;
@@ -1228,7 +1416,8 @@ tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
     if (st) return st;
     st = check_ready(c);
     if (st) return st;
-    if (!pipeline_ok(c, o, rep)) {
+    const bool whole = pipeline_whole_ok(c, o, rep) && step2d_table(c, o->order) == TLIM_OK;
+    if (!whole && !pipeline_ok(c, o, rep)) {
         st = resolve(c);
         if (st) return st;
         return advance_sync(c, o, rep);
@@ -1236,7 +1425,15 @@ tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
     // Pipelined: enqueue this step first, then verify the previous one while
     // this one runs.
     tlim_ctx::Pending np{};
-    enqueue_predicted(c, o, np);
+    if (whole) {
+        if (!enqueue_whole(c, o, np)) {
+            st = resolve(c);
+            if (st) return st;
+            return advance_sync(c, o, rep);
+        }
+    } else {
+        enqueue_predicted(c, o, np);
+    }
     c->pipelined_steps++;
     if (!c->pending) {
         c->pending = true;

@@ -51,7 +51,7 @@ class StepOptsC(C.Structure):
                 ("cycle_tol", C.c_double), ("max_cycles", C.c_int32), ("alpha_eps", C.c_double),
                 ("do_viscous", C.c_int32), ("frozen_lambda", C.POINTER(C.c_double)),
                 ("frozen_visc", C.POINTER(C.c_double)), ("time_sweeps", C.c_int32),
-                ("visc_heating", C.c_int32)]
+                ("visc_heating", C.c_int32), ("whole_step", C.c_int32)]
 
 
 class ReportC(C.Structure):
@@ -120,12 +120,14 @@ class StepOpts:
     frozen_visc: Optional[Sequence[float]] = None
     time_sweeps: int = 0
     visc_heating: int = 0
+    whole_step: int = 0
     _keep: list = dc_field(default_factory=list, repr=False)
 
     def c(self) -> StepOptsC:
         o = StepOptsC()
         for k in ("dt", "passes", "picard_tol", "order", "face_mean", "cycle_mode", "cycle_tol",
-                  "max_cycles", "alpha_eps", "do_viscous", "time_sweeps", "visc_heating"):
+                  "max_cycles", "alpha_eps", "do_viscous", "time_sweeps", "visc_heating",
+                  "whole_step"):
             setattr(o, k, getattr(self, k))
         self._keep = []
         for name in ("frozen_lambda", "frozen_visc"):

@@ -78,6 +78,46 @@ def test_levelset2d_fp64_full_size():
     # after the first step the schedule is predicted and confirmed without a
     # readback per pass
     assert not rg[0]["predicted"] and sum(r["predicted"] for r in rg[1:]) >= 5
+    # the same run as one launch per step, P decided on the device
+    fw, rw, _ = run_gpu(wl, tau, 10, whole_step=1)
+    assert [r["P"] for r in rw] == [r["P"] for r in ro]
+    assert all(r["sweep_launches"] == 1 for r in rw)
+    _compare(fo, fw, FIELDS_T, 1e-12)
+
+
+@pytest.mark.parametrize("shape,bc", [((256, 256), "periodic"), ((300, 200), "adiabatic"),
+                                      ((70, 390), "periodic"), ((1000, 131), "adiabatic")])
+def test_whole_step_kernel_vs_oracle(shape, bc):
+    """FP64 2D heat steps whose schedule is decided on the device: one
+    cooperative launch per step (relaxation, every Picard pass with its P
+    from the reduced lambda_G, stages in blocks with ring exchanges),
+    against the oracle deciding its own P (3 steps x 3 passes), then the
+    same steps pipelined without reports."""
+    from oracle import oracle as orc
+    from paper_2106_00282_amd.tlim import StepOpts
+    nx, ny = shape
+    ng = max(128, nx, ny)
+    wl = W.levelset2d(ng)
+    for k in wl["fields"]:
+        wl["fields"][k] = np.ascontiguousarray(wl["fields"][k][:, :ny, :nx])
+    wl["n"] = (nx, ny, 1)
+    wl["h"] = (1.0 / ng, 1.0 / ng, 1.0)
+    if bc == "adiabatic":
+        wl["bc"] = (W.ADIABATIC, W.ADIABATIC, W.PERIODIC)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 3)
+    fg, rg, _ = run_gpu(wl, tau, 3, whole_step=1)
+    assert [r["P"] for r in rg] == [r["P"] for r in ro]
+    assert all(r["sweep_launches"] == 1 for r in rg), [r["sweep_launches"] for r in rg]
+    assert all(r["sweeps"] == sum(2 * p - 1 for p in r["P"]) for r in rg)
+    _compare(fo, fg, FIELDS_T, 1e-12)
+    for r in rg:
+        assert abs(r["energy_after"] / r["energy_before"] - 1) < 1e-13
+    s = make_solver(wl)
+    for _ in range(3):
+        assert s.advance(StepOpts(dt=tau, passes=wl["passes"], whole_step=1), report=False)[0] == 0
+    s.finish()
+    assert rel_err(s.get_field("T1").cpu().numpy(), fo["T1"]) < 1e-12
 
 
 def test_bubbles3d_fp64_with_viscous():
@@ -244,13 +284,15 @@ def test_mispredicted_schedule_rolls_back():
     assert rel_err(s.get_field("T1").cpu().numpy(), fo["T1"]) < 1e-12
 
 
-@pytest.mark.parametrize("precision,n,hot,miss", [("fp64", 256, 1.0, False), ("fp64", 192, 3.0, True),
-                                                  ("fp32", 192, 3.0, True), ("fp32", 256, 3.0, False)])
-def test_pipelined_steps_match_oracle(precision, n, hot, miss):
+@pytest.mark.parametrize("precision,n,hot,miss,whole", [("fp64", 256, 1.0, False, 0), ("fp64", 192, 3.0, True, 0),
+                                                        ("fp32", 192, 3.0, True, 0), ("fp32", 256, 3.0, False, 0),
+                                                        ("fp64", 192, 3.0, True, 1)])
+def test_pipelined_steps_match_oracle(precision, n, hot, miss, whole):
     """Steps without a report run pipelined (each verified by the next call).
     With a hot spot (T up to 1 + hot) lambda_G falls from step to step, so
     the P predicted from two steps back is wrong now and then and the step
-    must be redone; the result must still match the oracle's unfrozen run."""
+    must be redone; the result must still match the oracle's unfrozen run.
+    FP64 with whole = 1 runs each step as one launch that decides P itself."""
     from oracle import oracle as orc
     from paper_2106_00282_amd.tlim import StepOpts
     wl = W.levelset2d(n)
@@ -265,7 +307,7 @@ def test_pipelined_steps_match_oracle(precision, n, hot, miss):
     fo, ro = run_oracle(orc, wl, tau, steps)
     Ps = [r["P"] for r in ro]
     s = make_solver(wl, precision)
-    o = StepOpts(dt=tau, passes=3)
+    o = StepOpts(dt=tau, passes=3, whole_step=whole)
     st, rep = s.advance(o)  # first step: synchronous, sets the schedule history
     assert st == 0 and rep["P"] == Ps[0]
     for _ in range(steps - 1):
@@ -280,13 +322,14 @@ def test_pipelined_steps_match_oracle(precision, n, hot, miss):
         assert any(Ps[k] != [Ps[k - 2][-1]] * 3 for k in range(2, steps)), Ps
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_pipelined_dt_change_redoes_steps(precision):
+@pytest.mark.parametrize("precision,whole", [("fp64", 0), ("fp32", 0), ("fp64", 1)])
+def test_pipelined_dt_change_redoes_steps(precision, whole):
     """Once the schedule is steady, steps without a report run pipelined.  A
     larger dt then makes the pending step's predicted P wrong: the next call
     finds it after enqueuing its own step, redoes the pending one and reruns
     its own; a final finish() completes the last one.  Matches the oracle run
-    with the same dt sequence."""
+    with the same dt sequence.  The one-launch FP64 step (whole = 1) decides
+    P on the device: it pipelines from the first step and redoes nothing."""
     from oracle import oracle as orc
     from paper_2106_00282_amd.tlim import StepOpts
     wl = W.levelset2d(160)
@@ -297,21 +340,25 @@ def test_pipelined_dt_change_redoes_steps(precision):
     s = make_solver(wl, precision)
     for dt in dts:
         orc.step(g, wl["phases"], orc.StepOpts(tau=dt, passes=3), fo)
-        assert s.advance(StepOpts(dt=dt, passes=3), report=False)[0] == 0
+        assert s.advance(StepOpts(dt=dt, passes=3, whole_step=whole), report=False)[0] == 0
     assert s.finish() == 0
     # one reported step reads the context's pipelining totals
     orc.step(g, wl["phases"], orc.StepOpts(tau=tau, passes=3), fo)
-    st, rep = s.advance(StepOpts(dt=tau, passes=3))
+    st, rep = s.advance(StepOpts(dt=tau, passes=3, whole_step=whole))
     assert st == 0
-    assert rep["pipelined_steps"] >= 3 and rep["pipeline_redos"] >= 1, rep
+    if precision == "fp64" and whole:
+        assert rep["pipelined_steps"] == len(dts) and rep["pipeline_redos"] == 0, rep
+    else:
+        assert rep["pipelined_steps"] >= 3 and rep["pipeline_redos"] >= 1, rep
     fg = {k: s.get_field(k).cpu().numpy() for k in FIELDS_T}
     _compare(fo, fg, FIELDS_T, 1e-12 if precision == "fp64" else 1e-5)
 
 
-def test_pipelined_step_then_report_and_phase_change():
+@pytest.mark.parametrize("whole", [0, 1])
+def test_pipelined_step_then_report_and_phase_change(whole):
     """A pending pipelined step is completed by set_phase (which may make
     the next prediction wrong) and by a reported step; the sequence matches
-    the oracle."""
+    the oracle (FP64, one launch per step or per block of stages)."""
     from oracle import oracle as orc
     from paper_2106_00282_amd.tlim import StepOpts
     wl = W.levelset2d(128)
@@ -320,7 +367,7 @@ def test_pipelined_step_then_report_and_phase_change():
     fo = {k: v.copy() for k, v in wl["fields"].items()}
     s = make_solver(wl)
     ph = [dict(p) for p in wl["phases"]]
-    o = StepOpts(dt=tau, passes=3)
+    o = StepOpts(dt=tau, passes=3, whole_step=whole)
     for step, (scale, report) in enumerate(((1.0, True), (1.0, False), (1.0, False), (3.0, False), (3.0, False),
                                              (3.0, True), (3.0, False))):
         for k in range(2):
