@@ -57,6 +57,11 @@ enum { TLIM_PERIODIC = 0, TLIM_ADIABATIC = 1 };         /* boundary per axis */
 enum { TLIM_FP64 = 0, TLIM_FP32 = 1 };                 /* arithmetic of the sweeps */
 enum { TLIM_ORDER_INTERLEAVED = 0, TLIM_ORDER_PAPER = 1, TLIM_ORDER_ASCENDING = 2 };
 enum { TLIM_FACE_ARITH = 0, TLIM_FACE_HARMONIC = 1 };
+/* whole_step: AUTO uses the one-launch step while the context has no
+ * schedule history for the step's pass count (its first step, whose P
+ * would otherwise be read back pass by pass), ALWAYS for every eligible
+ * step, NEVER for none. */
+enum { TLIM_WHOLE_AUTO = 0, TLIM_WHOLE_ALWAYS = 1, TLIM_WHOLE_NEVER = 2 };
 
 /* Fields of the state (Sec. 3.4, data of Algorithm 1): volume fraction of
  * phase 2, partial densities m_k = alpha_k rho_k (constant in this step),
@@ -111,11 +116,12 @@ typedef struct {
     int32_t time_sweeps;         /* 1: time the sweep launches with HIP events (report.sweep_ms) */
     int32_t visc_heating;        /* with do_viscous: the viscous part also heats the phases (Sec. 3.2,
                                     phase internal-energy update with the predicted velocity) */
-    int32_t whole_step;          /* 1: FP64 2D steps without sources and with equal p_inf whose tiles
-                                    all fit on the device at once run as one cooperative launch
-                                    (relaxation and every pass, P decided on the device from the
-                                    reduced lambda_G, no host prediction); 0: one launch per block
-                                    of stages.  Same results up to rounding order */
+    int32_t whole_step;          /* TLIM_WHOLE_*: when an FP64 2D step without sources and with equal
+                                    p_inf, whose tiles all fit on the device at once, runs as one
+                                    cooperative launch (relaxation and every pass, P decided on the
+                                    device from the reduced lambda_G, no host prediction) instead of
+                                    one launch per block of stages.  Same results up to rounding
+                                    order */
 } tlim_step_opts;
 
 #define TLIM_MAX_PASSES 64

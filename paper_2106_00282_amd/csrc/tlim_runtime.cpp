@@ -244,6 +244,22 @@ std::vector<double> cycle_params(int s, double lambda_max) {
     return b;
 }
 
+// b/lambda of every P <= kStepPmax for the stage order, at offset (P-1)^2.
+// Built when a context binds its workspace (default order) or when a step
+// asks for another order; the upload waits for the stream.
+tlim_status step2d_table(tlim_ctx* c, int order) {
+    if (c->chat_order == order) return TLIM_OK;
+    std::vector<double> t((size_t)kStepPmax * kStepPmax, 0.0);
+    for (int P = 1; P <= kStepPmax; ++P) {
+        const std::vector<double> ch = lim_params(P, 1.0, order);
+        std::copy(ch.begin(), ch.end(), t.begin() + (size_t)(P - 1) * (P - 1));
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->chat_tab, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->chat_order = order;
+    return TLIM_OK;
+}
+
 // ------------------------------------------------------------------ checks
 
 tlim_status check_ready(tlim_ctx* c, bool need_T = true) {
@@ -924,7 +940,7 @@ tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
         c->Lam32_alt = c->q32_alt = c->wzero = nullptr;
     }
     c->w0_zero = false;
-    return TLIM_OK;
+    return step2d_table(c, TLIM_ORDER_INTERLEAVED);
 }
 
 tlim_status tlim_set_phase(tlim_ctx* c, int32_t k, const tlim_phase* p) {
@@ -1007,28 +1023,16 @@ namespace {
 // ---- whole-step kernel (2D, FP64, no sources, equal p_inf)
 
 // The step runs as one cooperative launch (relaxation and every Picard pass,
-// P decided on the device) when asked, the grid's tiles can all be resident
-// and the schedule is not given by the caller.
+// P decided on the device) when asked (always, or while there is no schedule
+// history to predict P from), the grid's tiles can all be resident and the
+// schedule is not given by the caller.
 bool step2d_ok(const tlim_ctx* c, const tlim_step_opts* o) {
-    if (!o->whole_step || c->precision != TLIM_FP64 || o->cycle_mode || o->frozen_lambda || o->picard_tol > 0.0)
+    if (o->whole_step == TLIM_WHOLE_NEVER || (o->whole_step == TLIM_WHOLE_AUTO && c->hist_passes == o->passes))
         return false;
+    if (c->precision != TLIM_FP64 || o->cycle_mode || o->frozen_lambda || o->picard_tol > 0.0) return false;
     if (c->phase[0].pinf != c->phase[1].pinf) return false;
     const DevGrid g = dev_grid(c, kUnit);
     return fast_coeffs(c, g) && tlim::step2d_tiles(g) > 0;
-}
-
-// b/lambda of every P <= kStepPmax for the stage order, at offset (P-1)^2.
-tlim_status step2d_table(tlim_ctx* c, int order) {
-    if (c->chat_order == order) return TLIM_OK;
-    std::vector<double> t((size_t)kStepPmax * kStepPmax, 0.0);
-    for (int P = 1; P <= kStepPmax; ++P) {
-        const std::vector<double> ch = lim_params(P, 1.0, order);
-        std::copy(ch.begin(), ch.end(), t.begin() + (size_t)(P - 1) * (P - 1));
-    }
-    HIP_TRY(c, hipMemcpyAsync(c->chat_tab, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    c->chat_order = order;
-    return TLIM_OK;
 }
 
 // Enqueue a step by the whole-step kernel followed by the fold of its rows
@@ -1310,8 +1314,8 @@ void enqueue_predicted(tlim_ctx* c, const tlim_step_opts* o, tlim_ctx::Pending& 
 // Steps the whole-step kernel may run pipelined (its P needs no prediction):
 // no report, no viscous part, no total energy, no timing.
 bool pipeline_whole_ok(const tlim_ctx* c, const tlim_step_opts* o, const tlim_step_report* rep) {
-    return !rep && !o->do_viscous && !o->time_sweeps && !c->fset[TLIM_E] && c->res_host_dev != nullptr &&
-           step2d_ok(c, o);
+    return o->whole_step == TLIM_WHOLE_ALWAYS && !rep && !o->do_viscous && !o->time_sweeps && !c->fset[TLIM_E] &&
+           c->res_host_dev != nullptr && step2d_ok(c, o);
 }
 
 // Enqueue a whole-step kernel step and the fold of its rows into its own

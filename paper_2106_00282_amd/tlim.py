@@ -22,6 +22,7 @@ PERIODIC, ADIABATIC = 0, 1
 FP64, FP32 = 0, 1
 ORDER_INTERLEAVED, ORDER_PAPER, ORDER_ASCENDING = 0, 1, 2
 FACE_ARITH, FACE_HARMONIC = 0, 1
+WHOLE_AUTO, WHOLE_ALWAYS, WHOLE_NEVER = 0, 1, 2
 FIELDS = dict(alpha2=0, m1=1, m2=2, T1=3, T2=4, u=5, v=6, w=7, src1=8, src2=9, E=10)
 MAX_PASSES = 64
 

@@ -75,9 +75,11 @@ def test_levelset2d_fp64_full_size():
     _compare(fo, fg, FIELDS_T, 1e-12)
     for r in rg:
         assert abs(r["energy_after"] / r["energy_before"] - 1) < 1e-13
-    # after the first step the schedule is predicted and confirmed without a
-    # readback per pass
-    assert not rg[0]["predicted"] and sum(r["predicted"] for r in rg[1:]) >= 5
+    # the first step (no schedule history) runs as one launch that decides P
+    # on the device; after it the schedule is predicted and confirmed without
+    # a readback per pass
+    assert rg[0]["sweep_launches"] == 1 and not rg[0]["predicted"]
+    assert sum(r["predicted"] for r in rg[1:]) >= 5
     # the same run as one launch per step, P decided on the device
     fw, rw, _ = run_gpu(wl, tau, 10, whole_step=1)
     assert [r["P"] for r in rw] == [r["P"] for r in ro]
@@ -109,6 +111,11 @@ def test_whole_step_kernel_vs_oracle(shape, bc):
     fg, rg, _ = run_gpu(wl, tau, 3, whole_step=1)
     assert [r["P"] for r in rg] == [r["P"] for r in ro]
     assert all(r["sweep_launches"] == 1 for r in rg), [r["sweep_launches"] for r in rg]
+    # never: the first step reads P back pass by pass
+    fn, rn, _ = run_gpu(wl, tau, 3, whole_step=2)
+    assert [r["P"] for r in rn] == [r["P"] for r in ro]
+    assert rn[0]["sweep_launches"] > 1
+    _compare(fo, fn, FIELDS_T, 1e-12)
     assert all(r["sweeps"] == sum(2 * p - 1 for p in r["P"]) for r in rg)
     _compare(fo, fg, FIELDS_T, 1e-12)
     for r in rg:
