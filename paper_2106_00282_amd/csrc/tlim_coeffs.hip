@@ -20,7 +20,9 @@
 // conductivities of three consecutive rows in registers; the x-neighbours
 // come from the adjacent lanes (DPP).  Loads of T and alpha2 are coalesced
 // 512 B rows; halo overhead is (kRows+2)/kRows x 64/62.  No LDS, no barrier:
-// waves are independent.
+// waves are independent.  Strips of 4 rows: more waves in flight hide the
+// memory latency better than the smaller halo of 8 rows saves (the fused
+// relaxation kernel measured 23.6 us against 30.2 us at 1024^2).
 #include <hip/hip_runtime.h>
 
 #include "tlim_device.h"
@@ -37,7 +39,7 @@ using tb::fold;
 using tb::from_left;
 using tb::from_right;
 
-constexpr int kRows = 8;
+constexpr int kRows = 4;
 constexpr int kOut = 62;
 constexpr int kWaves = 4;
 
