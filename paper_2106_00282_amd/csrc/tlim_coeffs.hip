@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_coeffs2d(Coef2DArgs a) {
 // 3D grids: the same per-cell work, with each wave marching through a chunk
 // of z planes (kRows3 rows per wave) and keeping the conductivities (and g)
 // of the previous, current and next plane in registers.
-constexpr int kRows3 = 4;
+constexpr int kRows3 = 2;
 
 template <bool kRelax>
 __global__ void __launch_bounds__(64 * kWaves) k_coeffs3d(Coef2DArgs a) {

@@ -43,6 +43,7 @@ enum {
     kTgtK0a,
     kTgtK0b,
     kTgtFlag,      // whole-step kernel: failure count (schedule out of range, barrier time-out)
+    kTgtNextStep,  // bound of the next step's first pass, built by this step's last launch
     kTgtP0,        // whole-step kernel: P of pass it in slot 0 of row kTgtP0 + it
     kTargets = kTgtP0 + kMaxPasses
 };
@@ -62,8 +63,9 @@ struct PassResult {
 };
 
 // Fold rows [t0, t1) of the accumulator into res->v[t0..t1) (res may be
-// pinned host memory); consume = 1 also zeroes the rows.
-void launch_collect(hipStream_t s, double* acc, PassResult* res, int t0, int t1, int consume);
+// pinned host memory); consume = 1 also zeroes the rows.  move_from >= 0:
+// afterwards row t0 takes the contents of row move_from, which is zeroed.
+void launch_collect(hipStream_t s, double* acc, PassResult* res, int t0, int t1, int consume, int move_from = -1);
 // Zero rows [t0, t1) of the accumulator.
 void launch_zero_rows(hipStream_t s, double* acc, int t0, int t1);
 

@@ -683,8 +683,11 @@ __global__ void __launch_bounds__(256) k_total_energy_heat(int64_t n, const doub
 }
 
 // One wave per target row folds its kSlots slots with the target's
-// operation; consume = 1 also clears the row for its next use.
-__global__ void __launch_bounds__(64) k_collect(double* __restrict__ acc, PassResult* res, int t0, int consume) {
+// operation; consume = 1 also clears the row for its next use.  With
+// move_from >= 0 the wave of row t0 then moves row move_from into it (and
+// clears move_from): each lane touches only its own slots, in order.
+__global__ void __launch_bounds__(64) k_collect(double* __restrict__ acc, PassResult* res, int t0, int consume,
+                                                int move_from) {
     const int t = t0 + blockIdx.x, lane = threadIdx.x;
     double* row = acc + (int64_t)t * kSlots;
     const bool sum = tgt_is_sum(t);
@@ -694,6 +697,14 @@ __global__ void __launch_bounds__(64) k_collect(double* __restrict__ acc, PassRe
     if (consume) {
 #pragma unroll
         for (int k = 0; k < kSlots / 64; ++k) row[lane + 64 * k] = 0.0;
+    }
+    if (move_from >= 0 && blockIdx.x == 0) {
+        double* f = acc + (int64_t)move_from * kSlots;
+#pragma unroll
+        for (int k = 0; k < kSlots / 64; ++k) {
+            row[lane + 64 * k] = f[lane + 64 * k];
+            f[lane + 64 * k] = 0.0;
+        }
     }
     v = sum ? wave_sum(v) : wave_max(v);
     if (lane == 0) res->v[t] = v;
@@ -726,8 +737,8 @@ void launch_zero_rows(hipStream_t s, double* acc, int t0, int t1) {
     hipLaunchKernelGGL(k_fill, dim3(pointwise_blocks(n)), dim3(256), 0, s, acc + (int64_t)t0 * kSlots, 0.0, n);
 }
 
-void launch_collect(hipStream_t s, double* acc, PassResult* res, int t0, int t1, int consume) {
-    hipLaunchKernelGGL(k_collect, dim3(t1 - t0), dim3(64), 0, s, acc, res, t0, consume);
+void launch_collect(hipStream_t s, double* acc, PassResult* res, int t0, int t1, int consume, int move_from) {
+    hipLaunchKernelGGL(k_collect, dim3(t1 - t0), dim3(64), 0, s, acc, res, t0, consume, move_from);
 }
 
 void launch_relax(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double* alpha2,

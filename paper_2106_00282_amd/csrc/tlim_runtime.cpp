@@ -56,6 +56,14 @@ struct tlim_ctx {
     float *Lam32, *rC32, *q32, *wb[2];
     float *Lam32_alt, *q32_alt;  // the next pass's float coefficients, built by the pass before
     float* wzero;                // all zero: the correction form's start w0 = T^n - g without sources
+    double* rC_alt;              // the next step's 1/C, built by the last launch of a step
+    // The last launch of an FP64 step has relaxed the next step's state and
+    // built its first coefficients (valid until the state or the phases
+    // change); spare_clean: the row of that bound is zero.
+    // row0_moved: the step-end fold moved that bound into the first pass's
+    // row (zero it before any other use).
+    bool next_ready, spare_clean, row0_moved;
+    double next_eps;
     double* chat_tab;            // whole-step kernel: b/lambda per P (order chat_order, -1: not built)
     int chat_order;
     unsigned* bar;               // whole-step kernel: barrier counter
@@ -67,7 +75,14 @@ struct tlim_ctx {
     PassResult* res_blk[2];    // two pinned result blocks: a pipelined step keeps its own
     PassResult* res_blk_dev[2];
     int res_cur;
-    double* Tn_buf[2];         // T^n of consecutive steps alternate between two arrays
+    // T^n of consecutive steps rotate through three arrays and the relaxed
+    // alpha2 through the alpha2 field, a2n and a2x: a step's T^n and alpha2
+    // outlive the enqueue of the next step and of the one after it (whose
+    // start a step's last launch may build ahead of time).
+    double* Tn_buf[3];
+    double* a2x;
+    double* a2pool[3];  // the three alpha2 arrays
+    double *next_tn, *next_a2;  // where the next step's start was built
     // A predicted step enqueued without waiting for its readback (pipelined
     // mode); it is verified by the next call.
     bool pending;
@@ -126,7 +141,7 @@ tlim_status fail(tlim_ctx* c, tlim_status s, const char* fmt, ...) {
 // Layout of the workspace: byte offsets of every array (all 256-aligned).
 struct Layout {
     size_t field[TLIM_NFIELDS];
-    size_t Tn, Tn2, Tnew, a2n, Lam, Lam2, rC, rhs, vb[2], acc, res;
+    size_t Tn, Tn2, Tn3, Tnew, a2n, a2x, Lam, Lam2, rC, rC2, rhs, vb[2], acc, res;
     size_t Lam32, rC32, q32, wb[2], Lam32b, q32b, wzero;
     size_t chat, bar;
     size_t total;
@@ -141,7 +156,8 @@ Layout layout_of(const int64_t n[3], int precision) {
         L.field[i] = off;
         off += d;
     }
-    size_t* dd[] = {&L.Tn, &L.Tn2, &L.Tnew, &L.a2n, &L.Lam, &L.Lam2, &L.rC, &L.rhs, &L.vb[0], &L.vb[1]};
+    size_t* dd[] = {&L.Tn, &L.Tn2, &L.Tn3, &L.Tnew, &L.a2n, &L.a2x, &L.Lam, &L.Lam2, &L.rC, &L.rC2, &L.rhs,
+                    &L.vb[0], &L.vb[1]};
     for (size_t* p : dd) {
         *p = off;
         off += d;
@@ -463,12 +479,12 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
 
 // Fold the rows [t0, t1) and bring the results to the host (synchronises).
 // With consume the rows are also cleared on the device.
-tlim_status read_result(tlim_ctx* c, int t0, int t1, bool consume = false) {
+tlim_status read_result(tlim_ctx* c, int t0, int t1, bool consume = false, int move_from = -1) {
     if (c->res_host_dev) {
         // the fold writes straight into the pinned result block
-        tlim::launch_collect(c->stream, c->acc, c->res_host_dev, t0, t1, consume ? 1 : 0);
+        tlim::launch_collect(c->stream, c->acc, c->res_host_dev, t0, t1, consume ? 1 : 0, move_from);
     } else {
-        tlim::launch_collect(c->stream, c->acc, c->res_dev, t0, t1, consume ? 1 : 0);
+        tlim::launch_collect(c->stream, c->acc, c->res_dev, t0, t1, consume ? 1 : 0, move_from);
         HIP_TRY(c, hipMemcpyAsync(c->res_host, c->res_dev, sizeof(PassResult), hipMemcpyDeviceToHost, c->stream));
     }
     // The readbacks sit on the critical path between steps: poll the
@@ -489,6 +505,11 @@ tlim_status read_result(tlim_ctx* c, int t0, int t1, bool consume = false) {
 // Zero the rows of the Picard-pass targets a step uses, unless the previous
 // step's final readback left them zero.
 void begin_pass_rows(tlim_ctx* c, int passes) {
+    if (c->row0_moved) {
+        // a next-step bound that is not adopted: the rows are not clean
+        c->row0_moved = false;
+        c->clean_rows = 0;
+    }
     const int need = tlim::tgt_lam(passes);
     if (c->clean_rows < need) zero_rows(c, tlim::tgt_lam(0), need);
     c->clean_keep = std::max(c->clean_rows, need);
@@ -506,6 +527,7 @@ tlim_status viscous(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep,
                              c->rC, c->Lam32, c->rC32);
     const bool heat = o->visc_heating != 0;
     double* E = c->fset[TLIM_E] ? c->field[TLIM_E] : nullptr;
+    if (heat) c->next_ready = false;  // T changes before the relaxation
     if (heat && c->t2_alias) {
         // the phases are heated differently: T2 gets its own array again
         tlim::launch_copy(c->stream, c->field[TLIM_T2], c->field[TLIM_T1], c->N);
@@ -669,8 +691,59 @@ void adopt_next_coef(tlim_ctx* c) {
 }
 
 tlim::NextCoef next_coef(tlim_ctx* c, int it, const DevPhases& ph) {
-    return tlim::NextCoef{row(c, tlim::tgt_lam(it + 1)), c->field[TLIM_ALPHA2], c->Lam_alt, c->Lam32_alt, c->q32_alt,
-                          ph};
+    tlim::NextCoef nc{};
+    nc.lam = row(c, tlim::tgt_lam(it + 1));
+    nc.alpha2 = c->field[TLIM_ALPHA2];
+    nc.Lam = c->Lam_alt;
+    nc.Lam32 = c->Lam32_alt;
+    nc.q32 = c->q32_alt;
+    nc.ph = ph;
+    return nc;
+}
+
+// A T^n array that neither the current step nor a pending (unverified)
+// one uses.
+double* free_tn(const tlim_ctx* c) {
+    for (double* b : c->Tn_buf)
+        if (b != c->Tn && !(c->pending && b == c->pend.Tn)) return b;
+    return nullptr;  // unreachable: three arrays, at most two in use
+}
+
+// An alpha2 array (a2n or a2x, never the field) that a pending step does
+// not need for a redo.
+double* free_alpha2(const tlim_ctx* c) {
+    return c->pending && c->a2n == c->pend.alpha2 ? c->a2x : c->a2n;
+}
+
+// The last launch of an FP64 step without sources and with equal p_inf can
+// also relax the next step's state and build its first coefficients (what
+// the next step's relaxation kernel would compute from the same fields), as
+// long as nothing changes the state in between.
+bool next_step_ok(const tlim_ctx* c, const tlim_step_opts* o, const DevGrid& g) {
+    return c->precision == TLIM_FP64 && next_coef_ok(c, g) && !o->cycle_mode && o->picard_tol <= 0.0;
+}
+
+tlim::NextCoef next_step_coef(tlim_ctx* c, const tlim_step_opts* o, const DevPhases& ph) {
+    if (!c->spare_clean) zero_rows(c, tlim::kTgtNextStep, tlim::kTgtNextStep + 1);
+    c->spare_clean = false;
+    tlim::NextCoef nc{};
+    nc.lam = row(c, tlim::kTgtNextStep);
+    nc.alpha2 = c->field[TLIM_ALPHA2];
+    nc.Lam = c->Lam_alt;
+    nc.ph = ph;
+    nc.m1 = c->field[TLIM_M1];
+    nc.m2 = c->field[TLIM_M2];
+    nc.Tn = c->next_tn = free_tn(c);  // the next step's T^n array
+    nc.a2 = c->next_a2 = free_alpha2(c);
+    nc.rC = c->rC_alt;
+    nc.eps = o->alpha_eps;
+    return nc;
+}
+
+// After the last launch of a step: whether it built the next step's start.
+void note_next_step(tlim_ctx* c, const tlim_step_opts* o, bool done) {
+    c->next_ready = done;
+    c->next_eps = o->alpha_eps;
 }
 
 // pass0_done: the coefficients and bound of the first pass were built with
@@ -736,11 +809,18 @@ tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_st
             }
             if (!(res < o->cycle_tol)) out.cycle_fail = true;  // keep the last iterate
         } else {
-            tlim::NextCoef nc = next_coef(c, it, ph);
-            const bool want = !need_update && it + 1 < o->passes && next_coef_ok(c, g);
+            const bool last = it + 1 == o->passes;
+            const bool want = !need_update && !last && next_coef_ok(c, g);
+            const bool want_step = !need_update && last && next_step_ok(c, o, g);
+            tlim::NextCoef nc = want_step ? next_step_coef(c, o, ph) : next_coef(c, it, ph);
+            bool done = false;
             run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->g_heat, c->Tnew, need_update ? nullptr : Tit,
-                         pass_slots(c, it), tm, sc, true, nullptr, want ? &nc : nullptr, &coef_ready);
-            if (coef_ready) adopt_next_coef(c);
+                         pass_slots(c, it), tm, sc, true, nullptr, want || want_step ? &nc : nullptr, &done);
+            if (want_step) note_next_step(c, o, done);
+            else if (done) {
+                coef_ready = true;
+                adopt_next_coef(c);
+            }
         }
         if (need_update) {
             tlim::launch_pass_update(s, g, ph, o->alpha_eps, Tit, c->Tnew, c->Tn, c->a2n,
@@ -752,9 +832,16 @@ tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_st
     out.passes_run = it;
     if (!out.converged) {
         // it = o->passes here: the readback consumes every row the step used
-        tlim_status st = read_result(c, tlim::tgt_lam(0), tlim::tgt_lam(it), true);
+        // the next step's first bound, if this step's last launch built it,
+        // moves into the first pass's row with the same fold
+        const bool move = c->next_ready;
+        tlim_status st = read_result(c, tlim::tgt_lam(0), tlim::tgt_lam(it), true, move ? tlim::kTgtNextStep : -1);
         if (st) return st;
         c->clean_rows = c->clean_keep;
+        if (move) {
+            c->row0_moved = true;
+            c->spare_clean = true;
+        }
         int last = it - 1;
         out.last_err = change(last);
         out.bad = result(c, tlim::tgt_bad(last));
@@ -906,11 +993,20 @@ tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
     c->Tn = (double*)(base + L.Tn);
     c->Tn_buf[0] = c->Tn;
     c->Tn_buf[1] = (double*)(base + L.Tn2);
+    c->Tn_buf[2] = (double*)(base + L.Tn3);
+    c->a2x = (double*)(base + L.a2x);
     c->Tnew = (double*)(base + L.Tnew);
     c->a2n = (double*)(base + L.a2n);
+    c->a2pool[0] = c->field[TLIM_ALPHA2];
+    c->a2pool[1] = c->a2n;
+    c->a2pool[2] = c->a2x;
     c->Lam = (double*)(base + L.Lam);
     c->Lam_alt = (double*)(base + L.Lam2);
     c->rC = (double*)(base + L.rC);
+    c->rC_alt = (double*)(base + L.rC2);
+    c->next_ready = false;
+    c->spare_clean = true;  // zeroed below
+    c->row0_moved = false;
     c->rhs = (double*)(base + L.rhs);
     c->vb[0] = (double*)(base + L.vb[0]);
     c->vb[1] = (double*)(base + L.vb[1]);
@@ -924,7 +1020,7 @@ tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
     c->hist_steady = 0;
     c->hist_nlam = 0;
     c->clean_rows = c->clean_keep = 0;  // the new accumulator is not known to be zero
-    zero_rows(c, tlim::kTgtFlag, tlim::kTgtFlag + 1);
+    zero_rows(c, tlim::kTgtFlag, tlim::kTgtNextStep + 1);
     if (c->precision == TLIM_FP32) {
         c->Lam32 = (float*)(base + L.Lam32);
         c->rC32 = (float*)(base + L.rC32);
@@ -947,6 +1043,7 @@ tlim_status tlim_set_phase(tlim_ctx* c, int32_t k, const tlim_phase* p) {
     if (!c) return TLIM_E_ARG;
     tlim_status pst = resolve(c);
     if (pst) return pst;
+    c->next_ready = false;  // the state or the laws change
     if (k < 0 || k > 1 || !p) return fail(c, TLIM_E_ARG, "phase index must be 0 or 1");
     if (!(p->gamma > 1.0) || !(p->cv > 0.0) || !(p->k0 >= 0.0) || !(p->T0 > 0.0) || !(p->mu >= 0.0) ||
         !std::isfinite(p->pinf) || !std::isfinite(p->npow))
@@ -960,6 +1057,7 @@ tlim_status tlim_set_field(tlim_ctx* c, int32_t f, const double* src) {
     if (!c) return TLIM_E_ARG;
     tlim_status pst = resolve(c);
     if (pst) return pst;
+    c->next_ready = false;  // the state or the laws change
     if (f < 0 || f >= TLIM_NFIELDS || !src) return fail(c, TLIM_E_ARG, "bad field index or NULL source");
     if (!c->ws) return fail(c, TLIM_E_STATE, "no workspace bound");
     if (c->t2_alias && (f == TLIM_T1 || f == TLIM_T2)) {
@@ -987,6 +1085,7 @@ tlim_status tlim_clear_field(tlim_ctx* c, int32_t f) {
     if (!c) return TLIM_E_ARG;
     tlim_status pst = resolve(c);
     if (pst) return pst;
+    c->next_ready = false;  // the state or the laws change
     if (f < TLIM_U || f >= TLIM_NFIELDS) return fail(c, TLIM_E_ARG, "field %d is not optional", f);
     c->fset[f] = false;
     return TLIM_OK;
@@ -996,6 +1095,7 @@ tlim_status tlim_spectral_bound(tlim_ctx* c, int32_t face_mean, double alpha_eps
     if (!c) return TLIM_E_ARG;
     tlim_status pst = resolve(c);
     if (pst) return pst;
+    c->next_ready = false;  // the relaxation below uses the spare arrays
     if (!lambda_out || face_mean < 0 || face_mean > 1 || alpha_eps < 0.0 || alpha_eps >= 0.5)
         return fail(c, TLIM_E_ARG, "bad arguments");
     tlim_status st = check_ready(c);
@@ -1045,7 +1145,7 @@ bool step2d_enqueue(tlim_ctx* c, const tlim_step_opts* o, PassResult* res) {
     const DevGrid g = dev_grid(c, kUnit);
     begin_pass_rows(c, o->passes);
     tlim::launch_fill(s, (double*)c->bar, 0.0, tlim::kStepMaxTiles / 2);
-    double* Tn = c->Tn == c->Tn_buf[0] ? c->Tn_buf[1] : c->Tn_buf[0];
+    double* Tn = free_tn(c);
     tlim::Step2D st{};
     st.alpha2 = c->field[TLIM_ALPHA2];
     st.T1 = c->field[TLIM_T1];
@@ -1067,6 +1167,7 @@ bool step2d_enqueue(tlim_ctx* c, const tlim_step_opts* o, PassResult* res) {
     st.pmax = kStepPmax;
     st.passes = o->passes;
     if (!tlim::launch_step2d(s, g, dev_phases(c), o->alpha_eps, o->dt, o->face_mean, st)) return false;
+    c->next_ready = false;
     c->Tn = Tn;
     c->g_heat = Tn;
     std::swap(c->field[TLIM_ALPHA2], c->a2n);
@@ -1150,8 +1251,31 @@ bool relax_step(tlim_ctx* c, const tlim_step_opts* o) {
     DevGrid g = dev_grid(c, kUnit);
     DevPhases ph = dev_phases(c);
     const bool B1 = c->phase[0].pinf != c->phase[1].pinf;
-    c->Tn = c->Tn == c->Tn_buf[0] ? c->Tn_buf[1] : c->Tn_buf[0];
     bool pass0_done = false;
+    if (c->next_ready && c->row0_moved && c->precision == TLIM_FP64 && fast_coeffs(c, g) && !B1 &&
+        o->alpha_eps == c->next_eps) {
+        // the previous step's last launch relaxed this state already: adopt
+        // its relaxed T, alpha2, 1/C and Lambda; its bound is in the first
+        // pass's row, the other pass rows are zero up to clean_rows
+        const int need = tlim::tgt_lam(o->passes);
+        if (c->clean_rows < need) zero_rows(c, tlim::tgt_lam(1), need);
+        c->clean_keep = std::max(c->clean_rows, need);
+        c->clean_rows = 0;
+        c->row0_moved = false;
+        c->Tn = c->next_tn;
+        double* old = c->field[TLIM_ALPHA2];
+        c->field[TLIM_ALPHA2] = c->next_a2;
+        if (c->a2n == c->next_a2) c->a2n = old;
+        else c->a2x = old;
+        std::swap(c->rC, c->rC_alt);
+        std::swap(c->Lam, c->Lam_alt);
+        c->g_heat = c->Tn;
+        c->next_ready = false;
+        c->t2_alias = true;
+        return true;
+    }
+    c->next_ready = false;
+    c->Tn = free_tn(c);
     if (fast_coeffs(c, g)) {
         begin_pass_rows(c, o->passes);
         const bool need_lam64 = c->precision == TLIM_FP64 || o->cycle_mode;
@@ -1291,15 +1415,29 @@ void enqueue_predicted(tlim_ctx* c, const tlim_step_opts* o, tlim_ctx::Pending& 
         const int P = c->hist_P[it];
         p.P_used[it] = P;
         PassSchedule ps = device_schedule(P, o->order, row(c, tlim::tgt_lam(it)));
-        tlim::NextCoef nc = next_coef(c, it, ph);
-        const bool want = it + 1 < o->passes && next_coef_ok(c, g);
+        const bool last = it + 1 == o->passes;
+        const bool want = !last && next_coef_ok(c, g);
+        const bool want_step = last && next_step_ok(c, o, g);
+        tlim::NextCoef nc = want_step ? next_step_coef(c, o, ph) : next_coef(c, it, ph);
+        bool done = false;
         run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->g_heat, c->Tnew, Tit, pass_slots(c, it), tm, sc, true,
-                     nullptr, want ? &nc : nullptr, &coef_ready);
-        if (coef_ready) adopt_next_coef(c);
+                     nullptr, want || want_step ? &nc : nullptr, &done);
+        coef_ready = false;
+        if (want_step) note_next_step(c, o, done);
+        else if (done) {
+            coef_ready = true;
+            adopt_next_coef(c);
+        }
         std::swap(c->field[TLIM_T1], c->Tnew);
     }
-    tlim::launch_collect(s, c->acc, c->res_host_dev, tlim::tgt_lam(0), tlim::tgt_lam(o->passes), 1);
+    const bool move = c->next_ready;
+    tlim::launch_collect(s, c->acc, c->res_host_dev, tlim::tgt_lam(0), tlim::tgt_lam(o->passes), 1,
+                         move ? tlim::kTgtNextStep : -1);
     c->clean_rows = c->clean_keep;
+    if (move) {
+        c->row0_moved = true;
+        c->spare_clean = true;
+    }
     (void)hipEventRecord(c->ev_pend[c->res_cur], s);
     p.o = *o;
     p.o.frozen_lambda = nullptr;
@@ -1387,6 +1525,8 @@ tlim_status redo_pending(tlim_ctx* c, const tlim_ctx::Pending& p) {
     c->g_heat = p.Tn;
     c->field[TLIM_ALPHA2] = p.alpha2;
     c->a2n = p.alpha2_other;
+    for (double* a : c->a2pool)  // a2x: the third alpha2 array
+        if (a != c->field[TLIM_ALPHA2] && a != c->a2n) c->a2x = a;
     c->predict_misses++;
     c->pipeline_redos++;
     Timer tm{c, false};
@@ -1474,6 +1614,7 @@ tlim_status tlim_finish(tlim_ctx* c) {
 namespace {
 
 tlim_status check_adjoint(tlim_ctx* c, const tlim_step_opts* o) {
+    c->next_ready = false;  // the adjoint runs its own steps on the fields
     tlim_status st = check_opts(c, o);
     if (st) return st;
     st = check_ready(c);

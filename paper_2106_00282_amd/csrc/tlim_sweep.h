@@ -41,6 +41,17 @@ struct NextCoef {
     float* Lam32;   // FP32 correction form: float conductivities and the
     float* q32;     // correction source of the next pass (not the ones read)
     DevPhases ph;
+    // FP64, last pass of a step: with m1 != NULL the next step's first
+    // coefficients instead -- the temperature relaxation of every cell from
+    // (alpha2, T^{n+1}, T^{n+1}, m1, m2) as the relaxation kernel does it,
+    // then Lambda, 1/C and the bound at the relaxed state; the relaxed T,
+    // alpha2 and 1/C go to Tn, a2, rC (none of them read by the pass).
+    const double* m1;
+    const double* m2;
+    double* Tn;
+    double* a2;
+    double* rC;
+    double eps;
 };
 
 int launch_sweeps64(hipStream_t s, const DevGrid& g, int face, const double* v, const double* rhs,

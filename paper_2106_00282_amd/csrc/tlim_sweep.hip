@@ -74,6 +74,14 @@ struct TBArgs {
     double* Lam_next;        // FP64
     float* Lam32_next;       // FP32 correction form: float conductivities and
     float* q32_next;         // the correction source -tau rC' D' g of the next pass
+    // FP64, m1 != NULL: the next step's relaxation and first coefficients
+    // instead of the next pass's (relaxed T, alpha2, 1/C to Tn/a2/rC_next)
+    const double* m1;
+    const double* m2;
+    double* Tn_next;
+    double* a2_next;
+    double* rC_next;
+    double eps;
     DevPhases ph;
     int nx, ny, perx, pery;
     R wx, wy, tau;
@@ -369,11 +377,22 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
             // K cells in from the edge): Lambda = sum_k alpha_k lambda_k(v),
             // and at the output cells (K+1 in) the bound 2 rC sum_f w_f
             // mean(Lambda_a, Lambda_b), faces in the order -x, +x, -y, +y.
-            double Ln[ROWS];
+            // With m1 the next step's instead: every cell relaxed from
+            // (alpha2, v, v, m1, m2) first, Lambda and 1/C at the relaxed state.
+            const bool next_step = a.m1 != nullptr;
+            double Ln[ROWS], Tr[ROWS], ar[ROWS], rr[ROWS];
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
                 const int64_t idx = (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + xi;
-                Ln[r] = phys::cell_conductivity(a.ph, v[r], a.alpha2[idx]);
+                const double a2v = a.alpha2[idx];
+                if (next_step) {
+                    const double m1 = a.m1[idx], m2 = a.m2[idx];
+                    phys::relax_cell(a.ph, a.eps, a2v, v[r], v[r], m1, m2, Tr[r], ar[r]);
+                    rr[r] = phys::inv_heat_capacity(a.ph, a.eps, Tr[r], ar[r], m1, m2);
+                    Ln[r] = phys::cell_conductivity(a.ph, Tr[r], ar[r]);
+                } else {
+                    Ln[r] = phys::cell_conductivity(a.ph, v[r], a2v);
+                }
             }
             // the seam buffer not used by the last stage: its reads all
             // precede that stage's barrier
@@ -400,8 +419,14 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                     if (fR) d += a.wx * fmean<double>(Ln[r], Lr, a.face);
                     if (fD) d += a.wy * fmean<double>(Ln[r], Ld, a.face);
                     if (fU) d += a.wy * fmean<double>(Ln[r], Lu, a.face);
-                    bound = fmax(bound, 2.0 * d * a.rC[o]);
+                    const double rc = next_step ? rr[r] : a.rC[o];
+                    bound = fmax(bound, 2.0 * d * rc);
                     a.Lam_next[o] = Ln[r];
+                    if (next_step) {
+                        a.Tn_next[o] = Tr[r];
+                        a.a2_next[o] = ar[r];
+                        a.rC_next[o] = rr[r];
+                    }
                 }
             }
 #pragma unroll
@@ -427,6 +452,12 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
         a.Lam32_next = nc->Lam32;
         a.q32_next = nc->q32;
         a.ph = nc->ph;
+        a.m1 = nc->m1;
+        a.m2 = nc->m2;
+        a.Tn_next = nc->Tn;
+        a.a2_next = nc->a2;
+        a.rC_next = nc->rC;
+        a.eps = nc->eps;
     }
     a.g64 = g64;
     a.rC64 = rC64;

@@ -194,3 +194,43 @@ def interface3d(n: int = 512, steps: int = 10, nmodes: int = 12):
 
 WORKLOADS = dict(heat1d=heat1d, levelset2d=levelset2d, bubbles3d=bubbles3d,
                  levelset2d_adjoint=levelset2d_adjoint, interface3d=interface3d)
+
+
+def random_case(seed: int):
+    """A small random two-phase workload for property-style parity runs:
+    1D, 2D or 3D, random sizes and boundary conditions, random phase
+    constants (equal p_inf = 0, conductivity exponents including non-integer
+    ones), a smooth random interface with some pure cells, phase
+    temperatures out of equilibrium, dt between 1x and 300x the explicit
+    limit and 1-3 Picard passes."""
+    rs = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_BASE, 7, seed])))
+    dim = int(rs.integers(1, 4))
+    if dim == 1:
+        n = (int(rs.integers(3, 300)), 1, 1)
+    elif dim == 2:
+        n = (int(rs.integers(2, 160)), int(rs.integers(2, 160)), 1)
+    else:
+        n = (int(rs.integers(2, 24)), int(rs.integers(2, 24)), int(rs.integers(2, 24)))
+    bc = tuple(int(rs.integers(0, 2)) if n[d] > 1 else PERIODIC for d in range(3))
+    npow = float(rs.choice([0.0, 1.0, 2.0, 2.5, 3.0, 1.7]))
+    phases = []
+    for k in range(2):
+        phases.append(dict(gamma=float(rs.uniform(1.2, 3.0)), pinf=0.0, cv=float(rs.uniform(0.3, 2.0)), q=0.0,
+                           k0=float(10 ** rs.uniform(-2, 0.5)), T0=float(rs.uniform(0.5, 2.0)), npow=npow,
+                           mu=0.0, rho=float(10 ** rs.uniform(-0.5, 1.0))))
+    shape = (n[2], n[1], n[0])
+    coords = np.meshgrid(*[_centres(n[d]) for d in (2, 1, 0)], indexing="ij")  # z, y, x
+    phi = np.zeros(shape)
+    for _ in range(4):
+        kvec = rs.integers(0, 4, size=3)
+        amp = rs.uniform(0.2, 1.0)
+        phase = rs.uniform(0, 2 * np.pi)
+        phi += amp * np.cos(2 * np.pi * (kvec[0] * coords[2] + kvec[1] * coords[1] + kvec[2] * coords[0]) + phase)
+    alpha1 = 0.5 * (1.0 - np.tanh(phi * rs.uniform(2.0, 8.0)))
+    alpha1[alpha1 < 0.02] = 0.0
+    alpha1[alpha1 > 0.98] = 1.0
+    T = np.exp(0.3 * rs.standard_normal(shape))
+    wl = _finish(f"random{seed}", n, bc, phases, alpha1, T, float(rs.uniform(1.0, 300.0)), 2,
+                 int(rs.integers(1, 4)))
+    wl["fields"]["T2"] = np.ascontiguousarray(wl["fields"]["T1"] * np.exp(0.1 * rs.standard_normal(shape)))
+    return wl

@@ -31,6 +31,24 @@ def _compare(fo, fg, names, tol):
 
 # ----------------------------------------------------------------- FP64 path
 
+@pytest.mark.parametrize("seed", list(range(16)))
+def test_random_small_cases_vs_oracle(seed):
+    """Property-style sweep: random 1D/2D/3D grids, boundary conditions,
+    phase constants and out-of-equilibrium states (workloads.random_case),
+    2 steps in FP64 against the oracle at 1e-12 (schedule frozen to the
+    oracle's), and every fourth case also in the FP32 form at 1e-5."""
+    from oracle import oracle as orc
+    wl = W.random_case(seed)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 2)
+    fg, rg, _ = run_gpu(wl, tau, 2, frozen=_frozen(ro))
+    print("case", seed, wl["n"], wl["bc"], "passes", wl["passes"], "dt x", round(wl["dt_factor"], 1))
+    _compare(fo, fg, FIELDS_T, 1e-12)
+    if seed % 4 == 0:
+        f32, _, _ = run_gpu(wl, tau, 2, precision="fp32", frozen=_frozen(ro))
+        _compare(fo, f32, ("T1", "T2"), 1e-5)
+
+
 def test_heat1d_fp64_single_step():
     """1024 cells, one step at 100x the explicit limit: P = 12, 23 sweeps."""
     from oracle import oracle as orc
@@ -384,6 +402,38 @@ def test_pipelined_step_then_report_and_phase_change(whole):
         st, _ = s.advance(o, report=report)
         assert st == 0
     assert rel_err(s.get_field("T1").cpu().numpy(), fo["T1"]) < 1e-12
+
+
+def test_next_step_start_is_redone_after_changes():
+    """The last launch of an FP64 step relaxes the next step's state and
+    builds its first coefficients ahead of time.  Changing a field, the
+    phases or alpha_eps between steps must discard that: each case is
+    checked against the oracle doing the same."""
+    import torch
+    from oracle import oracle as orc
+    from paper_2106_00282_amd.tlim import StepOpts
+    wl = W.levelset2d(160)
+    tau, _ = oracle_dt(orc, wl)
+    g = orc.make_grid(wl["n"], wl["h"], wl["bc"])
+    fo = {k: v.copy() for k, v in wl["fields"].items()}
+    s = make_solver(wl)
+    ph = [dict(p) for p in wl["phases"]]
+    for step in range(6):
+        eps = 1e-10
+        if step == 2:  # new temperatures
+            for k in ("T1", "T2"):
+                fo[k] = np.ascontiguousarray(fo["T1"] * 1.02)
+                s.set_field(k, torch.from_numpy(fo[k].copy()))
+        if step == 3:  # new conductivity
+            ph[0]["k0"] *= 1.5
+            s.set_phase(0, ph[0])
+        if step == 4:
+            eps = 1e-3
+        orc.step(g, ph, orc.StepOpts(tau=tau, passes=3, alpha_eps=eps), fo)
+        st, rep = s.advance(StepOpts(dt=tau, passes=3, alpha_eps=eps))
+        assert st == 0
+        assert rel_err(s.get_field("T1").cpu().numpy(), fo["T1"]) < 1e-12, step
+        assert rel_err(s.get_field("alpha2").cpu().numpy(), fo["alpha2"]) < 1e-12, step
 
 
 def test_paper_order_and_harmonic_faces():
