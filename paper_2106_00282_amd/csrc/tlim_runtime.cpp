@@ -56,7 +56,6 @@ struct tlim_ctx {
     float *Lam32, *rC32, *q32, *wb[2];
     float *Lam32_alt, *q32_alt;  // the next pass's float coefficients, built by the pass before
     float* wzero;                // all zero: the correction form's start w0 = T^n - g without sources
-    double* rC_alt;              // the next step's 1/C, built by the last launch of a step
     // The last launch of an FP64 step has relaxed the next step's state and
     // built its first coefficients (valid until the state or the phases
     // change); spare_clean: the row of that bound is zero.
@@ -141,7 +140,7 @@ tlim_status fail(tlim_ctx* c, tlim_status s, const char* fmt, ...) {
 // Layout of the workspace: byte offsets of every array (all 256-aligned).
 struct Layout {
     size_t field[TLIM_NFIELDS];
-    size_t Tn, Tn2, Tn3, Tnew, a2n, a2x, Lam, Lam2, rC, rC2, rhs, vb[2], acc, res;
+    size_t Tn, Tn2, Tn3, Tnew, a2n, a2x, Lam, Lam2, rC, rhs, vb[2], acc, res;
     size_t Lam32, rC32, q32, wb[2], Lam32b, q32b, wzero;
     size_t chat, bar;
     size_t total;
@@ -156,8 +155,8 @@ Layout layout_of(const int64_t n[3], int precision) {
         L.field[i] = off;
         off += d;
     }
-    size_t* dd[] = {&L.Tn, &L.Tn2, &L.Tn3, &L.Tnew, &L.a2n, &L.a2x, &L.Lam, &L.Lam2, &L.rC, &L.rC2, &L.rhs,
-                    &L.vb[0], &L.vb[1]};
+    size_t* dd[] = {&L.Tn, &L.Tn2, &L.Tn3, &L.Tnew, &L.a2n, &L.a2x, &L.Lam, &L.Lam2, &L.rC, &L.rhs, &L.vb[0],
+                    &L.vb[1]};
     for (size_t* p : dd) {
         *p = off;
         off += d;
@@ -720,6 +719,8 @@ double* free_alpha2(const tlim_ctx* c) {
 // the next step's relaxation kernel would compute from the same fields), as
 // long as nothing changes the state in between.
 bool next_step_ok(const tlim_ctx* c, const tlim_step_opts* o, const DevGrid& g) {
+    // FP32 contexts: the relaxation in the launch that also runs the double
+    // final stage costs about what the separate relaxation kernel does
     return c->precision == TLIM_FP64 && next_coef_ok(c, g) && !o->cycle_mode && o->picard_tol <= 0.0;
 }
 
@@ -730,12 +731,13 @@ tlim::NextCoef next_step_coef(tlim_ctx* c, const tlim_step_opts* o, const DevPha
     nc.lam = row(c, tlim::kTgtNextStep);
     nc.alpha2 = c->field[TLIM_ALPHA2];
     nc.Lam = c->Lam_alt;
+    nc.Lam32 = c->Lam32_alt;
+    nc.q32 = c->q32_alt;
     nc.ph = ph;
     nc.m1 = c->field[TLIM_M1];
     nc.m2 = c->field[TLIM_M2];
     nc.Tn = c->next_tn = free_tn(c);  // the next step's T^n array
     nc.a2 = c->next_a2 = free_alpha2(c);
-    nc.rC = c->rC_alt;
     nc.eps = o->alpha_eps;
     return nc;
 }
@@ -1003,7 +1005,6 @@ tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
     c->Lam = (double*)(base + L.Lam);
     c->Lam_alt = (double*)(base + L.Lam2);
     c->rC = (double*)(base + L.rC);
-    c->rC_alt = (double*)(base + L.rC2);
     c->next_ready = false;
     c->spare_clean = true;  // zeroed below
     c->row0_moved = false;
@@ -1252,10 +1253,9 @@ bool relax_step(tlim_ctx* c, const tlim_step_opts* o) {
     DevPhases ph = dev_phases(c);
     const bool B1 = c->phase[0].pinf != c->phase[1].pinf;
     bool pass0_done = false;
-    if (c->next_ready && c->row0_moved && c->precision == TLIM_FP64 && fast_coeffs(c, g) && !B1 &&
-        o->alpha_eps == c->next_eps) {
+    if (c->next_ready && c->row0_moved && fast_coeffs(c, g) && !B1 && o->alpha_eps == c->next_eps) {
         // the previous step's last launch relaxed this state already: adopt
-        // its relaxed T, alpha2, 1/C and Lambda; its bound is in the first
+        // its relaxed T, alpha2 and Lambda (1/C is unchanged); its bound is in the first
         // pass's row, the other pass rows are zero up to clean_rows
         const int need = tlim::tgt_lam(o->passes);
         if (c->clean_rows < need) zero_rows(c, tlim::tgt_lam(1), need);
@@ -1267,8 +1267,7 @@ bool relax_step(tlim_ctx* c, const tlim_step_opts* o) {
         c->field[TLIM_ALPHA2] = c->next_a2;
         if (c->a2n == c->next_a2) c->a2n = old;
         else c->a2x = old;
-        std::swap(c->rC, c->rC_alt);
-        std::swap(c->Lam, c->Lam_alt);
+        adopt_next_coef(c);  // Lambda (FP32: float Lambda and the correction source)
         c->g_heat = c->Tn;
         c->next_ready = false;
         c->t2_alias = true;

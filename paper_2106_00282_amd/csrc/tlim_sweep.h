@@ -44,13 +44,13 @@ struct NextCoef {
     // FP64, last pass of a step: with m1 != NULL the next step's first
     // coefficients instead -- the temperature relaxation of every cell from
     // (alpha2, T^{n+1}, T^{n+1}, m1, m2) as the relaxation kernel does it,
-    // then Lambda, 1/C and the bound at the relaxed state; the relaxed T,
-    // alpha2 and 1/C go to Tn, a2, rC (none of them read by the pass).
+    // then Lambda and the bound at the relaxed state; the relaxed T and
+    // alpha2 go to Tn and a2 (neither read by the pass).  1/C is the step's
+    // (equal p_inf: it depends on the partial densities only).
     const double* m1;
     const double* m2;
     double* Tn;
     double* a2;
-    double* rC;
     double eps;
 };
 

@@ -74,13 +74,13 @@ struct TBArgs {
     double* Lam_next;        // FP64
     float* Lam32_next;       // FP32 correction form: float conductivities and
     float* q32_next;         // the correction source -tau rC' D' g of the next pass
-    // FP64, m1 != NULL: the next step's relaxation and first coefficients
-    // instead of the next pass's (relaxed T, alpha2, 1/C to Tn/a2/rC_next)
+    // m1 != NULL: the next step's relaxation and first coefficients instead
+    // of the next pass's (relaxed T and alpha2 to Tn_next/a2_next; 1/C is
+    // unchanged with equal p_inf)
     const double* m1;
     const double* m2;
     double* Tn_next;
     double* a2_next;
-    double* rC_next;
     double eps;
     DevPhases ph;
     int nx, ny, perx, pery;
@@ -425,7 +425,6 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                     if (next_step) {
                         a.Tn_next[o] = Tr[r];
                         a.a2_next[o] = ar[r];
-                        a.rC_next[o] = rr[r];
                     }
                 }
             }
@@ -456,7 +455,6 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
         a.m2 = nc->m2;
         a.Tn_next = nc->Tn;
         a.a2_next = nc->a2;
-        a.rC_next = nc->rC;
         a.eps = nc->eps;
     }
     a.g64 = g64;
