@@ -215,7 +215,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
-    ap.add_argument("--no-whole", action="store_true", help="skip the one-launch-per-step FP64 variant")
+    ap.add_argument("--no-whole", action="store_true",
+                    help="never run a step as one cooperative launch (also not the first step): for profilers")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding "
@@ -234,9 +235,10 @@ def main():
     del probe
     log(f"workload levelset2d {args.n}^2, tau*lambda_G = {tau * lam:.1f}")
 
-    r64 = measure("fp64", wl, tau, args.steps, args.warmup)
+    whole = 2 if args.no_whole else 0
+    r64 = measure("fp64", wl, tau, args.steps, args.warmup, whole=whole)
     log("fp64", r64)
-    r32 = None if args.fp64_only else measure("fp32", wl, tau, args.steps, args.warmup)
+    r32 = None if args.fp64_only else measure("fp32", wl, tau, args.steps, args.warmup, whole=whole)
     if r32:
         log("fp32", r32)
     rw = None if args.fp64_only or args.no_whole else measure("fp64", wl, tau, args.steps, args.warmup, whole=1)
