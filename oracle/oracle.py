@@ -23,6 +23,7 @@ LIB = os.path.join(HERE, "libtlim_oracle.so")
 PERIODIC, ADIABATIC = 0, 1
 ORDER_INTERLEAVED, ORDER_PAPER, ORDER_ASCENDING = 0, 1, 2
 FACE_ARITH, FACE_HARMONIC = 0, 1
+LAW_POWER, LAW_SPITZER = 0, 1
 MAX_PASSES = 64
 
 
@@ -41,7 +42,8 @@ class Grid(C.Structure):
 
 
 class Phase(C.Structure):
-    _fields_ = [(k, C.c_double) for k in ("gamma", "pinf", "cv", "q", "k0", "T0", "npow", "mu")]
+    _fields_ = ([(k, C.c_double) for k in ("gamma", "pinf", "cv", "q", "k0", "T0", "npow", "mu")] +
+                [("law", C.c_int32)] + [(k, C.c_double) for k in ("sh_D", "sh_LD", "sh_dB")])
 
 
 class Opts(C.Structure):
@@ -74,7 +76,7 @@ def lib():
         L.orc_lim_P.argtypes = [C.c_double, C.c_double]
         L.orc_lim_params.argtypes = [C.c_int32, C.c_double, C.c_int32, _dp]
         L.orc_cycle_params.argtypes = [C.c_int32, C.c_double, _dp]
-        L.orc_cell_conductivity.argtypes = [C.POINTER(Grid), C.POINTER(Phase), _dp, _dp, _dp]
+        L.orc_cell_conductivity.argtypes = [C.POINTER(Grid), C.POINTER(Phase), _dp, _dp, _dp, _dp, _dp]
         L.orc_heat_capacity.argtypes = [C.POINTER(Grid), C.POINTER(Phase), C.c_double,
                                         _dp, _dp, _dp, _dp, _dp]
         L.orc_gershgorin.restype = C.c_double
@@ -142,6 +144,9 @@ def make_phases(ph):
         p = ph[k]
         for name in ("gamma", "pinf", "cv", "q", "k0", "T0", "npow", "mu"):
             setattr(arr[k], name, float(p.get(name, 0.0 if name not in ("gamma", "T0") else 1.0)))
+        arr[k].law = int(p.get("law", LAW_POWER))
+        for name in ("sh_D", "sh_LD", "sh_dB"):
+            setattr(arr[k], name, float(p.get(name, 0.0)))
     return arr
 
 
@@ -187,11 +192,13 @@ def cycle_params(s, lam):
     return b
 
 
-def cell_conductivity(g, ph, alpha2, T):
-    """Lambda = sum_k alpha_k lambda_k(T) (Sec. 3.4.2, eq. qk_dis)."""
+def cell_conductivity(g, ph, alpha2, T, m1=None, m2=None):
+    """Lambda = sum_k alpha_k lambda_k(rho, T) (Sec. 3.4.2, eq. qk_dis), rho = m1 + m2
+    (needed only by the Spitzer-Harm law of Sec. 4.4)."""
     N = _ncell(g)
     out = np.empty_like(T)
-    lib().orc_cell_conductivity(C.byref(g), make_phases(ph), _p(alpha2, N), _p(T, N), _p(out, N))
+    lib().orc_cell_conductivity(C.byref(g), make_phases(ph), _p(alpha2, N), _p(m1, N), _p(m2, N),
+                                _p(T, N), _p(out, N))
     return out
 
 

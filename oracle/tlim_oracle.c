@@ -99,11 +99,51 @@ static double face_partial(double La, double Lb, int32_t face_mean) {
     return 0.5;
 }
 
-static double conductivity(const orc_phase* p, double T) { return p->k0 * pow(T / p->T0, p->npow); }
+/* Coulomb logarithm of the Spitzer-Harm law (Sec. 4.4): ln(l_D / l_LD) when
+ * the Landau length is at least the de Broglie length, else ln(l_D / l_dB),
+ * and never below 1.  *landau says which length was taken, *floored whether
+ * the floor applied. */
+static double coulomb_log(const orc_phase* p, double T, double rho, int* landau, int* floored) {
+    double lD = p->sh_D * sqrt(T / rho);
+    double lLD = p->sh_LD / T;
+    double ldB = p->sh_dB / sqrt(T);
+    int lan = lLD >= ldB;
+    double L = lan ? log(lD / lLD) : log(lD / ldB);
+    if (landau) *landau = lan;
+    if (floored) *floored = !(L > 1.0);
+    return L > 1.0 ? L : 1.0;
+}
 
-static double conductivity_dT(const orc_phase* p, double T) {
-    if (p->npow == 0.0) return 0.0;
-    return p->k0 * p->npow * pow(T / p->T0, p->npow - 1.0) / p->T0;
+/* lambda_k(rho, T) / k0: (T/T0)^n, divided by the Coulomb logarithm under the
+ * Spitzer-Harm law. */
+static double conductivity_per_k0(const orc_phase* p, double T, double rho) {
+    double x = pow(T / p->T0, p->npow);
+    if (p->law == ORC_LAW_SPITZER) x /= coulomb_log(p, T, rho, NULL, NULL);
+    return x;
+}
+
+static double conductivity(const orc_phase* p, double T, double rho) {
+    return p->k0 * conductivity_per_k0(p, T, rho);
+}
+
+/* d lambda_k / dT at fixed rho.  Under the Spitzer-Harm law, away from the
+ * floor, d ln(ln Lambda)/d ln T = (1/2 + 1)/ln Lambda with the Landau length
+ * (l_D grows as T^(1/2), l_LD falls as 1/T) and (1/2 + 1/2)/ln Lambda with
+ * the de Broglie length (l_dB falls as T^(-1/2)). */
+static double conductivity_dT(const orc_phase* p, double T, double rho) {
+    double lam = p->k0 * pow(T / p->T0, p->npow);
+    double dlog = p->npow / T; /* d ln lambda / dT of the power law */
+    if (p->law == ORC_LAW_SPITZER) {
+        int landau, floored;
+        double L = coulomb_log(p, T, rho, &landau, &floored);
+        lam /= L;
+        if (!floored) dlog -= (landau ? 1.5 : 1.0) / (T * L);
+    }
+    return lam * dlog;
+}
+
+static double mixture_density(const double* m1, const double* m2, int64_t i) {
+    return m1 && m2 ? m1[i] + m2[i] : 1.0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -173,11 +213,11 @@ void orc_cycle_params(int32_t s, double lambda_max, double* b) {
 /* Coefficients (Sec. 3.4.2).                                                 */
 
 void orc_cell_conductivity(const orc_grid* g, const orc_phase ph[2], const double* alpha2,
-                           const double* T, double* Lam) {
+                           const double* m1, const double* m2, const double* T, double* Lam) {
     int64_t N = ncells(g);
     for (int64_t i = 0; i < N; ++i) {
-        double a2 = alpha2[i], a1 = 1.0 - a2;
-        Lam[i] = a1 * conductivity(&ph[0], T[i]) + a2 * conductivity(&ph[1], T[i]);
+        double a2 = alpha2[i], a1 = 1.0 - a2, rho = mixture_density(m1, m2, i);
+        Lam[i] = a1 * conductivity(&ph[0], T[i], rho) + a2 * conductivity(&ph[1], T[i], rho);
     }
 }
 
@@ -424,7 +464,7 @@ static int32_t heat_picard(const orc_grid* g, const orc_phase ph[2], const orc_o
     int32_t converged = 0, it;
     for (it = 0; it < o->passes; ++it) {
         /* Coefficients lagged at T^(it), alpha2^(it). */
-        orc_cell_conductivity(g, ph, alpha2, T, Lam);
+        orc_cell_conductivity(g, ph, alpha2, m1, m2, T, Lam);
         orc_heat_capacity(g, ph, o->alpha_eps, alpha2, m1, m2, T, C);
         for (int64_t i = 0; i < N; ++i) {
             double f = 0.0;
@@ -749,7 +789,7 @@ int32_t orc_heat_adjoint(const orc_grid* g, const orc_phase ph[2], const orc_opt
             double lam = lamsched[n * np + it];
             int32_t P = orc_lim_P(tau, lam), nst = 2 * P - 1;
             orc_lim_params(P, lam, o->order, b);
-            orc_cell_conductivity(g, ph, alpha2, Tpass + (int64_t)it * N, Lam);
+            orc_cell_conductivity(g, ph, alpha2, m1, m2, Tpass + (int64_t)it * N, Lam);
             orc_lim_pass(g, Lam, C, UNIT_SCALE, o->face_mean, tau, nst, b, Tn, Tn,
                          Tpass + (int64_t)(it + 1) * N, NULL);
         }
@@ -768,7 +808,7 @@ int32_t orc_heat_adjoint(const orc_grid* g, const orc_phase ph[2], const orc_opt
             double lam = lamsched[n * np + it];
             int32_t P = orc_lim_P(tau, lam), nst = 2 * P - 1;
             orc_lim_params(P, lam, o->order, b);
-            orc_cell_conductivity(g, ph, alpha2, Tpass + (int64_t)it * N, Lam);
+            orc_cell_conductivity(g, ph, alpha2, m1, m2, Tpass + (int64_t)it * N, Lam);
             orc_lim_pass(g, Lam, C, UNIT_SCALE, o->face_mean, tau, nst, b, Tn, Tn,
                          Tpass + (int64_t)(it + 1) * N, stages + it * stride);
         }
@@ -779,20 +819,21 @@ int32_t orc_heat_adjoint(const orc_grid* g, const orc_phase ph[2], const orc_opt
             int32_t P = orc_lim_P(tau, lam), nst = 2 * P - 1;
             orc_lim_params(P, lam, o->order, b);
             const double* Tit = Tpass + (int64_t)it * N;
-            orc_cell_conductivity(g, ph, alpha2, Tit, Lam);
+            orc_cell_conductivity(g, ph, alpha2, m1, m2, Tit, Lam);
             memset(dg, 0, sizeof(double) * (size_t)N);
             memset(gLam, 0, sizeof(double) * (size_t)N);
             lim_pass_reverse(g, Lam, C, UNIT_SCALE, o->face_mean, tau, nst, b, stages + it * stride,
                              mu, dg, gLam);
             /* The pass reads T^n twice: as g and as v^(0). */
             for (int64_t i = 0; i < N; ++i) acc[i] += dg[i] + mu[i];
-            /* Lambda_i = sum_k alpha_k k0_k (T_i/T0_k)^n_k, evaluated at T^(it). */
+            /* Lambda_i = sum_k alpha_k lambda_k(rho_i, T_i), evaluated at T^(it);
+             * lambda_k is proportional to k0_k. */
             for (int64_t i = 0; i < N; ++i) {
-                double a2 = alpha2[i], a1 = 1.0 - a2;
-                dL_dk0[0] += gLam[i] * a1 * pow(Tit[i] / ph[0].T0, ph[0].npow);
-                dL_dk0[1] += gLam[i] * a2 * pow(Tit[i] / ph[1].T0, ph[1].npow);
-                mu[i] = gLam[i] * (a1 * conductivity_dT(&ph[0], Tit[i]) +
-                                   a2 * conductivity_dT(&ph[1], Tit[i]));
+                double a2 = alpha2[i], a1 = 1.0 - a2, rho = m1[i] + m2[i];
+                dL_dk0[0] += gLam[i] * a1 * conductivity_per_k0(&ph[0], Tit[i], rho);
+                dL_dk0[1] += gLam[i] * a2 * conductivity_per_k0(&ph[1], Tit[i], rho);
+                mu[i] = gLam[i] * (a1 * conductivity_dT(&ph[0], Tit[i], rho) +
+                                   a2 * conductivity_dT(&ph[1], Tit[i], rho));
             }
             /* T^(1) = T^n, so the first pass's coefficient gradient is T^n's;
              * otherwise mu is the adjoint of the previous pass's output. */

@@ -55,12 +55,21 @@ typedef struct {
     int32_t bc[3];
 } orc_grid;
 
-/* One phase: stiffened-gas EOS (gamma, p_inf, C_v, q), conductivity law
- * lambda(T) = k0 * (T/T0)^npow, dynamic viscosity mu. */
+/* One phase: stiffened-gas EOS (gamma, p_inf, C_v, q), conductivity law,
+ * dynamic viscosity mu.
+ * law ORC_LAW_POWER:   lambda(T) = k0 * (T/T0)^npow.
+ * law ORC_LAW_SPITZER: lambda(rho, T) = k0 * (T/T0)^npow / ln Lambda_ei(rho, T),
+ *   the Spitzer-Harm form of Sec. 4.4 (npow = 5/2 there) with its Coulomb
+ *   logarithm, from the Debye, Landau and de Broglie lengths
+ *   l_D = sh_D sqrt(T/rho), l_LD = sh_LD / T, l_dB = sh_dB / sqrt(T);
+ *   rho is the cell's mixture density m1 + m2. */
+enum { ORC_LAW_POWER = 0, ORC_LAW_SPITZER = 1 };
 typedef struct {
     double gamma, pinf, cv, q;
     double k0, T0, npow;
     double mu;
+    int32_t law;
+    double sh_D, sh_LD, sh_dB;
 } orc_phase;
 
 /* Options of one parabolic step. */
@@ -102,9 +111,10 @@ void orc_lim_params(int32_t P, double lambda_max, int32_t order, double* b);
 /* Stage parameters of one Chebyshev-Richardson cycle of s stages. */
 void orc_cycle_params(int32_t s, double lambda_max, double* b);
 
-/* Cell conductivity Lambda_i = sum_k alpha_k lambda_k(T_i). */
-void orc_cell_conductivity(const orc_grid* g, const orc_phase ph[2],
-                           const double* alpha2, const double* T, double* Lam);
+/* Cell conductivity Lambda_i = sum_k alpha_k lambda_k(rho_i, T_i), rho_i = m1 + m2
+ * (m1, m2 may be NULL when no phase uses the Spitzer-Harm law). */
+void orc_cell_conductivity(const orc_grid* g, const orc_phase ph[2], const double* alpha2,
+                           const double* m1, const double* m2, const double* T, double* Lam);
 /* Effective heat capacity of the equilibrium heat step (per unit volume). */
 void orc_heat_capacity(const orc_grid* g, const orc_phase ph[2], double eps,
                        const double* alpha2, const double* m1, const double* m2,

@@ -32,6 +32,11 @@ Workloads (sizes are parameters; the defaults are the full sizes):
   interface3d  512^3, x adiabatic, y and z periodic; planar interface at
              x = 1/2 perturbed by 12 cosine modes of amplitude 5 cells;
              k0 = (1, 0.01); T = 1 + alpha_1; 10 steps.
+  levelset2d_spitzer  the level-set fields with the Spitzer-Harm law for
+             both phases: n = 5/2, Coulomb-log lengths l_D = e^2.5 sqrt(T/rho),
+             l_LD = 1/T, l_dB = 1/sqrt(T), so that the Landau branch holds
+             below T = 1, the de Broglie branch above it, and the floor
+             ln Lambda = 1 in the cold dense cells; 10 steps at 200x.
 """
 from __future__ import annotations
 
@@ -39,6 +44,7 @@ import numpy as np
 
 SEED_BASE = 210600282
 PERIODIC, ADIABATIC = 0, 1
+LAW_POWER, LAW_SPITZER = 0, 1
 
 
 def base_phases(k0=(1.0, 0.05), npow=2.0, mu=(0.0, 0.0)):
@@ -47,6 +53,19 @@ def base_phases(k0=(1.0, 0.05), npow=2.0, mu=(0.0, 0.0)):
     gamma = (3.0, 1.4)
     return [dict(gamma=gamma[k], pinf=0.0, cv=cv[k], q=0.0, k0=k0[k], T0=1.0, npow=npow,
                  mu=mu[k], rho=rho[k]) for k in range(2)]
+
+
+def spitzer_phases(phases, sh_D=float(np.exp(2.5)), sh_LD=1.0, sh_dB=1.0, npow=2.5):
+    """Copies of ``phases`` switched to the Spitzer-Harm law with the given
+    Coulomb-log length constants (l_D = sh_D sqrt(T/rho), l_LD = sh_LD/T,
+    l_dB = sh_dB/sqrt(T))."""
+    out = []
+    for p in phases:
+        q = dict(p)
+        q.update(law=LAW_SPITZER, npow=float(npow), sh_D=float(sh_D), sh_LD=float(sh_LD),
+                 sh_dB=float(sh_dB))
+        out.append(q)
+    return out
 
 
 def _streams(config_id: int, n: int):
@@ -120,6 +139,14 @@ def levelset2d(n: int = 1024, steps: int = 10):
     phases = base_phases(k0=(1.0, 0.05), npow=2.0)
     alpha1, T = _levelset_fields(n, 2)
     return _finish("levelset2d", (n, n, 1), (PERIODIC,) * 3, phases, alpha1, T, 200.0, steps, 3)
+
+
+def levelset2d_spitzer(n: int = 1024, steps: int = 10):
+    """The level-set workload with Spitzer-Harm conductivities (both phases)."""
+    phases = spitzer_phases(base_phases(k0=(1.0, 0.05)))
+    alpha1, T = _levelset_fields(n, 2)
+    return _finish("levelset2d_spitzer", (n, n, 1), (PERIODIC,) * 3, phases, alpha1, T, 200.0,
+                   steps, 3)
 
 
 def levelset2d_adjoint(n: int = 2048, steps: int = 20):
@@ -200,7 +227,7 @@ def random_case(seed: int):
     """A small random two-phase workload for property-style parity runs:
     1D, 2D or 3D, random sizes and boundary conditions, random phase
     constants (equal p_inf = 0, conductivity exponents including non-integer
-    ones), a smooth random interface with some pure cells, phase
+    ones, about a third with the Spitzer-Harm Coulomb logarithm), a smooth random interface with some pure cells, phase
     temperatures out of equilibrium, dt between 1x and 300x the explicit
     limit and 1-3 Picard passes."""
     rs = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_BASE, 7, seed])))
@@ -233,4 +260,9 @@ def random_case(seed: int):
     wl = _finish(f"random{seed}", n, bc, phases, alpha1, T, float(rs.uniform(1.0, 300.0)), 2,
                  int(rs.integers(1, 4)))
     wl["fields"]["T2"] = np.ascontiguousarray(wl["fields"]["T1"] * np.exp(0.1 * rs.standard_normal(shape)))
+    # drawn last, so that the fields above do not depend on it
+    if rs.uniform() < 0.35:
+        wl["phases"] = spitzer_phases(phases, sh_D=float(np.exp(rs.uniform(1.0, 3.5))),
+                                      sh_LD=float(np.exp(rs.uniform(-0.5, 0.5))),
+                                      sh_dB=float(np.exp(rs.uniform(-0.5, 0.5))), npow=npow)
     return wl

@@ -834,6 +834,166 @@ def test_P10_adjoint_forward_model_matches_step(orc):
     assert np.abs(ff["T1"] - TN).max() < 1e-13 * np.abs(TN).max()
 
 
+# ------------------------------------------------ Spitzer-Harm conductivity
+
+def _sh_phase(sh_D, sh_LD, sh_dB, npow=0.0, k0=1.0):
+    return dict(gamma=2.0, pinf=0.0, cv=1.0, q=0.0, k0=k0, T0=1.0, npow=npow, mu=0.0,
+                law=W.LAW_SPITZER, sh_D=sh_D, sh_LD=sh_LD, sh_dB=sh_dB)
+
+
+def _sh_lambda(orc, ph, T, rho):
+    """Cell conductivity of phase 1 alone at the given (T, rho) values."""
+    T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64).reshape(1, 1, -1)
+    rho = np.broadcast_to(np.asarray(rho, dtype=np.float64), T.shape).copy()
+    g = orc.make_grid((T.size, 1, 1))
+    a2 = np.zeros_like(T)
+    return orc.cell_conductivity(g, [ph, ph], a2, T, rho, np.zeros_like(T)).ravel()
+
+
+@pytest.mark.parametrize("case", [
+    # (sh_D, sh_LD, sh_dB, T, rho, ln Lambda) worked by hand from the lengths
+    # l_D = sh_D (T/rho)^(1/2), l_LD = sh_LD/T, l_dB = sh_dB T^(-1/2)
+    (np.e ** 5, np.e, 0.0, 1.0, 1.0, 4.0),          # Landau: ln(e^5 / e)
+    (np.e ** 5, 0.0, np.e ** 2, 1.0, 1.0, 3.0),     # de Broglie: ln(e^5 / e^2)
+    (1.0, 0.0, 1.0, np.e ** 2, 1.0, 2.0),           # l_D = e, l_dB = 1/e
+    (1.0, 1.0, 0.0, 1.0, np.e ** -4, 2.0),          # l_D = e^2 from the density
+    (1.0, 1.0, 1.0, 1.0, 1.0, 1.0),                 # ln 1 = 0, floored at 1
+    (np.e ** 3, 2.0, 1.0, 4.0, 1.0, 3.0 + np.log(4.0)),  # l_LD = l_dB = 1/2: both give ln(2e^3 / (1/2))
+])
+def test_spitzer_coulomb_log_values(orc, case):
+    """Sec. 4.4: lambda = k0 (T/T0)^n / ln Lambda_ei; with n = 0 the oracle's
+    conductivity is k0 over the Coulomb logarithm worked out by hand."""
+    sh_D, sh_LD, sh_dB, T, rho, lnL = case
+    lam = _sh_lambda(orc, _sh_phase(sh_D, sh_LD, sh_dB, npow=0.0, k0=3.0), T, rho)
+    assert lam[0] == pytest.approx(3.0 / lnL, rel=1e-14)
+
+
+@pytest.mark.parametrize("T,branch", [(0.45, "landau"), (0.7, "landau"), (2.0, "debroglie"),
+                                      (9.0, "debroglie"), (0.02, "floor")])
+def test_spitzer_log_derivatives(orc, T, branch):
+    """The exponents of the lengths fix how lambda scales away from the
+    branch point and the floor: with L = ln Lambda,
+    d ln lambda / d ln T = n - 3/(2L) (Landau: l_D ~ T^(1/2), l_LD ~ 1/T),
+    n - 1/L (de Broglie: l_dB ~ T^(-1/2)), n on the floor, and
+    d ln lambda / d ln rho = 1/(2L) off the floor (l_D ~ rho^(-1/2)).
+    Checked by central differences in log space."""
+    n = 2.5
+    ph = _sh_phase(np.e ** 2.5, 1.0, 1.0, npow=n)  # branch point at T = (sh_LD/sh_dB)^2 = 1
+    rho = 1.0
+    hl = 1e-5
+    lam0 = _sh_lambda(orc, ph, T, rho)[0]
+    lnL = float(ph["k0"] * T ** n / lam0)
+    lp, lm = _sh_lambda(orc, ph, [T * np.exp(hl), T * np.exp(-hl)], rho)
+    dT = (np.log(lp) - np.log(lm)) / (2 * hl)
+    rp, rm = _sh_lambda(orc, ph, [T, T], [rho * np.exp(hl), rho * np.exp(-hl)])
+    dR = (np.log(rp) - np.log(rm)) / (2 * hl)
+    if branch == "floor":
+        assert lnL == 1.0
+        assert dT == pytest.approx(n, abs=1e-8) and dR == pytest.approx(0.0, abs=1e-8)
+    else:
+        assert lnL > 1.0
+        want = n - (1.5 if branch == "landau" else 1.0) / lnL
+        assert dT == pytest.approx(want, abs=1e-8)
+        assert dR == pytest.approx(0.5 / lnL, abs=1e-8)
+
+
+def test_spitzer_continuous_at_branch_point(orc):
+    """l_LD = l_dB at T = (sh_LD/sh_dB)^2: both branches give the same value."""
+    ph = _sh_phase(np.e ** 2.5, 2.0, 1.0, npow=2.5)
+    lo, hi = _sh_lambda(orc, ph, [4.0 * (1 - 1e-12), 4.0 * (1 + 1e-12)], 1.0)
+    assert hi == pytest.approx(lo, rel=1e-10)
+
+
+def test_spitzer_floor_reduces_to_power_law(orc):
+    """Where ln Lambda <= 1 in every cell the law is the power law: a whole
+    step (relaxation, 3 Picard passes) is bitwise the power-law step."""
+    wl = W.levelset2d(24, steps=1)
+    g = orc.make_grid(wl["n"], wl["h"], wl["bc"])
+    f0 = wl["fields"]
+    ph = [dict(p) for p in wl["phases"]]
+    for p in ph:
+        p["npow"] = 2.5
+    sh = W.spitzer_phases(ph, sh_D=1e-3, sh_LD=1.0, sh_dB=1.0, npow=2.5)
+    tau = 0.01
+    out = []
+    for phx in (ph, sh):
+        f = {k: v.copy() for k, v in f0.items()}
+        st, rep = orc.step(g, phx, orc.StepOpts(tau=tau, passes=3), f)
+        assert st == 0
+        out.append(f["T1"])
+    assert np.array_equal(out[0], out[1])
+
+
+def test_spitzer_step_invariants(orc):
+    """Spitzer-Harm law on the level-set fields: every pass conserves
+    sum C T h^d (P5), the Picard change shrinks from pass to pass (P9), and
+    T stays within the initial range (P6, reported for the LIM)."""
+    wl = W.levelset2d_spitzer(32, steps=1)
+    ph = wl["phases"]
+    g = orc.make_grid(wl["n"], wl["h"], wl["bc"])
+    f = {k: v.copy() for k, v in wl["fields"].items()}
+    Lam = orc.cell_conductivity(g, ph, f["alpha2"], f["T1"], f["m1"], f["m2"])
+    Cap = orc.heat_capacity(g, ph, f["alpha2"], f["m1"], f["m2"], f["T1"])
+    lam = orc.gershgorin(g, Lam, Cap)
+    tau = 200.0 * 2 / lam
+    # the first pass's coefficients reach both branches and the floor
+    T = f["T1"]
+    rho = f["m1"] + f["m2"]
+    lD = ph[0]["sh_D"] * np.sqrt(T / rho)
+    L = np.log(lD / np.maximum(ph[0]["sh_LD"] / T, ph[0]["sh_dB"] / np.sqrt(T)))
+    assert (L < 1).any() and ((L > 1) & (T < 1)).any() and ((L > 1) & (T > 1)).any()
+    lo, hi = f["T1"].min(), f["T1"].max()
+    st, rep = orc.step(g, ph, orc.StepOpts(tau=tau, passes=3), f)
+    assert st == 0
+    assert abs(rep["energy_after"] - rep["energy_before"]) <= 1e-14 * abs(rep["energy_before"])
+    assert rep["err"][1] < rep["err"][0] and rep["err"][2] < rep["err"][1]
+    assert lo - 1e-12 <= f["T1"].min() and f["T1"].max() <= hi + 1e-12
+
+
+def test_spitzer_adjoint_vs_central_fd(orc):
+    """The oracle adjoint through the Spitzer-Harm law (both branches and the
+    floor present) against central differences of its forward model."""
+    steps = 2
+    wl, ph, g, f, opts, sched = _adjoint_case(orc, npow=2.5, steps=steps)
+    ph = W.spitzer_phases(ph, sh_D=float(np.exp(2.5)), sh_LD=1.0, sh_dB=1.0, npow=2.5)
+    rho = f["m1"] + f["m2"]
+    T = f["T1"]
+    L = np.log(ph[0]["sh_D"] * np.sqrt(T / rho) / np.maximum(1 / T, 1 / np.sqrt(T)))
+    assert (L < 1).any() and ((L > 1) & (T < 1)).any() and ((L > 1) & (T > 1)).any()
+    rng = np.random.default_rng(11)
+    Tstar = f["T1"] * (1 + 0.05 * rng.standard_normal(f["T1"].shape))
+
+    def loss(T0, phx):
+        _, _, TN = orc.heat_adjoint(g, phx, opts, steps, sched, f["alpha2"], f["m1"], f["m2"], T0,
+                                    np.zeros_like(T0))
+        r = TN - Tstar
+        return 0.5 * np.sum(r * r)
+
+    _, _, TN = orc.heat_adjoint(g, ph, opts, steps, sched, f["alpha2"], f["m1"], f["m2"], f["T1"],
+                                np.zeros_like(f["T1"]))
+    dT0, dk0, _ = orc.heat_adjoint(g, ph, opts, steps, sched, f["alpha2"], f["m1"], f["m2"], f["T1"],
+                                   TN - Tstar)
+    # cells of each kind: floor, Landau, de Broglie
+    kinds = [np.flatnonzero((L < 0.9).ravel()), np.flatnonzero(((L > 1.1) & (T < 0.95)).ravel()),
+             np.flatnonzero(((L > 1.1) & (T > 1.05)).ravel())]
+    cells = np.concatenate([rng.choice(k, size=min(3, k.size), replace=False) for k in kinds])
+    for c in cells:
+        hstep = 1e-4 * abs(f["T1"].ravel()[c])
+        Tp, Tm = f["T1"].copy(), f["T1"].copy()
+        Tp.ravel()[c] += hstep
+        Tm.ravel()[c] -= hstep
+        fd = (loss(Tp, ph) - loss(Tm, ph)) / (2 * hstep)
+        assert dT0.ravel()[c] == pytest.approx(fd, rel=1e-6, abs=1e-9 * np.abs(dT0).max())
+    for k in range(2):
+        hstep = 1e-4 * ph[k]["k0"]
+        pp = [dict(p) for p in ph]
+        pm = [dict(p) for p in ph]
+        pp[k]["k0"] += hstep
+        pm[k]["k0"] -= hstep
+        fd = (loss(f["T1"], pp) - loss(f["T1"], pm)) / (2 * hstep)
+        assert dk0[k] == pytest.approx(fd, rel=1e-6)
+
+
 # ------------------------------------------------------------ P11 convergence
 
 def test_P11_first_order_consistency(orc):
