@@ -21,6 +21,8 @@ Reported (one JSON line):
              FETCH_SIZE/WRITE_SIZE summary (null once the kernel changed)
   adjoint    adjoint / forward time on the 2048^2, 20-step adjoint workload
   bubbles3d  the 256^3 FP32 workload with the viscous part
+  spitzer    FP64 on the same level-set fields with the Spitzer-Harm
+             conductivity law (T^(5/2) over the Coulomb logarithm)
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload
 """
 from __future__ import annotations
@@ -215,6 +217,10 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-spitzer", action="store_true")
+    ap.add_argument("--workload", choices=("levelset2d", "levelset2d_spitzer"), default="levelset2d",
+                    help="main workload (levelset2d_spitzer: the same fields with the Spitzer-Harm law, "
+                         "for profiling that path)")
     ap.add_argument("--no-whole", action="store_true",
                     help="never run a step as one cooperative launch (also not the first step): for profilers")
     args = ap.parse_args()
@@ -227,13 +233,13 @@ def main():
     from paper_2106_00282_amd import workloads as W
     from paper_2106_00282_amd.tlim import Solver
 
-    wl = W.levelset2d(args.n, steps=args.steps)
+    wl = getattr(W, args.workload)(args.n, steps=args.steps)
     probe = Solver(wl["n"], wl["h"], wl["bc"])
     probe.set_workload(wl)
     lam = probe.spectral_bound()
     tau = wl["dt_factor"] * 2.0 / lam
     del probe
-    log(f"workload levelset2d {args.n}^2, tau*lambda_G = {tau * lam:.1f}")
+    log(f"workload {args.workload} {args.n}^2, tau*lambda_G = {tau * lam:.1f}")
 
     whole = 2 if args.no_whole else 0
     r64 = measure("fp64", wl, tau, args.steps, args.warmup, whole=whole)
@@ -250,11 +256,26 @@ def main():
     b3 = None if args.no_3d or args.fp64_only else bubbles3d_rate()
     if b3:
         log("bubbles3d", b3)
+    sh = None
+    if not (args.no_spitzer or args.fp64_only or args.workload != "levelset2d"):
+        wls = W.levelset2d_spitzer(args.n, steps=args.steps)
+        probe = Solver(wls["n"], wls["h"], wls["bc"])
+        probe.set_workload(wls)
+        lam_s = probe.spectral_bound()
+        del probe
+        tau_s = wls["dt_factor"] * 2.0 / lam_s
+        rs = measure("fp64", wls, tau_s, args.steps, args.warmup, whole=whole)
+        log("spitzer fp64", rs)
+        sh = {"workload": f"levelset2d_spitzer {args.n}^2, Spitzer-Harm law (n = 5/2, Coulomb logarithm), "
+                          f"FP64, 200x, 3 passes, {args.steps} steps",
+              "value": round(rs["gupd"], 4), "unit": "Gcell-updates/s",
+              "ms_per_step": round(rs["wall_s"] / args.steps * 1e3, 4), "sweeps": rs["sweeps"],
+              "tau_lambda_G": round(tau_s * lam_s, 1)}
 
     avg_launch_ms = r64["sweep_ms"] / max(r64["launches"], 1)
     bytes_per_launch = r64["N"] * BYTES_PER_UPDATE["fp64"] * (r64["sweeps"] / max(r64["launches"], 1))
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if avg_launch_ms > 0 else None
-    traffic = pmc_traffic() if args.n == 1024 else None
+    traffic = pmc_traffic() if args.n == 1024 and args.workload == "levelset2d" else None
     dram_gbs = traffic / (avg_launch_ms * 1e-3) / 1e9 if traffic and avg_launch_ms > 0 else None
     out = {
         "metric": "Gcell-updates/s per Chebyshev sweep (FP64 vs FP32), HBM GB/s, adjoint/fwd",
@@ -270,7 +291,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"levelset2d {args.n}x{args.n} periodic, two phases, k=k0 (T/T0)^2, "
-                               f"dt=200x explicit limit, 3 Picard passes, {args.steps} steps",
+                               f"dt=200x explicit limit, 3 Picard passes, {args.steps} steps"
+                   if args.workload == "levelset2d" else
+                   f"levelset2d_spitzer {args.n}x{args.n} periodic, two phases, Spitzer-Harm law, "
+                   f"dt=200x explicit limit, 3 Picard passes, {args.steps} steps",
                    "cells": r64["N"], "sweeps_per_run": r64["sweeps"],
                    "predicted_steps": r64["predicted_steps"], "mispredicted_steps": r64["mispredicted_steps"]},
         "sweep_kernel_gupd": round(r64["N"] * r64["sweeps"] / (r64["sweep_ms"] * 1e-3) / 1e9, 2)
@@ -299,6 +323,8 @@ def main():
         out["adjoint"] = adj
     if b3:
         out["bubbles3d"] = b3
+    if sh:
+        out["spitzer"] = sh
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, tau)
     print(json.dumps(out), flush=True)

@@ -90,13 +90,32 @@ typedef struct {
     int32_t bc[3];
 } tlim_grid;
 
+/* Conductivity laws of a phase. */
+enum {
+    TLIM_LAW_POWER = 0,   /* lambda(T) = k0 (T/T0)^npow (Sec. 3.4.2 allows lambda = lambda(T)) */
+    TLIM_LAW_SPITZER = 1  /* lambda(rho, T) = k0 (T/T0)^npow / ln Lambda_ei(rho, T): the
+                             Spitzer-Harm form of Sec. 4.4 (npow = 5/2 there; the prefactor,
+                             charge state and atomic number go into k0) */
+};
+
 /* One phase: stiffened-gas EOS (eqs. eos_stiffened, eos_stiffened2:
- * gamma, p_inf, C_v, q), conductivity lambda(T) = k0 (T/T0)^npow (Sec.
- * 3.4.2 allows lambda = lambda(T)), dynamic viscosity mu (Sec. 3.2). */
+ * gamma, p_inf, C_v, q), conductivity law, dynamic viscosity mu (Sec. 3.2).
+ *
+ * law = TLIM_LAW_SPITZER takes the Coulomb logarithm of Sec. 4.4,
+ *   ln Lambda_ei = max(1, ln(l_D / l_LD))  if l_LD >= l_dB,
+ *                  max(1, ln(l_D / l_dB))  otherwise,
+ * with the Debye, Landau and de Broglie lengths written as
+ *   l_D = sh_D sqrt(T / rho),  l_LD = sh_LD / T,  l_dB = sh_dB / sqrt(T),
+ * rho the cell's mixture density m1 + m2.  The constants sh_* carry the
+ * physical constants, charge state and atomic number in the caller's
+ * units (sh_D > 0, sh_LD >= 0, sh_dB >= 0, not both zero).  They are
+ * ignored under TLIM_LAW_POWER. */
 typedef struct {
     double gamma, pinf, cv, q;
     double k0, T0, npow;
     double mu;
+    int32_t law;                /* TLIM_LAW_* */
+    double sh_D, sh_LD, sh_dB;  /* Spitzer-Harm length constants */
 } tlim_phase;
 
 /* Options of one parabolic step. */
@@ -171,7 +190,8 @@ tlim_status tlim_workspace_bytes(const tlim_ctx* ctx, size_t* bytes);
 tlim_status tlim_bind_workspace(tlim_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /* Set phase k (0 or 1).  Errors: TLIM_E_ARG for k out of range, gamma <= 1,
- * cv <= 0, k0 < 0, T0 <= 0 or mu < 0. */
+ * cv <= 0, k0 < 0, T0 <= 0, mu < 0, an unknown law, or Spitzer-Harm
+ * constants outside the ranges above. */
 tlim_status tlim_set_phase(tlim_ctx* ctx, int32_t k, const tlim_phase* phase);
 
 /* Copy a field from caller device memory (dense float64, see conventions)

@@ -57,6 +57,10 @@ struct AdjArgs {
     AdjCell cell;  // cell.acc != NULL: finish the pass (this launch reaches v^(0))
 };
 
+// kSH: some phase follows the Spitzer-Harm law (the pass epilogue's
+// conductivity derivatives take logarithms; the power-law kernel is kept
+// free of them).
+template <bool kSH>
 __global__ void __launch_bounds__(64 * WAVES, 2) k_tb2d_adj(AdjArgs a) {
     __shared__ double sh_lo[2][WAVES][64];
     __shared__ double sh_hi[2][WAVES][64];
@@ -167,17 +171,26 @@ __global__ void __launch_bounds__(64 * WAVES, 2) k_tb2d_adj(AdjArgs a) {
                 const int64_t o = (int64_t)y * a.nx + xg;
                 if (cl.acc) {
                     const DevPhases& ph = cl.ph;
-                    const double t = cl.Tit[o], a2 = cl.alpha2[o], a1 = 1.0 - a2, gl = gla[r];
+                    const double t = cl.Tit[o], a2 = cl.alpha2[o], gl = gla[r];
                     const double acc0 = cl.init ? 0.0 : cl.acc[o];
                     double acc_a = acc0 + (dga[r] + psi[r]) / a.rC[o];
-                    const double x0 = t * ph.invT0[0], x1 = t * ph.invT0[1];
-                    s0 += gl * a1 * powlaw(x0, ph.npow[0]);
-                    s1 += gl * a2 * powlaw(x1, ph.npow[1]);
-                    double dL = 0.0;
-                    if (ph.npow[0] != 0.0)
-                        dL += a1 * ph.k0[0] * ph.npow[0] * powlaw(x0, ph.npow[0] - 1.0) * ph.invT0[0];
-                    if (ph.npow[1] != 0.0)
-                        dL += a2 * ph.k0[1] * ph.npow[1] * powlaw(x1, ph.npow[1] - 1.0) * ph.invT0[1];
+                    double dL;
+                    if constexpr (kSH) {
+                        double dk[2];
+                        phys::cell_conductivity_grad(ph, t, a2, cl.m1[o] + cl.m2[o], dk, dL);
+                        s0 += gl * dk[0];
+                        s1 += gl * dk[1];
+                    } else {
+                        const double a1 = 1.0 - a2;
+                        const double x0 = t * ph.invT0[0], x1 = t * ph.invT0[1];
+                        s0 += gl * a1 * powlaw(x0, ph.npow[0]);
+                        s1 += gl * a2 * powlaw(x1, ph.npow[1]);
+                        dL = 0.0;
+                        if (ph.npow[0] != 0.0)
+                            dL += a1 * ph.k0[0] * ph.npow[0] * powlaw(x0, ph.npow[0] - 1.0) * ph.invT0[0];
+                        if (ph.npow[1] != 0.0)
+                            dL += a2 * ph.k0[1] * ph.npow[1] * powlaw(x1, ph.npow[1] - 1.0) * ph.invT0[1];
+                    }
                     const double mu = gl * dL;
                     cl.mu[o] = mu;
                     cl.acc[o] = cl.first_pass ? acc_a + mu : acc_a;
@@ -243,7 +256,10 @@ int launch_adjoint_sweeps(hipStream_t s, const DevGrid& g, int face, const doubl
         a.cm[k] = cm[k];
         a.tb[k] = tb[k];
     }
-    hipLaunchKernelGGL(k_tb2d_adj, dim3((unsigned)(a.tiles_x * tiles_y)), dim3(64 * WAVES), 0, s, a);
+    if (a.cell.acc && a.cell.ph.spitzer)
+        hipLaunchKernelGGL(k_tb2d_adj<true>, dim3((unsigned)(a.tiles_x * tiles_y)), dim3(64 * WAVES), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_tb2d_adj<false>, dim3((unsigned)(a.tiles_x * tiles_y)), dim3(64 * WAVES), 0, s, a);
     return K;
 }
 

@@ -69,7 +69,7 @@ struct Coef2DArgs {
     double wz;
 };
 
-template <bool kRelax>
+template <bool kRelax, bool kSH>
 __global__ void __launch_bounds__(64 * kWaves) k_coeffs2d(Coef2DArgs a) {
     const int lane = threadIdx.x & 63;
     const int strip = blockIdx.x * kWaves + (threadIdx.x >> 6);
@@ -101,7 +101,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_coeffs2d(Coef2DArgs a) {
         }
     }
 #pragma unroll
-    for (int r = 0; r < kRows + 2; ++r) Lw[r] = cell_conductivity(a.ph, tw[r], aw[r]);
+    for (int r = 0; r < kRows + 2; ++r)
+        Lw[r] = phys::cell_lambda<kSH>(a.ph, tw[r], aw[r], a.m1, a.m2, at(y0 - 1 + r));
 
     double bound = 0.0;
 #pragma unroll
@@ -163,7 +164,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_coeffs2d(Coef2DArgs a) {
 // of the previous, current and next plane in registers.
 constexpr int kRows3 = 2;
 
-template <bool kRelax>
+template <bool kRelax, bool kSH>
 __global__ void __launch_bounds__(64 * kWaves) k_coeffs3d(Coef2DArgs a) {
     constexpr int RW = kRows3 + 2;
     const int lane = threadIdx.x & 63;
@@ -202,7 +203,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_coeffs3d(Coef2DArgs a) {
                 aw[r] = a.alpha2[idx];
                 gw[r] = q ? a.g[idx] : 0.0;
             }
-            Lw[r] = cell_conductivity(a.ph, tw[r], aw[r]);
+            Lw[r] = phys::cell_lambda<kSH>(a.ph, tw[r], aw[r], a.m1, a.m2, idx);
         }
     };
     // window: Lambda and g of planes z-1, z, z+1; T and alpha2 of z and z+1
@@ -322,8 +323,13 @@ void launch_coeffs2d(hipStream_t s, const DevGrid& g, const DevPhases& ph, doubl
     if (g.nz == 1) {
         a.strips = a.tiles_x * ((g.ny + kRows - 1) / kRows);
         const int blocks = (a.strips + kWaves - 1) / kWaves;
-        if (T2_relax) hipLaunchKernelGGL(k_coeffs2d<true>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
-        else hipLaunchKernelGGL(k_coeffs2d<false>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+        if (ph.spitzer) {
+            if (T2_relax) hipLaunchKernelGGL((k_coeffs2d<true, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+            else hipLaunchKernelGGL((k_coeffs2d<false, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+        } else {
+            if (T2_relax) hipLaunchKernelGGL((k_coeffs2d<true, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+            else hipLaunchKernelGGL((k_coeffs2d<false, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+        }
         return;
     }
     a.nz = g.nz;
@@ -337,8 +343,13 @@ void launch_coeffs2d(hipStream_t s, const DevGrid& g, const DevPhases& ph, doubl
     a.zc = (int)zc;
     a.strips = (int)(cols * ((g.nz + a.zc - 1) / a.zc));
     const int blocks = (a.strips + kWaves - 1) / kWaves;
-    if (T2_relax) hipLaunchKernelGGL(k_coeffs3d<true>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
-    else hipLaunchKernelGGL(k_coeffs3d<false>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+    if (ph.spitzer) {
+        if (T2_relax) hipLaunchKernelGGL((k_coeffs3d<true, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+        else hipLaunchKernelGGL((k_coeffs3d<false, true>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+    } else {
+        if (T2_relax) hipLaunchKernelGGL((k_coeffs3d<true, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+        else hipLaunchKernelGGL((k_coeffs3d<false, false>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, s, a);
+    }
 }
 
 }  // namespace tlim

@@ -31,10 +31,96 @@ static __device__ __forceinline__ double pressure_stiffness(const DevPhases& ph,
     return (ph.gamma[0] - 1.0) * C1 / (a1 * a1) + (ph.gamma[1] - 1.0) * C2 / (a2 * a2);
 }
 
-// Cell conductivity Lambda = sum_k alpha_k k0_k (T/T0_k)^n_k (eq. qk_dis).
-static __device__ __forceinline__ double cell_conductivity(const DevPhases& ph, double t, double a2) {
-    return (1.0 - a2) * ph.k0[0] * powlaw(t * ph.invT0[0], ph.npow[0]) +
-           a2 * ph.k0[1] * powlaw(t * ph.invT0[1], ph.npow[1]);
+// Coulomb logarithm of the Spitzer-Harm law (Sec. 4.4) from ln T and
+// ln rho: ln(l_D / max(l_LD, l_dB)), floored at 1, with ln l_D =
+// ln sh_D + (ln T - ln rho)/2, ln l_LD = ln sh_LD - ln T and
+// ln l_dB = ln sh_dB - ln T / 2.  slope = d ln(ln Lambda)/d ln T times
+// ln Lambda: 3/2 with the Landau length, 1 with the de Broglie length, 0 on
+// the floor.
+static __device__ __forceinline__ double coulomb_log(const DevPhases& ph, int k, double lt, double lr,
+                                                     double& slope) {
+    const double lld = ph.ln_shLD[k] - lt, ldb = ph.ln_shdB[k] - 0.5 * lt;
+    const double L = ph.ln_shD[k] + 0.5 * (lt - lr) - fmax(lld, ldb);
+    slope = L > 1.0 ? (lld >= ldb ? 1.5 : 1.0) : 0.0;
+    return L > 1.0 ? L : 1.0;
+}
+
+// ln T and ln rho for the Spitzer-Harm law (unused otherwise).
+struct LawLogs {
+    double lt, lr;
+};
+static __device__ __forceinline__ LawLogs law_logs(const DevPhases& ph, double t, double rho) {
+    LawLogs g{0.0, 0.0};
+    if (ph.spitzer) {
+        g.lt = log(t);
+        g.lr = log(rho);
+    }
+    return g;
+}
+
+// Mixture density rho = m1 + m2 of cell i, read only when a phase uses the
+// Spitzer-Harm law (the power law does not depend on it).
+template <typename I>
+static __device__ __forceinline__ double mix_density(const DevPhases& ph, const double* m1, const double* m2, I i) {
+    return ph.spitzer ? m1[i] + m2[i] : 1.0;
+}
+
+// lambda_k / k0_k of phase k: (T/T0)^n, over ln Lambda_ei under the
+// Spitzer-Harm law.
+static __device__ __forceinline__ double phase_law(const DevPhases& ph, int k, double t, const LawLogs& g) {
+    double x = powlaw(t * ph.invT0[k], ph.npow[k]);
+    if (ph.sh_law[k]) {
+        double slope;
+        x /= coulomb_log(ph, k, g.lt, g.lr, slope);
+    }
+    return x;
+}
+
+// d lambda_k / dT of phase k at fixed rho.
+static __device__ __forceinline__ double phase_law_dT(const DevPhases& ph, int k, double t, const LawLogs& g) {
+    const double x = t * ph.invT0[k];
+    double d = ph.npow[k] != 0.0 ? ph.k0[k] * ph.npow[k] * powlaw(x, ph.npow[k] - 1.0) * ph.invT0[k] : 0.0;
+    if (ph.sh_law[k]) {
+        double slope;
+        const double L = coulomb_log(ph, k, g.lt, g.lr, slope);
+        d = (d - ph.k0[k] * powlaw(x, ph.npow[k]) * slope / (t * L)) / L;
+    }
+    return d;
+}
+
+// Derivatives of the cell conductivity at (rho, T) for the adjoint:
+// dk[k] = d Lambda / d k0_k = alpha_k lambda_k / k0_k and dT = d Lambda / dT.
+static __device__ __forceinline__ void cell_conductivity_grad(const DevPhases& ph, double t, double a2, double rho,
+                                                              double dk[2], double& dT) {
+    const LawLogs g = law_logs(ph, t, rho);
+    const double a1 = 1.0 - a2;
+    dk[0] = a1 * phase_law(ph, 0, t, g);
+    dk[1] = a2 * phase_law(ph, 1, t, g);
+    dT = a1 * phase_law_dT(ph, 0, t, g) + a2 * phase_law_dT(ph, 1, t, g);
+}
+
+// Cell conductivity Lambda = sum_k alpha_k lambda_k(rho, T) (eq. qk_dis);
+// rho (the mixture density) matters only under the Spitzer-Harm law.
+static __device__ __forceinline__ double cell_conductivity(const DevPhases& ph, double t, double a2, double rho) {
+    const LawLogs g = law_logs(ph, t, rho);
+    return (1.0 - a2) * (ph.k0[0] * phase_law(ph, 0, t, g)) + a2 * (ph.k0[1] * phase_law(ph, 1, t, g));
+}
+
+// The same when neither phase uses the Spitzer-Harm law (bitwise equal to
+// cell_conductivity there).
+static __device__ __forceinline__ double cell_conductivity_pow(const DevPhases& ph, double t, double a2) {
+    return (1.0 - a2) * (ph.k0[0] * powlaw(t * ph.invT0[0], ph.npow[0])) +
+           a2 * (ph.k0[1] * powlaw(t * ph.invT0[1], ph.npow[1]));
+}
+
+// Lambda of cell i in kernels compiled per law family: kSH when a phase
+// follows the Spitzer-Harm law (rho = m1 + m2 read), else the power law
+// only, so that the power-law kernels carry no logarithms.
+template <bool kSH, typename I>
+static __device__ __forceinline__ double cell_lambda(const DevPhases& ph, double t, double a2, const double* m1,
+                                                     const double* m2, I i) {
+    if constexpr (kSH) return cell_conductivity(ph, t, a2, m1[i] + m2[i]);
+    else return cell_conductivity_pow(ph, t, a2);
 }
 
 // 1 / C_eff (Sec. 3.4.2 under T_1 = T_2 and p_1 = p_2).

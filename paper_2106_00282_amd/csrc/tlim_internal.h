@@ -22,6 +22,10 @@ struct DevPhases {
     double gamma[2], pinf[2], cv[2];
     double k0[2], T0[2], invT0[2], npow[2];
     double mu[2];
+    // sh_law[k] = 1: phase k follows the Spitzer-Harm law (else the power
+    // law); spitzer = either phase does; logarithms of its length constants
+    int sh_law[2], spitzer;
+    double ln_shD[2], ln_shLD[2], ln_shdB[2];
 };
 
 constexpr int kMaxPasses = 64;
@@ -180,9 +184,9 @@ void launch_adj_stage(hipStream_t s, const DevGrid& g, int face, const double* l
 // acc at zero instead of reading it); mu = gLam dLam/dT(Tit); the two dL/dk0
 // sums are added to the rows k0a, k0b; if first_pass: acc += mu.
 void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* Tit,
-                     const double* alpha2, const double* gLam, const double* dg, const double* lam0,
-                     double* acc, double* mu, int first_pass, const double* rCpsi, double* k0a, double* k0b,
-                     int init);
+                     const double* alpha2, const double* m1, const double* m2, const double* gLam,
+                     const double* dg, const double* lam0, double* acc, double* mu, int first_pass,
+                     const double* rCpsi, double* k0a, double* k0b, int init);
 
 // Viscous heating by one velocity component (Sec. 3.2, phase internal
 // energies): with the predicted velocity uh (uh64, or g64 + w32 in the FP32

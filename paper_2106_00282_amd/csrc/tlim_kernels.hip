@@ -243,10 +243,11 @@ __device__ __forceinline__ int fold_coord(int c, int n, int per) {
 }
 
 // conductivity, 1/C and g = Tn + tau f/C of cell a
+template <bool kSH>
 __device__ __forceinline__ void cell_coef(const DevPhases& ph, double eps, double tau, const CoefIn& in, int64_t a,
                                           double& L, double& r, double& gv) {
     double t = in.T[a], a2 = in.alpha2[a];
-    L = cell_conductivity(ph, t, a2);
+    L = phys::cell_lambda<kSH>(ph, t, a2, in.m1, in.m2, a);
     r = inv_heat_capacity(ph, eps, t, a2, in.m1[a], in.m2[a]);
     double f = 0.0;
     if (in.src1) f += (1.0 - a2) * in.src1[a];
@@ -254,6 +255,7 @@ __device__ __forceinline__ void cell_coef(const DevPhases& ph, double eps, doubl
     gv = in.Tn[a] + tau * r * f;
 }
 
+template <bool kSH>
 __global__ void __launch_bounds__(256) k_heat_coeffs_bound(DevGrid g, DevPhases ph, double eps, double tau, int face,
                                                            CoefIn in, double* __restrict__ Lam,
                                                            double* __restrict__ rC, double* __restrict__ rhs,
@@ -275,7 +277,7 @@ __global__ void __launch_bounds__(256) k_heat_coeffs_bound(DevGrid g, DevPhases 
     // own cell (folded position)
     double L, r, gv;
     const int64_t a_self = at(i0 + tx, j0 + ty, kf);
-    cell_coef(ph, eps, tau, in, a_self, L, r, gv);
+    cell_coef<kSH>(ph, eps, tau, in, a_self, L, r, gv);
     sL[ty + 1][tx + 1] = L;
     sG[ty + 1][tx + 1] = gv;
     // halo: x sides (2 x TY cells), y sides (2 x TX cells), z layers (2 x TX x TY)
@@ -283,7 +285,7 @@ __global__ void __launch_bounds__(256) k_heat_coeffs_bound(DevGrid g, DevPhases 
         int side = tid / TY, jj = tid % TY;
         int ii = side ? i0 + TX : i0 - 1;
         double hl, hr, hg;
-        cell_coef(ph, eps, tau, in, at(ii, j0 + jj, kf), hl, hr, hg);
+        cell_coef<kSH>(ph, eps, tau, in, at(ii, j0 + jj, kf), hl, hr, hg);
         sL[jj + 1][side ? TX + 1 : 0] = hl;
         sG[jj + 1][side ? TX + 1 : 0] = hg;
     }
@@ -291,14 +293,14 @@ __global__ void __launch_bounds__(256) k_heat_coeffs_bound(DevGrid g, DevPhases 
         int side = tid / TX, ii = tid % TX;
         int jj = side ? j0 + TY : j0 - 1;
         double hl, hr, hg;
-        cell_coef(ph, eps, tau, in, at(i0 + ii, jj, kf), hl, hr, hg);
+        cell_coef<kSH>(ph, eps, tau, in, at(i0 + ii, jj, kf), hl, hr, hg);
         sL[side ? TY + 1 : 0][ii + 1] = hl;
         sG[side ? TY + 1 : 0][ii + 1] = hg;
     }
     if (g.nz > 1) {
         for (int side = 0; side < 2; ++side) {
             double hl, hr, hg;
-            cell_coef(ph, eps, tau, in, at(i0 + tx, j0 + ty, side ? k + 1 : k - 1), hl, hr, hg);
+            cell_coef<kSH>(ph, eps, tau, in, at(i0 + tx, j0 + ty, side ? k + 1 : k - 1), hl, hr, hg);
             zL[side][ty][tx] = hl;
             zG[side][ty][tx] = hg;
         }
@@ -344,6 +346,7 @@ __global__ void __launch_bounds__(256) k_heat_coeffs_bound(DevGrid g, DevPhases 
     if (tid == 0) atomic_max_nonneg(lam + block_slot(), fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
 }
 
+template <bool kSH>
 __global__ void __launch_bounds__(256) k_heat_coeffs(DevGrid g, DevPhases ph, double eps, double tau,
                                                      const double* __restrict__ T, const double* __restrict__ alpha2,
                                                      const double* __restrict__ m1, const double* __restrict__ m2,
@@ -355,7 +358,7 @@ __global__ void __launch_bounds__(256) k_heat_coeffs(DevGrid g, DevPhases ph, do
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
          a += (int64_t)gridDim.x * blockDim.x) {
         double t = T[a], a2 = alpha2[a], a1 = 1.0 - a2;
-        double L = a1 * ph.k0[0] * powlaw(t * ph.invT0[0], ph.npow[0]) + a2 * ph.k0[1] * powlaw(t * ph.invT0[1], ph.npow[1]);
+        double L = phys::cell_lambda<kSH>(ph, t, a2, m1, m2, a);
         double C1 = m1[a] * ph.cv[0], C2 = m2[a] * ph.cv[1];
         double C = C1 + C2;
         if (B1 != 0.0 && is_mixed(a2, eps)) C += B1 * B1 / (t * t * pressure_stiffness(ph, a2, C1, C2));
@@ -599,7 +602,8 @@ __global__ void __launch_bounds__(256) k_adj_stage(DevGrid g, int face, const do
 }
 
 __global__ void __launch_bounds__(256) k_adj_cell(DevGrid g, DevPhases ph, const double* __restrict__ Tit,
-                                                  const double* __restrict__ alpha2, const double* __restrict__ gLam,
+                                                  const double* __restrict__ alpha2, const double* __restrict__ m1,
+                                                  const double* __restrict__ m2, const double* __restrict__ gLam,
                                                   const double* __restrict__ dg, const double* __restrict__ lam0,
                                                   double* __restrict__ acc, double* __restrict__ mu, int first_pass,
                                                   const double* __restrict__ rCpsi, double* k0a, double* k0b,
@@ -608,16 +612,14 @@ __global__ void __launch_bounds__(256) k_adj_cell(DevGrid g, DevPhases ph, const
     double s0 = 0.0, s1 = 0.0;
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < g.N;
          a += (int64_t)gridDim.x * blockDim.x) {
-        double t = Tit[a], a2 = alpha2[a], a1 = 1.0 - a2, gl = gLam[a];
+        double t = Tit[a], a2 = alpha2[a], gl = gLam[a];
         // lambda form, or psi = C^-1 lambda form (rCpsi = 1/C): lambda = psi / rC
         const double acc0 = init ? 0.0 : acc[a];
         double acc_a = rCpsi ? acc0 + (dg[a] + lam0[a]) / rCpsi[a] : acc0 + dg[a] + lam0[a];
-        double x0 = t * ph.invT0[0], x1 = t * ph.invT0[1];
-        s0 += gl * a1 * powlaw(x0, ph.npow[0]);
-        s1 += gl * a2 * powlaw(x1, ph.npow[1]);
-        double dL = 0.0;
-        if (ph.npow[0] != 0.0) dL += a1 * ph.k0[0] * ph.npow[0] * powlaw(x0, ph.npow[0] - 1.0) * ph.invT0[0];
-        if (ph.npow[1] != 0.0) dL += a2 * ph.k0[1] * ph.npow[1] * powlaw(x1, ph.npow[1] - 1.0) * ph.invT0[1];
+        double dk[2], dL;
+        phys::cell_conductivity_grad(ph, t, a2, phys::mix_density(ph, m1, m2, a), dk, dL);
+        s0 += gl * dk[0];
+        s1 += gl * dk[1];
         double m = gl * dL;
         mu[a] = m;
         acc[a] = first_pass ? acc_a + m : acc_a;
@@ -751,8 +753,12 @@ void launch_heat_coeffs(hipStream_t s, const DevGrid& g, const DevPhases& ph, do
                         const double* T, const double* alpha2, const double* m1, const double* m2,
                         const double* Tn, const double* src1, const double* src2, double* Lam, double* rC,
                         double* rhs, float* Lam32, float* rC32) {
-    hipLaunchKernelGGL(k_heat_coeffs, dim3(pointwise_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, eps, tau, T,
-                       alpha2, m1, m2, Tn, src1, src2, Lam, rC, rhs, Lam32, rC32);
+    if (ph.spitzer)
+        hipLaunchKernelGGL(k_heat_coeffs<true>, dim3(pointwise_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, eps,
+                           tau, T, alpha2, m1, m2, Tn, src1, src2, Lam, rC, rhs, Lam32, rC32);
+    else
+        hipLaunchKernelGGL(k_heat_coeffs<false>, dim3(pointwise_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, eps,
+                           tau, T, alpha2, m1, m2, Tn, src1, src2, Lam, rC, rhs, Lam32, rC32);
 }
 
 void launch_heat_coeffs_bound(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double tau, int face,
@@ -760,8 +766,12 @@ void launch_heat_coeffs_bound(hipStream_t s, const DevGrid& g, const DevPhases& 
                               const double* Tn, const double* src1, const double* src2, double* Lam, double* rC,
                               double* rhs, float* Lam32, float* rC32, float* q32, float* w0, double* lam) {
     CoefIn in{T, alpha2, m1, m2, Tn, src1, src2};
-    hipLaunchKernelGGL(k_heat_coeffs_bound, tile_grid(g), dim3(TX, TY), 0, s, g, ph, eps, tau, face, in, Lam, rC, rhs,
-                       Lam32, rC32, q32, w0, lam);
+    if (ph.spitzer)
+        hipLaunchKernelGGL(k_heat_coeffs_bound<true>, tile_grid(g), dim3(TX, TY), 0, s, g, ph, eps, tau, face, in, Lam,
+                           rC, rhs, Lam32, rC32, q32, w0, lam);
+    else
+        hipLaunchKernelGGL(k_heat_coeffs_bound<false>, tile_grid(g), dim3(TX, TY), 0, s, g, ph, eps, tau, face, in, Lam,
+                           rC, rhs, Lam32, rC32, q32, w0, lam);
 }
 
 void launch_visc_coeffs(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* alpha2,
@@ -826,10 +836,11 @@ void launch_adj_stage(hipStream_t s, const DevGrid& g, int face, const double* l
 }
 
 void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* Tit, const double* alpha2,
-                     const double* gLam, const double* dg, const double* lam0, double* acc, double* mu,
-                     int first_pass, const double* rCpsi, double* k0a, double* k0b, int init) {
-    hipLaunchKernelGGL(k_adj_cell, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, Tit, alpha2, gLam, dg,
-                       lam0, acc, mu, first_pass, rCpsi, k0a, k0b, init);
+                     const double* m1, const double* m2, const double* gLam, const double* dg, const double* lam0,
+                     double* acc, double* mu, int first_pass, const double* rCpsi, double* k0a, double* k0b,
+                     int init) {
+    hipLaunchKernelGGL(k_adj_cell, dim3(reduce_blocks(g.N)), dim3(kReduceThreads), 0, s, g, ph, Tit, alpha2, m1, m2,
+                       gLam, dg, lam0, acc, mu, first_pass, rCpsi, k0a, k0b, init);
 }
 
 void launch_visc_heat(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, int face, double tau,

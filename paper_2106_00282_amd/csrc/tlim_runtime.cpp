@@ -206,6 +206,13 @@ DevPhases dev_phases(const tlim_ctx* c) {
         p.invT0[k] = 1.0 / c->phase[k].T0;
         p.npow[k] = c->phase[k].npow;
         p.mu[k] = c->phase[k].mu;
+        p.sh_law[k] = c->phase[k].law == TLIM_LAW_SPITZER;
+        if (p.sh_law[k]) {
+            p.spitzer = 1;
+            p.ln_shD[k] = std::log(c->phase[k].sh_D);
+            p.ln_shLD[k] = std::log(c->phase[k].sh_LD);  // -inf for 0: that length never wins
+            p.ln_shdB[k] = std::log(c->phase[k].sh_dB);
+        }
     }
     return p;
 }
@@ -697,6 +704,8 @@ tlim::NextCoef next_coef(tlim_ctx* c, int it, const DevPhases& ph) {
     nc.Lam32 = c->Lam32_alt;
     nc.q32 = c->q32_alt;
     nc.ph = ph;
+    nc.m1 = c->field[TLIM_M1];
+    nc.m2 = c->field[TLIM_M2];
     return nc;
 }
 
@@ -736,6 +745,7 @@ tlim::NextCoef next_step_coef(tlim_ctx* c, const tlim_step_opts* o, const DevPha
     nc.ph = ph;
     nc.m1 = c->field[TLIM_M1];
     nc.m2 = c->field[TLIM_M2];
+    nc.next_step = 1;
     nc.Tn = c->next_tn = free_tn(c);  // the next step's T^n array
     nc.a2 = c->next_a2 = free_alpha2(c);
     nc.eps = o->alpha_eps;
@@ -1049,6 +1059,11 @@ tlim_status tlim_set_phase(tlim_ctx* c, int32_t k, const tlim_phase* p) {
     if (!(p->gamma > 1.0) || !(p->cv > 0.0) || !(p->k0 >= 0.0) || !(p->T0 > 0.0) || !(p->mu >= 0.0) ||
         !std::isfinite(p->pinf) || !std::isfinite(p->npow))
         return fail(c, TLIM_E_ARG, "invalid phase constants");
+    if (p->law != TLIM_LAW_POWER && p->law != TLIM_LAW_SPITZER) return fail(c, TLIM_E_ARG, "unknown conductivity law");
+    if (p->law == TLIM_LAW_SPITZER &&
+        (!(p->sh_D > 0.0) || !(p->sh_LD >= 0.0) || !(p->sh_dB >= 0.0) || !(p->sh_LD > 0.0 || p->sh_dB > 0.0) ||
+         !std::isfinite(p->sh_D) || !std::isfinite(p->sh_LD) || !std::isfinite(p->sh_dB)))
+        return fail(c, TLIM_E_ARG, "invalid Spitzer-Harm length constants");
     c->phase[k] = *p;
     c->phase_set[k] = true;
     return TLIM_OK;
@@ -1811,7 +1826,8 @@ tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, i
             // blocked reverse stages in psi = C^-1 lambda form where the grid
             // allows; the launch that reaches v^(0) also finishes the pass
             bool psi_form = false, cell_done = false;
-            tlim::AdjCell cell{ph, Tit, c->field[TLIM_ALPHA2], acc, mu, it == np - 1 ? 1 : 0, it == 0 ? 1 : 0,
+            tlim::AdjCell cell{ph, Tit, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2], acc, mu,
+                               it == np - 1 ? 1 : 0, it == 0 ? 1 : 0,
                                row(c, tlim::kTgtK0a), row(c, tlim::kTgtK0b)};
             {
                 std::vector<double> cmv, tbv;
@@ -1850,7 +1866,8 @@ tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, i
             // cur = dL/dv^(0) (or its psi); mu <- dL/dT^(it) through Lambda(T^(it));
             // the last pass (reversed first) starts the step's sum acc
             if (!cell_done)
-                tlim::launch_adj_cell(s, g, ph, Tit, c->field[TLIM_ALPHA2], gLam, dg, cur, acc, mu, it == 0 ? 1 : 0,
+                tlim::launch_adj_cell(s, g, ph, Tit, c->field[TLIM_ALPHA2], c->field[TLIM_M1], c->field[TLIM_M2],
+                                      gLam, dg, cur, acc, mu, it == 0 ? 1 : 0,
                                       psi_form ? c->rC : nullptr, row(c, tlim::kTgtK0a), row(c, tlim::kTgtK0b),
                                       it == np - 1 ? 1 : 0);
         }

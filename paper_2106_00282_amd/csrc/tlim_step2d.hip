@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(64 * NW, 4) k_step2d(StepArgs a) {
             double T, a2;
             relax_cell(a.ph, a.eps, a.st.alpha2[idx], t1, t2, m1, m2, T, a2);
             rc[r] = inv_heat_capacity(a.ph, a.eps, T, a2, m1, m2);
-            L[r] = cell_conductivity(a.ph, T, a2);
+            L[r] = cell_conductivity(a.ph, T, a2, m1 + m2);
             sG[wv * ROWS + r][lane] = T;
             if (out_cell(r)) {
                 const int o = out_idx(r);
@@ -339,7 +339,8 @@ __global__ void __launch_bounds__(64 * NW, 4) k_step2d(StepArgs a) {
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r) {
                     const int idx = cell_idx(r);
-                    L[r] = cell_conductivity(a.ph, v[r], a.st.a2n[idx]);
+                    L[r] = cell_conductivity(a.ph, v[r], a.st.a2n[idx],
+                                             phys::mix_density(a.ph, a.st.m1, a.st.m2, idx));
                     rc[r] = a.st.rC[idx];
                 }
                 build(L, rc, a.st.acc + (size_t)tgt_lam(it + 1) * kSlots, false);
@@ -348,7 +349,8 @@ __global__ void __launch_bounds__(64 * NW, 4) k_step2d(StepArgs a) {
                 for (int r = 0; r < ROWS; ++r) {
                     if (!out_cell(r)) {
                         const int idx = cell_idx(r);
-                        L[r] = cell_conductivity(a.ph, cload(Tw + idx), a.st.a2n[idx]);
+                        L[r] = cell_conductivity(a.ph, cload(Tw + idx), a.st.a2n[idx],
+                                                 phys::mix_density(a.ph, a.st.m1, a.st.m2, idx));
                     }
                 }
                 build(L, rc, nullptr, true);

@@ -41,14 +41,16 @@ struct NextCoef {
     float* Lam32;   // FP32 correction form: float conductivities and the
     float* q32;     // correction source of the next pass (not the ones read)
     DevPhases ph;
-    // FP64, last pass of a step: with m1 != NULL the next step's first
+    // partial densities: the Spitzer-Harm law reads rho = m1 + m2
+    const double* m1;
+    const double* m2;
+    // FP64, last pass of a step: with next_step set the next step's first
     // coefficients instead -- the temperature relaxation of every cell from
     // (alpha2, T^{n+1}, T^{n+1}, m1, m2) as the relaxation kernel does it,
     // then Lambda and the bound at the relaxed state; the relaxed T and
     // alpha2 go to Tn and a2 (neither read by the pass).  1/C is the step's
     // (equal p_inf: it depends on the partial densities only).
-    const double* m1;
-    const double* m2;
+    int next_step;
     double* Tn;
     double* a2;
     double eps;
@@ -102,6 +104,7 @@ struct AdjCell {
     DevPhases ph;
     const double* Tit;     // T^(it), the lagged iterate of the pass
     const double* alpha2;
+    const double *m1, *m2;  // partial densities (the Spitzer-Harm law reads rho = m1 + m2)
     double* acc;           // dL/dT^n accumulator
     double* mu;            // out: dL/dT^(it) through Lambda(T^(it))
     int init, first_pass;  // as launch_adj_cell

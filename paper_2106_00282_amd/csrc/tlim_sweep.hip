@@ -74,11 +74,13 @@ struct TBArgs {
     double* Lam_next;        // FP64
     float* Lam32_next;       // FP32 correction form: float conductivities and
     float* q32_next;         // the correction source -tau rC' D' g of the next pass
-    // m1 != NULL: the next step's relaxation and first coefficients instead
-    // of the next pass's (relaxed T and alpha2 to Tn_next/a2_next; 1/C is
-    // unchanged with equal p_inf)
+    // partial densities (rho = m1 + m2 of the Spitzer-Harm law, and the
+    // relaxation); next_step: the next step's relaxation and first
+    // coefficients instead of the next pass's (relaxed T and alpha2 to
+    // Tn_next/a2_next; 1/C is unchanged with equal p_inf)
     const double* m1;
     const double* m2;
+    int next_step;
     double* Tn_next;
     double* a2_next;
     double eps;
@@ -90,13 +92,21 @@ struct TBArgs {
     double tb[KMAX_TB], chat[KMAX_TB];
 };
 
-template <typename R, int NW, bool kKeep>
+// kSH: the conductivities built in the epilogue follow the Spitzer-Harm law
+// in some phase (its logarithms would otherwise take registers from the
+// power-law kernels).
+template <typename R, int NW, bool kKeep, bool kSH>
 __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
     constexpr int WAVES = NW;
     constexpr int EXT_Y = NW * ROWS;
     __shared__ R sh_lo[2][WAVES][64];  // row 0 of each wave (the "up" row of the wave below)
     __shared__ R sh_hi[2][WAVES][64];  // row ROWS-1 of each wave (the "down" row of the wave above)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // Lambda of cell idx in the epilogues (rho = m1 + m2 read only under the
+    // Spitzer-Harm law)
+    auto conductivity = [&](double t, double a2, int64_t idx) -> double {
+        return phys::cell_lambda<kSH>(a.ph, t, a2, a.m1, a.m2, idx);
+    };
     const int K = a.K, H = a.H;
     const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
     const int xg = tx * a.ox - H + lane;
@@ -267,7 +277,7 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                     const int64_t idx = (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + xi;
                     rc[r] = a.rC64[idx];
                     const double tn = gfin[r] - a.taud * rc[r] * Sfin[r];
-                    Ln[r] = phys::cell_conductivity(a.ph, tn, a.alpha2[idx]);
+                    Ln[r] = conductivity(tn, a.alpha2[idx], idx);
                 }
                 __shared__ double esh[4][WAVES][64];  // seams of Lambda and g
                 esh[0][wv][lane] = Ln[0];
@@ -379,7 +389,7 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
             // mean(Lambda_a, Lambda_b), faces in the order -x, +x, -y, +y.
             // With m1 the next step's instead: every cell relaxed from
             // (alpha2, v, v, m1, m2) first, Lambda and 1/C at the relaxed state.
-            const bool next_step = a.m1 != nullptr;
+            const bool next_step = a.next_step != 0;
             double Ln[ROWS], Tr[ROWS], ar[ROWS], rr[ROWS];
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
@@ -389,9 +399,9 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                     const double m1 = a.m1[idx], m2 = a.m2[idx];
                     phys::relax_cell(a.ph, a.eps, a2v, v[r], v[r], m1, m2, Tr[r], ar[r]);
                     rr[r] = phys::inv_heat_capacity(a.ph, a.eps, Tr[r], ar[r], m1, m2);
-                    Ln[r] = phys::cell_conductivity(a.ph, Tr[r], ar[r]);
+                    Ln[r] = conductivity(Tr[r], ar[r], idx);
                 } else {
-                    Ln[r] = phys::cell_conductivity(a.ph, v[r], a2v);
+                    Ln[r] = conductivity(v[r], a2v, idx);
                 }
             }
             // the seam buffer not used by the last stage: its reads all
@@ -453,6 +463,7 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
         a.ph = nc->ph;
         a.m1 = nc->m1;
         a.m2 = nc->m2;
+        a.next_step = nc->next_step;
         a.Tn_next = nc->Tn;
         a.a2_next = nc->a2;
         a.eps = nc->eps;
@@ -496,12 +507,16 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
         else a.tb[k] = st.tb[k];
     }
     const dim3 grid((unsigned)(a.tiles_x * tiles_y));
-    if (stages) {
-        if (tall) hipLaunchKernelGGL((k_tb2d<R, 16, true>), grid, dim3(64 * 16), 0, s, a);
-        else hipLaunchKernelGGL((k_tb2d<R, 8, true>), grid, dim3(64 * 8), 0, s, a);
+    const bool sh = nc && nc->ph.spitzer;
+    if (stages) {  // (no epilogue: the kept-stage launches of the adjoint's recompute)
+        if (tall) hipLaunchKernelGGL((k_tb2d<R, 16, true, false>), grid, dim3(64 * 16), 0, s, a);
+        else hipLaunchKernelGGL((k_tb2d<R, 8, true, false>), grid, dim3(64 * 8), 0, s, a);
+    } else if (sh) {
+        if (tall) hipLaunchKernelGGL((k_tb2d<R, 16, false, true>), grid, dim3(64 * 16), 0, s, a);
+        else hipLaunchKernelGGL((k_tb2d<R, 8, false, true>), grid, dim3(64 * 8), 0, s, a);
     } else {
-        if (tall) hipLaunchKernelGGL((k_tb2d<R, 16, false>), grid, dim3(64 * 16), 0, s, a);
-        else hipLaunchKernelGGL((k_tb2d<R, 8, false>), grid, dim3(64 * 8), 0, s, a);
+        if (tall) hipLaunchKernelGGL((k_tb2d<R, 16, false, false>), grid, dim3(64 * 16), 0, s, a);
+        else hipLaunchKernelGGL((k_tb2d<R, 8, false, false>), grid, dim3(64 * 8), 0, s, a);
     }
     return K;
 }

@@ -23,6 +23,7 @@ FP64, FP32 = 0, 1
 ORDER_INTERLEAVED, ORDER_PAPER, ORDER_ASCENDING = 0, 1, 2
 FACE_ARITH, FACE_HARMONIC = 0, 1
 WHOLE_AUTO, WHOLE_ALWAYS, WHOLE_NEVER = 0, 1, 2
+LAW_POWER, LAW_SPITZER = 0, 1  # conductivity laws (tlim_phase.law)
 FIELDS = dict(alpha2=0, m1=1, m2=2, T1=3, T2=4, u=5, v=6, w=7, src1=8, src2=9, E=10)
 MAX_PASSES = 64
 
@@ -43,7 +44,8 @@ class Grid(C.Structure):
 
 
 class Phase(C.Structure):
-    _fields_ = [(k, C.c_double) for k in ("gamma", "pinf", "cv", "q", "k0", "T0", "npow", "mu")]
+    _fields_ = ([(k, C.c_double) for k in ("gamma", "pinf", "cv", "q", "k0", "T0", "npow", "mu")] +
+                [("law", C.c_int32)] + [(k, C.c_double) for k in ("sh_D", "sh_LD", "sh_dB")])
 
 
 class StepOptsC(C.Structure):
@@ -208,6 +210,9 @@ class Solver:
         ph = Phase()
         for name in ("gamma", "pinf", "cv", "q", "k0", "T0", "npow", "mu"):
             setattr(ph, name, float(p.get(name, 1.0 if name == "T0" else 0.0)))
+        ph.law = int(p.get("law", LAW_POWER))
+        for name in ("sh_D", "sh_LD", "sh_dB"):
+            setattr(ph, name, float(p.get(name, 0.0)))
         self._check(load_library().tlim_set_phase(self._ctx, int(k), C.byref(ph)))
 
     def _dev(self, t) -> torch.Tensor:

@@ -13,7 +13,7 @@ def oracle_dt(orc, wl, eps=1e-10):
     g = orc.make_grid(wl["n"], wl["h"], wl["bc"])
     f = {k: v.copy() for k, v in wl["fields"].items()}
     orc.relax(g, wl["phases"], f["alpha2"], f["m1"], f["m2"], f["T1"], f["T2"], eps)
-    Lam = orc.cell_conductivity(g, wl["phases"], f["alpha2"], f["T1"])
+    Lam = orc.cell_conductivity(g, wl["phases"], f["alpha2"], f["T1"], f["m1"], f["m2"])
     Cap = orc.heat_capacity(g, wl["phases"], f["alpha2"], f["m1"], f["m2"], f["T1"], eps)
     lam = orc.gershgorin(g, Lam, Cap)
     return wl["dt_factor"] * 2.0 / lam, lam
