@@ -105,6 +105,12 @@ def lib():
         L.orc_heat_adjoint.restype = C.c_int32
         L.orc_heat_adjoint.argtypes = [C.POINTER(Grid), C.POINTER(Phase), C.POINTER(Opts), C.c_int32,
                                        _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_hyperbolic.restype = C.c_int32
+        L.orc_hyperbolic.argtypes = [C.POINTER(Grid), C.POINTER(Phase), C.c_double, C.c_int32] + [_dp] * 9
+        L.orc_pressure_relax_cell.restype = None
+        L.orc_pressure_relax_cell.argtypes = [C.POINTER(Phase), _dp]
+        L.orc_hyperbolic_dt.restype = C.c_double
+        L.orc_hyperbolic_dt.argtypes = [C.POINTER(Grid), C.POINTER(Phase), C.c_double] + [_dp] * 8
         _lib = L
     return _lib
 
@@ -324,3 +330,31 @@ def heat_adjoint(g, ph, opts: StepOpts, nsteps, lamsched, alpha2, m1, m2, T0, dL
     if st != 0:
         raise ValueError("oracle adjoint: unsupported configuration")
     return dT0, dk0, TN
+
+
+# ------------------------------------------------------- hyperbolic part
+
+def hyperbolic(g, ph, dt, f: dict, relax_pressure=True):
+    """One Godunov-HLLC step of the hyperbolic part (Sec. 3.1, dimensional
+    splitting) and the pressure relaxation (Sec. 3.3), in place on the fields
+    of f (alpha2, m1, m2, T1, T2; u, v, w and E when present).  Returns 1 if a
+    cell left 0 < alpha2 < 1 or lost a positive temperature."""
+    N = _ncell(g)
+    return int(lib().orc_hyperbolic(C.byref(g), make_phases(ph), dt, int(relax_pressure),
+                                    *[_p(f.get(k), N) for k in ("alpha2", "m1", "m2", "T1", "T2",
+                                                                 "u", "v", "w", "E")]))
+
+
+def pressure_relax_cell(ph, q):
+    """Pressure relaxation (Sec. 3.3) of one conservative state q[9]; returns
+    the relaxed copy."""
+    q = np.ascontiguousarray(q, dtype=np.float64).copy()
+    lib().orc_pressure_relax_cell(make_phases(ph), _p(q, 9))
+    return q
+
+
+def hyperbolic_dt(g, ph, cfl, f: dict):
+    N = _ncell(g)
+    return float(lib().orc_hyperbolic_dt(C.byref(g), make_phases(ph), cfl,
+                                         *[_p(f.get(k), N) for k in ("alpha2", "m1", "m2", "T1", "T2",
+                                                                      "u", "v", "w")]))

@@ -855,3 +855,260 @@ int32_t orc_heat_adjoint(const orc_grid* g, const orc_phase ph[2], const orc_opt
     free(b);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Hyperbolic part and pressure relaxation (Sec. 3.1 and Sec. 3.3).          */
+/*                                                                            */
+/* Conservative state per cell, in the order of the vector U of eq.           */
+/* vectorForm (three momentum components here):                               */
+/*   q[0] = alpha_1 rho_1, q[1] = alpha_2 rho_2, q[2..4] = rho u, rho v,      */
+/*   rho w, q[5] = alpha_1 rho_1 e_1, q[6] = alpha_2 rho_2 e_2, q[7] = rho E, */
+/*   q[8] = alpha_2.                                                          */
+/* Phase energies follow the SG EOS (eqs. eos_stiffened, eos_stiffened2):    */
+/*   alpha_k rho_k e_k = alpha_k (p_k + gamma_k p_inf,k)/(gamma_k - 1)        */
+/*                       + alpha_k rho_k q_k                                   */
+/*                     = alpha_k rho_k C_v,k T_k + alpha_k p_inf,k            */
+/*                       + alpha_k rho_k q_k.                                 */
+
+#define NQ 9
+
+/* alpha_k p_k of phase k from its partial energy and mass. */
+static double phase_alpha_p(const orc_phase* p, double ak, double mk, double Ek) {
+    return (p->gamma - 1.0) * (Ek - mk * p->q) - p->gamma * ak * p->pinf;
+}
+
+typedef struct {
+    double rho, un, p, c;  /* mixture density, normal velocity, pressure, sound speed */
+} hyp_prim;
+
+/* Mixture quantities of a state for the normal axis d: p = sum alpha_k p_k,
+ * and the speed of sound of the model, c^2 = Y_1 c_1^2 + Y_2 c_2^2 with
+ * c_k^2 = gamma_k (p_k + p_inf,k)/rho_k (so rho c^2 = sum gamma_k alpha_k
+ * (p_k + p_inf,k)). */
+static hyp_prim hyp_mixture(const orc_phase ph[2], const double* q, int d) {
+    hyp_prim s;
+    double a2 = q[8], a1 = 1.0 - a2;
+    s.rho = q[0] + q[1];
+    s.un = q[2 + d] / s.rho;
+    double ap1 = phase_alpha_p(&ph[0], a1, q[0], q[5]);
+    double ap2 = phase_alpha_p(&ph[1], a2, q[1], q[6]);
+    s.p = ap1 + ap2;
+    double rc2 = ph[0].gamma * (ap1 + a1 * ph[0].pinf) + ph[1].gamma * (ap2 + a2 * ph[1].pinf);
+    s.c = sqrt(rc2 / s.rho);
+    return s;
+}
+
+/* HLLC solution at a face between states L and R along axis d (Sec. 3.1;
+ * three-wave solver with Davis speed estimates).  Returns the face flux of
+ * every component as in eq. vectorForm, F = u U + p D (D has 1 in the normal
+ * momentum and u in rho E), and the face velocity u* used by the
+ * non-conservative terms R(U) du/dx.  Star states: every advected density is
+ * scaled by (S_K - u_K)/(S_K - S*) -- the phase masses, the tangential
+ * momenta and the phase internal energies (their specific values carried
+ * across the waves) -- alpha_2 is continuous across S_K, the normal momentum
+ * is rho* S*, and the total energy takes the HLLC jump. */
+static void hllc_face(const orc_phase ph[2], const double* qL, const double* qR, int d, double* F,
+                      double* ustar) {
+    hyp_prim L = hyp_mixture(ph, qL, d), R = hyp_mixture(ph, qR, d);
+    double SL = fmin(L.un - L.c, R.un - R.c);
+    double SR = fmax(L.un + L.c, R.un + R.c);
+    double Ss = (R.p - L.p + L.rho * L.un * (SL - L.un) - R.rho * R.un * (SR - R.un)) /
+                (L.rho * (SL - L.un) - R.rho * (SR - R.un));
+    double U[NQ];
+    double uf, pf;
+    if (SL >= 0.0) {
+        memcpy(U, qL, sizeof(U));
+        uf = L.un;
+        pf = L.p;
+    } else if (SR <= 0.0) {
+        memcpy(U, qR, sizeof(U));
+        uf = R.un;
+        pf = R.p;
+    } else {
+        const double* qK = Ss >= 0.0 ? qL : qR;
+        const hyp_prim* K = Ss >= 0.0 ? &L : &R;
+        double SK = Ss >= 0.0 ? SL : SR;
+        double f = (SK - K->un) / (SK - Ss);
+        for (int c = 0; c < NQ; ++c) U[c] = qK[c] * f;
+        U[2 + d] = K->rho * f * Ss;
+        U[7] = f * (qK[7] + (Ss - K->un) * (K->rho * Ss + K->p / (SK - K->un)));
+        U[8] = qK[8];
+        uf = Ss;
+        pf = K->p + K->rho * (SK - K->un) * (Ss - K->un);
+    }
+    for (int c = 0; c < NQ; ++c) F[c] = uf * U[c];
+    F[2 + d] += pf;
+    F[7] += pf * uf;
+    *ustar = uf;
+}
+
+/* Ghost state behind a wall at the end of axis d: the mirror image of the
+ * boundary cell (normal momentum reversed). */
+static void wall_ghost(const double* q, int d, double* g) {
+    memcpy(g, q, sizeof(double) * NQ);
+    g[2 + d] = -q[2 + d];
+}
+
+/* One Godunov sweep along axis d (eq. of the Godunov method in Sec. 3.1):
+ * U_i -= dt/h (F_{i+1/2} - F_{i-1/2}) + dt/h R(U_i) (u*_{i+1/2} - u*_{i-1/2}),
+ * R = (0, 0, 0, 0, 0, alpha_1 p_1, alpha_2 p_2, 0, -alpha_2). */
+static void godunov_sweep(const orc_grid* g, const orc_phase ph[2], double dt, int d, double* q[NQ]) {
+    int64_t N = ncells(g);
+    int64_t n = g->n[d];
+    int64_t stride = d == 0 ? 1 : (d == 1 ? g->n[0] : g->n[0] * g->n[1]);
+    double lam = dt / g->h[d];
+    double* out = dalloc(N * NQ);
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t pos = (i / stride) % n;
+        double qc[NQ], qm[NQ], qp[NQ];
+        for (int c = 0; c < NQ; ++c) qc[c] = q[c][i];
+        /* left neighbour */
+        if (pos > 0 || g->bc[d] == ORC_PERIODIC) {
+            int64_t j = pos > 0 ? i - stride : i + (n - 1) * stride;
+            for (int c = 0; c < NQ; ++c) qm[c] = q[c][j];
+        } else {
+            wall_ghost(qc, d, qm);
+        }
+        if (pos < n - 1 || g->bc[d] == ORC_PERIODIC) {
+            int64_t j = pos < n - 1 ? i + stride : i - (n - 1) * stride;
+            for (int c = 0; c < NQ; ++c) qp[c] = q[c][j];
+        } else {
+            wall_ghost(qc, d, qp);
+        }
+        double Fm[NQ], Fp[NQ], um, up;
+        hllc_face(ph, qm, qc, d, Fm, &um);
+        hllc_face(ph, qc, qp, d, Fp, &up);
+        double a2 = qc[8], a1 = 1.0 - a2;
+        double R[NQ] = {0.0, 0.0, 0.0, 0.0, 0.0, phase_alpha_p(&ph[0], a1, qc[0], qc[5]),
+                        phase_alpha_p(&ph[1], a2, qc[1], qc[6]), 0.0, -a2};
+        for (int c = 0; c < NQ; ++c) out[c * N + i] = qc[c] - lam * (Fp[c] - Fm[c]) - lam * R[c] * (up - um);
+    }
+    for (int c = 0; c < NQ; ++c) memcpy(q[c], out + c * N, sizeof(double) * (size_t)N);
+    free(out);
+}
+
+/* Saturation condition of the pressure relaxation (Sec. 3.3, step 1): with
+ * the phase masses fixed and d(alpha_k rho_k e_k) = -p d alpha_k integrated
+ * at the relaxed pressure p, the SG EOS gives
+ *   alpha_k(p) = (gamma_k - 1)(E_k^0 - m_k q_k + p alpha_k^0) / (gamma_k (p + p_inf,k)),
+ * and p solves alpha_1(p) + alpha_2(p) = 1. */
+static double relaxed_alpha(const orc_phase* p, double a0, double m, double E0, double pr) {
+    return (p->gamma - 1.0) * (E0 - m * p->q + pr * a0) / (p->gamma * (pr + p->pinf));
+}
+
+void orc_pressure_relax_cell(const orc_phase ph[2], double* q) {
+    double a20 = q[8], a10 = 1.0 - a20;
+    /* sum_k alpha_k(p) - 1 falls from +inf just above -min p_inf,k to below 0:
+     * bracket it and bisect. */
+    double lo = -fmin(ph[0].pinf, ph[1].pinf);
+    double hi = fabs(lo) + 1.0;
+    for (int it = 0; it < 2000; ++it) {
+        double s = relaxed_alpha(&ph[0], a10, q[0], q[5], hi) + relaxed_alpha(&ph[1], a20, q[1], q[6], hi);
+        if (s < 1.0) break;
+        hi = 2.0 * hi;
+    }
+    for (int it = 0; it < 400; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double s = relaxed_alpha(&ph[0], a10, q[0], q[5], mid) + relaxed_alpha(&ph[1], a20, q[1], q[6], mid);
+        if (s > 1.0) lo = mid;
+        else hi = mid;
+    }
+    double p1 = 0.5 * (lo + hi);
+    double a1 = relaxed_alpha(&ph[0], a10, q[0], q[5], p1);
+    double a2 = 1.0 - a1;
+    /* Step 2: the pressure from the mixture energy rho e = rho E - rho |u|^2/2
+     * at the relaxed volume fractions (SG mixture), so that energy is
+     * conserved.  Step 3: the phase energies at that pressure. */
+    double rho = q[0] + q[1];
+    double ke = 0.5 * (q[2] * q[2] + q[3] * q[3] + q[4] * q[4]) / rho;
+    double rhoe = q[7] - ke;
+    double num = rhoe - q[0] * ph[0].q - q[1] * ph[1].q - a1 * ph[0].gamma * ph[0].pinf / (ph[0].gamma - 1.0) -
+                 a2 * ph[1].gamma * ph[1].pinf / (ph[1].gamma - 1.0);
+    double den = a1 / (ph[0].gamma - 1.0) + a2 / (ph[1].gamma - 1.0);
+    double p2 = num / den;
+    q[5] = a1 * (p2 + ph[0].gamma * ph[0].pinf) / (ph[0].gamma - 1.0) + q[0] * ph[0].q;
+    q[6] = a2 * (p2 + ph[1].gamma * ph[1].pinf) / (ph[1].gamma - 1.0) + q[1] * ph[1].q;
+    q[8] = a2;
+}
+
+/* State of the library (alpha_2, m_k, T_k, velocity, rho E) <-> U. */
+static void hyp_to_cons(const orc_phase ph[2], double a2, double m1, double m2, double T1, double T2,
+                        double u, double v, double w, const double* E, double* q) {
+    double a1 = 1.0 - a2;
+    q[0] = m1;
+    q[1] = m2;
+    double rho = m1 + m2;
+    q[2] = rho * u;
+    q[3] = rho * v;
+    q[4] = rho * w;
+    q[5] = m1 * (ph[0].cv * T1 + ph[0].q) + a1 * ph[0].pinf;
+    q[6] = m2 * (ph[1].cv * T2 + ph[1].q) + a2 * ph[1].pinf;
+    q[7] = E ? *E : q[5] + q[6] + 0.5 * rho * (u * u + v * v + w * w);
+    q[8] = a2;
+}
+
+int32_t orc_hyperbolic(const orc_grid* g, const orc_phase ph[2], double dt, int32_t relax_pressure,
+                       double* alpha2, double* m1, double* m2, double* T1, double* T2, double* u, double* v,
+                       double* w, double* E) {
+    int64_t N = ncells(g);
+    double* q[NQ];
+    for (int c = 0; c < NQ; ++c) q[c] = dalloc(N);
+    for (int64_t i = 0; i < N; ++i) {
+        double s[NQ];
+        hyp_to_cons(ph, alpha2[i], m1[i], m2[i], T1[i], T2[i], u ? u[i] : 0.0, v ? v[i] : 0.0, w ? w[i] : 0.0,
+                    E ? E + i : NULL, s);
+        for (int c = 0; c < NQ; ++c) q[c][i] = s[c];
+    }
+    /* Dimensional splitting: each directional sweep is followed by the
+     * pressure relaxation, so that every sweep starts from phase energies in
+     * pressure equilibrium and consistent with rho E. */
+    for (int d = 0; d < 3; ++d) {
+        if (g->n[d] <= 1) continue;
+        godunov_sweep(g, ph, dt, d, q);
+        if (!relax_pressure) continue;
+        for (int64_t i = 0; i < N; ++i) {
+            double s[NQ];
+            for (int c = 0; c < NQ; ++c) s[c] = q[c][i];
+            orc_pressure_relax_cell(ph, s);
+            for (int c = 0; c < NQ; ++c) q[c][i] = s[c];
+        }
+    }
+    int32_t bad = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        double s[NQ];
+        for (int c = 0; c < NQ; ++c) s[c] = q[c][i];
+        double a2 = s[8], a1 = 1.0 - a2, rho = s[0] + s[1];
+        alpha2[i] = a2;
+        m1[i] = s[0];
+        m2[i] = s[1];
+        /* T_k from eq. eos_stiffened2 */
+        T1[i] = (s[5] - s[0] * ph[0].q - a1 * ph[0].pinf) / (s[0] * ph[0].cv);
+        T2[i] = (s[6] - s[1] * ph[1].q - a2 * ph[1].pinf) / (s[1] * ph[1].cv);
+        if (u) u[i] = s[2] / rho;
+        if (v) v[i] = s[3] / rho;
+        if (w) w[i] = s[4] / rho;
+        if (E) E[i] = s[7];
+        if (!(a2 > 0.0 && a2 < 1.0) || !(T1[i] > 0.0) || !(T2[i] > 0.0)) bad = 1;
+    }
+    for (int c = 0; c < NQ; ++c) free(q[c]);
+    return bad;
+}
+
+double orc_hyperbolic_dt(const orc_grid* g, const orc_phase ph[2], double cfl, const double* alpha2,
+                         const double* m1, const double* m2, const double* T1, const double* T2, const double* u,
+                         const double* v, const double* w) {
+    int64_t N = ncells(g);
+    double rate = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        double s[NQ];
+        hyp_to_cons(ph, alpha2[i], m1[i], m2[i], T1[i], T2[i], u ? u[i] : 0.0, v ? v[i] : 0.0, w ? w[i] : 0.0,
+                    NULL, s);
+        for (int d = 0; d < 3; ++d) {
+            if (g->n[d] <= 1) continue;
+            hyp_prim m = hyp_mixture(ph, s, d);
+            rate = fmax(rate, (fabs(m.un) + m.c) / g->h[d]);
+        }
+    }
+    return rate > 0.0 ? cfl / rate : 0.0;
+}

@@ -200,6 +200,28 @@ int32_t orc_heat_adjoint(const orc_grid* g, const orc_phase ph[2], const orc_opt
                          const double* T0, const double* dL_dTN,
                          double* dL_dT0, double* dL_dk0, double* TN);
 
+/* ---- hyperbolic part and pressure relaxation (Sec. 3.1, Sec. 3.3) ---- */
+
+/* One first-order Godunov step of the hyperbolic part (eq. vectorForm, HLLC
+ * faces, dimensional splitting x, y, z), each directional sweep followed,
+ * if relax_pressure, by the pressure relaxation of every cell.  The state is updated in place: alpha2,
+ * m_k, T_k (eq. eos_stiffened2), the velocity (u, v, w nullable = 0 and not
+ * written) and rho E (E nullable: then taken from the state and not
+ * written).  Adiabatic axes are reflecting walls.  Every cell must hold
+ * both phases (0 < alpha2 < 1, m_k > 0).  Returns 1 if a cell left that
+ * range or a temperature is not positive, else 0. */
+int32_t orc_hyperbolic(const orc_grid* g, const orc_phase ph[2], double dt, int32_t relax_pressure,
+                       double* alpha2, double* m1, double* m2, double* T1, double* T2, double* u,
+                       double* v, double* w, double* E);
+/* Pressure relaxation of one conservative state q[9] (order of
+ * orc_hyperbolic's U: alpha1 rho1, alpha2 rho2, rho u, rho v, rho w,
+ * alpha1 rho1 e1, alpha2 rho2 e2, rho E, alpha2), in place. */
+void orc_pressure_relax_cell(const orc_phase ph[2], double* q);
+/* cfl / max over cells and axes of (|u_d| + c)/h_d. */
+double orc_hyperbolic_dt(const orc_grid* g, const orc_phase ph[2], double cfl, const double* alpha2,
+                         const double* m1, const double* m2, const double* T1, const double* T2,
+                         const double* u, const double* v, const double* w);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,311 @@
+"""Pins of the oracle's hyperbolic step and pressure relaxation (Sec. 3.1,
+Sec. 3.3) against what the mathematics and the paper fix: the Euler
+equations' HLLC scheme when both phases are one gas (a textbook routine
+written here in its own form), exact conservation, the preservation of
+uniform pressure, velocity and temperature across a material interface
+(Sec. 4.1), closed forms of the relaxation for ideal gases, and invariance
+of equilibrium states."""
+import numpy as np
+import pytest
+
+
+def _phases(g1=1.4, cv1=1.0, p1=0.0, g2=1.4, cv2=1.0, p2=0.0):
+    return [dict(gamma=g1, pinf=p1, cv=cv1, q=0.0, k0=1.0, T0=1.0, npow=0.0, mu=0.0),
+            dict(gamma=g2, pinf=p2, cv=cv2, q=0.0, k0=1.0, T0=1.0, npow=0.0, mu=0.0)]
+
+
+def _state_from_prim(ph, a2, rho1, rho2, p, vel):
+    """Library fields from volume fraction, phase densities, a common pressure
+    and velocity (eq. eos_stiffened2: T_k = (p + p_inf,k)/((gamma_k-1) rho_k C_v,k))."""
+    a1 = 1.0 - a2
+    shp = np.shape(a2)
+
+    def full(x):
+        return np.array(np.broadcast_to(x, shp), dtype=np.float64)
+
+    f = dict(alpha2=full(a2), m1=full(a1 * rho1), m2=full(a2 * rho2))
+    f["T1"] = full((p + ph[0]["pinf"]) / ((ph[0]["gamma"] - 1) * rho1 * ph[0]["cv"]))
+    f["T2"] = full((p + ph[1]["pinf"]) / ((ph[1]["gamma"] - 1) * rho2 * ph[1]["cv"]))
+    for k, v in zip("uvw", vel):
+        f[k] = np.array(np.broadcast_to(v, np.shape(a2)), dtype=np.float64)  # a copy: the step writes it
+    return f
+
+
+def _euler_hllc_sweep(rho, mom, E, gamma, lam, axis, periodic=True):
+    """Textbook first-order Godunov sweep with the HLLC flux for the Euler
+    equations (flux written as F_K + S_K (U*_K - U_K), Davis speeds); mom is
+    the list of momentum arrays, the normal one at index `axis`.  Array axis
+    of grid axis d is 2 - d."""
+    ax = 2 - axis
+    U = [rho] + list(mom) + [E]
+    nd = len(mom)
+
+    def prim(U):
+        r = U[0]
+        vel = [m / r for m in U[1:1 + nd]]
+        p = (gamma - 1) * (U[-1] - 0.5 * r * sum(v * v for v in vel))
+        return r, vel, p
+
+    def flux(U, r, vel, p):
+        un = vel[axis]
+        F = [r * un] + [U[1 + c] * un for c in range(nd)] + [(U[-1] + p) * un]
+        F[1 + axis] = F[1 + axis] + p
+        return F
+
+    UL = U
+    UR = [np.roll(x, -1, axis=ax) for x in U]
+    rL, vL, pL = prim(UL)
+    rR, vR, pR = prim(UR)
+    cL, cR = np.sqrt(gamma * pL / rL), np.sqrt(gamma * pR / rR)
+    uL, uR = vL[axis], vR[axis]
+    SL = np.minimum(uL - cL, uR - cR)
+    SR = np.maximum(uL + cL, uR + cR)
+    Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR))
+    FL, FR = flux(UL, rL, vL, pL), flux(UR, rR, vR, pR)
+
+    def star(U, r, vel, p, S):
+        un = vel[axis]
+        coef = r * (S - un) / (S - Ss)
+        out = [coef] + [coef * v for v in vel] + [coef * (U[-1] / r + (Ss - un) * (Ss + p / (r * (S - un))))]
+        out[1 + axis] = coef * Ss
+        return out
+
+    sL, sR = star(UL, rL, vL, pL, SL), star(UR, rR, vR, pR, SR)
+    Fface = []
+    for c in range(len(U)):
+        fsl = FL[c] + SL * (sL[c] - UL[c])
+        fsr = FR[c] + SR * (sR[c] - UR[c])
+        Fface.append(np.where(SL >= 0, FL[c], np.where(SR <= 0, FR[c], np.where(Ss >= 0, fsl, fsr))))
+    return [U[c] - lam * (Fface[c] - np.roll(Fface[c], 1, axis=ax)) for c in range(len(U))]
+
+
+@pytest.mark.parametrize("dims,relax", [(1, False), (1, True), (2, True), (3, True)])
+def test_single_gas_reduces_to_euler_hllc(orc, dims, relax):
+    """Both phases one ideal gas in pressure equilibrium: the mixture density,
+    momentum and total energy after one split step equal the textbook Euler
+    HLLC scheme's, whatever the split between the phases.  Across sweeps the
+    phase energies must agree with rho E again, which the pressure
+    relaxation after each sweep provides."""
+    rng = np.random.default_rng(21)
+    n = {1: (48, 1, 1), 2: (20, 16, 1), 3: (10, 9, 8)}[dims]
+    shape = (n[2], n[1], n[0])
+    ph = _phases()
+    rho = 1.0 + 0.5 * rng.random(shape)
+    p = 1.0 + 0.8 * rng.random(shape)
+    vel = [0.5 * rng.standard_normal(shape) if d < dims else np.zeros(shape) for d in range(3)]
+    a2 = 0.1 + 0.8 * rng.random(shape)
+    f = _state_from_prim(ph, a2, rho, rho, p, vel)  # equal phase densities
+    g = orc.make_grid(n)
+    dt = 0.4 * orc.hyperbolic_dt(g, ph, 1.0, f)
+    E = p / 0.4 + 0.5 * rho * sum(v * v for v in vel)
+    f["E"] = E.copy()
+    assert orc.hyperbolic(g, ph, dt, f, relax_pressure=relax) == 0
+    U = [rho, rho * vel[0], rho * vel[1], rho * vel[2], E]
+    for d in range(dims):
+        h = 1.0 / n[d]
+        out = _euler_hllc_sweep(U[0], U[1:4], U[4], 1.4, dt / h, d)
+        U = out
+    rho_o = f["m1"] + f["m2"]
+    assert np.abs(rho_o - U[0]).max() <= 1e-13 * np.abs(U[0]).max()
+    for d, k in enumerate("uvw"):
+        assert np.abs(rho_o * f[k] - U[1 + d]).max() <= 1e-13 * max(np.abs(U[1 + d]).max(), 1.0)
+    assert np.abs(f["E"] - U[4]).max() <= 1e-13 * np.abs(U[4]).max()
+
+
+def test_pvt_interface_translation(orc):
+    """Sec. 4.1: a liquid/gas interface moving at 1000 m/s in uniform
+    p = 1e5 Pa and T = 300 K keeps p, u and T uniform (SG constants of that
+    test).  p carries the cancellation of p_inf = 6e8 against 1e5."""
+    n = 200
+    ph = _phases(4.4, 500.0, 6e8, 1.4, 200.0, 0.0)
+    x = (np.arange(n) + 0.5) / n
+    a2 = (0.5 * (1 + np.tanh((x - 0.2) / (2.0 / n)))).clip(1e-6, 1 - 1e-6).reshape(1, 1, n)
+    T, p = 300.0, 1e5
+    rho1 = (p + 6e8) / (3.4 * 500.0 * T)
+    rho2 = p / (0.4 * 200.0 * T)
+    f = _state_from_prim(ph, a2, rho1, rho2, p, [np.full((1, 1, n), 1000.0), np.zeros((1, 1, n)),
+                                                np.zeros((1, 1, n))])
+    f["E"] = np.zeros_like(a2)
+    g = orc.make_grid((n, 1, 1))
+    # rho E from the state
+    a1 = 1 - a2
+    f["E"] = (f["m1"] * ph[0]["cv"] * f["T1"] + a1 * 6e8 + f["m2"] * ph[1]["cv"] * f["T2"] +
+              0.5 * (f["m1"] + f["m2"]) * 1e6)
+    dt = orc.hyperbolic_dt(g, ph, 0.5, f)
+    for _ in range(40):
+        assert orc.hyperbolic(g, ph, dt, f) == 0
+    assert np.abs(f["u"] - 1000.0).max() <= 1e-9 * 1000.0
+    # phase values where the phase holds at least 1e-3 of the cell (a trace
+    # phase's p_k and T_k come from alpha_k p_k / alpha_k, which divides the
+    # rounding of the p_inf cancellation by alpha_k), and the mixture pressure
+    pmix = 0.0
+    for k, (gam, cv, pinf) in ((1, (4.4, 500.0, 6e8)), (2, (1.4, 200.0, 0.0))):
+        ak = 1 - f["alpha2"] if k == 1 else f["alpha2"]
+        rk = f[f"m{k}"] / ak
+        pk = (gam - 1) * rk * cv * f[f"T{k}"] - pinf
+        sel = ak > 1e-3
+        assert np.abs(pk - p)[sel].max() <= 1e-7 * p, k
+        assert np.abs(f[f"T{k}"] - T)[sel].max() <= 1e-9 * T, k
+        pmix = pmix + ak * pk
+    assert np.abs(pmix - p).max() <= 1e-7 * p
+    # the interface has moved: 40 steps at CFL 0.5
+    assert np.abs(f["alpha2"] - a2).max() > 0.1
+
+
+def _random_two_phase(rng, n, ph):
+    shape = (n[2], n[1], n[0])
+    zz, yy, xx = np.meshgrid(*[(np.arange(m) + 0.5) / m for m in (n[2], n[1], n[0])], indexing="ij")
+    phi = np.sin(2 * np.pi * (xx + 0.3 * yy)) + 0.5 * np.cos(2 * np.pi * (yy - zz))
+    a2 = (0.5 * (1 + np.tanh(3 * phi))).clip(1e-6, 1 - 1e-6)
+    rho1 = 1.0 + 0.3 * rng.random(shape)
+    rho2 = 0.2 + 0.1 * rng.random(shape)
+    p = 1.0 + 0.5 * rng.random(shape)
+    vel = [0.3 * np.sin(2 * np.pi * (xx + d * yy)) if n[d] > 1 else np.zeros(shape) for d in range(3)]
+    f = _state_from_prim(ph, a2, rho1, rho2, p, vel)
+    # phases slightly out of pressure equilibrium
+    f["T2"] = f["T2"] * (1 + 0.05 * rng.standard_normal(shape))
+    rho = f["m1"] + f["m2"]
+    f["E"] = (f["m1"] * ph[0]["cv"] * f["T1"] + (1 - a2) * ph[0]["pinf"] + f["m2"] * ph[1]["cv"] * f["T2"] +
+              a2 * ph[1]["pinf"] + 0.5 * rho * sum(v * v for v in vel))
+    return f
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 0)])
+def test_conservation(orc, bc):
+    """Phase masses and total energy are conserved exactly (flux form, zero
+    mass and energy flux through walls); momentum too on periodic grids."""
+    rng = np.random.default_rng(22)
+    n = (24, 20, 1)
+    ph = _phases(1.4, 1.0, 0.0, 3.0, 2.0, 0.5)
+    f = _random_two_phase(rng, n, ph)
+    g = orc.make_grid(n, bc=bc)
+    sums0 = {k: f[k].sum() for k in ("m1", "m2", "E")}
+    mom0 = [(f["m1"] + f["m2"]) * f[k] for k in "uv"]
+    for _ in range(5):
+        dt = orc.hyperbolic_dt(g, ph, 0.45, f)
+        assert orc.hyperbolic(g, ph, dt, f) == 0
+    for k, s0 in sums0.items():
+        assert abs(f[k].sum() - s0) <= 1e-13 * np.abs(f[k]).sum(), k
+    if bc == (0, 0, 0):
+        for d, k in enumerate("uv"):
+            m = (f["m1"] + f["m2"]) * f[k]
+            assert abs(m.sum() - mom0[d].sum()) <= 1e-13 * np.abs(mom0[d]).sum()
+
+
+def test_wall_symmetry_and_rest_state(orc):
+    """A walled box: a state at rest with uniform pressure stays unchanged,
+    and a mirror-symmetric state stays mirror-symmetric."""
+    ph = _phases(1.4, 1.0, 0.0, 4.4, 0.5, 3.0)
+    n = (30, 1, 1)
+    g = orc.make_grid(n, bc=(1, 0, 0))
+    x = (np.arange(30) + 0.5) / 30
+    a2 = (0.5 * (1 + np.tanh((np.abs(x - 0.5) - 0.2) * 30))).clip(1e-6, 1 - 1e-6).reshape(1, 1, 30)
+    z = np.zeros((1, 1, 30))
+    f = _state_from_prim(ph, a2, 1.0, 2.0, 1.5, [z, z, z])
+    f0 = {k: v.copy() for k, v in f.items()}
+    assert orc.hyperbolic(g, ph, 0.5 * orc.hyperbolic_dt(g, ph, 1.0, f), f) == 0
+    for k in ("alpha2", "m1", "m2"):
+        assert np.abs(f[k] - f0[k]).max() <= 1e-13 * np.abs(f0[k]).max(), k
+    # temperatures where the phase holds at least 1e-3 of the cell (a trace
+    # phase's T_k divides the rounding of its energy by its mass)
+    for k, ak in (("T1", 1 - f0["alpha2"]), ("T2", f0["alpha2"])):
+        assert np.abs(f[k] - f0[k])[ak > 1e-3].max() <= 1e-13 * np.abs(f0[k]).max(), k
+    assert np.abs(f["u"]).max() <= 1e-13
+    # mirror-symmetric pressure bump with antisymmetric velocity
+    p = 1.5 + np.exp(-((x - 0.5) / 0.1) ** 2).reshape(1, 1, 30)
+    u = (0.2 * np.sin(2 * np.pi * (x - 0.5))).reshape(1, 1, 30)
+    f = _state_from_prim(ph, a2, 1.0, 2.0, p, [u, z, z])
+    for _ in range(6):
+        assert orc.hyperbolic(g, ph, 0.5 * orc.hyperbolic_dt(g, ph, 1.0, f), f) == 0
+    for k in ("alpha2", "m1", "m2"):
+        assert np.abs(f[k] - f[k][..., ::-1]).max() <= 1e-12 * np.abs(f[k]).max(), k
+    for k, ak in (("T1", 1 - f["alpha2"]), ("T2", f["alpha2"])):
+        assert np.abs(f[k] - f[k][..., ::-1])[ak > 1e-3].max() <= 1e-12 * np.abs(f[k]).max(), k
+    assert np.abs(f["u"] + f["u"][..., ::-1]).max() <= 1e-12
+
+
+def test_pressure_relaxation_ideal_gas_closed_form(orc):
+    """Sec. 3.3 for two ideal gases: step 1 is linear in p, giving
+    p1 = ((g1-1) g2 E1 + (g2-1) g1 E2) / (g1 g2 - (g1-1) g2 a1 - (g2-1) g1 a2)
+    and alpha_k = (g_k-1)(E_k + p1 a_k)/(g_k p1); step 2 gives
+    p2 = rho e / sum alpha_k/(g_k-1) = rho e / sum_k..., and p_1 = p_2 = p2."""
+    ph = _phases(1.4, 1.0, 0.0, 1.67, 3.0, 0.0)
+    g1, g2 = 1.4, 1.67
+    rng = np.random.default_rng(23)
+    for _ in range(20):
+        a2 = rng.uniform(0.05, 0.95)
+        a1 = 1 - a2
+        m1, m2 = rng.uniform(0.1, 2), rng.uniform(0.1, 2)
+        pA, pB = rng.uniform(0.5, 3), rng.uniform(0.5, 3)  # unequal phase pressures
+        E1, E2 = a1 * pA / (g1 - 1), a2 * pB / (g2 - 1)
+        mom = rng.standard_normal(3)
+        rho = m1 + m2
+        Et = E1 + E2 + 0.5 * (mom @ mom) / rho
+        q = np.array([m1, m2, *mom, E1, E2, Et, a2])
+        r = orc.pressure_relax_cell(ph, q)
+        p1 = ((g1 - 1) * g2 * E1 + (g2 - 1) * g1 * E2) / (g1 * g2 - (g1 - 1) * g2 * a1 - (g2 - 1) * g1 * a2)
+        al1 = (g1 - 1) * (E1 + p1 * a1) / (g1 * p1)
+        assert r[8] == pytest.approx(1 - al1, rel=1e-12)
+        p2 = (E1 + E2) / (al1 / (g1 - 1) + (1 - al1) / (g2 - 1))
+        assert r[5] == pytest.approx(al1 * p2 / (g1 - 1), rel=1e-12)
+        assert r[6] == pytest.approx((1 - al1) * p2 / (g2 - 1), rel=1e-12)
+        assert np.array_equal(r[:5], q[:5]) and r[7] == q[7]
+
+
+def test_pressure_relaxation_sg_equilibrium_and_energy(orc):
+    """Stiffened gases (water/air constants of Sec. 4.2): an input already in
+    pressure equilibrium is returned unchanged; otherwise the output has
+    p_1 = p_2, alpha_1 + alpha_2 = 1 and the mixture internal energy of rho E."""
+    ph = _phases(4.4, 1606.0, 6e8, 1.4, 714.0, 0.0)
+    gam = (4.4, 1.4)
+    pinf = (6e8, 0.0)
+    rng = np.random.default_rng(24)
+
+    def cons(a2, r1, r2, pa, pb, mom):
+        a1 = 1 - a2
+        E1 = a1 * (pa + gam[0] * pinf[0]) / (gam[0] - 1)
+        E2 = a2 * (pb + gam[1] * pinf[1]) / (gam[1] - 1)
+        rho = a1 * r1 + a2 * r2
+        return np.array([a1 * r1, a2 * r2, *mom, E1, E2, E1 + E2 + 0.5 * (mom @ mom) / rho, a2])
+
+    def phase_p(q):
+        a2 = q[8]
+        return [((gam[k] - 1) * q[5 + k] - gam[k] * (1 - a2 if k == 0 else a2) * pinf[k]) /
+                (1 - a2 if k == 0 else a2) for k in range(2)]
+
+    for _ in range(10):
+        a2 = rng.uniform(0.05, 0.95)
+        mom = rng.standard_normal(3)
+        q = cons(a2, 1000.0, 1.0, 2e5, 2e5, mom)
+        r = orc.pressure_relax_cell(ph, q)
+        assert np.abs(r - q).max() <= 1e-12 * np.abs(q).max()
+        q = cons(a2, 1000.0, 1.0, rng.uniform(1e5, 1e6), rng.uniform(1e5, 1e6), mom)
+        r = orc.pressure_relax_cell(ph, q)
+        pa, pb = phase_p(r)
+        assert pa == pytest.approx(pb, rel=1e-6, abs=1.0)  # p carries the p_inf = 6e8 cancellation
+        assert 0 < r[8] < 1
+        assert r[5] + r[6] == pytest.approx(q[7] - 0.5 * (mom @ mom) / (q[0] + q[1]), rel=1e-14)
+
+
+@pytest.mark.parametrize("relax", [False, True])
+def test_volume_fraction_is_advected(orc, relax):
+    """alpha_2 obeys d alpha_2/dt + u . grad alpha_2 = 0 (eq. bn_six1:vol):
+    a uniform alpha_2 stays uniform under a compressive random flow when both
+    phases are one gas with equal phase densities (so that the relaxation
+    has nothing to move either), which fixes the sign of its
+    non-conservative term -alpha_2 du/dx and the proportion of the two phase
+    energy terms alpha_k p_k du/dx."""
+    rng = np.random.default_rng(25)
+    n = (32, 24, 1)
+    shape = (1, 24, 32)
+    ph = _phases()
+    rho = 1.0 + 0.3 * rng.random(shape)
+    p = 1.0 + 0.5 * rng.random(shape)
+    vel = [0.4 * rng.standard_normal(shape), 0.4 * rng.standard_normal(shape), np.zeros(shape)]
+    f = _state_from_prim(ph, np.full(shape, 0.3), rho, rho, p, vel)
+    g = orc.make_grid(n)
+    for _ in range(3):
+        assert orc.hyperbolic(g, ph, orc.hyperbolic_dt(g, ph, 0.4, f), f, relax_pressure=relax) == 0
+    assert np.abs(f["alpha2"] - 0.3).max() <= 1e-14
+    assert np.abs(f["T1"] - f["T2"]).max() <= 1e-13 * f["T1"].max()
+    assert np.abs(f["u"] - vel[0]).max() > 1e-3  # the flow did change
