@@ -273,6 +273,51 @@ tlim_status tlim_adjoint(tlim_ctx* ctx, const tlim_step_opts* opts, int32_t nste
                          const double* ckpt_dev, const double* lam, const double* dL_dTN_dev,
                          double* dL_dT0_dev, double* dL_dk0, void* adj_ws_dev, size_t adj_ws_bytes);
 
+/* ---- Hyperbolic part and pressure relaxation (the mechanical stage on the
+ * other side of the splitting, Sec. 3.1 and Sec. 3.3) ---- */
+
+typedef struct {
+    double dt;               /* time step > 0; stable for dt * (|u_d| + c) / h_d <= 1 on every axis */
+    int32_t relax_pressure;  /* 1: pressure relaxation after each directional sweep */
+} tlim_hyp_opts;
+
+typedef struct {
+    double bad_cells;        /* cells that left 0 < alpha2 < 1 or lost a positive temperature */
+} tlim_hyp_report;
+
+/* One step of the hyperbolic part of the six-equation model: the Godunov
+ * method with HLLC faces on eq. vectorForm (the phase masses, momentum,
+ * total energy and alpha_2, and the non-conservative phase internal-energy
+ * equations with R(U) du/dx), one directional sweep per axis with more than
+ * one cell in the order x, y, z (dimensional splitting), each followed by
+ * the pressure relaxation of Sec. 3.3 when opts->relax_pressure is set:
+ * step 1 relaxes alpha_k at fixed phase masses with d(alpha_k rho_k e_k) =
+ * -p d alpha_k up to the pressure that saturates alpha_1 + alpha_2 = 1,
+ * step 2 takes the pressure of the mixture at the total energy, step 3 the
+ * phase energies at that pressure.  HLLC details that the paper leaves open:
+ * Davis wave speeds, the model's sound speed c^2 = Y_1 c_1^2 + Y_2 c_2^2,
+ * star states that scale every advected density (phase masses, tangential
+ * momenta, phase internal energies) by (S_K - u_K)/(S_K - S*).  An adiabatic
+ * axis is a reflecting wall.
+ *
+ * Reads and writes the state: alpha2, M1, M2, T1, T2 (from the phase
+ * internal energies by eq. eos_stiffened2), the velocity U, V, W and E
+ * (rho E).  Velocity components and E that are not set count as zero and as
+ * the energy of the state, and are set afterwards.  Every cell must hold
+ * both phases (0 < alpha2 < 1, M1 > 0, M2 > 0).  The step runs in FP64 in
+ * both precisions, uses the heat step's scratch arrays and cancels its
+ * prepared start.  With report != NULL it synchronises and returns
+ * TLIM_E_NUMERIC if a cell left the admissible range (the fields then hold
+ * the offending values).  Errors: TLIM_E_ARG (dt not finite or <= 0),
+ * TLIM_E_STATE (workspace, phases or the five state fields missing). */
+tlim_status tlim_advance_hyperbolic(tlim_ctx* ctx, const tlim_hyp_opts* opts, tlim_hyp_report* report);
+
+/* The largest stable time step of the hyperbolic part scaled by cfl:
+ * cfl / max over cells and axes with more than one cell of (|u_d| + c)/h_d
+ * (0 if no axis has more than one cell).  Synchronises.  Errors: TLIM_E_ARG
+ * (cfl not finite or <= 0, NULL dt_out), TLIM_E_STATE. */
+tlim_status tlim_hyperbolic_dt(tlim_ctx* ctx, double cfl, double* dt_out);
+
 /* Human-readable name of a status, and the last error message of a context. */
 const char* tlim_status_str(tlim_status s);
 const char* tlim_last_error(const tlim_ctx* ctx);

@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtlim.so")
 ARCH = "gfx950"
 
-SOURCES = ["tlim_kernels.hip", "tlim_coeffs.hip", "tlim_sweep.hip", "tlim_sweep3d.hip", "tlim_step2d.hip", "tlim_adjoint.hip", "tlim_runtime.cpp"]
+SOURCES = ["tlim_kernels.hip", "tlim_coeffs.hip", "tlim_sweep.hip", "tlim_sweep3d.hip", "tlim_step2d.hip", "tlim_adjoint.hip", "tlim_hyperbolic.hip",
+           "tlim_runtime.cpp"]
 
 # Packed FP32 instructions are disabled for all device code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

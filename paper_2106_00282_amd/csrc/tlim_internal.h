@@ -19,7 +19,7 @@ struct DevGrid {
 
 // Material constants the kernels need (both phases).
 struct DevPhases {
-    double gamma[2], pinf[2], cv[2];
+    double gamma[2], pinf[2], cv[2], qf[2];  // SG EOS (qf: the constant q of eq. eos_stiffened)
     double k0[2], T0[2], invT0[2], npow[2];
     double mu[2];
     // sh_law[k] = 1: phase k follows the Spitzer-Harm law (else the power
@@ -48,6 +48,8 @@ enum {
     kTgtK0b,
     kTgtFlag,      // whole-step kernel: failure count (schedule out of range, barrier time-out)
     kTgtNextStep,  // bound of the next step's first pass, built by this step's last launch
+    kTgtHypBad,    // hyperbolic step: cells that left 0 < alpha2 < 1 or lost a positive T
+    kTgtHypRate,   // hyperbolic step: max (|u_d| + c)/h_d
     kTgtP0,        // whole-step kernel: P of pass it in slot 0 of row kTgtP0 + it
     kTargets = kTgtP0 + kMaxPasses
 };
@@ -58,7 +60,7 @@ __host__ __device__ constexpr int tgt_bad(int it) { return 4 * it + 3; }
 // reduction of a target: sums for counts and sums, max otherwise
 __host__ __device__ constexpr bool tgt_is_sum(int t) {
     return (t < kTgtLambda && (t & 3) == 3) || t == kTgtEnergy || t == kTgtRR || t == kTgtGG || t == kTgtK0a ||
-           t == kTgtK0b || t == kTgtFlag;
+           t == kTgtK0b || t == kTgtFlag || t == kTgtHypBad;
 }
 
 // Results folded for the host (one double per target).
@@ -183,6 +185,22 @@ void launch_adj_stage(hipStream_t s, const DevGrid& g, int face, const double* l
 // psi = C^-1 lambda form and divided by rCpsi = 1/C first; init = 1 starts
 // acc at zero instead of reading it); mu = gLam dLam/dT(Tit); the two dL/dk0
 // sums are added to the rows k0a, k0b; if first_pass: acc += mu.
+// Hyperbolic part (tlim_hyperbolic.hip).  Component arrays in the order
+// alpha_1 rho_1, alpha_2 rho_2, rho u, rho v, rho w, alpha_1 rho_1 e_1,
+// alpha_2 rho_2 e_2, rho E, alpha_2; the primitive fields in the matching
+// order m1, m2, u, v, w, T1, T2, rho E, alpha2 (u, v, w, rho E may be NULL
+// on input: zero, and the energy of the state).
+void launch_hyp_cons(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* const prim[9],
+                     double* const U[9]);
+// One Godunov sweep along axis (0..2) with dt/h = lam, then (relax) the
+// pressure relaxation; to_prim: write the primitive fields and count bad
+// cells into bad_row.  in and out must not overlap.
+void launch_hyp_sweep(hipStream_t s, const DevGrid& g, const DevPhases& ph, int axis, double lam, int relax,
+                      const double* const in[9], double* const out[9], int to_prim, double* bad_row);
+// max over cells and axes of (|u_d| + c) * ih[d] (ih[d] = 0 skips the axis) into rate_row.
+void launch_hyp_rate(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* const prim[9],
+                     const double ih[3], double* rate_row);
+
 void launch_adj_cell(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* Tit,
                      const double* alpha2, const double* m1, const double* m2, const double* gLam,
                      const double* dg, const double* lam0, double* acc, double* mu, int first_pass,

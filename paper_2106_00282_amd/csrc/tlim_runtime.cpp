@@ -201,6 +201,7 @@ DevPhases dev_phases(const tlim_ctx* c) {
         p.gamma[k] = c->phase[k].gamma;
         p.pinf[k] = c->phase[k].pinf;
         p.cv[k] = c->phase[k].cv;
+        p.qf[k] = c->phase[k].q;
         p.k0[k] = c->phase[k].k0;
         p.T0[k] = c->phase[k].T0;
         p.invT0[k] = 1.0 / c->phase[k].T0;
@@ -1104,6 +1105,91 @@ tlim_status tlim_clear_field(tlim_ctx* c, int32_t f) {
     c->next_ready = false;  // the state or the laws change
     if (f < TLIM_U || f >= TLIM_NFIELDS) return fail(c, TLIM_E_ARG, "field %d is not optional", f);
     c->fset[f] = false;
+    return TLIM_OK;
+}
+
+// ---- hyperbolic part and pressure relaxation (Sec. 3.1, Sec. 3.3)
+
+tlim_status tlim_advance_hyperbolic(tlim_ctx* c, const tlim_hyp_opts* o, tlim_hyp_report* rep) {
+    if (!c) return TLIM_E_ARG;
+    tlim_status pst = resolve(c);
+    if (pst) return pst;
+    c->next_ready = false;  // the state changes
+    if (!o || !(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(c, TLIM_E_ARG, "dt must be finite and > 0");
+    tlim_status st = check_ready(c);
+    if (st) return st;
+    hipStream_t s = c->stream;
+    if (c->t2_alias) {
+        tlim::launch_copy(s, c->field[TLIM_T2], c->field[TLIM_T1], c->N);
+        c->t2_alias = false;
+    }
+    const DevGrid g = dev_grid(c, kUnit);
+    const DevPhases ph = dev_phases(c);
+    // the state's fields in the order of the conservative components; the
+    // velocity components and rho E that are not set count as zero and as
+    // the energy of the state
+    const int fidx[9] = {TLIM_M1, TLIM_M2, TLIM_U, TLIM_V, TLIM_W, TLIM_T1, TLIM_T2, TLIM_E, TLIM_ALPHA2};
+    double* F[9];
+    const double* prim[9];
+    for (int k = 0; k < 9; ++k) {
+        F[k] = c->field[fidx[k]];
+        prim[k] = c->fset[fidx[k]] ? F[k] : nullptr;
+    }
+    // U ping-pongs between scratch arrays (free between steps) and the field
+    // storage, starting where the last sweep ends up writing the fields
+    double* A[9] = {c->Tn_buf[0], c->Tn_buf[1], c->Tn_buf[2], c->Tnew, c->a2n, c->a2x, c->Lam, c->Lam_alt, c->rC};
+    int axes[3], ns = 0;
+    for (int d = 0; d < 3; ++d)
+        if (c->n[d] > 1) axes[ns++] = d;
+    double* bad = row(c, tlim::kTgtHypBad);
+    zero_rows(c, tlim::kTgtHypBad, tlim::kTgtHypBad + 1);
+    double* const* cur = (ns % 2 == 1 || ns == 0) ? A : F;
+    tlim::launch_hyp_cons(s, g, ph, prim, cur);
+    if (ns == 0) {
+        tlim::launch_hyp_sweep(s, g, ph, 0, 0.0, 0, A, F, 1, bad);  // no face: back to the fields
+    } else {
+        for (int k = 0; k < ns; ++k) {
+            const int d = axes[k];
+            double* const* out = cur == A ? F : A;
+            tlim::launch_hyp_sweep(s, g, ph, d, o->dt / c->h[d], o->relax_pressure ? 1 : 0, cur, out,
+                                   k == ns - 1 ? 1 : 0, bad);
+            cur = out;
+        }
+    }
+    HIP_TRY(c, hipGetLastError());
+    for (int f : {TLIM_U, TLIM_V, TLIM_W, TLIM_E}) c->fset[f] = true;
+    if (rep) {
+        st = read_result(c, tlim::kTgtHypBad, tlim::kTgtHypBad + 1);
+        if (st) return st;
+        rep->bad_cells = result(c, tlim::kTgtHypBad);
+        if (rep->bad_cells > 0.0)
+            return fail(c, TLIM_E_NUMERIC, "%.0f cells left 0 < alpha2 < 1 or lost a positive temperature",
+                        rep->bad_cells);
+    }
+    return TLIM_OK;
+}
+
+tlim_status tlim_hyperbolic_dt(tlim_ctx* c, double cfl, double* dt_out) {
+    if (!c) return TLIM_E_ARG;
+    tlim_status pst = resolve(c);
+    if (pst) return pst;
+    if (!dt_out || !(cfl > 0.0) || !std::isfinite(cfl)) return fail(c, TLIM_E_ARG, "cfl must be finite and > 0");
+    tlim_status st = check_ready(c);
+    if (st) return st;
+    const DevGrid g = dev_grid(c, kUnit);
+    const DevPhases ph = dev_phases(c);
+    const int fidx[9] = {TLIM_M1, TLIM_M2, TLIM_U, TLIM_V, TLIM_W, TLIM_T1, TLIM_T2, TLIM_E, TLIM_ALPHA2};
+    const double* prim[9];
+    for (int k = 0; k < 9; ++k) prim[k] = c->fset[fidx[k]] ? c->field[fidx[k]] : nullptr;
+    prim[6] = T2_ptr(c);
+    double ih[3];
+    for (int d = 0; d < 3; ++d) ih[d] = c->n[d] > 1 ? 1.0 / c->h[d] : 0.0;
+    zero_rows(c, tlim::kTgtHypRate, tlim::kTgtHypRate + 1);
+    tlim::launch_hyp_rate(c->stream, g, ph, prim, ih, row(c, tlim::kTgtHypRate));
+    st = read_result(c, tlim::kTgtHypRate, tlim::kTgtHypRate + 1);
+    if (st) return st;
+    const double rate = result(c, tlim::kTgtHypRate);
+    *dt_out = rate > 0.0 ? cfl / rate : 0.0;
     return TLIM_OK;
 }
 

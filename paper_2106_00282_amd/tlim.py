@@ -30,7 +30,8 @@ MAX_PASSES = 64
 EXPORTED = ("tlim_create", "tlim_destroy", "tlim_workspace_bytes", "tlim_bind_workspace",
             "tlim_set_phase", "tlim_set_field", "tlim_get_field", "tlim_clear_field", "tlim_spectral_bound",
             "tlim_advance", "tlim_finish", "tlim_forward_checkpointed", "tlim_adjoint_workspace_bytes",
-            "tlim_adjoint", "tlim_status_str", "tlim_last_error")
+            "tlim_adjoint", "tlim_advance_hyperbolic", "tlim_hyperbolic_dt", "tlim_status_str",
+            "tlim_last_error")
 
 
 class TlimError(RuntimeError):
@@ -55,6 +56,14 @@ class StepOptsC(C.Structure):
                 ("do_viscous", C.c_int32), ("frozen_lambda", C.POINTER(C.c_double)),
                 ("frozen_visc", C.POINTER(C.c_double)), ("time_sweeps", C.c_int32),
                 ("visc_heating", C.c_int32), ("whole_step", C.c_int32)]
+
+
+class HypOptsC(C.Structure):
+    _fields_ = [("dt", C.c_double), ("relax_pressure", C.c_int32)]
+
+
+class HypReportC(C.Structure):
+    _fields_ = [("bad_cells", C.c_double)]
 
 
 class ReportC(C.Structure):
@@ -97,6 +106,8 @@ def load_library(path: str = LIB_PATH):
     L.tlim_adjoint.argtypes = [vp, C.POINTER(StepOptsC), C.c_int32, C.c_int32, vp, dp, vp, vp, dp, vp,
                                C.c_size_t]
     L.tlim_status_str.restype = C.c_char_p
+    L.tlim_advance_hyperbolic.argtypes = [vp, C.POINTER(HypOptsC), C.POINTER(HypReportC)]
+    L.tlim_hyperbolic_dt.argtypes = [vp, C.c_double, dp]
     L.tlim_status_str.argtypes = [C.c_int]
     L.tlim_last_error.restype = C.c_char_p
     L.tlim_last_error.argtypes = [vp]
@@ -257,6 +268,21 @@ class Solver:
         if st not in (OK, E_NOCONV, E_NUMERIC):
             self._check(st)
         return st, (_report(rep) if report else None)
+
+    def advance_hyperbolic(self, dt: float, relax_pressure: bool = True, report: bool = True):
+        """One step of the hyperbolic part and the pressure relaxation
+        (tlim_advance_hyperbolic).  Returns (status, bad_cells or None)."""
+        o = HypOptsC(float(dt), int(bool(relax_pressure)))
+        rep = HypReportC()
+        st = load_library().tlim_advance_hyperbolic(self._ctx, C.byref(o), C.byref(rep) if report else None)
+        if st not in (OK, E_NUMERIC):
+            self._check(st)
+        return st, (rep.bad_cells if report else None)
+
+    def hyperbolic_dt(self, cfl: float) -> float:
+        dt = C.c_double()
+        self._check(load_library().tlim_hyperbolic_dt(self._ctx, float(cfl), C.byref(dt)))
+        return dt.value
 
     def advance_raw(self, oc: StepOptsC) -> int:
         """Advance with a prepared options struct and no report (timing

@@ -32,6 +32,17 @@ Workloads (sizes are parameters; the defaults are the full sizes):
   interface3d  512^3, x adiabatic, y and z periodic; planar interface at
              x = 1/2 perturbed by 12 cosine modes of amplitude 5 cells;
              k0 = (1, 0.01); T = 1 + alpha_1; 10 steps.
+  interface1d  the interface translation of Sec. 4.1 (PVT property): 1 m,
+             SG liquid (gamma 4.4, C_v 500, p_inf 6e8) left of x = 0.2 and
+             ideal gas (gamma 1.4, C_v 200) right of it, tanh profile of
+             width 2 cells, alpha clipped to [1e-6, 1 - 1e-6], u = 1000,
+             p = 1e5, T = 300 in both phases; periodic.
+  shocktube2d  hyperbolic workload, 1024^2 periodic: the level-set
+             interface of levelset2d between a gas (gamma 1.4, rho 1) and a
+             stiffened liquid (gamma 4.4, p_inf 10, rho 10), alpha clipped to
+             [1e-6, 1 - 1e-6], at rest, with pressure 10 in the band
+             0.25 < x < 0.5 and 1 elsewhere (T_k from p and rho_k); steps at
+             CFL 0.4.
   levelset2d_spitzer  the level-set fields with the Spitzer-Harm law for
              both phases: n = 5/2, Coulomb-log lengths l_D = e^2.5 sqrt(T/rho),
              l_LD = 1/T, l_dB = 1/sqrt(T), so that the Landau branch holds
@@ -147,6 +158,47 @@ def levelset2d_spitzer(n: int = 1024, steps: int = 10):
     alpha1, T = _levelset_fields(n, 2)
     return _finish("levelset2d_spitzer", (n, n, 1), (PERIODIC,) * 3, phases, alpha1, T, 200.0,
                    steps, 3)
+
+
+def _sg_state(phases, alpha2, rho, p, vel):
+    """Library fields from alpha_2, phase densities, a common pressure and a
+    velocity: T_k = (p + p_inf,k) / ((gamma_k - 1) rho_k C_v,k), the SG EOS
+    read at the given density and pressure (input construction only)."""
+    a2 = np.ascontiguousarray(alpha2, dtype=np.float64)
+    f = dict(alpha2=a2, m1=np.ascontiguousarray((1.0 - a2) * rho[0]), m2=np.ascontiguousarray(a2 * rho[1]))
+    for k in range(2):
+        ph = phases[k]
+        T = (p + ph["pinf"]) / ((ph["gamma"] - 1.0) * rho[k] * ph["cv"])
+        f[f"T{k + 1}"] = np.ascontiguousarray(np.broadcast_to(T, a2.shape), dtype=np.float64)
+    for key, v in zip(("u", "v", "w"), vel):
+        f[key] = np.ascontiguousarray(np.broadcast_to(v, a2.shape), dtype=np.float64)
+    return f
+
+
+def interface1d(n: int = 1000, steps: int = 100):
+    """Interface translation in uniform p, u, T (Sec. 4.1)."""
+    phases = [dict(gamma=4.4, pinf=6e8, cv=500.0, q=0.0, k0=0.0, T0=1.0, npow=0.0, mu=0.0),
+              dict(gamma=1.4, pinf=0.0, cv=200.0, q=0.0, k0=0.0, T0=1.0, npow=0.0, mu=0.0)]
+    x = _centres(n)
+    a2 = (0.5 * (1.0 + np.tanh((x - 0.2) / (2.0 / n)))).clip(1e-6, 1.0 - 1e-6).reshape(1, 1, n)
+    p, T = 1e5, 300.0
+    rho = [(p + 6e8) / (3.4 * 500.0 * T), p / (0.4 * 200.0 * T)]
+    f = _sg_state(phases, a2, rho, p, (1000.0, 0.0, 0.0))
+    return dict(name="interface1d", n=(n, 1, 1), h=(1.0 / n, 1.0, 1.0), bc=(PERIODIC,) * 3, phases=phases,
+                fields=f, steps=int(steps), cfl=0.5, T=T, p=p, u=1000.0)
+
+
+def shocktube2d(n: int = 1024, steps: int = 10):
+    """Hyperbolic workload: a pressure band crossing a level-set interface."""
+    phases = [dict(gamma=1.4, pinf=0.0, cv=1.0, q=0.0, k0=1.0, T0=1.0, npow=0.0, mu=0.0),
+              dict(gamma=4.4, pinf=10.0, cv=0.5, q=0.0, k0=0.05, T0=1.0, npow=0.0, mu=0.0)]
+    alpha1, _ = _levelset_fields(n, 6)
+    a2 = (1.0 - alpha1).clip(1e-6, 1.0 - 1e-6)
+    x = _centres(n)[None, None, :]
+    p = np.where((x > 0.25) & (x < 0.5), 10.0, 1.0) * np.ones_like(a2)
+    f = _sg_state(phases, a2, (1.0, 10.0), p, (0.0, 0.0, 0.0))
+    return dict(name="shocktube2d", n=(n, n, 1), h=(1.0 / n, 1.0 / n, 1.0), bc=(PERIODIC,) * 3, phases=phases,
+                fields=f, steps=int(steps), cfl=0.4)
 
 
 def levelset2d_adjoint(n: int = 2048, steps: int = 20):
