@@ -21,6 +21,10 @@ Reported (one JSON line):
              FETCH_SIZE/WRITE_SIZE summary (null once the kernel changed)
   adjoint    adjoint / forward time on the 2048^2, 20-step adjoint workload
   bubbles3d  the 256^3 FP32 workload with the viscous part
+  hyperbolic the hyperbolic part with pressure relaxation on the 1024^2
+             shock-tube workload (one Godunov-HLLC sweep per axis per step):
+             cell updates per second per sweep, and the sweep kernel's
+             algorithmic bandwidth (9 doubles in, 9 out per cell and sweep)
   spitzer    FP64 on the same level-set fields with the Spitzer-Harm
              conductivity law (T^(5/2) over the Coulomb logarithm)
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload
@@ -186,6 +190,37 @@ def bubbles3d_rate(n=256, steps=5):
                 ms_per_step=round(wall / steps * 1e3, 3), sweeps=sweeps)
 
 
+def hyperbolic_rate(n=1024, steps=10, warmup=2):
+    """Whole-step throughput of the hyperbolic part: `steps` steps at the
+    CFL-0.4 time step of the initial state, inputs resident on the device."""
+    import torch
+    from paper_2106_00282_amd import workloads as W
+    from paper_2106_00282_amd.tlim import Solver
+    wl = W.shocktube2d(n, steps=steps)
+    s = Solver(wl["n"], wl["h"], wl["bc"])
+    s.set_workload(wl)
+    dt = s.hyperbolic_dt(wl["cfl"])
+    for _ in range(warmup):
+        s.advance_hyperbolic(dt, report=False)
+    s.set_workload(wl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.advance_hyperbolic(dt, report=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st, bad = s.advance_hyperbolic(dt)  # the state is still admissible
+    if st != 0 or bad:
+        raise RuntimeError(f"hyperbolic step failed: status {st}, {bad} bad cells")
+    N = s.N
+    sweeps = 2 * steps
+    return dict(workload=f"shocktube2d {n}^2 periodic, two SG phases, Godunov-HLLC + pressure relaxation, "
+                         f"{steps} steps at CFL 0.4",
+                value=round(N * sweeps / wall / 1e9, 3), unit="Gcell-updates/s (per directional sweep)",
+                ms_per_step=round(wall / steps * 1e3, 4),
+                algorithmic_GBs=round(N * 144 * sweeps / wall / 1e9, 1))
+
+
 def cpu_baseline(wl, tau, budget_s=12.0):
     """The FP64 oracle, as it is, on whole steps of the same workload until
     about budget_s of CPU time has passed."""
@@ -218,6 +253,9 @@ def main():
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-spitzer", action="store_true")
+    ap.add_argument("--no-hyperbolic", action="store_true")
+    ap.add_argument("--hyperbolic-only", action="store_true",
+                    help="run only the hyperbolic measurement and print its JSON (for profiling that path)")
     ap.add_argument("--workload", choices=("levelset2d", "levelset2d_spitzer"), default="levelset2d",
                     help="main workload (levelset2d_spitzer: the same fields with the Spitzer-Harm law, "
                          "for profiling that path)")
@@ -232,6 +270,10 @@ def main():
     import torch
     from paper_2106_00282_amd import workloads as W
     from paper_2106_00282_amd.tlim import Solver
+
+    if args.hyperbolic_only:
+        print(json.dumps(hyperbolic_rate(n=args.n, steps=args.steps, warmup=args.warmup)), flush=True)
+        return
 
     wl = getattr(W, args.workload)(args.n, steps=args.steps)
     probe = Solver(wl["n"], wl["h"], wl["bc"])
@@ -256,6 +298,9 @@ def main():
     b3 = None if args.no_3d or args.fp64_only else bubbles3d_rate()
     if b3:
         log("bubbles3d", b3)
+    hy = None if args.no_hyperbolic or args.fp64_only or args.workload != "levelset2d" else hyperbolic_rate()
+    if hy:
+        log("hyperbolic", hy)
     sh = None
     if not (args.no_spitzer or args.fp64_only or args.workload != "levelset2d"):
         wls = W.levelset2d_spitzer(args.n, steps=args.steps)
@@ -325,6 +370,8 @@ def main():
         out["bubbles3d"] = b3
     if sh:
         out["spitzer"] = sh
+    if hy:
+        out["hyperbolic"] = hy
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, tau)
     print(json.dumps(out), flush=True)

@@ -6,19 +6,21 @@
 // one per component, x fastest: alpha_1 rho_1, alpha_2 rho_2, rho u, rho v,
 // rho w, alpha_1 rho_1 e_1, alpha_2 rho_2 e_2, rho E, alpha_2.
 //
-// A sweep along axis D runs one work-item per cell.  It loads its own cell
-// and its two neighbours along D (27 doubles; the neighbours are the
-// adjacent work-items' own cells and come from cache: along x within the
-// wave, along y and z from the rows that the waves of the same block and the
-// blocks before it load), solves the Riemann problems of its two faces,
-// updates the cell, relaxes its pressure and writes nine doubles.  Every face
-// is solved by both cells that share it: about twice the arithmetic of a
-// face pass, for one pass over memory instead of two.  The last sweep of a
-// step writes the library's primitive fields (alpha_2, m_k, T_k, velocity,
-// rho E) instead of U and counts the cells that left the admissible range.
+// Every face's Riemann problem is solved once.  Along x a wave holds 64
+// consecutive cells, one per lane; lane l solves the face between cells l-1
+// (taken from the next lane down by DPP) and l, and the cell of lane l takes
+// its right face from lane l+1 by DPP, so lanes 1..62 update their cells and
+// a wave advances 62 cells per 64 loaded.  Along y and z a work-item owns a
+// column segment of K cells at one x (a wave covers 64 consecutive x, so
+// every load is a coalesced row) and marches along it, carrying the flux of
+// the face behind it: K + 1 faces and K + 2 cell loads per K cells.  The
+// update of a cell is then relaxed in pressure and written as U, or, in the
+// last sweep of a step, as the library's primitive fields (alpha_2, m_k, T_k,
+// velocity, rho E) with a count of the cells that left the admissible range.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "tlim_device.h"
 #include "tlim_internal.h"
 
 namespace tlim {
@@ -140,97 +142,186 @@ struct HypArgs {
     int n, per;            // cells along the axis; periodic axis
     double lam;            // dt / h
     int relax, to_prim;
+    int from_prim;         // in[] holds the primitive fields: convert on load
     double* bad;           // accumulator row of the count of inadmissible cells (to_prim)
 };
 
-// Primitive fields of the library in component order: m1, m2, u, v, w, T1,
-// T2, rho E, alpha2 (out[] of the last sweep, in[] of k_hyp_cons).
-template <int D>
-__global__ void __launch_bounds__(kHypThreads) k_hyp_sweep(HypArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * kHypThreads + threadIdx.x;
-    double bad = 0.0;
-    if (i < a.N) {
-        const int64_t nxy = (int64_t)a.nx * a.ny;
-        const int pos = D == 0 ? (int)(i % a.nx) : (D == 1 ? (int)((i / a.nx) % a.ny) : (int)(i / nxy));
-        double qc[NQ], qm[NQ], qp[NQ];
-#pragma unroll
-        for (int c = 0; c < NQ; ++c) qc[c] = a.in[c][i];
-        // neighbours: the next cell along D, wrapped on a periodic axis, or the
-        // mirror image of this cell behind a wall (normal momentum reversed)
-        const bool hasm = pos > 0 || a.per, hasp = pos < a.n - 1 || a.per;
-        const int64_t jm = pos > 0 ? i - a.stride : i + (int64_t)(a.n - 1) * a.stride;
-        const int64_t jp = pos < a.n - 1 ? i + a.stride : i - (int64_t)(a.n - 1) * a.stride;
-#pragma unroll
-        for (int c = 0; c < NQ; ++c) {
-            qm[c] = hasm ? a.in[c][jm] : qc[c];
-            qp[c] = hasp ? a.in[c][jp] : qc[c];
-        }
-        if (!hasm) qm[2 + D] = -qc[2 + D];
-        if (!hasp) qp[2 + D] = -qc[2 + D];
-        double Fm[NQ], Fp[NQ], um, up;
-        hllc<D>(a.ph, qm, qc, Fm, um);
-        hllc<D>(a.ph, qc, qp, Fp, up);
-        const double a2 = qc[8], a1 = 1.0 - a2;
-        // non-conservative terms R(U_i) (u*_{i+1/2} - u*_{i-1/2})
-        const double du = up - um;
-        double R[NQ] = {0.0, 0.0, 0.0, 0.0, 0.0, alpha_p(a.ph, 0, a1, qc[0], qc[5]),
-                        alpha_p(a.ph, 1, a2, qc[1], qc[6]), 0.0, -a2};
-        double q[NQ];
-#pragma unroll
-        for (int c = 0; c < NQ; ++c) q[c] = qc[c] - a.lam * (Fp[c] - Fm[c]) - a.lam * R[c] * du;
-        if (a.relax) relax_pressure(a.ph, q);
-        if (a.to_prim) {
-            const double b2 = q[8], b1 = 1.0 - b2, rho = q[0] + q[1];
-            const double T1 = (q[5] - q[0] * a.ph.qf[0] - b1 * a.ph.pinf[0]) / (q[0] * a.ph.cv[0]);
-            const double T2 = (q[6] - q[1] * a.ph.qf[1] - b2 * a.ph.pinf[1]) / (q[1] * a.ph.cv[1]);
-            a.out[0][i] = q[0];
-            a.out[1][i] = q[1];
-            a.out[2][i] = q[2] / rho;
-            a.out[3][i] = q[3] / rho;
-            a.out[4][i] = q[4] / rho;
-            a.out[5][i] = T1;
-            a.out[6][i] = T2;
-            a.out[7][i] = q[7];
-            a.out[8][i] = b2;
-            if (!(b2 > 0.0 && b2 < 1.0) || !(T1 > 0.0) || !(T2 > 0.0) || isinf(T1) || isinf(T2)) bad = 1.0;
-        } else {
-#pragma unroll
-            for (int c = 0; c < NQ; ++c) a.out[c][i] = q[c];
-        }
-    }
-    if (a.to_prim) {
-        // every wave: one atomic per wave that saw a bad cell
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, 64);
-        if ((threadIdx.x & 63) == 0 && bad != 0.0) {
-            const int sl = (int)(((int64_t)blockIdx.x * (kHypThreads / 64) + (threadIdx.x >> 6)) % kSlots);
-            atomicAdd(a.bad + sl, bad);
-        }
-    }
-}
-
-// The library's state (alpha2, m_k, T_k, velocity, rho E) to U; in[2..4] and
-// in[7] may be NULL (velocity 0; rho E from the state).  Pointwise, so out
-// may alias in.
-__global__ void __launch_bounds__(kHypThreads) k_hyp_cons(HypArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * kHypThreads + threadIdx.x;
-    if (i >= a.N) return;
+// U of cell i from the library's state (alpha2, m_k, T_k, velocity, rho E);
+// in[2..4] and in[7] may be NULL (velocity 0; rho E from the state).
+__device__ __forceinline__ void prim_to_cons(const HypArgs& a, int64_t i, double* q) {
     const double m1 = a.in[0][i], m2 = a.in[1][i];
     const double u = a.in[2] ? a.in[2][i] : 0.0, v = a.in[3] ? a.in[3][i] : 0.0, w = a.in[4] ? a.in[4][i] : 0.0;
     const double T1 = a.in[5][i], T2 = a.in[6][i], a2 = a.in[8][i], a1 = 1.0 - a2;
     const double rho = m1 + m2;
     const double E1 = m1 * (a.ph.cv[0] * T1 + a.ph.qf[0]) + a1 * a.ph.pinf[0];
     const double E2 = m2 * (a.ph.cv[1] * T2 + a.ph.qf[1]) + a2 * a.ph.pinf[1];
-    const double Et = a.in[7] ? a.in[7][i] : E1 + E2 + 0.5 * rho * (u * u + v * v + w * w);
-    a.out[0][i] = m1;
-    a.out[1][i] = m2;
-    a.out[2][i] = rho * u;
-    a.out[3][i] = rho * v;
-    a.out[4][i] = rho * w;
-    a.out[5][i] = E1;
-    a.out[6][i] = E2;
-    a.out[7][i] = Et;
-    a.out[8][i] = a2;
+    q[0] = m1;
+    q[1] = m2;
+    q[2] = rho * u;
+    q[3] = rho * v;
+    q[4] = rho * w;
+    q[5] = E1;
+    q[6] = E2;
+    q[7] = a.in[7] ? a.in[7][i] : E1 + E2 + 0.5 * rho * (u * u + v * v + w * w);
+    q[8] = a2;
+}
+
+// Load U of cell i (converted from the state in the first sweep of a step).
+__device__ __forceinline__ void load_cell(const HypArgs& a, int64_t i, double* q) {
+    if (a.from_prim) {
+        prim_to_cons(a, i, q);
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) q[c] = a.in[c][i];
+}
+
+// Update of cell qc from its left and right face fluxes (eq. of the
+// Godunov method in Sec. 3.1, with the non-conservative terms R(U_i)
+// (u*_{i+1/2} - u*_{i-1/2}), R = (0, 0, 0, 0, 0, alpha_1 p_1, alpha_2 p_2,
+// 0, -alpha_2)), the pressure relaxation, and the store: U, or the
+// primitive fields with the admissibility check (returns 1 for a bad cell).
+__device__ __forceinline__ double finish_cell(const HypArgs& a, int64_t i, const double* qc, const double* Fm,
+                                              const double* Fp, double um, double up) {
+    const double a2 = qc[8], a1 = 1.0 - a2;
+    const double du = up - um;
+    const double R[NQ] = {0.0, 0.0, 0.0, 0.0, 0.0, alpha_p(a.ph, 0, a1, qc[0], qc[5]),
+                          alpha_p(a.ph, 1, a2, qc[1], qc[6]), 0.0, -a2};
+    double q[NQ];
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) q[c] = qc[c] - a.lam * (Fp[c] - Fm[c]) - a.lam * R[c] * du;
+    if (a.relax) relax_pressure(a.ph, q);
+    if (!a.to_prim) {
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) a.out[c][i] = q[c];
+        return 0.0;
+    }
+    const double b2 = q[8], b1 = 1.0 - b2, rho = q[0] + q[1];
+    const double T1 = (q[5] - q[0] * a.ph.qf[0] - b1 * a.ph.pinf[0]) / (q[0] * a.ph.cv[0]);
+    const double T2 = (q[6] - q[1] * a.ph.qf[1] - b2 * a.ph.pinf[1]) / (q[1] * a.ph.cv[1]);
+    a.out[0][i] = q[0];
+    a.out[1][i] = q[1];
+    a.out[2][i] = q[2] / rho;
+    a.out[3][i] = q[3] / rho;
+    a.out[4][i] = q[4] / rho;
+    a.out[5][i] = T1;
+    a.out[6][i] = T2;
+    a.out[7][i] = q[7];
+    a.out[8][i] = b2;
+    return (!(b2 > 0.0 && b2 < 1.0) || !(T1 > 0.0) || !(T2 > 0.0) || isinf(T1) || isinf(T2)) ? 1.0 : 0.0;
+}
+
+// One wave-level count of bad cells into a slot of the row.
+__device__ __forceinline__ void count_bad(const HypArgs& a, double bad) {
+    if (!a.to_prim) return;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, 64);
+    if ((threadIdx.x & 63) == 0 && bad != 0.0) {
+        const int sl = (int)(((int64_t)blockIdx.x * (kHypThreads / 64) + (threadIdx.x >> 6)) % kSlots);
+        atomicAdd(a.bad + sl, bad);
+    }
+}
+
+constexpr int kXOut = 62;  // cells a wave updates along x (lanes 1..62)
+
+// Sweep along x.  Wave w of row r loads cells x = 62 t - 1 + lane of tile t
+// (wrapped on a periodic axis; outside a wall the mirror image of the end
+// cell, normal momentum reversed), every lane active.
+__global__ void __launch_bounds__(kHypThreads) k_hyp_sweep_x(HypArgs a, int tiles_x, int64_t waves) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * (kHypThreads / 64) + (threadIdx.x >> 6);
+    double bad = 0.0;
+    if (wid < waves) {  // wave-uniform
+        const int t = (int)(wid % tiles_x);
+        const int64_t rowi = wid / tiles_x;
+        const int nx = a.nx;
+        const int xg = kXOut * t - 1 + lane;
+        int xc = xg;
+        bool mirror = false;
+        if (a.per) {
+            xc = xg % nx;
+            if (xc < 0) xc += nx;
+        } else if (xg < 0 || xg >= nx) {
+            xc = xg < 0 ? 0 : nx - 1;
+            mirror = true;
+        }
+        const int64_t base = rowi * nx;
+        double qc[NQ];
+        load_cell(a, base + xc, qc);
+        if (mirror) qc[2] = -qc[2];
+        // face between the cell of lane-1 and this lane's cell
+        double qL[NQ];
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) qL[c] = tb::from_left(qc[c]);
+        double F[NQ], uf;
+        hllc<0>(a.ph, qL, qc, F, uf);
+        double Fr[NQ];
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) Fr[c] = tb::from_right(F[c]);
+        const double ur = tb::from_right(uf);
+        if (lane >= 1 && lane <= kXOut && xg < nx) bad = finish_cell(a, base + xg, qc, F, Fr, uf, ur);
+    }
+    count_bad(a, bad);
+}
+
+// Sweep along y (D = 1) or z (D = 2): a work-item marches along a column
+// segment of K cells.
+template <int D>
+__global__ void __launch_bounds__(kHypThreads) k_hyp_sweep_col(HypArgs a, int K, int segs, int64_t items) {
+    const int64_t it = (int64_t)blockIdx.x * kHypThreads + threadIdx.x;
+    double bad = 0.0;
+    if (it < items) {
+        const int nx = a.nx;
+        const int x = (int)(it % nx);
+        const int64_t r = it / nx;
+        const int seg = (int)(r % segs);
+        const int64_t other = r / segs;  // z (for D = 1) or y (for D = 2)
+        const int64_t s = a.stride;
+        const int64_t col0 = D == 1 ? other * (int64_t)nx * a.ny + x : other * (int64_t)nx + x;
+        const int n = a.n;
+        const int j0 = seg * K;
+        const int j1 = j0 + K < n ? j0 + K : n;
+        // neighbour j of the column: wrapped, or the mirror of the end cell
+        auto load_nb = [&](int j, double* q) {
+            bool mirror = false;
+            int jc = j;
+            if (j < 0 || j >= n) {
+                if (a.per) jc = j < 0 ? j + n : j - n;
+                else {
+                    jc = j < 0 ? 0 : n - 1;
+                    mirror = true;
+                }
+            }
+            load_cell(a, col0 + (int64_t)jc * s, q);
+            if (mirror) q[2 + D] = -q[2 + D];
+        };
+        double qm[NQ], qc[NQ], qp[NQ], Fm[NQ], Fp[NQ], um, up;
+        load_nb(j0 - 1, qm);
+        load_cell(a, col0 + (int64_t)j0 * s, qc);
+        hllc<D>(a.ph, qm, qc, Fm, um);
+        for (int j = j0; j < j1; ++j) {
+            load_nb(j + 1, qp);
+            hllc<D>(a.ph, qc, qp, Fp, up);
+            bad += finish_cell(a, col0 + (int64_t)j * s, qc, Fm, Fp, um, up);
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                qc[c] = qp[c];
+                Fm[c] = Fp[c];
+            }
+            um = up;
+        }
+    }
+    count_bad(a, bad);
+}
+
+// The library's state to U (pointwise, so out may alias in).
+__global__ void __launch_bounds__(kHypThreads) k_hyp_cons(HypArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * kHypThreads + threadIdx.x;
+    if (i >= a.N) return;
+    double q[NQ];
+    prim_to_cons(a, i, q);
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) a.out[c][i] = q[c];
 }
 
 // Largest (|u_d| + c) / h_d over the cells and the axes with more than one
@@ -280,8 +371,10 @@ void launch_hyp_cons(hipStream_t s, const DevGrid& g, const DevPhases& ph, const
 }
 
 void launch_hyp_sweep(hipStream_t s, const DevGrid& g, const DevPhases& ph, int axis, double lam, int relax,
-                      const double* const in[9], double* const out[9], int to_prim, double* bad_row) {
+                      const double* const in[9], double* const out[9], int from_prim, int to_prim,
+                      double* bad_row) {
     HypArgs a{};
+    a.from_prim = from_prim;
     for (int c = 0; c < NQ; ++c) {
         a.in[c] = in[c];
         a.out[c] = out[c];
@@ -299,10 +392,25 @@ void launch_hyp_sweep(hipStream_t s, const DevGrid& g, const DevPhases& ph, int 
     a.relax = relax;
     a.to_prim = to_prim;
     a.bad = bad_row;
-    const dim3 grid(hyp_blocks(g.N)), block(kHypThreads);
-    if (axis == 0) hipLaunchKernelGGL(k_hyp_sweep<0>, grid, block, 0, s, a);
-    else if (axis == 1) hipLaunchKernelGGL(k_hyp_sweep<1>, grid, block, 0, s, a);
-    else hipLaunchKernelGGL(k_hyp_sweep<2>, grid, block, 0, s, a);
+    const dim3 block(kHypThreads);
+    if (axis == 0) {
+        const int tiles_x = (g.nx + kXOut - 1) / kXOut;
+        const int64_t waves = (int64_t)tiles_x * g.ny * g.nz;
+        const int64_t blocks = (waves + kHypThreads / 64 - 1) / (kHypThreads / 64);
+        hipLaunchKernelGGL(k_hyp_sweep_x, dim3((unsigned)blocks), block, 0, s, a, tiles_x, waves);
+        return;
+    }
+    // column segments of K cells: as long as about 2^18 work-items still
+    // fill the chip (four waves per SIMD), at most 16
+    const int64_t cols = g.N / a.n;
+    int64_t K = g.N / ((int64_t)1 << 18);
+    K = K < 1 ? 1 : (K > 16 ? 16 : K);
+    if (K > a.n) K = a.n;
+    const int segs = (int)((a.n + K - 1) / K);
+    const int64_t items = cols * segs;
+    const dim3 grid(hyp_blocks(items));
+    if (axis == 1) hipLaunchKernelGGL(k_hyp_sweep_col<1>, grid, block, 0, s, a, (int)K, segs, items);
+    else hipLaunchKernelGGL(k_hyp_sweep_col<2>, grid, block, 0, s, a, (int)K, segs, items);
 }
 
 void launch_hyp_rate(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* const prim[9],

@@ -193,10 +193,12 @@ void launch_adj_stage(hipStream_t s, const DevGrid& g, int face, const double* l
 void launch_hyp_cons(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* const prim[9],
                      double* const U[9]);
 // One Godunov sweep along axis (0..2) with dt/h = lam, then (relax) the
-// pressure relaxation; to_prim: write the primitive fields and count bad
-// cells into bad_row.  in and out must not overlap.
+// pressure relaxation; from_prim: in[] holds the primitive fields (as for
+// launch_hyp_cons); to_prim: write the primitive fields and count bad cells
+// into bad_row.  in and out must not overlap.
 void launch_hyp_sweep(hipStream_t s, const DevGrid& g, const DevPhases& ph, int axis, double lam, int relax,
-                      const double* const in[9], double* const out[9], int to_prim, double* bad_row);
+                      const double* const in[9], double* const out[9], int from_prim, int to_prim,
+                      double* bad_row);
 // max over cells and axes of (|u_d| + c) * ih[d] (ih[d] = 0 skips the axis) into rate_row.
 void launch_hyp_rate(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* const prim[9],
                      const double ih[3], double* rate_row);

@@ -1136,22 +1136,27 @@ tlim_status tlim_advance_hyperbolic(tlim_ctx* c, const tlim_hyp_opts* o, tlim_hy
         prim[k] = c->fset[fidx[k]] ? F[k] : nullptr;
     }
     // U ping-pongs between scratch arrays (free between steps) and the field
-    // storage, starting where the last sweep ends up writing the fields
+    // storage so that the last sweep writes the fields.  With an even number
+    // of sweeps the first one reads the state itself and converts it on
+    // load; otherwise U is built in the scratch arrays first.
     double* A[9] = {c->Tn_buf[0], c->Tn_buf[1], c->Tn_buf[2], c->Tnew, c->a2n, c->a2x, c->Lam, c->Lam_alt, c->rC};
     int axes[3], ns = 0;
     for (int d = 0; d < 3; ++d)
         if (c->n[d] > 1) axes[ns++] = d;
     double* bad = row(c, tlim::kTgtHypBad);
     zero_rows(c, tlim::kTgtHypBad, tlim::kTgtHypBad + 1);
-    double* const* cur = (ns % 2 == 1 || ns == 0) ? A : F;
-    tlim::launch_hyp_cons(s, g, ph, prim, cur);
+    const bool fused = ns % 2 == 0 && ns > 0;
+    if (!fused) tlim::launch_hyp_cons(s, g, ph, prim, A);
     if (ns == 0) {
-        tlim::launch_hyp_sweep(s, g, ph, 0, 0.0, 0, A, F, 1, bad);  // no face: back to the fields
+        tlim::launch_hyp_sweep(s, g, ph, 0, 0.0, 0, A, F, 0, 1, bad);  // no face: back to the fields
     } else {
+        double* const* cur = fused ? F : A;
         for (int k = 0; k < ns; ++k) {
             const int d = axes[k];
             double* const* out = cur == A ? F : A;
-            tlim::launch_hyp_sweep(s, g, ph, d, o->dt / c->h[d], o->relax_pressure ? 1 : 0, cur, out,
+            const bool first = k == 0 && fused;
+            tlim::launch_hyp_sweep(s, g, ph, d, o->dt / c->h[d], o->relax_pressure ? 1 : 0,
+                                   first ? prim : (const double* const*)cur, out, first ? 1 : 0,
                                    k == ns - 1 ? 1 : 0, bad);
             cur = out;
         }
