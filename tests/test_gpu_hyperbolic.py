@@ -185,3 +185,39 @@ def test_hyperbolic_then_parabolic_step():
     st, rg = s.advance(StepOpts(dt=tau, passes=3, frozen_lambda=rep["lambda_G"]))
     assert st == 0
     _compare({k: s.get_field(k).cpu().numpy() for k in FIELDS}, fo)
+
+
+def test_fp32_context_and_pending_parabolic_steps():
+    """The hyperbolic step runs in FP64 in both precisions (same result in an
+    FP32 context), and completes a pipelined parabolic step that is still
+    pending before it changes the state: parabolic steps without a report,
+    then a hyperbolic step, against the same sequence with reports."""
+    from oracle import oracle as orc
+    from paper_2106_00282_amd.tlim import StepOpts
+    wl = W.shocktube2d(96)
+    wl["phases"] = [dict(p, npow=2.0, pinf=0.0) for p in wl["phases"]]  # equal p_inf: pipelined steps
+    for k in ("T1", "T2"):
+        wl["fields"][k] = wl["fields"][k].copy()
+    fo, dts = _oracle_run(orc, wl, 1)
+    f64, _ = _gpu_run(wl, dts)
+    s32 = make_solver(wl, "fp32")
+    assert s32.advance_hyperbolic(dts[0])[0] == 0
+    for k in FIELDS:
+        assert np.array_equal(s32.get_field(k).cpu().numpy(), f64[k]), k
+    # parabolic steps left pending, then the hyperbolic step
+    g = orc.make_grid(wl["n"], wl["h"], wl["bc"])
+    ph = wl["phases"]
+    Lam = orc.cell_conductivity(g, ph, wl["fields"]["alpha2"], wl["fields"]["T1"])
+    Cap = orc.heat_capacity(g, ph, wl["fields"]["alpha2"], wl["fields"]["m1"], wl["fields"]["m2"],
+                            wl["fields"]["T1"])
+    tau = 50.0 * 2 / orc.gershgorin(g, Lam, Cap)
+    runs = []
+    for report in (True, False):
+        s = make_solver(wl)
+        for _ in range(3):
+            st, _ = s.advance(StepOpts(dt=tau, passes=3), report=report)
+            assert st == 0
+        st, bad = s.advance_hyperbolic(dts[0])
+        assert st == 0 and bad == 0.0
+        runs.append({k: s.get_field(k).cpu().numpy() for k in FIELDS})
+    _compare(runs[1], runs[0])
