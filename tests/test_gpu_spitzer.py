@@ -136,3 +136,44 @@ def test_spitzer_invalid_constants_rejected():
     p = dict(wl["phases"][0])
     p.update(law=W.LAW_POWER, sh_D=0.0)
     s.set_phase(0, p)
+
+
+@pytest.mark.parametrize("sources", [False, True])
+def test_spitzer_unequal_pinf_and_sources(sources):
+    """The Spitzer-Harm law on stiffened-gas phases (p_inf 6e8 / 0) out of
+    thermal equilibrium, with and without heat sources: relaxation, C_eff,
+    the alpha_2 update and (with sources) the tiled coefficient kernel with
+    the law's logarithms, against the oracle."""
+    from oracle import oracle as orc
+    nx, ny = 70, 48
+    rng = np.random.default_rng(17)
+    ph = [dict(gamma=4.4, pinf=6e8, cv=1606.0, q=0.0, k0=0.6, T0=300.0, npow=2.5, mu=0.0),
+          dict(gamma=1.4, pinf=0.0, cv=714.0, q=0.0, k0=0.03, T0=300.0, npow=2.5, mu=0.0)]
+    # lengths chosen so that T ~ 300 and rho ~ 1..1e3 straddle the branch
+    # point (T = (sh_LD/sh_dB)^2 = 300) and the floor
+    ph = W.spitzer_phases(ph, sh_D=0.25, sh_LD=300.0 ** 0.5, sh_dB=1.0, npow=2.5)
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    a1 = 0.5 * (1 - np.tanh((x[None, :] - 0.5 - 0.1 * np.sin(2 * np.pi * y[:, None])) / (2.0 / nx)))
+    a2 = 1 - a1
+    rho1 = (1e9 + 6e8) / (3.4 * 1606.0 * 293.0)
+    rho2 = 1e5 / (0.4 * 714.0 * 293.0)
+    T1 = 280.0 + 40 * rng.random((ny, nx))
+    T2 = 280.0 + 40 * rng.random((ny, nx))
+    fields = dict(alpha2=a2.reshape(1, ny, nx), m1=(a1 * rho1).reshape(1, ny, nx),
+                  m2=(a2 * rho2).reshape(1, ny, nx), T1=T1.reshape(1, ny, nx), T2=T2.reshape(1, ny, nx))
+    if sources:
+        fields.update(src1=1e3 * rng.random((1, ny, nx)), src2=1e2 * rng.random((1, ny, nx)))
+    fields = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in fields.items()}
+    wl = dict(n=(nx, ny, 1), h=(1e-3, 1e-3, 1.0), bc=(0, 1, 0), phases=ph, fields=fields, dt_factor=50.0,
+              passes=3, viscous=False)
+    # the law's three regimes are present in the input
+    T = fields["T1"]
+    rho = fields["m1"] + fields["m2"]
+    L = np.log(0.25 * np.sqrt(T / rho) / np.maximum(300.0 ** 0.5 / T, 1.0 / np.sqrt(T)))
+    assert (L < 1).any() and ((L > 1) & (T < 300)).any() and ((L > 1) & (T > 300)).any()
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 2)
+    fg, rg, _ = run_gpu(wl, tau, 2, frozen=_frozen(ro))
+    errs = {k: rel_err(fg[k], fo[k]) for k in FIELDS_T}
+    assert max(errs.values()) <= 1e-12, errs
