@@ -221,3 +221,25 @@ def test_fp32_context_and_pending_parabolic_steps():
         assert st == 0 and bad == 0.0
         runs.append({k: s.get_field(k).cpu().numpy() for k in FIELDS})
     _compare(runs[1], runs[0])
+
+
+@pytest.mark.parametrize("n,bc", [((1, 40, 30), (0, 1, 0)), ((1, 1, 50), (0, 0, 1)), ((30, 1, 20), (1, 0, 0)),
+                                  ((2, 3, 2), (0, 0, 0))])
+def test_degenerate_axes_vs_oracle(n, bc):
+    """Grids with single-cell axes where the first sweep is not along x (the
+    column kernel converting the state on load, or a lone z sweep after the
+    conversion pass), and the smallest 3D grid, against the oracle."""
+    from oracle import oracle as orc
+    rng = np.random.default_rng([210600282, 32, n[0], n[1], n[2]])
+    phases = [dict(gamma=1.4, pinf=0.0, cv=1.0, q=0.0, k0=1.0, T0=1.0, npow=0.0, mu=0.0),
+              dict(gamma=4.4, pinf=2.0, cv=0.5, q=0.1, k0=1.0, T0=1.0, npow=0.0, mu=0.0)]
+    shape = (n[2], n[1], n[0])
+    a2 = rng.uniform(0.05, 0.95, shape)
+    p = 1.0 + 2.0 * rng.random(shape)
+    vel = [0.3 * rng.standard_normal(shape) for _ in range(3)]
+    f = W._sg_state(phases, a2, (1.0, 5.0), p, vel)
+    wl = dict(name="degenerate", n=n, h=tuple(1.0 / m if m > 1 else 1.0 for m in n), bc=bc, phases=phases,
+              fields=f, cfl=0.4)
+    fo, dts = _oracle_run(orc, wl, 3)
+    fg, _ = _gpu_run(wl, dts)
+    _compare(fg, fo)
