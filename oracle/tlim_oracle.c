@@ -1,8 +1,9 @@
 /*
  * FP64 CPU oracle of the parabolic sub-step (arXiv 2106.00282, Sec. 3.2 and
- * Sec. 3.4, Algorithm 1).  TEST INFRASTRUCTURE ONLY: the product path never
- * links or calls it.  See tlim_oracle.h for the scope, the pins and what is
- * left unpinned.
+ * Sec. 3.4, Algorithm 1), and of the mechanical stage before it (hyperbolic
+ * part and pressure relaxation, Sec. 3.1 and Sec. 3.3).  TEST
+ * INFRASTRUCTURE ONLY: the product path never links or calls it.  See
+ * tlim_oracle.h for the scope, the pins and what is left unpinned.
  *
  * Readings of the paper taken here (each one is also listed with its reason
  * in the design notes of the repository):
@@ -30,6 +31,13 @@
  *    eq. Taverage.  The root with T' <= 0 is rejected.
  *  - Picard: every pass restarts the LIM from T^n with coefficients lagged
  *    at T^(it); err = max|T^(it+1) - T^(it)| / max|T^(it+1)|.
+ *  - Spitzer-Harm law (Sec. 4.4): the Coulomb logarithm from the Debye,
+ *    Landau and de Broglie lengths with caller-given constants, floored at
+ *    1; rho is the cell's mixture density.
+ *  - Hyperbolic part: Davis wave speeds, the model's sound speed, star
+ *    states that scale every advected density by (S_K - u_K)/(S_K - S*);
+ *    each directional sweep is followed by the pressure relaxation, whose
+ *    step 1 integrates at the relaxed pressure; walls reflect.
  */
 #include "tlim_oracle.h"
 

@@ -18,18 +18,30 @@
  *   - Picard loop with volume-fraction update    (Algorithm 1)
  *   - viscous momentum diffusion                 (Sec. 3.2, eq. viscous1D)
  *   - Chebyshev cycles to the backward-Euler
- *     solution ("cycle mode") and its adjoint.
+ *     solution ("cycle mode") and its adjoint
+ *   - the power and Spitzer-Harm conductivity
+ *     laws                                       (Sec. 3.4.2, Sec. 4.4)
+ *   - the hyperbolic part, Godunov method with
+ *     HLLC faces, and the pressure relaxation    (Sec. 3.1, eq. vectorForm;
+ *                                                 Sec. 3.3)
  *
  * Pinned by the CPU tests: closed-form Fourier multiplier of one LIM pass,
  * brute-force backward Euler, Chebyshev cycle rate, energy conservation,
  * maximum principle, PVT invariance, relaxation closed forms, Picard
  * invariance for constant conductivity, adjoint vs finite differences and
- * the dot-product identity.
+ * the dot-product identity; the Spitzer-Harm law's worked values,
+ * log-derivatives and floor; for the hyperbolic part the Euler HLLC
+ * reduction, conservation, interface translation, volume-fraction
+ * advection, wall symmetry and the ideal-gas closed form of the pressure
+ * relaxation.
  *
  * Parity unpinned: the nonlinear-conductivity Picard result has no closed
  * form; it is held only by the invariants above (energy, maximum principle,
  * Picard monotonicity).  The general stiffened-gas heat step (p_inf,1 !=
  * p_inf,2) is held by per-cell energy and pressure-equality checks only.
+ * The split of the internal energy between two different phases across a
+ * wave of the hyperbolic part is held only through the mixture, the
+ * advection of alpha_2 and the interface translation.
  */
 #ifndef TLIM_ORACLE_H
 #define TLIM_ORACLE_H
