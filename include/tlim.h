@@ -14,6 +14,9 @@
  * P = ceil(pi/4 sqrt(tau lambda_max + 1)), the last one in conservative
  * flux form.  Heat conduction wraps the sweeps in a Picard loop with face
  * conductivities lagged at the previous iterate (Algorithm 1).
+ * tlim_advance_hyperbolic runs the mechanical stage that comes before it in
+ * the splitting: the hyperbolic part (Sec. 3.1) and the pressure relaxation
+ * (Sec. 3.3).
  *
  * ---------------------------------------------------------------- conventions
  * Memory.  Every pointer argument named *_dev is a device pointer on the
@@ -25,8 +28,8 @@
  * Streams.  All device work of a context is enqueued on the HIP stream given
  * to tlim_create (NULL = the null stream).  Calls that return values
  * computed on the device (spectral bound, step report, adjoint k0
- * gradient) synchronise that stream before returning; tlim_set_field and
- * tlim_get_field do not.
+ * gradient, hyperbolic time step and report) synchronise that stream before
+ * returning; tlim_set_field and tlim_get_field do not.
  * Errors.  Every entry point returns a tlim_status; nothing is thrown across
  * the ABI.  TLIM_E_ARG leaves the context unchanged.  tlim_last_error gives
  * a message for the last failing call on a context.
