@@ -177,3 +177,18 @@ def test_spitzer_unequal_pinf_and_sources(sources):
     fg, rg, _ = run_gpu(wl, tau, 2, frozen=_frozen(ro))
     errs = {k: rel_err(fg[k], fo[k]) for k in FIELDS_T}
     assert max(errs.values()) <= 1e-12, errs
+
+
+def test_spitzer_levelset2d_full_size_fp32():
+    """The FP32 form on the 1024^2 Spitzer-Harm workload, 10 steps, per-field
+    error against the FP64 oracle (with the oracle's schedule)."""
+    from oracle import oracle as orc
+    wl = W.levelset2d_spitzer(1024)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 10)
+    fg, rg, _ = run_gpu(wl, tau, 10, precision="fp32", frozen=_frozen(ro))
+    errs = {k: rel_err(fg[k], fo[k]) for k in FIELDS_T}
+    print("spitzer 1024^2 fp32 errors", errs)
+    assert errs["T1"] <= 1e-5 and errs["T2"] <= 1e-5 and errs["alpha2"] <= 1e-12
+    for r in rg:
+        assert abs(r["energy_after"] / r["energy_before"] - 1) < 1e-12
