@@ -73,3 +73,38 @@ def test_product_does_not_import_oracle():
             if fn.endswith((".py", ".cpp", ".hip", ".h")):
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "oracle" not in text.lower() or fn == "workloads.py", fn
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more it exits with a message
+    before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_ctypes_structs_match_the_header_fields():
+    """The binding's structs list the header's fields in order (the ABI is
+    by position): tlim_phase and the hyperbolic options."""
+    from paper_2106_00282_amd import tlim
+    text = open(HEADER).read()
+
+    def fields(struct):
+        end = text.index("} " + struct + ";")
+        body = text[text.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        names = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            parts = decl.split(None, 1)[1]
+            names += [n.strip().split("[")[0] for n in parts.split(",")]
+        return names
+
+    assert [f[0] for f in tlim.Phase._fields_] == fields("tlim_phase")
+    assert [f[0] for f in tlim.HypOptsC._fields_] == fields("tlim_hyp_opts")
+    assert [f[0] for f in tlim.HypReportC._fields_] == fields("tlim_hyp_report")
