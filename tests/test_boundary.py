@@ -88,7 +88,7 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_ctypes_structs_match_the_header_fields():
     """The binding's structs list the header's fields in order (the ABI is
-    by position): tlim_phase and the hyperbolic options."""
+    by position)."""
     from paper_2106_00282_amd import tlim
     text = open(HEADER).read()
 
@@ -101,10 +101,13 @@ def test_ctypes_structs_match_the_header_fields():
             decl = decl.strip()
             if not decl:
                 continue
-            parts = decl.split(None, 1)[1]
-            names += [n.strip().split("[")[0] for n in parts.split(",")]
+            # the declarators after the type: the last identifier of each
+            first, *more = decl.split(",")
+            for d in [first] + more:
+                names.append(re.search(r"(\w+)\s*(\[[^\]]*\])?\s*$", d).group(1))
         return names
 
-    assert [f[0] for f in tlim.Phase._fields_] == fields("tlim_phase")
-    assert [f[0] for f in tlim.HypOptsC._fields_] == fields("tlim_hyp_opts")
-    assert [f[0] for f in tlim.HypReportC._fields_] == fields("tlim_hyp_report")
+    for py, struct in ((tlim.Grid, "tlim_grid"), (tlim.Phase, "tlim_phase"), (tlim.StepOptsC, "tlim_step_opts"),
+                       (tlim.ReportC, "tlim_step_report"), (tlim.HypOptsC, "tlim_hyp_opts"),
+                       (tlim.HypReportC, "tlim_hyp_report")):
+        assert [f[0] for f in py._fields_] == fields(struct), struct
