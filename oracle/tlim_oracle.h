@@ -33,13 +33,17 @@
  * log-derivatives and floor; for the hyperbolic part the Euler HLLC
  * reduction, conservation, interface translation, volume-fraction
  * advection, wall symmetry and the ideal-gas closed form of the pressure
- * relaxation.
+ * relaxation.  The heat step of two stiffened gases with unequal p_inf
+ * (effective capacity and volume-fraction update) is pinned from the
+ * equation of state alone: under a uniform source it reaches the exact
+ * end state (energy E0 + tau I, p_1 = p_2) with an O(tau^2) error; with
+ * conduction on one explicit stage every cell's EOS energy changes by tau
+ * times the net flux of eq. qk_dis and the pressure gap is O(tau^2); at
+ * tau lambda = 400 the domain's EOS energy is conserved.
  *
  * Parity unpinned: the nonlinear-conductivity Picard result has no closed
  * form; it is held only by the invariants above (energy, maximum principle,
- * Picard monotonicity).  The general stiffened-gas heat step (p_inf,1 !=
- * p_inf,2) is held by per-cell energy and pressure-equality checks only.
- * The split of the internal energy between two different phases across a
+ * Picard monotonicity).  The split of the internal energy between two different phases across a
  * wave of the hyperbolic part is held only through the mixture, the
  * advection of alpha_2 and the interface translation.
  */
