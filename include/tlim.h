@@ -5,7 +5,7 @@
  * diffusion processes" (arXiv 2106.00282), on one AMD Instinct MI355X
  * (gfx950).
  *
- * One call of tlim_advance is one parabolic step of the paper's splitting
+ * One call of tlim_advance_parabolic is one parabolic step of the paper's splitting
  * (Sec. 3): the viscous part (Sec. 3.2, eq. viscous), instantaneous
  * temperature relaxation in interface cells (Sec. 3.4.1) and heat conduction
  * (Sec. 3.4.2, Algorithm 1).  Both diffusion problems are advanced with the
@@ -23,8 +23,9 @@
  * device that was current at tlim_create; every other pointer is host
  * memory.  The caller owns all memory, including the workspace it binds with
  * tlim_bind_workspace; the library only borrows pointers during a call and
- * never frees caller memory.  Fields are dense float64 arrays of
- * nx*ny*nz values in C order with x fastest, index i + nx*(j + ny*k).
+ * never frees caller memory.  Fields are dense arrays of nx*ny*nz values
+ * in C order with x fastest, index i + nx*(j + ny*k); the context keeps its
+ * state in float64, and tlim_set_field / tlim_get_field also take float32.
  * Streams.  All device work of a context is enqueued on the HIP stream given
  * to tlim_create (NULL = the null stream).  Calls that return values
  * computed on the device (spectral bound, step report, adjoint k0
@@ -58,6 +59,7 @@ typedef enum {
 
 enum { TLIM_PERIODIC = 0, TLIM_ADIABATIC = 1 };         /* boundary per axis */
 enum { TLIM_FP64 = 0, TLIM_FP32 = 1 };                 /* arithmetic of the sweeps */
+enum { TLIM_DTYPE_F64 = 0, TLIM_DTYPE_F32 = 1 };       /* element type of a caller's field buffer */
 enum { TLIM_ORDER_INTERLEAVED = 0, TLIM_ORDER_PAPER = 1, TLIM_ORDER_ASCENDING = 2 };
 enum { TLIM_FACE_ARITH = 0, TLIM_FACE_HARMONIC = 1 };
 /* whole_step: AUTO uses the one-launch step while the context has no
@@ -143,7 +145,13 @@ typedef struct {
                                     cooperative launch (relaxation and every pass, P decided on the
                                     device from the reduced lambda_G, no host prediction) instead of
                                     one launch per block of stages.  Same results up to rounding
-                                    order */
+                                    order.  Its grid barriers wait a bounded time (about a second;
+                                    the environment variable TLIM_STEP2D_SPIN_LIMIT, read at
+                                    tlim_create, sets the poll count, a test hook); a wait that runs
+                                    out makes the step return TLIM_E_HIP (or the call that verifies
+                                    a pipelined one) with alpha2, T1 and T2 marked as not set, so
+                                    that the next step returns TLIM_E_STATE until they are set
+                                    again */
 } tlim_step_opts;
 
 #define TLIM_MAX_PASSES 64
@@ -168,7 +176,7 @@ typedef struct {
     int32_t mispredicted;                 /* 1: a predicted P was wrong; the heat passes were rerun
                                              with one readback per pass (sweeps counts the rerun only) */
     int64_t pipelined_steps;              /* context totals so far: steps run pipelined (see */
-    int64_t pipeline_redos;               /* tlim_advance) and pipelined steps redone */
+    int64_t pipeline_redos;               /* tlim_advance_parabolic) and pipelined steps redone */
 } tlim_step_report;
 
 typedef struct tlim_ctx tlim_ctx;
@@ -197,14 +205,20 @@ tlim_status tlim_bind_workspace(tlim_ctx* ctx, void* dev_ptr, size_t bytes);
  * constants outside the ranges above. */
 tlim_status tlim_set_phase(tlim_ctx* ctx, int32_t k, const tlim_phase* phase);
 
-/* Copy a field from caller device memory (dense float64, see conventions)
- * into the context.  Sources are optional (absent = 0); velocity is needed
- * only for the viscous sub-step. */
-tlim_status tlim_set_field(tlim_ctx* ctx, int32_t field, const double* src_dev);
+/* Copy a field (Sec. 3.4, the data of Algorithm 1) from caller device
+ * memory into the context: nx*ny*nz values in the layout of the conventions,
+ * of type dtype (TLIM_DTYPE_F64, or TLIM_DTYPE_F32, widened to the state's
+ * float64 on the device).  Sources are optional (absent = 0); velocity is
+ * needed only for the viscous sub-step.  Errors: TLIM_E_ARG for an unknown
+ * field or dtype or a NULL pointer (nothing changed), TLIM_E_STATE without a
+ * workspace. */
+tlim_status tlim_set_field(tlim_ctx* ctx, int32_t field, const void* src_dev, int32_t dtype);
 
-/* Copy a field out of the context into caller device memory (a pending
- * pipelined step is completed first, see tlim_advance). */
-tlim_status tlim_get_field(tlim_ctx* ctx, int32_t field, double* dst_dev);
+/* Copy a field out of the context into caller device memory of type dtype
+ * (float64, or rounded to float32 on the device); a pending pipelined step
+ * is completed first (see tlim_advance_parabolic).  Errors: TLIM_E_ARG as
+ * for tlim_set_field, TLIM_E_STATE for a field that is not set. */
+tlim_status tlim_get_field(tlim_ctx* ctx, int32_t field, void* dst_dev, int32_t dtype);
 
 /* Mark an optional field (TLIM_U, TLIM_V, TLIM_W, TLIM_SRC1, TLIM_SRC2,
  * TLIM_E) as not set: absent sources are zero again and the total energy is
@@ -239,9 +253,9 @@ tlim_status tlim_spectral_bound(tlim_ctx* ctx, int32_t face_mean, double alpha_e
  * non-positive temperature of the checked step is returned by that call as
  * TLIM_E_NUMERIC.  Every other entry point, and tlim_finish, completes the
  * pending step first. */
-tlim_status tlim_advance(tlim_ctx* ctx, const tlim_step_opts* opts, tlim_step_report* report);
+tlim_status tlim_advance_parabolic(tlim_ctx* ctx, const tlim_step_opts* opts, tlim_step_report* report);
 
-/* Complete a pending pipelined step (see tlim_advance): wait for its
+/* Complete a pending pipelined step (see tlim_advance_parabolic): wait for its
  * readback, redo it if its schedule was mispredicted, and return its status
  * (TLIM_OK when nothing is pending).  Synchronises. */
 tlim_status tlim_finish(tlim_ctx* ctx);
@@ -251,13 +265,19 @@ tlim_status tlim_finish(tlim_ctx* ctx);
  * n % ckpt_every == 0 (so ckpt_dev holds ceil(nsteps/ckpt_every) fields),
  * and lambda_max of every pass goes to lam_out[n * passes + it] (host).
  * Requires equal p_inf of the two phases, no sources, no viscous part, no
- * cycle mode, picard_tol = 0.  Relaxation is applied by tlim_advance as usual. */
+ * cycle mode, picard_tol = 0.  Relaxation is applied by tlim_advance_parabolic as usual. */
 tlim_status tlim_forward_checkpointed(tlim_ctx* ctx, const tlim_step_opts* opts, int32_t nsteps,
                                       int32_t ckpt_every, double* ckpt_dev, double* lam_out);
 
-/* Device scratch the adjoint needs for a schedule whose largest P is Pmax. */
-tlim_status tlim_adjoint_workspace_bytes(const tlim_ctx* ctx, const tlim_step_opts* opts,
-                                         int32_t Pmax, size_t* bytes);
+/* Device scratch tlim_adjoint_parabolic needs for nsteps steps of the frozen
+ * schedule lam (nsteps*passes host values, as written by
+ * tlim_forward_checkpointed): every stage iterate of one step's passes, whose
+ * count follows from the largest P = ceil(pi/4 sqrt(dt lam + 1)) of the
+ * schedule (Sec. 3.2, eq. LIM).  Errors: TLIM_E_ARG for NULL pointers,
+ * nsteps < 1, passes out of range, dt not finite and > 0, or a schedule
+ * entry that is negative or not finite. */
+tlim_status tlim_adjoint_workspace_bytes(const tlim_ctx* ctx, const tlim_step_opts* opts, int32_t nsteps,
+                                         const double* lam, size_t* bytes);
 
 /* Discrete adjoint of nsteps heat steps with the frozen schedule lam
  * (nsteps*passes host values, as written by tlim_forward_checkpointed):
@@ -272,7 +292,7 @@ tlim_status tlim_adjoint_workspace_bytes(const tlim_ctx* ctx, const tlim_step_op
  * tlim_forward_checkpointed.  The recomputation and the reverse stages run
  * in FP64 also in FP32 contexts: the result is the gradient of the FP64
  * discretisation at the checkpointed states.  Synchronises. */
-tlim_status tlim_adjoint(tlim_ctx* ctx, const tlim_step_opts* opts, int32_t nsteps, int32_t ckpt_every,
+tlim_status tlim_adjoint_parabolic(tlim_ctx* ctx, const tlim_step_opts* opts, int32_t nsteps, int32_t ckpt_every,
                          const double* ckpt_dev, const double* lam, const double* dL_dTN_dev,
                          double* dL_dT0_dev, double* dL_dk0, void* adj_ws_dev, size_t adj_ws_bytes);
 

@@ -247,6 +247,7 @@ struct Step2D {
     const double* chat;  // b/lambda of P at chat + (P-1)^2, P = 1..pmax
     int pmax;
     int passes;
+    unsigned spin_limit;  // polls a barrier wait may take before it counts a time-out
 };
 // Tiles the whole-step kernel uses on grid g (0 if it does not apply: fewer
 // than 128 rows, or more tiles than can be resident at once).
@@ -257,5 +258,7 @@ bool launch_step2d(hipStream_t s, const DevGrid& g, const DevPhases& ph, double 
 
 void launch_fill(hipStream_t s, double* p, double v, int64_t n);
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n);
+void launch_widen(hipStream_t s, double* dst, const float* src, int64_t n);
+void launch_narrow(hipStream_t s, float* dst, const double* src, int64_t n);
 
 }  // namespace tlim

@@ -722,6 +722,13 @@ __global__ void __launch_bounds__(256) k_copy(double* __restrict__ d, const doub
         d[a] = s[a];
 }
 
+// Field copies between the caller's precision and the state's float64.
+template <typename To, typename From>
+__global__ void __launch_bounds__(256) k_convert(To* __restrict__ d, const From* __restrict__ s, int64_t n) {
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x)
+        d[a] = (To)s[a];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launches
@@ -862,6 +869,14 @@ void launch_fill(hipStream_t s, double* p, double v, int64_t n) {
 
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n) {
     hipLaunchKernelGGL(k_copy, dim3(pointwise_blocks(n)), dim3(256), 0, s, dst, src, n);
+}
+
+void launch_widen(hipStream_t s, double* dst, const float* src, int64_t n) {
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(pointwise_blocks(n)), dim3(256), 0, s, dst, src, n);
+}
+
+void launch_narrow(hipStream_t s, float* dst, const double* src, int64_t n) {
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(pointwise_blocks(n)), dim3(256), 0, s, dst, src, n);
 }
 
 }  // namespace tlim

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -114,6 +115,9 @@ struct tlim_ctx {
     bool t2_alias;
     int64_t predict_misses;
     int64_t pipelined_steps, pipeline_redos;
+    // Polls a grid-barrier wait of the whole-step kernel may take before it
+    // counts a time-out (about a second by default).
+    unsigned step2d_spin_limit;
     std::string err;
 };
 
@@ -136,6 +140,22 @@ tlim_status fail(tlim_ctx* c, tlim_status s, const char* fmt, ...) {
         hipError_t e_ = (expr);                                                                 \
         if (e_ != hipSuccess) return fail((c), TLIM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
+
+// A grid-barrier wait of the whole-step kernel timed out.  Workgroups that
+// stopped waiting may have written a pass's T^(it+1) into the T1 field while
+// another workgroup had not yet read it for its relaxation, so neither the
+// step's result nor its relaxed start can be trusted.  Wait for everything
+// enqueued (a pipelined step after it included), drop it, and mark the
+// fields the heat step writes (alpha2, T1, T2) as not set: the next call
+// that needs them returns TLIM_E_STATE until the caller sets them again.
+tlim_status lose_heat_state(tlim_ctx* c) {
+    (void)hipStreamSynchronize(c->stream);
+    c->pending = false;
+    c->next_ready = false;
+    c->t2_alias = false;
+    c->fset[TLIM_ALPHA2] = c->fset[TLIM_T1] = c->fset[TLIM_T2] = false;
+    return fail(c, TLIM_E_HIP, "whole-step kernel: barrier time-out; alpha2, T1 and T2 are lost and must be set again");
+}
 
 // Layout of the workspace: byte offsets of every array (all 256-aligned).
 struct Layout {
@@ -951,6 +971,13 @@ tlim_status tlim_create(const tlim_grid* grid, int32_t precision, void* hip_stre
     c->res_host_dev = c->res_blk_dev[0];
     c->clean_rows = c->clean_keep = 0;
     c->pending = false;
+    c->step2d_spin_limit = 1u << 20;
+    if (const char* e = std::getenv("TLIM_STEP2D_SPIN_LIMIT")) {
+        // test hook: a small limit forces the time-out path from the host
+        char* end = nullptr;
+        const unsigned long v = std::strtoul(e, &end, 10);
+        if (end != e && v <= 0xffffffffUL) c->step2d_spin_limit = (unsigned)v;
+    }
     for (int i = 0; i < kMaxEvents; ++i) {
         if (hipEventCreate(&c->ev[i]) != hipSuccess) {
             for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->ev[j]);
@@ -1070,31 +1097,39 @@ tlim_status tlim_set_phase(tlim_ctx* c, int32_t k, const tlim_phase* p) {
     return TLIM_OK;
 }
 
-tlim_status tlim_set_field(tlim_ctx* c, int32_t f, const double* src) {
+tlim_status tlim_set_field(tlim_ctx* c, int32_t f, const void* src, int32_t dtype) {
     if (!c) return TLIM_E_ARG;
+    if (f < 0 || f >= TLIM_NFIELDS || !src) return fail(c, TLIM_E_ARG, "bad field index or NULL source");
+    if (dtype != TLIM_DTYPE_F64 && dtype != TLIM_DTYPE_F32) return fail(c, TLIM_E_ARG, "unknown dtype %d", dtype);
     tlim_status pst = resolve(c);
     if (pst) return pst;
     c->next_ready = false;  // the state or the laws change
-    if (f < 0 || f >= TLIM_NFIELDS || !src) return fail(c, TLIM_E_ARG, "bad field index or NULL source");
     if (!c->ws) return fail(c, TLIM_E_STATE, "no workspace bound");
     if (c->t2_alias && (f == TLIM_T1 || f == TLIM_T2)) {
         // give T2 its own values again before either temperature changes
         tlim::launch_copy(c->stream, c->field[TLIM_T2], c->field[TLIM_T1], c->N);
         c->t2_alias = false;
     }
-    HIP_TRY(c, hipMemcpyAsync(c->field[f], src, sizeof(double) * (size_t)c->N, hipMemcpyDeviceToDevice, c->stream));
+    if (dtype == TLIM_DTYPE_F64)
+        HIP_TRY(c, hipMemcpyAsync(c->field[f], src, sizeof(double) * (size_t)c->N, hipMemcpyDeviceToDevice, c->stream));
+    else
+        tlim::launch_widen(c->stream, c->field[f], (const float*)src, c->N);
     c->fset[f] = true;
     return TLIM_OK;
 }
 
-tlim_status tlim_get_field(tlim_ctx* c, int32_t f, double* dst) {
+tlim_status tlim_get_field(tlim_ctx* c, int32_t f, void* dst, int32_t dtype) {
     if (!c) return TLIM_E_ARG;
+    if (f < 0 || f >= TLIM_NFIELDS || !dst) return fail(c, TLIM_E_ARG, "bad field index or NULL destination");
+    if (dtype != TLIM_DTYPE_F64 && dtype != TLIM_DTYPE_F32) return fail(c, TLIM_E_ARG, "unknown dtype %d", dtype);
     tlim_status pst = resolve(c);
     if (pst) return pst;
-    if (f < 0 || f >= TLIM_NFIELDS || !dst) return fail(c, TLIM_E_ARG, "bad field index or NULL destination");
     if (!c->ws || !c->fset[f]) return fail(c, TLIM_E_STATE, "field %d not set", f);
     const double* src = f == TLIM_T2 ? T2_ptr(c) : c->field[f];
-    HIP_TRY(c, hipMemcpyAsync(dst, src, sizeof(double) * (size_t)c->N, hipMemcpyDeviceToDevice, c->stream));
+    if (dtype == TLIM_DTYPE_F64)
+        HIP_TRY(c, hipMemcpyAsync(dst, src, sizeof(double) * (size_t)c->N, hipMemcpyDeviceToDevice, c->stream));
+    else
+        tlim::launch_narrow(c->stream, (float*)dst, src, c->N);
     return TLIM_OK;
 }
 
@@ -1273,6 +1308,7 @@ bool step2d_enqueue(tlim_ctx* c, const tlim_step_opts* o, PassResult* res) {
     st.chat = c->chat_tab;
     st.pmax = kStepPmax;
     st.passes = o->passes;
+    st.spin_limit = c->step2d_spin_limit;
     if (!tlim::launch_step2d(s, g, dev_phases(c), o->alpha_eps, o->dt, o->face_mean, st)) return false;
     c->next_ready = false;
     c->Tn = Tn;
@@ -1320,7 +1356,7 @@ tlim_status step2d_sync(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* 
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     Step2DResult r;
     step2d_result(c->res_host, o->passes, r);
-    if (r.timeout) return fail(c, TLIM_E_HIP, "whole-step kernel: barrier time-out");
+    if (r.timeout) return lose_heat_state(c);
     if (r.out_of_range) {
         // schedule beyond the table: the passes again, one launch per block of stages
         out = HeatOutcome{};
@@ -1608,7 +1644,7 @@ Verdict verify(tlim_ctx* c, const tlim_ctx::Pending& p) {
         Step2DResult r;
         step2d_result(res, np, r);
         if (r.timeout) {
-            v.st = fail(c, TLIM_E_HIP, "whole-step kernel: barrier time-out");
+            v.st = lose_heat_state(c);
             return v;
         }
         v.mispredicted = r.out_of_range;  // redone with one launch per block of stages
@@ -1659,7 +1695,7 @@ tlim_status resolve(tlim_ctx* c) {
 
 }  // namespace
 
-tlim_status tlim_advance(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep) {
+tlim_status tlim_advance_parabolic(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep) {
     if (!c) return TLIM_E_ARG;
     tlim_status st = check_opts(c, o);
     if (st) return st;
@@ -1839,20 +1875,28 @@ tlim_status tlim_forward_checkpointed(tlim_ctx* c, const tlim_step_opts* o, int3
         if (n % ckpt_every == 0)
             tlim::launch_copy(c->stream, ckpt_dev + (size_t)(n / ckpt_every) * (size_t)c->N, c->field[TLIM_T1], c->N);
         tlim_step_report rep;
-        st = tlim_advance(c, o, &rep);
+        st = tlim_advance_parabolic(c, o, &rep);
         if (st) return st;
         for (int it = 0; it < o->passes; ++it) lam_out[(size_t)n * o->passes + it] = rep.lambda_G[it];
     }
     return TLIM_OK;
 }
 
-tlim_status tlim_adjoint_workspace_bytes(const tlim_ctx* c, const tlim_step_opts* o, int32_t Pmax, size_t* bytes) {
-    if (!c || !o || !bytes || Pmax < 1 || o->passes < 1 || o->passes > TLIM_MAX_PASSES) return TLIM_E_ARG;
+tlim_status tlim_adjoint_workspace_bytes(const tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps,
+                                         const double* lam, size_t* bytes) {
+    if (!c || !o || !bytes || !lam || nsteps < 1 || o->passes < 1 || o->passes > TLIM_MAX_PASSES ||
+        !(o->dt > 0.0) || !std::isfinite(o->dt))
+        return TLIM_E_ARG;
+    int Pmax = 1;
+    for (int k = 0; k < nsteps * o->passes; ++k) {
+        if (!(lam[k] >= 0.0) || !std::isfinite(lam[k])) return TLIM_E_ARG;
+        Pmax = std::max(Pmax, lim_P(o->dt, lam[k]));
+    }
     *bytes = adj_layout(c->N, o->passes, Pmax).total;
     return TLIM_OK;
 }
 
-tlim_status tlim_adjoint(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, int32_t ckpt_every,
+tlim_status tlim_adjoint_parabolic(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, int32_t ckpt_every,
                          const double* ckpt_dev, const double* lam, const double* dL_dTN_dev, double* dL_dT0_dev,
                          double* dL_dk0, void* adj_ws_dev, size_t adj_ws_bytes) {
     if (!c) return TLIM_E_ARG;

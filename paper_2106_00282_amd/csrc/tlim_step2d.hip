@@ -24,7 +24,7 @@
 // All workgroups take the same branches (P comes from the same reduced
 // lambda_G), so every one reaches every barrier.  The barrier waits are
 // bounded: a workgroup that waits too long adds 1 to the flag row and goes
-// on, and the host discards the step.
+// on; the host then treats the step as lost (alpha2, T1 and T2 must be set again).
 // Data one workgroup writes and another reads within the launch (relaxed
 // alpha2, 1/C, the exchange arrays, the pass results, the reduction rows)
 // moves by device-coherent loads and stores, so a barrier needs no cache
@@ -54,7 +54,6 @@ constexpr int NW = 16;          // waves per workgroup
 constexpr int EY = NW * ROWS;   // rows of the extended tile
 constexpr int kHmin = 4, kHmax = 12;
 constexpr double kPiQuarter = 3.14159265358979323846 / 4.0;
-constexpr unsigned kSpinLimit = 1u << 20;  // barrier wait polls (about a second)
 
 struct StepArgs {
     DevPhases ph;
@@ -86,7 +85,7 @@ __device__ __forceinline__ int fresh(int x) {
 // wave of every workgroup then polls all arrival words until each holds at
 // least g.  No word is written by more than one workgroup, so arrivals do not
 // queue on one address.
-__device__ void grid_barrier(unsigned* bar, unsigned g, double* flag) {
+__device__ void grid_barrier(unsigned* bar, unsigned g, double* flag, unsigned limit) {
     __builtin_amdgcn_s_waitcnt(0);  // this wave's coherent stores have landed
     __syncthreads();
     const unsigned nblk = gridDim.x;
@@ -100,7 +99,7 @@ __device__ void grid_barrier(unsigned* bar, unsigned g, double* flag) {
                 here = here && __hip_atomic_load(bar + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= g;
             if (__all(here)) break;
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit) {
+            if (++spins > limit) {
                 if (lane == 0) atomicAdd(flag, 1.0);
                 break;
             }
@@ -218,7 +217,7 @@ __global__ void __launch_bounds__(64 * NW, 4) k_step2d(StepArgs a) {
         }
         build(L, rc, a.st.acc + (size_t)tgt_lam(0) * kSlots, true);
     }
-    grid_barrier(a.st.bar, ++nbar, flag);
+    grid_barrier(a.st.bar, ++nbar, flag, a.st.spin_limit);
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) v[r] = sG[wv * ROWS + r][lane];
 
@@ -291,7 +290,7 @@ __global__ void __launch_bounds__(64 * NW, 4) k_step2d(StepArgs a) {
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r)
                     if (out_cell(r)) cstore(xa + out_idx(r), v[r]);
-                grid_barrier(a.st.bar, ++nbar, flag);
+                grid_barrier(a.st.bar, ++nbar, flag, a.st.spin_limit);
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r)
                     if (!out_cell(r)) v[r] = cload(xa + cell_idx(r));
@@ -344,7 +343,7 @@ __global__ void __launch_bounds__(64 * NW, 4) k_step2d(StepArgs a) {
                     rc[r] = a.st.rC[idx];
                 }
                 build(L, rc, a.st.acc + (size_t)tgt_lam(it + 1) * kSlots, false);
-                grid_barrier(a.st.bar, ++nbar, flag);
+                grid_barrier(a.st.bar, ++nbar, flag, a.st.spin_limit);
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r) {
                     if (!out_cell(r)) {

@@ -7,8 +7,10 @@ library is missing or no HIP device is present, construction fails.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass, field as dc_field
 from typing import Optional, Sequence
 
@@ -20,6 +22,8 @@ LIB_PATH = os.path.join(HERE, "libtlim.so")
 OK, E_ARG, E_STATE, E_HIP, E_NOMEM, E_NOCONV, E_NUMERIC = range(7)
 PERIODIC, ADIABATIC = 0, 1
 FP64, FP32 = 0, 1
+DTYPE_F64, DTYPE_F32 = 0, 1  # element type of a field buffer (tlim_set_field / tlim_get_field)
+_DTYPES = {torch.float64: DTYPE_F64, torch.float32: DTYPE_F32}
 ORDER_INTERLEAVED, ORDER_PAPER, ORDER_ASCENDING = 0, 1, 2
 FACE_ARITH, FACE_HARMONIC = 0, 1
 WHOLE_AUTO, WHOLE_ALWAYS, WHOLE_NEVER = 0, 1, 2
@@ -29,8 +33,8 @@ MAX_PASSES = 64
 
 EXPORTED = ("tlim_create", "tlim_destroy", "tlim_workspace_bytes", "tlim_bind_workspace",
             "tlim_set_phase", "tlim_set_field", "tlim_get_field", "tlim_clear_field", "tlim_spectral_bound",
-            "tlim_advance", "tlim_finish", "tlim_forward_checkpointed", "tlim_adjoint_workspace_bytes",
-            "tlim_adjoint", "tlim_advance_hyperbolic", "tlim_hyperbolic_dt", "tlim_status_str",
+            "tlim_advance_parabolic", "tlim_finish", "tlim_forward_checkpointed", "tlim_adjoint_workspace_bytes",
+            "tlim_adjoint_parabolic", "tlim_advance_hyperbolic", "tlim_hyperbolic_dt", "tlim_status_str",
             "tlim_last_error")
 
 
@@ -78,6 +82,19 @@ class ReportC(C.Structure):
 
 
 _lib = None
+# Contexts still open when the interpreter exits are closed by the atexit
+# hook below, while the HIP runtime and torch are still fully alive, rather
+# than by __del__ during module teardown.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts():
+    for s in list(_live):
+        try:
+            s.close()
+        except Exception:
+            pass
 
 
 def load_library(path: str = LIB_PATH):
@@ -95,15 +112,15 @@ def load_library(path: str = LIB_PATH):
     L.tlim_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
     L.tlim_bind_workspace.argtypes = [vp, vp, C.c_size_t]
     L.tlim_set_phase.argtypes = [vp, C.c_int32, C.POINTER(Phase)]
-    L.tlim_set_field.argtypes = [vp, C.c_int32, vp]
-    L.tlim_get_field.argtypes = [vp, C.c_int32, vp]
+    L.tlim_set_field.argtypes = [vp, C.c_int32, vp, C.c_int32]
+    L.tlim_get_field.argtypes = [vp, C.c_int32, vp, C.c_int32]
     L.tlim_clear_field.argtypes = [vp, C.c_int32]
     L.tlim_spectral_bound.argtypes = [vp, C.c_int32, C.c_double, dp]
-    L.tlim_advance.argtypes = [vp, C.POINTER(StepOptsC), C.POINTER(ReportC)]
+    L.tlim_advance_parabolic.argtypes = [vp, C.POINTER(StepOptsC), C.POINTER(ReportC)]
     L.tlim_finish.argtypes = [vp]
     L.tlim_forward_checkpointed.argtypes = [vp, C.POINTER(StepOptsC), C.c_int32, C.c_int32, vp, dp]
-    L.tlim_adjoint_workspace_bytes.argtypes = [vp, C.POINTER(StepOptsC), C.c_int32, C.POINTER(C.c_size_t)]
-    L.tlim_adjoint.argtypes = [vp, C.POINTER(StepOptsC), C.c_int32, C.c_int32, vp, dp, vp, vp, dp, vp,
+    L.tlim_adjoint_workspace_bytes.argtypes = [vp, C.POINTER(StepOptsC), C.c_int32, dp, C.POINTER(C.c_size_t)]
+    L.tlim_adjoint_parabolic.argtypes = [vp, C.POINTER(StepOptsC), C.c_int32, C.c_int32, vp, dp, vp, vp, dp, vp,
                                C.c_size_t]
     L.tlim_status_str.restype = C.c_char_p
     L.tlim_advance_hyperbolic.argtypes = [vp, C.POINTER(HypOptsC), C.POINTER(HypReportC)]
@@ -198,6 +215,7 @@ class Solver:
             self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
             self._check(L.tlim_bind_workspace(ctx, C.c_void_p(self.workspace.data_ptr()), nbytes.value))
         self._adj_ws = None
+        _live.add(self)
 
     # -------------------------------------------------------------- basics
     def _check(self, st):
@@ -207,9 +225,20 @@ class Solver:
             raise TlimError(st, f"{L.tlim_status_str(st).decode()}: {msg}")
 
     def close(self):
+        """Destroy the context (completing a pending step) and drop the
+        workspace; the Solver is unusable afterwards."""
         if getattr(self, "_ctx", None):
             load_library().tlim_destroy(self._ctx)
             self._ctx = None
+            self.workspace = None
+            self._adj_ws = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:
@@ -227,24 +256,30 @@ class Solver:
         self._check(load_library().tlim_set_phase(self._ctx, int(k), C.byref(ph)))
 
     def _dev(self, t) -> torch.Tensor:
-        t = torch.as_tensor(t, dtype=torch.float64)
+        t = torch.as_tensor(t)
+        if t.dtype not in _DTYPES:
+            t = t.to(torch.float64)
         t = t.to(self.device).contiguous()
         if t.numel() != self.N:
             raise ValueError(f"field has {t.numel()} values, grid has {self.N}")
         return t
 
     def set_field(self, name: str, values):
+        """Copy a field in (float64 or float32 values; other types are
+        converted to float64 first)."""
         t = self._dev(values)
-        self._check(load_library().tlim_set_field(self._ctx, FIELDS[name], C.c_void_p(t.data_ptr())))
+        self._check(load_library().tlim_set_field(self._ctx, FIELDS[name], C.c_void_p(t.data_ptr()),
+                                                  _DTYPES[t.dtype]))
         self.stream.synchronize()
 
     def clear_field(self, name: str) -> None:
         """Mark an optional field (u, v, w, src1, src2, E) as not set."""
         self._check(load_library().tlim_clear_field(self._ctx, FIELDS[name]))
 
-    def get_field(self, name: str) -> torch.Tensor:
-        out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
-        self._check(load_library().tlim_get_field(self._ctx, FIELDS[name], C.c_void_p(out.data_ptr())))
+    def get_field(self, name: str, dtype=torch.float64) -> torch.Tensor:
+        out = torch.empty(self.shape, dtype=dtype, device=self.device)
+        self._check(load_library().tlim_get_field(self._ctx, FIELDS[name], C.c_void_p(out.data_ptr()),
+                                                  _DTYPES[dtype]))
         self.stream.synchronize()
         return out
 
@@ -253,7 +288,7 @@ class Solver:
         for k in range(2):
             self.set_phase(k, wl["phases"][k])
         for name, arr in wl["fields"].items():
-            self.set_field(name, torch.from_numpy(arr))
+            self.set_field(name, torch.tensor(arr))
 
     # ------------------------------------------------------------ stepping
     def spectral_bound(self, face_mean: int = FACE_ARITH, alpha_eps: float = 1e-10) -> float:
@@ -264,7 +299,7 @@ class Solver:
     def advance(self, opts: StepOpts, report: bool = True):
         rep = ReportC()
         oc = opts.c()
-        st = load_library().tlim_advance(self._ctx, C.byref(oc), C.byref(rep) if report else None)
+        st = load_library().tlim_advance_parabolic(self._ctx, C.byref(oc), C.byref(rep) if report else None)
         if st not in (OK, E_NOCONV, E_NUMERIC):
             self._check(st)
         return st, (_report(rep) if report else None)
@@ -288,7 +323,7 @@ class Solver:
         """Advance with a prepared options struct and no report (timing
         loops).  Predicted steps may stay pending (pipelined): finish()
         completes them."""
-        return load_library().tlim_advance(self._ctx, C.byref(oc), None)
+        return load_library().tlim_advance_parabolic(self._ctx, C.byref(oc), None)
 
     def finish(self) -> int:
         """Complete a pending pipelined step; returns its status."""
@@ -307,17 +342,15 @@ class Solver:
     def adjoint(self, opts: StepOpts, nsteps: int, ckpt_every: int, ckpt: torch.Tensor, lam, dL_dTN):
         L = load_library()
         lam_arr = (C.c_double * len(lam))(*[float(x) for x in lam])
-        import math
-        Pmax = max(int(math.ceil(math.pi / 4 * math.sqrt(opts.dt * x + 1.0))) for x in lam)
         oc = opts.c()
         nbytes = C.c_size_t()
-        self._check(L.tlim_adjoint_workspace_bytes(self._ctx, C.byref(oc), Pmax, C.byref(nbytes)))
+        self._check(L.tlim_adjoint_workspace_bytes(self._ctx, C.byref(oc), nsteps, lam_arr, C.byref(nbytes)))
         if self._adj_ws is None or self._adj_ws.numel() < nbytes.value:
             self._adj_ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         g = self._dev(dL_dTN)
         out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         dk0 = (C.c_double * 2)()
-        self._check(L.tlim_adjoint(self._ctx, C.byref(oc), nsteps, ckpt_every, C.c_void_p(ckpt.data_ptr()),
+        self._check(L.tlim_adjoint_parabolic(self._ctx, C.byref(oc), nsteps, ckpt_every, C.c_void_p(ckpt.data_ptr()),
                                    lam_arr, C.c_void_p(g.data_ptr()), C.c_void_p(out.data_ptr()), dk0,
                                    C.c_void_p(self._adj_ws.data_ptr()), self._adj_ws.numel()))
         return out, [dk0[0], dk0[1]]
@@ -329,7 +362,7 @@ class ParabolicRun(torch.autograd.Function):
     forward(T0, k0, solver, opts, nsteps, ckpt_every, phases): sets k0 of both
     phases and T1 = T2 = T0 on ``solver`` (whose alpha2, m1, m2 are already
     set), runs the checkpointed forward and returns T^N.  backward recomputes
-    each step from its checkpoint and reverses it (tlim_adjoint)."""
+    each step from its checkpoint and reverses it (tlim_adjoint_parabolic)."""
 
     @staticmethod
     def forward(ctx, T0, k0, solver: Solver, opts: StepOpts, nsteps: int, ckpt_every: int, phases):

@@ -213,24 +213,27 @@ def levelset2d_adjoint(n: int = 2048, steps: int = 20):
                    steps, 3, extra=dict(target_k0_scale=1.1, fd_cells=np.sort(probe)))
 
 
-def bubbles3d(n: int = 256, steps: int = 5, nbubbles: int = 20):
-    """3D periodic bubbles with temperature jumps and velocity, plus viscosity."""
+def bubbles3d(n: int = 256, steps: int = 5, nbubbles: int = 20, shape=None):
+    """3D periodic bubbles with temperature jumps and velocity, plus viscosity.
+    shape = (nx, ny, nz) gives a box of other proportions on the same unit
+    cube (spacing 1/n per axis; the interface width is 2 cells of x)."""
     phases = base_phases(k0=(1.0, 0.05), npow=2.0, mu=(1e-2, 1e-3))
     rs_c, rs_r, rs_J, rs_u = _streams(3, 4)
     centres = rs_c.uniform(0.0, 1.0, size=(nbubbles, 3))
     radii = rs_r.uniform(10.0, 30.0, size=nbubbles) / 256.0
     jumps = rs_J.uniform(1.0, 2.0, size=nbubbles)
     uvec = 0.1 * rs_u.uniform(-1.0, 1.0, size=(nbubbles, 3))
-    h = 1.0 / n
-    c = _centres(n)
-    alpha2 = np.zeros((n, n, n))
-    Tbump = np.zeros((n, n, n))
-    vel = [np.zeros((n, n, n)) for _ in range(3)]
+    nx, ny, nz = shape if shape is not None else (n, n, n)
+    h = 1.0 / nx
+    cx, cy, cz = _centres(nx), _centres(ny), _centres(nz)
+    alpha2 = np.zeros((nz, ny, nx))
+    Tbump = np.zeros((nz, ny, nx))
+    vel = [np.zeros((nz, ny, nx)) for _ in range(3)]
     for b in range(nbubbles):
         # periodic distance along each axis (z, y, x order of the array)
-        dz = np.abs(c - centres[b, 2]); dz = np.minimum(dz, 1.0 - dz)
-        dy = np.abs(c - centres[b, 1]); dy = np.minimum(dy, 1.0 - dy)
-        dx = np.abs(c - centres[b, 0]); dx = np.minimum(dx, 1.0 - dx)
+        dz = np.abs(cz - centres[b, 2]); dz = np.minimum(dz, 1.0 - dz)
+        dy = np.abs(cy - centres[b, 1]); dy = np.minimum(dy, 1.0 - dy)
+        dx = np.abs(cx - centres[b, 0]); dx = np.minimum(dx, 1.0 - dx)
         r = np.sqrt(dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2)
         s = 0.5 * (1.0 - np.tanh((r - radii[b]) / (2.0 * h)))
         np.maximum(alpha2, s, out=alpha2)
@@ -238,12 +241,14 @@ def bubbles3d(n: int = 256, steps: int = 5, nbubbles: int = 20):
         for d in range(3):
             vel[d] += uvec[b, d] * s
     T = 1.0 + Tbump
-    return _finish("bubbles3d", (n, n, n), (PERIODIC,) * 3, phases, 1.0 - alpha2, T, 200.0,
+    return _finish("bubbles3d", (nx, ny, nz), (PERIODIC,) * 3, phases, 1.0 - alpha2, T, 200.0,
                    steps, 3, vel=vel)
 
 
-def interface3d(n: int = 512, steps: int = 10, nmodes: int = 12):
-    """3D perturbed planar interface, conductivity contrast 100."""
+def interface3d(n: int = 512, steps: int = 10, nmodes: int = 12, shape=None):
+    """3D perturbed planar interface, conductivity contrast 100.  shape =
+    (nx, ny, nz) gives a box of other proportions (spacing 1/n per axis, the
+    modes stay periodic in y and z, amplitude 5 cells of x)."""
     phases = base_phases(k0=(1.0, 0.01), npow=2.0)
     rs = _streams(5, 1)[0]
     modes = []
@@ -253,21 +258,21 @@ def interface3d(n: int = 512, steps: int = 10, nmodes: int = 12):
             modes.append((m, q))
     amp = rs.uniform(0.5, 1.0, size=nmodes)
     theta = rs.uniform(0.0, 2.0 * np.pi, size=nmodes)
-    h = 1.0 / n
-    c = _centres(n)
-    y = c[:, None]
-    z = c[None, :]
-    pert = np.zeros((n, n))
+    nx, ny, nz = shape if shape is not None else (n, n, n)
+    h = 1.0 / nx
+    y = _centres(ny)[:, None]
+    z = _centres(nz)[None, :]
+    pert = np.zeros((ny, nz))
     for j, (m, q) in enumerate(modes):
         pert += amp[j] * np.cos(2.0 * np.pi * (m * y + q * z) + theta[j])
     pert *= 5.0 * h / np.abs(pert).max()
     xint = 0.5 + pert  # indexed (y, z)
-    x = c
-    alpha1 = np.empty((n, n, n))
-    for k in range(n):  # z
+    x = _centres(nx)
+    alpha1 = np.empty((nz, ny, nx))
+    for k in range(nz):
         alpha1[k] = 0.5 * (1.0 - np.tanh((x[None, :] - xint[:, k][:, None]) / (2.0 * h)))
     T = 1.0 + alpha1
-    return _finish("interface3d", (n, n, n), (ADIABATIC, PERIODIC, PERIODIC), phases, alpha1, T,
+    return _finish("interface3d", (nx, ny, nz), (ADIABATIC, PERIODIC, PERIODIC), phases, alpha1, T,
                    200.0, steps, 3)
 
 

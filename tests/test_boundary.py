@@ -19,7 +19,7 @@ def declared_symbols():
 
 def test_header_declares_the_entry_points():
     syms = declared_symbols()
-    for name in ("tlim_create", "tlim_advance", "tlim_set_field", "tlim_get_field", "tlim_adjoint"):
+    for name in ("tlim_create", "tlim_advance_parabolic", "tlim_set_field", "tlim_get_field", "tlim_adjoint_parabolic"):
         assert name in syms
 
 
@@ -63,6 +63,32 @@ def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(tlim, "_lib", None)
     with pytest.raises(ImportError):
         tlim.load_library(str(tmp_path / "missing.so"))
+
+
+def test_binding_holds_no_arithmetic_of_the_method():
+    """The Python binding marshals arguments only: it imports no maths
+    module and names no function or constant of eq. LIM's schedule
+    (P = ceil(pi/4 sqrt(tau lambda + 1)), the Chebyshev roots) or of the
+    heat step; workspace sizes come from the library."""
+    import ast
+    src = open(os.path.join(ROOT, "paper_2106_00282_amd", "tlim.py")).read()
+    tree = ast.parse(src)
+    imported = set()
+    for node in ast.walk(tree):
+        if isinstance(node, ast.Import):
+            imported |= {a.name.split(".")[0] for a in node.names}
+        elif isinstance(node, ast.ImportFrom):
+            imported.add((node.module or "").split(".")[0])
+    assert not imported & {"math", "numpy", "cmath", "scipy"}, imported
+    names = {n.attr for n in ast.walk(tree) if isinstance(n, ast.Attribute)}
+    names |= {n.id for n in ast.walk(tree) if isinstance(n, ast.Name)}
+    banned = {"sqrt", "ceil", "cos", "pi", "acos", "floor", "log", "exp", "pow"}
+    assert not names & banned, names & banned
+    # no operators beyond size bookkeeping (ctypes array types, the
+    # checkpoint count) and the unit box's default spacing h = 1/n
+    ops = [type(n.op).__name__ for n in ast.walk(tree) if isinstance(n, ast.BinOp)]
+    assert set(ops) <= {"Add", "Sub", "Mult", "FloorDiv", "Div"}, set(ops)
+    assert sum(op == "Div" for op in ops) == 1
 
 
 def test_product_does_not_import_oracle():

@@ -555,6 +555,79 @@ def test_get_set_roundtrip_and_spectral_bound():
     assert np.array_equal(s.get_field("T1").cpu().numpy(), wl["fields"]["T1"])
 
 
+def test_float32_field_buffers():
+    """tlim_set_field / tlim_get_field with float32 buffers: the state keeps
+    float64, widened exactly on the way in and rounded to nearest on the way
+    out; a step from float32 inputs equals the step from the same values
+    given in float64."""
+    import torch
+    from paper_2106_00282_amd.tlim import StepOpts
+    wl = W.levelset2d(64)
+    s = make_solver(wl)
+    T32 = torch.from_numpy(wl["fields"]["T1"]).to(torch.float32)
+    s.set_field("T1", T32)
+    s.set_field("T2", T32)
+    got = s.get_field("T1").cpu()
+    assert torch.equal(got, T32.to(torch.float64))
+    assert torch.equal(s.get_field("T2", dtype=torch.float32).cpu(), T32)
+    full = torch.from_numpy(wl["fields"]["alpha2"])
+    assert torch.equal(s.get_field("alpha2", dtype=torch.float32).cpu(), full.to(torch.float32))
+    r = make_solver(wl)
+    r.set_field("T1", T32.to(torch.float64))
+    r.set_field("T2", T32.to(torch.float64))
+    o = StepOpts(dt=1e-5, passes=2)
+    assert s.advance(o)[0] == 0 and r.advance(o)[0] == 0
+    assert torch.equal(s.get_field("T1"), r.get_field("T1"))
+
+
+def test_whole_step_barrier_timeout_loses_the_state(monkeypatch):
+    """A grid-barrier wait of the whole-step kernel that runs out (forced
+    from the host: a spin limit of 0 polls, every kernel still exits) makes
+    the step return TLIM_E_HIP and marks alpha2, T1 and T2 as not set, in
+    the synchronous path and in the pipelined one; setting the fields again
+    makes the context usable."""
+    from paper_2106_00282_amd.tlim import E_HIP, E_STATE, StepOpts, TlimError
+    wl = W.levelset2d(256)
+    tau = wl["dt_factor"] * 2.0 / make_solver(wl).spectral_bound()
+    monkeypatch.setenv("TLIM_STEP2D_SPIN_LIMIT", "0")
+    sync, piped = make_solver(wl), make_solver(wl)
+    monkeypatch.delenv("TLIM_STEP2D_SPIN_LIMIT")
+    o = StepOpts(dt=tau, passes=3, whole_step=1)
+    lost = 0
+    for _ in range(3):
+        try:
+            sync.advance(o)
+        except TlimError as e:
+            assert e.status == E_HIP and "time-out" in str(e)
+            lost += 1
+            break
+    assert lost == 1
+    with pytest.raises(TlimError) as ei:
+        sync.get_field("T1")
+    assert ei.value.status == E_STATE
+    with pytest.raises(TlimError) as ei:
+        sync.advance(o)
+    assert ei.value.status == E_STATE
+    sync.set_workload(wl)
+    # the pipelined path: the time-out is found by the call that verifies
+    st = 0
+    for _ in range(3):
+        st = piped.advance_raw(o.c())
+        if st != 0:
+            break
+    if st == 0:
+        st = piped.finish()
+    assert st == E_HIP
+    with pytest.raises(TlimError):
+        piped.get_field("alpha2")
+    piped.set_workload(wl)
+    # usable again (the spin limit is read per context: these still have 0,
+    # so take the launch-per-block path)
+    for s in (sync, piped):
+        st, rep = s.advance(StepOpts(dt=tau, passes=3, whole_step=2))
+        assert st == 0 and rep["bad_cells"] == 0
+
+
 def test_single_cell_and_two_cell_periodic():
     from oracle import oracle as orc
     for n in ((1, 1, 1), (2, 1, 1), (2, 2, 2)):
@@ -778,7 +851,7 @@ def test_autograd_function_vs_central_fd():
         Tm.view(-1)[c] -= hstep
         fd = (fwd_loss(Tp, k0.detach()) - fwd_loss(Tm, k0.detach())) / (2 * hstep)
         g = float(T0.grad.view(-1)[c])
-        assert g == pytest.approx(fd, rel=1e-6, abs=1e-8 * float(T0.grad.abs().max()))
+        assert g == pytest.approx(fd, rel=1e-6, abs=1e-9 * float(T0.grad.abs().max()))
     for k in range(2):
         hstep = 1e-4 * float(k0[k])
         kp, km = k0.detach().clone(), k0.detach().clone()
@@ -859,7 +932,7 @@ def test_adjoint_full_size_2048_fd():
     for c in wl["fd_cells"]:
         h = 1e-3 * float(base.view(-1)[int(c)])
         fd = (4 * fd_cell(int(c), h / 2) - fd_cell(int(c), h)) / 3
-        assert float(dT0.view(-1)[int(c)]) == pytest.approx(fd, rel=1e-6, abs=1e-8 * gmax), c
+        assert float(dT0.view(-1)[int(c)]) == pytest.approx(fd, rel=1e-6, abs=1e-9 * gmax), c
     for k in range(2):
         h = 1e-3 * k0[k]
         fd = (4 * fd_k0(k, h / 2) - fd_k0(k, h)) / 3
