@@ -449,6 +449,8 @@ def main():
                     help="run only the hyperbolic measurement and print its JSON (for profiling that path)")
     ap.add_argument("--copy-only", action="store_true",
                     help="run only the 1 GiB copy and print its bandwidth (counter calibration)")
+    ap.add_argument("--c3-only", action="store_true",
+                    help="run only the 256^3 bubbles measurement and print its JSON (for profiling)")
     ap.add_argument("--c5-only", action="store_true",
                     help="run only the 512^3 interface measurement and print its JSON (for profiling)")
     ap.add_argument("--workload", choices=("levelset2d", "levelset2d_spitzer"), default="levelset2d",
@@ -471,6 +473,9 @@ def main():
         return
     if args.copy_only:
         print(json.dumps({"copy_peak_GBs": copy_peak()}), flush=True)
+        return
+    if args.c3_only:
+        print(json.dumps(bubbles3d_rate(steps=args.steps)), flush=True)
         return
     if args.c5_only:
         print(json.dumps(interface3d_rate(n=args.c5_n, steps=args.steps)), flush=True)
