@@ -231,6 +231,26 @@ tlim_status tlim_clear_field(tlim_ctx* ctx, int32_t field);
  * changed.  The explicit stability limit is 2 / lambda_G.  Synchronises. */
 tlim_status tlim_spectral_bound(tlim_ctx* ctx, int32_t face_mean, double alpha_eps, double* lambda_out);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops and harnesses that forbid hipMalloc): the value tlim_spectral_bound
+ * returns, with no context, no workspace and no allocation of any kind.
+ * Inputs are the caller's device fields alpha2, m1, m2, T1, T2 (dense
+ * float64, layout of the conventions) on the grid `grid` with the two
+ * phases `phases` (checked as tlim_create and tlim_set_phase check them);
+ * the bound is written to lambda_dev[0] (device memory) on hip_stream (NULL
+ * = the null stream) and nothing synchronises.  The current device must be
+ * the one that holds the fields.
+ * Scratch: a library-owned device array of 256 doubles (2 KiB) per device,
+ * held until the process ends; every call clears it first with a kernel.
+ * Calls that overlap on one device race on it.  Limit: at most 2^31 - 1
+ * cells (larger grids return TLIM_E_ARG).  Errors: TLIM_E_ARG (nothing
+ * launched), TLIM_E_HIP; tlim_last_error(NULL) gives the reason of the
+ * calling thread's last failing call. */
+tlim_status tlim_spectral_bound_noalloc(const tlim_grid* grid, const tlim_phase phases[2], int32_t face_mean,
+                                        double alpha_eps, const double* alpha2_dev, const double* m1_dev,
+                                        const double* m2_dev, const double* T1_dev, const double* T2_dev,
+                                        double* lambda_dev, void* hip_stream);
+
 /* Advance the fields by one parabolic step: viscous part (optional),
  * temperature relaxation, Picard loop of LIM passes (Algorithm 1).
  * report may be NULL.  Returns TLIM_E_NOCONV when picard_tol > 0 (or the
@@ -341,7 +361,8 @@ tlim_status tlim_advance_hyperbolic(tlim_ctx* ctx, const tlim_hyp_opts* opts, tl
  * (cfl not finite or <= 0, NULL dt_out), TLIM_E_STATE. */
 tlim_status tlim_hyperbolic_dt(tlim_ctx* ctx, double cfl, double* dt_out);
 
-/* Human-readable name of a status, and the last error message of a context. */
+/* Human-readable name of a status, and the last error message of a context
+ * (with NULL: of the calling thread's last failing context-free call). */
 const char* tlim_status_str(tlim_status s);
 const char* tlim_last_error(const tlim_ctx* ctx);
 

@@ -12,6 +12,7 @@ LIB = os.path.join(HERE, "libtlim.so")
 ARCH = "gfx950"
 
 SOURCES = ["tlim_kernels.hip", "tlim_coeffs.hip", "tlim_sweep.hip", "tlim_sweep3d.hip", "tlim_step2d.hip", "tlim_adjoint.hip", "tlim_hyperbolic.hip",
+           "tlim_noalloc.hip",
            "tlim_runtime.cpp"]
 
 # Packed FP32 instructions are disabled for all device code.

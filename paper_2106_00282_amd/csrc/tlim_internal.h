@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tlim.h"
+
 namespace tlim {
 
 // Grid as the kernels see it.  w[d] = scale_d / h_d^2 is the weight of a
@@ -255,6 +257,16 @@ int step2d_tiles(const DevGrid& g);
 // Enqueue the step; false if the cooperative launch was refused (nothing ran).
 bool launch_step2d(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double tau, int face,
                    const Step2D& st);
+
+// Argument checks and packing shared by the context entry points and the
+// context-free one (tlim_runtime.cpp): NULL when valid, else the reason.
+const char* check_grid(const tlim_grid* g);
+const char* check_phase(const tlim_phase* p);
+DevPhases pack_phases(const tlim_phase ph[2]);
+DevGrid pack_grid(const tlim_grid* g);
+// Message of the last failing context-free call on the calling thread
+// (returned by tlim_last_error(NULL)).
+void set_free_error(const char* msg);
 
 void launch_fill(hipStream_t s, double* p, double v, int64_t n);
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n);

@@ -215,28 +215,7 @@ DevGrid dev_grid(const tlim_ctx* c, const double scale[3]) {
 
 const double kUnit[3] = {1.0, 1.0, 1.0};
 
-DevPhases dev_phases(const tlim_ctx* c) {
-    DevPhases p{};
-    for (int k = 0; k < 2; ++k) {
-        p.gamma[k] = c->phase[k].gamma;
-        p.pinf[k] = c->phase[k].pinf;
-        p.cv[k] = c->phase[k].cv;
-        p.qf[k] = c->phase[k].q;
-        p.k0[k] = c->phase[k].k0;
-        p.T0[k] = c->phase[k].T0;
-        p.invT0[k] = 1.0 / c->phase[k].T0;
-        p.npow[k] = c->phase[k].npow;
-        p.mu[k] = c->phase[k].mu;
-        p.sh_law[k] = c->phase[k].law == TLIM_LAW_SPITZER;
-        if (p.sh_law[k]) {
-            p.spitzer = 1;
-            p.ln_shD[k] = std::log(c->phase[k].sh_D);
-            p.ln_shLD[k] = std::log(c->phase[k].sh_LD);  // -inf for 0: that length never wins
-            p.ln_shdB[k] = std::log(c->phase[k].sh_dB);
-        }
-    }
-    return p;
-}
+DevPhases dev_phases(const tlim_ctx* c) { return tlim::pack_phases(c->phase); }
 
 // ---------------------------------------------------------------- schedule
 
@@ -909,11 +888,84 @@ tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_st
 
 // =================================================================== C ABI
 
+namespace tlim {
+
+DevPhases pack_phases(const tlim_phase ph[2]) {
+    DevPhases p{};
+    for (int k = 0; k < 2; ++k) {
+        p.gamma[k] = ph[k].gamma;
+        p.pinf[k] = ph[k].pinf;
+        p.cv[k] = ph[k].cv;
+        p.qf[k] = ph[k].q;
+        p.k0[k] = ph[k].k0;
+        p.T0[k] = ph[k].T0;
+        p.invT0[k] = 1.0 / ph[k].T0;
+        p.npow[k] = ph[k].npow;
+        p.mu[k] = ph[k].mu;
+        p.sh_law[k] = ph[k].law == TLIM_LAW_SPITZER;
+        if (p.sh_law[k]) {
+            p.spitzer = 1;
+            p.ln_shD[k] = std::log(ph[k].sh_D);
+            p.ln_shLD[k] = std::log(ph[k].sh_LD);  // -inf for 0: that length never wins
+            p.ln_shdB[k] = std::log(ph[k].sh_dB);
+        }
+    }
+    return p;
+}
+
+DevGrid pack_grid(const tlim_grid* gr) {
+    DevGrid g{};
+    g.nx = (int)gr->n[0];
+    g.ny = (int)gr->n[1];
+    g.nz = (int)gr->n[2];
+    for (int d = 0; d < 3; ++d) {
+        g.per[d] = gr->bc[d] == TLIM_PERIODIC;
+        g.w[d] = 1.0 / (gr->h[d] * gr->h[d]);
+    }
+    g.N = gr->n[0] * gr->n[1] * gr->n[2];
+    return g;
+}
+
+const char* check_grid(const tlim_grid* g) {
+    if (!g) return "grid is NULL";
+    // launch limits of the tiled kernels: ceil(ny/4) and nz blocks along y and z
+    const int64_t nmax[3] = {(int64_t)1 << 24, (int64_t)4 * 65535, 65535};
+    for (int d = 0; d < 3; ++d) {
+        if (g->n[d] < 1 || g->n[d] > nmax[d]) return "cell count out of range on an axis";
+        if (!(g->h[d] > 0.0) || !std::isfinite(g->h[d])) return "spacing must be finite and > 0";
+        if (g->bc[d] != TLIM_PERIODIC && g->bc[d] != TLIM_ADIABATIC) return "unknown boundary condition";
+    }
+    if (g->n[0] * g->n[1] * g->n[2] > ((int64_t)1 << 34)) return "more than 2^34 cells";
+    return nullptr;
+}
+
+const char* check_phase(const tlim_phase* p) {
+    if (!p) return "phase is NULL";
+    if (!(p->gamma > 1.0) || !(p->cv > 0.0) || !(p->k0 >= 0.0) || !(p->T0 > 0.0) || !(p->mu >= 0.0) ||
+        !std::isfinite(p->pinf) || !std::isfinite(p->npow))
+        return "invalid phase constants";
+    if (p->law != TLIM_LAW_POWER && p->law != TLIM_LAW_SPITZER) return "unknown conductivity law";
+    if (p->law == TLIM_LAW_SPITZER &&
+        (!(p->sh_D > 0.0) || !(p->sh_LD >= 0.0) || !(p->sh_dB >= 0.0) || !(p->sh_LD > 0.0 || p->sh_dB > 0.0) ||
+         !std::isfinite(p->sh_D) || !std::isfinite(p->sh_LD) || !std::isfinite(p->sh_dB)))
+        return "invalid Spitzer-Harm length constants";
+    return nullptr;
+}
+
+namespace {
+thread_local std::string free_error;
+}
+
+void set_free_error(const char* msg) { free_error = msg ? msg : ""; }
+
+}  // namespace tlim
+
 extern "C" {
 
 namespace {
 tlim_status resolve(tlim_ctx* c);
 }  // namespace
+
 
 const char* tlim_status_str(tlim_status s) {
     switch (s) {
@@ -928,21 +980,14 @@ const char* tlim_status_str(tlim_status s) {
     return "unknown";
 }
 
-const char* tlim_last_error(const tlim_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+const char* tlim_last_error(const tlim_ctx* c) { return c ? c->err.c_str() : tlim::free_error.c_str(); }
 
 tlim_status tlim_create(const tlim_grid* grid, int32_t precision, void* hip_stream, tlim_ctx** out) {
     if (!grid || !out) return TLIM_E_ARG;
     *out = nullptr;
-    // launch limits of the tiled kernels: ceil(ny/4) and nz blocks along y and z
-    const int64_t nmax[3] = {(int64_t)1 << 24, (int64_t)4 * 65535, 65535};
-    for (int d = 0; d < 3; ++d) {
-        if (grid->n[d] < 1 || grid->n[d] > nmax[d]) return TLIM_E_ARG;
-        if (!(grid->h[d] > 0.0) || !std::isfinite(grid->h[d])) return TLIM_E_ARG;
-        if (grid->bc[d] != TLIM_PERIODIC && grid->bc[d] != TLIM_ADIABATIC) return TLIM_E_ARG;
-    }
+    if (tlim::check_grid(grid)) return TLIM_E_ARG;
     if (precision != TLIM_FP64 && precision != TLIM_FP32) return TLIM_E_ARG;
     int64_t N = grid->n[0] * grid->n[1] * grid->n[2];
-    if (N > ((int64_t)1 << 34)) return TLIM_E_ARG;
     tlim_ctx* c = new tlim_ctx();
     for (int d = 0; d < 3; ++d) {
         c->n[d] = grid->n[d];
@@ -1084,14 +1129,7 @@ tlim_status tlim_set_phase(tlim_ctx* c, int32_t k, const tlim_phase* p) {
     if (pst) return pst;
     c->next_ready = false;  // the state or the laws change
     if (k < 0 || k > 1 || !p) return fail(c, TLIM_E_ARG, "phase index must be 0 or 1");
-    if (!(p->gamma > 1.0) || !(p->cv > 0.0) || !(p->k0 >= 0.0) || !(p->T0 > 0.0) || !(p->mu >= 0.0) ||
-        !std::isfinite(p->pinf) || !std::isfinite(p->npow))
-        return fail(c, TLIM_E_ARG, "invalid phase constants");
-    if (p->law != TLIM_LAW_POWER && p->law != TLIM_LAW_SPITZER) return fail(c, TLIM_E_ARG, "unknown conductivity law");
-    if (p->law == TLIM_LAW_SPITZER &&
-        (!(p->sh_D > 0.0) || !(p->sh_LD >= 0.0) || !(p->sh_dB >= 0.0) || !(p->sh_LD > 0.0 || p->sh_dB > 0.0) ||
-         !std::isfinite(p->sh_D) || !std::isfinite(p->sh_LD) || !std::isfinite(p->sh_dB)))
-        return fail(c, TLIM_E_ARG, "invalid Spitzer-Harm length constants");
+    if (const char* why = tlim::check_phase(p)) return fail(c, TLIM_E_ARG, "%s", why);
     c->phase[k] = *p;
     c->phase_set[k] = true;
     return TLIM_OK;

@@ -35,7 +35,7 @@ EXPORTED = ("tlim_create", "tlim_destroy", "tlim_workspace_bytes", "tlim_bind_wo
             "tlim_set_phase", "tlim_set_field", "tlim_get_field", "tlim_clear_field", "tlim_spectral_bound",
             "tlim_advance_parabolic", "tlim_finish", "tlim_forward_checkpointed", "tlim_adjoint_workspace_bytes",
             "tlim_adjoint_parabolic", "tlim_advance_hyperbolic", "tlim_hyperbolic_dt", "tlim_status_str",
-            "tlim_last_error")
+            "tlim_last_error", "tlim_spectral_bound_noalloc")
 
 
 class TlimError(RuntimeError):
@@ -128,6 +128,8 @@ def load_library(path: str = LIB_PATH):
     L.tlim_status_str.argtypes = [C.c_int]
     L.tlim_last_error.restype = C.c_char_p
     L.tlim_last_error.argtypes = [vp]
+    L.tlim_spectral_bound_noalloc.argtypes = [C.POINTER(Grid), C.POINTER(Phase), C.c_int32, C.c_double, vp, vp, vp,
+                                              vp, vp, vp, vp]
     for name in EXPORTED:
         if name != "tlim_status_str" and name != "tlim_last_error":
             getattr(L, name).restype = C.c_int
@@ -190,19 +192,12 @@ class Solver:
         if not torch.cuda.is_available():
             raise RuntimeError("tlim needs a HIP device (torch.cuda.is_available() is False)")
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        n = tuple(int(x) for x in n) + (1,) * (3 - len(n))
-        if h is None:
-            h = tuple(1.0 / x if x > 1 else 1.0 for x in n)
-        h = tuple(float(x) for x in h) + (1.0,) * (3 - len(h))
-        bc = tuple(bc) if bc is not None else (PERIODIC,) * 3
-        bc = bc + (PERIODIC,) * (3 - len(bc))
+        g = make_grid(n, h, bc)
+        n, h, bc = tuple(g.n), tuple(g.h), tuple(g.bc)
         self.n, self.h, self.bc = n, h, bc
         self.shape = (n[2], n[1], n[0])
         self.N = n[0] * n[1] * n[2]
         self.precision = FP32 if precision in ("fp32", FP32) else FP64
-        g = Grid()
-        for d in range(3):
-            g.n[d], g.h[d], g.bc[d] = n[d], h[d], bc[d]
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             ctx = C.c_void_p()
@@ -247,13 +242,8 @@ class Solver:
             pass
 
     def set_phase(self, k: int, p: dict):
-        ph = Phase()
-        for name in ("gamma", "pinf", "cv", "q", "k0", "T0", "npow", "mu"):
-            setattr(ph, name, float(p.get(name, 1.0 if name == "T0" else 0.0)))
-        ph.law = int(p.get("law", LAW_POWER))
-        for name in ("sh_D", "sh_LD", "sh_dB"):
-            setattr(ph, name, float(p.get(name, 0.0)))
-        self._check(load_library().tlim_set_phase(self._ctx, int(k), C.byref(ph)))
+        ph = make_phases([p, p])
+        self._check(load_library().tlim_set_phase(self._ctx, int(k), C.byref(ph[0])))
 
     def _dev(self, t) -> torch.Tensor:
         t = torch.as_tensor(t)
@@ -354,6 +344,53 @@ class Solver:
                                    lam_arr, C.c_void_p(g.data_ptr()), C.c_void_p(out.data_ptr()), dk0,
                                    C.c_void_p(self._adj_ws.data_ptr()), self._adj_ws.numel()))
         return out, [dk0[0], dk0[1]]
+
+
+def make_grid(n, h=None, bc=None) -> Grid:
+    """tlim_grid of n = (nx[, ny[, nz]]) cells; h defaults to the unit box's
+    spacing, bc to periodic axes."""
+    n = tuple(int(x) for x in n) + (1,) * (3 - len(n))
+    if h is None:
+        h = tuple(1.0 / x if x > 1 else 1.0 for x in n)
+    h = tuple(float(x) for x in h) + (1.0,) * (3 - len(h))
+    bc = tuple(bc) if bc is not None else (PERIODIC,) * 3
+    bc = bc + (PERIODIC,) * (3 - len(bc))
+    g = Grid()
+    for d in range(3):
+        g.n[d], g.h[d], g.bc[d] = n[d], h[d], bc[d]
+    return g
+
+
+def make_phases(phases) -> "C.Array":
+    """tlim_phase[2] from two dicts (keys of tlim_phase; missing ones 0, T0 1)."""
+    arr = (Phase * 2)()
+    for k in range(2):
+        p = phases[k]
+        for name in ("gamma", "pinf", "cv", "q", "k0", "T0", "npow", "mu"):
+            setattr(arr[k], name, float(p.get(name, 1.0 if name == "T0" else 0.0)))
+        arr[k].law = int(p.get("law", LAW_POWER))
+        for name in ("sh_D", "sh_LD", "sh_dB"):
+            setattr(arr[k], name, float(p.get(name, 0.0)))
+    return arr
+
+
+def spectral_bound_noalloc(grid: Grid, phases, alpha2, m1, m2, T1, T2, out, face_mean: int = FACE_ARITH,
+                           alpha_eps: float = 1e-10, stream=None) -> None:
+    """tlim_spectral_bound_noalloc: the bound of the relaxed fields (float64
+    device tensors, contiguous) into out[0] (a float64 device tensor), queued
+    on `stream` (default: the current stream); no allocation, no
+    synchronisation."""
+    L = load_library()
+    for t in (alpha2, m1, m2, T1, T2, out):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise TypeError("fields and out must be contiguous float64 device tensors")
+    st = stream if stream is not None else torch.cuda.current_stream(out.device)
+    ph = make_phases(phases)
+    r = L.tlim_spectral_bound_noalloc(C.byref(grid), ph, int(face_mean), float(alpha_eps),
+                                      *[C.c_void_p(t.data_ptr()) for t in (alpha2, m1, m2, T1, T2, out)],
+                                      C.c_void_p(st.cuda_stream))
+    if r != OK:
+        raise TlimError(r, f"{L.tlim_status_str(r).decode()}: {L.tlim_last_error(None).decode()}")
 
 
 class ParabolicRun(torch.autograd.Function):
