@@ -1869,15 +1869,12 @@ void adj_forward_step(tlim_ctx* c, const tlim_step_opts* o, const double* lamv, 
                     done = tlim::launch_sweeps64_keep(s, g, o->face_mean, vin(m), T0, Lam, c->rC, out, stg, k, o->dt,
                                                       st0 + (size_t)m * sf, (int64_t)sf);
                 if (done < 0) {
+                    // one stage into its own slot, by the kernel the forward
+                    // run uses for this grid (z-marching waves in 3D)
                     double* one = m + 1 == nst ? Tout : st0 + (size_t)(m + 1) * sf;
-                    if (m + 1 == nst) {
-                        tlim::launch_final64(s, g, o->face_mean, vin(m), T0, Lam, c->rC, one, o->dt, nullptr,
-                                             tlim::PassSlots{});
-                    } else {
-                        tlim::StageParam sp{nullptr, tbv[m], 0.0};
-                        tlim::launch_stage64(s, g, o->face_mean, vin(m), T0, Lam, c->rC, one, sp, o->dt);
-                    }
-                    done = 1;
+                    tlim::Stages s1{nullptr, tbv.data() + m, nullptr};
+                    done = tlim::launch_sweeps64(s, g, o->face_mean, vin(m), T0, Lam, c->rC, one, s1, 1, m + 1 == nst,
+                                                 o->dt, nullptr, tlim::PassSlots{});
                 }
                 m += done;
             }
@@ -2023,6 +2020,23 @@ tlim_status tlim_adjoint_parabolic(tlim_ctx* c, const tlim_step_opts* o, int32_t
                     pp ^= 1;
                     m -= done;
                 }
+            }
+            if (!psi_form && tlim::use_adj_z3d(g, o->face_mean)) {
+                // 3D grids: reverse stages by z-marching waves in psi form
+                tlim::launch_fill(s, dg, 0.0, N);
+                tlim::launch_fill(s, gLam, 0.0, N);
+                tlim::launch_psi_from_lambda(s, N, cur, c->rC, bufs[pp]);
+                cur = bufs[pp];
+                pp ^= 1;
+                for (int m = nst; m >= 1; --m) {
+                    const double tb = o->dt * b[m - 1];
+                    const double* vprev = m == 1 ? T0 : st0 + (size_t)(m - 1) * sf;
+                    tlim::launch_adj_z3d(s, g, cur, vprev, Lam, c->rC, bufs[pp], dg, gLam, 1.0 / (1.0 + tb), tb,
+                                         o->dt);
+                    cur = bufs[pp];
+                    pp ^= 1;
+                }
+                psi_form = true;
             }
             if (!psi_form) {
                 tlim::launch_fill(s, dg, 0.0, N);

@@ -72,6 +72,15 @@ bool use_z3d(const DevGrid& g);
 template <typename R>
 void launch_z3d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* G, const R* Lam, const R* rC, R* out,
                 StageParam sp, double tau, const double* Tit, PassSlots ps);
+// Reverse stages of the adjoint on 3D grids by z-marching waves (arithmetic
+// face means): psi_out = c_m (tb psi - tau rC A' psi) with the face gradient
+// and dL/dg accumulated in place into gLam and dgpsi (psi = C^-1 lambda;
+// launch_psi_from_lambda converts the first stage's input).
+bool use_adj_z3d(const DevGrid& g, int face);
+void launch_psi_from_lambda(hipStream_t s, int64_t n, const double* lam, const double* rC, double* psi);
+void launch_adj_z3d(hipStream_t s, const DevGrid& g, const double* psi, const double* vprev, const double* Lam,
+                    const double* rC, double* psi_out, double* dgpsi, double* gLam, double cm, double tb,
+                    double tau);
 // The FP32 correction form's final stage on a 3D grid (as launch_final32).
 void launch_z3d_final32(hipStream_t s, const DevGrid& g, int face, const float* w, const double* rhs,
                         const float* Lam32, const double* rC, double* out, double tau, const double* Tit,

@@ -288,3 +288,235 @@ template void launch_z3d<float>(hipStream_t, const DevGrid&, int, const float*, 
                                 const float*, float*, StageParam, double, const double*, PassSlots);
 
 }  // namespace tlim
+
+// ------------------------------------------------------------------ adjoint
+
+namespace tlim {
+
+namespace {
+
+// One reverse stage of the LIM adjoint on a 3D grid in psi = C^-1 lambda
+// form (arithmetic face means), marching along z like k_z3d:
+//   psi^(m-1) = c_m (tau b_m psi^(m) - tau rC sum_f w_f Lambda_f (psi_a - psi_b)),
+//   dgpsi += c_m psi^(m)_a,
+//   gLam  += c_m sum_f (tau w_f / 2) (v_b - v_a)^(m-1) (psi_a - psi_b)^(m),
+// the same operations as the blocked 2D reverse stages (tlim_adjoint.hip)
+// with the z faces added.  A wave keeps psi, v^(m-1) and Lambda of four
+// consecutive planes for its rows and the rows around them in registers.
+struct AZ3Args {
+    const double* psi;
+    const double* vprev;
+    const double* Lam;
+    const double* rC;
+    double* psi_out;
+    double* dgpsi;
+    double* gLam;
+    double cm, tb, tau;
+    int nx, ny, nz, perx, pery, perz;
+    double wx, wy, wz;
+    int tiles_x, tiles_y, zc, nwaves;
+};
+
+template <int ROWS>
+__global__ void __launch_bounds__(64 * kZWaves) k_adj_z3d(AZ3Args a) {
+    constexpr int RW = ROWS + 2;
+    const int lane = threadIdx.x & 63;
+    const int wid = blockIdx.x * kZWaves + (threadIdx.x >> 6);
+    if (wid >= a.nwaves) return;  // wave-uniform
+    const int tx = wid % a.tiles_x, rest = wid / a.tiles_x;
+    const int ty = rest % a.tiles_y, tz = rest / a.tiles_y;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int xg = tx * 64 + lane;
+    const int xi = fold(xg, nx, a.perx);
+    const int xl = fold(tx * 64 - 1, nx, a.perx), xr = fold(tx * 64 + 64, nx, a.perx);
+    const bool inx = xg < nx;
+    const bool fL = a.perx ? nx > 1 : (inx && xg > 0);
+    const bool fR = a.perx ? nx > 1 : (inx && xg < nx - 1);
+    const int y0 = ty * ROWS, z0 = tz * a.zc;
+    const int z1 = z0 + a.zc < nz ? z0 + a.zc : nz;
+    const double cm = a.cm, tb = a.tb, tf = a.tau;
+    const double wx = a.wx, wy = a.wy, wz = a.wz;
+    const double hx = 0.5 * tf * wx, hy = 0.5 * tf * wy, hz = 0.5 * tf * wz;
+
+    unsigned rowoff[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) rowoff[r] = (unsigned)fold(y0 - 1 + r, ny, a.pery) * (unsigned)nx;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const unsigned uxi = (unsigned)xi;
+    const unsigned hx_i = (unsigned)(lane == 0 ? xl : xr);
+    const bool halo_lane = lane == 0 || lane == 63;
+
+    // windows: p (psi), u (v^(m-1)), L (Lambda) of planes z-1 (m), z (c),
+    // z+1 (p), z+2 (q)
+    double pm[RW], pc[RW], pp[RW], pq[RW], um[RW], uc[RW], up_[RW], uq[RW], Lm[RW], Lc[RW], Lp[RW], Lq[RW];
+    // own cells of planes z (c) and z+1 (n): 1/C, the accumulators, and the
+    // x-halo cells of the end lanes
+    double rcc[ROWS], dgc[ROWS], glc[ROWS], rcn[ROWS], dgn[ROWS], gln[ROWS];
+    double hpc[ROWS], huc[ROWS], hLc[ROWS], hpn[ROWS], hun[ROWS], hLn[ROWS];
+    auto load_plane = [&](int z, double* P, double* U, double* L) {
+        const unsigned pz = (unsigned)fold(z, nz, a.perz) * plane;
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            P[r] = a.psi[pz + rowoff[r] + uxi];
+            U[r] = a.vprev[pz + rowoff[r] + uxi];
+            L[r] = a.Lam[pz + rowoff[r] + uxi];
+        }
+    };
+    auto load_own = [&](int z, double* rc, double* dg, double* gl, double* hp, double* hu, double* hL) {
+        const unsigned pz = (unsigned)(z < nz ? z : nz - 1) * plane;
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const unsigned o = pz + rowoff[r + 1] + uxi;
+            rc[r] = a.rC[o];
+            dg[r] = a.dgpsi[o];
+            gl[r] = a.gLam[o];
+            hp[r] = 0.0;
+            hu[r] = 0.0;
+            hL[r] = 0.0;
+            if (halo_lane) {
+                const unsigned h = pz + rowoff[r + 1] + hx_i;
+                hp[r] = a.psi[h];
+                hu[r] = a.vprev[h];
+                hL[r] = a.Lam[h];
+            }
+        }
+    };
+    load_plane(z0 - 1, pm, um, Lm);
+    load_plane(z0, pc, uc, Lc);
+    load_plane(z0 + 1, pp, up_, Lp);
+    load_own(z0, rcc, dgc, glc, hpc, huc, hLc);
+    for (int z = z0; z < z1; ++z) {
+        const unsigned pzc = (unsigned)z * plane;
+        load_plane(z + 2, pq, uq, Lq);
+        load_own(z + 1, rcn, dgn, gln, hpn, hun, hLn);
+        const bool fB = a.perz ? nz > 1 : z > 0;
+        const bool fF = a.perz ? nz > 1 : z < nz - 1;
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            // x-neighbours with every lane active
+            double pl = from_left(pc[r + 1]), pr = from_right(pc[r + 1]);
+            double ul = from_left(uc[r + 1]), ur = from_right(uc[r + 1]);
+            double Ll = from_left(Lc[r + 1]), Lr = from_right(Lc[r + 1]);
+            if (lane == 0) {
+                pl = hpc[r];
+                ul = huc[r];
+                Ll = hLc[r];
+            }
+            if (lane == 63) {
+                pr = hpc[r];
+                ur = huc[r];
+                Lr = hLc[r];
+            }
+            const int y = y0 + r;
+            if (inx && y < ny) {
+                const bool fD = a.pery ? ny > 1 : y > 0;
+                const bool fU = a.pery ? ny > 1 : y < ny - 1;
+                const double c = pc[r + 1], va = uc[r + 1], La = Lc[r + 1];
+                double S = 0.0, G = 0.0;
+                if (fL) {
+                    S += wx * fmean<double>(La, Ll, 0) * (c - pl);
+                    G += hx * (ul - va) * (c - pl);
+                }
+                if (fR) {
+                    S += wx * fmean<double>(La, Lr, 0) * (c - pr);
+                    G += hx * (ur - va) * (c - pr);
+                }
+                if (fD) {
+                    S += wy * fmean<double>(La, Lc[r], 0) * (c - pc[r]);
+                    G += hy * (uc[r] - va) * (c - pc[r]);
+                }
+                if (fU) {
+                    S += wy * fmean<double>(La, Lc[r + 2], 0) * (c - pc[r + 2]);
+                    G += hy * (uc[r + 2] - va) * (c - pc[r + 2]);
+                }
+                if (fB) {
+                    S += wz * fmean<double>(La, Lm[r + 1], 0) * (c - pm[r + 1]);
+                    G += hz * (um[r + 1] - va) * (c - pm[r + 1]);
+                }
+                if (fF) {
+                    S += wz * fmean<double>(La, Lp[r + 1], 0) * (c - pp[r + 1]);
+                    G += hz * (up_[r + 1] - va) * (c - pp[r + 1]);
+                }
+                const unsigned o = pzc + (unsigned)y * (unsigned)nx + (unsigned)xg;
+                a.psi_out[o] = cm * (tb * c - tf * rcc[r] * S);
+                a.dgpsi[o] = dgc[r] + cm * c;
+                a.gLam[o] = glc[r] + cm * G;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            pm[r] = pc[r];
+            um[r] = uc[r];
+            Lm[r] = Lc[r];
+            pc[r] = pp[r];
+            uc[r] = up_[r];
+            Lc[r] = Lp[r];
+            pp[r] = pq[r];
+            up_[r] = uq[r];
+            Lp[r] = Lq[r];
+        }
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            rcc[r] = rcn[r];
+            dgc[r] = dgn[r];
+            glc[r] = gln[r];
+            hpc[r] = hpn[r];
+            huc[r] = hun[r];
+            hLc[r] = hLn[r];
+        }
+    }
+}
+
+constexpr int kAdjRows = 2;
+
+__global__ void __launch_bounds__(256) k_scale_rc(int64_t n, const double* __restrict__ x, const double* __restrict__ rC,
+                                                  double* __restrict__ y) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = x[i] * rC[i];
+}
+
+}  // namespace
+
+bool use_adj_z3d(const DevGrid& g, int face) { return use_z3d(g) && face == 0; }
+
+void launch_psi_from_lambda(hipStream_t s, int64_t n, const double* lam, const double* rC, double* psi) {
+    const int64_t b = (n + 255) / 256;
+    hipLaunchKernelGGL(k_scale_rc, dim3((unsigned)(b < 8192 ? b : 8192)), dim3(256), 0, s, n, lam, rC, psi);
+}
+
+void launch_adj_z3d(hipStream_t s, const DevGrid& g, const double* psi, const double* vprev, const double* Lam,
+                    const double* rC, double* psi_out, double* dgpsi, double* gLam, double cm, double tb,
+                    double tau) {
+    AZ3Args a{};
+    a.psi = psi;
+    a.vprev = vprev;
+    a.Lam = Lam;
+    a.rC = rC;
+    a.psi_out = psi_out;
+    a.dgpsi = dgpsi;
+    a.gLam = gLam;
+    a.cm = cm;
+    a.tb = tb;
+    a.tau = tau;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nz = g.nz;
+    a.perx = g.per[0];
+    a.pery = g.per[1];
+    a.perz = g.per[2];
+    a.wx = g.w[0];
+    a.wy = g.w[1];
+    a.wz = g.w[2];
+    a.tiles_x = (g.nx + 63) / 64;
+    a.tiles_y = (g.ny + kAdjRows - 1) / kAdjRows;
+    const int64_t cols = (int64_t)a.tiles_x * a.tiles_y;
+    int64_t zc = (int64_t)g.nz * cols / 4096;
+    zc = zc < 4 ? 4 : (zc > 64 ? 64 : zc);
+    a.zc = (int)zc;
+    const int64_t nw = cols * ((g.nz + a.zc - 1) / a.zc);
+    a.nwaves = (int)nw;
+    const unsigned blocks = (unsigned)((nw + kZWaves - 1) / kZWaves);
+    hipLaunchKernelGGL(k_adj_z3d<kAdjRows>, dim3(blocks), dim3(64 * kZWaves), 0, s, a);
+}
+
+}  // namespace tlim
