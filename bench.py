@@ -267,10 +267,38 @@ def bubbles3d_rate(n=256, steps=5):
                 ms_per_step=round(wall / steps * 1e3, 3), sweeps=sweeps)
 
 
+def adjoint_pair(wl, precision, steps, ckpt_every):
+    """Checkpointed forward and adjoint of `steps` steps of workload wl in a
+    context of `precision`, timed each (seconds)."""
+    import torch
+    from paper_2106_00282_amd.tlim import Solver, StepOpts
+    with Solver(wl["n"], wl["h"], wl["bc"], precision=precision) as s:
+        s.set_workload(wl)
+        tau = wl["dt_factor"] * 2.0 / s.spectral_bound()
+        opts = StepOpts(dt=tau, passes=wl["passes"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ckpt, lam = s.forward_checkpointed(opts, steps, ckpt_every)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        TN = s.get_field("T1")
+        g = TN - torch.from_numpy(wl["fields"]["T1"]).to(TN.device)
+        del TN
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.adjoint(opts, steps, ckpt_every, ckpt, lam, g)
+        torch.cuda.synchronize()
+        t_adj = time.perf_counter() - t0
+        del ckpt, g
+    torch.cuda.empty_cache()
+    return t_fwd, t_adj
+
+
 def interface3d_rate(n=512, steps=10, ckpt_every=2):
     """The 3D interface workload (512^3, x adiabatic, contrast 100) in an FP32
     context: forward throughput over `steps` steps, then the checkpointed
-    forward (every `ckpt_every` steps) and the adjoint, timed each."""
+    forward (every `ckpt_every` steps) and the adjoint, timed each; and the
+    same pair in an FP64 context."""
     import torch
     from paper_2106_00282_amd import workloads as W
     from paper_2106_00282_amd.tlim import Solver, StepOpts
@@ -293,31 +321,21 @@ def interface3d_rate(n=512, steps=10, ckpt_every=2):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         log(f"interface3d forward {wall:.3f} s")
-        s.set_workload(wl)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ckpt, lam = s.forward_checkpointed(opts, steps, ckpt_every)
-        torch.cuda.synchronize()
-        t_fwd = time.perf_counter() - t0
-        TN = s.get_field("T1")
-        g = TN - torch.from_numpy(wl["fields"]["T1"]).to(TN.device)
-        del TN
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.adjoint(opts, steps, ckpt_every, ckpt, lam, g)
-        torch.cuda.synchronize()
-        t_adj = time.perf_counter() - t0
-        log(f"interface3d adjoint {t_adj:.3f} s")
-        del ckpt, g
         N = s.N
     torch.cuda.empty_cache()
+    t_fwd, t_adj = adjoint_pair(wl, "fp32", steps, ckpt_every)
+    log(f"interface3d FP32 context: checkpointed forward {t_fwd:.3f} s, adjoint {t_adj:.3f} s")
+    f64_fwd, f64_adj = adjoint_pair(wl, "fp64", steps, ckpt_every)
+    log(f"interface3d FP64 context: checkpointed forward {f64_fwd:.3f} s, adjoint {f64_adj:.3f} s")
     return dict(workload=f"interface3d {n}^3, x adiabatic, k0 = (1, 0.01), FP32 sweeps with FP64 state, "
                          f"sums and relaxation, {steps} steps x 3 passes",
                 value=round(N * sweeps / wall / 1e9, 3), unit="Gcell-updates/s",
                 ms_per_step=round(wall / steps * 1e3, 3), sweeps=sweeps,
                 adjoint={"checkpoint_every": ckpt_every, "forward_checkpointed_s": round(t_fwd, 4),
                          "adjoint_s": round(t_adj, 4), "ratio": round(t_adj / t_fwd, 3),
-                         "note": "the adjoint recomputes each step from its checkpoint and reverses it in FP64"})
+                         "note": "the adjoint recomputes each step from its checkpoint and reverses it in FP64",
+                         "fp64_context": {"forward_checkpointed_s": round(f64_fwd, 4), "adjoint_s": round(f64_adj, 4),
+                                          "ratio": round(f64_adj / f64_fwd, 3)}})
 
 
 def hyperbolic_rate(n=1024, steps=10, warmup=2):
