@@ -84,25 +84,39 @@ __global__ void __launch_bounds__(64 * kWaves) k_coeffs2d(Coef2DArgs a) {
     const bool q = a.q32 != nullptr;
 
     auto at = [&](int y) { return (int64_t)fold(y, a.ny, a.pery) * a.nx + xi; };
-    // rows y0-1 .. y0+kRows: T, alpha2 -> Lambda (and g in FP32 contexts)
+    // rows y0-1 .. y0+kRows: T, alpha2 -> Lambda (and g in FP32 contexts).
+    // Every word the kernel reads is in flight before the first law
+    // evaluation (one round trip to memory, not one per row): m1, m2 for the
+    // relaxation, the Spitzer-Harm law and 1/C, and 1/C itself when kept.
     double Lw[kRows + 2], tw[kRows + 2], aw[kRows + 2], gw[kRows + 2];
+    double m1w[kRows + 2], m2w[kRows + 2], rcw[kRows + 2];
+    const bool need_m = kRelax || kSH || a.rebuild;
+    {
+        double t2w[kRows + 2];
 #pragma unroll
-    for (int r = 0; r < kRows + 2; ++r) {
-        const int64_t idx = at(y0 - 1 + r);
-        if constexpr (kRelax) {
-            const double t1 = a.T[idx];
-            const double t2 = a.T2 == a.T ? t1 : a.T2[idx];
-            phys::relax_cell(a.ph, a.eps, a.alpha2[idx], t1, t2, a.m1[idx], a.m2[idx], tw[r], aw[r]);
-            gw[r] = tw[r];  // g = T^n, the relaxed T
-        } else {
+        for (int r = 0; r < kRows + 2; ++r) {
+            const int64_t idx = at(y0 - 1 + r);
             tw[r] = a.T[idx];
             aw[r] = a.alpha2[idx];
-            gw[r] = q ? a.g[idx] : 0.0;
+            if constexpr (kRelax) t2w[r] = a.T2[idx];
+            else gw[r] = q ? a.g[idx] : 0.0;
+            m1w[r] = need_m ? a.m1[idx] : 0.0;
+            m2w[r] = need_m ? a.m2[idx] : 0.0;
+            rcw[r] = a.rebuild ? 0.0 : a.rC_in[idx];
+        }
+        if constexpr (kRelax) {
+#pragma unroll
+            for (int r = 0; r < kRows + 2; ++r) {
+                phys::relax_cell(a.ph, a.eps, aw[r], tw[r], t2w[r], m1w[r], m2w[r], tw[r], aw[r]);
+                gw[r] = tw[r];  // g = T^n, the relaxed T
+            }
         }
     }
 #pragma unroll
-    for (int r = 0; r < kRows + 2; ++r)
-        Lw[r] = phys::cell_lambda<kSH>(a.ph, tw[r], aw[r], a.m1, a.m2, at(y0 - 1 + r));
+    for (int r = 0; r < kRows + 2; ++r) {
+        if constexpr (kSH) Lw[r] = phys::cell_conductivity(a.ph, tw[r], aw[r], m1w[r] + m2w[r]);
+        else Lw[r] = phys::cell_conductivity_pow(a.ph, tw[r], aw[r]);
+    }
 
     double bound = 0.0;
 #pragma unroll
@@ -123,11 +137,11 @@ __global__ void __launch_bounds__(64 * kWaves) k_coeffs2d(Coef2DArgs a) {
             }
             double rc;
             if (a.rebuild) {
-                rc = inv_heat_capacity(a.ph, a.eps, tw[r], aw[r], a.m1[o], a.m2[o]);
+                rc = inv_heat_capacity(a.ph, a.eps, tw[r], aw[r], m1w[r], m2w[r]);
                 a.rC[o] = rc;
                 if (a.rC32) a.rC32[o] = (float)rc;
             } else {
-                rc = a.rC_in[o];
+                rc = rcw[r];
             }
             if (a.Lam) a.Lam[o] = L;
             if (a.Lam32) a.Lam32[o] = Lf;
@@ -190,20 +204,28 @@ __global__ void __launch_bounds__(64 * kWaves) k_coeffs3d(Coef2DArgs a) {
     // T, alpha2 (relaxed when kRelax), Lambda and g of the window rows of plane z
     auto load_plane = [&](int z, double* tw, double* aw, double* Lw, double* gw) {
         const unsigned pz = (unsigned)fold(z, nz, a.perz) * plane;
+        // all rows' words in flight before the first law evaluation
+        double t2w[RW], m1w[RW], m2w[RW];
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             const unsigned idx = pz + rowoff[r];
-            if constexpr (kRelax) {
-                const double t1 = a.T[idx];
-                const double t2 = a.T2 == a.T ? t1 : a.T2[idx];
-                phys::relax_cell(a.ph, a.eps, a.alpha2[idx], t1, t2, a.m1[idx], a.m2[idx], tw[r], aw[r]);
-                gw[r] = tw[r];
-            } else {
-                tw[r] = a.T[idx];
-                aw[r] = a.alpha2[idx];
-                gw[r] = q ? a.g[idx] : 0.0;
+            tw[r] = a.T[idx];
+            aw[r] = a.alpha2[idx];
+            if constexpr (kRelax) t2w[r] = a.T2[idx];
+            else gw[r] = q ? a.g[idx] : 0.0;
+            if constexpr (kRelax || kSH) {
+                m1w[r] = a.m1[idx];
+                m2w[r] = a.m2[idx];
             }
-            Lw[r] = phys::cell_lambda<kSH>(a.ph, tw[r], aw[r], a.m1, a.m2, idx);
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            if constexpr (kRelax) {
+                phys::relax_cell(a.ph, a.eps, aw[r], tw[r], t2w[r], m1w[r], m2w[r], tw[r], aw[r]);
+                gw[r] = tw[r];
+            }
+            if constexpr (kSH) Lw[r] = phys::cell_conductivity(a.ph, tw[r], aw[r], m1w[r] + m2w[r]);
+            else Lw[r] = phys::cell_conductivity_pow(a.ph, tw[r], aw[r]);
         }
     };
     // window: Lambda and g of planes z-1, z, z+1; T and alpha2 of z and z+1
@@ -215,6 +237,16 @@ __global__ void __launch_bounds__(64 * kWaves) k_coeffs3d(Coef2DArgs a) {
         load_plane(z + 1, tp, ap, Lp, gp);
         const bool fB = a.perz ? nz > 1 : z > 0;
         const bool fF = a.perz ? nz > 1 : z < nz - 1;
+        // the output rows' m1, m2 (1/C rebuilt) or 1/C, both rows at once
+        double m1o[kRows3 + 1], m2o[kRows3 + 1], rco[kRows3 + 1];
+#pragma unroll
+        for (int r = 1; r <= kRows3; ++r) {
+            const int y = y0 + r - 1;
+            const unsigned o = out_lane && y < ny ? (unsigned)z * plane + (unsigned)y * (unsigned)nx + (unsigned)xg : 0u;
+            m1o[r] = a.rebuild ? a.m1[o] : 0.0;
+            m2o[r] = a.rebuild ? a.m2[o] : 0.0;
+            rco[r] = a.rebuild ? 0.0 : a.rC_in[o];
+        }
 #pragma unroll
         for (int r = 1; r <= kRows3; ++r) {
             const int y = y0 + r - 1;
@@ -233,11 +265,11 @@ __global__ void __launch_bounds__(64 * kWaves) k_coeffs3d(Coef2DArgs a) {
                 }
                 double rc;
                 if (a.rebuild) {
-                    rc = inv_heat_capacity(a.ph, a.eps, tc[r], ac[r], a.m1[o], a.m2[o]);
+                    rc = inv_heat_capacity(a.ph, a.eps, tc[r], ac[r], m1o[r], m2o[r]);
                     a.rC[o] = rc;
                     if (a.rC32) a.rC32[o] = (float)rc;
                 } else {
-                    rc = a.rC_in[o];
+                    rc = rco[r];
                 }
                 if (a.Lam) a.Lam[o] = L;
                 if (a.Lam32) a.Lam32[o] = Lf;

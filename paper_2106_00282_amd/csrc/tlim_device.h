@@ -12,6 +12,17 @@
 namespace tlim {
 namespace phys {
 
+// Out-of-line pieces of the cell laws: a general power, the logarithm, the
+// relaxation of an interface cell and the interface term of 1/C.  The 2D
+// kernels evaluate the laws for 8 rows per lane in one-shot prologues and
+// epilogues; inlined, every row carries its own copy of this code, the
+// kernels grow past the instruction cache and that straight-line code runs
+// at the pace of instruction fetch.  Called, one copy serves every row.
+// Arguments are scalars: a reference to a kernel argument would copy the
+// whole argument block to scratch memory.
+static __device__ __attribute__((noinline)) double pow_ool(double x, double n) { return pow(x, n); }
+static __device__ __attribute__((noinline)) double log_ool(double x) { return log(x); }
+
 // (T/T0)^n with the exponents the conductivity laws use written out, so the
 // common integer and half-integer cases are exact products.
 static __device__ __forceinline__ double powlaw(double x, double n) {
@@ -20,7 +31,7 @@ static __device__ __forceinline__ double powlaw(double x, double n) {
     if (n == 2.0) return x * x;
     if (n == 3.0) return x * x * x;
     if (n == 2.5) return x * x * sqrt(x);
-    return pow(x, n);
+    return pow_ool(x, n);
 }
 
 static __device__ __forceinline__ bool is_mixed(double a2, double eps) { return a2 > eps && a2 < 1.0 - eps; }
@@ -52,8 +63,8 @@ struct LawLogs {
 static __device__ __forceinline__ LawLogs law_logs(const DevPhases& ph, double t, double rho) {
     LawLogs g{0.0, 0.0};
     if (ph.spitzer) {
-        g.lt = log(t);
-        g.lr = log(rho);
+        g.lt = log_ool(t);
+        g.lr = log_ool(rho);
     }
     return g;
 }
@@ -123,13 +134,21 @@ static __device__ __forceinline__ double cell_lambda(const DevPhases& ph, double
     else return cell_conductivity_pow(ph, t, a2);
 }
 
+// B1^2 / (T^2 W) of an interface cell, with W of pressure_stiffness.
+static __device__ __attribute__((noinline)) double interface_capacity(double B1, double gam0, double gam1, double t,
+                                                                      double a2, double C1, double C2) {
+    const double a1 = 1.0 - a2;
+    const double W = (gam0 - 1.0) * C1 / (a1 * a1) + (gam1 - 1.0) * C2 / (a2 * a2);
+    return B1 * B1 / (t * t * W);
+}
+
 // 1 / C_eff (Sec. 3.4.2 under T_1 = T_2 and p_1 = p_2).
 static __device__ __forceinline__ double inv_heat_capacity(const DevPhases& ph, double eps, double t, double a2,
                                                            double m1, double m2) {
     double B1 = ph.pinf[0] - ph.pinf[1];
     double C1 = m1 * ph.cv[0], C2 = m2 * ph.cv[1];
     double C = C1 + C2;
-    if (B1 != 0.0 && is_mixed(a2, eps)) C += B1 * B1 / (t * t * pressure_stiffness(ph, a2, C1, C2));
+    if (B1 != 0.0 && is_mixed(a2, eps)) C += interface_capacity(B1, ph.gamma[0], ph.gamma[1], t, a2, C1, C2);
     return 1.0 / C;
 }
 
@@ -139,17 +158,17 @@ static __device__ __forceinline__ double inv_heat_capacity(const DevPhases& ph, 
 // T'(a) = (C1 T1 + C2 T2 + (alpha2^0 - a) B)/(C1 + C2) and
 // (p_1 - p_2) a (1-a) = A2 a^2 + A1 a + A0 is quadratic in a = alpha2'.
 // The root with 0 < a < 1 and T'(a) > 0 is taken (eq. Taverage when B = 0).
-static __device__ __forceinline__ void relax_cell(const DevPhases& ph, double eps, double a20, double T1,
-                                                  double T2, double m1, double m2, double& T, double& a2) {
-    if (a20 <= eps || a20 >= 1.0 - eps) {
-        // pure cell: the absent phase takes the present phase's temperature
-        T = a20 <= eps ? T1 : T2;
-        a2 = a20;
-        return;
-    }
-    const double B = ph.pinf[1] - ph.pinf[0];
-    const double G1 = ph.gamma[0] - 1.0, G2 = ph.gamma[1] - 1.0;
-    double C1 = m1 * ph.cv[0], C2 = m2 * ph.cv[1];
+// Interface cell (eps < alpha2^0 < 1 - eps) of relax_cell.
+struct Relaxed {
+    double T, a2;
+};
+static __device__ __attribute__((noinline)) Relaxed relax_interface(double pinf0, double pinf1, double gam0,
+                                                                    double gam1, double cv0, double cv1,
+                                                                    double a20, double T1, double T2, double m1,
+                                                                    double m2) {
+    const double B = pinf1 - pinf0;
+    const double G1 = gam0 - 1.0, G2 = gam1 - 1.0;
+    double C1 = m1 * cv0, C2 = m2 * cv1;
     double S = C1 + C2;
     double E = C1 * T1 + C2 * T2;
     double t0 = (E + a20 * B) / S, t1 = -B / S;   // T'(a) = t0 + t1 a
@@ -185,8 +204,21 @@ static __device__ __forceinline__ void relax_cell(const DevPhases& ph, double ep
             if (df != 0.0) root -= f / df;
         }
     }
-    T = t0 + t1 * root;
-    a2 = root;
+    return Relaxed{t0 + t1 * root, root};
+}
+
+static __device__ __forceinline__ void relax_cell(const DevPhases& ph, double eps, double a20, double T1,
+                                                  double T2, double m1, double m2, double& T, double& a2) {
+    if (a20 <= eps || a20 >= 1.0 - eps) {
+        // pure cell: the absent phase takes the present phase's temperature
+        T = a20 <= eps ? T1 : T2;
+        a2 = a20;
+        return;
+    }
+    const Relaxed r = relax_interface(ph.pinf[0], ph.pinf[1], ph.gamma[0], ph.gamma[1], ph.cv[0], ph.cv[1], a20,
+                                      T1, T2, m1, m2);
+    T = r.T;
+    a2 = r.a2;
 }
 
 }  // namespace phys

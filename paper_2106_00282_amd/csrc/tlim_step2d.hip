@@ -94,9 +94,19 @@ __device__ void grid_barrier(unsigned* bar, unsigned g, double* flag, unsigned l
         const unsigned lane = threadIdx.x;
         unsigned spins = 0;
         for (;;) {
+            // the arrival words in batches of 4 per lane, each batch in
+            // flight at once (a resident grid fits one batch)
             bool here = true;
-            for (unsigned b = lane; b < nblk; b += 64)
-                here = here && __hip_atomic_load(bar + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= g;
+            for (unsigned b0 = 0; b0 < nblk; b0 += 256) {
+                unsigned w[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const unsigned b = b0 + lane + 64u * k;
+                    w[k] = b < nblk ? __hip_atomic_load(bar + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : g;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) here = here && w[k] >= g;
+            }
             if (__all(here)) break;
             __builtin_amdgcn_s_sleep(1);
             if (++spins > limit) {
@@ -108,6 +118,16 @@ __device__ void grid_barrier(unsigned* bar, unsigned g, double* flag, unsigned l
     __syncthreads();
 }
 
+// Lambda of a cell under the law family the kernel is compiled for (kSH: a
+// phase follows the Spitzer-Harm law, which needs rho = m1 + m2; the power
+// law ignores rho).
+template <bool kSH>
+__device__ __forceinline__ double step_lambda(const StepArgs& a, double t, double a2, double rho) {
+    if constexpr (kSH) return cell_conductivity(a.ph, t, a2, rho);
+    else return phys::cell_conductivity_pow(a.ph, t, a2);
+}
+
+template <bool kSH>
 __global__ void __launch_bounds__(64 * NW, 4) k_step2d(StepArgs a) {
     __shared__ double sG[EY][64];
     __shared__ double sh_lo[2][NW][64], sh_hi[2][NW][64];
@@ -197,16 +217,24 @@ __global__ void __launch_bounds__(64 * NW, 4) k_step2d(StepArgs a) {
     // ---- 1. relaxation and the first pass's coefficients
     {
         double L[ROWS], rc[ROWS];
+        // the inputs of all rows in flight before the relaxation (T2 may alias T1)
+        const double* const T2p = a.st.T2 ? a.st.T2 : a.st.T1;
+        double t1[ROWS], t2[ROWS], m1[ROWS], m2[ROWS], a20[ROWS];
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int idx = cell_idx(r);
-            const double t1 = a.st.T1[idx];
-            const double t2 = a.st.T2 == a.st.T1 ? t1 : a.st.T2[idx];
-            const double m1 = a.st.m1[idx], m2 = a.st.m2[idx];
+            t1[r] = a.st.T1[idx];
+            t2[r] = T2p[idx];
+            m1[r] = a.st.m1[idx];
+            m2[r] = a.st.m2[idx];
+            a20[r] = a.st.alpha2[idx];
+        }
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
             double T, a2;
-            relax_cell(a.ph, a.eps, a.st.alpha2[idx], t1, t2, m1, m2, T, a2);
-            rc[r] = inv_heat_capacity(a.ph, a.eps, T, a2, m1, m2);
-            L[r] = cell_conductivity(a.ph, T, a2, m1 + m2);
+            relax_cell(a.ph, a.eps, a20[r], t1[r], t2[r], m1[r], m2[r], T, a2);
+            rc[r] = inv_heat_capacity(a.ph, a.eps, T, a2, m1[r], m2[r]);
+            L[r] = step_lambda<kSH>(a, T, a2, m1[r] + m2[r]);
             sG[wv * ROWS + r][lane] = T;
             if (out_cell(r)) {
                 const int o = out_idx(r);
@@ -291,9 +319,14 @@ __global__ void __launch_bounds__(64 * NW, 4) k_step2d(StepArgs a) {
                 for (int r = 0; r < ROWS; ++r)
                     if (out_cell(r)) cstore(xa + out_idx(r), v[r]);
                 grid_barrier(a.st.bar, ++nbar, flag, a.st.spin_limit);
+                // every row's word in flight at once (an output cell reads
+                // back what it published), then the ring keeps its values
+                double w[ROWS];
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) w[r] = cload(xa + cell_idx(r));
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r)
-                    if (!out_cell(r)) v[r] = cload(xa + cell_idx(r));
+                    if (!out_cell(r)) v[r] = w[r];
                 xb ^= 1;
             }
         }
@@ -303,12 +336,16 @@ __global__ void __launch_bounds__(64 * NW, 4) k_step2d(StepArgs a) {
             double* Tw = a.st.Tout[it & 1];
             const double* Tprev = a.st.Tout[(it + 1) & 1];
             double dmax = 0.0, tmax = 0.0, bad = 0.0;
+            double tp[ROWS];
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r)
+                tp[r] = it == 0 ? sG[wv * ROWS + r][lane] : cload(Tprev + (out_cell(r) ? out_idx(r) : 0));
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
                 if (out_cell(r)) {
                     const int o = out_idx(r);
                     const double tn = v[r];
-                    const double tit = it == 0 ? sG[wv * ROWS + r][lane] : cload(Tprev + o);
+                    const double tit = tp[r];
                     dmax = fmax(dmax, fabs(tn - tit));
                     tmax = fmax(tmax, fabs(tn));
                     if (!(tn > 0.0) || isinf(tn)) bad += 1.0;
@@ -338,18 +375,19 @@ __global__ void __launch_bounds__(64 * NW, 4) k_step2d(StepArgs a) {
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r) {
                     const int idx = cell_idx(r);
-                    L[r] = cell_conductivity(a.ph, v[r], a.st.a2n[idx],
-                                             phys::mix_density(a.ph, a.st.m1, a.st.m2, idx));
+                    L[r] = step_lambda<kSH>(a, v[r], a.st.a2n[idx], kSH ? a.st.m1[idx] + a.st.m2[idx] : 1.0);
                     rc[r] = a.st.rC[idx];
                 }
                 build(L, rc, a.st.acc + (size_t)tgt_lam(it + 1) * kSlots, false);
                 grid_barrier(a.st.bar, ++nbar, flag, a.st.spin_limit);
+                double w[ROWS];
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) w[r] = cload(Tw + cell_idx(r));
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r) {
                     if (!out_cell(r)) {
                         const int idx = cell_idx(r);
-                        L[r] = cell_conductivity(a.ph, cload(Tw + idx), a.st.a2n[idx],
-                                                 phys::mix_density(a.ph, a.st.m1, a.st.m2, idx));
+                        L[r] = step_lambda<kSH>(a, w[r], a.st.a2n[idx], kSH ? a.st.m1[idx] + a.st.m2[idx] : 1.0);
                     }
                 }
                 build(L, rc, nullptr, true);
@@ -370,7 +408,7 @@ int resident_limit() {
         int dev = 0, cus = 0, per = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step2d, 64 * NW, 0) != hipSuccess)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step2d<true>, 64 * NW, 0) != hipSuccess)
             limit = 0;
         else
             limit = cus * per;
@@ -419,7 +457,8 @@ bool launch_step2d(hipStream_t s, const DevGrid& g, const DevPhases& ph, double 
     a.ox = 64 - 2 * t.H;
     a.oy = EY - 2 * t.H;
     void* args[] = {&a};
-    const hipError_t e = hipLaunchCooperativeKernel((const void*)k_step2d, dim3((unsigned)(t.tiles_x * t.tiles_y)),
+    const void* kern = ph.spitzer ? (const void*)k_step2d<true> : (const void*)k_step2d<false>;
+    const hipError_t e = hipLaunchCooperativeKernel(kern, dim3((unsigned)(t.tiles_x * t.tiles_y)),
                                                     dim3(64 * NW), args, 0, s);
     if (e != hipSuccess) {
         (void)hipGetLastError();

@@ -102,10 +102,11 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
     __shared__ R sh_lo[2][WAVES][64];  // row 0 of each wave (the "up" row of the wave below)
     __shared__ R sh_hi[2][WAVES][64];  // row ROWS-1 of each wave (the "down" row of the wave above)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // Lambda of cell idx in the epilogues (rho = m1 + m2 read only under the
+    // Lambda of a cell in the epilogues (rho = m1 + m2 used only under the
     // Spitzer-Harm law)
-    auto conductivity = [&](double t, double a2, int64_t idx) -> double {
-        return phys::cell_lambda<kSH>(a.ph, t, a2, a.m1, a.m2, idx);
+    auto law = [&](double t, double a2, double m1, double m2) -> double {
+        if constexpr (kSH) return phys::cell_conductivity(a.ph, t, a2, m1 + m2);
+        else return phys::cell_conductivity_pow(a.ph, t, a2);
     };
     const int K = a.K, H = a.H;
     const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
@@ -130,17 +131,38 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
     R Ldk = 0, Luk = 0;
     {
         R L[ROWS], t[ROWS];
+        if constexpr (kFloat) {
+            // every row's words in flight before the first is used (the
+            // double kernels load row by row, as in the epilogue)
+            int64_t idx[ROWS];
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            const int yi = row_index(yi0, yg0, r, a.ny, a.pery);
-            const int64_t idx = (int64_t)yi * a.nx + xi;
-            v[r] = a.v[idx];
+            for (int r = 0; r < ROWS; ++r) idx[r] = (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + xi;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                v[r] = a.v[idx[r]];
+                L[r] = a.Lam[idx[r]];
+                t[r] = a.rC[idx[r]];
+            }
             // the first launch of a pass starts from v^(0) = T^n = g
-            const R gv = same ? v[r] : a.G[idx];
-            if constexpr (kGinLds) sG[wv * ROWS + r][lane] = gv;
-            else G[r] = gv;
-            L[r] = a.Lam[idx];
-            t[r] = a.tau * a.rC[idx];
+            if (same) {
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) G[r] = v[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) G[r] = a.G[idx[r]];
+            }
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) t[r] = a.tau * t[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int64_t idx = (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + xi;
+                v[r] = a.v[idx];
+                // the first launch of a pass starts from v^(0) = T^n = g
+                sG[wv * ROWS + r][lane] = same ? v[r] : a.G[idx];
+                L[r] = a.Lam[idx];
+                t[r] = a.tau * a.rC[idx];
+            }
         }
         sh_lo[0][wv][lane] = L[0];
         sh_hi[0][wv][lane] = L[ROWS - 1];
@@ -271,13 +293,19 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                 // in double for the bound, its float rounding and the source
                 // q = -tau rC' D' g from the float-rounded Lambda' and rC', at
                 // the output cells (K+1 in), faces in the order -x, +x, -y, +y.
-                double Ln[ROWS], rc[ROWS];
+                double Ln[ROWS], rc[ROWS], a2v[ROWS], m1v[ROWS], m2v[ROWS];
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r) {
                     const int64_t idx = (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + xi;
                     rc[r] = a.rC64[idx];
+                    a2v[r] = a.alpha2[idx];
+                    m1v[r] = kSH ? a.m1[idx] : 0.0;
+                    m2v[r] = kSH ? a.m2[idx] : 0.0;
+                }
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) {
                     const double tn = gfin[r] - a.taud * rc[r] * Sfin[r];
-                    Ln[r] = conductivity(tn, a.alpha2[idx], idx);
+                    Ln[r] = law(tn, a2v[r], m1v[r], m2v[r]);
                 }
                 __shared__ double esh[4][WAVES][64];  // seams of Lambda and g
                 esh[0][wv][lane] = Ln[0];
@@ -335,16 +363,44 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
     double dmax = 0.0, tmax = 0.0, bad = 0.0;
     // the first pass's previous iterate is T^n = g, already on chip
     const bool tit_is_g = kFloat ? (fin && a.Tit == a.g64) : (const void*)a.Tit == (const void*)a.G;
+    // Float kernels read the epilogue's words of every row up front, before
+    // any is used (bit r of outm: row r of this lane is an output cell).  The
+    // double kernels read them row by row: there the registers that batching
+    // takes cost more than the load order gains (measured).
+    unsigned outm = 0;
     if (lane >= H && lane < 64 - H && xg < a.nx) {
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int row = wv * ROWS + r;
-            const int y = yg0 + r;
-            if (row >= H && row < EXT_Y - H && y < a.ny) {
-                const int64_t o = (int64_t)y * a.nx + xg;
+            if (row >= H && row < EXT_Y - H && yg0 + r < a.ny) outm |= 1u << r;
+        }
+    }
+    auto out_at = [&](int r) -> int64_t { return (outm >> r) & 1u ? (int64_t)(yg0 + r) * a.nx + xg : 0; };
+    double titv[ROWS], rcf[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        titv[r] = 0.0;
+        rcf[r] = 0.0;
+    }
+    if constexpr (kFloat) {
+        if (a.Tit && !tit_is_g) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) titv[r] = a.Tit[out_at(r)];
+        }
+        if (fin) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) rcf[r] = a.rC64[out_at(r)];
+        }
+    }
+    if (lane >= H && lane < 64 - H && xg < a.nx) {
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int row = wv * ROWS + r;
+            if (row >= H && row < EXT_Y - H && yg0 + r < a.ny) {
+                const int64_t o = (int64_t)(yg0 + r) * a.nx + xg;
                 double tnew;
                 if (fin) {
-                    tnew = gfin[r] - a.taud * a.rC64[o] * Sfin[r];
+                    tnew = gfin[r] - a.taud * rcf[r] * Sfin[r];
                     a.out64[o] = tnew;
                 } else {
                     a.out[o] = v[r];
@@ -357,7 +413,8 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                         if constexpr (kFloat) tit = gfin[r];
                         else tit = (double)sG[wv * ROWS + r][lane];
                     } else {
-                        tit = a.Tit[o];
+                        if constexpr (kFloat) tit = titv[r];
+                        else tit = a.Tit[o];
                     }
                     dmax = fmax(dmax, fabs(tn - tit));
                     tmax = fmax(tmax, fabs(tn));
@@ -399,9 +456,11 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                     const double m1 = a.m1[idx], m2 = a.m2[idx];
                     phys::relax_cell(a.ph, a.eps, a2v, v[r], v[r], m1, m2, Tr[r], ar[r]);
                     rr[r] = phys::inv_heat_capacity(a.ph, a.eps, Tr[r], ar[r], m1, m2);
-                    Ln[r] = conductivity(Tr[r], ar[r], idx);
+                    Ln[r] = law(Tr[r], ar[r], m1, m2);
+                } else if constexpr (kSH) {
+                    Ln[r] = law(v[r], a2v, a.m1[idx], a.m2[idx]);
                 } else {
-                    Ln[r] = conductivity(v[r], a2v, idx);
+                    Ln[r] = law(v[r], a2v, 0.0, 0.0);
                 }
             }
             // the seam buffer not used by the last stage: its reads all
