@@ -1511,7 +1511,12 @@ tlim_status advance_sync(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
         const bool pass0_done = relax_step(c, o);
         Mode mode = Mode::Sync;
         if (o->frozen_lambda) mode = Mode::Frozen;
-        else if (!o->cycle_mode && o->picard_tol <= 0.0 && c->hist_passes == o->passes) mode = Mode::Predict;
+        // Predict only once the schedule has held for a step: a miss costs
+        // the whole heat part twice, a readback per pass only a round trip
+        // (where the first pass's bound keeps differing from the last pass's
+        // of the step before, every prediction would miss)
+        else if (!o->cycle_mode && o->picard_tol <= 0.0 && c->hist_passes == o->passes && c->hist_steady >= 1)
+            mode = Mode::Predict;
         st = heat_passes(c, o, mode, rep, tm, sc, out, pass0_done);
         if (st) return st;
         predicted = mode == Mode::Predict && !out.mispredicted;

@@ -285,7 +285,8 @@ def test_interface3d_fp64_adiabatic_x():
 def test_mispredicted_schedule_rolls_back():
     """Change k0 between steps so that the predicted P is wrong: the step is
     rolled back, rerun with one readback per pass, and still matches the
-    oracle run with the same change."""
+    oracle run with the same change.  Prediction resumes once the new
+    schedule has held for a step."""
     from oracle import oracle as orc
     wl = W.levelset2d(96)
     tau, _ = oracle_dt(orc, wl)
@@ -295,7 +296,7 @@ def test_mispredicted_schedule_rolls_back():
     from paper_2106_00282_amd.tlim import StepOpts
     ph = [dict(p) for p in wl["phases"]]
     reps = []
-    for step, scale in enumerate((1.0, 1.0, 4.0, 4.0)):
+    for step, scale in enumerate((1.0, 1.0, 1.0, 4.0, 4.0, 4.0)):
         for k in range(2):
             ph[k]["k0"] = wl["phases"][k]["k0"] * scale
             s.set_phase(k, ph[k])
@@ -303,9 +304,14 @@ def test_mispredicted_schedule_rolls_back():
         st, rep = s.advance(StepOpts(dt=tau, passes=3))
         assert st == 0
         reps.append(rep)
-    assert reps[2]["mispredicted"] and not reps[2]["predicted"]
-    assert reps[3]["predicted"]
-    assert reps[2]["sweeps"] == sum(2 * p - 1 for p in reps[2]["P"])
+    # steps 0 and 1 build the history, step 2 is predicted; the new k0 of
+    # step 3 makes its prediction miss, step 4 runs with one readback per
+    # pass (the schedule changed) and step 5 is predicted again
+    assert reps[2]["predicted"]
+    assert reps[3]["mispredicted"] and not reps[3]["predicted"]
+    assert not reps[4]["predicted"] and not reps[4]["mispredicted"]
+    assert reps[5]["predicted"]
+    assert reps[3]["sweeps"] == sum(2 * p - 1 for p in reps[3]["P"])
     assert rel_err(s.get_field("T1").cpu().numpy(), fo["T1"]) < 1e-12
 
 
