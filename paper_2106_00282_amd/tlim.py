@@ -34,6 +34,7 @@ MAX_PASSES = 64
 EXPORTED = ("tlim_create", "tlim_destroy", "tlim_workspace_bytes", "tlim_bind_workspace",
             "tlim_set_phase", "tlim_set_field", "tlim_get_field", "tlim_clear_field", "tlim_spectral_bound",
             "tlim_advance_parabolic", "tlim_finish", "tlim_forward_checkpointed", "tlim_adjoint_workspace_bytes",
+            "tlim_adjoint_workspace_bytes_kept",
             "tlim_adjoint_parabolic", "tlim_advance_hyperbolic", "tlim_hyperbolic_dt", "tlim_status_str",
             "tlim_last_error", "tlim_spectral_bound_noalloc")
 
@@ -120,6 +121,8 @@ def load_library(path: str = LIB_PATH):
     L.tlim_finish.argtypes = [vp]
     L.tlim_forward_checkpointed.argtypes = [vp, C.POINTER(StepOptsC), C.c_int32, C.c_int32, vp, dp]
     L.tlim_adjoint_workspace_bytes.argtypes = [vp, C.POINTER(StepOptsC), C.c_int32, dp, C.POINTER(C.c_size_t)]
+    L.tlim_adjoint_workspace_bytes_kept.argtypes = [vp, C.POINTER(StepOptsC), C.c_int32, C.c_int32, dp,
+                                                    C.POINTER(C.c_size_t)]
     L.tlim_adjoint_parabolic.argtypes = [vp, C.POINTER(StepOptsC), C.c_int32, C.c_int32, vp, dp, vp, vp, dp, vp,
                                C.c_size_t]
     L.tlim_status_str.restype = C.c_char_p
@@ -329,14 +332,47 @@ class Solver:
                                                              C.c_void_p(ckpt.data_ptr()), lam))
         return ckpt, [lam[i] for i in range(nsteps * opts.passes)]
 
-    def adjoint(self, opts: StepOpts, nsteps: int, ckpt_every: int, ckpt: torch.Tensor, lam, dL_dTN):
+    def adjoint_workspace(self, opts: StepOpts, nsteps: int, ckpt_every: int, lam, keep_interval=None) -> int:
+        """Allocate (or keep) the adjoint's device workspace for this schedule;
+        returns its size in bytes.  keep_interval: True sizes it for the layout
+        that keeps every step of a checkpoint interval (no step recomputed
+        twice), False for the one that keeps one step, None for the first when
+        it fits in free device memory with a 10% margin.  A workspace already
+        held is kept when large enough, and the adjoint takes the layout its
+        size allows (both give the same result, bit for bit)."""
         L = load_library()
         lam_arr = (C.c_double * len(lam))(*[float(x) for x in lam])
         oc = opts.c()
         nbytes = C.c_size_t()
         self._check(L.tlim_adjoint_workspace_bytes(self._ctx, C.byref(oc), nsteps, lam_arr, C.byref(nbytes)))
-        if self._adj_ws is None or self._adj_ws.numel() < nbytes.value:
-            self._adj_ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        need = int(nbytes.value)
+        if keep_interval is not False and min(ckpt_every, nsteps) > 1:
+            kept = C.c_size_t()
+            self._check(L.tlim_adjoint_workspace_bytes_kept(self._ctx, C.byref(oc), nsteps, ckpt_every, lam_arr,
+                                                            C.byref(kept)))
+            have = 0 if self._adj_ws is None else self._adj_ws.numel()
+            if keep_interval:
+                need = int(kept.value)
+            elif have < kept.value:
+                torch.cuda.empty_cache()
+                free, _ = torch.cuda.mem_get_info(self.device)
+                if kept.value - have <= 0.9 * free:
+                    need = int(kept.value)
+            else:
+                need = int(kept.value)
+        if self._adj_ws is None or self._adj_ws.numel() < need:
+            self._adj_ws = None
+            self._adj_ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._adj_ws.numel()
+
+    def adjoint(self, opts: StepOpts, nsteps: int, ckpt_every: int, ckpt: torch.Tensor, lam, dL_dTN,
+                keep_interval=None):
+        """dL/dT^0 and dL/dk0 from dL/dT^N (see adjoint_workspace for
+        keep_interval; a workspace already large enough is reused)."""
+        L = load_library()
+        lam_arr = (C.c_double * len(lam))(*[float(x) for x in lam])
+        oc = opts.c()
+        self.adjoint_workspace(opts, nsteps, ckpt_every, lam, keep_interval)
         g = self._dev(dL_dTN)
         out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         dk0 = (C.c_double * 2)()

@@ -767,6 +767,49 @@ def test_adjoint_in_fp32_context():
         assert dk0[k] == pytest.approx(odk0[k], rel=1e-10)
 
 
+@pytest.mark.parametrize("shape,steps,every", [((40, 40, 1), 5, 2), ((40, 36, 20), 4, 3), ((70, 24, 12), 3, 2)])
+def test_adjoint_keeping_the_interval_equals_one_step_blocks(shape, steps, every):
+    """The workspace that keeps every step of a checkpoint interval (each
+    interval recomputed once) gives the same gradient, bit for bit, as the
+    one that keeps one step (earlier steps of the interval recomputed for
+    each later one), with a ragged last interval; and the oracle's."""
+    import torch
+    from oracle import oracle as orc
+    from paper_2106_00282_amd.tlim import StepOpts
+    if shape[2] == 1:
+        wl = W.levelset2d(shape[0])
+    else:
+        wl = W.bubbles3d(shape[0], shape=shape)
+        wl["viscous"] = False
+        for k in ("u", "v", "w"):
+            wl["fields"].pop(k)
+    tau, _ = oracle_dt(orc, wl)
+    print(f"case adjoint kept interval {wl['n']} steps={steps} every={every}", flush=True)
+    s = make_solver(wl)
+    opts = StepOpts(dt=tau, passes=3)
+    ckpt, lam = s.forward_checkpointed(opts, steps, every)
+    TN = s.get_field("T1").cpu().numpy()
+    # L = |T^N - mean|^2 / 2: conduction lowers it everywhere, so the terms
+    # of dL/dk0 share their sign and the sum keeps the fields' agreement
+    g = torch.from_numpy(TN - TN.mean())
+    d1, k1 = s.adjoint(opts, steps, every, ckpt, lam, g, keep_interval=False)
+    n1 = s._adj_ws.numel()
+    d1 = d1.cpu().numpy()
+    s._adj_ws = None
+    dk, kk = s.adjoint(opts, steps, every, ckpt, lam, g, keep_interval=True)
+    assert s._adj_ws.numel() > n1
+    assert np.array_equal(dk.cpu().numpy(), d1)
+    assert kk == k1
+    f = wl["fields"]
+    odT0, odk0, _ = orc.heat_adjoint(orc.make_grid(wl["n"], wl["h"], wl["bc"]), wl["phases"],
+                                     orc.StepOpts(tau=tau, passes=3), steps, np.array(lam), f["alpha2"], f["m1"],
+                                     f["m2"], f["T1"], g.numpy())
+    assert rel_err(d1, odT0) < 1e-12
+    for k in range(2):
+        assert k1[k] == pytest.approx(odk0[k], rel=1e-11)
+    s.close()
+
+
 @pytest.mark.parametrize("case", ["harmonic2d", "grid3d", "adiabatic2d"])
 def test_adjoint_other_paths_vs_oracle(case):
     """The adjoint on grids and face means outside the blocked 2D path
