@@ -77,10 +77,10 @@ def sweep_source_digest():
 
 
 def pmc_traffic(prec):
-    """HBM bytes per launch of the blocked sweep of precision `prec` from the
-    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (each counter scaled
-    by what it reads for a plain 1 GiB copy).  None when the summary is
-    missing or the kernel's sources changed since the counters were taken."""
+    """L2-to-memory bytes per launch of the blocked sweep of precision `prec`
+    from the committed rocprofv3 summary of the raw request counters
+    (checked on a plain 1 GiB copy).  None when the summary is missing or
+    the kernel's sources changed since the counters were taken."""
     try:
         with open(PMC_SUMMARY) as fh:
             kv = dict(line.split(": ", 1) for line in fh.read().splitlines()
@@ -136,8 +136,11 @@ def measure(precision, wl, tau, steps, warmup, whole=0):
     sweeps = launches = 0
     sweep_ms = 0.0
     predicted = mispredicted = 0
-    # the blocked-sweep launches alone (a step run as one cooperative launch
-    # of the whole-step kernel is left out of these): the roofline's kernel
+    # the blocked-sweep launches alone, of the steps with a predicted
+    # schedule: the roofline's kernel.  Left out: a step run as one
+    # cooperative launch of the whole-step kernel, and a step that reads each
+    # pass's bound back before enqueueing the pass (its event pairs would also
+    # hold the GPU's wait for the host's launches)
     tb_sweeps = tb_launches = 0
     tb_ms = 0.0
     topts = StepOpts(dt=tau, passes=wl["passes"], time_sweeps=1, whole_step=whole)
@@ -150,7 +153,7 @@ def measure(precision, wl, tau, steps, warmup, whole=0):
             sweep_ms += rep["sweep_ms"]
             predicted += rep["predicted"]
             mispredicted += rep["mispredicted"]
-            if rep["sweep_launches"] > 1:
+            if rep["sweep_launches"] > 1 and rep["predicted"]:
                 tb_sweeps += rep["sweeps"]
                 tb_launches += rep["sweep_launches"]
                 tb_ms += rep["sweep_ms"]
