@@ -41,11 +41,14 @@
  * times the net flux of eq. qk_dis and the pressure gap is O(tau^2); at
  * tau lambda = 400 the domain's EOS energy is conserved.
  *
- * Parity unpinned: the nonlinear-conductivity Picard result has no closed
- * form; it is held only by the invariants above (energy, maximum principle,
- * Picard monotonicity).  The split of the internal energy between two different phases across a
- * wave of the hyperbolic part is held only through the mixture, the
- * advection of alpha_2 and the interface translation.
+ * The nonlinear-conductivity Picard result has no closed form; it is
+ * pinned as the fixed point of the lagged pass: at convergence T* equals one
+ * LIM pass from T^n at Lambda(T*), evaluated through the eigendecomposition
+ * of the symmetric operator and the pass's closed-form multiplier.
+ *
+ * Parity unpinned: the split of the internal energy between two different
+ * phases across a wave of the hyperbolic part is held only through the
+ * mixture, the advection of alpha_2 and the interface translation.
  */
 #ifndef TLIM_ORACLE_H
 #define TLIM_ORACLE_H

@@ -748,6 +748,76 @@ def test_P9_picard_error_decreases_and_tol(orc):
     assert st == 3 and not rep["converged"]
 
 
+def _lim_map_numpy(T, Tn, alpha2, m1, m2, phases, h, tau, face_rolls=True):
+    """One LIM pass from T^n at the conductivities Lambda(T), written here in
+    numpy from the definitions (Sec. 3.2, eq. qk_dis and eq. LIM; Sec. 3.4.2
+    with equal p_inf): Lambda = sum_k alpha_k k0_k (T/T0_k)^n_k, C = m1 Cv_1 +
+    m2 Cv_2, D the periodic face-conductance operator with arithmetic face
+    means and weights 1/h_d^2, lambda_G = max 2 sum_f w_f Lambda_f / C,
+    P = ceil(pi/4 sqrt(tau lambda_G + 1)), and the pass applied as
+    C^-1/2 R(tau S) C^1/2 T^n with S = C^-1/2 D C^-1/2 diagonalised and R the
+    pass's closed-form multiplier (lim_multiplier).  2D grids (ny, nx)."""
+    a1 = 1.0 - alpha2
+    law = [p["k0"] * (T / p.get("T0", 1.0)) ** p["npow"] for p in phases]
+    Lam = a1 * law[0] + alpha2 * law[1]
+    C = m1 * phases[0]["cv"] + m2 * phases[1]["cv"]
+    ny, nx = T.shape
+    N = nx * ny
+    idx = np.arange(N).reshape(ny, nx)
+    D = np.zeros((N, N))
+    diag_sum = np.zeros((ny, nx))
+    for ax, hd in ((1, h[0]), (0, h[1])):
+        for sh in (1, -1):
+            nb = np.roll(idx, -sh, axis=ax)
+            Lf = 0.5 * (Lam + np.roll(Lam, -sh, axis=ax)) / hd ** 2
+            D[idx.ravel(), nb.ravel()] -= Lf.ravel()
+            diag_sum += Lf
+    D[idx.ravel(), idx.ravel()] += diag_sum.ravel()
+    lamG = float((2.0 * diag_sum / C).max())
+    P = int(np.ceil(np.pi / 4.0 * np.sqrt(tau * lamG + 1.0)))
+    cs = np.sqrt(C.ravel())
+    S = D / cs[:, None] / cs[None, :]
+    mu, V = np.linalg.eigh(0.5 * (S + S.T))
+    R = np.array([lim_multiplier(tau * m, tau * lamG, P) for m in mu])
+    out = (V @ (R * (V.T @ (cs * Tn.ravel())))) / cs
+    return out.reshape(ny, nx), P
+
+
+def test_P9_picard_fixed_point_is_the_pass_at_its_own_conductivities(orc):
+    """Algorithm 1 lags the conductivities: at convergence the step's result
+    T* is a fixed point of one LIM pass from T^n with Lambda(T*).  The pass is
+    evaluated here through the eigendecomposition of the symmetric operator
+    and the closed-form multiplier (no stage recursion, no oracle operator), on
+    a nonlinear law (T^2) where T* differs from a pass at Lambda(T^n) by far
+    more than the bar; a pass at Lambda(T^n) is checked too, against the
+    oracle's one-pass step."""
+    wl = W.levelset2d(14)
+    g, f, Lam0, Cap = relaxed_coeffs(orc, wl)
+    lam = orc.gershgorin(g, Lam0, Cap)
+    tau = 20.0 * 2 / lam
+    h = tuple(g.h)
+    ph = wl["phases"]
+    shp = f["T1"].shape[1:] if f["T1"].ndim == 3 else f["T1"].shape
+    sq = lambda x: x.reshape(shp)
+    Tn = sq(f["T1"])
+    a2, m1, m2 = sq(f["alpha2"]), sq(f["m1"]), sq(f["m2"])
+    # one pass: the pass at Lambda(T^n)
+    f1 = {k: v.copy() for k, v in f.items()}
+    orc.step(g, ph, orc.StepOpts(tau=tau, passes=1), f1)
+    T1pass, _ = _lim_map_numpy(Tn, Tn, a2, m1, m2, ph, h, tau)
+    assert np.abs(sq(f1["T1"]) - T1pass).max() <= 1e-12 * np.abs(T1pass).max()
+    # converged Picard: the fixed point of the lagged pass
+    fs = {k: v.copy() for k, v in f.items()}
+    st, rep = orc.step(g, ph, orc.StepOpts(tau=tau, passes=60, picard_tol=1e-14), fs)
+    assert st == 0 and rep["converged"]
+    Ts = sq(fs["T1"])
+    Tfix, P = _lim_map_numpy(Ts, Tn, a2, m1, m2, ph, h, tau)
+    scale = np.abs(Ts).max()
+    assert np.abs(Tfix - Ts).max() <= 1e-12 * scale
+    # the lag matters: T* is far from the one-pass result
+    assert np.abs(Ts - T1pass).max() > 1e-4 * scale
+
+
 # ------------------------------------------------------------ P10 adjoint
 
 def _adjoint_case(orc, npow, n=12, steps=2):
