@@ -48,7 +48,8 @@
  *
  * Parity unpinned: the split of the internal energy between two different
  * phases across a wave of the hyperbolic part is held only through the
- * mixture, the advection of alpha_2 and the interface translation.
+ * mixture, the advection of alpha_2, the interface translation and the
+ * interchangeability of the phase labels.
  */
 #ifndef TLIM_ORACLE_H
 #define TLIM_ORACLE_H
