@@ -6,13 +6,13 @@ is compared after one step, with the oracle's schedule frozen into the GPU
 run (heat and viscous bounds), at the usual bars: FP64 1e-12, FP32 form
 1e-5 per field (max-norm, relative).
 
-512^3 interface (x walls, contrast 100): one oracle step would take minutes,
-so the full-size run is held to properties that hold at any size and are
-exact for the method: the heat step conserves the energy sum_cells C T
-(no sources, adiabatic walls), keeps T within the initial bounds (maximum
+512^3 interface (x walls, contrast 100): one step against the oracle's whole
+fields the same way (the oracle's step takes under a minute with the box's
+cores), and two steps held to properties that hold at any size and are exact
+for the method: the heat step conserves the energy sum_cells C T (no
+sources, adiabatic walls), keeps T within the initial bounds (maximum
 principle of the LIM pass with its final stage), and the FP32 form agrees
-with the FP64 path (oracle-verified on the same setup at 192 x 64 x 48 in
-test_gpu_3d_wide.py) within the FP32 form's bar.
+with the FP64 path within the FP32 form's bar.
 """
 import numpy as np
 import pytest
@@ -102,3 +102,27 @@ def test_interface3d_512_full_size_properties():
     assert e_T <= 1e-5 and e_a <= 1e-5
     # the run is not trivial: heat moved
     assert rel_err(out["fp64"][0], f0["T1"]) > 1e-3
+
+
+@pytest.mark.timeout(900)
+def test_interface3d_512_one_step_vs_oracle():
+    """The 512^3 interface workload itself: one step in the FP32 form (the
+    benchmark's arithmetic) and in FP64 against the oracle's whole fields,
+    with the oracle's schedule frozen into both runs."""
+    from oracle import oracle as orc
+    wl = W.interface3d(512)
+    tau, _ = oracle_dt(orc, wl)
+    print("case interface3d 512^3: oracle step", flush=True)
+    fo, ro = run_oracle(orc, wl, tau, 1)
+    frozen = [r["lambda_G"] for r in ro]
+    for precision, tol in (("fp32", 1e-5), ("fp64", 1e-12)):
+        print(f"case interface3d 512^3 {precision}", flush=True)
+        fg, rg, s = run_gpu(wl, tau, 1, precision=precision, frozen=frozen)
+        s.close()
+        assert [r["P"] for r in rg] == [r["P"] for r in ro]
+        errs = {k: rel_err(fg[k], fo[k]) for k in ("T1", "T2", "alpha2")}
+        print(f"per-field error vs the FP64 oracle ({precision}): {errs}", flush=True)
+        for k, e in errs.items():
+            assert e <= tol, (precision, k, e)
+        del fg
+    assert rel_err(fo["T1"], wl["fields"]["T1"]) > 1e-3
