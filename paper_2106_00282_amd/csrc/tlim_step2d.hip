@@ -300,15 +300,18 @@ __global__ void __launch_bounds__(64 * NW, 4) k_step2d(StepArgs a) {
                 const double vdn = wv > 0 ? sdn : v[0];
                 const double vup = wv < NW - 1 ? sup : v[ROWS - 1];
                 const double tb = lane_value(ptb, s), cm = lane_value(pcm, s);
-                double prev = vdn;
+                // face differences shared by the face's two cells (exact)
+                double ddn = v[0] - vdn;
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r) {
                     const double c = v[r];
                     const double up = r < ROWS - 1 ? v[r + 1] : vup;
-                    const double lf = from_left(c), rt = from_right(c);
-                    const double S = kL[r] * (c - lf) + kR[r] * (c - rt) + kD[r] * (c - prev) + kU[r] * (c - up);
+                    const double drt = c - from_right(c);
+                    const double dlf = -from_left(drt);
+                    const double dup = c - up;
+                    const double S = kL[r] * dlf + kR[r] * drt + kD[r] * ddn + kU[r] * dup;
                     v[r] = cm * (sG[wv * ROWS + r][lane] + tb * c - S);
-                    prev = c;
+                    ddn = -dup;
                 }
             }
             m += K;

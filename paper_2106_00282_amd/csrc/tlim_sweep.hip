@@ -220,18 +220,24 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
         const R vup = wv < WAVES - 1 ? sup : v[ROWS - 1];
         const double tbd = lane_value(ptb, s);
         const R cm = (R)lane_value(pcm, s), tb = (R)tbd;
-        R prev = vdn;
+        // Each face difference is formed once and shared by the face's two
+        // cells: c - c_left is minus the left neighbour's c - c_right, and
+        // c - c_below minus the row below's c - c_above (exact in floating
+        // point, so S is the same number as with four differences per cell).
+        R ddn = v[0] - vdn;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const R c = v[r];
             const R up = r < ROWS - 1 ? v[r + 1] : vup;
-            const R lf = from_left(c), rt = from_right(c);
-            const R S = kL[r] * (c - lf) + kR[r] * (c - rt) + kD[r] * (c - prev) + kU[r] * (c - up);
+            const R drt = c - from_right(c);
+            const R dlf = -from_left(drt);
+            const R dup = c - up;
+            const R S = kL[r] * dlf + kR[r] * drt + kD[r] * ddn + kU[r] * dup;
             R Gr;
             if constexpr (kGinLds) Gr = sG[wv * ROWS + r][lane];
             else Gr = G[r];
             v[r] = cm * (Gr + tb * c - S);
-            prev = c;
+            ddn = -dup;
         }
         // the output cells are exact after every stage: keep the intermediate
         // stages when asked (the adjoint's recomputation)
