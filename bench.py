@@ -136,11 +136,10 @@ def measure(precision, wl, tau, steps, warmup, whole=0):
     sweeps = launches = 0
     sweep_ms = 0.0
     predicted = mispredicted = 0
-    # the blocked-sweep launches alone, of the steps with a predicted
-    # schedule: the roofline's kernel.  Left out: a step run as one
-    # cooperative launch of the whole-step kernel, and a step that reads each
-    # pass's bound back before enqueueing the pass (its event pairs would also
-    # hold the GPU's wait for the host's launches)
+    # the blocked-sweep launches that the library times (the roofline's
+    # kernel): those of the passes enqueued behind earlier device work of
+    # their step, in the steps with a predicted schedule (a whole-step launch
+    # and a pass enqueued right after a readback are not timed)
     tb_sweeps = tb_launches = 0
     tb_ms = 0.0
     topts = StepOpts(dt=tau, passes=wl["passes"], time_sweeps=1, whole_step=whole)
@@ -153,9 +152,9 @@ def measure(precision, wl, tau, steps, warmup, whole=0):
             sweep_ms += rep["sweep_ms"]
             predicted += rep["predicted"]
             mispredicted += rep["mispredicted"]
-            if rep["sweep_launches"] > 1 and rep["predicted"]:
-                tb_sweeps += rep["sweeps"]
-                tb_launches += rep["sweep_launches"]
+            if rep["predicted"]:
+                tb_sweeps += rep["timed_sweeps"]
+                tb_launches += rep["timed_launches"]
                 tb_ms += rep["sweep_ms"]
     return dict(wall_s=wall, sweeps=sweeps, launches=launches, sweep_ms=sweep_ms, N=N,
                 gupd=N * sweeps / wall / 1e9, predicted_steps=predicted, mispredicted_steps=mispredicted,
@@ -571,8 +570,8 @@ def main():
                    f"dt=200x explicit limit, 3 Picard passes, {args.steps} steps",
                    "cells": r64["N"], "sweeps_per_run": r64["sweeps"],
                    "predicted_steps": r64["predicted_steps"], "mispredicted_steps": r64["mispredicted_steps"]},
-        "sweep_kernel_gupd": round(r64["N"] * r64["sweeps"] / (r64["sweep_ms"] * 1e-3) / 1e9, 2)
-        if r64["sweep_ms"] > 0 else None,
+        "sweep_kernel_gupd": round(r64["N"] * r64["tb_sweeps"] / (r64["tb_ms"] * 1e-3) / 1e9, 2)
+        if r64["tb_ms"] > 0 else None,
         "roofline": roofline(r64, "fp64", cp),
     }
     if r32:

@@ -169,7 +169,10 @@ typedef struct {
     double energy_before, energy_after;   /* sum_i vol (sum_k C_k T_k + alpha_k p_inf,k) */
     int64_t sweeps;                       /* stencil sweeps run (heat + viscous) */
     int64_t sweep_launches;               /* sweep kernel launches (<= sweeps when fused) */
-    double sweep_ms;                      /* time_sweeps: summed event time of the sweep launches */
+    double sweep_ms;                      /* time_sweeps: summed event time of the sweep launches
+                                             enqueued behind earlier device work of the step (a pass
+                                             enqueued right after a readback is left out: its events
+                                             would also time the host's enqueueing) */
     int64_t bad_cells;                    /* cells with non-finite or T <= 0 after the last pass */
     int32_t predicted;                    /* 1: P of every pass was predicted from the previous step
                                              and confirmed (no per-pass readback) */
@@ -177,6 +180,8 @@ typedef struct {
                                              with one readback per pass (sweeps counts the rerun only) */
     int64_t pipelined_steps;              /* context totals so far: steps run pipelined (see */
     int64_t pipeline_redos;               /* tlim_advance_parabolic) and pipelined steps redone */
+    int64_t timed_sweeps;                 /* time_sweeps: the stages and launches sweep_ms covers */
+    int64_t timed_launches;
 } tlim_step_report;
 
 typedef struct tlim_ctx tlim_ctx;

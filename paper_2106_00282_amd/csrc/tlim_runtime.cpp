@@ -324,15 +324,16 @@ tlim_status check_opts(tlim_ctx* c, const tlim_step_opts* o) {
 struct Timer {
     tlim_ctx* c;
     bool on;
+    bool skip = false;  // the next run follows a readback: not timed
     int used = 0;
     double folded_ms = 0.0;
     void start() {
-        if (!on) return;
+        if (!on || skip) return;
         if (used + 1 >= kMaxEvents) fold();
         (void)hipEventRecord(c->ev[used], c->stream);
     }
     void stop() {
-        if (!on) return;
+        if (!on || skip) return;
         (void)hipEventRecord(c->ev[used + 1], c->stream);
         used += 2;
     }
@@ -356,6 +357,7 @@ struct Timer {
 
 struct SweepCount {
     int64_t sweeps = 0, launches = 0;
+    int64_t timed_sweeps = 0, timed_launches = 0;  // inside the timer's event pairs
 };
 
 // Reduction rows are zeroed before the kernels that accumulate into them
@@ -430,6 +432,7 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
     if (c->precision == TLIM_FP32 && !have_q)
         tlim::launch_q32(s, g, face, rhs, v0, c->Lam32, c->rC32, tau, c->q32, c->wb[0]);
     // one event pair around the pass's back-to-back sweep launches
+    const int64_t launches0 = sc.launches;
     tm.start();
     if (c->precision == TLIM_FP32) {
         // 2P-2 float stages on the correction, the final one in double; the
@@ -481,6 +484,11 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
     }
     tm.stop();
     sc.sweeps += nst;
+    if (tm.on && !tm.skip) {
+        sc.timed_sweeps += nst;
+        sc.timed_launches += sc.launches - launches0;
+    }
+    tm.skip = false;
 }
 
 // Fold the rows [t0, t1) and bring the results to the host (synchronises).
@@ -557,6 +565,7 @@ tlim_status viscous(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep,
         PassSchedule ps = host_schedule(o->dt, lam, o->order);
         double* u = c->field[TLIM_U + comp];
         Vhat vh;
+        tm.skip = true;  // after the bound's readback
         run_lim_pass(c, g, o->face_mean, o->dt, ps, u, u, c->Tnew, nullptr, tlim::PassSlots{}, tm, sc, false,
                      heat || E ? &vh : nullptr);
         if (heat || E)
@@ -609,6 +618,7 @@ tlim_status cycle_pass(tlim_ctx* c, const DevGrid& g, const tlim_step_opts* o, i
     int cur = 0;
     int cyc = 0;
     double r = 0.0;
+    tm.skip = true;  // every cycle follows the residual's readback: not timed
     while (cyc < o->max_cycles) {
         tm.start();
         for (int m = 0; m < s_stages; ++m) {
@@ -826,6 +836,8 @@ tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_st
             const bool want_step = !need_update && last && next_step_ok(c, o, g);
             tlim::NextCoef nc = want_step ? next_step_coef(c, o, ph) : next_coef(c, it, ph);
             bool done = false;
+            // timed only behind the step's earlier passes (not after a readback)
+            tm.skip = mode == Mode::Sync || it == 0;
             run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->g_heat, c->Tnew, need_update ? nullptr : Tit,
                          pass_slots(c, it), tm, sc, true, nullptr, want || want_step ? &nc : nullptr, &done);
             if (want_step) note_next_step(c, o, done);
@@ -1385,9 +1397,11 @@ tlim_status step2d_sync(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* 
     done = false;
     tlim_status st = step2d_table(c, o->order);
     if (st) return st;
+    tm.skip = true;  // the step's first launch: not timed
     tm.start();
     const bool ok = step2d_enqueue(c, o, c->res_host_dev);
     tm.stop();
+    tm.skip = false;
     if (!ok) return TLIM_OK;
     done = true;
     if (!c->res_host_dev) HIP_TRY(c, hipMemcpyAsync(c->res_host, c->res_dev, sizeof(PassResult), hipMemcpyDeviceToHost, c->stream));
@@ -1545,6 +1559,8 @@ tlim_status advance_sync(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report*
         rep->converged = (o->picard_tol <= 0.0 || out.converged) && !out.cycle_fail;
         rep->sweeps = sc.sweeps;
         rep->sweep_launches = sc.launches;
+        rep->timed_sweeps = sc.timed_sweeps;
+        rep->timed_launches = sc.timed_launches;
         rep->bad_cells = (int64_t)out.bad;
         rep->predicted = predicted ? 1 : 0;
         rep->mispredicted = mispredicted ? 1 : 0;

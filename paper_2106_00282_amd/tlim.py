@@ -79,7 +79,8 @@ class ReportC(C.Structure):
                 ("visc_lambda_G", C.c_double * 3), ("energy_before", C.c_double),
                 ("energy_after", C.c_double), ("sweeps", C.c_int64), ("sweep_launches", C.c_int64),
                 ("sweep_ms", C.c_double), ("bad_cells", C.c_int64), ("predicted", C.c_int32),
-                ("mispredicted", C.c_int32), ("pipelined_steps", C.c_int64), ("pipeline_redos", C.c_int64)]
+                ("mispredicted", C.c_int32), ("pipelined_steps", C.c_int64), ("pipeline_redos", C.c_int64),
+                ("timed_sweeps", C.c_int64), ("timed_launches", C.c_int64)]
 
 
 _lib = None
@@ -184,7 +185,7 @@ def _report(r: ReportC) -> dict:
                 energy_after=r.energy_after, sweeps=r.sweeps, sweep_launches=r.sweep_launches,
                 sweep_ms=r.sweep_ms, bad_cells=r.bad_cells, predicted=bool(r.predicted),
                 mispredicted=bool(r.mispredicted), pipelined_steps=r.pipelined_steps,
-                pipeline_redos=r.pipeline_redos)
+                pipeline_redos=r.pipeline_redos, timed_sweeps=r.timed_sweeps, timed_launches=r.timed_launches)
 
 
 class Solver:
