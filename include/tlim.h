@@ -62,9 +62,10 @@ enum { TLIM_FP64 = 0, TLIM_FP32 = 1 };                 /* arithmetic of the swee
 enum { TLIM_DTYPE_F64 = 0, TLIM_DTYPE_F32 = 1 };       /* element type of a caller's field buffer */
 enum { TLIM_ORDER_INTERLEAVED = 0, TLIM_ORDER_PAPER = 1, TLIM_ORDER_ASCENDING = 2 };
 enum { TLIM_FACE_ARITH = 0, TLIM_FACE_HARMONIC = 1 };
-/* whole_step: AUTO uses the one-launch step while the context has no
- * schedule history for the step's pass count (its first step, whose P
- * would otherwise be read back pass by pass), ALWAYS for every eligible
+/* whole_step: AUTO uses the one-launch step for the steps whose P would
+ * otherwise be read back pass by pass: while the context has no schedule
+ * history for the step's pass count, or one that has not yet held for a
+ * step (a step is predicted only after that); ALWAYS for every eligible
  * step, NEVER for none. */
 enum { TLIM_WHOLE_AUTO = 0, TLIM_WHOLE_ALWAYS = 1, TLIM_WHOLE_NEVER = 2 };
 

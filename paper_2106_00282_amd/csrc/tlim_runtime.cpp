@@ -1319,7 +1319,10 @@ namespace {
 // history to predict P from), the grid's tiles can all be resident and the
 // schedule is not given by the caller.
 bool step2d_ok(const tlim_ctx* c, const tlim_step_opts* o) {
-    if (o->whole_step == TLIM_WHOLE_NEVER || (o->whole_step == TLIM_WHOLE_AUTO && c->hist_passes == o->passes))
+    // AUTO: the steps that would otherwise read each pass's bound back (no
+    // schedule history, or one that has not yet held for a step)
+    if (o->whole_step == TLIM_WHOLE_NEVER ||
+        (o->whole_step == TLIM_WHOLE_AUTO && c->hist_passes == o->passes && c->hist_steady >= 1))
         return false;
     if (c->precision != TLIM_FP64 || o->cycle_mode || o->frozen_lambda || o->picard_tol > 0.0) return false;
     if (c->phase[0].pinf != c->phase[1].pinf) return false;
