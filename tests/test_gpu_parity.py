@@ -385,6 +385,33 @@ def test_pipelined_dt_change_redoes_steps(precision, whole):
     _compare(fo, fg, FIELDS_T, 1e-12 if precision == "fp64" else 1e-5)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sweep_timing_covers_the_passes_enqueued_behind_device_work(precision):
+    """time_sweeps: a step's first pass follows the previous step's readback
+    and is not timed; the later passes of a predicted step are, and the
+    report counts their stages and launches.  Steps that read every pass's
+    bound back (and the whole-step launch) time nothing."""
+    from paper_2106_00282_amd.tlim import StepOpts
+    wl = W.levelset2d(256)
+    s = make_solver(wl, precision)
+    tau = wl["dt_factor"] * 2.0 / s.spectral_bound()
+    reps = []
+    for _ in range(5):
+        st, rep = s.advance(StepOpts(dt=tau, passes=3, time_sweeps=1))
+        assert st == 0
+        reps.append(rep)
+    s.close()
+    for r in reps:
+        assert 0 <= r["timed_launches"] <= r["sweep_launches"] and 0 <= r["timed_sweeps"] <= r["sweeps"]
+        if r["predicted"]:
+            # passes 2 and 3 are timed, pass 1 is not
+            assert r["timed_sweeps"] == sum(2 * p - 1 for p in r["P"][1:])
+            assert r["timed_launches"] >= 2 and r["sweep_ms"] > 0.0
+        else:
+            assert r["timed_sweeps"] == 0 and r["timed_launches"] == 0 and r["sweep_ms"] == 0.0
+    assert sum(r["predicted"] for r in reps) >= 2
+
+
 @pytest.mark.parametrize("whole", [0, 1])
 def test_pipelined_step_then_report_and_phase_change(whole):
     """A pending pipelined step is completed by set_phase (which may make
