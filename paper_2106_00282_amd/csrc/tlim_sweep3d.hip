@@ -95,8 +95,6 @@ __global__ void __launch_bounds__(64 * kZWaves) k_z3d(Z3Args<R> a) {
     // cells' G, 1/C and the x-halo of plane z+1) are already being loaded.
     R vm[RW], vc[RW], vp[RW], vq[RW], Lm[RW], Lc[RW], Lp[RW], Lq[RW];
     R Gc[ROWS], rc_c[ROWS], Gn[ROWS], rc_n[ROWS], hvc[ROWS], hLc[ROWS], hvn[ROWS], hLn[ROWS];
-    const unsigned hx = (unsigned)(lane == 0 ? xl : xr);
-    const bool halo_lane = lane == 0 || lane == 63;
     auto ld_v = [&](unsigned i) -> R {
         if constexpr (kCorr) return a.G[i] + (R)a.w32[i];
         else return a.v[i];
@@ -114,19 +112,28 @@ __global__ void __launch_bounds__(64 * kZWaves) k_z3d(Z3Args<R> a) {
         }
     };
     // own cells of plane z (clamped into the grid: only used for z < z1):
-    // G and 1/C, and the x-halo cells of the ends of the wave
+    // G and 1/C, and the x-halo cells of the ends of the wave.  The halo
+    // cells of all rows come in one load per field (lane q < ROWS: the left
+    // halo of row q, lane ROWS + q: the right one) and go to the end lanes
+    // by shuffle.
+    const int hq = lane < ROWS ? lane : lane - ROWS;
+    const bool hload = lane < 2 * ROWS;
+    const unsigned hoff = hload ? (unsigned)fold(y0 + hq, ny, a.pery) * (unsigned)nx + (unsigned)(lane < ROWS ? xl : xr)
+                                : 0u;
     auto load_own = [&](int z, R* GG, R* rr, R* hv, R* hL) {
         const unsigned pz = (unsigned)(z < nz ? z : nz - 1) * plane;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             GG[r] = a.G[pz + rowoff[r + 1] + uxi];
             rr[r] = a.rC[pz + rowoff[r + 1] + uxi];
-            hv[r] = R(0);
-            hL[r] = R(0);
-            if (halo_lane) {
-                hv[r] = ld_v(pz + rowoff[r + 1] + hx);
-                hL[r] = ld_L(pz + rowoff[r + 1] + hx);
-            }
+        }
+        const R hvq = hload ? ld_v(pz + hoff) : R(0);
+        const R hLq = hload ? ld_L(pz + hoff) : R(0);
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int src = lane == 63 ? ROWS + r : r;
+            hv[r] = __shfl(hvq, src, 64);
+            hL[r] = __shfl(hLq, src, 64);
         }
     };
     load_plane(z0 - 1, vm, Lm);
@@ -343,8 +350,13 @@ __global__ void __launch_bounds__(64 * kZWaves) k_adj_z3d(AZ3Args a) {
     for (int r = 0; r < RW; ++r) rowoff[r] = (unsigned)fold(y0 - 1 + r, ny, a.pery) * (unsigned)nx;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
     const unsigned uxi = (unsigned)xi;
-    const unsigned hx_i = (unsigned)(lane == 0 ? xl : xr);
-    const bool halo_lane = lane == 0 || lane == 63;
+    // x-halo cells of the end lanes: all rows in one load per field (lane
+    // q < ROWS: the left halo of row q, lane ROWS + q: the right one), handed
+    // to the end lanes by shuffle
+    const int hq = lane < ROWS ? lane : lane - ROWS;
+    const bool hload = lane < 2 * ROWS;
+    const unsigned hoff = hload ? (unsigned)fold(y0 + hq, ny, a.pery) * (unsigned)nx + (unsigned)(lane < ROWS ? xl : xr)
+                                : 0u;
 
     // windows: p (psi), u (v^(m-1)), L (Lambda) of planes z-1 (m), z (c),
     // z+1 (p), z+2 (q)
@@ -370,15 +382,16 @@ __global__ void __launch_bounds__(64 * kZWaves) k_adj_z3d(AZ3Args a) {
             rc[r] = a.rC[o];
             dg[r] = a.dgpsi[o];
             gl[r] = a.gLam[o];
-            hp[r] = 0.0;
-            hu[r] = 0.0;
-            hL[r] = 0.0;
-            if (halo_lane) {
-                const unsigned h = pz + rowoff[r + 1] + hx_i;
-                hp[r] = a.psi[h];
-                hu[r] = a.vprev[h];
-                hL[r] = a.Lam[h];
-            }
+        }
+        const double hpq = hload ? a.psi[pz + hoff] : 0.0;
+        const double huq = hload ? a.vprev[pz + hoff] : 0.0;
+        const double hLq = hload ? a.Lam[pz + hoff] : 0.0;
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int src = lane == 63 ? ROWS + r : r;
+            hp[r] = __shfl(hpq, src, 64);
+            hu[r] = __shfl(huq, src, 64);
+            hL[r] = __shfl(hLq, src, 64);
         }
     };
     load_plane(z0 - 1, pm, um, Lm);
