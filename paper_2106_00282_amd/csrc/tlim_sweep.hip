@@ -8,21 +8,30 @@
 // form is the same update with c = 1.
 //
 // k_tb2d advances K stages per launch.  A workgroup of NW wave64s
-// loads a 64 x (NW*ROWS) extended tile once (v, G, Lambda, 1/C; one
-// coalesced 64-wide row per wave per field), builds the four kappa of every
-// cell in registers, and then runs the K stages out of registers:
-//   - x-neighbours come from the adjacent lanes through DPP wave shifts;
-//   - y-neighbours are the lane's own registers (each lane owns ROWS
-//     consecutive cells of one column), except at the seams between waves,
-//     which go through a double-buffered LDS row (one barrier per stage).
+// loads an extended tile once (v, G, Lambda, 1/C; coalesced rows, one per
+// wave and field), builds the four kappa of every cell in registers, and
+// then runs the K stages out of registers:
+//   - each lane owns C adjacent cells of a row (C = 1 or 2): x-neighbours
+//     come from the lane's own cells or from the adjacent lanes through DPP
+//     wave shifts;
+//   - y-neighbours are the lane's own registers (each lane owns 8/C
+//     consecutive rows), except at the seams between waves, which go
+//     through a double-buffered LDS row (one barrier per stage).
 // Cells within K of the extended tile's edge go stale one ring per stage;
-// the inner (64-2K) x (NW*ROWS-2K) cells are exact and written out.
-// Grids of at least 128 rows use 16 waves (128-row tiles, one workgroup per
-// CU, up to 10 stages per launch), smaller ones 8 waves (64-row tiles, up to
-// 8 stages).  Every workgroup of a launch is resident at once on the 1024^2
-// grids, so a launch costs one load phase plus its stages: the taller tile
-// halves the halo per stage and lets a Picard pass of 15-20 stages run in
-// two launches instead of three.
+// the inner (64C-2K) x (NW*8/C-2K) cells are exact and written out.
+// Grids of at least 128 rows use 16 waves (64 x 128 tiles, or for the float
+// stages on grids of at least 128 columns 128 x 64 tiles with two cells per
+// lane), smaller ones 8 waves (64 x 64, up to 8 stages); one workgroup per
+// CU, up to 10 stages per launch.  Every workgroup of a launch is resident at
+// once on the 1024^2 grids, so a launch costs one load phase plus its stages:
+// the 16-wave tiles halve the halo per stage against 64 x 64 and let a Picard
+// pass of 15-20 stages run in two launches instead of three.  A 64-wide row
+// of floats spans 3 cache lines for 2 lines of data (the rows start where
+// the tile falls), a 128-wide one 5 for 4, and the lane's two cells come in
+// one load: the FP32 form's launches that reach the final stage take 10%
+// less time on the 128 x 64 tiles.  The double kernels gain nothing from
+// them (5 lines for 4 against 9 for 8; the launch that relaxes and builds the
+// next step's start runs slower), so they keep the 64 x 128 tiles.
 // Bytes per launch: 4 words read per extended cell + 1 word written per
 // output cell, for K stages.
 #include <hip/hip_runtime.h>
@@ -41,6 +50,7 @@ using tb::lane_value;
 constexpr int KMAX_TB = 10;     // stages per launch, 16-wave tiles
 constexpr int KMAX_SHORT = 8;   // stages per launch, 8-wave tiles
 constexpr int TALL_ROWS = 128;  // grids with at least this many rows use 16-wave tiles
+constexpr int WIDE_COLS = 128;  // ... and 128-wide ones (two cells per lane) with at least this many columns
 using tb::from_left;
 using tb::from_right;
 using tb::fmean;
@@ -87,20 +97,24 @@ struct TBArgs {
     DevPhases ph;
     int nx, ny, perx, pery;
     R wx, wy, tau;
-    int K, H, face, tiles_x, ox, oy;
+    int K, H, hx, face, tiles_x, ox, oy;
     double taud;
     double tb[KMAX_TB], chat[KMAX_TB];
 };
 
 // kSH: the conductivities built in the epilogue follow the Spitzer-Harm law
 // in some phase (its logarithms would otherwise take registers from the
-// power-law kernels).
-template <typename R, int NW, bool kKeep, bool kSH>
+// power-law kernels).  C: cells per lane along x (1: 64-wide tiles of 8 rows
+// per wave; 2: 128-wide tiles of 4 rows per wave, lane l owning cells 2l and
+// 2l + 1, so that one of each cell's x-neighbours is in the lane itself).
+template <typename R, int NW, int C, bool kKeep, bool kSH>
 __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
     constexpr int WAVES = NW;
-    constexpr int EXT_Y = NW * ROWS;
-    __shared__ R sh_lo[2][WAVES][64];  // row 0 of each wave (the "up" row of the wave below)
-    __shared__ R sh_hi[2][WAVES][64];  // row ROWS-1 of each wave (the "down" row of the wave above)
+    constexpr int RW = ROWS / C;       // rows per wave
+    constexpr int EXT_X = 64 * C;
+    constexpr int EXT_Y = NW * RW;
+    __shared__ R sh_lo[2][WAVES][C][64];  // row 0 of each wave (the "up" row of the wave below)
+    __shared__ R sh_hi[2][WAVES][C][64];  // row RW-1 of each wave (the "down" row of the wave above)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // Lambda of a cell in the epilogues (rho = m1 + m2 used only under the
     // Spitzer-Harm law)
@@ -108,15 +122,54 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
         if constexpr (kSH) return phys::cell_conductivity(a.ph, t, a2, m1 + m2);
         else return phys::cell_conductivity_pow(a.ph, t, a2);
     };
+    // x-neighbours of cell j of this lane, from the lane's own cells or the
+    // adjacent lanes (j is a compile-time index in the unrolled loops)
+    auto left_of = [&](const auto (&x)[C], int j) { return j > 0 ? x[j - 1] : from_left(x[C - 1]); };
+    auto right_of = [&](const auto (&x)[C], int j) { return j < C - 1 ? x[j + 1] : from_right(x[0]); };
     const int K = a.K, H = a.H;
+    // the x ring: H, or with two cells per lane H rounded up to even, so that
+    // the tile starts at an even column and a lane's two cells are adjacent
+    // in memory (periodic x with an even width, or clamped walls)
+    const int HX = a.hx;
     const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
-    const int xg = tx * a.ox - H + lane;
-    const int yg0 = ty * a.oy - H + wv * ROWS;
-    const int xi = fold(xg, a.nx, a.perx);
+    const int yg0 = ty * a.oy - H + wv * RW;
     const int yi0 = fold(yg0, a.ny, a.pery);
-    const bool inx = xg >= 0 && xg < a.nx;
-    const bool fL = a.perx ? a.nx > 1 : (inx && xg > 0);
-    const bool fR = a.perx ? a.nx > 1 : (inx && xg < a.nx - 1);
+    int xg[C], xi[C];
+    bool fL[C], fR[C];
+    // output column: cell j of this lane is at least HX in from the tile's x edges
+    bool xo[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        const int xl = C * lane + j;
+        xg[j] = tx * a.ox - HX + xl;
+        xi[j] = fold(xg[j], a.nx, a.perx);
+        const bool inx = xg[j] >= 0 && xg[j] < a.nx;
+        fL[j] = a.perx ? a.nx > 1 : (inx && xg[j] > 0);
+        fR[j] = a.perx ? a.nx > 1 : (inx && xg[j] < a.nx - 1);
+        xo[j] = xl >= HX && xl < EXT_X - HX && xg[j] < a.nx;
+    }
+    // Two cells per lane come in one load of two words at column sx: the
+    // pair (xi0, xi0 + 1) away from the walls, the clamped copies (both the
+    // wall cell) beyond them; sel_j tells which word is cell j.
+    const int sx = C == 2 ? min(xi[0], a.nx - 2) : xi[0];
+    bool sel[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) sel[j] = xi[j] == sx;
+    // first word of row r of the tile's lane (formed once per row: every
+    // field's load of the row shares it)
+    auto row_at = [&](int r) -> int64_t { return (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + sx; };
+    auto ld = [&](const auto* f, int64_t o, auto (&out)[C]) {
+        if constexpr (C == 1) {
+            out[0] = f[o];
+        } else {
+            using T = std::remove_cv_t<std::remove_reference_t<decltype(f[0])>>;
+            struct alignas(sizeof(T)) Pair { T x, y; } pr;
+            __builtin_memcpy(&pr, f + o, sizeof(Pair));
+#pragma unroll
+            for (int j = 0; j < C; ++j) out[j] = sel[j] ? pr.x : pr.y;
+        }
+    };
+    auto yout = [&](int r) { const int row = wv * RW + r; return row >= H && row < EXT_Y - H && yg0 + r < a.ny; };
 
     constexpr bool kFloat = sizeof(R) == 4;
     const bool fin = kFloat && a.g64 != nullptr;
@@ -124,70 +177,95 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
     // the four kappa and v already take 80 of the 128 VGPRs that four
     // workgroups per CU leave, and G in registers spills.
     constexpr bool kGinLds = !kFloat;
-    __shared__ R sG[kGinLds ? EXT_Y : 1][64];
-    R v[ROWS], G[ROWS], kL[ROWS], kR[ROWS], kD[ROWS], kU[ROWS];
+    __shared__ R sG[kGinLds ? EXT_Y : 1][C][64];
+    R v[RW][C], G[RW][C], kL[RW][C], kR[RW][C], kD[RW][C], kU[RW][C];
     const bool same = a.v == a.G;
-    R Lk[ROWS];     // cell conductivities, kept for a fused FP64 final stage
-    R Ldk = 0, Luk = 0;
+    R Lk[RW][C];     // cell conductivities, kept for a fused FP64 final stage
+    R Ldk[C], Luk[C];
     {
-        R L[ROWS], t[ROWS];
+        R L[RW][C], t[RW][C];
         if constexpr (kFloat) {
             // every row's words in flight before the first is used (the
             // double kernels load row by row, as in the epilogue)
-            int64_t idx[ROWS];
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) idx[r] = (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + xi;
-#pragma unroll
-            for (int r = 0; r < ROWS; ++r) {
-                v[r] = a.v[idx[r]];
-                L[r] = a.Lam[idx[r]];
-                t[r] = a.rC[idx[r]];
+            for (int r = 0; r < RW; ++r) {
+                const int64_t o = row_at(r);
+                ld(a.v, o, v[r]);
+                ld(a.Lam, o, L[r]);
+                ld(a.rC, o, t[r]);
             }
             // the first launch of a pass starts from v^(0) = T^n = g
             if (same) {
 #pragma unroll
-                for (int r = 0; r < ROWS; ++r) G[r] = v[r];
+                for (int r = 0; r < RW; ++r)
+#pragma unroll
+                    for (int j = 0; j < C; ++j) G[r][j] = v[r][j];
             } else {
 #pragma unroll
-                for (int r = 0; r < ROWS; ++r) G[r] = a.G[idx[r]];
+                for (int r = 0; r < RW; ++r) ld(a.G, row_at(r), G[r]);
             }
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) t[r] = a.tau * t[r];
-        } else {
+            for (int r = 0; r < RW; ++r)
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) {
-                const int64_t idx = (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + xi;
-                v[r] = a.v[idx];
-                // the first launch of a pass starts from v^(0) = T^n = g
-                sG[wv * ROWS + r][lane] = same ? v[r] : a.G[idx];
-                L[r] = a.Lam[idx];
-                t[r] = a.tau * a.rC[idx];
+                for (int j = 0; j < C; ++j) t[r][j] = a.tau * t[r][j];
+        } else {
+            // G is read even where it is v (the first launch of a pass starts
+            // from v^(0) = T^n = g: the same words, served by the cache), so
+            // that a row's four loads issue together
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                R Gr[C];
+                const int64_t o = row_at(r);
+                ld(a.v, o, v[r]);
+                ld(a.G, o, Gr);
+                ld(a.Lam, o, L[r]);
+                ld(a.rC, o, t[r]);
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    sG[wv * RW + r][j][lane] = same ? v[r][j] : Gr[j];
+                    t[r][j] = a.tau * t[r][j];
+                }
             }
         }
-        sh_lo[0][wv][lane] = L[0];
-        sh_hi[0][wv][lane] = L[ROWS - 1];
-        __syncthreads();
-        const R Ldn = wv > 0 ? sh_hi[0][wv - 1][lane] : L[0];
-        const R Lup = wv < WAVES - 1 ? sh_lo[0][wv + 1][lane] : L[ROWS - 1];
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
+        for (int j = 0; j < C; ++j) {
+            sh_lo[0][wv][j][lane] = L[0][j];
+            sh_hi[0][wv][j][lane] = L[RW - 1][j];
+        }
+        __syncthreads();
+        R Ldn[C], Lup[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            Ldn[j] = wv > 0 ? sh_hi[0][wv - 1][j][lane] : L[0][j];
+            Lup[j] = wv < WAVES - 1 ? sh_lo[0][wv + 1][j][lane] : L[RW - 1][j];
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
             const int y = yg0 + r;
             const bool iny = y >= 0 && y < a.ny;
             const bool fD = a.pery ? a.ny > 1 : (iny && y > 0);
             const bool fU = a.pery ? a.ny > 1 : (iny && y < a.ny - 1);
-            const R Ll = from_left(L[r]), Lr = from_right(L[r]);
-            const R Ld = r > 0 ? L[r - 1] : Ldn;
-            const R Lu = r < ROWS - 1 ? L[r + 1] : Lup;
-            kL[r] = fL ? t[r] * a.wx * fmean<R>(L[r], Ll, a.face) : R(0);
-            kR[r] = fR ? t[r] * a.wx * fmean<R>(L[r], Lr, a.face) : R(0);
-            kD[r] = fD ? t[r] * a.wy * fmean<R>(L[r], Ld, a.face) : R(0);
-            kU[r] = fU ? t[r] * a.wy * fmean<R>(L[r], Lu, a.face) : R(0);
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const R Ll = left_of(L[r], j), Lr = right_of(L[r], j);
+                const R Ld = r > 0 ? L[r - 1][j] : Ldn[j];
+                const R Lu = r < RW - 1 ? L[r + 1][j] : Lup[j];
+                kL[r][j] = fL[j] ? t[r][j] * a.wx * fmean<R>(L[r][j], Ll, a.face) : R(0);
+                kR[r][j] = fR[j] ? t[r][j] * a.wx * fmean<R>(L[r][j], Lr, a.face) : R(0);
+                kD[r][j] = fD ? t[r][j] * a.wy * fmean<R>(L[r][j], Ld, a.face) : R(0);
+                kU[r][j] = fU ? t[r][j] * a.wy * fmean<R>(L[r][j], Lu, a.face) : R(0);
+            }
         }
         if constexpr (kFloat) {
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) Lk[r] = L[r];
-            Ldk = Ldn;
-            Luk = Lup;
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int j = 0; j < C; ++j) Lk[r][j] = L[r][j];
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                Ldk[j] = Ldn[j];
+                Luk[j] = Lup[j];
+            }
         }
     }
     // lambda_G of the pass from its accumulator row (every wave folds it)
@@ -212,86 +290,106 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
     const int wdn = wv > 0 ? wv - 1 : 0, wup = wv < WAVES - 1 ? wv + 1 : wv;
     for (int s = 0; s < Kin; ++s) {
         const int buf = (s + 1) & 1;
-        sh_lo[buf][wv][lane] = v[0];
-        sh_hi[buf][wv][lane] = v[ROWS - 1];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            sh_lo[buf][wv][j][lane] = v[0][j];
+            sh_hi[buf][wv][j][lane] = v[RW - 1][j];
+        }
         __syncthreads();
-        const R sdn = sh_hi[buf][wdn][lane], sup = sh_lo[buf][wup][lane];
-        const R vdn = wv > 0 ? sdn : v[0];
-        const R vup = wv < WAVES - 1 ? sup : v[ROWS - 1];
+        R vup[C], ddn[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const R sdn = sh_hi[buf][wdn][j][lane], sup = sh_lo[buf][wup][j][lane];
+            const R vdn = wv > 0 ? sdn : v[0][j];
+            vup[j] = wv < WAVES - 1 ? sup : v[RW - 1][j];
+            ddn[j] = v[0][j] - vdn;
+        }
         const double tbd = lane_value(ptb, s);
         const R cm = (R)lane_value(pcm, s), tb = (R)tbd;
         // Each face difference is formed once and shared by the face's two
         // cells: c - c_left is minus the left neighbour's c - c_right, and
         // c - c_below minus the row below's c - c_above (exact in floating
         // point, so S is the same number as with four differences per cell).
-        R ddn = v[0] - vdn;
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            const R c = v[r];
-            const R up = r < ROWS - 1 ? v[r + 1] : vup;
-            const R drt = c - from_right(c);
-            const R dlf = -from_left(drt);
-            const R dup = c - up;
-            const R S = kL[r] * dlf + kR[r] * drt + kD[r] * ddn + kU[r] * dup;
-            R Gr;
-            if constexpr (kGinLds) Gr = sG[wv * ROWS + r][lane];
-            else Gr = G[r];
-            v[r] = cm * (Gr + tb * c - S);
-            ddn = -dup;
+        for (int r = 0; r < RW; ++r) {
+            R drt[C];
+#pragma unroll
+            for (int j = 0; j < C; ++j) drt[j] = v[r][j] - right_of(v[r], j);
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const R c = v[r][j];
+                const R up = r < RW - 1 ? v[r + 1][j] : vup[j];
+                const R dlf = -left_of(drt, j);
+                const R dup = c - up;
+                const R S = kL[r][j] * dlf + kR[r][j] * drt[j] + kD[r][j] * ddn[j] + kU[r][j] * dup;
+                R Gr;
+                if constexpr (kGinLds) Gr = sG[wv * RW + r][j][lane];
+                else Gr = G[r][j];
+                v[r][j] = cm * (Gr + tb * c - S);
+                ddn[j] = -dup;
+            }
         }
         // the output cells are exact after every stage: keep the intermediate
         // stages when asked (the adjoint's recomputation)
-        if (kKeep && s + 1 < K && lane >= H && lane < 64 - H && xg < a.nx) {
+        if (kKeep && s + 1 < K) {
             R* dst = a.stages + (int64_t)(s + 1) * a.sstride;
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) {
-                const int row = wv * ROWS + r;
-                const int y = yg0 + r;
-                if (row >= H && row < EXT_Y - H && y < a.ny) dst[(int64_t)y * a.nx + xg] = v[r];
-            }
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int j = 0; j < C; ++j)
+                    if (xo[j] && yout(r)) dst[(int64_t)(yg0 + r) * a.nx + xg[j]] = v[r][j];
         }
     }
     // Final stage (b = 0) of the FP32 correction form, in double on v = g + w:
     // T = g - tau rC64 sum_f w_f mean(Lambda'_a, Lambda'_b) (v_a - v_b), with
     // Lambda' the float conductivities.  Sfin holds the flux sum, gfin g.
-    double Sfin[ROWS], gfin[ROWS];
+    double Sfin[RW][C], gfin[RW][C];
     if constexpr (kFloat) {
         if (fin) {
-            __shared__ double dsh_lo[WAVES][64], dsh_hi[WAVES][64];
-            double vf[ROWS];
+            __shared__ double dsh_lo[WAVES][C][64], dsh_hi[WAVES][C][64];
+            double vf[RW][C];
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) {
-                const int64_t idx = (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + xi;
-                gfin[r] = a.g64[idx];
-                vf[r] = gfin[r] + (double)v[r];
+            for (int r = 0; r < RW; ++r) ld(a.g64, row_at(r), gfin[r]);
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int j = 0; j < C; ++j) vf[r][j] = gfin[r][j] + (double)v[r][j];
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                dsh_lo[wv][j][lane] = vf[0][j];
+                dsh_hi[wv][j][lane] = vf[RW - 1][j];
             }
-            dsh_lo[wv][lane] = vf[0];
-            dsh_hi[wv][lane] = vf[ROWS - 1];
             __syncthreads();
-            const double vdn = wv > 0 ? dsh_hi[wv - 1][lane] : vf[0];
-            const double vup = wv < WAVES - 1 ? dsh_lo[wv + 1][lane] : vf[ROWS - 1];
-            const double wxd = a.g64w[0], wyd = a.g64w[1];
-            double prev = vdn;
+            double vup[C], prev[C];
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) {
+            for (int j = 0; j < C; ++j) {
+                prev[j] = wv > 0 ? dsh_hi[wv - 1][j][lane] : vf[0][j];
+                vup[j] = wv < WAVES - 1 ? dsh_lo[wv + 1][j][lane] : vf[RW - 1][j];
+            }
+            const double wxd = a.g64w[0], wyd = a.g64w[1];
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
                 const int y = yg0 + r;
                 const bool iny = y >= 0 && y < a.ny;
                 const bool fD = a.pery ? a.ny > 1 : (iny && y > 0);
                 const bool fU = a.pery ? a.ny > 1 : (iny && y < a.ny - 1);
-                const double c = vf[r];
-                const double up = r < ROWS - 1 ? vf[r + 1] : vup;
-                const double La = (double)Lk[r];
-                const double Ll = (double)from_left(Lk[r]), Lr = (double)from_right(Lk[r]);
-                const double Ld = (double)(r > 0 ? Lk[r - 1] : Ldk);
-                const double Lu = (double)(r < ROWS - 1 ? Lk[r + 1] : Luk);
-                const double lf = from_left(c), rt = from_right(c);
-                double S = 0.0;
-                if (fL) S += wxd * fmean<double>(La, Ll, a.face) * (c - lf);
-                if (fR) S += wxd * fmean<double>(La, Lr, a.face) * (c - rt);
-                if (fD) S += wyd * fmean<double>(La, Ld, a.face) * (c - prev);
-                if (fU) S += wyd * fmean<double>(La, Lu, a.face) * (c - up);
-                prev = c;
-                Sfin[r] = S;
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    const double c = vf[r][j];
+                    const double up = r < RW - 1 ? vf[r + 1][j] : vup[j];
+                    const double La = (double)Lk[r][j];
+                    const double Ll = (double)left_of(Lk[r], j), Lr = (double)right_of(Lk[r], j);
+                    const double Ld = (double)(r > 0 ? Lk[r - 1][j] : Ldk[j]);
+                    const double Lu = (double)(r < RW - 1 ? Lk[r + 1][j] : Luk[j]);
+                    const double lf = left_of(vf[r], j), rt = right_of(vf[r], j);
+                    double S = 0.0;
+                    if (fL[j]) S += wxd * fmean<double>(La, Ll, a.face) * (c - lf);
+                    if (fR[j]) S += wxd * fmean<double>(La, Lr, a.face) * (c - rt);
+                    if (fD) S += wyd * fmean<double>(La, Ld, a.face) * (c - prev[j]);
+                    if (fU) S += wyd * fmean<double>(La, Lu, a.face) * (c - up);
+                    prev[j] = c;
+                    Sfin[r][j] = S;
+                }
             }
             if (a.lam_next) {
                 // Coefficients of the next Picard pass at the new iterate T
@@ -299,61 +397,78 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                 // in double for the bound, its float rounding and the source
                 // q = -tau rC' D' g from the float-rounded Lambda' and rC', at
                 // the output cells (K+1 in), faces in the order -x, +x, -y, +y.
-                double Ln[ROWS], rc[ROWS], a2v[ROWS], m1v[ROWS], m2v[ROWS];
+                double Ln[RW][C], rc[RW][C], a2v[RW][C], m1v[RW][C], m2v[RW][C];
 #pragma unroll
-                for (int r = 0; r < ROWS; ++r) {
-                    const int64_t idx = (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + xi;
-                    rc[r] = a.rC64[idx];
-                    a2v[r] = a.alpha2[idx];
-                    m1v[r] = kSH ? a.m1[idx] : 0.0;
-                    m2v[r] = kSH ? a.m2[idx] : 0.0;
+                for (int r = 0; r < RW; ++r) {
+                    const int64_t o = row_at(r);
+                    ld(a.rC64, o, rc[r]);
+                    ld(a.alpha2, o, a2v[r]);
+                    if constexpr (kSH) {
+                        ld(a.m1, o, m1v[r]);
+                        ld(a.m2, o, m2v[r]);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < C; ++j) m1v[r][j] = m2v[r][j] = 0.0;
+                    }
                 }
 #pragma unroll
-                for (int r = 0; r < ROWS; ++r) {
-                    const double tn = gfin[r] - a.taud * rc[r] * Sfin[r];
-                    Ln[r] = law(tn, a2v[r], m1v[r], m2v[r]);
+                for (int r = 0; r < RW; ++r)
+#pragma unroll
+                    for (int j = 0; j < C; ++j) {
+                        const double tn = gfin[r][j] - a.taud * rc[r][j] * Sfin[r][j];
+                        Ln[r][j] = law(tn, a2v[r][j], m1v[r][j], m2v[r][j]);
+                    }
+                __shared__ double esh[4][WAVES][C][64];  // seams of Lambda and g
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    esh[0][wv][j][lane] = Ln[0][j];
+                    esh[1][wv][j][lane] = Ln[RW - 1][j];
+                    esh[2][wv][j][lane] = gfin[0][j];
+                    esh[3][wv][j][lane] = gfin[RW - 1][j];
                 }
-                __shared__ double esh[4][WAVES][64];  // seams of Lambda and g
-                esh[0][wv][lane] = Ln[0];
-                esh[1][wv][lane] = Ln[ROWS - 1];
-                esh[2][wv][lane] = gfin[0];
-                esh[3][wv][lane] = gfin[ROWS - 1];
                 __syncthreads();
-                const double Ldn = wv > 0 ? esh[1][wv - 1][lane] : Ln[0];
-                const double Lup = wv < WAVES - 1 ? esh[0][wv + 1][lane] : Ln[ROWS - 1];
-                const double gdn = wv > 0 ? esh[3][wv - 1][lane] : gfin[0];
-                const double gup = wv < WAVES - 1 ? esh[2][wv + 1][lane] : gfin[ROWS - 1];
-                const double wxd = a.g64w[0], wyd = a.g64w[1];
+                double Ldn[C], Lup[C], gdn[C], gup[C];
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    Ldn[j] = wv > 0 ? esh[1][wv - 1][j][lane] : Ln[0][j];
+                    Lup[j] = wv < WAVES - 1 ? esh[0][wv + 1][j][lane] : Ln[RW - 1][j];
+                    gdn[j] = wv > 0 ? esh[3][wv - 1][j][lane] : gfin[0][j];
+                    gup[j] = wv < WAVES - 1 ? esh[2][wv + 1][j][lane] : gfin[RW - 1][j];
+                }
                 double bound = 0.0;
 #pragma unroll
-                for (int r = 0; r < ROWS; ++r) {
-                    const double L = Ln[r];
-                    const double Ll = from_left(L), Lr = from_right(L);
-                    const float Lf = (float)L;
-                    const float Llf = from_left(Lf), Lrf = from_right(Lf);
-                    const double gl = from_left(gfin[r]), gr = from_right(gfin[r]);
-                    const double Ld = r > 0 ? Ln[r - 1] : Ldn, Lu = r < ROWS - 1 ? Ln[r + 1] : Lup;
-                    const double gd = r > 0 ? gfin[r - 1] : gdn, gu = r < ROWS - 1 ? gfin[r + 1] : gup;
-                    const int row = wv * ROWS + r;
-                    const int y = yg0 + r;
-                    if (lane >= H && lane < 64 - H && xg < a.nx && row >= H && row < EXT_Y - H && y < a.ny) {
-                        const bool fD = a.pery ? a.ny > 1 : y > 0;
-                        const bool fU = a.pery ? a.ny > 1 : y < a.ny - 1;
-                        const int64_t o = (int64_t)y * a.nx + xg;
-                        double d = 0.0;
-                        if (fL) d += wxd * fmean<double>(L, Ll, a.face);
-                        if (fR) d += wxd * fmean<double>(L, Lr, a.face);
-                        if (fD) d += wyd * fmean<double>(L, Ld, a.face);
-                        if (fU) d += wyd * fmean<double>(L, Lu, a.face);
-                        bound = fmax(bound, 2.0 * d * rc[r]);
-                        const double La = (double)Lf, rf = (double)(float)rc[r], ga = gfin[r];
-                        double Sq = 0.0;
-                        if (fL) Sq += wxd * fmean<double>(La, (double)Llf, a.face) * (ga - gl);
-                        if (fR) Sq += wxd * fmean<double>(La, (double)Lrf, a.face) * (ga - gr);
-                        if (fD) Sq += wyd * fmean<double>(La, (double)(float)Ld, a.face) * (ga - gd);
-                        if (fU) Sq += wyd * fmean<double>(La, (double)(float)Lu, a.face) * (ga - gu);
-                        a.Lam32_next[o] = Lf;
-                        a.q32_next[o] = (float)(-a.taud * rf * Sq);
+                for (int r = 0; r < RW; ++r) {
+                    float Lf[C];
+#pragma unroll
+                    for (int j = 0; j < C; ++j) Lf[j] = (float)Ln[r][j];
+#pragma unroll
+                    for (int j = 0; j < C; ++j) {
+                        const double L = Ln[r][j];
+                        const double Ll = left_of(Ln[r], j), Lr = right_of(Ln[r], j);
+                        const float Llf = left_of(Lf, j), Lrf = right_of(Lf, j);
+                        const double gl = left_of(gfin[r], j), gr = right_of(gfin[r], j);
+                        const double Ld = r > 0 ? Ln[r - 1][j] : Ldn[j], Lu = r < RW - 1 ? Ln[r + 1][j] : Lup[j];
+                        const double gd = r > 0 ? gfin[r - 1][j] : gdn[j], gu = r < RW - 1 ? gfin[r + 1][j] : gup[j];
+                        const int y = yg0 + r;
+                        if (xo[j] && yout(r)) {
+                            const bool fD = a.pery ? a.ny > 1 : y > 0;
+                            const bool fU = a.pery ? a.ny > 1 : y < a.ny - 1;
+                            const int64_t o = (int64_t)y * a.nx + xg[j];
+                            double d = 0.0;
+                            if (fL[j]) d += wxd * fmean<double>(L, Ll, a.face);
+                            if (fR[j]) d += wxd * fmean<double>(L, Lr, a.face);
+                            if (fD) d += wyd * fmean<double>(L, Ld, a.face);
+                            if (fU) d += wyd * fmean<double>(L, Lu, a.face);
+                            bound = fmax(bound, 2.0 * d * rc[r][j]);
+                            const double La = (double)Lf[j], rf = (double)(float)rc[r][j], ga = gfin[r][j];
+                            double Sq = 0.0;
+                            if (fL[j]) Sq += wxd * fmean<double>(La, (double)Llf, a.face) * (ga - gl);
+                            if (fR[j]) Sq += wxd * fmean<double>(La, (double)Lrf, a.face) * (ga - gr);
+                            if (fD) Sq += wyd * fmean<double>(La, (double)(float)Ld, a.face) * (ga - gd);
+                            if (fU) Sq += wyd * fmean<double>(La, (double)(float)Lu, a.face) * (ga - gu);
+                            a.Lam32_next[o] = Lf[j];
+                            a.q32_next[o] = (float)(-a.taud * rf * Sq);
+                        }
                     }
                 }
 #pragma unroll
@@ -370,56 +485,63 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
     // the first pass's previous iterate is T^n = g, already on chip
     const bool tit_is_g = kFloat ? (fin && a.Tit == a.g64) : (const void*)a.Tit == (const void*)a.G;
     // Float kernels read the epilogue's words of every row up front, before
-    // any is used (bit r of outm: row r of this lane is an output cell).  The
-    // double kernels read them row by row: there the registers that batching
-    // takes cost more than the load order gains (measured).
+    // any is used (bit r*C + j of outm: cell j of row r of this lane is an
+    // output cell).  The double kernels read them row by row: there the
+    // registers that batching takes cost more than the load order gains
+    // (measured).
     unsigned outm = 0;
-    if (lane >= H && lane < 64 - H && xg < a.nx) {
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            const int row = wv * ROWS + r;
-            if (row >= H && row < EXT_Y - H && yg0 + r < a.ny) outm |= 1u << r;
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int j = 0; j < C; ++j)
+            if (xo[j] && yout(r)) outm |= 1u << (r * C + j);
+    auto out_at = [&](int r, int j) -> int64_t {
+        return (outm >> (r * C + j)) & 1u ? (int64_t)(yg0 + r) * a.nx + xg[j] : 0;
+    };
+    double titv[RW][C], rcf[RW][C];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            titv[r][j] = 0.0;
+            rcf[r][j] = 0.0;
         }
-    }
-    auto out_at = [&](int r) -> int64_t { return (outm >> r) & 1u ? (int64_t)(yg0 + r) * a.nx + xg : 0; };
-    double titv[ROWS], rcf[ROWS];
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        titv[r] = 0.0;
-        rcf[r] = 0.0;
-    }
     if constexpr (kFloat) {
         if (a.Tit && !tit_is_g) {
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) titv[r] = a.Tit[out_at(r)];
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int j = 0; j < C; ++j) titv[r][j] = a.Tit[out_at(r, j)];
         }
         if (fin) {
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) rcf[r] = a.rC64[out_at(r)];
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int j = 0; j < C; ++j) rcf[r][j] = a.rC64[out_at(r, j)];
         }
     }
-    if (lane >= H && lane < 64 - H && xg < a.nx) {
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            const int row = wv * ROWS + r;
-            if (row >= H && row < EXT_Y - H && yg0 + r < a.ny) {
-                const int64_t o = (int64_t)(yg0 + r) * a.nx + xg;
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            if ((outm >> (r * C + j)) & 1u) {
+                const int64_t o = (int64_t)(yg0 + r) * a.nx + xg[j];
                 double tnew;
                 if (fin) {
-                    tnew = gfin[r] - a.taud * rcf[r] * Sfin[r];
+                    tnew = gfin[r][j] - a.taud * rcf[r][j] * Sfin[r][j];
                     a.out64[o] = tnew;
                 } else {
-                    a.out[o] = v[r];
-                    tnew = (double)v[r];
+                    a.out[o] = v[r][j];
+                    tnew = (double)v[r][j];
                 }
                 if (a.Tit) {
                     const double tn = tnew;
                     double tit;
                     if (tit_is_g) {
-                        if constexpr (kFloat) tit = gfin[r];
-                        else tit = (double)sG[wv * ROWS + r][lane];
+                        if constexpr (kFloat) tit = gfin[r][j];
+                        else tit = (double)sG[wv * RW + r][j][lane];
                     } else {
-                        if constexpr (kFloat) tit = titv[r];
+                        if constexpr (kFloat) tit = titv[r][j];
                         else tit = a.Tit[o];
                     }
                     dmax = fmax(dmax, fabs(tn - tit));
@@ -428,7 +550,6 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                 }
             }
         }
-    }
     if (a.Tit) {
         // wave-level fold, then lane 0 of every wave adds to a slot of the rows
 #pragma unroll
@@ -453,56 +574,71 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
             // With m1 the next step's instead: every cell relaxed from
             // (alpha2, v, v, m1, m2) first, Lambda and 1/C at the relaxed state.
             const bool next_step = a.next_step != 0;
-            double Ln[ROWS], Tr[ROWS], ar[ROWS], rr[ROWS];
+            double Ln[RW][C], Tr[RW][C], ar[RW][C], rr[RW][C];
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) {
-                const int64_t idx = (int64_t)row_index(yi0, yg0, r, a.ny, a.pery) * a.nx + xi;
-                const double a2v = a.alpha2[idx];
-                if (next_step) {
-                    const double m1 = a.m1[idx], m2 = a.m2[idx];
-                    phys::relax_cell(a.ph, a.eps, a2v, v[r], v[r], m1, m2, Tr[r], ar[r]);
-                    rr[r] = phys::inv_heat_capacity(a.ph, a.eps, Tr[r], ar[r], m1, m2);
-                    Ln[r] = law(Tr[r], ar[r], m1, m2);
-                } else if constexpr (kSH) {
-                    Ln[r] = law(v[r], a2v, a.m1[idx], a.m2[idx]);
-                } else {
-                    Ln[r] = law(v[r], a2v, 0.0, 0.0);
+            for (int r = 0; r < RW; ++r) {
+                double a2v[C], m1[C], m2[C];
+                const int64_t o = row_at(r);
+                ld(a.alpha2, o, a2v);
+                if (next_step || kSH) {
+                    ld(a.m1, o, m1);
+                    ld(a.m2, o, m2);
+                }
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    if (next_step) {
+                        phys::relax_cell(a.ph, a.eps, a2v[j], v[r][j], v[r][j], m1[j], m2[j], Tr[r][j], ar[r][j]);
+                        rr[r][j] = phys::inv_heat_capacity(a.ph, a.eps, Tr[r][j], ar[r][j], m1[j], m2[j]);
+                        Ln[r][j] = law(Tr[r][j], ar[r][j], m1[j], m2[j]);
+                    } else if constexpr (kSH) {
+                        Ln[r][j] = law(v[r][j], a2v[j], m1[j], m2[j]);
+                    } else {
+                        Ln[r][j] = law(v[r][j], a2v[j], 0.0, 0.0);
+                    }
                 }
             }
             // the seam buffer not used by the last stage: its reads all
             // precede that stage's barrier
             const int b2 = (K + 1) & 1;
-            sh_lo[b2][wv][lane] = Ln[0];
-            sh_hi[b2][wv][lane] = Ln[ROWS - 1];
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                sh_lo[b2][wv][j][lane] = Ln[0][j];
+                sh_hi[b2][wv][j][lane] = Ln[RW - 1][j];
+            }
             __syncthreads();
-            const double Ldn = wv > 0 ? sh_hi[b2][wv - 1][lane] : Ln[0];
-            const double Lup = wv < WAVES - 1 ? sh_lo[b2][wv + 1][lane] : Ln[ROWS - 1];
+            double Ldn[C], Lup[C];
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                Ldn[j] = wv > 0 ? sh_hi[b2][wv - 1][j][lane] : Ln[0][j];
+                Lup[j] = wv < WAVES - 1 ? sh_lo[b2][wv + 1][j][lane] : Ln[RW - 1][j];
+            }
             double bound = 0.0;
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) {
-                const double Ll = from_left(Ln[r]), Lr = from_right(Ln[r]);
-                const double Ld = r > 0 ? Ln[r - 1] : Ldn;
-                const double Lu = r < ROWS - 1 ? Ln[r + 1] : Lup;
-                const int row = wv * ROWS + r;
-                const int y = yg0 + r;
-                if (lane >= H && lane < 64 - H && xg < a.nx && row >= H && row < EXT_Y - H && y < a.ny) {
-                    const bool fD = a.pery ? a.ny > 1 : y > 0;
-                    const bool fU = a.pery ? a.ny > 1 : y < a.ny - 1;
-                    const int64_t o = (int64_t)y * a.nx + xg;
-                    double d = 0.0;
-                    if (fL) d += a.wx * fmean<double>(Ln[r], Ll, a.face);
-                    if (fR) d += a.wx * fmean<double>(Ln[r], Lr, a.face);
-                    if (fD) d += a.wy * fmean<double>(Ln[r], Ld, a.face);
-                    if (fU) d += a.wy * fmean<double>(Ln[r], Lu, a.face);
-                    const double rc = next_step ? rr[r] : a.rC[o];
-                    bound = fmax(bound, 2.0 * d * rc);
-                    a.Lam_next[o] = Ln[r];
-                    if (next_step) {
-                        a.Tn_next[o] = Tr[r];
-                        a.a2_next[o] = ar[r];
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    const double Ll = left_of(Ln[r], j), Lr = right_of(Ln[r], j);
+                    const double Ld = r > 0 ? Ln[r - 1][j] : Ldn[j];
+                    const double Lu = r < RW - 1 ? Ln[r + 1][j] : Lup[j];
+                    const int y = yg0 + r;
+                    if (xo[j] && yout(r)) {
+                        const bool fD = a.pery ? a.ny > 1 : y > 0;
+                        const bool fU = a.pery ? a.ny > 1 : y < a.ny - 1;
+                        const int64_t o = (int64_t)y * a.nx + xg[j];
+                        double d = 0.0;
+                        if (fL[j]) d += a.wx * fmean<double>(Ln[r][j], Ll, a.face);
+                        if (fR[j]) d += a.wx * fmean<double>(Ln[r][j], Lr, a.face);
+                        if (fD) d += a.wy * fmean<double>(Ln[r][j], Ld, a.face);
+                        if (fU) d += a.wy * fmean<double>(Ln[r][j], Lu, a.face);
+                        const double rc = next_step ? rr[r][j] : a.rC[o];
+                        bound = fmax(bound, 2.0 * d * rc);
+                        a.Lam_next[o] = Ln[r][j];
+                        if (next_step) {
+                            a.Tn_next[o] = Tr[r][j];
+                            a.a2_next[o] = ar[r][j];
+                        }
                     }
                 }
-            }
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) bound = fmax(bound, __shfl_xor(bound, o, 64));
             if (lane == 0) {
@@ -541,8 +677,13 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
     a.stages = stages;
     a.sstride = sstride;
     const bool tall = g.ny >= TALL_ROWS;
+    // two cells per lane (float stages only): a lane's pair must not
+    // straddle a periodic wrap
+    constexpr bool kWideOk = sizeof(R) == 4;
+    const bool wide = kWideOk && tall && g.nx >= WIDE_COLS && (g.nx % 2 == 0 || !g.per[0]);
     const int kmax = tall ? KMAX_TB : KMAX_SHORT;
-    const int EXT_Y = (tall ? 16 : 8) * ROWS;
+    const int EXT_X = wide ? 128 : 64;
+    const int EXT_Y = wide ? 16 * (ROWS / 2) : (tall ? 16 : 8) * ROWS;
     int K = count < kmax ? count : kmax;
     a.v = v;
     a.G = G;
@@ -563,7 +704,8 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
     a.K = K;
     a.H = nc ? K + 1 : K;
     a.face = face;
-    a.ox = 64 - 2 * a.H;
+    a.hx = wide ? (a.H + 1) & ~1 : a.H;
+    a.ox = EXT_X - 2 * a.hx;
     a.oy = EXT_Y - 2 * a.H;
     a.tiles_x = (g.nx + a.ox - 1) / a.ox;
     int tiles_y = (g.ny + a.oy - 1) / a.oy;
@@ -573,15 +715,28 @@ int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* 
     }
     const dim3 grid((unsigned)(a.tiles_x * tiles_y));
     const bool sh = nc && nc->ph.spitzer;
+    auto go = [&](auto kern, int nw) { hipLaunchKernelGGL(kern, grid, dim3(64 * nw), 0, s, a); };
     if (stages) {  // (no epilogue: the kept-stage launches of the adjoint's recompute)
-        if (tall) hipLaunchKernelGGL((k_tb2d<R, 16, true, false>), grid, dim3(64 * 16), 0, s, a);
-        else hipLaunchKernelGGL((k_tb2d<R, 8, true, false>), grid, dim3(64 * 8), 0, s, a);
+        if (tall) go(k_tb2d<R, 16, 1, true, false>, 16);
+        else go(k_tb2d<R, 8, 1, true, false>, 8);
     } else if (sh) {
-        if (tall) hipLaunchKernelGGL((k_tb2d<R, 16, false, true>), grid, dim3(64 * 16), 0, s, a);
-        else hipLaunchKernelGGL((k_tb2d<R, 8, false, true>), grid, dim3(64 * 8), 0, s, a);
+        if constexpr (kWideOk) {
+            if (wide) {
+                go(k_tb2d<R, 16, 2, false, true>, 16);
+                return K;
+            }
+        }
+        if (tall) go(k_tb2d<R, 16, 1, false, true>, 16);
+        else go(k_tb2d<R, 8, 1, false, true>, 8);
     } else {
-        if (tall) hipLaunchKernelGGL((k_tb2d<R, 16, false, false>), grid, dim3(64 * 16), 0, s, a);
-        else hipLaunchKernelGGL((k_tb2d<R, 8, false, false>), grid, dim3(64 * 8), 0, s, a);
+        if constexpr (kWideOk) {
+            if (wide) {
+                go(k_tb2d<R, 16, 2, false, false>, 16);
+                return K;
+            }
+        }
+        if (tall) go(k_tb2d<R, 16, 1, false, false>, 16);
+        else go(k_tb2d<R, 8, 1, false, false>, 8);
     }
     return K;
 }

@@ -81,6 +81,43 @@ def test_levelset2d_fp64_ragged(shape):
     _compare(fo, fg, FIELDS_T, 1e-12)
 
 
+@pytest.mark.parametrize("precision,shape,bc", [("fp64", (261, 140), "periodic"), ("fp64", (129, 128), "adiabatic"),
+                                                ("fp64", (300, 200), "adiabatic"), ("fp32", (261, 140), "periodic"),
+                                                ("fp32", (129, 128), "adiabatic"), ("fp32", (300, 200), "adiabatic"),
+                                                ("fp32", (260, 150), "periodic")])
+def test_two_cells_per_lane_tiles(precision, shape, bc):
+    """The FP32 form's float stages run 128-wide tiles with two cells per
+    lane on grids of at least 128 x 128 cells (even widths when x is
+    periodic, so that no lane's pair straddles the wrap): an odd periodic
+    width (which keeps one cell per lane), the smallest such grid (a
+    one-column last tile), and adiabatic walls on both axes, where the pairs
+    past the walls are clamped copies; the FP64 path (64 x 128 tiles) on the
+    same grids.  2 steps x 3 passes against the oracle (FP64 1e-12, FP32
+    form 1e-5)."""
+    from oracle import oracle as orc
+    nx, ny = shape
+    ng = max(128, nx, ny)
+    wl = W.levelset2d(ng)
+    for k in wl["fields"]:
+        wl["fields"][k] = np.ascontiguousarray(wl["fields"][k][:, :ny, :nx])
+    wl["n"] = (nx, ny, 1)
+    wl["h"] = (1.0 / ng, 1.0 / ng, 1.0)
+    if bc == "adiabatic":
+        wl["bc"] = (W.ADIABATIC, W.ADIABATIC, W.PERIODIC)
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 2)
+    fg, rg, _ = run_gpu(wl, tau, 2, precision=precision, frozen=_frozen(ro))
+    assert [r["P"] for r in rg] == [r["P"] for r in ro]
+    if precision == "fp64":
+        _compare(fo, fg, FIELDS_T, 1e-12)
+    else:
+        errs = {k: rel_err(fg[k], fo[k]) for k in FIELDS_T}
+        print("fp32 two-cells-per-lane per-field error:", shape, bc, errs)
+        assert max(errs.values()) <= 1e-5
+    for r in rg:
+        assert abs(r["energy_after"] / r["energy_before"] - 1) < 1e-12
+
+
 def test_levelset2d_fp64_full_size():
     """1024^2 periodic, T^2 conductivities, 10 steps x 3 passes at 200x the
     explicit limit (the benchmark workload) against the full oracle run."""
@@ -505,7 +542,8 @@ def test_cycle_mode_reaches_backward_euler():
     assert rel_err(fg["T1"], fo["T1"]) < 1e-13
 
 
-@pytest.mark.parametrize("sources,shape", [(True, (48, 48)), (False, (48, 48)), (False, (70, 33))])
+@pytest.mark.parametrize("sources,shape", [(True, (48, 48)), (False, (48, 48)), (False, (70, 33)),
+                                           (True, (150, 130)), (False, (133, 140))])
 def test_relaxation_unequal_pinf_and_sources(sources, shape):
     """Stiffened-gas phases (p_inf 6e8/0, Sec. 5 constants) out of thermal
     equilibrium, with and without heat sources: relaxation, C_eff, the alpha2
@@ -768,6 +806,31 @@ def test_adjoint_vs_oracle_adjoint():
     ck2, lam2 = s2.forward_checkpointed(opts, steps, 2)
     d2, k2 = s2.adjoint(opts, steps, 2, ck2, lam2, torch.from_numpy(TN - Tstar))
     assert rel_err(d2.cpu().numpy(), dT0.cpu().numpy()) < 1e-13
+
+
+@pytest.mark.parametrize("n", [140, 129])
+def test_adjoint_wide_grids_vs_oracle_adjoint(n):
+    """The adjoint on grids of 16-wave tiles with ragged last tiles (its
+    recompute keeps the stages of the blocked forward kernel), against the
+    oracle's adjoint."""
+    import torch
+    from paper_2106_00282_amd.tlim import StepOpts
+    orc, wl, tau, steps = _adjoint_setup(n=n, steps=2)
+    s = make_solver(wl)
+    opts = StepOpts(dt=tau, passes=3)
+    ckpt, lam = s.forward_checkpointed(opts, steps, 1)
+    TN = s.get_field("T1").cpu().numpy()
+    g = TN - TN.mean()
+    dT0, dk0 = s.adjoint(opts, steps, 1, ckpt, lam, torch.from_numpy(g))
+    f = wl["fields"]
+    odT0, odk0, oTN = orc.heat_adjoint(orc.make_grid(wl["n"], wl["h"], wl["bc"]), wl["phases"],
+                                       orc.StepOpts(tau=tau, passes=3), steps, np.array(lam), f["alpha2"], f["m1"],
+                                       f["m2"], f["T1"], g)
+    assert rel_err(TN, oTN) < 1e-12
+    assert rel_err(dT0.cpu().numpy(), odT0) < 1e-12
+    for k in range(2):
+        assert dk0[k] == pytest.approx(odk0[k], rel=1e-10)
+    s.close()
 
 
 def test_adjoint_in_fp32_context():
