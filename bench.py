@@ -176,7 +176,8 @@ def roofline(r, prec, copy_peak):
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4),
            "traffic": int(traffic) if traffic else None,
-           "kernel": f"k_tb2d<{'double' if prec == 'fp64' else 'float'}, 16> (blocked LIM stages)",
+           "kernel": ("k_tb2d<double, 16, 1> (blocked LIM stages, 64 x 128 tiles)" if prec == "fp64" else
+                      "k_tb2d<float, 16, 2> (blocked LIM stages, 128 x 64 tiles, two cells per lane)"),
            "avg_launch_us": round(avg_s * 1e6, 3), "stages_per_launch": round(stages, 3),
            "compulsory_bytes_per_launch": int(compulsory),
            "traffic_over_compulsory": round(traffic / compulsory, 3) if traffic else None,

@@ -209,20 +209,31 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
 #pragma unroll
                 for (int j = 0; j < C; ++j) t[r][j] = a.tau * t[r][j];
         } else {
-            // G is read even where it is v (the first launch of a pass starts
-            // from v^(0) = T^n = g: the same words, served by the cache), so
-            // that a row's four loads issue together
 #pragma unroll
             for (int r = 0; r < RW; ++r) {
-                R Gr[C];
                 const int64_t o = row_at(r);
+                // the first launch of a pass starts from v^(0) = T^n = g (G
+                // is then not read)
+                if constexpr (C == 1) {
+                    v[r][0] = a.v[o];
+                    sG[wv * RW + r][0][lane] = same ? v[r][0] : a.G[o];
+                    L[r][0] = a.Lam[o];
+                    t[r][0] = a.tau * a.rC[o];
+                    continue;
+                }
+                R Gr[C];
                 ld(a.v, o, v[r]);
-                ld(a.G, o, Gr);
+                if (same) {
+#pragma unroll
+                    for (int j = 0; j < C; ++j) Gr[j] = v[r][j];
+                } else {
+                    ld(a.G, o, Gr);
+                }
                 ld(a.Lam, o, L[r]);
                 ld(a.rC, o, t[r]);
 #pragma unroll
                 for (int j = 0; j < C; ++j) {
-                    sG[wv * RW + r][j][lane] = same ? v[r][j] : Gr[j];
+                    sG[wv * RW + r][j][lane] = Gr[j];
                     t[r][j] = a.tau * t[r][j];
                 }
             }
@@ -342,8 +353,9 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
     }
     // Final stage (b = 0) of the FP32 correction form, in double on v = g + w:
     // T = g - tau rC64 sum_f w_f mean(Lambda'_a, Lambda'_b) (v_a - v_b), with
-    // Lambda' the float conductivities.  Sfin holds the flux sum, gfin g.
-    double Sfin[RW][C], gfin[RW][C];
+    // Lambda' the float conductivities, into Tfin (every cell of the tile:
+    // exact K - 1 in from the edge); gfin holds g, rcfin rC64.
+    double Tfin[RW][C], gfin[RW][C], rcfin[RW][C];
     if constexpr (kFloat) {
         if (fin) {
             __shared__ double dsh_lo[WAVES][C][64], dsh_hi[WAVES][C][64];
@@ -388,20 +400,25 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                     if (fD) S += wyd * fmean<double>(La, Ld, a.face) * (c - prev[j]);
                     if (fU) S += wyd * fmean<double>(La, Lu, a.face) * (c - up);
                     prev[j] = c;
-                    Sfin[r][j] = S;
+                    Tfin[r][j] = S;
                 }
             }
+#pragma unroll
+            for (int r = 0; r < RW; ++r) ld(a.rC64, row_at(r), rcfin[r]);
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int j = 0; j < C; ++j) Tfin[r][j] = gfin[r][j] - a.taud * rcfin[r][j] * Tfin[r][j];
             if (a.lam_next) {
                 // Coefficients of the next Picard pass at the new iterate T
                 // (valid K cells in from the edge; g = T^n): the conductivity
                 // in double for the bound, its float rounding and the source
                 // q = -tau rC' D' g from the float-rounded Lambda' and rC', at
                 // the output cells (K+1 in), faces in the order -x, +x, -y, +y.
-                double Ln[RW][C], rc[RW][C], a2v[RW][C], m1v[RW][C], m2v[RW][C];
+                double Ln[RW][C], a2v[RW][C], m1v[RW][C], m2v[RW][C];
 #pragma unroll
                 for (int r = 0; r < RW; ++r) {
                     const int64_t o = row_at(r);
-                    ld(a.rC64, o, rc[r]);
                     ld(a.alpha2, o, a2v[r]);
                     if constexpr (kSH) {
                         ld(a.m1, o, m1v[r]);
@@ -415,7 +432,7 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                 for (int r = 0; r < RW; ++r)
 #pragma unroll
                     for (int j = 0; j < C; ++j) {
-                        const double tn = gfin[r][j] - a.taud * rc[r][j] * Sfin[r][j];
+                        const double tn = Tfin[r][j];
                         Ln[r][j] = law(tn, a2v[r][j], m1v[r][j], m2v[r][j]);
                     }
                 __shared__ double esh[4][WAVES][C][64];  // seams of Lambda and g
@@ -459,8 +476,8 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                             if (fR[j]) d += wxd * fmean<double>(L, Lr, a.face);
                             if (fD) d += wyd * fmean<double>(L, Ld, a.face);
                             if (fU) d += wyd * fmean<double>(L, Lu, a.face);
-                            bound = fmax(bound, 2.0 * d * rc[r][j]);
-                            const double La = (double)Lf[j], rf = (double)(float)rc[r][j], ga = gfin[r][j];
+                            bound = fmax(bound, 2.0 * d * rcfin[r][j]);
+                            const double La = (double)Lf[j], rf = (double)(float)rcfin[r][j], ga = gfin[r][j];
                             double Sq = 0.0;
                             if (fL[j]) Sq += wxd * fmean<double>(La, (double)Llf, a.face) * (ga - gl);
                             if (fR[j]) Sq += wxd * fmean<double>(La, (double)Lrf, a.face) * (ga - gr);
@@ -498,26 +515,17 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
     auto out_at = [&](int r, int j) -> int64_t {
         return (outm >> (r * C + j)) & 1u ? (int64_t)(yg0 + r) * a.nx + xg[j] : 0;
     };
-    double titv[RW][C], rcf[RW][C];
+    double titv[RW][C];
 #pragma unroll
     for (int r = 0; r < RW; ++r)
 #pragma unroll
-        for (int j = 0; j < C; ++j) {
-            titv[r][j] = 0.0;
-            rcf[r][j] = 0.0;
-        }
+        for (int j = 0; j < C; ++j) titv[r][j] = 0.0;
     if constexpr (kFloat) {
         if (a.Tit && !tit_is_g) {
 #pragma unroll
             for (int r = 0; r < RW; ++r)
 #pragma unroll
                 for (int j = 0; j < C; ++j) titv[r][j] = a.Tit[out_at(r, j)];
-        }
-        if (fin) {
-#pragma unroll
-            for (int r = 0; r < RW; ++r)
-#pragma unroll
-                for (int j = 0; j < C; ++j) rcf[r][j] = a.rC64[out_at(r, j)];
         }
     }
 #pragma unroll
@@ -528,7 +536,7 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                 const int64_t o = (int64_t)(yg0 + r) * a.nx + xg[j];
                 double tnew;
                 if (fin) {
-                    tnew = gfin[r][j] - a.taud * rcf[r][j] * Sfin[r][j];
+                    tnew = Tfin[r][j];
                     a.out64[o] = tnew;
                 } else {
                     a.out[o] = v[r][j];
