@@ -82,7 +82,7 @@ constexpr int kReduceThreads = 256;
 
 // Rows of the pass reductions of one Picard pass.
 struct PassSlots {
-    double* dmax;
+    double* dmax;  // nullable: the Picard change max |T^(it+1) - T^(it)| is then not formed
     double* tmax;
     double* bad;
 };

@@ -177,7 +177,7 @@ struct PassAcc {
                 r3 += red[2][w];
             }
             const int sl = block_slot();
-            atomic_max_nonneg(ps.dmax + sl, r0);
+            if (ps.dmax) atomic_max_nonneg(ps.dmax + sl, r0);
             atomic_max_nonneg(ps.tmax + sl, r1);
             if (r3 != 0.0) atomicAdd(ps.bad + sl, r3);
         }

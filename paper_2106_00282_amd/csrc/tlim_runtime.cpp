@@ -366,8 +366,12 @@ double* row(tlim_ctx* c, int t) { return c->acc + (size_t)t * tlim::kSlots; }
 void zero_rows(tlim_ctx* c, int t0, int t1) { tlim::launch_zero_rows(c->stream, c->acc, t0, t1); }
 double result(const tlim_ctx* c, int t) { return c->res_host->v[t]; }
 
-tlim::PassSlots pass_slots(tlim_ctx* c, int it) {
-    return tlim::PassSlots{row(c, tlim::tgt_dmax(it)), row(c, tlim::tgt_tmax(it)), row(c, tlim::tgt_bad(it))};
+// The reduction rows of pass it.  With dmax = false the Picard change is not
+// formed (its row stays zero and the kernels do not read T^(it)): a step
+// without a report and without a Picard tolerance never reads it.
+tlim::PassSlots pass_slots(tlim_ctx* c, int it, bool dmax = true) {
+    return tlim::PassSlots{dmax ? row(c, tlim::tgt_dmax(it)) : nullptr, row(c, tlim::tgt_tmax(it)),
+                           row(c, tlim::tgt_bad(it))};
 }
 
 double* T2_ptr(tlim_ctx* c) { return c->t2_alias ? c->field[TLIM_T1] : c->field[TLIM_T2]; }
@@ -839,7 +843,8 @@ tlim_status heat_passes(tlim_ctx* c, const tlim_step_opts* o, Mode mode, tlim_st
             // timed only behind the step's earlier passes (not after a readback)
             tm.skip = mode == Mode::Sync || it == 0;
             run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->g_heat, c->Tnew, need_update ? nullptr : Tit,
-                         pass_slots(c, it), tm, sc, true, nullptr, want || want_step ? &nc : nullptr, &done);
+                         pass_slots(c, it, rep != nullptr || o->picard_tol > 0.0), tm, sc, true, nullptr,
+                         want || want_step ? &nc : nullptr, &done);
             if (want_step) note_next_step(c, o, done);
             else if (done) {
                 coef_ready = true;
@@ -1623,8 +1628,9 @@ void enqueue_predicted(tlim_ctx* c, const tlim_step_opts* o, tlim_ctx::Pending& 
         const bool want_step = last && next_step_ok(c, o, g);
         tlim::NextCoef nc = want_step ? next_step_coef(c, o, ph) : next_coef(c, it, ph);
         bool done = false;
-        run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->g_heat, c->Tnew, Tit, pass_slots(c, it), tm, sc, true,
-                     nullptr, want || want_step ? &nc : nullptr, &done);
+        // (a pipelined step has neither a report nor a Picard tolerance)
+        run_lim_pass(c, g, o->face_mean, o->dt, ps, c->Tn, c->g_heat, c->Tnew, Tit, pass_slots(c, it, false), tm, sc,
+                     true, nullptr, want || want_step ? &nc : nullptr, &done);
         coef_ready = false;
         if (want_step) note_next_step(c, o, done);
         else if (done) {

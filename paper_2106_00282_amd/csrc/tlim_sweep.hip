@@ -521,7 +521,7 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
 #pragma unroll
         for (int j = 0; j < C; ++j) titv[r][j] = 0.0;
     if constexpr (kFloat) {
-        if (a.Tit && !tit_is_g) {
+        if (a.Tit && a.ps.dmax && !tit_is_g) {
 #pragma unroll
             for (int r = 0; r < RW; ++r)
 #pragma unroll
@@ -544,15 +544,18 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                 }
                 if (a.Tit) {
                     const double tn = tnew;
-                    double tit;
-                    if (tit_is_g) {
-                        if constexpr (kFloat) tit = gfin[r][j];
-                        else tit = (double)sG[wv * RW + r][j][lane];
-                    } else {
-                        if constexpr (kFloat) tit = titv[r][j];
-                        else tit = a.Tit[o];
+                    // the Picard change only where asked for (ps.dmax set)
+                    if (a.ps.dmax) {
+                        double tit;
+                        if (tit_is_g) {
+                            if constexpr (kFloat) tit = gfin[r][j];
+                            else tit = (double)sG[wv * RW + r][j][lane];
+                        } else {
+                            if constexpr (kFloat) tit = titv[r][j];
+                            else tit = a.Tit[o];
+                        }
+                        dmax = fmax(dmax, fabs(tn - tit));
                     }
-                    dmax = fmax(dmax, fabs(tn - tit));
                     tmax = fmax(tmax, fabs(tn));
                     if (!(tn > 0.0) || isinf(tn)) bad += 1.0;
                 }
@@ -568,7 +571,8 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
         }
         if (lane == 0) {
             const int sl = (int)(((int64_t)blockIdx.x * WAVES + wv) % kSlots);
-            atomicMax((unsigned long long*)(a.ps.dmax + sl), (unsigned long long)__double_as_longlong(dmax + 0.0));
+            if (a.ps.dmax)
+                atomicMax((unsigned long long*)(a.ps.dmax + sl), (unsigned long long)__double_as_longlong(dmax + 0.0));
             atomicMax((unsigned long long*)(a.ps.tmax + sl), (unsigned long long)__double_as_longlong(tmax + 0.0));
             if (bad != 0.0) atomicAdd(a.ps.bad + sl, bad);
         }

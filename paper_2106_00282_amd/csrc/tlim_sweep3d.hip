@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(64 * kZWaves) k_z3d(Z3Args<R> a) {
                 a.out[o] = t;
                 if (a.Tit) {
                     const double tn = (double)t;
-                    dmax = fmax(dmax, fabs(tn - a.Tit[o]));
+                    if (a.ps.dmax) dmax = fmax(dmax, fabs(tn - a.Tit[o]));
                     tmax = fmax(tmax, fabs(tn));
                     if (!(tn > 0.0) || isinf(tn)) bad += 1.0;
                 }
@@ -215,7 +215,8 @@ __global__ void __launch_bounds__(64 * kZWaves) k_z3d(Z3Args<R> a) {
         }
         if (lane == 0) {
             const int sl = wid % kSlots;
-            atomicMax((unsigned long long*)(a.ps.dmax + sl), (unsigned long long)__double_as_longlong(dmax + 0.0));
+            if (a.ps.dmax)
+                atomicMax((unsigned long long*)(a.ps.dmax + sl), (unsigned long long)__double_as_longlong(dmax + 0.0));
             atomicMax((unsigned long long*)(a.ps.tmax + sl), (unsigned long long)__double_as_longlong(tmax + 0.0));
             if (bad != 0.0) atomicAdd(a.ps.bad + sl, bad);
         }
