@@ -84,7 +84,8 @@ def test_levelset2d_fp64_ragged(shape):
 @pytest.mark.parametrize("precision,shape,bc", [("fp64", (261, 140), "periodic"), ("fp64", (129, 128), "adiabatic"),
                                                 ("fp64", (300, 200), "adiabatic"), ("fp32", (261, 140), "periodic"),
                                                 ("fp32", (129, 128), "adiabatic"), ("fp32", (300, 200), "adiabatic"),
-                                                ("fp32", (260, 150), "periodic")])
+                                                ("fp32", (260, 150), "periodic"), ("fp32", (128, 128), "periodic"),
+                                                ("fp32", (130, 256), "adiabatic")])
 def test_two_cells_per_lane_tiles(precision, shape, bc):
     """The FP32 form's float stages run 128-wide tiles with two cells per
     lane on grids of at least 128 x 128 cells (even widths when x is
