@@ -583,24 +583,37 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
             // K cells in from the edge): Lambda = sum_k alpha_k lambda_k(v),
             // and at the output cells (K+1 in) the bound 2 rC sum_f w_f
             // mean(Lambda_a, Lambda_b), faces in the order -x, +x, -y, +y.
-            // With m1 the next step's instead: every cell relaxed from
-            // (alpha2, v, v, m1, m2) first, Lambda and 1/C at the relaxed state.
+            // With next_step the next step's instead: every cell relaxed from
+            // (alpha2, v, v, m1, m2) first, Lambda at the relaxed state.
             const bool next_step = a.next_step != 0;
-            double Ln[RW][C], Tr[RW][C], ar[RW][C], rr[RW][C];
+            // The partial densities enter only the relaxation of interface
+            // cells (pure cells keep their T and alpha2) and the Spitzer-Harm
+            // law; 1/C, which they also fix, is the step's own (equal p_inf),
+            // so under the power law they are read in interface cells only.
+            double Ln[RW][C], Tr[RW][C], ar[RW][C];
 #pragma unroll
             for (int r = 0; r < RW; ++r) {
                 double a2v[C], m1[C], m2[C];
                 const int64_t o = row_at(r);
                 ld(a.alpha2, o, a2v);
-                if (next_step || kSH) {
+                if constexpr (kSH) {
                     ld(a.m1, o, m1);
                     ld(a.m2, o, m2);
+                } else if (next_step) {
+#pragma unroll
+                    for (int j = 0; j < C; ++j) {
+                        m1[j] = m2[j] = 0.0;
+                        if (phys::is_mixed(a2v[j], a.eps)) {
+                            const int64_t oj = o + (sel[j] ? 0 : 1);
+                            m1[j] = a.m1[oj];
+                            m2[j] = a.m2[oj];
+                        }
+                    }
                 }
 #pragma unroll
                 for (int j = 0; j < C; ++j) {
                     if (next_step) {
                         phys::relax_cell(a.ph, a.eps, a2v[j], v[r][j], v[r][j], m1[j], m2[j], Tr[r][j], ar[r][j]);
-                        rr[r][j] = phys::inv_heat_capacity(a.ph, a.eps, Tr[r][j], ar[r][j], m1[j], m2[j]);
                         Ln[r][j] = law(Tr[r][j], ar[r][j], m1[j], m2[j]);
                     } else if constexpr (kSH) {
                         Ln[r][j] = law(v[r][j], a2v[j], m1[j], m2[j]);
@@ -642,7 +655,7 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
                         if (fR[j]) d += a.wx * fmean<double>(Ln[r][j], Lr, a.face);
                         if (fD) d += a.wy * fmean<double>(Ln[r][j], Ld, a.face);
                         if (fU) d += a.wy * fmean<double>(Ln[r][j], Lu, a.face);
-                        const double rc = next_step ? rr[r][j] : a.rC[o];
+                        const double rc = a.rC[o];
                         bound = fmax(bound, 2.0 * d * rc);
                         a.Lam_next[o] = Ln[r][j];
                         if (next_step) {
