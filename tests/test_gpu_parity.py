@@ -119,6 +119,32 @@ def test_two_cells_per_lane_tiles(precision, shape, bc):
         assert abs(r["energy_after"] / r["energy_before"] - 1) < 1e-12
 
 
+@pytest.mark.parametrize("precision,shape", [("fp64", (150, 140)), ("fp32", (150, 140)), ("fp32", (100, 76))])
+def test_power_law_with_a_general_exponent(precision, shape):
+    """A power law whose exponent the law evaluation does not write out as
+    products (n = 1.7 in one phase: the general power) on grids of the
+    blocked 2D kernels, against the oracle (2 steps x 3 passes)."""
+    from oracle import oracle as orc
+    nx, ny = shape
+    ng = max(128, nx, ny)
+    wl = W.levelset2d(ng)
+    for k in wl["fields"]:
+        wl["fields"][k] = np.ascontiguousarray(wl["fields"][k][:, :ny, :nx])
+    wl["n"] = (nx, ny, 1)
+    wl["h"] = (1.0 / ng, 1.0 / ng, 1.0)
+    wl["phases"] = [dict(p) for p in wl["phases"]]
+    wl["phases"][1]["npow"] = 1.7
+    tau, _ = oracle_dt(orc, wl)
+    fo, ro = run_oracle(orc, wl, tau, 2)
+    fg, rg, _ = run_gpu(wl, tau, 2, precision=precision, frozen=_frozen(ro))
+    assert [r["P"] for r in rg] == [r["P"] for r in ro]
+    if precision == "fp64":
+        _compare(fo, fg, FIELDS_T, 1e-12)
+    else:
+        errs = {k: rel_err(fg[k], fo[k]) for k in FIELDS_T}
+        assert max(errs.values()) <= 1e-5, errs
+
+
 def test_levelset2d_fp64_full_size():
     """1024^2 periodic, T^2 conductivities, 10 steps x 3 passes at 200x the
     explicit limit (the benchmark workload) against the full oracle run."""
