@@ -52,6 +52,9 @@ enum {
     kTgtNextStep,  // bound of the next step's first pass, built by this step's last launch
     kTgtHypBad,    // hyperbolic step: cells that left 0 < alpha2 < 1 or lost a positive T
     kTgtHypRate,   // hyperbolic step: max (|u_d| + c)/h_d
+    kTgtVisc,      // viscous part: bound of velocity component c in row kTgtVisc + c
+    kTgtVisc1,
+    kTgtVisc2,
     kTgtP0,        // whole-step kernel: P of pass it in slot 0 of row kTgtP0 + it
     kTargets = kTgtP0 + kMaxPasses
 };
@@ -133,7 +136,12 @@ void launch_coeffs2d(hipStream_t s, const DevGrid& g, const DevPhases& ph, doubl
                      double* a2_out = nullptr);
 
 // Gershgorin bound max_i 2 rC_i sum_f w Lam_f -> max into the row lam.
-void launch_gershgorin(hipStream_t s, const DevGrid& g, int face, const double* Lam, const double* rC, double* lam);
+// The Gershgorin bounds of the three velocity components of the viscous part
+// in one pass over (Lambda, 1/C): component c with the face weights wc[c]
+// (its axis scaled by 4/3), into rows + c*kSlots, for the components with
+// bit c of mask set.
+void launch_gershgorin_visc(hipStream_t s, const DevGrid& g, int face, const double* Lam, const double* rC,
+                            const double wc[3][3], int mask, double* rows);
 
 // Energy sum of the state -> added to the row energy.
 void launch_energy(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* alpha2,

@@ -396,23 +396,42 @@ __global__ void __launch_bounds__(256) k_visc_coeffs(DevGrid g, DevPhases ph, co
 
 // --------------------------------------------------------------- reductions
 
-__global__ void __launch_bounds__(256) k_gershgorin(DevGrid g, int face, const double* __restrict__ Lam,
-                                                    const double* __restrict__ rC, double* lam) {
+// The Gershgorin bounds 2 rC sum_f w_f mean(Lambda_a, Lambda_b) of the three
+// velocity components from one read of Lambda and 1/C: per cell the face
+// means once, then each component's weighted sum (faces -x, +x, -y, +y, -z,
+// +z) and its block max.
+struct ViscW {
+    double w[3][3];
+};
+__global__ void __launch_bounds__(256) k_gershgorin_visc(DevGrid g, int face, const double* __restrict__ Lam,
+                                                         const double* __restrict__ rC, ViscW wc, int mask,
+                                                         double* rows) {
     __shared__ double sh[16];
     int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
-    double mx = 0.0;
+    double mx[3] = {0.0, 0.0, 0.0};
     if (i < g.nx && j < g.ny) {
         int64_t a = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
         Faces f;
         faces_of(g, i, j, k, f);
-        double d = 0.0, La = Lam[a];
+        const double La = Lam[a], rc = rC[a];
+        double m[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q)
-            if (f.has[q]) d += g.w[q >> 1] * face_mean<double>(La, Lam[a + f.off[q]], face);
-        mx = 2.0 * d * rC[a];
+        for (int q = 0; q < 6; ++q) m[q] = f.has[q] ? face_mean<double>(La, Lam[a + f.off[q]], face) : 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double d = 0.0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                if (f.has[q]) d += wc.w[c][q >> 1] * m[q];
+            mx[c] = 2.0 * d * rc;
+        }
     }
-    mx = block_max(mx, sh);
-    if (flat_tid() == 0) atomic_max_nonneg(lam + block_slot(), mx);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (!((mask >> c) & 1)) continue;  // uniform
+        const double b = block_max(mx[c], sh);
+        if (flat_tid() == 0) atomic_max_nonneg(rows + (size_t)c * kSlots + block_slot(), b);
+    }
 }
 
 __global__ void __launch_bounds__(256) k_energy(DevGrid g, DevPhases ph, const double* __restrict__ alpha2,
@@ -787,9 +806,14 @@ void launch_visc_coeffs(hipStream_t s, const DevGrid& g, const DevPhases& ph, co
                        Lam, rC, Lam32, rC32);
 }
 
-void launch_gershgorin(hipStream_t s, const DevGrid& g, int face, const double* Lam, const double* rC, double* lam) {
-    hipLaunchKernelGGL(k_gershgorin, tile_grid(g), dim3(TX, TY), 0, s, g, face, Lam, rC, lam);
+void launch_gershgorin_visc(hipStream_t s, const DevGrid& g, int face, const double* Lam, const double* rC,
+                            const double wc[3][3], int mask, double* rows) {
+    ViscW w;
+    for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) w.w[c][d] = wc[c][d];
+    hipLaunchKernelGGL(k_gershgorin_visc, tile_grid(g), dim3(TX, TY), 0, s, g, face, Lam, rC, w, mask, rows);
 }
+
 
 void launch_energy(hipStream_t s, const DevGrid& g, const DevPhases& ph, const double* alpha2, const double* m1,
                    const double* m2, const double* T1, const double* T2, double* energy) {

@@ -551,25 +551,35 @@ tlim_status viscous(tlim_ctx* c, const tlim_step_opts* o, tlim_step_report* rep,
         tlim::launch_copy(c->stream, c->field[TLIM_T2], c->field[TLIM_T1], c->N);
         c->t2_alias = false;
     }
+    // the components' bounds depend on (Lambda, 1/C) only, which the passes
+    // do not change: all of them from one kernel and one readback
+    double lam_c[3] = {0.0, 0.0, 0.0};
+    if (!o->frozen_visc) {
+        double wc[3][3];
+        int mask = 0;
+        for (int comp = 0; comp < 3; ++comp) {
+            double scale[3] = {1.0, 1.0, 1.0};
+            scale[comp] = 4.0 / 3.0;
+            const DevGrid gc = dev_grid(c, scale);
+            for (int d = 0; d < 3; ++d) wc[comp][d] = gc.w[d];
+            if (c->n[comp] > 1) mask |= 1 << comp;
+        }
+        zero_rows(c, tlim::kTgtVisc, tlim::kTgtVisc + 3);
+        tlim::launch_gershgorin_visc(c->stream, g0, o->face_mean, c->Lam, c->rC, wc, mask, row(c, tlim::kTgtVisc));
+        tlim_status st = read_result(c, tlim::kTgtVisc, tlim::kTgtVisc + 3);
+        if (st) return st;
+        for (int comp = 0; comp < 3; ++comp) lam_c[comp] = result(c, tlim::kTgtVisc + comp);
+    }
     for (int comp = 0; comp < 3; ++comp) {
         if (c->n[comp] <= 1) continue;
         double scale[3] = {1.0, 1.0, 1.0};
         scale[comp] = 4.0 / 3.0;
         DevGrid g = dev_grid(c, scale);
-        double lam;
-        if (o->frozen_visc) {
-            lam = o->frozen_visc[comp];
-        } else {
-            zero_rows(c, tlim::kTgtLambda, tlim::kTgtLambda + 1);
-            tlim::launch_gershgorin(c->stream, g, o->face_mean, c->Lam, c->rC, row(c, tlim::kTgtLambda));
-            tlim_status st = read_result(c, tlim::kTgtLambda, tlim::kTgtLambda + 1);
-            if (st) return st;
-            lam = result(c, tlim::kTgtLambda);
-        }
+        const double lam = o->frozen_visc ? o->frozen_visc[comp] : lam_c[comp];
         PassSchedule ps = host_schedule(o->dt, lam, o->order);
         double* u = c->field[TLIM_U + comp];
         Vhat vh;
-        tm.skip = true;  // after the bound's readback
+        tm.skip = true;  // the viscous passes are left out of the sweep timing
         run_lim_pass(c, g, o->face_mean, o->dt, ps, u, u, c->Tnew, nullptr, tlim::PassSlots{}, tm, sc, false,
                      heat || E ? &vh : nullptr);
         if (heat || E)
