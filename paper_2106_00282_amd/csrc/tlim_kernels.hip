@@ -551,7 +551,7 @@ __global__ void __launch_bounds__(256) k_q32(DevGrid g, int face, const double* 
     faces_of(g, i, j, k, f);
     double S = stencil<double, double, float>(g, f, a, rhs, Lam32, face);
     q[a] = (float)(-tau * (double)rC32[a] * S);
-    w0[a] = (float)(v0[a] - rhs[a]);
+    if (w0) w0[a] = (float)(v0[a] - rhs[a]);  // (not needed where v0 is rhs: w0 = 0)
 }
 
 __global__ void __launch_bounds__(256) k_stage32(DevGrid g, int face, const float* __restrict__ w,

@@ -433,8 +433,11 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
     if (nc_done) *nc_done = false;
     const int nst = ps.nst;
     hipStream_t s = c->stream;
+    // a pass that starts from its own source (v0 = rhs: the viscous part)
+    // has w0 = v0 - rhs = 0: it starts from the zero array
+    const bool zero_start = c->precision == TLIM_FP32 && v0 == rhs && c->wzero != nullptr;
     if (c->precision == TLIM_FP32 && !have_q)
-        tlim::launch_q32(s, g, face, rhs, v0, c->Lam32, c->rC32, tau, c->q32, c->wb[0]);
+        tlim::launch_q32(s, g, face, rhs, v0, c->Lam32, c->rC32, tau, c->q32, zero_start ? nullptr : c->wb[0]);
     // one event pair around the pass's back-to-back sweep launches
     const int64_t launches0 = sc.launches;
     tm.start();
@@ -442,7 +445,7 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
         // 2P-2 float stages on the correction, the final one in double; the
         // launch that reaches it writes `out`
         // w0 = 0 without sources: start from the zero array (no write needed)
-        const float* cur = have_q && c->w0_zero ? c->wzero : c->wb[0];
+        const float* cur = (have_q && c->w0_zero) || zero_start ? c->wzero : c->wb[0];
         int m = 0;
         const int upto = vh ? nst - 1 : nst;  // with vh the final stage runs on its own
         while (m < upto) {
