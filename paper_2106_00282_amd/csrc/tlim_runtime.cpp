@@ -448,6 +448,20 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
         const float* cur = (have_q && c->w0_zero) || zero_start ? c->wzero : c->wb[0];
         int m = 0;
         const int upto = vh ? nst - 1 : nst;  // with vh the final stage runs on its own
+        // (stage 1 must be a float stage: the final stage is the last of
+        // upto unless vh takes it)
+        if (cur == c->wzero && tlim::use_z3d(g) && upto >= (vh ? 2 : 3)) {
+            // one stage per launch on 3D grids: the first stage from w = 0 is
+            // c_0 q exactly, so it rides along with the second
+            auto sp = [&](int k) {
+                return ps.lam_dev ? tlim::StageParam{ps.lam_dev, 0.0, ps.chat[k]}
+                                  : tlim::StageParam{nullptr, ps.tb[k], 0.0};
+            };
+            tlim::launch_z3d_two_from_zero32(s, g, face, c->q32, c->Lam32, c->rC32, c->wb[0], sp(0), sp(1), tau);
+            cur = c->wb[0];
+            m = 2;
+            sc.launches++;
+        }
         while (m < upto) {
             int k = tlim::sweeps_per_launch(g, upto - m);
             bool last = !vh && m + k == nst;

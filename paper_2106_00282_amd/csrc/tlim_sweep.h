@@ -81,6 +81,11 @@ void launch_psi_from_lambda(hipStream_t s, int64_t n, const double* lam, const d
 void launch_adj_z3d(hipStream_t s, const DevGrid& g, const double* psi, const double* vprev, const double* Lam,
                     const double* rC, double* psi_out, double* dgpsi, double* gLam, double cm, double tb,
                     double tau);
+// The first two float stages of an FP32 pass that starts from w = 0 on a 3D
+// grid in one launch: stage 0 gives c_0 qn exactly, so the launch runs stage
+// 1 on that input read from qn (sp0, sp1: the two stages' parameters).
+void launch_z3d_two_from_zero32(hipStream_t s, const DevGrid& g, int face, const float* qn, const float* Lam32,
+                                const float* rC32, float* out, StageParam sp0, StageParam sp1, double tau);
 // The FP32 correction form's final stage on a 3D grid (as launch_final32).
 void launch_z3d_final32(hipStream_t s, const DevGrid& g, int face, const float* w, const double* rhs,
                         const float* Lam32, const double* rC, double* out, double tau, const double* Tit,

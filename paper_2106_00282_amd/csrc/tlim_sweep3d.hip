@@ -50,9 +50,12 @@ struct Z3Args {
     // double); v and Lam are then unused
     const float* w32;
     const float* Lam32;
+    // kFromG: the input is the stage before this one from w = 0, c_0 G
+    // (c_0 = 1/(1 + tau b_0) of sp_in), read from G; v is then unused
+    StageParam sp_in;
 };
 
-template <typename R, int ROWS, bool kCorr>
+template <typename R, int ROWS, bool kCorr, bool kFromG = false>
 __global__ void __launch_bounds__(64 * kZWaves) k_z3d(Z3Args<R> a) {
     constexpr int RW = ROWS + 2;
     const int lane = threadIdx.x & 63;
@@ -66,6 +69,21 @@ __global__ void __launch_bounds__(64 * kZWaves) k_z3d(Z3Args<R> a) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
         tbd = a.tau * m * a.sp.chat;
+    }
+    // the input's scale: 1, or c_0 of the stage folded into this one (the
+    // same number that stage's cm was)
+    R vs = R(1);
+    if constexpr (kFromG) {
+        double tb0 = a.sp_in.tb;
+        if (a.sp_in.lam) {
+            double m = 0.0;
+#pragma unroll
+            for (int k = 0; k < kSlots / 64; ++k) m = fmax(m, a.sp_in.lam[lane + 64 * k]);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+            tb0 = a.tau * m * a.sp_in.chat;
+        }
+        vs = (R)(1.0 / (1.0 + tb0));
     }
     if (wid >= a.nwaves) return;  // wave-uniform
     const int tx = wid % a.tiles_x, rest = wid / a.tiles_x;
@@ -97,6 +115,7 @@ __global__ void __launch_bounds__(64 * kZWaves) k_z3d(Z3Args<R> a) {
     R Gc[ROWS], rc_c[ROWS], Gn[ROWS], rc_n[ROWS], hvc[ROWS], hLc[ROWS], hvn[ROWS], hLn[ROWS];
     auto ld_v = [&](unsigned i) -> R {
         if constexpr (kCorr) return a.G[i] + (R)a.w32[i];
+        else if constexpr (kFromG) return vs * a.G[i];
         else return a.v[i];
     };
     auto ld_L = [&](unsigned i) -> R {
@@ -230,11 +249,12 @@ constexpr int z_rows() {
 }
 
 
-template <typename R, bool kCorr>
+template <typename R, bool kCorr, bool kFromG = false>
 void launch_z3d_impl(hipStream_t s, const DevGrid& g, int face, const R* v, const R* G, const R* Lam, const R* rC,
                      R* out, StageParam sp, double tau, const double* Tit, PassSlots ps, const float* w32,
-                     const float* Lam32) {
+                     const float* Lam32, StageParam sp_in = StageParam{nullptr, 0.0, 0.0}) {
     Z3Args<R> a{};
+    a.sp_in = sp_in;
     a.w32 = w32;
     a.Lam32 = Lam32;
     a.v = v;
@@ -270,7 +290,7 @@ void launch_z3d_impl(hipStream_t s, const DevGrid& g, int face, const R* v, cons
     const int64_t nw = cols * ((g.nz + a.zc - 1) / a.zc);
     a.nwaves = (int)nw;
     const unsigned blocks = (unsigned)((nw + kZWaves - 1) / kZWaves);
-    hipLaunchKernelGGL((k_z3d<R, rows, kCorr>), dim3(blocks), dim3(64 * kZWaves), 0, s, a);
+    hipLaunchKernelGGL((k_z3d<R, rows, kCorr, kFromG>), dim3(blocks), dim3(64 * kZWaves), 0, s, a);
 }
 
 }  // namespace
@@ -279,6 +299,12 @@ template <typename R>
 void launch_z3d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* G, const R* Lam, const R* rC, R* out,
                 StageParam sp, double tau, const double* Tit, PassSlots ps) {
     launch_z3d_impl<R, false>(s, g, face, v, G, Lam, rC, out, sp, tau, Tit, ps, nullptr, nullptr);
+}
+
+void launch_z3d_two_from_zero32(hipStream_t s, const DevGrid& g, int face, const float* qn, const float* Lam32,
+                                const float* rC32, float* out, StageParam sp0, StageParam sp1, double tau) {
+    launch_z3d_impl<float, false, true>(s, g, face, nullptr, qn, Lam32, rC32, out, sp1, tau, nullptr, PassSlots{},
+                                        nullptr, nullptr, sp0);
 }
 
 void launch_z3d_final32(hipStream_t s, const DevGrid& g, int face, const float* w, const double* rhs,
