@@ -468,7 +468,7 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
             float* nxt = cur == c->wb[0] ? c->wb[1] : c->wb[0];
             int done = tlim::launch_sweeps32(s, g, face, cur, c->q32, c->Lam32, c->rC32, nxt, ps.at(m), k, last, tau,
                                              rhs, c->rC, out, Tit, slots, last ? nc : nullptr,
-                                             last ? nc_done : nullptr);
+                                             last ? nc_done : nullptr, cur == c->wzero);
             cur = nxt;
             m += done;
             sc.launches++;

@@ -63,7 +63,7 @@ int launch_sweeps64(hipStream_t s, const DevGrid& g, int face, const double* v, 
 int launch_sweeps32(hipStream_t s, const DevGrid& g, int face, const float* w, const float* qn,
                     const float* Lam32, const float* rC32, float* out, Stages st, int count, bool last, double tau,
                     const double* rhs, const double* rC, double* out64, const double* Tit, PassSlots ps,
-                    const NextCoef* nc = nullptr, bool* nc_done = nullptr);
+                    const NextCoef* nc = nullptr, bool* nc_done = nullptr, bool w_zero = false);
 
 // One stage on a 3D grid by z-marching waves (tlim_sweep3d.hip): as
 // launch_stage64 / launch_stage32, and with Tit != NULL also the pass

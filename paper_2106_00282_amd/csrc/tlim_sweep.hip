@@ -98,6 +98,7 @@ struct TBArgs {
     int nx, ny, perx, pery;
     R wx, wy, tau;
     int K, H, hx, face, tiles_x, ox, oy;
+    int vzero;  // float stages: v is the all-zero start w0 = 0 (not read)
     double taud;
     double tb[KMAX_TB], chat[KMAX_TB];
 };
@@ -173,6 +174,9 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
 
     constexpr bool kFloat = sizeof(R) == 4;
     const bool fin = kFloat && a.g64 != nullptr;
+    // A float pass's first launch starts from w0 = 0, where its first stage
+    // gives c_0 G exactly: v is then not read, and that stage is c_0 G.
+    const bool vz = kFloat && !kKeep && a.vzero && a.v != a.G && (fin ? K - 1 : K) >= 1;
     // In double the source G lives in LDS (read once per cell and stage):
     // the four kappa and v already take 80 of the 128 VGPRs that four
     // workgroups per CU leave, and G in registers spills.
@@ -190,7 +194,12 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
 #pragma unroll
             for (int r = 0; r < RW; ++r) {
                 const int64_t o = row_at(r);
-                ld(a.v, o, v[r]);
+                if (vz) {
+#pragma unroll
+                    for (int j = 0; j < C; ++j) v[r][j] = R(0);
+                } else {
+                    ld(a.v, o, v[r]);
+                }
                 ld(a.Lam, o, L[r]);
                 ld(a.rC, o, t[r]);
             }
@@ -299,8 +308,20 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
     // The end waves read a valid row and discard it (no branch).
     const int Kin = fin ? K - 1 : K;
     const int wdn = wv > 0 ? wv - 1 : 0, wup = wv < WAVES - 1 ? wv + 1 : wv;
-    for (int s = 0; s < Kin; ++s) {
-        const int buf = (s + 1) & 1;
+    // from w0 = 0 the first stage is c_0 G (the same number the stage below
+    // gives with every difference zero)
+    int s0 = 0;
+    if (vz) {
+        const R cm0 = (R)lane_value(pcm, 0);
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+            for (int j = 0; j < C; ++j) v[r][j] = cm0 * G[r][j];
+        s0 = 1;
+    }
+    for (int s = s0; s < Kin; ++s) {
+        // the first stage run writes buffer 1 (buffer 0 held the Lambda seams)
+        const int buf = (s - s0 + 1) & 1;
 #pragma unroll
         for (int j = 0; j < C; ++j) {
             sh_lo[buf][wv][j][lane] = v[0][j];
@@ -678,8 +699,9 @@ template <typename R>
 int launch_tb2d(hipStream_t s, const DevGrid& g, int face, const R* v, const R* G, const R* Lam, const R* rC,
                 R* out, Stages st, int count, double tau, const double* Tit, PassSlots ps, R* stages = nullptr,
                 int64_t sstride = 0, const double* g64 = nullptr, const double* rC64 = nullptr,
-                double* out64 = nullptr, const NextCoef* nc = nullptr) {
+                double* out64 = nullptr, const NextCoef* nc = nullptr, int vzero = 0) {
     TBArgs<R> a{};
+    a.vzero = vzero;
     if (nc) {
         a.lam_next = nc->lam;
         a.alpha2 = nc->alpha2;
@@ -825,15 +847,16 @@ int launch_sweeps64(hipStream_t s, const DevGrid& g, int face, const double* v, 
 int launch_sweeps32(hipStream_t s, const DevGrid& g, int face, const float* w, const float* qn,
                     const float* Lam32, const float* rC32, float* out, Stages st, int count, bool last, double tau,
                     const double* rhs, const double* rC, double* out64, const double* Tit, PassSlots ps,
-                    const NextCoef* nc, bool* nc_done) {
+                    const NextCoef* nc, bool* nc_done, bool w_zero) {
     if (nc_done) *nc_done = false;
     if (use_tb2d(g, count)) {
         if (last) {
             if (nc_done) *nc_done = nc != nullptr;
             return launch_tb2d<float>(s, g, face, w, qn, Lam32, rC32, nullptr, st, count, tau, Tit, ps, nullptr, 0,
-                                      rhs, rC, out64, nc);
+                                      rhs, rC, out64, nc, w_zero ? 1 : 0);
         }
-        return launch_tb2d<float>(s, g, face, w, qn, Lam32, rC32, out, st, count, tau, nullptr, PassSlots{});
+        return launch_tb2d<float>(s, g, face, w, qn, Lam32, rC32, out, st, count, tau, nullptr, PassSlots{}, nullptr,
+                                  0, nullptr, nullptr, nullptr, nullptr, w_zero ? 1 : 0);
     }
     if (last) {
         if (use_z3d(g)) launch_z3d_final32(s, g, face, w, rhs, Lam32, rC, out64, tau, Tit, ps);
