@@ -71,12 +71,19 @@ __host__ __device__ constexpr bool tgt_is_sum(int t) {
 // Results folded for the host (one double per target).
 struct PassResult {
     double v[kTargets];
+    // sequence number of the fold that wrote v (pipelined steps): published
+    // after every value, so a host that reads it sees the values
+    unsigned long long seq;
 };
 
 // Fold rows [t0, t1) of the accumulator into res->v[t0..t1) (res may be
 // pinned host memory); consume = 1 also zeroes the rows.  move_from >= 0:
 // afterwards row t0 takes the contents of row move_from, which is zeroed.
-void launch_collect(hipStream_t s, double* acc, PassResult* res, int t0, int t1, int consume, int move_from = -1);
+// seq != 0: the last workgroup to finish then stores seq into res->seq with
+// a system-scope release, counting the workgroups in *done (zero before the
+// launch, zero again after it).
+void launch_collect(hipStream_t s, double* acc, PassResult* res, int t0, int t1, int consume, int move_from = -1,
+                    unsigned long long seq = 0, unsigned* done = nullptr);
 // Zero rows [t0, t1) of the accumulator.
 void launch_zero_rows(hipStream_t s, double* acc, int t0, int t1);
 

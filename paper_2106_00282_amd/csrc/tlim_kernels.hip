@@ -708,7 +708,7 @@ __global__ void __launch_bounds__(256) k_total_energy_heat(int64_t n, const doub
 // move_from >= 0 the wave of row t0 then moves row move_from into it (and
 // clears move_from): each lane touches only its own slots, in order.
 __global__ void __launch_bounds__(64) k_collect(double* __restrict__ acc, PassResult* res, int t0, int consume,
-                                                int move_from) {
+                                                int move_from, unsigned long long seq, unsigned* done) {
     const int t = t0 + blockIdx.x, lane = threadIdx.x;
     double* row = acc + (int64_t)t * kSlots;
     const bool sum = tgt_is_sum(t);
@@ -728,7 +728,20 @@ __global__ void __launch_bounds__(64) k_collect(double* __restrict__ acc, PassRe
         }
     }
     v = sum ? wave_sum(v) : wave_max(v);
-    if (lane == 0) res->v[t] = v;
+    if (lane == 0) {
+        res->v[t] = v;
+        if (seq) {
+            // each workgroup releases its value to the host before it counts
+            // itself in; the last one publishes seq after all of them
+            __threadfence_system();
+            const unsigned n = __hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (n == gridDim.x - 1) {
+                __threadfence_system();
+                __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&res->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256) k_fill(double* p, double v, int64_t n) {
@@ -765,8 +778,10 @@ void launch_zero_rows(hipStream_t s, double* acc, int t0, int t1) {
     hipLaunchKernelGGL(k_fill, dim3(pointwise_blocks(n)), dim3(256), 0, s, acc + (int64_t)t0 * kSlots, 0.0, n);
 }
 
-void launch_collect(hipStream_t s, double* acc, PassResult* res, int t0, int t1, int consume, int move_from) {
-    hipLaunchKernelGGL(k_collect, dim3(t1 - t0), dim3(64), 0, s, acc, res, t0, consume, move_from);
+void launch_collect(hipStream_t s, double* acc, PassResult* res, int t0, int t1, int consume, int move_from,
+                    unsigned long long seq, unsigned* done) {
+    hipLaunchKernelGGL(k_collect, dim3(t1 - t0), dim3(64), 0, s, acc, res, t0, consume, move_from, done ? seq : 0ULL,
+                       done);
 }
 
 void launch_relax(hipStream_t s, const DevGrid& g, const DevPhases& ph, double eps, double* alpha2,

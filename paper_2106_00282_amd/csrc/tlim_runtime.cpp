@@ -67,6 +67,8 @@ struct tlim_ctx {
     double* chat_tab;            // whole-step kernel: b/lambda per P (order chat_order, -1: not built)
     int chat_order;
     unsigned* bar;               // whole-step kernel: barrier counter
+    unsigned* collect_done;      // folds that publish a sequence number: workgroups done
+    unsigned long long res_seq;  // last sequence number given to such a fold
     bool w0_zero;                // the coefficients of the current pass came without sources
     double* acc;           // reduction rows: kTargets x kSlots
     PassResult* res_dev;   // folded results (one double per target)
@@ -94,6 +96,7 @@ struct tlim_ctx {
         double* alpha2;         // its relaxed alpha2 (the alpha2 field during its passes)
         double* alpha2_other;   // the other alpha2 array
         bool whole;             // run by the whole-step kernel (P decided on the device)
+        unsigned long long seq; // nonzero: its fold publishes seq in its result block (no event)
     } pend;
     hipEvent_t ev_pend[2];
     // Leading rows of the Picard-pass targets known to be zero, and the count
@@ -162,7 +165,7 @@ struct Layout {
     size_t field[TLIM_NFIELDS];
     size_t Tn, Tn2, Tn3, Tnew, a2n, a2x, Lam, Lam2, rC, rhs, vb[2], acc, res;
     size_t Lam32, rC32, q32, wb[2], Lam32b, q32b, wzero;
-    size_t chat, bar;
+    size_t chat, bar, cnt;
     size_t total;
 };
 
@@ -189,6 +192,8 @@ Layout layout_of(const int64_t n[3], int precision) {
     off += align_up(sizeof(double) * (size_t)kStepPmax * kStepPmax);
     L.bar = off;
     off += align_up(sizeof(unsigned) * tlim::kStepMaxTiles);
+    L.cnt = off;
+    off += align_up(sizeof(double));
     if (precision == TLIM_FP32) {
         size_t* ff[] = {&L.Lam32, &L.rC32, &L.q32, &L.wb[0], &L.wb[1], &L.Lam32b, &L.q32b, &L.wzero};
         for (size_t* p : ff) {
@@ -1045,7 +1050,9 @@ tlim_status tlim_create(const tlim_grid* grid, int32_t precision, void* hip_stre
         delete c;
         return TLIM_E_HIP;
     }
-    if (hipHostMalloc((void**)&c->res_blk[0], 2 * sizeof(PassResult), hipHostMallocDefault) != hipSuccess) {
+    // coherent: a fold's stores reach the host while later kernels run (the
+    // pipelined steps poll its sequence number, not an event)
+    if (hipHostMalloc((void**)&c->res_blk[0], 2 * sizeof(PassResult), hipHostMallocCoherent) != hipSuccess) {
         delete c;
         return TLIM_E_HIP;
     }
@@ -1055,6 +1062,8 @@ tlim_status tlim_create(const tlim_grid* grid, int32_t precision, void* hip_stre
         (void)hipGetLastError();
     }
     c->res_blk_dev[1] = c->res_blk_dev[0] ? c->res_blk_dev[0] + 1 : nullptr;
+    c->res_blk[0]->seq = c->res_blk[1]->seq = 0;
+    c->res_seq = 0;
     c->res_cur = 0;
     c->res_host = c->res_blk[0];
     c->res_host_dev = c->res_blk_dev[0];
@@ -1143,6 +1152,8 @@ tlim_status tlim_bind_workspace(tlim_ctx* c, void* dev_ptr, size_t bytes) {
     c->chat_tab = (double*)(base + L.chat);
     c->chat_order = -1;
     c->bar = (unsigned*)(base + L.bar);
+    c->collect_done = (unsigned*)(base + L.cnt);
+    tlim::launch_fill(c->stream, (double*)c->collect_done, 0.0, 1);
     c->t2_alias = false;
     c->hist_passes = 0;
     c->hist_steady = 0;
@@ -1667,14 +1678,18 @@ void enqueue_predicted(tlim_ctx* c, const tlim_step_opts* o, tlim_ctx::Pending& 
         std::swap(c->field[TLIM_T1], c->Tnew);
     }
     const bool move = c->next_ready;
+    // the step's results and then its sequence number go to its pinned
+    // block: the host polls that number (an event between steps costs about
+    // 5 us of idle GPU)
+    const unsigned long long seq = ++c->res_seq;
     tlim::launch_collect(s, c->acc, c->res_host_dev, tlim::tgt_lam(0), tlim::tgt_lam(o->passes), 1,
-                         move ? tlim::kTgtNextStep : -1);
+                         move ? tlim::kTgtNextStep : -1, seq, c->collect_done);
     c->clean_rows = c->clean_keep;
     if (move) {
         c->row0_moved = true;
         c->spare_clean = true;
     }
-    (void)hipEventRecord(c->ev_pend[c->res_cur], s);
+    p.seq = seq;
     p.o = *o;
     p.o.frozen_lambda = nullptr;
     p.o.frozen_visc = nullptr;
@@ -1698,6 +1713,7 @@ bool enqueue_whole(tlim_ctx* c, const tlim_step_opts* o, tlim_ctx::Pending& p) {
     next_result_block(c);
     if (!step2d_enqueue(c, o, c->res_host_dev)) return false;
     (void)hipEventRecord(c->ev_pend[c->res_cur], c->stream);
+    p.seq = 0;
     p.o = *o;
     p.o.frozen_lambda = nullptr;
     p.o.frozen_visc = nullptr;
@@ -1720,20 +1736,39 @@ struct Verdict {
 // the P it used in every pass against its lambda_G.
 Verdict verify(tlim_ctx* c, const tlim_ctx::Pending& p) {
     Verdict v{TLIM_OK, false, 0.0, {0}};
-    hipEvent_t e = c->ev_pend[p.blk];
+    PassResult* res = c->res_blk[p.blk];
     hipError_t r = hipErrorNotReady;
     const auto t0c = std::chrono::steady_clock::now();
-    while ((r = hipEventQuery(e)) == hipErrorNotReady) {
-        if (std::chrono::steady_clock::now() - t0c > std::chrono::microseconds(2000)) {
-            r = hipEventSynchronize(e);
-            break;
+    auto waited = [&] { return std::chrono::steady_clock::now() - t0c > std::chrono::microseconds(2000); };
+    if (p.seq) {
+        // the fold's sequence number arrives after its values; past ~2 ms
+        // (or a fault that stopped the stream) the stream is drained instead
+        bool seen;
+        while (!(seen = __atomic_load_n(&res->seq, __ATOMIC_ACQUIRE) == p.seq)) {
+            if (waited()) {
+                r = hipStreamSynchronize(c->stream);
+                seen = __atomic_load_n(&res->seq, __ATOMIC_ACQUIRE) == p.seq;
+                break;
+            }
+        }
+        if (!seen && r == hipSuccess) {
+            v.st = fail(c, TLIM_E_HIP, "pipelined step: the stream drained without the step's results");
+            return v;
+        }
+        if (seen) r = hipSuccess;
+    } else {
+        hipEvent_t e = c->ev_pend[p.blk];
+        while ((r = hipEventQuery(e)) == hipErrorNotReady) {
+            if (waited()) {
+                r = hipEventSynchronize(e);
+                break;
+            }
         }
     }
     if (r != hipSuccess) {
         v.st = fail(c, TLIM_E_HIP, "pipelined step: %s", hipGetErrorString(r));
         return v;
     }
-    const PassResult* res = c->res_blk[p.blk];
     const int np = p.o.passes;
     if (p.whole) {
         Step2DResult r;
