@@ -517,11 +517,39 @@ void run_lim_pass(tlim_ctx* c, const DevGrid& g, int face, double tau, const Pas
     tm.skip = false;
 }
 
+// Wait until the fold that carries sequence number seq has written its
+// results into the pinned block res: its number arrives after its values.
+// Past ~2 ms (or after a fault that stopped the stream) the stream is
+// drained instead.  The readbacks sit on the critical path between steps,
+// and an event there costs about 5 us of idle GPU.
+hipError_t wait_fold(tlim_ctx* c, PassResult* res, unsigned long long seq, bool* seen) {
+    const auto t0c = std::chrono::steady_clock::now();
+    hipError_t r = hipSuccess;
+    while (!(*seen = __atomic_load_n(&res->seq, __ATOMIC_ACQUIRE) == seq)) {
+        if (std::chrono::steady_clock::now() - t0c > std::chrono::microseconds(2000)) {
+            r = hipStreamSynchronize(c->stream);
+            *seen = __atomic_load_n(&res->seq, __ATOMIC_ACQUIRE) == seq;
+            break;
+        }
+    }
+    return *seen ? hipSuccess : r;
+}
+
 // Fold the rows [t0, t1) and bring the results to the host (synchronises).
 // With consume the rows are also cleared on the device.
 tlim_status read_result(tlim_ctx* c, int t0, int t1, bool consume = false, int move_from = -1) {
-    if (c->res_host_dev) {
+    if (c->res_host_dev && t1 > t0) {
         // the fold writes straight into the pinned result block
+        const unsigned long long seq = ++c->res_seq;
+        tlim::launch_collect(c->stream, c->acc, c->res_host_dev, t0, t1, consume ? 1 : 0, move_from, seq,
+                             c->collect_done);
+        bool seen = false;
+        const hipError_t e = wait_fold(c, c->res_host, seq, &seen);
+        if (e != hipSuccess) return fail(c, TLIM_E_HIP, "readback: %s", hipGetErrorString(e));
+        if (!seen) return fail(c, TLIM_E_HIP, "readback: the stream drained without the results");
+        return TLIM_OK;
+    }
+    if (c->res_host_dev) {
         tlim::launch_collect(c->stream, c->acc, c->res_host_dev, t0, t1, consume ? 1 : 0, move_from);
     } else {
         tlim::launch_collect(c->stream, c->acc, c->res_dev, t0, t1, consume ? 1 : 0, move_from);
@@ -1738,28 +1766,18 @@ Verdict verify(tlim_ctx* c, const tlim_ctx::Pending& p) {
     Verdict v{TLIM_OK, false, 0.0, {0}};
     PassResult* res = c->res_blk[p.blk];
     hipError_t r = hipErrorNotReady;
-    const auto t0c = std::chrono::steady_clock::now();
-    auto waited = [&] { return std::chrono::steady_clock::now() - t0c > std::chrono::microseconds(2000); };
     if (p.seq) {
-        // the fold's sequence number arrives after its values; past ~2 ms
-        // (or a fault that stopped the stream) the stream is drained instead
-        bool seen;
-        while (!(seen = __atomic_load_n(&res->seq, __ATOMIC_ACQUIRE) == p.seq)) {
-            if (waited()) {
-                r = hipStreamSynchronize(c->stream);
-                seen = __atomic_load_n(&res->seq, __ATOMIC_ACQUIRE) == p.seq;
-                break;
-            }
-        }
-        if (!seen && r == hipSuccess) {
+        bool seen = false;
+        r = wait_fold(c, res, p.seq, &seen);
+        if (r == hipSuccess && !seen) {
             v.st = fail(c, TLIM_E_HIP, "pipelined step: the stream drained without the step's results");
             return v;
         }
-        if (seen) r = hipSuccess;
     } else {
         hipEvent_t e = c->ev_pend[p.blk];
+        const auto t0c = std::chrono::steady_clock::now();
         while ((r = hipEventQuery(e)) == hipErrorNotReady) {
-            if (waited()) {
+            if (std::chrono::steady_clock::now() - t0c > std::chrono::microseconds(2000)) {
                 r = hipEventSynchronize(e);
                 break;
             }
