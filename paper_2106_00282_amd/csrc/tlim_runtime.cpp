@@ -1079,10 +1079,14 @@ tlim_status tlim_create(const tlim_grid* grid, int32_t precision, void* hip_stre
         return TLIM_E_HIP;
     }
     // coherent: a fold's stores reach the host while later kernels run (the
-    // pipelined steps poll its sequence number, not an event)
+    // readbacks poll its sequence number, not an event).  Where only the
+    // default kind exists, the polls end in their stream drain instead.
     if (hipHostMalloc((void**)&c->res_blk[0], 2 * sizeof(PassResult), hipHostMallocCoherent) != hipSuccess) {
-        delete c;
-        return TLIM_E_HIP;
+        (void)hipGetLastError();
+        if (hipHostMalloc((void**)&c->res_blk[0], 2 * sizeof(PassResult), hipHostMallocDefault) != hipSuccess) {
+            delete c;
+            return TLIM_E_HIP;
+        }
     }
     c->res_blk[1] = c->res_blk[0] + 1;
     if (hipHostGetDevicePointer((void**)&c->res_blk_dev[0], c->res_blk[0], 0) != hipSuccess) {
