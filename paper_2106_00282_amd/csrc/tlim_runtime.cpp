@@ -1677,7 +1677,8 @@ bool pipeline_ok(const tlim_ctx* c, const tlim_step_opts* o, const tlim_step_rep
 
 // Enqueue a predicted step without waiting for anything: relaxation with the
 // first coefficients, the passes with the predicted P, and the fold of the
-// step's reductions into its own pinned result block, followed by an event.
+// step's reductions into its own pinned result block, which ends with the
+// step's sequence number.
 void enqueue_predicted(tlim_ctx* c, const tlim_step_opts* o, tlim_ctx::Pending& p) {
     hipStream_t s = c->stream;
     DevGrid g = dev_grid(c, kUnit);
