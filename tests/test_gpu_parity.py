@@ -501,6 +501,33 @@ def test_pipelined_step_then_report_and_phase_change(whole):
     assert rel_err(s.get_field("T1").cpu().numpy(), fo["T1"]) < 1e-12
 
 
+@pytest.mark.parametrize("precision,whole", [("fp64", 0), ("fp32", 0), ("fp64", 1)])
+def test_two_contexts_interleave_pipelined_steps(precision, whole):
+    """Two contexts on the same stream take turns stepping without reports,
+    so each has a pipelined step pending while the other enqueues and
+    verifies its own.  Each context folds into its own pinned result blocks
+    with its own sequence numbers: both runs must match their own oracle
+    runs (grids of different sizes, so their schedules differ)."""
+    from oracle import oracle as orc
+    from paper_2106_00282_amd.tlim import StepOpts
+    steps = 7
+    runs = []
+    for n in (160, 128):
+        wl = W.levelset2d(n)
+        tau, _ = oracle_dt(orc, wl)
+        fo, _ = run_oracle(orc, wl, tau, steps)
+        runs.append((make_solver(wl, precision), StepOpts(dt=tau, passes=3, whole_step=whole), fo))
+    for s, o, _ in runs:
+        assert s.advance(o)[0] == 0  # a reported first step each
+    for _ in range(steps - 1):
+        for s, o, _ in runs:
+            assert s.advance(o, report=False)[0] == 0
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for s, _, fo in runs:
+        assert s.finish() == 0
+        _compare(fo, {k: s.get_field(k).cpu().numpy() for k in FIELDS_T}, FIELDS_T, tol)
+
+
 def test_next_step_start_is_redone_after_changes():
     """The last launch of an FP64 step relaxes the next step's state and
     builds its first coefficients ahead of time.  Changing a field, the
