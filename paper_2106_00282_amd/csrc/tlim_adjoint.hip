@@ -68,7 +68,8 @@ __global__ void __launch_bounds__(64 * WAVES, 2) k_tb2d_adj(AdjArgs a) {
     __shared__ double sv_hi[2][WAVES][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int K = a.K;
-    const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+    const int tile = tb::xcd_block();  // tiles in XCD order (neighbours share an L2)
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int xg = tx * a.ox - K + lane;
     const int yg0 = ty * a.oy - K + wv * ROWS;
     const int xi = fold(xg, a.nx, a.perx);

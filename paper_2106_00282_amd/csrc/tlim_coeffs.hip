@@ -72,7 +72,7 @@ struct Coef2DArgs {
 template <bool kRelax, bool kSH>
 __global__ void __launch_bounds__(64 * kWaves) k_coeffs2d(Coef2DArgs a) {
     const int lane = threadIdx.x & 63;
-    const int strip = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int strip = tb::xcd_block() * kWaves + (threadIdx.x >> 6);  // strips in XCD order
     if (strip >= a.strips) return;  // wave-uniform
     const int tx = strip % a.tiles_x, ty = strip / a.tiles_x;
     const int xg = tx * kOut - 1 + lane;
@@ -182,7 +182,7 @@ template <bool kRelax, bool kSH>
 __global__ void __launch_bounds__(64 * kWaves) k_coeffs3d(Coef2DArgs a) {
     constexpr int RW = kRows3 + 2;
     const int lane = threadIdx.x & 63;
-    const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int wid = tb::xcd_block() * kWaves + (threadIdx.x >> 6);  // waves in XCD order
     if (wid >= a.strips) return;  // wave-uniform
     const int tx = wid % a.tiles_x, rest = wid / a.tiles_x;
     const int ty = rest % a.tiles_y, tz = rest / a.tiles_y;

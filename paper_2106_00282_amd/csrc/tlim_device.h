@@ -277,6 +277,15 @@ static __device__ __forceinline__ int row_index(int yi0, int yg0, int r, int ny,
     return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
 }
 
+// This workgroup's place in an order in which each of the 8 XCDs (each with
+// an L2 of its own, and given workgroups in turn) runs a contiguous run of
+// places: XCD x runs floor(n/8) of them, one more for x < n mod 8.  Tiles
+// taken in this order put most neighbours, whose halos overlap, on one L2.
+static __device__ __forceinline__ int xcd_block() {
+    const int nb = (int)gridDim.x, x = (int)blockIdx.x & 7;
+    return x * (nb >> 3) + min(x, nb & 7) + ((int)blockIdx.x >> 3);
+}
+
 // Lane l's value of a double (l wave-uniform), without memory access.
 static __device__ __forceinline__ double lane_value(double x, int l) {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),

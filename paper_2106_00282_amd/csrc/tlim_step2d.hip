@@ -133,7 +133,8 @@ __global__ void __launch_bounds__(64 * NW, 4) k_step2d(StepArgs a) {
     __shared__ double sh_lo[2][NW][64], sh_hi[2][NW][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int H = a.H;
-    const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+    const int tile = tb::xcd_block();  // tiles in XCD order (neighbours share an L2)
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int xg = tx * a.ox - H + lane;
     const int yg0 = ty * a.oy - H + wv * ROWS;
     const int xi = fold(xg, a.nx, a.perx);

@@ -132,12 +132,9 @@ __global__ void __launch_bounds__(64 * NW, 4) k_tb2d(TBArgs<R> a) {
     // the tile starts at an even column and a lane's two cells are adjacent
     // in memory (periodic x with an even width, or clamped walls)
     const int HX = a.hx;
-    // Workgroups go to the 8 XCDs in turn, each XCD with an L2 of its own:
-    // XCD x takes a contiguous run of tiles in row order (floor(n/8) of
-    // them, one more for x < n mod 8), so that x-neighbours, whose extended
-    // tiles overlap by 2H columns, mostly share an L2.
-    const int nb = (int)gridDim.x, xcd = (int)blockIdx.x & 7;
-    const int tile = xcd * (nb >> 3) + min(xcd, nb & 7) + ((int)blockIdx.x >> 3);
+    // tiles in XCD order: x-neighbours, whose extended tiles overlap by 2H
+    // columns, mostly share an L2
+    const int tile = tb::xcd_block();
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int yg0 = ty * a.oy - H + wv * RW;
     const int yi0 = fold(yg0, a.ny, a.pery);

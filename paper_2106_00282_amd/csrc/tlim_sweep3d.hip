@@ -59,7 +59,7 @@ template <typename R, int ROWS, bool kCorr, bool kFromG = false>
 __global__ void __launch_bounds__(64 * kZWaves) k_z3d(Z3Args<R> a) {
     constexpr int RW = ROWS + 2;
     const int lane = threadIdx.x & 63;
-    const int wid = blockIdx.x * kZWaves + (threadIdx.x >> 6);
+    const int wid = tb::xcd_block() * kZWaves + (threadIdx.x >> 6);  // waves in XCD order
     // tau*b of the stage (every lane of every wave takes part in the fold)
     double tbd = a.sp.tb;
     if (a.sp.lam) {
@@ -355,7 +355,7 @@ template <int ROWS>
 __global__ void __launch_bounds__(64 * kZWaves) k_adj_z3d(AZ3Args a) {
     constexpr int RW = ROWS + 2;
     const int lane = threadIdx.x & 63;
-    const int wid = blockIdx.x * kZWaves + (threadIdx.x >> 6);
+    const int wid = tb::xcd_block() * kZWaves + (threadIdx.x >> 6);  // waves in XCD order
     if (wid >= a.nwaves) return;  // wave-uniform
     const int tx = wid % a.tiles_x, rest = wid / a.tiles_x;
     const int ty = rest % a.tiles_y, tz = rest / a.tiles_y;
