@@ -182,7 +182,8 @@ template <bool kRelax, bool kSH>
 __global__ void __launch_bounds__(64 * kWaves) k_coeffs3d(Coef2DArgs a) {
     constexpr int RW = kRows3 + 2;
     const int lane = threadIdx.x & 63;
-    const int wid = tb::xcd_block() * kWaves + (threadIdx.x >> 6);  // waves in XCD order
+    // launch order: with the relaxation this kernel measured 8% slower in XCD order
+    const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (wid >= a.strips) return;  // wave-uniform
     const int tx = wid % a.tiles_x, rest = wid / a.tiles_x;
     const int ty = rest % a.tiles_y, tz = rest / a.tiles_y;

@@ -355,7 +355,8 @@ template <int ROWS>
 __global__ void __launch_bounds__(64 * kZWaves) k_adj_z3d(AZ3Args a) {
     constexpr int RW = ROWS + 2;
     const int lane = threadIdx.x & 63;
-    const int wid = tb::xcd_block() * kZWaves + (threadIdx.x >> 6);  // waves in XCD order
+    // launch order: the z-marching reverse stage measured 2% slower in XCD order
+    const int wid = blockIdx.x * kZWaves + (threadIdx.x >> 6);
     if (wid >= a.nwaves) return;  // wave-uniform
     const int tx = wid % a.tiles_x, rest = wid / a.tiles_x;
     const int ty = rest % a.tiles_y, tz = rest / a.tiles_y;
